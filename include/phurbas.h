@@ -1,0 +1,200 @@
+/*
+ * libphurbas: the per-particle spatial-derivative stage of the Phurbas
+ * adaptive Lagrangian meshless MHD method (McNally, Maron & Mac Low, paper II,
+ * arXiv:1110.0836) on one AMD Instinct MI355X (gfx950).
+ *
+ * The library finds every neighbor inside the sphere of radius
+ * r_f,i = 2.3 lambda_i about each particle (Sec. 2 and 2.1), fits a local
+ * weighted third-order (20-monomial) moving-least-squares polynomial to each
+ * particle's neighborhood (Sec. 2), applies the resulting derivative operator
+ * to the carried fields and forms the ideal-MHD Lagrangian time derivatives
+ * (Sec. 2; the evolution equations of App. A without viscosity) that drive
+ * the second-order predictor-corrector step (Sec. 2).  A hand-written
+ * reverse-mode kernel gives gradients of a scalar of those time derivatives.
+ *
+ * Conventions for every entry point
+ *  - Pointers are DEVICE pointers unless marked "host".  phb_params and
+ *    phb_ctx are host objects.
+ *  - Arrays are structure-of-arrays, FP64 unless stated, in the caller's
+ *    particle order, particle index fastest: pos[3][n], lambda[n], fields
+ *    q[8][n] = (rho, Vx, Vy, Vz, Bx, By, Bz, sigma).
+ *  - Neighbor lists are CSR: offsets int64[n+1] (offsets[0] = 0),
+ *    idx int32[nnz]; row i lists, in ascending order, every j (i itself
+ *    included) with  d2 < r*r,  where per axis dx = x_j - x_i, then on a
+ *    periodic axis dx -= L if dx > L/2, else dx += L if dx < -L/2;
+ *    d2 = (dx*dx + dy*dy) + dz*dz evaluated in FP64 without fused
+ *    multiply-adds, and r = rf_ratio * lambda_i.  Rows are gathered with the
+ *    centre's radius and the relation is not mutual (Sec. 2.1).
+ *  - The caller allocates and owns every input and output buffer.  The
+ *    library owns only the context, its workspace and its stream binding,
+ *    and never frees caller memory.
+ *  - Work is enqueued on the context's stream.  Calls that must size their
+ *    output (neighbor build, steps) read a few bytes back to the host and so
+ *    synchronize that stream; the others return without waiting.
+ *  - Return codes: PHB_OK (0) or a negative PHB_E* code.  Nothing throws
+ *    across this boundary.  phb_last_error() gives the message of the last
+ *    failure on a context.
+ *  - Per-particle numerical failure is not an error: status[i] is
+ *    PHB_STATUS_OK, PHB_STATUS_TOO_FEW (fewer than 20 neighbors, i itself
+ *    included) or PHB_STATUS_SINGULAR (the equilibrated 20x20 moment matrix
+ *    has a non-positive pivot or reciprocal condition estimate
+ *    (min L_kk / max L_kk)^2 below 1e-12), and that particle's derivative
+ *    outputs are NaN.
+ *  - Inputs are validated on the device before use: every position must be
+ *    finite and inside [0, L) on every axis, every lambda finite and
+ *    positive, and rf_ratio * lambda below L/2 on every periodic axis;
+ *    otherwise PHB_EINVAL.
+ */
+#ifndef PHURBAS_H
+#define PHURBAS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHB_OK 0
+#define PHB_EINVAL (-1)    /* bad argument or out-of-domain input data */
+#define PHB_ENOMEM (-2)    /* workspace allocation failed */
+#define PHB_ECAPACITY (-3) /* caller buffer too small; the needed size is reported */
+#define PHB_EHIP (-4)      /* HIP runtime error (see phb_last_error) */
+#define PHB_ESTATE (-5)    /* call not allowed in the context's current state */
+#define PHB_ENOTIMPL (-6)  /* option not built */
+
+#define PHB_FP64 0        /* all arithmetic in FP64 */
+#define PHB_MIXED 1       /* FP32 assembly and application, FP64 factor and solve,
+                             one data-level refinement step */
+#define PHB_W_POLY3 0     /* w = (1 - d^2/r_f^2)^3 */
+#define PHB_W_UNIT 1      /* w = 1 */
+#define PHB_FIT_FULL20 0  /* all 20 monomials, constant included */
+
+#define PHB_STATUS_OK 0
+#define PHB_STATUS_TOO_FEW 1
+#define PHB_STATUS_SINGULAR 2
+
+typedef struct phb_ctx phb_ctx;
+
+typedef struct {
+  double L[3];          /* box lengths; positions live in [0, L) */
+  int32_t periodic[3];  /* 1: minimum-image periodic axis, 0: open axis */
+  double gamma;         /* adiabatic index of P = (gamma - 1) sigma */
+  double rf_ratio;      /* r_f / lambda; the paper uses 2.3 */
+  int32_t precision;    /* PHB_FP64 or PHB_MIXED */
+  int32_t weight;       /* PHB_W_POLY3 or PHB_W_UNIT */
+  int32_t fit;          /* PHB_FIT_FULL20 */
+} phb_params;
+
+/* ---- context ------------------------------------------------------------
+ * phb_create: bind a new context to HIP device `device` and stream
+ * `hip_stream` (a hipStream_t; NULL = the default stream).  *out receives the
+ * context.  EINVAL on a null out or bad device; EHIP on runtime failure. */
+int phb_create(phb_ctx** out, int device, void* hip_stream);
+/* Release the context and its workspace (waits for its stream first). */
+int phb_destroy(phb_ctx* ctx);
+/* Rebind the context to another stream of the same device. */
+int phb_set_stream(phb_ctx* ctx, void* hip_stream);
+/* Grow the workspace for up to n_max particles and nnz_max neighbor entries
+ * so that later calls within those sizes allocate nothing. */
+int phb_reserve(phb_ctx* ctx, int64_t n_max, int64_t nnz_max);
+/* Static text for a return code. */
+const char* phb_strerror(int code);
+/* Message of the last failure on ctx (never NULL). */
+const char* phb_last_error(phb_ctx* ctx);
+
+/* ---- neighbor search (Sec. 2 and 2.1) ------------------------------------
+ * Build the CSR neighbor lists of n particles.  offsets: int64[n+1];
+ * idx: int32[idx_capacity].  *nnz_out (host) receives the total number of
+ * entries.  If it exceeds idx_capacity the call returns PHB_ECAPACITY, fills
+ * offsets but leaves idx unspecified; call again with a larger buffer.
+ * Synchronizes the context stream (sizes are read back).  n < 2^31. */
+int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                        const double* lambda, int64_t* offsets, int32_t* idx,
+                        int64_t idx_capacity, int64_t* nnz_out);
+
+/* Transposed lists for the reverse-mode kernels: t_offsets int64[n+1],
+ * t_src int32[nnz] (row j lists, ascending, every i whose row holds j),
+ * t_pos int32[nnz] (for forward entry s = (i, j): the index into t_src at
+ * which i appears in row j).  nnz = offsets[n].  Asynchronous. */
+int phb_neighbors_transpose(phb_ctx* ctx, int64_t n, int64_t nnz, const int64_t* offsets,
+                            const int32_t* idx, int64_t* t_offsets, int32_t* t_src,
+                            int32_t* t_pos);
+
+/* A spatially coherent particle order (Morton order of cells about r_f,min
+ * wide, ties by index): perm int32[n] lists caller indices in that order.
+ * The analogue of the Peano-Hilbert ordering of the paper's framework
+ * (Sec. 2.1); kernels run fastest on data permuted into it.  Synchronizes. */
+int phb_spatial_order(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                      const double* lambda, int32_t* perm);
+
+/* Gather rows: dst[c][k] = src[c][perm[k]] for c < ncomp, k < n.  src and
+ * dst must not overlap.  Asynchronous. */
+int phb_permute(phb_ctx* ctx, int64_t n, const int32_t* perm, int32_t ncomp, const double* src,
+                double* dst);
+
+/* ---- moving-least-squares derivatives (Sec. 2) ---------------------------
+ * For each particle fit f_j - f_i over its neighbors with the 20 monomials
+ * of xi = (x_j - x_i) / lambda_i (min-image), weighted, and return physical
+ * derivatives of nf fields: d1[nf][3][n] (d/dx, d/dy, d/dz) and, when
+ * max_order == 2, d2[nf][6][n] (xx, xy, xz, yy, yz, zz; d2 may be NULL when
+ * max_order == 1).  status int32[n].  Asynchronous. */
+int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                   const double* lambda, const int64_t* offsets, const int32_t* idx, int32_t nf,
+                   const double* fields, int32_t max_order, double* d1, double* d2,
+                   int32_t* status);
+
+/* ---- ideal-MHD time derivatives (Sec. 2; App. A without viscosity) -------
+ * rhs[8][n] = d/dt of (rho, V, B, sigma) following the particle:
+ *   drho/dt = -rho div V ; dV/dt = (-(gamma-1) grad sigma + (curl B) x B) / rho ;
+ *   dB/dt = (B . grad) V - B div V ; dsigma/dt = -gamma sigma div V ;
+ * dxdt[3][n] = V.  status int32[n].  tape: NULL or a device buffer of
+ * phb_tape_bytes(n) bytes that keeps what the reverse-mode call reuses.
+ * Asynchronous. */
+int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                const double* lambda, const int64_t* offsets, const int32_t* idx,
+                const double* q, double* rhs, double* dxdt, int32_t* status, void* tape);
+int64_t phb_tape_bytes(int64_t n);
+
+/* ---- reverse mode --------------------------------------------------------
+ * Gradient of  S = sum_i rhs_bar_i . rhs_i + dxdt_bar_i . dxdt_i  with respect
+ * to q (q_bar[8][n]) and positions (pos_bar[3][n]), neighbor lists held
+ * fixed.  dxdt_bar may be NULL (zero).  t_* come from
+ * phb_neighbors_transpose of the same lists.  tape: the buffer filled by
+ * phb_mhd_rhs on the same inputs, or NULL to recompute it.  Particles with
+ * nonzero status pass no gradient through rhs.  Outputs are overwritten.
+ * Deterministic: contributions are summed in a fixed order, without atomics.
+ * Asynchronous. */
+int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                        const double* lambda, const int64_t* offsets, const int32_t* idx,
+                        const int64_t* t_offsets, const int32_t* t_src, const int32_t* t_pos,
+                        const double* q, const double* rhs_bar, const double* dxdt_bar,
+                        double* q_bar, double* pos_bar, const void* tape);
+
+/* ---- predictor-corrector step (Sec. 2) -----------------------------------
+ * Advance (pos, q) in place by dt with Heun's trapezoidal scheme:
+ *   y* = y + dt F(y);  y <- y + dt/2 (F(y) + F(y*)),  y = (x, q),  F = (V, rhs),
+ * rebuilding the neighbor lists at the predicted state and wrapping positions
+ * into [0, L) on periodic axes after each stage.  On return offsets/idx hold
+ * the lists of the predicted state.  status[i] is the larger of the two
+ * stages' statuses.  PHB_ECAPACITY (with *nnz_out) when idx is too small;
+ * PHB_EINVAL when a particle leaves [0, L) on an open axis.  Synchronizes. */
+int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, double* pos, double* q,
+                const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+                int64_t* nnz_out, int32_t* status);
+
+/* ---- instrumentation -----------------------------------------------------
+ * phb_profile: enable (1) or disable (0) per-kernel timing on ctx; clears the
+ * totals.  While enabled every kernel launch is bracketed by HIP events on the
+ * context stream.  phb_profile_read: synchronizes the stream and reports up
+ * to max_entries kernels: names (host, 64 chars per entry, NUL-terminated),
+ * total_ms and counts (host arrays); *n_out (host) receives the number of
+ * distinct kernels seen. */
+int phb_profile(phb_ctx* ctx, int enable);
+int phb_profile_read(phb_ctx* ctx, int32_t max_entries, char* names, double* total_ms,
+                     int32_t* counts, int32_t* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHURBAS_H */

@@ -60,6 +60,9 @@ def lib():
         L.orc_mhd_rhs_adjoint.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, P, P, P, P, P, I]
         L.orc_adjoint_sampled.restype = I
         L.orc_adjoint_sampled.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, I64, P, P, P, I]
+        L.orc_adjoint_rows.restype = I
+        L.orc_adjoint_rows.argtypes = [I64, P, P, P, P, D, D, I, I, I64, P, P, P, P, P, P, P,
+                                       P, I]
         L.orc_pc_step.restype = I
         L.orc_pc_step.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, P, I]
         _lib = L
@@ -187,6 +190,28 @@ def mhd_rhs_adjoint(pos, lam, off, idx, q, rhs_bar, dxdt_bar=None, L=(1.0, 1.0, 
     if rc != 0:
         raise ValueError("orc_mhd_rhs_adjoint: invalid arguments")
     return qbar, pbar, st
+
+
+def adjoint_rows(pos, lam, off, idx, q, rhs_bar, rows, dxdt_bar=None, L=(1.0, 1.0, 1.0),
+                 periodic=(1, 1, 1), gamma=5.0 / 3.0, weight=0, fit=0, threads=0,
+                 rf_ratio=RF_RATIO):
+    """Contributions of the owner ``rows`` (CSR restricted to them) to (q_bar, pos_bar)."""
+    pos = _c(pos, np.float64)
+    lam = _c(lam, np.float64)
+    q = _c(q, np.float64)
+    n = lam.shape[0]
+    Lb, pb = _box(L, periodic)
+    r = _c(rows, np.int64)
+    qbar = np.zeros((8, n))
+    pbar = np.zeros((3, n))
+    xb = None if dxdt_bar is None else _c(dxdt_bar, np.float64)
+    rc = lib().orc_adjoint_rows(n, _p(pos), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight, fit,
+                                r.shape[0], _p(r), _p(_c(off, np.int64)), _p(_c(idx, np.int32)),
+                                _p(q), _p(_c(rhs_bar, np.float64)), _p(xb), _p(qbar), _p(pbar),
+                                threads)
+    if rc != 0:
+        raise ValueError("orc_adjoint_rows: invalid arguments")
+    return qbar, pbar
 
 
 def adjoint_sampled(pos, lam, q, rhs_bar, samples, dxdt_bar=None, L=(1.0, 1.0, 1.0),

@@ -758,6 +758,47 @@ int orc_mhd_rhs_adjoint(int64_t n, const double* pos, const double* lambda, cons
   return 0;
 }
 
+// Reverse-mode contributions of the listed owner rows only (CSR restricted to
+// those rows), accumulated into full q_bar (8 x n) and pos_bar (3 x n), which
+// are zeroed first.  With every row listed this is orc_mhd_rhs_adjoint; with a
+// sample of rows it is that sample's share of the work.
+int orc_adjoint_rows(int64_t n, const double* pos, const double* lambda, const double* L,
+                     const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
+                     int64_t nrows, const int64_t* rows, const int64_t* offsets,
+                     const int32_t* idx, const double* q, const double* rhs_bar,
+                     const double* dxdt_bar, double* q_bar, double* pos_bar, int nthreads) {
+  if (n <= 0 || nrows <= 0 || !rows || !offsets || !idx || !q || !rhs_bar || !q_bar || !pos_bar)
+    return -1;
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  std::vector<LocalAdj> all(nrows);
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    const int m = (int)(offsets[r + 1] - offsets[r]);
+    double gb[8], xb[3];
+    for (int f = 0; f < 8; ++f) gb[f] = rhs_bar[f * n + i];
+    if (dxdt_bar)
+      for (int a = 0; a < 3; ++a) xb[a] = dxdt_bar[a * n + i];
+    adjoint_particle(n, i, pos, lambda, idx + offsets[r], m, q, s, gb, dxdt_bar ? xb : nullptr,
+                     all[r]);
+  }
+  for (int64_t k = 0; k < 8 * n; ++k) q_bar[k] = 0.0;
+  for (int64_t k = 0; k < 3 * n; ++k) pos_bar[k] = 0.0;
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = rows[r];
+    for (int f = 0; f < 8; ++f) q_bar[f * n + i] += all[r].qb_self[f];
+    for (int a = 0; a < 3; ++a) pos_bar[a * n + i] += all[r].xb_self[a];
+    const int m = (int)(offsets[r + 1] - offsets[r]);
+    for (int k = 0; k < (int)all[r].xb.size() / 3 && k < m; ++k) {
+      const int64_t j = idx[offsets[r] + k];
+      for (int f = 0; f < 8; ++f) q_bar[f * n + j] += all[r].qb[k * 8 + f];
+      for (int a = 0; a < 3; ++a) pos_bar[a * n + j] += all[r].xb[k * 3 + a];
+    }
+  }
+  return 0;
+}
+
 // Gradient entries of the same scalar for a few sampled particles only, at
 // any n: finds every particle whose sphere holds the sample (brute force),
 // rebuilds those particles' neighbor lists (brute force), and sums their

@@ -1,0 +1,23 @@
+// Entry-point bodies built from several kernels: the reverse mode, the
+// mixed-precision evaluation and the predictor-corrector step.
+#pragma once
+
+#include "internal.hpp"
+#include "mls.hpp"
+
+namespace phb {
+
+int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
+                const int32_t* t_src, const int32_t* t_pos, const double* q,
+                const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
+                const double* tape);
+
+size_t mixed_rhs_bytes(int64_t n);
+int mixed_rhs(phb_ctx* ctx, const EvalArgs& a, double gamma, const double* q, double* rhs,
+              double* dxdt, int32_t* status, double* tape);
+
+int pc_step(phb_ctx* ctx, const phb_params* p, int n, double dt, double* pos, double* q,
+            const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+            int64_t* nnz_out, int32_t* status);
+
+}  // namespace phb

@@ -1,0 +1,536 @@
+// C-ABI entry points of libphurbas (see include/phurbas.h for the contract).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "internal.hpp"
+#include "mls.hpp"
+#include "neighbors.hpp"
+#include "adjoint.hpp"
+
+namespace phb {
+
+int set_error(phb_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return code;
+}
+
+int hip_check(phb_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return PHB_OK;
+  return set_error(ctx, PHB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int Workspace::commit() {
+  const size_t need = ctx->arena_base + total;
+  if (need <= ctx->arena_cap) return PHB_OK;
+  if (ctx->arena_base != 0)
+    return set_error(ctx, PHB_ESTATE, "nested workspace exceeds the reserved arena");
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_check(ctx, e, "workspace sync");
+  if (ctx->arena) hipFree(ctx->arena);
+  ctx->arena = nullptr;
+  ctx->arena_cap = 0;
+  const size_t want = need + need / 4 + (1 << 20);
+  e = hipMalloc((void**)&ctx->arena, want);
+  if (e != hipSuccess) {
+    ctx->arena = nullptr;
+    return set_error(ctx, PHB_ENOMEM, "workspace allocation of " + std::to_string(want) +
+                                          " bytes failed");
+  }
+  ctx->arena_cap = want;
+  return PHB_OK;
+}
+
+Box make_box(const phb_params* p) {
+  Box b;
+  for (int a = 0; a < 3; ++a) {
+    b.L[a] = p->L[a];
+    b.halfL[a] = 0.5 * p->L[a];
+    b.periodic[a] = p->periodic[a] ? 1 : 0;
+  }
+  return b;
+}
+
+static int ensure_host(phb_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->host_cap) return PHB_OK;
+  if (ctx->host) hipHostFree(ctx->host);
+  ctx->host = nullptr;
+  ctx->host_cap = 0;
+  hipError_t e = hipHostMalloc((void**)&ctx->host, bytes);
+  if (e != hipSuccess) return hip_check(ctx, e, "pinned host allocation");
+  ctx->host_cap = bytes;
+  return PHB_OK;
+}
+
+static int check_params(phb_ctx* ctx, const phb_params* p) {
+  if (!p) return set_error(ctx, PHB_EINVAL, "params is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!(p->L[a] > 0.0) || !isfinite(p->L[a]))
+      return set_error(ctx, PHB_EINVAL, "box length must be finite and positive");
+  if (!(p->rf_ratio > 0.0) || !isfinite(p->rf_ratio))
+    return set_error(ctx, PHB_EINVAL, "rf_ratio must be finite and positive");
+  if (p->precision != PHB_FP64 && p->precision != PHB_MIXED)
+    return set_error(ctx, PHB_EINVAL, "unknown precision");
+  if (p->weight != PHB_W_POLY3 && p->weight != PHB_W_UNIT)
+    return set_error(ctx, PHB_EINVAL, "unknown weight");
+  if (p->fit != PHB_FIT_FULL20) return set_error(ctx, PHB_ENOTIMPL, "only the 20-monomial fit");
+  return PHB_OK;
+}
+
+static int check_n(phb_ctx* ctx, int64_t n) {
+  if (n <= 0 || n >= (int64_t(1) << 31) - 1)
+    return set_error(ctx, PHB_EINVAL, "n must be in [1, 2^31 - 2]");
+  return PHB_OK;
+}
+
+// Device-side validation of positions and lambdas; returns min/max lambda.
+static constexpr int VALIDATE_BLOCKS = 512;
+static int validate_inputs(phb_ctx* ctx, const phb_params* p, int n, const double* pos,
+                           const double* lam, double* part, double* lmin, double* lmax) {
+  const Box box = make_box(p);
+  int rc = hip_check(ctx, launch_validate(ctx->stream, n, pos, lam, box, part, VALIDATE_BLOCKS),
+                     "validate");
+  if (rc) return rc;
+  if ((rc = ensure_host(ctx, 3 * VALIDATE_BLOCKS * sizeof(double)))) return rc;
+  rc = hip_check(ctx,
+                 hipMemcpyAsync(ctx->host, part, 3 * VALIDATE_BLOCKS * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream),
+                 "validate read-back");
+  if (rc) return rc;
+  if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "validate sync"))) return rc;
+  const double* h = reinterpret_cast<const double*>(ctx->host);
+  double mn = 1e300, mx = -1e300, bad = 0.0;
+  for (int b = 0; b < VALIDATE_BLOCKS; ++b) {
+    mn = std::min(mn, h[3 * b]);
+    mx = std::max(mx, h[3 * b + 1]);
+    bad = std::max(bad, h[3 * b + 2]);
+  }
+  if (bad != 0.0)
+    return set_error(ctx, PHB_EINVAL,
+                     "a position is outside [0, L) or not finite, or a lambda is not positive");
+  for (int a = 0; a < 3; ++a)
+    if (p->periodic[a] && !(p->rf_ratio * mx < 0.5 * p->L[a]))
+      return set_error(ctx, PHB_EINVAL, "r_f must stay below L/2 on periodic axes");
+  *lmin = mn;
+  *lmax = mx;
+  return PHB_OK;
+}
+
+static Grid make_grid(const phb_params* p, double rmin, int cells_per_rf, int64_t max_cells,
+                      int max_per_axis) {
+  Grid g;
+  double h = rmin / std::max(1, cells_per_rf);
+  for (;;) {
+    int64_t total = 1;
+    for (int a = 0; a < 3; ++a) {
+      double c = floor(p->L[a] / h);
+      if (c < 1) c = 1;
+      if (c > max_per_axis) c = max_per_axis;
+      g.nc[a] = (int)c;
+      total *= g.nc[a];
+    }
+    if (total <= max_cells) break;
+    h *= 1.26;
+  }
+  double hmin = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    g.inv_h[a] = g.nc[a] / p->L[a];
+    hmin = std::min(hmin, p->L[a] / g.nc[a]);
+  }
+  g.margin = 1e-6 * hmin;
+  return g;
+}
+
+// The grid is sized after validation, so its arrays are planned at the
+// largest allowed size.
+static const int64_t kMaxCells = int64_t(1) << 23;
+static void plan_neighbors(Workspace& ws, int64_t n, int64_t idx_capacity) {
+  ws.plan(3 * VALIDATE_BLOCKS * sizeof(double));
+  ws.plan((size_t)n * sizeof(int32_t));                 // key
+  ws.plan((size_t)(kMaxCells + 1) * sizeof(int32_t));   // cell count / cursor
+  ws.plan((size_t)(kMaxCells + 1) * sizeof(int32_t));   // cell start
+  ws.plan((size_t)scan_tmp_elems(kMaxCells) * sizeof(int32_t));
+  ws.plan((size_t)n * sizeof(int32_t));                 // sorted id
+  ws.plan((size_t)n * sizeof(double4));                 // sorted positions
+  ws.plan((size_t)n * sizeof(int32_t));                 // counts
+  ws.plan((size_t)scan_tmp_elems(n) * sizeof(int64_t));
+  ws.plan((size_t)std::max<int64_t>(idx_capacity, 1) * sizeof(int32_t));  // unsorted rows
+}
+
+static void plan_rhs(Workspace& ws, int64_t n, int precision);
+
+size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity) {
+  phb_ctx dummy;
+  Workspace ws(&dummy);
+  plan_neighbors(ws, n, idx_capacity);
+  return ws.total;
+}
+
+size_t ws_bytes_rhs(int64_t n, int precision) {
+  phb_ctx dummy;
+  Workspace ws(&dummy);
+  plan_rhs(ws, n, precision);
+  return ws.total;
+}
+
+static void plan_rhs(Workspace& ws, int64_t n, int precision) {
+  if (precision == PHB_MIXED) {
+    ws.plan(mixed_rhs_bytes(n));
+    return;
+  }
+  ws.plan((size_t)NMOM * n * sizeof(double));
+  ws.plan((size_t)3 * NBASIS * n * sizeof(double));
+}
+
+}  // namespace phb
+
+using namespace phb;
+
+extern "C" {
+
+const char* phb_strerror(int code) {
+  switch (code) {
+    case PHB_OK: return "ok";
+    case PHB_EINVAL: return "invalid argument";
+    case PHB_ENOMEM: return "out of memory";
+    case PHB_ECAPACITY: return "output buffer too small";
+    case PHB_EHIP: return "HIP runtime error";
+    case PHB_ESTATE: return "call not allowed in this state";
+    case PHB_ENOTIMPL: return "not implemented";
+    default: return "unknown error";
+  }
+}
+
+const char* phb_last_error(phb_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+int phb_create(phb_ctx** out, int device, void* hip_stream) {
+  if (!out) return PHB_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return PHB_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return PHB_EHIP;
+  phb_ctx* c = new phb_ctx();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  *out = c;
+  return PHB_OK;
+}
+
+int phb_destroy(phb_ctx* ctx) {
+  if (!ctx) return PHB_EINVAL;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->arena) hipFree(ctx->arena);
+  if (ctx->host) hipHostFree(ctx->host);
+  delete ctx;
+  return PHB_OK;
+}
+
+int phb_set_stream(phb_ctx* ctx, void* hip_stream) {
+  if (!ctx) return PHB_EINVAL;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return PHB_OK;
+}
+
+int phb_reserve(phb_ctx* ctx, int64_t n_max, int64_t nnz_max) {
+  if (!ctx || n_max < 0 || nnz_max < 0) return PHB_EINVAL;
+  Workspace ws(ctx);
+  ws.plan((size_t)n_max * 1600 + (size_t)nnz_max * 96 + (64 << 20));
+  return ws.commit();
+}
+
+int phb_profile(phb_ctx* ctx, int enable) {
+  if (!ctx) return PHB_EINVAL;
+  hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->prof_pending) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  ctx->prof_pending.clear();
+  ctx->prof_total.clear();
+  ctx->prof_on = enable != 0;
+  return PHB_OK;
+}
+
+int phb_profile_read(phb_ctx* ctx, int32_t max_entries, char* names, double* total_ms,
+                     int32_t* counts, int32_t* n_out) {
+  if (!ctx || !n_out || max_entries < 0) return PHB_EINVAL;
+  if (max_entries > 0 && (!names || !total_ms || !counts)) return PHB_EINVAL;
+  int rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "profile sync");
+  if (rc) return rc;
+  for (auto& r : ctx->prof_pending) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, r.a, r.b);
+    auto& t = ctx->prof_total[r.name];
+    t.first += ms;
+    t.second += 1;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  ctx->prof_pending.clear();
+  int k = 0;
+  for (auto& kv : ctx->prof_total) {
+    if (k < max_entries) {
+      strncpy(names + 64 * k, kv.first.c_str(), 63);
+      names[64 * k + 63] = 0;
+      total_ms[k] = kv.second.first;
+      counts[k] = kv.second.second;
+    }
+    ++k;
+  }
+  *n_out = k;
+  return PHB_OK;
+}
+
+int64_t phb_tape_bytes(int64_t n) { return n <= 0 ? 0 : n * 22 * (int64_t)sizeof(double); }
+
+int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                        const double* lambda, int64_t* offsets, int32_t* idx,
+                        int64_t idx_capacity, int64_t* nnz_out) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!pos || !lambda || !offsets || !nnz_out || idx_capacity < 0 || (idx_capacity > 0 && !idx))
+    return set_error(ctx, PHB_EINVAL, "null pointer or negative capacity");
+  hipSetDevice(ctx->device);
+  const int n = (int)n64;
+  const Box box = make_box(p);
+  const int64_t max_cells = kMaxCells;
+  Workspace ws(ctx);
+  plan_neighbors(ws, n, idx_capacity);
+  if ((rc = ws.commit())) return rc;
+  double* part = ws.take<double>(3 * VALIDATE_BLOCKS);
+  int32_t* key = ws.take<int32_t>(n);
+  int32_t* ccount = ws.take<int32_t>(max_cells + 1);
+  int32_t* cstart = ws.take<int32_t>(max_cells + 1);
+  int32_t* cscan = ws.take<int32_t>(scan_tmp_elems(max_cells));
+  int32_t* sid = ws.take<int32_t>(n);
+  double4* spos = ws.take<double4>(n);
+  int32_t* cnt = ws.take<int32_t>(n);
+  int64_t* oscan = ws.take<int64_t>(scan_tmp_elems(n));
+  int32_t* tmp = ws.take<int32_t>(std::max<int64_t>(idx_capacity, 1));
+
+  double lmin, lmax;
+  if ((rc = validate_inputs(ctx, p, n, pos, lambda, part, &lmin, &lmax))) return rc;
+  const Grid g = make_grid(p, p->rf_ratio * lmin, ctx->cells_per_rf, max_cells, 1024);
+  Prof pf_sort(ctx, "neighbors_cell_sort");
+  if ((rc = hip_check(ctx, launch_cell_sort(ctx->stream, n, pos, lambda, g, key, ccount, cstart,
+                                            cscan, sid, spos),
+                      "cell sort")))
+    return rc;
+  { Prof pf(ctx, "k_neighbors<false>");
+  if ((rc = hip_check(ctx, launch_neighbor_count(ctx->stream, n, box, g, p->rf_ratio, cstart, sid,
+                                                 spos, cnt),
+                      "neighbor count")))
+    return rc; }
+  if ((rc = hip_check(ctx, exclusive_scan_i32_to_i64(ctx->stream, cnt, n, offsets, oscan),
+                      "offset scan")))
+    return rc;
+  if ((rc = ensure_host(ctx, 64))) return rc;
+  if ((rc = hip_check(ctx,
+                      hipMemcpyAsync(ctx->host, offsets + n, sizeof(int64_t),
+                                     hipMemcpyDeviceToHost, ctx->stream),
+                      "nnz read-back")))
+    return rc;
+  if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "nnz sync"))) return rc;
+  const int64_t nnz = *reinterpret_cast<int64_t*>(ctx->host);
+  *nnz_out = nnz;
+  if (nnz > idx_capacity)
+    return set_error(ctx, PHB_ECAPACITY, "idx capacity " + std::to_string(idx_capacity) +
+                                             " < required " + std::to_string(nnz));
+  { Prof pf(ctx, "k_neighbors<true>");
+  if ((rc = hip_check(ctx, launch_neighbor_fill(ctx->stream, n, box, g, p->rf_ratio, cstart, sid,
+                                                spos, offsets, tmp),
+                      "neighbor fill")))
+    return rc; }
+  Prof pf_rs(ctx, "k_row_sort");
+  return hip_check(ctx, launch_row_sort(ctx->stream, n, offsets, tmp, idx), "row sort");
+}
+
+int phb_neighbors_transpose(phb_ctx* ctx, int64_t n64, int64_t nnz, const int64_t* offsets,
+                            const int32_t* idx, int64_t* t_offsets, int32_t* t_src,
+                            int32_t* t_pos) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_n(ctx, n64))) return rc;
+  if (nnz < 0 || !offsets || !t_offsets || (nnz > 0 && (!idx || !t_src || !t_pos)))
+    return set_error(ctx, PHB_EINVAL, "null pointer or negative nnz");
+  hipSetDevice(ctx->device);
+  const int n = (int)n64;
+  Workspace ws(ctx);
+  ws.plan((size_t)n * sizeof(int32_t));
+  ws.plan((size_t)scan_tmp_elems(n) * sizeof(int64_t));
+  ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+  if ((rc = ws.commit())) return rc;
+  int32_t* cnt = ws.take<int32_t>(n);
+  int64_t* scan = ws.take<int64_t>(scan_tmp_elems(n));
+  int32_t* tmp = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  return hip_check(ctx,
+                   launch_transpose(ctx->stream, n, nnz, offsets, idx, t_offsets, t_src, t_pos,
+                                    cnt, scan, tmp),
+                   "transpose");
+}
+
+int phb_spatial_order(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                      const double* lambda, int32_t* perm) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!pos || !lambda || !perm) return set_error(ctx, PHB_EINVAL, "null pointer");
+  hipSetDevice(ctx->device);
+  const int n = (int)n64;
+  const int max_bits = 7;
+  const int64_t nbins_max = int64_t(1) << (3 * max_bits);
+  Workspace ws(ctx);
+  ws.plan(3 * VALIDATE_BLOCKS * sizeof(double));
+  ws.plan((size_t)n * sizeof(int32_t));
+  ws.plan((size_t)(nbins_max + 1) * sizeof(int32_t));
+  ws.plan((size_t)(nbins_max + 1) * sizeof(int32_t));
+  ws.plan((size_t)scan_tmp_elems(nbins_max) * sizeof(int32_t));
+  if ((rc = ws.commit())) return rc;
+  double* part = ws.take<double>(3 * VALIDATE_BLOCKS);
+  int32_t* key = ws.take<int32_t>(n);
+  int32_t* bcount = ws.take<int32_t>(nbins_max + 1);
+  int32_t* bstart = ws.take<int32_t>(nbins_max + 1);
+  int32_t* bscan = ws.take<int32_t>(scan_tmp_elems(nbins_max));
+  double lmin, lmax;
+  if ((rc = validate_inputs(ctx, p, n, pos, lambda, part, &lmin, &lmax))) return rc;
+  // power-of-two cells per axis, about r_f,min wide
+  const double rmin = p->rf_ratio * lmin;
+  const double lmaxbox = std::max(p->L[0], std::max(p->L[1], p->L[2]));
+  int bits = 0;
+  while (bits < max_bits && lmaxbox / (1 << (bits + 1)) >= rmin) ++bits;
+  Grid g;
+  for (int a = 0; a < 3; ++a) {
+    g.nc[a] = 1 << bits;
+    g.inv_h[a] = g.nc[a] / p->L[a];
+  }
+  g.margin = 0.0;
+  return hip_check(ctx, launch_morton_order(ctx->stream, n, pos, g, key, bcount, bstart, bscan,
+                                            perm),
+                   "spatial order");
+}
+
+int phb_permute(phb_ctx* ctx, int64_t n64, const int32_t* perm, int32_t ncomp, const double* src,
+                double* dst) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_n(ctx, n64))) return rc;
+  if (!perm || !src || !dst || ncomp <= 0) return set_error(ctx, PHB_EINVAL, "bad arguments");
+  hipSetDevice(ctx->device);
+  return hip_check(ctx, launch_permute(ctx->stream, (int)n64, ncomp, perm, src, dst), "permute");
+}
+
+static int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                     const double* lambda, const int64_t* offsets, const int32_t* idx,
+                     EvalArgs* a) {
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!pos || !lambda || !offsets || !idx) return set_error(ctx, PHB_EINVAL, "null pointer");
+  a->n = (int)n64;
+  a->pos = pos;
+  a->lam = lambda;
+  a->off = offsets;
+  a->idx = idx;
+  a->box = make_box(p);
+  a->rf_ratio = p->rf_ratio;
+  a->wkind = p->weight;
+  return PHB_OK;
+}
+
+int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                   const double* lambda, const int64_t* offsets, const int32_t* idx, int32_t nf,
+                   const double* fields, int32_t max_order, double* d1, double* d2,
+                   int32_t* status) {
+  if (!ctx) return PHB_EINVAL;
+  EvalArgs a;
+  int rc;
+  if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
+  if (nf <= 0 || !fields || !d1 || !status || (max_order != 1 && max_order != 2) ||
+      (max_order == 2 && !d2))
+    return set_error(ctx, PHB_EINVAL, "bad field arguments");
+  if (p->precision != PHB_FP64)
+    return set_error(ctx, PHB_ENOTIMPL, "derivatives are built in FP64 only");
+  hipSetDevice(ctx->device);
+  const int n = a.n;
+  Workspace ws(ctx);
+  ws.plan((size_t)NMOM * n * sizeof(double));
+  ws.plan((size_t)9 * NBASIS * n * sizeof(double));
+  if ((rc = ws.commit())) return rc;
+  double* mom = ws.take<double>((size_t)NMOM * n);
+  double* gop = ws.take<double>((size_t)9 * NBASIS * n);
+  { Prof pf(ctx, "k_moments");
+  if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
+    return rc; }
+  { Prof pf(ctx, "k_factor<9>");
+  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, 9, mom, gop, status), "factor")))
+    return rc; }
+  Prof pf(ctx, "k_apply_derivs");
+  return hip_check(ctx,
+                   launch_apply_derivs(ctx->stream, a, ctx->lanes_apply, gop, status, nf, fields,
+                                       d1, max_order == 2 ? d2 : nullptr),
+                   "apply derivatives");
+}
+
+int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                const double* lambda, const int64_t* offsets, const int32_t* idx,
+                const double* q, double* rhs, double* dxdt, int32_t* status, void* tape) {
+  if (!ctx) return PHB_EINVAL;
+  EvalArgs a;
+  int rc;
+  if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
+  if (!q || !rhs || !dxdt || !status) return set_error(ctx, PHB_EINVAL, "null pointer");
+  hipSetDevice(ctx->device);
+  if (p->precision == PHB_MIXED)
+    return mixed_rhs(ctx, a, p->gamma, q, rhs, dxdt, status, reinterpret_cast<double*>(tape));
+  const int n = a.n;
+  Workspace ws(ctx);
+  plan_rhs(ws, n, PHB_FP64);
+  if ((rc = ws.commit())) return rc;
+  double* mom = ws.take<double>((size_t)NMOM * n);
+  double* gop = ws.take<double>((size_t)3 * NBASIS * n);
+  { Prof pf(ctx, "k_moments");
+  if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
+    return rc; }
+  { Prof pf(ctx, "k_factor<3>");
+  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, 3, mom, gop, status), "factor")))
+    return rc; }
+  Prof pf(ctx, "k_apply_rhs");
+  return hip_check(ctx,
+                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, gop, status, q,
+                                    rhs, dxdt, reinterpret_cast<double*>(tape)),
+                   "apply rhs");
+}
+
+int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                        const double* lambda, const int64_t* offsets, const int32_t* idx,
+                        const int64_t* t_offsets, const int32_t* t_src, const int32_t* t_pos,
+                        const double* q, const double* rhs_bar, const double* dxdt_bar,
+                        double* q_bar, double* pos_bar, const void* tape) {
+  if (!ctx) return PHB_EINVAL;
+  EvalArgs a;
+  int rc;
+  if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
+  if (!t_offsets || !t_src || !t_pos || !q || !rhs_bar || !q_bar || !pos_bar)
+    return set_error(ctx, PHB_EINVAL, "null pointer");
+  hipSetDevice(ctx->device);
+  return adjoint_rhs(ctx, a, p, t_offsets, t_src, t_pos, q, rhs_bar, dxdt_bar, q_bar, pos_bar,
+                     reinterpret_cast<const double*>(tape));
+}
+
+int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt, double* pos, double* q,
+                const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+                int64_t* nnz_out, int32_t* status) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!pos || !q || !lambda || !offsets || !idx || !nnz_out || !status || !isfinite(dt))
+    return set_error(ctx, PHB_EINVAL, "bad arguments");
+  hipSetDevice(ctx->device);
+  return pc_step(ctx, p, (int)n64, dt, pos, q, lambda, offsets, idx, idx_capacity, nnz_out,
+                 status);
+}
+
+}  // extern "C"

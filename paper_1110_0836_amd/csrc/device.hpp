@@ -1,0 +1,232 @@
+// Device helpers shared by the gfx950 kernels of libphurbas.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace phb {
+
+// ---------------------------------------------------------------------------
+// Polynomial basis.  The 20 monomials of degree <= 3 in xi = (x, y, z), in the
+// order 1; x,y,z; xx,xy,xz,yy,yz,zz; xxx,xxy,xxz,xyy,xyz,xzz,yyy,yyz,yzz,zzz.
+// The moment matrix A = sum_j w_j p(xi_j) p(xi_j)^T has entries that are
+// weighted sums of the 84 distinct monomials of degree <= 6; those sums are
+// the "moments".
+// ---------------------------------------------------------------------------
+struct Expo {
+  int a, b, c;
+};
+
+__host__ __device__ constexpr Expo basis_expo(int k) {
+  constexpr int E[20][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {2, 0, 0},
+                            {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
+                            {3, 0, 0}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 1, 1},
+                            {1, 0, 2}, {0, 3, 0}, {0, 2, 1}, {0, 1, 2}, {0, 0, 3}};
+  return Expo{E[k][0], E[k][1], E[k][2]};
+}
+
+// Index of monomial x^a y^b z^c (a+b+c <= 6) among the 84 moments, ordered
+// by a, then b, then c.
+__host__ __device__ constexpr int moment_index(int a, int b, int c) {
+  int idx = 0;
+  for (int aa = 0; aa < a; ++aa) {
+    const int m = 6 - aa;
+    idx += (m + 1) * (m + 2) / 2;
+  }
+  for (int bb = 0; bb < b; ++bb) idx += 6 - a - bb + 1;
+  return idx + c;
+}
+
+constexpr int NMOM = 84;
+constexpr int NBASIS = 20;
+
+__host__ __device__ constexpr int entry_moment(int r, int s) {
+  return moment_index(basis_expo(r).a + basis_expo(s).a, basis_expo(r).b + basis_expo(s).b,
+                      basis_expo(r).c + basis_expo(s).c);
+}
+
+// All 84 weighted monomials w x^a y^b z^c accumulated into m[].  Fully
+// unrolled: every index is a compile-time constant, so m[] stays in VGPRs.
+template <class T>
+__device__ __forceinline__ void accumulate_moments(T (&m)[NMOM], T w, T x, T y, T z) {
+  T zp[7];
+  zp[0] = T(1);
+#pragma unroll
+  for (int c = 1; c < 7; ++c) zp[c] = zp[c - 1] * z;
+  T wx = w;
+#pragma unroll
+  for (int a = 0; a < 7; ++a) {
+    T wxy = wx;
+#pragma unroll
+    for (int b = 0; b + a < 7; ++b) {
+#pragma unroll
+      for (int c = 0; a + b + c < 7; ++c) {
+        const int k = moment_index(a, b, c);
+        if (c == 0)
+          m[k] += wxy;
+        else
+          m[k] = fma(wxy, zp[c], m[k]);
+      }
+      wxy = wxy * y;
+    }
+    wx = wx * x;
+  }
+}
+
+// The 20 basis monomials at (x, y, z).
+template <class T>
+__device__ __forceinline__ void basis(T (&p)[NBASIS], T x, T y, T z) {
+  const T xx = x * x, yy = y * y, zz = z * z;
+  p[0] = T(1);
+  p[1] = x;
+  p[2] = y;
+  p[3] = z;
+  p[4] = xx;
+  p[5] = x * y;
+  p[6] = x * z;
+  p[7] = yy;
+  p[8] = y * z;
+  p[9] = zz;
+  p[10] = xx * x;
+  p[11] = xx * y;
+  p[12] = xx * z;
+  p[13] = x * yy;
+  p[14] = p[5] * z;
+  p[15] = x * zz;
+  p[16] = yy * y;
+  p[17] = yy * z;
+  p[18] = y * zz;
+  p[19] = zz * z;
+}
+
+// d p_k / d xi_axis for all k, at (x, y, z).
+template <class T>
+__device__ __forceinline__ void basis_grad(T (&gx)[NBASIS], T (&gy)[NBASIS], T (&gz)[NBASIS],
+                                           T x, T y, T z) {
+  const T xx = x * x, yy = y * y, zz = z * z;
+  const T xy = x * y, xz = x * z, yz = y * z;
+  // d/dx
+  gx[0] = 0; gx[1] = 1; gx[2] = 0; gx[3] = 0;
+  gx[4] = 2 * x; gx[5] = y; gx[6] = z; gx[7] = 0; gx[8] = 0; gx[9] = 0;
+  gx[10] = 3 * xx; gx[11] = 2 * xy; gx[12] = 2 * xz; gx[13] = yy; gx[14] = yz;
+  gx[15] = zz; gx[16] = 0; gx[17] = 0; gx[18] = 0; gx[19] = 0;
+  // d/dy
+  gy[0] = 0; gy[1] = 0; gy[2] = 1; gy[3] = 0;
+  gy[4] = 0; gy[5] = x; gy[6] = 0; gy[7] = 2 * y; gy[8] = z; gy[9] = 0;
+  gy[10] = 0; gy[11] = xx; gy[12] = 0; gy[13] = 2 * xy; gy[14] = xz;
+  gy[15] = 0; gy[16] = 3 * yy; gy[17] = 2 * yz; gy[18] = zz; gy[19] = 0;
+  // d/dz
+  gz[0] = 0; gz[1] = 0; gz[2] = 0; gz[3] = 1;
+  gz[4] = 0; gz[5] = 0; gz[6] = x; gz[7] = 0; gz[8] = y; gz[9] = 2 * z;
+  gz[10] = 0; gz[11] = 0; gz[12] = xx; gz[13] = 0; gz[14] = xy;
+  gz[15] = 2 * xz; gz[16] = 0; gz[17] = yy; gz[18] = 2 * yz; gz[19] = 3 * zz;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry
+// ---------------------------------------------------------------------------
+struct Box {
+  double L[3];
+  double halfL[3];
+  int periodic[3];
+};
+
+__device__ __forceinline__ double min_image(double d, double L, double halfL, int periodic) {
+  if (periodic) {
+    if (d > halfL)
+      d -= L;
+    else if (d < -halfL)
+      d += L;
+  }
+  return d;
+}
+
+// The neighbor predicate's squared distance, evaluated exactly as
+// (dx*dx + dy*dy) + dz*dz with no fused multiply-add.
+__device__ __forceinline__ double dist2_nofma(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+  const double a = dx * dx;
+  const double b = dy * dy;
+  const double c = dz * dz;
+  return (a + b) + c;
+}
+
+__device__ __forceinline__ double radius2_nofma(double rf_ratio, double lam) {
+#pragma clang fp contract(off)
+  const double r = rf_ratio * lam;
+  return r * r;
+}
+
+// Weight reading: w = (1 - q)^3, q = d^2 / r_f^2 (kind 0) or w = 1 (kind 1).
+template <class T>
+__device__ __forceinline__ T weight_of(T q, int kind) {
+  if (kind == 1) return T(1);
+  const T u = T(1) - q;
+  return u * u * u;
+}
+template <class T>
+__device__ __forceinline__ T weight_dq(T q, int kind) {
+  if (kind == 1) return T(0);
+  const T u = T(1) - q;
+  return T(-3) * u * u;
+}
+
+// ---------------------------------------------------------------------------
+// Cross-lane exchange inside groups of 4 lanes (DPP quad permutes).
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// quad_perm selectors: lane l of each quad reads lane sel[l].
+constexpr int QP_XOR1 = 0xB1;  // [1,0,3,2]
+constexpr int QP_XOR2 = 0x4E;  // [2,3,0,1]
+template <int O>
+constexpr int qp_bcast() {
+  return O * 0x55;
+}
+
+template <class T>
+__device__ __forceinline__ T quad_xor1(T v);
+template <>
+__device__ __forceinline__ double quad_xor1(double v) { return dpp_f64<QP_XOR1>(v); }
+template <>
+__device__ __forceinline__ float quad_xor1(float v) { return dpp_f32<QP_XOR1>(v); }
+template <class T>
+__device__ __forceinline__ T quad_xor2(T v);
+template <>
+__device__ __forceinline__ double quad_xor2(double v) { return dpp_f64<QP_XOR2>(v); }
+template <>
+__device__ __forceinline__ float quad_xor2(float v) { return dpp_f32<QP_XOR2>(v); }
+
+// Sum over the G consecutive lanes of a group (G = 1, 2 or 4); every lane of
+// the group receives the total.
+template <int G, class T>
+__device__ __forceinline__ T group_sum(T v) {
+  if constexpr (G >= 2) v += quad_xor1(v);
+  if constexpr (G >= 4) v += quad_xor2(v);
+  return v;
+}
+
+template <int O>
+__device__ __forceinline__ double quad_bcast(double v) {
+  return dpp_f64<qp_bcast<O>()>(v);
+}
+
+__device__ __forceinline__ double quad_min(double v) {
+  v = fmin(v, dpp_f64<QP_XOR1>(v));
+  return fmin(v, dpp_f64<QP_XOR2>(v));
+}
+__device__ __forceinline__ double quad_max(double v) {
+  v = fmax(v, dpp_f64<QP_XOR1>(v));
+  return fmax(v, dpp_f64<QP_XOR2>(v));
+}
+
+}  // namespace phb

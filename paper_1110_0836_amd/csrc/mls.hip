@@ -1,0 +1,474 @@
+// Moving-least-squares derivatives and ideal-MHD time derivatives
+// (paper II, Sec. 2) in FP64.
+//
+// Three kernels per evaluation:
+//  1. k_moments: for each particle, the 84 distinct weighted moments
+//     sum_j w_j xi_j^alpha (|alpha| <= 6) that make up the 20x20 normal
+//     matrix A = sum_j w_j p(xi_j) p(xi_j)^T.  G lanes share one particle's
+//     neighbor list and combine their partial sums with DPP quad permutes.
+//  2. k_factor: four lanes per particle hold A row-cyclically (lane l owns
+//     rows l, l+4, ...), Jacobi-equilibrate it, factor it by Cholesky in FP64
+//     and solve for the requested rows of A^{-1} (the derivative operator in
+//     monomial space): G = E A^{-1}, E selecting the gradient (and Hessian)
+//     monomials.
+//  3. k_apply_*: for each neighbor, gamma_j = w_j G p(xi_j) are the operator
+//     weights; derivatives are sum_j gamma_j (f_j - f_i) scaled by powers of
+//     1/lambda_i, followed (for the time derivatives) by the pointwise
+//     ideal-MHD right-hand side.
+// This "operator" form needs 84 + 3x20 accumulations per neighbor instead of
+// the 84 + 20 x nfields of solving for every field's coefficients.
+#include <type_traits>
+
+#include "internal.hpp"
+#include "mls.hpp"
+
+namespace phb {
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+namespace {
+
+constexpr int THREADS = 256;
+
+struct EntryTable {
+  unsigned char v[NBASIS * NBASIS];
+};
+constexpr EntryTable make_entry_table() {
+  EntryTable t{};
+  for (int r = 0; r < NBASIS; ++r)
+    for (int c = 0; c < NBASIS; ++c) t.v[r * NBASIS + c] = (unsigned char)entry_moment(r, c);
+  return t;
+}
+__constant__ EntryTable c_entry = make_entry_table();
+
+// ---------------------------------------------------------------------------
+// 1. moments
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(THREADS)
+    k_moments(int n, const double* __restrict__ pos, const double* __restrict__ lam,
+              const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
+              double rf_ratio, int wkind, double* __restrict__ mom) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid / G;
+  const int l = tid % G;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  double m[NMOM];
+#pragma unroll
+  for (int k = 0; k < NMOM; ++k) m[k] = 0.0;
+  const double xi = pos[ii], yi = pos[(int64_t)n + ii], zi = pos[2 * (int64_t)n + ii];
+  const double li = lam[ii];
+  const double inv_lam = 1.0 / li;
+  const double r = rf_ratio * li;
+  const double inv_r2 = 1.0 / (r * r);
+  const int64_t s0 = off[ii], s1 = valid ? off[ii + 1] : s0;
+  for (int64_t s = s0 + l; s < s1; s += G) {
+    const int j = idx[s];
+    const double dx = min_image(pos[j] - xi, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(pos[(int64_t)n + j] - yi, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz =
+        min_image(pos[2 * (int64_t)n + j] - zi, box.L[2], box.halfL[2], box.periodic[2]);
+    const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
+    const double w = weight_of(qd, wkind);
+    accumulate_moments(m, w, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+  }
+#pragma unroll
+  for (int k = 0; k < NMOM; ++k) m[k] = group_sum<G>(m[k]);
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k)
+      if (k % G == l) mom[(int64_t)k * n + i] = m[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 2. factor: equilibrated FP64 Cholesky, four lanes per particle
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int aoff(int rho) { return 2 * rho * (rho + 1); }
+
+// Writes rows first_target .. first_target+NT-1 of A^{-1} to gop[t][20][n].
+template <int NT>
+__global__ void __launch_bounds__(THREADS)
+    k_factor(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
+             double* __restrict__ gop, int32_t* __restrict__ status) {
+  constexpr int T0 = 1;  // first target row: the x monomial
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid >> 2;
+  const int l = tid & 3;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+
+  double a[60];     // own rows, row rho at a[aoff(rho) .. aoff(rho) + 4 rho + 3]
+  double dg[5];     // own diagonal entries
+  static_for<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    const int r = 4 * rho + l;
+    static_for<0, 4 * rho + 4>([&](auto C) {
+      constexpr int c = C;
+      a[aoff(rho) + c] = mom[(int64_t)c_entry.v[r * NBASIS + c] * n + ii];
+    });
+    dg[rho] = mom[(int64_t)c_entry.v[r * NBASIS + r] * n + ii];
+  });
+
+  // Jacobi equilibration: A_hat = S A S, S = diag(1/sqrt(A_rr)).
+  bool ok = true;
+  double s_own[5];
+  static_for<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    ok = ok && (dg[rho] > 0.0);
+    s_own[rho] = dg[rho] > 0.0 ? 1.0 / sqrt(dg[rho]) : 1.0;
+  });
+  double s_all[NBASIS];
+  static_for<0, NBASIS>([&](auto C) {
+    constexpr int c = C;
+    s_all[c] = quad_bcast<c & 3>(s_own[c >> 2]);
+  });
+  static_for<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    static_for<0, 4 * rho + 4>([&](auto C) {
+      constexpr int c = C;
+      a[aoff(rho) + c] *= s_own[rho] * s_all[c];
+    });
+  });
+
+  // Right-looking Cholesky.  Entries right of a lane's own diagonal hold
+  // scratch values that are never read.
+  double inv_ld[NBASIS];
+  double ldmin = 1e300, ldmax = 0.0;
+  static_for<0, NBASIS>([&](auto K) {
+    constexpr int k = K;
+    constexpr int o = k & 3;
+    constexpr int rk = k >> 2;
+    const double dkk = quad_bcast<o>(a[aoff(rk) + k]);
+    ok = ok && (dkk > 0.0);
+    const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0);
+    ldmin = fmin(ldmin, lkk);
+    ldmax = fmax(ldmax, lkk);
+    const double inv = 1.0 / lkk;
+    inv_ld[k] = inv;
+    static_for<rk, 5>([&](auto R) {
+      constexpr int rho = R;
+      a[aoff(rho) + k] *= inv;
+    });
+    double colk[NBASIS];
+    static_for<k + 1, NBASIS>([&](auto C) {
+      constexpr int c = C;
+      colk[c] = quad_bcast<c & 3>(a[aoff(c >> 2) + k]);
+    });
+    static_for<rk, 5>([&](auto R) {
+      constexpr int rho = R;
+      static_for<k + 1, 4 * rho + 4>([&](auto C) {
+        constexpr int c = C;
+        a[aoff(rho) + c] = fma(-a[aoff(rho) + k], colk[c], a[aoff(rho) + c]);
+      });
+    });
+  });
+  const double rc = ldmin / ldmax;
+  const int nnb = (int)(off[ii + 1] - off[ii]);
+  int st = PHB_STATUS_OK;
+  if (nnb < NBASIS)
+    st = PHB_STATUS_TOO_FEW;
+  else if (!ok || !(rc * rc >= 1e-12))
+    st = PHB_STATUS_SINGULAR;
+
+  // Rows of A_hat^{-1}: forward then backward substitution per unit vector.
+  static_for<0, NT>([&](auto TI) {
+    constexpr int t = T0 + TI;
+    double y[5];
+    static_for<0, 5>([&](auto R) {
+      constexpr int rho = R;
+      y[rho] = (4 * rho + l == t) ? 1.0 : 0.0;
+    });
+    static_for<t, NBASIS>([&](auto K) {
+      constexpr int k = K;
+      constexpr int o = k & 3;
+      constexpr int rk = k >> 2;
+      const double yk = quad_bcast<o>(y[rk]) * inv_ld[k];
+      static_for<rk + 1, 5>([&](auto R) {
+        constexpr int rho = R;
+        y[rho] = fma(-a[aoff(rho) + k], yk, y[rho]);
+      });
+      const double upd = fma(-a[aoff(rk) + k], yk, y[rk]);
+      y[rk] = (l == o) ? yk : ((l > o) ? upd : y[rk]);
+    });
+    double x[5];
+    static_for<0, 5>([&](auto R) { x[R] = y[R]; });
+    static_for<0, NBASIS>([&](auto KK) {
+      constexpr int k = NBASIS - 1 - KK;
+      constexpr int o = k & 3;
+      constexpr int rk = k >> 2;
+      double part = 0.0;
+      static_for<rk + 1, 5>([&](auto R) {
+        constexpr int rho = R;
+        part = fma(a[aoff(rho) + k], x[rho], part);
+      });
+      part += (l > o) ? a[aoff(rk) + k] * x[rk] : 0.0;
+      part = group_sum<4>(part);
+      const double xk = (y[rk] - part) * inv_ld[k];
+      x[rk] = (l == o) ? xk : x[rk];
+    });
+    if (valid) {
+      static_for<0, 5>([&](auto R) {
+        constexpr int rho = R;
+        const int r = 4 * rho + l;
+        gop[((int64_t)TI * NBASIS + r) * n + i] = s_all[t] * x[rho] * s_own[rho];
+      });
+    }
+  });
+  if (valid && l == 0) status[i] = st;
+}
+
+// ---------------------------------------------------------------------------
+// 3a. derivatives of up to 8 fields for three operator rows
+// ---------------------------------------------------------------------------
+constexpr int FCHUNK = 8;
+
+template <int G>
+__global__ void __launch_bounds__(THREADS)
+    k_apply_derivs(int n, const double* __restrict__ pos, const double* __restrict__ lam,
+                   const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
+                   double rf_ratio, int wkind, const double* __restrict__ gop, int row0,
+                   const int32_t* __restrict__ status, int nf, int f0,
+                   const double* __restrict__ fields, double* __restrict__ out, int out_comp,
+                   int comp0, double c0, double c1, double c2, int power) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid / G;
+  const int l = tid % G;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  const int st = status[ii];
+  double g[3][NBASIS];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) g[t][b] = gop[((int64_t)(row0 + t) * NBASIS + b) * n + ii];
+  const int nfc = (nf - f0) < FCHUNK ? (nf - f0) : FCHUNK;
+  double fi[FCHUNK];
+#pragma unroll
+  for (int f = 0; f < FCHUNK; ++f) fi[f] = f < nfc ? fields[(int64_t)(f0 + f) * n + ii] : 0.0;
+  const double xi = pos[ii], yi = pos[(int64_t)n + ii], zi = pos[2 * (int64_t)n + ii];
+  const double li = lam[ii];
+  const double inv_lam = 1.0 / li;
+  const double r = rf_ratio * li;
+  const double inv_r2 = 1.0 / (r * r);
+  double acc[FCHUNK][3];
+#pragma unroll
+  for (int f = 0; f < FCHUNK; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
+  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
+  for (int64_t s = s0 + l; s < s1; s += G) {
+    const int j = idx[s];
+    const double dx = min_image(pos[j] - xi, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(pos[(int64_t)n + j] - yi, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz =
+        min_image(pos[2 * (int64_t)n + j] - zi, box.L[2], box.halfL[2], box.periodic[2]);
+    const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+    double p[NBASIS];
+    basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    double gam[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      double v = 0.0;
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b) v = fma(g[t][b], p[b], v);
+      gam[t] = w * v;
+    }
+#pragma unroll
+    for (int f = 0; f < FCHUNK; ++f) {
+      if (f < nfc) {
+        const double df = fields[(int64_t)(f0 + f) * n + j] - fi[f];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) acc[f][t] = fma(gam[t], df, acc[f][t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < FCHUNK; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[f][t] = group_sum<G>(acc[f][t]);
+  if (valid && l == 0) {
+    const double scale = power == 1 ? inv_lam : inv_lam * inv_lam;
+    const double cf[3] = {c0, c1, c2};
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    for (int f = 0; f < nfc; ++f)
+      for (int t = 0; t < 3; ++t)
+        out[((int64_t)(f0 + f) * out_comp + comp0 + t) * n + i] =
+            st == 0 ? cf[t] * acc[f][t] * scale : nan;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3b. ideal-MHD time derivatives
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ void __launch_bounds__(THREADS)
+    k_apply_rhs(int n, const double* __restrict__ pos, const double* __restrict__ lam,
+                const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
+                double rf_ratio, int wkind, double gamma, const double* __restrict__ gop,
+                const int32_t* __restrict__ status, const double* __restrict__ q,
+                double* __restrict__ rhs, double* __restrict__ dxdt, double* __restrict__ tape) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid / G;
+  const int l = tid % G;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  const int st = status[ii];
+  double g[3][NBASIS];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) g[t][b] = gop[((int64_t)t * NBASIS + b) * n + ii];
+  double qi[8];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) qi[f] = q[(int64_t)f * n + ii];
+  const double xi = pos[ii], yi = pos[(int64_t)n + ii], zi = pos[2 * (int64_t)n + ii];
+  const double li = lam[ii];
+  const double inv_lam = 1.0 / li;
+  const double r = rf_ratio * li;
+  const double inv_r2 = 1.0 / (r * r);
+  double acc[7][3];
+#pragma unroll
+  for (int f = 0; f < 7; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
+  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
+  for (int64_t s = s0 + l; s < s1; s += G) {
+    const int j = idx[s];
+    const double dx = min_image(pos[j] - xi, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(pos[(int64_t)n + j] - yi, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz =
+        min_image(pos[2 * (int64_t)n + j] - zi, box.L[2], box.halfL[2], box.periodic[2]);
+    const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+    double p[NBASIS];
+    basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    double gam[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      double v = 0.0;
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b) v = fma(g[t][b], p[b], v);
+      gam[t] = w * v;
+    }
+#pragma unroll
+    for (int f = 0; f < 7; ++f) {
+      const double df = q[(int64_t)(f + 1) * n + j] - qi[f + 1];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[f][t] = fma(gam[t], df, acc[f][t]);
+    }
+  }
+  double grad[7][3];
+#pragma unroll
+  for (int f = 0; f < 7; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) grad[f][t] = group_sum<G>(acc[f][t]) * inv_lam;
+  if (valid && l == 0) {
+    double out[8];
+    if (st == 0) {
+      mhd_point(qi, grad, gamma, out);
+    } else {
+      const double nan = __longlong_as_double(0x7ff8000000000000LL);
+#pragma unroll
+      for (int f = 0; f < 8; ++f) out[f] = nan;
+    }
+#pragma unroll
+    for (int f = 0; f < 8; ++f) rhs[(int64_t)f * n + i] = out[f];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dxdt[(int64_t)a * n + i] = qi[1 + a];
+    if (tape) {  // gradients (7 x 3) and the status, for the reverse mode
+#pragma unroll
+      for (int f = 0; f < 7; ++f)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + i] = grad[f][t];
+      tape[(int64_t)21 * n + i] = (double)st;
+    }
+  }
+}
+
+template <int G>
+hipError_t launch_moments_g(hipStream_t s, const EvalArgs& a, double* mom) {
+  hipLaunchKernelGGL((k_moments<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0, s,
+                     a.n, a.pos, a.lam, a.off, a.idx, a.box, a.rf_ratio, a.wkind, mom);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom) {
+  switch (lanes) {
+    case 1: return launch_moments_g<1>(s, a, mom);
+    case 2: return launch_moments_g<2>(s, a, mom);
+    default: return launch_moments_g<4>(s, a, mom);
+  }
+}
+
+hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,
+                         double* gop, int32_t* status) {
+  const unsigned grid = grid_for((int64_t)a.n * 4, THREADS);
+  if (ntargets == 3)
+    hipLaunchKernelGGL((k_factor<3>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status);
+  else
+    hipLaunchKernelGGL((k_factor<9>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status);
+  return hipGetLastError();
+}
+
+template <int G>
+static hipError_t derivs_g(hipStream_t s, const EvalArgs& a, const double* gop,
+                           const int32_t* status, int nf, const double* fields, double* d1,
+                           double* d2) {
+  const unsigned grid = grid_for((int64_t)a.n * G, THREADS);
+  for (int f0 = 0; f0 < nf; f0 += FCHUNK) {
+    hipLaunchKernelGGL((k_apply_derivs<G>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
+                       a.off, a.idx, a.box, a.rf_ratio, a.wkind, gop, 0, status, nf, f0, fields,
+                       d1, 3, 0, 1.0, 1.0, 1.0, 1);
+    if (d2) {
+      // rows 4..6: xx (2 c), xy, xz ; rows 7..9: yy (2 c), yz, zz (2 c)
+      hipLaunchKernelGGL((k_apply_derivs<G>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
+                         a.off, a.idx, a.box, a.rf_ratio, a.wkind, gop, 3, status, nf, f0, fields,
+                         d2, 6, 0, 2.0, 1.0, 1.0, 2);
+      hipLaunchKernelGGL((k_apply_derivs<G>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
+                         a.off, a.idx, a.box, a.rf_ratio, a.wkind, gop, 6, status, nf, f0, fields,
+                         d2, 6, 3, 2.0, 1.0, 2.0, 2);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,
+                               const int32_t* status, int nf, const double* fields, double* d1,
+                               double* d2) {
+  switch (lanes) {
+    case 1: return derivs_g<1>(s, a, gop, status, nf, fields, d1, d2);
+    case 2: return derivs_g<2>(s, a, gop, status, nf, fields, d1, d2);
+    default: return derivs_g<4>(s, a, gop, status, nf, fields, d1, d2);
+  }
+}
+
+template <int G>
+static hipError_t rhs_g(hipStream_t s, const EvalArgs& a, double gamma, const double* gop,
+                        const int32_t* status, const double* q, double* rhs, double* dxdt,
+                        double* tape) {
+  hipLaunchKernelGGL((k_apply_rhs<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0,
+                     s, a.n, a.pos, a.lam, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gamma, gop,
+                     status, q, rhs, dxdt, tape);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_rhs(hipStream_t s, const EvalArgs& a, int lanes, double gamma,
+                            const double* gop, const int32_t* status, const double* q,
+                            double* rhs, double* dxdt, double* tape) {
+  switch (lanes) {
+    case 1: return rhs_g<1>(s, a, gamma, gop, status, q, rhs, dxdt, tape);
+    case 2: return rhs_g<2>(s, a, gamma, gop, status, q, rhs, dxdt, tape);
+    default: return rhs_g<4>(s, a, gamma, gop, status, q, rhs, dxdt, tape);
+  }
+}
+
+}  // namespace phb

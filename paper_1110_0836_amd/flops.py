@@ -1,0 +1,58 @@
+"""Algorithmic operation counts of the GPU kernels (FP64 flops: add, multiply,
+divide and square root count 1, a fused multiply-add counts 2).
+
+They count the arithmetic each kernel's formulation needs, not the
+instructions it issues: lane reductions, padding and index arithmetic are
+left out.  Per neighbor entry (one (i, j) pair of the CSR) and per particle:
+
+k_moments        per pair: displacement, weight and xi (15) + the 84 weighted
+                 monomials of degree <= 6 built from shared partial products
+                 (32 multiplies, 28 adds, 56 fused multiply-adds)        = 187
+k_factor<3>      per particle: equilibration (20 sqrt, 20 div, 420 mul),
+                 20x20 Cholesky (20 sqrt, 20 div, 190 mul, 1330 FMA),
+                 three unit-vector solves (2234), output scaling (120)   = 5704
+k_apply_rhs      per pair: geometry and weight (15), basis (16), three
+                 operator rows G p (60 FMA), w (3), field differences (7),
+                 gradient accumulation (21 FMA)                          = 203
+                 per particle: gradient scaling (21) + right-hand side (45) = 66
+k_adj_y          per pair: geometry (15), basis (16), h = Ubar df (7 sub,
+                 21 FMA), w h (3), Y update (60 FMA)                      = 203
+                 per particle: pointwise adjoint                          = 150
+k_adj_factor     per particle: equilibration + Cholesky (3330), three
+                 unit-vector and three general solves (2234 + 2460),
+                 scaling (240)                                            = 8264
+k_adj_pairs      per pair: geometry and dw/dq (18), basis (16),
+                 G p and K p (120 FMA), h (7 sub, 21 FMA), dfbar (42),
+                 wbar (5), pbar = w (G^T b - K^T a) (120 FMA, 20 mul),
+                 basis gradient (25), xibar over the 30 nonzero basis
+                 derivatives (30 FMA), dbar (12), sums (10)               = 683
+k_adj_gather     memory bound: 80 B per pair record, 232 B per particle.
+"""
+
+PER_PAIR = {
+    "k_moments": 187,
+    "k_apply_rhs": 203,
+    "k_adj_y": 203,
+    "k_adj_pairs": 683,
+}
+PER_PARTICLE = {
+    "k_factor<3>": 5704,
+    "k_apply_rhs": 66,
+    "k_adj_y": 150,
+    "k_adj_factor": 8264,
+}
+BYTES_PER_PAIR = {"k_adj_gather": 80}
+BYTES_PER_PARTICLE = {"k_adj_gather": 232}
+
+
+def flops(kernel: str, n: int, nnz: int) -> float:
+    return PER_PAIR.get(kernel, 0) * nnz + PER_PARTICLE.get(kernel, 0) * n
+
+
+def bytes_moved(kernel: str, n: int, nnz: int) -> float:
+    return BYTES_PER_PAIR.get(kernel, 0) * nnz + BYTES_PER_PARTICLE.get(kernel, 0) * n
+
+
+# MI355X peaks: FP64 vector = 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+PEAK_FP64_VALU = 256 * 4 * 16 * 2 * 2.4e9  # 78.6 TFLOP/s
+PEAK_HBM = 8.0e12
