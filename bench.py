@@ -39,6 +39,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU oracle sample")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times (a plain "
+                         "copy of known size, to calibrate hardware byte counters)")
+    ap.add_argument("--tune", default="",
+                    help="schedule knobs key=value,... (see phb_tune_set)")
     return ap.parse_args()
 
 
@@ -121,6 +126,13 @@ def main():
     lam0 = torch.from_numpy(c["lam"]).to(dev)
     q0 = torch.from_numpy(c["q"]).to(dev)
     w0 = torch.from_numpy(w_np).to(dev)
+
+    tune = {}
+    for kv in filter(None, args.tune.split(",")):
+        k, v = kv.split("=")
+        tune[k] = int(v)
+    for k, v in tune.items():
+        P.phb_tune_set(k, v)
 
     log("spatial ordering (set-up)")
     torch.cuda.synchronize()
@@ -223,6 +235,15 @@ def main():
                 kernels[name]["tflops"] = f / (kernels[name]["avg_ms"] / 1e3) / 1e12
         log("kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f} ms" for k, v in kernels.items()))
 
+    if args.copy_mib > 0:
+        nbytes = args.copy_mib << 20
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_mib} MiB three times (counter calibration)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("oracle CPU baseline")
@@ -242,6 +263,7 @@ def main():
         "config": {"workload": f"shear_layer_adaptive_{n}", "n_particles": n, "nnz": int(nnz),
                    "neighbors_median": int(np.median(counts)), "lambda_range": "4x",
                    "precision": args.precision, "step": "forward + reverse mode",
+                   "tuning": {k: P.phb_tune_get(k) for k in P.TUNE_KEYS},
                    "loss": "sum_i w_i |dV/dt|_i^2, w ~ U(0,1)"},
         "roofline": roof,
         "cpu_baseline": cpu,

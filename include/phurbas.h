@@ -182,6 +182,20 @@ int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, double*
                 const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
                 int64_t* nnz_out, int32_t* status);
 
+/* ---- schedule knobs (set by the autotuner; every value gives the same
+ * results to rounding) ------------------------------------------------------
+ * Keys: "cells_per_rf" (1..4: neighbor-grid cells per minimum r_f),
+ * "lanes_moments", "lanes_apply", "lanes_adj_y" (1, 2 or 4 lanes sharing one
+ * particle's neighbor loop in the moment, application and reverse-mode
+ * assembly kernels), "lanes_gather" (1, 2 or 4 lanes summing one particle's
+ * transposed row in the reverse mode), "adj_pairs_mode" (0: one lane per
+ * neighbor entry, 1: one wavefront per owner particle), "record_order" (0:
+ * pair records written at their transposed position, 1: written in forward
+ * order and gathered through the inverse map).  EINVAL for an unknown key or
+ * value. */
+int phb_tune_set(phb_ctx* ctx, const char* key, int value);
+int phb_tune_get(phb_ctx* ctx, const char* key, int* value);
+
 /* ---- instrumentation -----------------------------------------------------
  * phb_profile: enable (1) or disable (0) per-kernel timing on ctx; clears the
  * totals.  While enabled every kernel launch is bracketed by HIP events on the

@@ -36,7 +36,7 @@ EXPORTS = [
     "phb_create", "phb_destroy", "phb_set_stream", "phb_reserve", "phb_strerror",
     "phb_last_error", "phb_neighbors_build", "phb_neighbors_transpose", "phb_spatial_order",
     "phb_permute", "phb_mls_derivs", "phb_mhd_rhs", "phb_tape_bytes", "phb_mhd_rhs_adjoint",
-    "phb_pc_step", "phb_profile", "phb_profile_read",
+    "phb_pc_step", "phb_profile", "phb_profile_read", "phb_tune_set", "phb_tune_get",
 ]
 
 
@@ -110,6 +110,8 @@ def lib():
             "phb_mhd_rhs_adjoint": (I, [P, PP, I64, P, P, P, P, P, P, P, P, P, P, P, P, P]),
             "phb_pc_step": (I, [P, PP, I64, D, P, P, P, P, P, I64, ctypes.POINTER(I64), P]),
             "phb_profile": (I, [P, I]),
+            "phb_tune_set": (I, [P, ctypes.c_char_p, I]),
+            "phb_tune_get": (I, [P, ctypes.c_char_p, ctypes.POINTER(I)]),
             "phb_profile_read": (I, [P, I32, P, P, P, ctypes.POINTER(I32)]),
         }
         for name, (res, args) in sig.items():
@@ -238,6 +240,22 @@ def phb_pc_step(setup, dt, pos, q, lam, offsets, idx, capacity, status):
     if rc not in (PHB_OK, PHB_ECAPACITY):
         _check(ctx, rc)
     return rc, nnz.value
+
+
+TUNE_KEYS = ("cells_per_rf", "lanes_moments", "lanes_apply", "lanes_adj_y", "lanes_gather",
+             "adj_pairs_mode", "record_order")
+
+
+def phb_tune_set(key, value, device=None):
+    ctx = context(device)
+    _check(ctx, lib().phb_tune_set(ctx, key.encode(), int(value)))
+
+
+def phb_tune_get(key, device=None):
+    ctx = context(device)
+    v = ctypes.c_int(0)
+    _check(ctx, lib().phb_tune_get(ctx, key.encode(), ctypes.byref(v)))
+    return v.value
 
 
 def phb_profile(enable, device=None):

@@ -40,6 +40,12 @@ namespace {
 
 constexpr int THREADS = 256;
 constexpr int REC = 10;  // doubles per pair record: dfbar (7), dbar (3)
+// Per-owner record of the pair kernel (one 1152-byte block per particle, so a
+// wavefront's lanes that share an owner read a few cache lines):
+// G (3 x 20) at 0, K (3 x 20) at 60, Ubar (7 x 3) at 120, padding to 144.
+constexpr int OREC = 144;
+constexpr int UOFF = 120;
+constexpr int PAIRS_PER_BLOCK = 256;
 
 struct EntryTableA {
   unsigned char v[NBASIS * NBASIS];
@@ -93,7 +99,7 @@ __device__ __forceinline__ void pointwise_adjoint(int n, int i, const double* __
 // ---- 2. Y = sum_j w_j p_j (Ubar df_j)^T, plus Ubar and the direct qbar ------
 template <int G>
 __global__ void __launch_bounds__(THREADS)
-    k_adj_y(int n, const double* __restrict__ pos, const double* __restrict__ lam,
+    k_adj_y(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
             const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
             double rf_ratio, int wkind, double gamma, const double* __restrict__ q,
             const double* __restrict__ tape, const double* __restrict__ rhs_bar,
@@ -104,13 +110,12 @@ __global__ void __launch_bounds__(THREADS)
   const int l = tid % G;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
-  const double li = lam[ii];
-  const double inv_lam = 1.0 / li;
+  const double4 gi = geo[ii];
+  const double inv_lam = 1.0 / gi.w;
   const int st = (int)tape[(int64_t)21 * n + ii];
   double qi[8], ub[7][3], qb[8];
   pointwise_adjoint(n, ii, q, tape, rhs_bar, dxdt_bar, gamma, inv_lam, st, qi, ub, qb);
-  const double xi = pos[ii], yi = pos[(int64_t)n + ii], zi = pos[2 * (int64_t)n + ii];
-  const double r = rf_ratio * li;
+  const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
   double y[3][NBASIS];
 #pragma unroll
@@ -118,19 +123,35 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b) y[t][b] = 0.0;
   const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
-  for (int64_t s = s0 + l; s < s1; s += G) {
-    const int j = idx[s];
-    const double dx = min_image(pos[j] - xi, box.L[0], box.halfL[0], box.periodic[0]);
-    const double dy = min_image(pos[(int64_t)n + j] - yi, box.L[1], box.halfL[1], box.periodic[1]);
-    const double dz =
-        min_image(pos[2 * (int64_t)n + j] - zi, box.L[2], box.halfL[2], box.periodic[2]);
+  int64_t s = s0 + l;
+  int jc = ii, jn = ii;
+  double4 gn = gi;
+  if (s < s1) {
+    jc = idx[s];
+    gn = geo[jc];
+  }
+  if (s + G < s1) jn = idx[s + G];
+  for (; s < s1; s += G) {
+    const double4 gj = gn;
+    const int j = jc;
+    if (s + G < s1) {
+      gn = geo[jn];
+      jc = jn;
+      if (s + 2 * G < s1) jn = idx[s + 2 * G];
+    }
+    const double2* fj = reinterpret_cast<const double2*>(fq + 8 * (int64_t)j);
+    const double2 f01 = fj[0], f23 = fj[1], f45 = fj[2], f67 = fj[3];
+    const double qj[8] = {f01.x, f01.y, f23.x, f23.y, f45.x, f45.y, f67.x, f67.y};
+    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
     const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
     double p[NBASIS];
     basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
     double h[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int f = 0; f < 7; ++f) {
-      const double df = q[(int64_t)(f + 1) * n + j] - qi[f + 1];
+      const double df = qj[f + 1] - qi[f + 1];
 #pragma unroll
       for (int t = 0; t < 3; ++t) h[t] = fma(ub[f][t], df, h[t]);
     }
@@ -155,7 +176,7 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
       for (int f = 0; f < 7; ++f)
 #pragma unroll
-        for (int t = 0; t < 3; ++t) ubuf[((int64_t)f * 3 + t) * n + i] = ub[f][t];
+        for (int t = 0; t < 3; ++t) ubuf[(int64_t)i * OREC + UOFF + f * 3 + t] = ub[f][t];
 #pragma unroll
       for (int f = 0; f < 8; ++f) qb_direct[(int64_t)f * n + i] = qb[f];
     }
@@ -167,8 +188,7 @@ __host__ __device__ constexpr int aoff_a(int rho) { return 2 * rho * (rho + 1); 
 
 __global__ void __launch_bounds__(THREADS)
     k_adj_factor(int n, const double* __restrict__ mom, const double* __restrict__ ybuf,
-                 const double* __restrict__ tape, double* __restrict__ gop,
-                 double* __restrict__ kop) {
+                 const double* __restrict__ tape, double* __restrict__ gop) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
@@ -277,142 +297,360 @@ __global__ void __launch_bounds__(THREADS)
         constexpr int rho = R;
         const int r = 4 * rho + l;
         const double v = st == 0 ? x[rho] * s_own[rho] : 0.0;
-        if constexpr (rh < 3)
-          gop[((int64_t)rh * NBASIS + r) * n + i] = v;
-        else
-          kop[((int64_t)(rh - 3) * NBASIS + r) * n + i] = v;
+        // G rows at 0..59 and K rows at 60..119 of the owner record
+        gop[(int64_t)i * OREC + rh * NBASIS + r] = v;
       });
     }
   });
 }
 
-// ---- 4. pair contributions --------------------------------------------------
-__global__ void __launch_bounds__(THREADS)
-    k_adj_pairs(int n, const double* __restrict__ pos, const double* __restrict__ lam,
+// ---- 4. pair contributions, one lane per neighbor entry ----------------------
+// A block covers 256 consecutive CSR entries (slots); every lane finds its
+// owner row in the block's slice of the offsets, computes the pair's
+// contributions and writes them as one record at the pair's transposed
+// position.  The owner's own share (minus the sum of its pair records) is a
+// segmented sum over the wavefront's lanes: rows that lie inside one
+// wavefront are finished here, pieces of longer rows go to per-wavefront
+// partial slots that k_adj_combine adds up in wavefront order.
+__device__ __forceinline__ void poly_val_grad(const double* __restrict__ c,
+                                              const double (&p)[NBASIS], const double (&gx)[NBASIS],
+                                              const double (&gy)[NBASIS],
+                                              const double (&gz)[NBASIS], double& v, double& dx,
+                                              double& dy, double& dz) {
+  double cr[NBASIS];
+#pragma unroll
+  for (int b = 0; b < NBASIS; b += 2) {
+    const double2 t = *reinterpret_cast<const double2*>(c + b);
+    cr[b] = t.x;
+    cr[b + 1] = t.y;
+  }
+  v = dx = dy = dz = 0.0;
+#pragma unroll
+  for (int b = 0; b < NBASIS; ++b) {
+    v = fma(cr[b], p[b], v);
+    dx = fma(cr[b], gx[b], dx);  // the compiler drops the zero entries
+    dy = fma(cr[b], gy[b], dy);
+    dz = fma(cr[b], gz[b], dz);
+  }
+}
+
+__global__ void __launch_bounds__(PAIRS_PER_BLOCK)
+    k_adj_pairs(int n, int64_t nnz, const double4* __restrict__ geo,
                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
                 const int32_t* __restrict__ t_pos, Box box, double rf_ratio, int wkind,
-                const double* __restrict__ q, const double* __restrict__ gop,
-                const double* __restrict__ kop, const double* __restrict__ ubuf,
-                double* __restrict__ rec, double* __restrict__ own) {
+                const double* __restrict__ fq, const double* __restrict__ orec,
+                double* __restrict__ rec, double* __restrict__ own, double* __restrict__ wpart,
+                int slot_order) {
+  __shared__ int64_t sh_off[PAIRS_PER_BLOCK + 1];
+  __shared__ int sh_i0;
+  const int64_t S0 = (int64_t)blockIdx.x * PAIRS_PER_BLOCK;
+  if (threadIdx.x == 0) {  // last row starting at or before S0
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= S0)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    sh_i0 = lo;
+  }
+  __syncthreads();
+  const int i0 = sh_i0;
+  for (int k = threadIdx.x; k <= PAIRS_PER_BLOCK; k += PAIRS_PER_BLOCK) {
+    const int r = i0 + k;
+    sh_off[k] = off[r < n ? r : n];
+  }
+  __syncthreads();
+  const int64_t s = S0 + threadIdx.x;
+  const bool valid = s < nnz;
+  const int lane = threadIdx.x & 63;
+  int i = 0x7fffffff;  // owner (sentinel for lanes past the end)
+  double v[REC];
+#pragma unroll
+  for (int c = 0; c < REC; ++c) v[c] = 0.0;
+  if (valid) {
+    int lo = 0, hi = PAIRS_PER_BLOCK;
+    while (lo < hi) {  // last staged row with off <= s
+      const int mid = (lo + hi + 1) >> 1;
+      if (sh_off[mid] <= s)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    i = i0 + lo;
+    if (lo == PAIRS_PER_BLOCK) {  // only with many empty rows: search the rest
+      int a = i, b = n - 1;
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (off[mid] <= s)
+          a = mid;
+        else
+          b = mid - 1;
+      }
+      i = a;
+    }
+    const int j = idx[s];
+    if (j != i) {
+      const double4 gi = geo[i], gj = geo[j];
+      const double inv_lam = 1.0 / gi.w;
+      const double r = rf_ratio * gi.w;
+      const double inv_r2 = 1.0 / (r * r);
+      const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+      const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+      const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+      const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
+      const double w = weight_of(qd, wkind);
+      const double dw = weight_dq(qd, wkind);
+      const double ex = dx * inv_lam, ey = dy * inv_lam, ez = dz * inv_lam;
+      double p[NBASIS], gx[NBASIS], gy[NBASIS], gz[NBASIS];
+      basis(p, ex, ey, ez);
+      basis_grad(gx, gy, gz, ex, ey, ez);
+      const double* o = orec + (int64_t)i * OREC;
+      double av[3], ag[3][3], kp[3], kg[3][3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        poly_val_grad(o + t * NBASIS, p, gx, gy, gz, av[t], ag[t][0], ag[t][1], ag[t][2]);
+        poly_val_grad(o + 60 + t * NBASIS, p, gx, gy, gz, kp[t], kg[t][0], kg[t][1], kg[t][2]);
+      }
+      double bv[3] = {-kp[0], -kp[1], -kp[2]};
+      const double* fi = fq + 8 * (int64_t)i;
+      const double* fj = fq + 8 * (int64_t)j;
+#pragma unroll
+      for (int f = 0; f < 7; ++f) {
+        const double df = fj[f + 1] - fi[f + 1];
+        const double u0 = o[UOFF + 3 * f], u1 = o[UOFF + 3 * f + 1], u2 = o[UOFF + 3 * f + 2];
+        bv[0] = fma(u0, df, bv[0]);
+        bv[1] = fma(u1, df, bv[1]);
+        bv[2] = fma(u2, df, bv[2]);
+        v[f] = w * (u0 * av[0] + u1 * av[1] + u2 * av[2]);
+      }
+      const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
+      const double geo = wbar * dw * 2.0 * inv_r2;
+      // xibar_c = w (b . (G dp/dxi_c) - a . (K dp/dxi_c))
+      double xb[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        xb[c] = w * (bv[0] * ag[0][c] + bv[1] * ag[1][c] + bv[2] * ag[2][c] -
+                     av[0] * kg[0][c] - av[1] * kg[1][c] - av[2] * kg[2][c]);
+      v[7] = xb[0] * inv_lam + geo * dx;
+      v[8] = xb[1] * inv_lam + geo * dy;
+      v[9] = xb[2] * inv_lam + geo * dz;
+    }
+    double2* out = reinterpret_cast<double2*>(rec + (slot_order ? s : (int64_t)t_pos[s]) * REC);
+#pragma unroll
+    for (int c = 0; c < REC; c += 2) out[c / 2] = make_double2(v[c], v[c + 1]);
+  }
+  // segmented inclusive sum over the wavefront (owners are non-decreasing)
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int ku = __shfl_up(i, d, 64);
+    double u[REC];
+#pragma unroll
+    for (int c = 0; c < REC; ++c) u[c] = __shfl_up(v[c], d, 64);
+    if (lane >= d && ku == i) {
+#pragma unroll
+      for (int c = 0; c < REC; ++c) v[c] += u[c];
+    }
+  }
+  const int knext = __shfl_down(i, 1, 64);
+  if (valid && (lane == 63 || knext != i)) {
+    const int64_t wfirst = s - lane;
+    const int64_t wlast = wfirst + 63;
+    const int64_t rs = off[i], re = off[i + 1] - 1;
+    if (rs >= wfirst && re <= wlast) {
+#pragma unroll
+      for (int c = 0; c < REC; ++c) own[(int64_t)c * n + i] = -v[c];
+    } else {
+      const int64_t wv = wfirst >> 6;
+      double* dst = wpart + (wv * 2 + (rs <= wfirst ? 0 : 1)) * REC;
+#pragma unroll
+      for (int c = 0; c < REC; ++c) dst[c] = v[c];
+    }
+  }
+}
+
+// Owners whose rows span several wavefronts: add the pieces in order.
+__global__ void __launch_bounds__(THREADS)
+    k_adj_combine(int n, const int64_t* __restrict__ off, const double* __restrict__ wpart,
+                  double* __restrict__ own) {
   const int i = blockIdx.x * THREADS + threadIdx.x;
   if (i >= n) return;
-  double g[3][NBASIS], k[3][NBASIS], ub[7][3], qi[7];
+  const int64_t rs = off[i], re = off[i + 1] - 1;
+  if (re < rs) {  // empty row: nothing owned
 #pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) {
-      g[t][b] = gop[((int64_t)t * NBASIS + b) * n + i];
-      k[t][b] = kop[((int64_t)t * NBASIS + b) * n + i];
-    }
-#pragma unroll
-  for (int f = 0; f < 7; ++f) {
-    qi[f] = q[(int64_t)(f + 1) * n + i];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) ub[f][t] = ubuf[((int64_t)f * 3 + t) * n + i];
+    for (int c = 0; c < REC; ++c) own[(int64_t)c * n + i] = 0.0;
+    return;
   }
-  const double xi = pos[i], yi = pos[(int64_t)n + i], zi = pos[2 * (int64_t)n + i];
-  const double li = lam[i];
-  const double inv_lam = 1.0 / li;
-  const double r = rf_ratio * li;
+  const int64_t w0 = rs >> 6, w1 = re >> 6;
+  if (w0 == w1) return;
+  double acc[REC];
+  const double* first = wpart + (w0 * 2 + (rs == (w0 << 6) ? 0 : 1)) * REC;
+#pragma unroll
+  for (int c = 0; c < REC; ++c) acc[c] = first[c];
+  for (int64_t wv = w0 + 1; wv <= w1; ++wv) {
+    const double* pc = wpart + wv * 2 * REC;
+#pragma unroll
+    for (int c = 0; c < REC; ++c) acc[c] += pc[c];
+  }
+#pragma unroll
+  for (int c = 0; c < REC; ++c) own[(int64_t)c * n + i] = -acc[c];
+}
+
+// ---- 4b. pair contributions, one wavefront per owner ------------------------
+// The owner's G, K and Ubar are wavefront-uniform (scalar loads into SGPRs);
+// lanes take the owner's neighbor entries 64 at a time; the owner's own share
+// is one wavefront reduction at the end.  Rows longer than 64 entries loop.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += quad_xor1(v);
+  v += quad_xor2(v);
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+__device__ __forceinline__ void poly_val_grad_s(const double* __restrict__ c,
+                                                const double (&p)[NBASIS],
+                                                const double (&gx)[NBASIS],
+                                                const double (&gy)[NBASIS],
+                                                const double (&gz)[NBASIS], double& v, double& dx,
+                                                double& dy, double& dz) {
+  v = dx = dy = dz = 0.0;
+#pragma unroll
+  for (int b = 0; b < NBASIS; ++b) {
+    const double cb = c[b];
+    v = fma(cb, p[b], v);
+    dx = fma(cb, gx[b], dx);
+    dy = fma(cb, gy[b], dy);
+    dz = fma(cb, gz[b], dz);
+  }
+}
+
+__global__ void __launch_bounds__(THREADS)
+    k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                  const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
+                  double rf_ratio, int wkind, const double* __restrict__ fq,
+                  const double* __restrict__ orec, double* __restrict__ rec,
+                  double* __restrict__ own, int slot_order) {
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;  // whole wavefronts leave together
+  const int64_t rs = off[i], re = off[i + 1];
+  const double4 gi = geo[i];
+  const double inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
-  double sdf[7] = {0, 0, 0, 0, 0, 0, 0}, sd[3] = {0, 0, 0};
-  for (int64_t s = off[i]; s < off[i + 1]; ++s) {
+  const double* o = orec + (int64_t)i * OREC;
+  const double* fi = fq + 8 * (int64_t)i;
+  double acc[REC];
+#pragma unroll
+  for (int c = 0; c < REC; ++c) acc[c] = 0.0;
+  for (int64_t s = rs + lane; s < re; s += 64) {
     const int j = idx[s];
-    double* out = rec + (int64_t)t_pos[s] * REC;
-    if (j == i) {  // the self pair adds and removes the same terms
+    double v[REC];
 #pragma unroll
-      for (int c = 0; c < REC; ++c) out[c] = 0.0;
-      continue;
-    }
-    const double dx = min_image(pos[j] - xi, box.L[0], box.halfL[0], box.periodic[0]);
-    const double dy = min_image(pos[(int64_t)n + j] - yi, box.L[1], box.halfL[1], box.periodic[1]);
-    const double dz =
-        min_image(pos[2 * (int64_t)n + j] - zi, box.L[2], box.halfL[2], box.periodic[2]);
-    const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
-    const double w = weight_of(qd, wkind);
-    const double dw = weight_dq(qd, wkind);
-    const double ex = dx * inv_lam, ey = dy * inv_lam, ez = dz * inv_lam;
-    double p[NBASIS];
-    basis(p, ex, ey, ez);
-    double av[3], bv[3];
+    for (int c = 0; c < REC; ++c) v[c] = 0.0;
+    if (j != i) {
+      const double4 gj = geo[j];
+      const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+      const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+      const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+      const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
+      const double w = weight_of(qd, wkind);
+      const double dw = weight_dq(qd, wkind);
+      const double ex = dx * inv_lam, ey = dy * inv_lam, ez = dz * inv_lam;
+      double p[NBASIS], gx[NBASIS], gy[NBASIS], gz[NBASIS];
+      basis(p, ex, ey, ez);
+      basis_grad(gx, gy, gz, ex, ey, ez);
+      double av[3], ag[3][3], kp[3], kg[3][3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      double ga = 0.0, kp = 0.0;
-#pragma unroll
-      for (int b = 0; b < NBASIS; ++b) {
-        ga = fma(g[t][b], p[b], ga);
-        kp = fma(k[t][b], p[b], kp);
+      for (int t = 0; t < 3; ++t) {
+        poly_val_grad_s(o + t * NBASIS, p, gx, gy, gz, av[t], ag[t][0], ag[t][1], ag[t][2]);
+        poly_val_grad_s(o + 60 + t * NBASIS, p, gx, gy, gz, kp[t], kg[t][0], kg[t][1],
+                        kg[t][2]);
       }
-      av[t] = ga;
-      bv[t] = -kp;
+      double bv[3] = {-kp[0], -kp[1], -kp[2]};
+      const double* fj = fq + 8 * (int64_t)j;
+#pragma unroll
+      for (int f = 0; f < 7; ++f) {
+        const double df = fj[f + 1] - fi[f + 1];
+        const double u0 = o[UOFF + 3 * f], u1 = o[UOFF + 3 * f + 1], u2 = o[UOFF + 3 * f + 2];
+        bv[0] = fma(u0, df, bv[0]);
+        bv[1] = fma(u1, df, bv[1]);
+        bv[2] = fma(u2, df, bv[2]);
+        v[f] = w * (u0 * av[0] + u1 * av[1] + u2 * av[2]);
+      }
+      const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
+      const double geo_f = wbar * dw * 2.0 * inv_r2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double xb = w * (bv[0] * ag[0][c] + bv[1] * ag[1][c] + bv[2] * ag[2][c] -
+                               av[0] * kg[0][c] - av[1] * kg[1][c] - av[2] * kg[2][c]);
+        v[7 + c] = xb * inv_lam + geo_f * (c == 0 ? dx : (c == 1 ? dy : dz));
+      }
     }
-    double dfb[7];
+    double2* out = reinterpret_cast<double2*>(rec + (slot_order ? s : (int64_t)t_pos[s]) * REC);
 #pragma unroll
-    for (int f = 0; f < 7; ++f) {
-      const double df = q[(int64_t)(f + 1) * n + j] - qi[f];
+    for (int c = 0; c < REC; c += 2) out[c / 2] = make_double2(v[c], v[c + 1]);
 #pragma unroll
-      for (int t = 0; t < 3; ++t) bv[t] = fma(ub[f][t], df, bv[t]);
-      dfb[f] = w * (ub[f][0] * av[0] + ub[f][1] * av[1] + ub[f][2] * av[2]);
-    }
-    const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
-    // pbar = w (G^T b - K^T a)
-    double pb[NBASIS];
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) {
-      double v = 0.0;
-#pragma unroll
-      for (int t = 0; t < 3; ++t) v = fma(g[t][b], bv[t], fma(-k[t][b], av[t], v));
-      pb[b] = w * v;
-    }
-    double gx[NBASIS], gy[NBASIS], gz[NBASIS];
-    basis_grad(gx, gy, gz, ex, ey, ez);
-    double xb0 = 0.0, xb1 = 0.0, xb2 = 0.0;
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) {
-      xb0 = fma(pb[b], gx[b], xb0);
-      xb1 = fma(pb[b], gy[b], xb1);
-      xb2 = fma(pb[b], gz[b], xb2);
-    }
-    const double geo = wbar * dw * 2.0 * inv_r2;
-    const double db0 = xb0 * inv_lam + geo * dx;
-    const double db1 = xb1 * inv_lam + geo * dy;
-    const double db2 = xb2 * inv_lam + geo * dz;
-#pragma unroll
-    for (int f = 0; f < 7; ++f) {
-      out[f] = dfb[f];
-      sdf[f] += dfb[f];
-    }
-    out[7] = db0;
-    out[8] = db1;
-    out[9] = db2;
-    sd[0] += db0;
-    sd[1] += db1;
-    sd[2] += db2;
+    for (int c = 0; c < REC; ++c) acc[c] += v[c];
   }
 #pragma unroll
-  for (int f = 0; f < 7; ++f) own[(int64_t)f * n + i] = -sdf[f];
+  for (int c = 0; c < REC; ++c) acc[c] = wave_sum(acc[c]);
+  if (lane < REC) {
+    double mine = acc[0];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) own[(int64_t)(7 + a) * n + i] = -sd[a];
+    for (int c = 1; c < REC; ++c) mine = lane == c ? acc[c] : mine;
+    own[(int64_t)lane * n + i] = -mine;
+  }
+}
+
+// Inverse of t_pos: for transposed entry k, the forward entry it came from.
+__global__ void __launch_bounds__(THREADS)
+    k_invert(int64_t nnz, const int32_t* __restrict__ t_pos, int32_t* __restrict__ t_slot) {
+  const int64_t s = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+  if (s < nnz) t_slot[t_pos[s]] = (int32_t)s;
 }
 
 // ---- 5. gather over the transposed lists ------------------------------------
+// G lanes share one particle's transposed row; their partial sums meet in a
+// quad reduction.  The summation order is fixed for a given G.
+template <int G>
 __global__ void __launch_bounds__(THREADS)
-    k_adj_gather(int n, const int64_t* __restrict__ t_off, const double* __restrict__ rec,
-                 const double* __restrict__ own, const double* __restrict__ qb_direct,
-                 double* __restrict__ q_bar, double* __restrict__ pos_bar) {
-  const int j = blockIdx.x * THREADS + threadIdx.x;
-  if (j >= n) return;
+    k_adj_gather(int n, const int64_t* __restrict__ t_off, const int32_t* __restrict__ t_slot,
+                 const double* __restrict__ rec, const double* __restrict__ own,
+                 const double* __restrict__ qb_direct, double* __restrict__ q_bar,
+                 double* __restrict__ pos_bar) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int j = tid / G;
+  const int l = tid % G;
+  const bool valid = j < n;
+  const int jj = valid ? j : n - 1;
   double acc[REC];
 #pragma unroll
-  for (int c = 0; c < REC; ++c) acc[c] = own[(int64_t)c * n + j];
-  for (int64_t k = t_off[j]; k < t_off[j + 1]; ++k) {
-    const double* r = rec + k * REC;
+  for (int c = 0; c < REC; ++c) acc[c] = 0.0;
+  const int64_t k1 = valid ? t_off[jj + 1] : 0;
+  for (int64_t k = t_off[jj] + l; k < k1; k += G) {
+    const double2* r =
+        reinterpret_cast<const double2*>(rec + (t_slot ? (int64_t)t_slot[k] : k) * REC);
 #pragma unroll
-    for (int c = 0; c < REC; ++c) acc[c] += r[c];
+    for (int c = 0; c < REC; c += 2) {
+      const double2 t = r[c / 2];
+      acc[c] += t.x;
+      acc[c + 1] += t.y;
+    }
   }
+#pragma unroll
+  for (int c = 0; c < REC; ++c) acc[c] = group_sum<G>(acc[c]);
+  if (!valid || l != 0) return;
+#pragma unroll
+  for (int c = 0; c < REC; ++c) acc[c] += own[(int64_t)c * n + j];
   q_bar[j] = qb_direct[j];
 #pragma unroll
-  for (int f = 0; f < 7; ++f) q_bar[(int64_t)(f + 1) * n + j] = qb_direct[(int64_t)(f + 1) * n + j] + acc[f];
+  for (int f = 0; f < 7; ++f)
+    q_bar[(int64_t)(f + 1) * n + j] = qb_direct[(int64_t)(f + 1) * n + j] + acc[f];
 #pragma unroll
   for (int a = 0; a < 3; ++a) pos_bar[(int64_t)a * n + j] = acc[7 + a];
 }
@@ -422,7 +660,7 @@ hipError_t launch_adj_y_g(hipStream_t s, const EvalArgs& a, double gamma, const 
                           const double* tape, const double* rhs_bar, const double* dxdt_bar,
                           double* ybuf, double* ubuf, double* qbd) {
   hipLaunchKernelGGL((k_adj_y<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0, s,
-                     a.n, a.pos, a.lam, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gamma, q, tape,
+                     a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gamma, q, tape,
                      rhs_bar, dxdt_bar, ybuf, ubuf, qbd);
   return hipGetLastError();
 }
@@ -451,65 +689,108 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   }
   Workspace ws(ctx);
   const size_t nd = (size_t)n * sizeof(double);
-  ws.plan(NMOM * nd);          // moments
-  ws.plan(3 * NBASIS * nd);    // Y
-  ws.plan(3 * NBASIS * nd);    // G
-  ws.plan(3 * NBASIS * nd);    // K
-  ws.plan(21 * nd);            // Ubar
-  ws.plan(8 * nd);             // direct qbar
-  ws.plan(10 * nd);            // own sums
+  const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
+  ws.plan((size_t)n * sizeof(double4));  // packed geometry
+  ws.plan(8 * nd);                       // packed fields
+  ws.plan(3 * NBASIS * nd);            // Y
+  ws.plan((size_t)OREC * nd);          // owner records: G, K, Ubar
+  ws.plan(8 * nd);                     // direct qbar
+  ws.plan((size_t)REC * nd);           // own sums
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * REC * sizeof(double));  // pair records
+  ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
+  ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
   const bool need_tape = tape_in == nullptr;
   if (need_tape) {
-    ws.plan(22 * nd);  // tape
-    ws.plan(8 * nd);   // rhs scratch
-    ws.plan(3 * nd);   // dxdt scratch
+    ws.plan((size_t)TAPE_DOUBLES * nd);  // tape (gradients, status, moments)
+    ws.plan(3 * NBASIS * nd);            // forward operator
+    ws.plan(8 * nd);                     // rhs scratch
+    ws.plan(3 * nd);                     // dxdt scratch
     ws.plan((size_t)n * sizeof(int32_t));
   }
   if ((rc = ws.commit())) return rc;
-  double* mom = ws.take<double>((size_t)NMOM * n);
+  double4* geo = ws.take<double4>(n);
+  double* fq = ws.take<double>((size_t)8 * n);
   double* ybuf = ws.take<double>((size_t)3 * NBASIS * n);
-  double* gop = ws.take<double>((size_t)3 * NBASIS * n);
-  double* kop = ws.take<double>((size_t)3 * NBASIS * n);
-  double* ubuf = ws.take<double>((size_t)21 * n);
+  double* orec = ws.take<double>((size_t)OREC * n);
   double* qbd = ws.take<double>((size_t)8 * n);
-  double* own = ws.take<double>((size_t)10 * n);
+  double* own = ws.take<double>((size_t)REC * n);
   double* rec = ws.take<double>((size_t)std::max<int64_t>(nnz, 1) * REC);
+  double* wpart = ws.take<double>((size_t)nwaves * 2 * REC);
+  int32_t* t_slot = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  const int slot_order = ctx->record_order;
   const double* tape = tape_in;
   hipStream_t s = ctx->stream;
-  { Prof pf(ctx, "k_moments");
-  if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, mom), "adjoint moments")))
-    return rc; }
-  if (need_tape) {
-    double* tp = ws.take<double>((size_t)22 * n);
+  EvalArgs ap = a;
+  ap.geo = geo;
+  ap.fq = fq;
+  { Prof pf(ctx, "k_pack");
+  if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
+  if (need_tape) {  // run the forward pass to fill a private tape
+    double* tp = ws.take<double>((size_t)TAPE_DOUBLES * n);
+    double* fg = ws.take<double>((size_t)3 * NBASIS * n);
     double* rs = ws.take<double>((size_t)8 * n);
     double* dx = ws.take<double>((size_t)3 * n);
     int32_t* st = ws.take<int32_t>(n);
-    if ((rc = hip_check(ctx, launch_factor(s, a, 3, mom, gop, st), "adjoint factor"))) return rc;
+    double* tmom = tp + (size_t)TAPE_MOM * n;
+    if ((rc = hip_check(ctx, launch_moments(s, ap, ctx->lanes_assemble, tmom), "moments")))
+      return rc;
+    if ((rc = hip_check(ctx, launch_factor(s, ap, 3, tmom, fg, st), "adjoint factor"))) return rc;
     if ((rc = hip_check(ctx,
-                        launch_apply_rhs(s, a, ctx->lanes_apply, p->gamma, gop, st, q, rs, dx, tp),
+                        launch_apply_rhs(s, ap, ctx->lanes_apply, p->gamma, fg, st, q, rs, dx, tp),
                         "adjoint forward")))
       return rc;
     tape = tp;
   }
+  const double* mom = tape + (size_t)TAPE_MOM * n;
   { Prof pf(ctx, "k_adj_y");
-  switch (ctx->lanes_assemble) {
-    case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, a, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, ubuf, qbd), "adjoint Y"); break;
-    case 2: rc = hip_check(ctx, launch_adj_y_g<2>(s, a, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, ubuf, qbd), "adjoint Y"); break;
-    default: rc = hip_check(ctx, launch_adj_y_g<4>(s, a, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, ubuf, qbd), "adjoint Y"); break;
+  switch (ctx->lanes_adj_y) {
+    case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+    case 2: rc = hip_check(ctx, launch_adj_y_g<2>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+    default: rc = hip_check(ctx, launch_adj_y_g<4>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
   }
   if (rc) return rc; }
   { Prof pf(ctx, "k_adj_factor");
   hipLaunchKernelGGL(k_adj_factor, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS), 0, s, n,
-                     mom, ybuf, tape, gop, kop);
+                     mom, ybuf, tape, orec);
   if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
-  { Prof pf(ctx, "k_adj_pairs");
-  hipLaunchKernelGGL(k_adj_pairs, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, a.pos, a.lam,
-                     a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, q, gop, kop, ubuf, rec, own);
-  if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc; }
+  if (ctx->adj_pairs_mode == 1) {
+    Prof pf(ctx, "k_adj_pairs_w");
+    hipLaunchKernelGGL(k_adj_pairs_w, dim3(grid_for((int64_t)n * 64, THREADS)), dim3(THREADS), 0,
+                       s, n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, rec,
+                       own, slot_order);
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
+  } else {
+    if (nnz > 0) {
+      Prof pf(ctx, "k_adj_pairs");
+      hipLaunchKernelGGL(k_adj_pairs, dim3(grid_for(nnz, PAIRS_PER_BLOCK)), dim3(PAIRS_PER_BLOCK),
+                         0, s, n, nnz, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq,
+                         orec, rec, own, wpart, slot_order);
+      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
+    }
+    Prof pf(ctx, "k_adj_combine");
+    hipLaunchKernelGGL(k_adj_combine, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, a.off,
+                       wpart, own);
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint combine"))) return rc;
+  }
+  if (slot_order && nnz > 0) {
+    Prof pf(ctx, "k_invert");
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(nnz, THREADS)), dim3(THREADS), 0, s, nnz, t_pos,
+                       t_slot);
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint invert"))) return rc;
+  }
+  const int32_t* tsl = slot_order ? t_slot : nullptr;
   Prof pf(ctx, "k_adj_gather");
-  hipLaunchKernelGGL(k_adj_gather, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, t_offsets,
-                     rec, own, qbd, q_bar, pos_bar);
+  const int gl = ctx->lanes_gather;
+  const unsigned gg = grid_for((int64_t)n * gl, THREADS);
+  if (gl == 1)
+    hipLaunchKernelGGL((k_adj_gather<1>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets, tsl, rec, own,
+                       qbd, q_bar, pos_bar);
+  else if (gl == 2)
+    hipLaunchKernelGGL((k_adj_gather<2>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets, tsl, rec, own,
+                       qbd, q_bar, pos_bar);
+  else
+    hipLaunchKernelGGL((k_adj_gather<4>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets, tsl, rec, own,
+                       qbd, q_bar, pos_bar);
   return hip_check(ctx, hipGetLastError(), "adjoint gather");
 }
 

@@ -182,6 +182,8 @@ static void plan_rhs(Workspace& ws, int64_t n, int precision) {
   }
   ws.plan((size_t)NMOM * n * sizeof(double));
   ws.plan((size_t)3 * NBASIS * n * sizeof(double));
+  ws.plan((size_t)n * sizeof(double4));
+  ws.plan((size_t)n * 8 * sizeof(double));
 }
 
 }  // namespace phb
@@ -284,7 +286,39 @@ int phb_profile_read(phb_ctx* ctx, int32_t max_entries, char* names, double* tot
   return PHB_OK;
 }
 
-int64_t phb_tape_bytes(int64_t n) { return n <= 0 ? 0 : n * 22 * (int64_t)sizeof(double); }
+static int* tune_slot(phb_ctx* ctx, const char* key) {
+  if (!strcmp(key, "cells_per_rf")) return &ctx->cells_per_rf;
+  if (!strcmp(key, "lanes_moments")) return &ctx->lanes_assemble;
+  if (!strcmp(key, "lanes_apply")) return &ctx->lanes_apply;
+  if (!strcmp(key, "lanes_adj_y")) return &ctx->lanes_adj_y;
+  if (!strcmp(key, "lanes_gather")) return &ctx->lanes_gather;
+  if (!strcmp(key, "adj_pairs_mode")) return &ctx->adj_pairs_mode;
+  if (!strcmp(key, "record_order")) return &ctx->record_order;
+  return nullptr;
+}
+
+int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
+  if (!ctx || !key) return PHB_EINVAL;
+  int* slot = tune_slot(ctx, key);
+  if (!slot) return set_error(ctx, PHB_EINVAL, std::string("unknown tuning key ") + key);
+  const bool lanes = strncmp(key, "lanes_", 6) == 0;
+  const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order");
+  if (lanes ? !(value == 1 || value == 2 || value == 4)
+            : (mode ? !(value == 0 || value == 1) : !(value >= 1 && value <= 4)))
+    return set_error(ctx, PHB_EINVAL, std::string("bad value for ") + key);
+  *slot = value;
+  return PHB_OK;
+}
+
+int phb_tune_get(phb_ctx* ctx, const char* key, int* value) {
+  if (!ctx || !key || !value) return PHB_EINVAL;
+  int* slot = tune_slot(ctx, key);
+  if (!slot) return set_error(ctx, PHB_EINVAL, std::string("unknown tuning key ") + key);
+  *value = *slot;
+  return PHB_OK;
+}
+
+int64_t phb_tape_bytes(int64_t n) { return n <= 0 ? 0 : n * TAPE_DOUBLES * (int64_t)sizeof(double); }
 
 int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
                         const double* lambda, int64_t* offsets, int32_t* idx,
@@ -458,9 +492,15 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double*
   Workspace ws(ctx);
   ws.plan((size_t)NMOM * n * sizeof(double));
   ws.plan((size_t)9 * NBASIS * n * sizeof(double));
+  ws.plan((size_t)n * sizeof(double4));
   if ((rc = ws.commit())) return rc;
   double* mom = ws.take<double>((size_t)NMOM * n);
   double* gop = ws.take<double>((size_t)9 * NBASIS * n);
+  double4* geo = ws.take<double4>(n);
+  a.geo = geo;
+  if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, pos, lambda, nullptr, geo, nullptr),
+                      "pack")))
+    return rc;
   { Prof pf(ctx, "k_moments");
   if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
     return rc; }
@@ -491,6 +531,15 @@ int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* po
   if ((rc = ws.commit())) return rc;
   double* mom = ws.take<double>((size_t)NMOM * n);
   double* gop = ws.take<double>((size_t)3 * NBASIS * n);
+  double4* geo = ws.take<double4>(n);
+  double* fq = ws.take<double>((size_t)8 * n);
+  // with a tape, the moments go straight into it for the reverse mode
+  if (tape) mom = reinterpret_cast<double*>(tape) + (size_t)TAPE_MOM * n;
+  a.geo = geo;
+  a.fq = fq;
+  { Prof pf(ctx, "k_pack");
+  if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, pos, lambda, q, geo, fq), "pack")))
+    return rc; }
   { Prof pf(ctx, "k_moments");
   if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
     return rc; }

@@ -24,8 +24,12 @@ struct phb_ctx {
   std::string last_error;
   // Tunables (see phb_tune_* in the binding).
   int cells_per_rf = 2;      // neighbor grid cells per minimum r_f
-  int lanes_assemble = 4;    // lanes per particle in neighbor loops (1, 2, 4)
+  int lanes_assemble = 1;    // lanes per particle in neighbor loops (1, 2, 4)
   int lanes_apply = 4;
+  int lanes_adj_y = 2;
+  int lanes_gather = 4;
+  int adj_pairs_mode = 1;  // 0: one lane per entry, 1: one wavefront per owner
+  int record_order = 0;    // pair records at 0: transposed positions, 1: forward slots
   // Per-kernel timing (phb_profile): event pairs awaiting read-out and totals.
   bool prof_on = false;
   struct ProfRec {

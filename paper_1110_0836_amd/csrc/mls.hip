@@ -50,11 +50,36 @@ __constant__ EntryTable c_entry = make_entry_table();
 // ---------------------------------------------------------------------------
 // 1. moments
 // ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(THREADS)
+    k_pack(int n, const double* __restrict__ pos, const double* __restrict__ lam,
+           const double* __restrict__ q, double4* __restrict__ geo, double* __restrict__ fq) {
+  const int i = blockIdx.x * THREADS + threadIdx.x;
+  if (i >= n) return;
+  geo[i] = make_double4(pos[i], pos[(int64_t)n + i], pos[2 * (int64_t)n + i], lam[i]);
+  if (q) {
+    double2* o = reinterpret_cast<double2*>(fq + 8 * (int64_t)i);
+#pragma unroll
+    for (int f = 0; f < 8; f += 2)
+      o[f / 2] = make_double2(q[(int64_t)f * n + i], q[(int64_t)(f + 1) * n + i]);
+  }
+}
+
+// Eight fields of particle j from the packed records.
+__device__ __forceinline__ void load_fields(const double* __restrict__ fq, int j, double (&v)[8]) {
+  const double2* p = reinterpret_cast<const double2*>(fq + 8 * (int64_t)j);
+#pragma unroll
+  for (int f = 0; f < 8; f += 2) {
+    const double2 t = p[f / 2];
+    v[f] = t.x;
+    v[f + 1] = t.y;
+  }
+}
+
 template <int G>
 __global__ void __launch_bounds__(THREADS)
-    k_moments(int n, const double* __restrict__ pos, const double* __restrict__ lam,
-              const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
-              double rf_ratio, int wkind, double* __restrict__ mom) {
+    k_moments(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+              const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
+              double* __restrict__ mom) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
@@ -63,18 +88,26 @@ __global__ void __launch_bounds__(THREADS)
   double m[NMOM];
 #pragma unroll
   for (int k = 0; k < NMOM; ++k) m[k] = 0.0;
-  const double xi = pos[ii], yi = pos[(int64_t)n + ii], zi = pos[2 * (int64_t)n + ii];
-  const double li = lam[ii];
-  const double inv_lam = 1.0 / li;
-  const double r = rf_ratio * li;
+  const double4 gi = geo[ii];
+  const double inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
   const int64_t s0 = off[ii], s1 = valid ? off[ii + 1] : s0;
-  for (int64_t s = s0 + l; s < s1; s += G) {
-    const int j = idx[s];
-    const double dx = min_image(pos[j] - xi, box.L[0], box.halfL[0], box.periodic[0]);
-    const double dy = min_image(pos[(int64_t)n + j] - yi, box.L[1], box.halfL[1], box.periodic[1]);
-    const double dz =
-        min_image(pos[2 * (int64_t)n + j] - zi, box.L[2], box.halfL[2], box.periodic[2]);
+  // neighbor records are fetched one iteration ahead, indices two ahead
+  int64_t s = s0 + l;
+  double4 gn = gi;
+  int jn = 0;
+  if (s < s1) gn = geo[idx[s]];
+  if (s + G < s1) jn = idx[s + G];
+  for (; s < s1; s += G) {
+    const double4 gj = gn;
+    if (s + G < s1) {
+      gn = geo[jn];
+      if (s + 2 * G < s1) jn = idx[s + 2 * G];
+    }
+    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
     const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
     const double w = weight_of(qd, wkind);
     accumulate_moments(m, w, dx * inv_lam, dy * inv_lam, dz * inv_lam);
@@ -310,11 +343,11 @@ __global__ void __launch_bounds__(THREADS)
 // ---------------------------------------------------------------------------
 template <int G>
 __global__ void __launch_bounds__(THREADS)
-    k_apply_rhs(int n, const double* __restrict__ pos, const double* __restrict__ lam,
+    k_apply_rhs(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
                 double rf_ratio, int wkind, double gamma, const double* __restrict__ gop,
-                const int32_t* __restrict__ status, const double* __restrict__ q,
-                double* __restrict__ rhs, double* __restrict__ dxdt, double* __restrict__ tape) {
+                const int32_t* __restrict__ status, double* __restrict__ rhs,
+                double* __restrict__ dxdt, double* __restrict__ tape) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
@@ -327,12 +360,10 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b) g[t][b] = gop[((int64_t)t * NBASIS + b) * n + ii];
   double qi[8];
-#pragma unroll
-  for (int f = 0; f < 8; ++f) qi[f] = q[(int64_t)f * n + ii];
-  const double xi = pos[ii], yi = pos[(int64_t)n + ii], zi = pos[2 * (int64_t)n + ii];
-  const double li = lam[ii];
-  const double inv_lam = 1.0 / li;
-  const double r = rf_ratio * li;
+  load_fields(fq, ii, qi);
+  const double4 gi = geo[ii];
+  const double inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
   double acc[7][3];
 #pragma unroll
@@ -340,12 +371,27 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
     for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
   const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
-  for (int64_t s = s0 + l; s < s1; s += G) {
-    const int j = idx[s];
-    const double dx = min_image(pos[j] - xi, box.L[0], box.halfL[0], box.periodic[0]);
-    const double dy = min_image(pos[(int64_t)n + j] - yi, box.L[1], box.halfL[1], box.periodic[1]);
-    const double dz =
-        min_image(pos[2 * (int64_t)n + j] - zi, box.L[2], box.halfL[2], box.periodic[2]);
+  int64_t s = s0 + l;
+  int jc = ii, jn = ii;
+  double4 gn = gi;
+  if (s < s1) {
+    jc = idx[s];
+    gn = geo[jc];
+  }
+  if (s + G < s1) jn = idx[s + G];
+  for (; s < s1; s += G) {
+    const double4 gj = gn;
+    const int j = jc;
+    if (s + G < s1) {
+      gn = geo[jn];
+      jc = jn;
+      if (s + 2 * G < s1) jn = idx[s + 2 * G];
+    }
+    double qj[8];
+    load_fields(fq, j, qj);
+    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
     const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
     double p[NBASIS];
     basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
@@ -359,7 +405,7 @@ __global__ void __launch_bounds__(THREADS)
     }
 #pragma unroll
     for (int f = 0; f < 7; ++f) {
-      const double df = q[(int64_t)(f + 1) * n + j] - qi[f + 1];
+      const double df = qj[f + 1] - qi[f + 1];
 #pragma unroll
       for (int t = 0; t < 3; ++t) acc[f][t] = fma(gam[t], df, acc[f][t]);
     }
@@ -395,7 +441,7 @@ __global__ void __launch_bounds__(THREADS)
 template <int G>
 hipError_t launch_moments_g(hipStream_t s, const EvalArgs& a, double* mom) {
   hipLaunchKernelGGL((k_moments<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0, s,
-                     a.n, a.pos, a.lam, a.off, a.idx, a.box, a.rf_ratio, a.wkind, mom);
+                     a.n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind, mom);
   return hipGetLastError();
 }
 
@@ -455,9 +501,17 @@ template <int G>
 static hipError_t rhs_g(hipStream_t s, const EvalArgs& a, double gamma, const double* gop,
                         const int32_t* status, const double* q, double* rhs, double* dxdt,
                         double* tape) {
+  (void)q;  // read through the packed records a.fq
   hipLaunchKernelGGL((k_apply_rhs<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0,
-                     s, a.n, a.pos, a.lam, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gamma, gop,
-                     status, q, rhs, dxdt, tape);
+                     s, a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gamma, gop,
+                     status, rhs, dxdt, tape);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* lam,
+                       const double* q, double4* geo, double* fq) {
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, pos, lam, q, geo,
+                     fq);
   return hipGetLastError();
 }
 

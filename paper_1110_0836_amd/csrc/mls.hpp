@@ -9,7 +9,10 @@
 
 namespace phb {
 
-// Geometry and neighbor lists of one evaluation.
+// Geometry and neighbor lists of one evaluation.  geo and fq are the packed
+// per-particle records the neighbor loops read: geo[i] = (x, y, z, lambda)
+// (32 bytes) and fq[8 i .. 8 i + 7] = the eight fields (64 bytes), so that one
+// neighbor costs one or two cache lines instead of one line per array.
 struct EvalArgs {
   int n;
   const double* pos;
@@ -19,8 +22,18 @@ struct EvalArgs {
   Box box;
   double rf_ratio;
   int wkind;
+  const double4* geo = nullptr;
+  const double* fq = nullptr;
 };
 
+// Tape of the forward evaluation, per particle (SoA, n entries each):
+// 21 gradients (7 fields x 3), the status, then the 84 moments.
+constexpr int TAPE_MOM = 22;
+constexpr int TAPE_DOUBLES = 22 + NMOM;
+
+// geo (and fq when q != null) from the SoA inputs.
+hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* lam,
+                       const double* q, double4* geo, double* fq);
 hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom);
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,
                          double* gop, int32_t* status);

@@ -34,6 +34,7 @@ PER_PAIR = {
     "k_apply_rhs": 203,
     "k_adj_y": 203,
     "k_adj_pairs": 683,
+    "k_adj_pairs_w": 683,
 }
 PER_PARTICLE = {
     "k_factor<3>": 5704,

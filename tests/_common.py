@@ -30,14 +30,31 @@ def rel_err(g, o, axis=None):
 GROUPS = {"rho": [0], "V": [1, 2, 3], "B": [4, 5, 6], "sigma": [7]}
 
 
-def rhs_err(g, o):
-    """Max relative error of (8, m) time derivatives per physical quantity:
-    components of a vector share one denominator (a component that vanishes
+def rhs_err(g, o, q=None, d1=None, gamma=5.0 / 3.0):
+    """Max relative error of (8, m) time derivatives per physical quantity.
+    Components of a vector share one denominator (a component that vanishes
     identically, such as dBx/dt of a plane wave along x, is judged against
-    the size of its vector)."""
+    the size of its vector).  Given the fields q (8, m) and their first
+    derivatives d1 (8, 3, m), the denominator is at least the size of the
+    terms each quantity is summed from, e.g. |rho| max|grad V| for drho/dt:
+    a time derivative that cancels to far below its terms (div V of a
+    shear flow) cannot be held to 1e-12 of its own size by any evaluation."""
     g = np.asarray(g)
     o = np.asarray(o)
-    return {k: float(np.abs(g[v] - o[v]).max() / max(np.abs(o[v]).max(), 1e-300))
+    floor = {k: 0.0 for k in GROUPS}
+    if q is not None and d1 is not None:
+        q = np.asarray(q)
+        d1 = np.asarray(d1)
+        gv = np.abs(d1[1:4]).max()
+        gb = np.abs(d1[4:7]).max()
+        gs = np.abs(d1[7]).max()
+        bmax = np.abs(q[4:7]).max()
+        rmin = np.abs(q[0]).min()
+        floor = {"rho": np.abs(q[0]).max() * gv,
+                 "V": ((gamma - 1) * gs + bmax * gb) / rmin,
+                 "B": bmax * gv,
+                 "sigma": gamma * np.abs(q[7]).max() * gv}
+    return {k: float(np.abs(g[v] - o[v]).max() / max(np.abs(o[v]).max(), floor[k], 1e-300))
             for k, v in GROUPS.items()}
 
 

@@ -79,25 +79,39 @@ def test_status_paths():
 
 
 def rhs_both(c, rows=None, **kw):
+    """GPU and oracle time derivatives (optionally on sampled rows), plus the
+    GPU's saved gradients and the oracle's first derivatives of all fields."""
     s = setup_of(c, **kw)
     pos, lam = dev(c["pos"]), dev(c["lam"])
     off, idx = P.neighbors(pos, lam, s)
-    rhs, dxdt, st = P.mhd_rhs(pos, lam, off, idx, dev(c["q"]), s)
+    rhs, dxdt, st, tape = P.mhd_rhs(pos, lam, off, idx, dev(c["q"]), s, tape=True)
+    n = c["lam"].shape[0]
     ooff, oidx = oracle.neighbors(c["pos"], c["lam"], L=c["L"], periodic=c["periodic"], rows=rows)
     orhs, odx, ost = oracle.mhd_rhs(c["pos"], c["lam"], ooff, oidx, c["q"], L=c["L"],
-                                    periodic=c["periodic"], gamma=c["gamma"], rows=rows)
-    g = (rhs.cpu().numpy(), dxdt.cpu().numpy(), st.cpu().numpy())
+                                    periodic=c["periodic"], gamma=c["gamma"], rows=rows,
+                                    weight=kw.get("weight", 0))
+    od1, _, _ = oracle.mls_derivs(c["pos"], c["lam"], ooff, oidx, c["q"], L=c["L"],
+                                  periodic=c["periodic"], rows=rows, second=False,
+                                  weight=kw.get("weight", 0))
+    grads = tape[:21 * n].view(7, 3, n).cpu().numpy()
+    g = (rhs.cpu().numpy(), dxdt.cpu().numpy(), st.cpu().numpy(), grads)
+    qs = c["q"]
     if rows is not None:
-        g = (g[0][:, rows], g[1][:, rows], g[2][rows])
-    return g, (orhs, odx, ost)
+        g = (g[0][:, rows], g[1][:, rows], g[2][rows], g[3][:, :, rows])
+        qs = c["q"][:, rows]
+    return g, (orhs, odx, ost, od1), qs
 
 
-def check_rhs(g, o, tol, sel=None):
-    (r, x, s), (orr, ox, os_) = g, o
+def check_rhs(g, o, qs, tol, sel=None, gamma=5.0 / 3.0):
+    (r, x, s, gd), (orr, ox, os_, od1) = g, o
     assert np.array_equal(s, os_)
     ok = s == 0 if sel is None else (s == 0) & sel
-    e = rhs_err(r[:, ok], orr[:, ok])
-    print("rhs max rel err per quantity", e)
+    # the derivative operator itself, per field (V, B, sigma)
+    ed = rel_err(gd[:, :, ok], od1[1:, :, ok], axis=(1, 2))
+    print("gradient max rel err per field", ed)
+    assert ed.max() < tol
+    e = rhs_err(r[:, ok], orr[:, ok], qs[:, ok], od1[:, :, ok], gamma)
+    print("rhs max rel err per quantity (relative to its terms)", e)
     assert max(e.values()) < tol
     assert np.array_equal(x, ox)
     return e
@@ -115,21 +129,18 @@ def test_rhs_cp_alfven():
 def test_rhs_random_open_box():
     c = synth.random_cloud(2500, seed=12, lam_range=(0.07, 0.1), periodic=(0, 1, 0))
     c["q"][0] = 1.0 + 0.1 * np.abs(c["q"][0])
-    g, o = rhs_both(c)
-    check_rhs(g, o, TOL64, interior(c["pos"], c["lam"], c["L"], c["periodic"]))
-    check_rhs(g, o, 1e-5)
+    g, o, qs = rhs_both(c)
+    check_rhs(g, o, qs, TOL64, interior(c["pos"], c["lam"], c["L"], c["periodic"]))
+    check_rhs(g, o, qs, 1e-5)
 
 
 def test_rhs_unit_weight():
     c = synth.config2(side=16)
-    s = setup_of(c, weight=P.PHB_W_UNIT)
-    pos, lam = dev(c["pos"]), dev(c["lam"])
-    off, idx = P.neighbors(pos, lam, s)
-    rhs, dxdt, st = P.mhd_rhs(pos, lam, off, idx, dev(c["q"]), s)
-    ooff, oidx = oracle.neighbors(c["pos"], c["lam"])
-    orhs, _, ost = oracle.mhd_rhs(c["pos"], c["lam"], ooff, oidx, c["q"], weight=1)
-    assert np.array_equal(st.cpu().numpy(), ost)
-    assert max(rhs_err(rhs.cpu().numpy(), orhs).values()) < TOL64
+    g, o, qs = rhs_both(c, weight=P.PHB_W_UNIT)
+    orhs, _, _ = oracle.mhd_rhs(c["pos"], c["lam"], *oracle.neighbors(c["pos"], c["lam"]),
+                                c["q"], weight=1)
+    assert np.array_equal(o[0], orhs)  # rhs_both passed the weight to the oracle
+    check_rhs(g, o, qs, TOL64)
 
 
 def test_rhs_fast_wave_full_size_sampled():
