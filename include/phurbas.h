@@ -191,8 +191,11 @@ int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, double*
  * transposed row in the reverse mode), "adj_pairs_mode" (0: one lane per
  * neighbor entry, 1: one wavefront per owner particle), "record_order" (0:
  * pair records written at their transposed position, 1: written in forward
- * order and gathered through the inverse map).  EINVAL for an unknown key or
- * value. */
+ * order and gathered through the inverse map), "mixed_cond_exp" (0..12,
+ * default 3: in the mixed form a particle whose FP32-assembled moment matrix,
+ * scaled to unit diagonal, has an estimated ||A^{-1}||_2 above 10^exp is
+ * evaluated in FP64 instead; this knob moves results within the mixed
+ * tolerance, the others only by rounding).  EINVAL for an unknown key or value. */
 int phb_tune_set(phb_ctx* ctx, const char* key, int value);
 int phb_tune_get(phb_ctx* ctx, const char* key, int* value);
 

@@ -243,7 +243,7 @@ def phb_pc_step(setup, dt, pos, q, lam, offsets, idx, capacity, status):
 
 
 TUNE_KEYS = ("cells_per_rf", "lanes_moments", "lanes_apply", "lanes_adj_y", "lanes_gather",
-             "adj_pairs_mode", "record_order")
+             "adj_pairs_mode", "record_order", "mixed_cond_exp")
 
 
 def phb_tune_set(key, value, device=None):

@@ -23,19 +23,11 @@
 #include <type_traits>
 
 #include "adjoint.hpp"
+#include "chol.hpp"
 #include "mhd.hpp"
 #include "neighbors.hpp"
 
 namespace phb {
-
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for_a(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for_a<B + 1, E>(f);
-  }
-}
-
 namespace {
 
 constexpr int THREADS = 256;
@@ -46,17 +38,6 @@ constexpr int REC = 10;  // doubles per pair record: dfbar (7), dbar (3)
 constexpr int OREC = 144;
 constexpr int UOFF = 120;
 constexpr int PAIRS_PER_BLOCK = 256;
-
-struct EntryTableA {
-  unsigned char v[NBASIS * NBASIS];
-};
-constexpr EntryTableA make_entry_table_a() {
-  EntryTableA t{};
-  for (int r = 0; r < NBASIS; ++r)
-    for (int c = 0; c < NBASIS; ++c) t.v[r * NBASIS + c] = (unsigned char)entry_moment(r, c);
-  return t;
-}
-__constant__ EntryTableA c_entry_a = make_entry_table_a();
 
 // Pointwise adjoint of particle i; returns Ubar (coefficient space) and adds
 // the direct part to qb.  Status != 0: no gradient through rhs.
@@ -184,7 +165,7 @@ __global__ void __launch_bounds__(THREADS)
 }
 
 // ---- 3. factor again: G = rows 1..3 of A^{-1}, K_t = A^{-1} Y_t ------------
-__host__ __device__ constexpr int aoff_a(int rho) { return 2 * rho * (rho + 1); }
+__constant__ EntryTab c_tab_a = make_entry_tab();
 
 __global__ void __launch_bounds__(THREADS)
     k_adj_factor(int n, const double* __restrict__ mom, const double* __restrict__ ybuf,
@@ -194,111 +175,28 @@ __global__ void __launch_bounds__(THREADS)
   const int l = tid & 3;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
-  double a[60];
-  double dg[5];
-  static_for_a<0, 5>([&](auto R) {
-    constexpr int rho = R;
-    const int r = 4 * rho + l;
-    static_for_a<0, 4 * rho + 4>([&](auto C) {
-      constexpr int c = C;
-      a[aoff_a(rho) + c] = mom[(int64_t)c_entry_a.v[r * NBASIS + c] * n + ii];
-    });
-    dg[rho] = mom[(int64_t)c_entry_a.v[r * NBASIS + r] * n + ii];
-  });
-  double s_own[5];
-  static_for_a<0, 5>([&](auto R) {
-    constexpr int rho = R;
-    s_own[rho] = dg[rho] > 0.0 ? 1.0 / sqrt(dg[rho]) : 1.0;
-  });
-  double s_all[NBASIS];
-  static_for_a<0, NBASIS>([&](auto C) {
-    constexpr int c = C;
-    s_all[c] = quad_bcast<c & 3>(s_own[c >> 2]);
-  });
-  static_for_a<0, 5>([&](auto R) {
-    constexpr int rho = R;
-    static_for_a<0, 4 * rho + 4>([&](auto C) {
-      constexpr int c = C;
-      a[aoff_a(rho) + c] *= s_own[rho] * s_all[c];
-    });
-  });
-  double inv_ld[NBASIS];
-  static_for_a<0, NBASIS>([&](auto K) {
-    constexpr int k = K;
-    constexpr int o = k & 3;
-    constexpr int rk = k >> 2;
-    const double dkk = quad_bcast<o>(a[aoff_a(rk) + k]);
-    const double inv = 1.0 / sqrt(dkk > 0.0 ? dkk : 1.0);
-    inv_ld[k] = inv;
-    static_for_a<rk, 5>([&](auto R) {
-      constexpr int rho = R;
-      a[aoff_a(rho) + k] *= inv;
-    });
-    double colk[NBASIS];
-    static_for_a<k + 1, NBASIS>([&](auto C) {
-      constexpr int c = C;
-      colk[c] = quad_bcast<c & 3>(a[aoff_a(c >> 2) + k]);
-    });
-    static_for_a<rk, 5>([&](auto R) {
-      constexpr int rho = R;
-      static_for_a<k + 1, 4 * rho + 4>([&](auto C) {
-        constexpr int c = C;
-        a[aoff_a(rho) + c] = fma(-a[aoff_a(rho) + k], colk[c], a[aoff_a(rho) + c]);
-      });
-    });
-  });
+  QuadChol c;
+  quad_chol_factor(c, c_tab_a, mom, n, ii, l);
   const int st = (int)tape[(int64_t)21 * n + ii];
-  // Six right-hand sides: e_1, e_2, e_3 (rows of A^{-1}) and Y_0..Y_2.
-  // In equilibrated form A^{-1} b = S A_hat^{-1} (S b).
-  static_for_a<0, 6>([&](auto RH) {
+  // G rows at 0..59 and K rows at 60..119 of the owner record
+  sfor<0, 6>([&](auto RH) {
     constexpr int rh = RH;
-    double y[5];
-    static_for_a<0, 5>([&](auto R) {
-      constexpr int rho = R;
-      const int r = 4 * rho + l;
-      double b;
-      if constexpr (rh < 3)
-        b = (r == 1 + rh) ? s_all[1 + rh] : 0.0;
-      else
-        b = ybuf[((int64_t)(rh - 3) * NBASIS + r) * n + ii] * s_own[rho];
-      y[rho] = b;
-    });
-    constexpr int k0 = rh < 3 ? 1 + rh : 0;
-    static_for_a<k0, NBASIS>([&](auto K) {
-      constexpr int k = K;
-      constexpr int o = k & 3;
-      constexpr int rk = k >> 2;
-      const double yk = quad_bcast<o>(y[rk]) * inv_ld[k];
-      static_for_a<rk + 1, 5>([&](auto R) {
+    double out[5];
+    if constexpr (rh < 3) {
+      quad_chol_inverse_row<1 + rh>(c, l, out);
+    } else {
+      double b[5];
+      sfor<0, 5>([&](auto R) {
         constexpr int rho = R;
-        y[rho] = fma(-a[aoff_a(rho) + k], yk, y[rho]);
+        b[rho] = ybuf[((int64_t)(rh - 3) * NBASIS + 4 * rho + l) * n + ii];
       });
-      const double upd = fma(-a[aoff_a(rk) + k], yk, y[rk]);
-      y[rk] = (l == o) ? yk : ((l > o) ? upd : y[rk]);
-    });
-    double x[5];
-    static_for_a<0, 5>([&](auto R) { x[R] = y[R]; });
-    static_for_a<0, NBASIS>([&](auto KK) {
-      constexpr int k = NBASIS - 1 - KK;
-      constexpr int o = k & 3;
-      constexpr int rk = k >> 2;
-      double part = 0.0;
-      static_for_a<rk + 1, 5>([&](auto R) {
-        constexpr int rho = R;
-        part = fma(a[aoff_a(rho) + k], x[rho], part);
-      });
-      part += (l > o) ? a[aoff_a(rk) + k] * x[rk] : 0.0;
-      part = group_sum<4>(part);
-      const double xk = (y[rk] - part) * inv_ld[k];
-      x[rk] = (l == o) ? xk : x[rk];
-    });
+      quad_chol_apply_inverse(c, l, b, out);
+    }
     if (valid) {
-      static_for_a<0, 5>([&](auto R) {
+      sfor<0, 5>([&](auto R) {
         constexpr int rho = R;
-        const int r = 4 * rho + l;
-        const double v = st == 0 ? x[rho] * s_own[rho] : 0.0;
-        // G rows at 0..59 and K rows at 60..119 of the owner record
-        gop[(int64_t)i * OREC + rh * NBASIS + r] = v;
+        const double v = out[rho];
+        gop[(int64_t)i * OREC + rh * NBASIS + 4 * rho + l] = st == 0 ? v : 0.0;
       });
     }
   });
@@ -707,6 +605,12 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     ws.plan(3 * nd);                     // dxdt scratch
     ws.plan((size_t)n * sizeof(int32_t));
   }
+  // The mixed form's tape holds FP32-assembled moments.  Its forward pass
+  // refines them away at the data level, but the reverse mode solves with
+  // right-hand sides built from the incoming gradients, which carry no such
+  // structure: it assembles the moments again in FP64.
+  const bool fresh_mom = !need_tape && p->precision == PHB_MIXED;
+  if (fresh_mom) ws.plan((size_t)NMOM * nd);
   if ((rc = ws.commit())) return rc;
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
@@ -742,6 +646,13 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     tape = tp;
   }
   const double* mom = tape + (size_t)TAPE_MOM * n;
+  if (fresh_mom) {
+    double* m64 = ws.take<double>((size_t)NMOM * n);
+    Prof pf(ctx, "k_moments");
+    if ((rc = hip_check(ctx, launch_moments(s, ap, ctx->lanes_assemble, m64), "moments")))
+      return rc;
+    mom = m64;
+  }
   { Prof pf(ctx, "k_adj_y");
   switch (ctx->lanes_adj_y) {
     case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
@@ -792,13 +703,6 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     hipLaunchKernelGGL((k_adj_gather<4>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets, tsl, rec, own,
                        qbd, q_bar, pos_bar);
   return hip_check(ctx, hipGetLastError(), "adjoint gather");
-}
-
-size_t mixed_rhs_bytes(int64_t n) { return 0; }
-
-int mixed_rhs(phb_ctx* ctx, const EvalArgs& a, double gamma, const double* q, double* rhs,
-              double* dxdt, int32_t* status, double* tape) {
-  return set_error(ctx, PHB_ENOTIMPL, "mixed precision not built yet");
 }
 
 }  // namespace phb

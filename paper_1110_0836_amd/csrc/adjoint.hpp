@@ -16,6 +16,9 @@ size_t mixed_rhs_bytes(int64_t n);
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a, double gamma, const double* q, double* rhs,
               double* dxdt, int32_t* status, double* tape);
 
+int mixed_derivs(phb_ctx* ctx, const EvalArgs& a, int nf, const double* fields, double* d1,
+                 double* d2, int32_t* status);
+
 int pc_step(phb_ctx* ctx, const phb_params* p, int n, double dt, double* pos, double* q,
             const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
             int64_t* nnz_out, int32_t* status);

@@ -292,6 +292,7 @@ static int* tune_slot(phb_ctx* ctx, const char* key) {
   if (!strcmp(key, "lanes_apply")) return &ctx->lanes_apply;
   if (!strcmp(key, "lanes_adj_y")) return &ctx->lanes_adj_y;
   if (!strcmp(key, "lanes_gather")) return &ctx->lanes_gather;
+  if (!strcmp(key, "mixed_cond_exp")) return &ctx->mixed_cond_exp;
   if (!strcmp(key, "adj_pairs_mode")) return &ctx->adj_pairs_mode;
   if (!strcmp(key, "record_order")) return &ctx->record_order;
   return nullptr;
@@ -303,8 +304,10 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
   if (!slot) return set_error(ctx, PHB_EINVAL, std::string("unknown tuning key ") + key);
   const bool lanes = strncmp(key, "lanes_", 6) == 0;
   const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order");
-  if (lanes ? !(value == 1 || value == 2 || value == 4)
-            : (mode ? !(value == 0 || value == 1) : !(value >= 1 && value <= 4)))
+  const bool cut = !strcmp(key, "mixed_cond_exp");
+  if (cut ? !(value >= 0 && value <= 12)
+          : lanes ? !(value == 1 || value == 2 || value == 4)
+                  : (mode ? !(value == 0 || value == 1) : !(value >= 1 && value <= 4)))
     return set_error(ctx, PHB_EINVAL, std::string("bad value for ") + key);
   *slot = value;
   return PHB_OK;
@@ -485,9 +488,9 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double*
   if (nf <= 0 || !fields || !d1 || !status || (max_order != 1 && max_order != 2) ||
       (max_order == 2 && !d2))
     return set_error(ctx, PHB_EINVAL, "bad field arguments");
-  if (p->precision != PHB_FP64)
-    return set_error(ctx, PHB_ENOTIMPL, "derivatives are built in FP64 only");
   hipSetDevice(ctx->device);
+  if (p->precision == PHB_MIXED)
+    return mixed_derivs(ctx, a, nf, fields, d1, max_order == 2 ? d2 : nullptr, status);
   const int n = a.n;
   Workspace ws(ctx);
   ws.plan((size_t)NMOM * n * sizeof(double));

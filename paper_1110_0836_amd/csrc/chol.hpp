@@ -1,0 +1,200 @@
+// Equilibrated FP64 Cholesky of one particle's 20x20 moment matrix, held by
+// the four lanes of a quad (lane l owns rows l, l+4, l+8, l+12, l+16), and
+// the triangular solves against it.  Used by every kernel that needs A^{-1}.
+#pragma once
+
+#include <type_traits>
+
+#include "device.hpp"
+
+namespace phb {
+
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+// Row rho of a lane lives at a[aoff(rho) .. aoff(rho) + 4 rho + 3]: the
+// longest row any lane can own among rows 4 rho .. 4 rho + 3.  Entries right
+// of a lane's own diagonal hold scratch values that are never read.
+__host__ __device__ constexpr int chol_aoff(int rho) { return 2 * rho * (rho + 1); }
+
+struct EntryTab {
+  unsigned char v[NBASIS * NBASIS];
+};
+constexpr EntryTab make_entry_tab() {
+  EntryTab t{};
+  for (int r = 0; r < NBASIS; ++r)
+    for (int c = 0; c < NBASIS; ++c) t.v[r * NBASIS + c] = (unsigned char)entry_moment(r, c);
+  return t;
+}
+
+struct QuadChol {
+  double a[60];        // own rows of L (equilibrated)
+  double s_own[5];     // equilibration scale of the own rows
+  double s_all[NBASIS];
+  double inv_ld[NBASIS];
+  bool ok;
+  double ldmin, ldmax;
+};
+
+// Loads A from the moments (SoA [84][n]), equilibrates A_hat = S A S with
+// S = diag(1/sqrt(A_rr)) and factors A_hat = L L^T.  tab is the entry->moment
+// table in constant memory.
+__device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& tab,
+                                                 const double* __restrict__ mom, int64_t n,
+                                                 int ii, int l) {
+  double dg[5];
+  sfor<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    const int r = 4 * rho + l;
+    sfor<0, 4 * rho + 4>([&](auto C) {
+      constexpr int cc = C;
+      c.a[chol_aoff(rho) + cc] = mom[(int64_t)tab.v[r * NBASIS + cc] * n + ii];
+    });
+    dg[rho] = mom[(int64_t)tab.v[r * NBASIS + r] * n + ii];
+  });
+  c.ok = true;
+  sfor<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    c.ok = c.ok && (dg[rho] > 0.0);
+    c.s_own[rho] = dg[rho] > 0.0 ? 1.0 / sqrt(dg[rho]) : 1.0;
+  });
+  c.ok = quad_min(c.ok ? 1.0 : 0.0) > 0.5;  // the same verdict on all four lanes
+  sfor<0, NBASIS>([&](auto C) {
+    constexpr int cc = C;
+    c.s_all[cc] = quad_bcast<cc & 3>(c.s_own[cc >> 2]);
+  });
+  sfor<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    sfor<0, 4 * rho + 4>([&](auto C) {
+      constexpr int cc = C;
+      c.a[chol_aoff(rho) + cc] *= c.s_own[rho] * c.s_all[cc];
+    });
+  });
+  c.ldmin = 1e300;
+  c.ldmax = 0.0;
+  sfor<0, NBASIS>([&](auto K) {
+    constexpr int k = K;
+    constexpr int o = k & 3;
+    constexpr int rk = k >> 2;
+    const double dkk = quad_bcast<o>(c.a[chol_aoff(rk) + k]);
+    c.ok = c.ok && (dkk > 0.0);
+    const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0);
+    c.ldmin = fmin(c.ldmin, lkk);
+    c.ldmax = fmax(c.ldmax, lkk);
+    const double inv = 1.0 / lkk;
+    c.inv_ld[k] = inv;
+    sfor<rk, 5>([&](auto R) {
+      constexpr int rho = R;
+      c.a[chol_aoff(rho) + k] *= inv;
+    });
+    double colk[NBASIS];
+    sfor<k + 1, NBASIS>([&](auto C) {
+      constexpr int cc = C;
+      colk[cc] = quad_bcast<cc & 3>(c.a[chol_aoff(cc >> 2) + k]);
+    });
+    sfor<rk, 5>([&](auto R) {
+      constexpr int rho = R;
+      sfor<k + 1, 4 * rho + 4>([&](auto C) {
+        constexpr int cc = C;
+        c.a[chol_aoff(rho) + cc] = fma(-c.a[chol_aoff(rho) + k], colk[cc], c.a[chol_aoff(rho) + cc]);
+      });
+    });
+  });
+}
+
+// Status of the factorization: too few neighbors, singular, or fine.
+__device__ __forceinline__ int quad_chol_status(const QuadChol& c, int nnb) {
+  const double rc = c.ldmin / c.ldmax;
+  if (nnb < NBASIS) return 1;
+  if (!c.ok || !(rc * rc >= 1e-12)) return 2;
+  return 0;
+}
+
+// x = A_hat^{-1} y for own rows; y is overwritten with the forward solution.
+// K0: index of the first possibly nonzero entry of y.  ADAPT: the right-hand
+// side is not given but chosen entry by entry as +-1, with the sign that
+// makes the forward solution grow most (LINPACK's condition estimator); y
+// must enter as zeros.
+template <int K0, bool ADAPT = false>
+__device__ __forceinline__ void quad_chol_solve(const QuadChol& c, int l, double (&y)[5],
+                                                double (&x)[5]) {
+  sfor<K0, NBASIS>([&](auto K) {
+    constexpr int k = K;
+    constexpr int o = k & 3;
+    constexpr int rk = k >> 2;
+    double t = quad_bcast<o>(y[rk]);
+    if constexpr (ADAPT) t += t >= 0.0 ? 1.0 : -1.0;
+    const double yk = t * c.inv_ld[k];
+    sfor<rk + 1, 5>([&](auto R) {
+      constexpr int rho = R;
+      y[rho] = fma(-c.a[chol_aoff(rho) + k], yk, y[rho]);
+    });
+    const double upd = fma(-c.a[chol_aoff(rk) + k], yk, y[rk]);
+    y[rk] = (l == o) ? yk : ((l > o) ? upd : y[rk]);
+  });
+  sfor<0, 5>([&](auto R) { x[R] = y[R]; });
+  sfor<0, NBASIS>([&](auto KK) {
+    constexpr int k = NBASIS - 1 - KK;
+    constexpr int o = k & 3;
+    constexpr int rk = k >> 2;
+    double part = 0.0;
+    sfor<rk + 1, 5>([&](auto R) {
+      constexpr int rho = R;
+      part = fma(c.a[chol_aoff(rho) + k], x[rho], part);
+    });
+    part += (l > o) ? c.a[chol_aoff(rk) + k] * x[rk] : 0.0;
+    part = group_sum<4>(part);
+    const double xk = (y[rk] - part) * c.inv_ld[k];
+    x[rk] = (l == o) ? xk : x[rk];
+  });
+}
+
+// Row t of A^{-1} (own entries): A^{-1} = S A_hat^{-1} S.
+template <int T>
+__device__ __forceinline__ void quad_chol_inverse_row(const QuadChol& c, int l, double (&out)[5]) {
+  double y[5];
+  sfor<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    y[rho] = (4 * rho + l == T) ? c.s_all[T] : 0.0;
+  });
+  double x[5];
+  quad_chol_solve<T>(c, l, y, x);
+  sfor<0, 5>([&](auto R) { out[R] = x[R] * c.s_own[R]; });
+}
+
+// Estimate of the 2-norm of A_hat^{-1} (the equilibrated matrix), from below
+// and in practice within a small factor: x = A_hat^{-1} e with the signs of e
+// chosen for growth as above, then one power step z = A_hat^{-1} x and
+// ||z|| / ||x||.
+__device__ __forceinline__ double quad_chol_inv_norm_est(const QuadChol& c, int l) {
+  double y[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double x[5], z[5];
+  quad_chol_solve<0, true>(c, l, y, x);
+  sfor<0, 5>([&](auto R) { y[R] = x[R]; });
+  quad_chol_solve<0>(c, l, y, z);
+  double xx = 0.0, zz = 0.0;
+  sfor<0, 5>([&](auto R) {
+    xx = fma(x[R], x[R], xx);
+    zz = fma(z[R], z[R], zz);
+  });
+  xx = group_sum<4>(xx);
+  zz = group_sum<4>(zz);
+  return sqrt(zz / xx);
+}
+
+// A^{-1} b for a general right-hand side b given by its own rows.
+__device__ __forceinline__ void quad_chol_apply_inverse(const QuadChol& c, int l,
+                                                        const double (&b)[5], double (&out)[5]) {
+  double y[5];
+  sfor<0, 5>([&](auto R) { y[R] = b[R] * c.s_own[R]; });
+  double x[5];
+  quad_chol_solve<0>(c, l, y, x);
+  sfor<0, 5>([&](auto R) { out[R] = x[R] * c.s_own[R]; });
+}
+
+}  // namespace phb

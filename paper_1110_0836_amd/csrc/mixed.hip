@@ -1,0 +1,563 @@
+// Mixed-precision moving-least-squares derivatives and time derivatives.
+//
+// Assembly and field application run in FP32 (displacements and field
+// differences are formed in FP64 first, scaled by 1/lambda_i, then rounded),
+// the 20x20 factorization and solves stay in FP64, and one data-level
+// refinement step follows.  With C~ = A~^{-1} B~ from the FP32 sums, the
+// residuals r_j = df_j - p(xi_j) . C~ of every neighbor are summed into
+// dB = sum_j w_j p(xi_j) r_j (FP32), and the requested coefficient rows are
+// E C = E C~ + G~ dB with G~ = E A~^{-1}.  This is one step of the corrected
+// seminormal equations (Bjorck): forming the normal matrix in FP32 costs
+// kappa(A) eps_32, while the refined solution only sees the data rounding,
+// amplified by kappa(P) = sqrt(kappa(A)).
+//
+// A particle whose FP32-assembled matrix is too ill-conditioned for one step
+// to converge (estimated norm of the inverse of the equilibrated matrix above
+// a cut, or a failed pivot) is recomputed entirely in FP64: its moments and
+// right-hand sides are re-assembled in FP64 and factored again, so that its
+// status and result are those of the FP64 form.  Such particles are collected into a
+// list (order irrelevant: each is processed on its own).
+//
+// Kernels, per evaluation of up to 8 fields:
+//   k_moments<fp32>   84 moments, FP32 accumulation            (mls.hip)
+//   k_mixed_b         B~ = sum w p df, quad per particle, lane l owns fields
+//                     l and l + 4
+//   k_mixed_factor    FP64 equilibrated Cholesky of A~, screening, C~ and G~
+//   k_mixed_repair    FP64 moments and B of the listed particles
+//   k_mixed_factor    (list form) FP64 factor and solves of the listed ones
+//   k_mixed_resid     dB in FP32 and the refined rows E C~ + G~ dB
+//   finish            scaling by powers of 1/lambda, the MHD right-hand side
+#include "adjoint.hpp"
+#include "chol.hpp"
+#include "internal.hpp"
+#include "mhd.hpp"
+#include "mls.hpp"
+
+namespace phb {
+namespace {
+
+constexpr int THREADS = 256;
+constexpr int LIST_BLOCKS = 512;  // grid of the list-driven kernels
+
+__constant__ EntryTab c_mtab = make_entry_tab();
+
+// Local frame of particle i: FP64 displacement to a neighbor, then FP32
+// weight and scaled coordinates.
+struct Frame {
+  double x, y, z, inv_lam, inv_r2;
+  Box box;
+  int wkind;
+  __device__ __forceinline__ void at(const double4& gj, float& w, float& xs, float& ys,
+                                     float& zs) const {
+    const double dx = min_image(gj.x - x, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(gj.y - y, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz = min_image(gj.z - z, box.L[2], box.halfL[2], box.periodic[2]);
+    w = (float)weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+    xs = (float)(dx * inv_lam);
+    ys = (float)(dy * inv_lam);
+    zs = (float)(dz * inv_lam);
+  }
+};
+
+__device__ __forceinline__ Frame make_frame(const double4& gi, const Box& box, double rf_ratio,
+                                            int wkind) {
+  Frame f;
+  f.x = gi.x;
+  f.y = gi.y;
+  f.z = gi.z;
+  f.inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
+  f.inv_r2 = 1.0 / (r * r);
+  f.box = box;
+  f.wkind = wkind;
+  return f;
+}
+
+// B~[f][b] = sum_j w_j p_b(xi_j) (f_j - f_i) in FP32.  Four lanes per
+// particle; lane l owns fields l and l + 4 of the records fa[8 j + fb + f].
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_b(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+              const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
+              const double* __restrict__ fa, int fb, int nf, double* __restrict__ bout) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid >> 2;
+  const int l = tid & 3;
+  if (i >= n) return;
+  const bool has0 = l < nf, has1 = l + 4 < nf;
+  const int fa0 = fb + (has0 ? l : 0), fa1 = fb + (has1 ? l + 4 : 0);
+  const double4 gi = geo[i];
+  const Frame fr = make_frame(gi, box, rf_ratio, wkind);
+  const double fi0 = fa[8 * (int64_t)i + fa0], fi1 = fa[8 * (int64_t)i + fa1];
+  float acc0[NBASIS], acc1[NBASIS];
+#pragma unroll
+  for (int b = 0; b < NBASIS; ++b) acc0[b] = acc1[b] = 0.f;
+  const int64_t s0 = off[i], s1 = off[i + 1];
+  int64_t s = s0;
+  // the next neighbor's record is fetched one iteration ahead
+  double4 gn = gi;
+  double vn0 = fi0, vn1 = fi1;
+  if (s < s1) {
+    const int j = idx[s];
+    gn = geo[j];
+    vn0 = fa[8 * (int64_t)j + fa0];
+    vn1 = fa[8 * (int64_t)j + fa1];
+  }
+  for (; s < s1; ++s) {
+    const double4 gj = gn;
+    const double v0 = vn0, v1 = vn1;
+    if (s + 1 < s1) {
+      const int j = idx[s + 1];
+      gn = geo[j];
+      vn0 = fa[8 * (int64_t)j + fa0];
+      vn1 = fa[8 * (int64_t)j + fa1];
+    }
+    float w, xs, ys, zs;
+    fr.at(gj, w, xs, ys, zs);
+    float p[NBASIS];
+    basis(p, xs, ys, zs);
+    const float d0 = w * (float)(v0 - fi0);
+    const float d1 = w * (float)(v1 - fi1);
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) {
+      acc0[b] = fmaf(d0, p[b], acc0[b]);
+      acc1[b] = fmaf(d1, p[b], acc1[b]);
+    }
+  }
+  if (has0) {
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) bout[((int64_t)l * NBASIS + b) * n + i] = (double)acc0[b];
+  }
+  if (has1) {
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b)
+      bout[((int64_t)(l + 4) * NBASIS + b) * n + i] = (double)acc1[b];
+  }
+}
+
+// Equilibrated FP64 Cholesky of the moments of particle i (quad lanes),
+// C = A^{-1} B for nf fields and G = rows 1..NG of A^{-1}.
+//
+// Screening form (list_in == null, one quad per particle): a particle with at
+// least 20 neighbors whose factorization fails or whose equilibrated matrix
+// has an estimated ||A_hat^{-1}|| above ncut is flagged and appended to
+// list_out; its outputs are left to the list form.  (The refinement step
+// contracts the error by about kappa * eps_32 * sqrt(n); the equilibrated
+// matrix has unit diagonal, so kappa <= 20 ||A_hat^{-1}||.)  List form: the
+// particles list_in[0 .. *count) (FP64 moments by then), a grid-stride loop
+// over quads.
+template <int NG>
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_factor(int n, const double* __restrict__ mom, const int64_t* __restrict__ off, int nf,
+                   const double* __restrict__ bin, double* __restrict__ cfit,
+                   double* __restrict__ gt, int32_t* __restrict__ status,
+                   int32_t* __restrict__ flag, double ncut, const int32_t* __restrict__ list_in,
+                   int32_t* __restrict__ list_out, int32_t* __restrict__ count) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int l = tid & 3;
+  const int quad = tid >> 2;
+  const bool listed = list_in != nullptr;
+  const int total = listed ? *count : n;
+  const int stride = listed ? (int)(gridDim.x * (THREADS / 4)) : total;
+  for (int k = quad; k < total; k += stride) {
+    const int i = listed ? list_in[k] : k;
+    QuadChol c;
+    quad_chol_factor(c, c_mtab, mom, n, i, l);
+    const int nnb = (int)(off[i + 1] - off[i]);
+    const int st = quad_chol_status(c, nnb);
+    if (!listed) {
+      const bool bad = nnb >= NBASIS && (st != 0 || !(quad_chol_inv_norm_est(c, l) <= ncut));
+      if (l == 0) flag[i] = bad ? 1 : 0;
+      if (bad) {
+        if (l == 0) list_out[atomicAdd(count, 1)] = i;
+        continue;
+      }
+    }
+    if (l == 0) status[i] = st;
+    for (int f = 0; f < nf; ++f) {
+      double b[5], x[5];
+      sfor<0, 5>([&](auto R) {
+        constexpr int rho = R;
+        b[rho] = bin[((int64_t)f * NBASIS + 4 * rho + l) * n + i];
+      });
+      quad_chol_apply_inverse(c, l, b, x);
+      sfor<0, 5>([&](auto R) {
+        constexpr int rho = R;
+        cfit[((int64_t)f * NBASIS + 4 * rho + l) * n + i] = st == 0 ? x[rho] : 0.0;
+      });
+    }
+    sfor<0, NG>([&](auto TI) {
+      constexpr int t = 1 + TI;
+      double row[5];
+      quad_chol_inverse_row<t>(c, l, row);
+      sfor<0, 5>([&](auto R) {
+        constexpr int rho = R;
+        gt[((int64_t)TI * NBASIS + 4 * rho + l) * n + i] = st == 0 ? row[rho] : 0.0;
+      });
+    });
+  }
+}
+
+// FP64 moments and right-hand sides of the listed particles, one thread per
+// particle (few per set).
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_repair(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                   const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
+                   const double* __restrict__ fa, int fb, int nf, const int32_t* __restrict__ list,
+                   const int32_t* __restrict__ count, double* __restrict__ mom,
+                   double* __restrict__ bout) {
+  const int total = *count;
+  for (int k = blockIdx.x * THREADS + threadIdx.x; k < total; k += gridDim.x * THREADS) {
+    const int i = list[k];
+    const double4 gi = geo[i];
+    const double inv_lam = 1.0 / gi.w;
+    const double r = rf_ratio * gi.w;
+    const double inv_r2 = 1.0 / (r * r);
+    const int64_t s0 = off[i], s1 = off[i + 1];
+    double m[NMOM];
+#pragma unroll
+    for (int q = 0; q < NMOM; ++q) m[q] = 0.0;
+    for (int64_t s = s0; s < s1; ++s) {
+      const double4 gj = geo[idx[s]];
+      const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+      const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+      const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+      const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+      accumulate_moments(m, w, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    }
+#pragma unroll
+    for (int q = 0; q < NMOM; ++q) mom[(int64_t)q * n + i] = m[q];
+    for (int f = 0; f < nf; ++f) {
+      const double fi = fa[8 * (int64_t)i + fb + f];
+      double acc[NBASIS];
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b) acc[b] = 0.0;
+      for (int64_t s = s0; s < s1; ++s) {
+        const int j = idx[s];
+        const double4 gj = geo[j];
+        const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+        const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+        const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+        const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+        double p[NBASIS];
+        basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+        const double wd = w * (fa[8 * (int64_t)j + fb + f] - fi);
+#pragma unroll
+        for (int b = 0; b < NBASIS; ++b) acc[b] = fma(wd, p[b], acc[b]);
+      }
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b) bout[((int64_t)f * NBASIS + b) * n + i] = acc[b];
+    }
+  }
+}
+
+// dB = sum_j w_j p(xi_j) (df_j - p(xi_j) . C~) in FP32 for the fields of
+// this lane (l and l + 4), then rows[f][t] = C[f][1 + t] + (G~ dB)[t] for
+// t < NG (FP64).  Flagged particles and particles with status != 0 skip the
+// neighbor loop (dB = 0).
+template <int NG>
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_resid(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                  const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
+                  const double* __restrict__ fa, int fb, int nf, const double* __restrict__ cfit,
+                  const double* __restrict__ gt, const int32_t* __restrict__ status,
+                  const int32_t* __restrict__ flag, double* __restrict__ rows) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid >> 2;
+  const int l = tid & 3;
+  if (i >= n) return;
+  const bool has0 = l < nf, has1 = l + 4 < nf;
+  const int f0 = has0 ? l : 0, f1 = has1 ? l + 4 : 0;
+  const double4 gi = geo[i];
+  const Frame fr = make_frame(gi, box, rf_ratio, wkind);
+  const double fi0 = fa[8 * (int64_t)i + fb + f0], fi1 = fa[8 * (int64_t)i + fb + f1];
+  float c0[NBASIS], c1[NBASIS], a0[NBASIS], a1[NBASIS];
+#pragma unroll
+  for (int b = 0; b < NBASIS; ++b) {
+    c0[b] = (float)cfit[((int64_t)f0 * NBASIS + b) * n + i];
+    c1[b] = (float)cfit[((int64_t)f1 * NBASIS + b) * n + i];
+    a0[b] = a1[b] = 0.f;
+  }
+  const bool refine = status[i] == 0 && flag[i] == 0;
+  const int64_t s0 = off[i], s1 = refine ? off[i + 1] : s0;
+  int64_t s = s0;
+  double4 gn = gi;
+  double vn0 = fi0, vn1 = fi1;
+  if (s < s1) {
+    const int j = idx[s];
+    gn = geo[j];
+    vn0 = fa[8 * (int64_t)j + fb + f0];
+    vn1 = fa[8 * (int64_t)j + fb + f1];
+  }
+  for (; s < s1; ++s) {
+    const double4 gj = gn;
+    const double v0 = vn0, v1 = vn1;
+    if (s + 1 < s1) {
+      const int j = idx[s + 1];
+      gn = geo[j];
+      vn0 = fa[8 * (int64_t)j + fb + f0];
+      vn1 = fa[8 * (int64_t)j + fb + f1];
+    }
+    float w, xs, ys, zs;
+    fr.at(gj, w, xs, ys, zs);
+    float p[NBASIS];
+    basis(p, xs, ys, zs);
+    float fit0 = 0.f, fit1 = 0.f;
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) {
+      fit0 = fmaf(c0[b], p[b], fit0);
+      fit1 = fmaf(c1[b], p[b], fit1);
+    }
+    const float r0 = w * ((float)(v0 - fi0) - fit0);
+    const float r1 = w * ((float)(v1 - fi1) - fit1);
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) {
+      a0[b] = fmaf(r0, p[b], a0[b]);
+      a1[b] = fmaf(r1, p[b], a1[b]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NG; ++t) {
+    double u0 = cfit[((int64_t)f0 * NBASIS + 1 + t) * n + i];
+    double u1 = cfit[((int64_t)f1 * NBASIS + 1 + t) * n + i];
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) {
+      const double g = gt[((int64_t)t * NBASIS + b) * n + i];
+      u0 = fma(g, (double)a0[b], u0);
+      u1 = fma(g, (double)a1[b], u1);
+    }
+    if (has0) rows[((int64_t)f0 * NG + t) * n + i] = u0;
+    if (has1) rows[((int64_t)f1 * NG + t) * n + i] = u1;
+  }
+}
+
+// Gradients = rows / lambda; pointwise right-hand side; tape.
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_rhs_finish(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
+                       const double* __restrict__ rows, const int32_t* __restrict__ status,
+                       double gamma, double* __restrict__ rhs, double* __restrict__ dxdt,
+                       double* __restrict__ tape) {
+  const int i = blockIdx.x * THREADS + threadIdx.x;
+  if (i >= n) return;
+  const double inv_lam = 1.0 / geo[i].w;
+  double qi[8];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) qi[f] = fq[8 * (int64_t)i + f];
+  double grad[7][3];
+#pragma unroll
+  for (int f = 0; f < 7; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) grad[f][t] = rows[((int64_t)f * 3 + t) * n + i] * inv_lam;
+  const int st = status[i];
+  double out[8];
+  if (st == 0) {
+    mhd_point(qi, grad, gamma, out);
+  } else {
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+#pragma unroll
+    for (int f = 0; f < 8; ++f) out[f] = nan;
+  }
+#pragma unroll
+  for (int f = 0; f < 8; ++f) rhs[(int64_t)f * n + i] = out[f];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dxdt[(int64_t)a * n + i] = qi[1 + a];
+  if (tape) {
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + i] = grad[f][t];
+    tape[(int64_t)21 * n + i] = (double)st;
+  }
+}
+
+// First (rows 0..2) and second (rows 3..8: xx, xy, xz, yy, yz, zz) physical
+// derivatives of a chunk of fields.
+template <int NG>
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_derivs_finish(int n, const double4* __restrict__ geo, const double* __restrict__ rows,
+                          const int32_t* __restrict__ status, int nfc, int f0,
+                          double* __restrict__ d1, double* __restrict__ d2) {
+  const int i = blockIdx.x * THREADS + threadIdx.x;
+  if (i >= n) return;
+  const double inv_lam = 1.0 / geo[i].w;
+  const bool ok = status[i] == 0;
+  const double nan = __longlong_as_double(0x7ff8000000000000LL);
+  const double fac[6] = {2.0, 1.0, 1.0, 2.0, 1.0, 2.0};
+  for (int f = 0; f < nfc; ++f) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      d1[((int64_t)(f0 + f) * 3 + t) * n + i] =
+          ok ? rows[((int64_t)f * NG + t) * n + i] * inv_lam : nan;
+    if constexpr (NG == 9) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t)
+        d2[((int64_t)(f0 + f) * 6 + t) * n + i] =
+            ok ? fac[t] * rows[((int64_t)f * NG + 3 + t) * n + i] * inv_lam * inv_lam : nan;
+    }
+  }
+}
+
+// fa[8 i + f] = fields[f0 + f][i] for f < nfc.
+__global__ void __launch_bounds__(THREADS)
+    k_pack_chunk(int n, const double* __restrict__ fields, int f0, int nfc,
+                 double* __restrict__ fa) {
+  const int i = blockIdx.x * THREADS + threadIdx.x;
+  if (i >= n) return;
+  for (int f = 0; f < 8; ++f)
+    fa[8 * (int64_t)i + f] = f < nfc ? fields[(int64_t)(f0 + f) * n + i] : 0.0;
+}
+
+__global__ void k_zero_i32(int32_t* p, int m) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) p[k] = 0;
+}
+
+struct MixedBufs {
+  double* mom;
+  double* b;
+  double* cfit;
+  double* gt;
+  double* rows;
+  int32_t* flag;
+  int32_t* list;
+  int32_t* count;
+};
+
+void plan_mixed(Workspace& ws, int64_t n, int nf, int ng) {
+  const size_t nd = (size_t)n * sizeof(double);
+  ws.plan(NMOM * nd);
+  ws.plan((size_t)nf * NBASIS * nd);
+  ws.plan((size_t)nf * NBASIS * nd);
+  ws.plan((size_t)ng * NBASIS * nd);
+  ws.plan((size_t)nf * ng * nd);
+  ws.plan((size_t)n * sizeof(int32_t));
+  ws.plan((size_t)n * sizeof(int32_t));
+  ws.plan(sizeof(int32_t));
+}
+
+MixedBufs take_mixed(Workspace& ws, int64_t n, int nf, int ng) {
+  MixedBufs m;
+  m.mom = ws.take<double>((size_t)NMOM * n);
+  m.b = ws.take<double>((size_t)nf * NBASIS * n);
+  m.cfit = ws.take<double>((size_t)nf * NBASIS * n);
+  m.gt = ws.take<double>((size_t)ng * NBASIS * n);
+  m.rows = ws.take<double>((size_t)nf * ng * n);
+  m.flag = ws.take<int32_t>(n);
+  m.list = ws.take<int32_t>(n);
+  m.count = ws.take<int32_t>(1);
+  return m;
+}
+
+// Refined coefficient rows 1..NG (unscaled) of nf <= 8 fields stored in the
+// records fa[8 j + fb + f]; m.mom receives the moments (FP32-assembled, FP64
+// for the listed particles).
+template <int NG>
+int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
+              const MixedBufs& m, int32_t* status) {
+  hipStream_t s = ctx->stream;
+  const int n = a.n;
+  const double ncut = pow(10.0, (double)ctx->mixed_cond_exp);
+  const unsigned gq = grid_for((int64_t)n * 4, THREADS);
+  int rc;
+  { Prof pf(ctx, "k_moments<fp32>");
+    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, m.mom, true), "moments")))
+      return rc; }
+  { Prof pf(ctx, "k_mixed_b");
+    hipLaunchKernelGGL(k_mixed_b, dim3(gq), dim3(THREADS), 0, s, n, a.geo, a.off, a.idx, a.box,
+                       a.rf_ratio, a.wkind, fa, fb, nf, m.b);
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed B"))) return rc; }
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
+  { Prof pf(ctx, "k_mixed_factor");
+    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, nf,
+                       m.b, m.cfit, m.gt, status, m.flag, ncut, nullptr, m.list, m.count);
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed factor"))) return rc; }
+  { Prof pf(ctx, "k_mixed_repair");
+    hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS / 4), dim3(THREADS), 0, s, n, a.geo, a.off,
+                       a.idx, a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.list, m.count, m.mom, m.b);
+    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, m.mom,
+                       a.off, nf, m.b, m.cfit, m.gt, status, m.flag, ncut, m.list, nullptr,
+                       m.count);
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed repair"))) return rc; }
+  Prof pf(ctx, "k_mixed_resid");
+  hipLaunchKernelGGL((k_mixed_resid<NG>), dim3(gq), dim3(THREADS), 0, s, n, a.geo, a.off, a.idx,
+                     a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.cfit, m.gt, status, m.flag, m.rows);
+  return hip_check(ctx, hipGetLastError(), "mixed residual");
+}
+
+}  // namespace
+
+size_t mixed_rhs_bytes(int64_t n) {
+  phb_ctx dummy;
+  Workspace ws(&dummy);
+  plan_mixed(ws, n, 7, 3);
+  ws.plan((size_t)n * sizeof(double4));
+  ws.plan((size_t)8 * n * sizeof(double));
+  return ws.total;
+}
+
+int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const double* q, double* rhs,
+              double* dxdt, int32_t* status, double* tape) {
+  const int n = a0.n;
+  Workspace ws(ctx);
+  plan_mixed(ws, n, 7, 3);
+  ws.plan((size_t)n * sizeof(double4));
+  ws.plan((size_t)8 * n * sizeof(double));
+  int rc;
+  if ((rc = ws.commit())) return rc;
+  MixedBufs m = take_mixed(ws, n, 7, 3);
+  double4* geo = ws.take<double4>(n);
+  double* fq = ws.take<double>((size_t)8 * n);
+  if (tape) m.mom = tape + (size_t)TAPE_MOM * n;
+  EvalArgs a = a0;
+  a.geo = geo;
+  a.fq = fq;
+  { Prof pf(ctx, "k_pack");
+    if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
+      return rc; }
+  // V, B and sigma are entries 1..7 of the packed records
+  if ((rc = mixed_fit<3>(ctx, a, fq, 1, 7, m, status))) return rc;
+  Prof pf(ctx, "k_mixed_rhs_finish");
+  hipLaunchKernelGGL(k_mixed_rhs_finish, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, ctx->stream,
+                     n, geo, fq, m.rows, status, gamma, rhs, dxdt, tape);
+  return hip_check(ctx, hipGetLastError(), "mixed rhs");
+}
+
+int mixed_derivs(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields, double* d1,
+                 double* d2, int32_t* status) {
+  const int n = a0.n;
+  const int ng = d2 ? 9 : 3;
+  Workspace ws(ctx);
+  plan_mixed(ws, n, 8, ng);
+  ws.plan((size_t)n * sizeof(double4));
+  ws.plan((size_t)8 * n * sizeof(double));
+  int rc;
+  if ((rc = ws.commit())) return rc;
+  MixedBufs m = take_mixed(ws, n, 8, ng);
+  double4* geo = ws.take<double4>(n);
+  double* fa = ws.take<double>((size_t)8 * n);
+  EvalArgs a = a0;
+  a.geo = geo;
+  if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, nullptr, geo, nullptr),
+                      "pack")))
+    return rc;
+  for (int f0 = 0; f0 < nf; f0 += 8) {
+    const int nfc = nf - f0 < 8 ? nf - f0 : 8;
+    hipLaunchKernelGGL(k_pack_chunk, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, ctx->stream, n,
+                       fields, f0, nfc, fa);
+    if ((rc = hip_check(ctx, hipGetLastError(), "pack fields"))) return rc;
+    // the moments are assembled again per chunk: the list form has replaced
+    // the flagged particles' moments by FP64 ones
+    if (ng == 9) {
+      if ((rc = mixed_fit<9>(ctx, a, fa, 0, nfc, m, status))) return rc;
+      hipLaunchKernelGGL((k_mixed_derivs_finish<9>), dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
+                         ctx->stream, n, geo, m.rows, status, nfc, f0, d1, d2);
+    } else {
+      if ((rc = mixed_fit<3>(ctx, a, fa, 0, nfc, m, status))) return rc;
+      hipLaunchKernelGGL((k_mixed_derivs_finish<3>), dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
+                         ctx->stream, n, geo, m.rows, status, nfc, f0, d1, d2);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed derivatives"))) return rc;
+  }
+  return PHB_OK;
+}
+
+}  // namespace phb

@@ -19,33 +19,14 @@
 // the 84 + 20 x nfields of solving for every field's coefficients.
 #include <type_traits>
 
+#include "chol.hpp"
 #include "internal.hpp"
 #include "mls.hpp"
 
 namespace phb {
-
-template <int B, int E, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (B < E) {
-    f(std::integral_constant<int, B>{});
-    static_for<B + 1, E>(f);
-  }
-}
-
 namespace {
 
 constexpr int THREADS = 256;
-
-struct EntryTable {
-  unsigned char v[NBASIS * NBASIS];
-};
-constexpr EntryTable make_entry_table() {
-  EntryTable t{};
-  for (int r = 0; r < NBASIS; ++r)
-    for (int c = 0; c < NBASIS; ++c) t.v[r * NBASIS + c] = (unsigned char)entry_moment(r, c);
-  return t;
-}
-__constant__ EntryTable c_entry = make_entry_table();
 
 // ---------------------------------------------------------------------------
 // 1. moments
@@ -75,7 +56,10 @@ __device__ __forceinline__ void load_fields(const double* __restrict__ fq, int j
   }
 }
 
-template <int G>
+// T is the accumulation type: double, or float for the mixed form (the
+// displacement, its scaling by 1/lambda and the weight are formed in FP64 and
+// only then rounded to FP32).
+template <int G, class T = double>
 __global__ void __launch_bounds__(THREADS)
     k_moments(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
               const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
@@ -85,9 +69,9 @@ __global__ void __launch_bounds__(THREADS)
   const int l = tid % G;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
-  double m[NMOM];
+  T m[NMOM];
 #pragma unroll
-  for (int k = 0; k < NMOM; ++k) m[k] = 0.0;
+  for (int k = 0; k < NMOM; ++k) m[k] = T(0);
   const double4 gi = geo[ii];
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
@@ -110,152 +94,81 @@ __global__ void __launch_bounds__(THREADS)
     const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
     const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
     const double w = weight_of(qd, wkind);
-    accumulate_moments(m, w, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    accumulate_moments(m, T(w), T(dx * inv_lam), T(dy * inv_lam), T(dz * inv_lam));
   }
 #pragma unroll
   for (int k = 0; k < NMOM; ++k) m[k] = group_sum<G>(m[k]);
   if (valid) {
 #pragma unroll
     for (int k = 0; k < NMOM; ++k)
-      if (k % G == l) mom[(int64_t)k * n + i] = m[k];
+      if (k % G == l) mom[(int64_t)k * n + i] = (double)m[k];
   }
 }
 
 // ---------------------------------------------------------------------------
 // 2. factor: equilibrated FP64 Cholesky, four lanes per particle
 // ---------------------------------------------------------------------------
-__host__ __device__ constexpr int aoff(int rho) { return 2 * rho * (rho + 1); }
+__constant__ EntryTab c_tab = make_entry_tab();
 
-// Writes rows first_target .. first_target+NT-1 of A^{-1} to gop[t][20][n].
+// Writes rows 1 .. NT of A^{-1} (the x, y, z monomials first) to
+// gop[t][20][n], and the status.
 template <int NT>
 __global__ void __launch_bounds__(THREADS)
     k_factor(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
              double* __restrict__ gop, int32_t* __restrict__ status) {
-  constexpr int T0 = 1;  // first target row: the x monomial
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
-
-  double a[60];     // own rows, row rho at a[aoff(rho) .. aoff(rho) + 4 rho + 3]
-  double dg[5];     // own diagonal entries
-  static_for<0, 5>([&](auto R) {
-    constexpr int rho = R;
-    const int r = 4 * rho + l;
-    static_for<0, 4 * rho + 4>([&](auto C) {
-      constexpr int c = C;
-      a[aoff(rho) + c] = mom[(int64_t)c_entry.v[r * NBASIS + c] * n + ii];
-    });
-    dg[rho] = mom[(int64_t)c_entry.v[r * NBASIS + r] * n + ii];
-  });
-
-  // Jacobi equilibration: A_hat = S A S, S = diag(1/sqrt(A_rr)).
-  bool ok = true;
-  double s_own[5];
-  static_for<0, 5>([&](auto R) {
-    constexpr int rho = R;
-    ok = ok && (dg[rho] > 0.0);
-    s_own[rho] = dg[rho] > 0.0 ? 1.0 / sqrt(dg[rho]) : 1.0;
-  });
-  double s_all[NBASIS];
-  static_for<0, NBASIS>([&](auto C) {
-    constexpr int c = C;
-    s_all[c] = quad_bcast<c & 3>(s_own[c >> 2]);
-  });
-  static_for<0, 5>([&](auto R) {
-    constexpr int rho = R;
-    static_for<0, 4 * rho + 4>([&](auto C) {
-      constexpr int c = C;
-      a[aoff(rho) + c] *= s_own[rho] * s_all[c];
-    });
-  });
-
-  // Right-looking Cholesky.  Entries right of a lane's own diagonal hold
-  // scratch values that are never read.
-  double inv_ld[NBASIS];
-  double ldmin = 1e300, ldmax = 0.0;
-  static_for<0, NBASIS>([&](auto K) {
-    constexpr int k = K;
-    constexpr int o = k & 3;
-    constexpr int rk = k >> 2;
-    const double dkk = quad_bcast<o>(a[aoff(rk) + k]);
-    ok = ok && (dkk > 0.0);
-    const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0);
-    ldmin = fmin(ldmin, lkk);
-    ldmax = fmax(ldmax, lkk);
-    const double inv = 1.0 / lkk;
-    inv_ld[k] = inv;
-    static_for<rk, 5>([&](auto R) {
-      constexpr int rho = R;
-      a[aoff(rho) + k] *= inv;
-    });
-    double colk[NBASIS];
-    static_for<k + 1, NBASIS>([&](auto C) {
-      constexpr int c = C;
-      colk[c] = quad_bcast<c & 3>(a[aoff(c >> 2) + k]);
-    });
-    static_for<rk, 5>([&](auto R) {
-      constexpr int rho = R;
-      static_for<k + 1, 4 * rho + 4>([&](auto C) {
-        constexpr int c = C;
-        a[aoff(rho) + c] = fma(-a[aoff(rho) + k], colk[c], a[aoff(rho) + c]);
-      });
-    });
-  });
-  const double rc = ldmin / ldmax;
-  const int nnb = (int)(off[ii + 1] - off[ii]);
-  int st = PHB_STATUS_OK;
-  if (nnb < NBASIS)
-    st = PHB_STATUS_TOO_FEW;
-  else if (!ok || !(rc * rc >= 1e-12))
-    st = PHB_STATUS_SINGULAR;
-
-  // Rows of A_hat^{-1}: forward then backward substitution per unit vector.
-  static_for<0, NT>([&](auto TI) {
-    constexpr int t = T0 + TI;
-    double y[5];
-    static_for<0, 5>([&](auto R) {
-      constexpr int rho = R;
-      y[rho] = (4 * rho + l == t) ? 1.0 : 0.0;
-    });
-    static_for<t, NBASIS>([&](auto K) {
-      constexpr int k = K;
-      constexpr int o = k & 3;
-      constexpr int rk = k >> 2;
-      const double yk = quad_bcast<o>(y[rk]) * inv_ld[k];
-      static_for<rk + 1, 5>([&](auto R) {
-        constexpr int rho = R;
-        y[rho] = fma(-a[aoff(rho) + k], yk, y[rho]);
-      });
-      const double upd = fma(-a[aoff(rk) + k], yk, y[rk]);
-      y[rk] = (l == o) ? yk : ((l > o) ? upd : y[rk]);
-    });
-    double x[5];
-    static_for<0, 5>([&](auto R) { x[R] = y[R]; });
-    static_for<0, NBASIS>([&](auto KK) {
-      constexpr int k = NBASIS - 1 - KK;
-      constexpr int o = k & 3;
-      constexpr int rk = k >> 2;
-      double part = 0.0;
-      static_for<rk + 1, 5>([&](auto R) {
-        constexpr int rho = R;
-        part = fma(a[aoff(rho) + k], x[rho], part);
-      });
-      part += (l > o) ? a[aoff(rk) + k] * x[rk] : 0.0;
-      part = group_sum<4>(part);
-      const double xk = (y[rk] - part) * inv_ld[k];
-      x[rk] = (l == o) ? xk : x[rk];
-    });
+  QuadChol c;
+  quad_chol_factor(c, c_tab, mom, n, ii, l);
+  const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
+  sfor<0, NT>([&](auto TI) {
+    constexpr int t = 1 + TI;
+    double row[5];
+    quad_chol_inverse_row<t>(c, l, row);
     if (valid) {
-      static_for<0, 5>([&](auto R) {
+      sfor<0, 5>([&](auto R) {
         constexpr int rho = R;
-        const int r = 4 * rho + l;
-        gop[((int64_t)TI * NBASIS + r) * n + i] = s_all[t] * x[rho] * s_own[rho];
+        gop[((int64_t)TI * NBASIS + 4 * rho + l) * n + i] = row[rho];
       });
     }
   });
   if (valid && l == 0) status[i] = st;
+}
+
+// X_r = A^{-1} R_r for NR general right-hand sides R (SoA [NR][20][n]);
+// status as in k_factor.  NaN-free: a failed factorization writes zeros.
+template <int NR>
+__global__ void __launch_bounds__(THREADS)
+    k_factor_solve(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
+                   const double* __restrict__ rhs, double* __restrict__ x,
+                   int32_t* __restrict__ status) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid >> 2;
+  const int l = tid & 3;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  QuadChol c;
+  quad_chol_factor(c, c_tab, mom, n, ii, l);
+  const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
+  sfor<0, NR>([&](auto RI) {
+    constexpr int r = RI;
+    double b[5], out[5];
+    sfor<0, 5>([&](auto R) {
+      constexpr int rho = R;
+      b[rho] = rhs[((int64_t)r * NBASIS + 4 * rho + l) * n + ii];
+    });
+    quad_chol_apply_inverse(c, l, b, out);
+    if (valid) {
+      sfor<0, 5>([&](auto R) {
+        constexpr int rho = R;
+        x[((int64_t)r * NBASIS + 4 * rho + l) * n + i] = st == 0 ? out[rho] : 0.0;
+      });
+    }
+  });
+  if (status && valid && l == 0) status[i] = st;
 }
 
 // ---------------------------------------------------------------------------
@@ -438,21 +351,44 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
-template <int G>
+template <int G, class T>
 hipError_t launch_moments_g(hipStream_t s, const EvalArgs& a, double* mom) {
-  hipLaunchKernelGGL((k_moments<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0, s,
-                     a.n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind, mom);
+  hipLaunchKernelGGL((k_moments<G, T>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0,
+                     s, a.n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind, mom);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom) {
-  switch (lanes) {
-    case 1: return launch_moments_g<1>(s, a, mom);
-    case 2: return launch_moments_g<2>(s, a, mom);
-    default: return launch_moments_g<4>(s, a, mom);
+hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom, bool fp32) {
+  if (fp32) {
+    switch (lanes) {
+      case 1: return launch_moments_g<1, float>(s, a, mom);
+      case 2: return launch_moments_g<2, float>(s, a, mom);
+      default: return launch_moments_g<4, float>(s, a, mom);
+    }
   }
+  switch (lanes) {
+    case 1: return launch_moments_g<1, double>(s, a, mom);
+    case 2: return launch_moments_g<2, double>(s, a, mom);
+    default: return launch_moments_g<4, double>(s, a, mom);
+  }
+}
+
+hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
+                               const double* mom, const double* rhs, double* x, int32_t* status) {
+  const unsigned grid = grid_for((int64_t)n * 4, THREADS);
+  switch (nr) {
+    case 1: hipLaunchKernelGGL((k_factor_solve<1>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    case 2: hipLaunchKernelGGL((k_factor_solve<2>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    case 3: hipLaunchKernelGGL((k_factor_solve<3>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    case 4: hipLaunchKernelGGL((k_factor_solve<4>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    case 5: hipLaunchKernelGGL((k_factor_solve<5>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    case 6: hipLaunchKernelGGL((k_factor_solve<6>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    case 7: hipLaunchKernelGGL((k_factor_solve<7>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    default: hipLaunchKernelGGL((k_factor_solve<8>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,

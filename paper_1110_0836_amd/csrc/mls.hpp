@@ -34,9 +34,14 @@ constexpr int TAPE_DOUBLES = 22 + NMOM;
 // geo (and fq when q != null) from the SoA inputs.
 hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* lam,
                        const double* q, double4* geo, double* fq);
-hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom);
+// fp32: accumulate in FP32 (the mixed form); the moments are stored in FP64.
+hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom,
+                          bool fp32 = false);
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,
                          double* gop, int32_t* status);
+// X = A^{-1} R for nr (1..8) right-hand sides given as SoA [nr][20][n].
+hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
+                               const double* mom, const double* rhs, double* x, int32_t* status);
 hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,
                                const int32_t* status, int nf, const double* fields, double* d1,
                                double* d2);

@@ -1,0 +1,171 @@
+"""Mixed-precision form (FP32 assembly and application of displacement- and
+field-differences formed in FP64, FP64 factor and solves, one data-level
+refinement step) against the FP64 oracle: max relative error per field and
+derivative order at most 1e-5, for derivatives, time derivatives and the
+reverse mode."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1110_0836_amd import synth
+from _common import dev, setup_of, rel_err, interior
+from test_gpu_mls import check_rhs, rhs_both
+from test_gpu_adjoint import grad_err, random_set
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_1110_0836_amd")
+
+TOLMIX = 1e-5
+
+
+def mixed_derivs(c, fields=None, second=True):
+    fields = c["q"] if fields is None else fields
+    s = setup_of(c, precision=P.PHB_MIXED)
+    pos, lam = dev(c["pos"]), dev(c["lam"])
+    off, idx = P.neighbors(pos, lam, s)
+    d1, d2, st = P.mls_derivs(pos, lam, off, idx, dev(fields), s, second=second)
+    ooff, oidx = oracle.neighbors(c["pos"], c["lam"], L=c["L"], periodic=c["periodic"])
+    o1, o2, ost = oracle.mls_derivs(c["pos"], c["lam"], ooff, oidx, fields, L=c["L"],
+                                    periodic=c["periodic"])
+    return (d1.cpu().numpy(), None if d2 is None else d2.cpu().numpy(), st.cpu().numpy()), \
+        (o1, o2, ost)
+
+
+def per_order(g1, g2, o1, o2, sel):
+    e1 = rel_err(g1[:, :, sel], o1[:, :, sel], axis=(1, 2))
+    e2 = rel_err(g2[:, :, sel], o2[:, :, sel], axis=(1, 2))
+    print("mixed first-order max rel err per field", e1)
+    print("mixed second-order max rel err per field", e2)
+    return e1.max(), e2.max()
+
+
+def test_config1_derivatives_periodic():
+    c = synth.config1()
+    (g1, g2, gs), (o1, o2, os_) = mixed_derivs(c)
+    assert np.array_equal(gs, os_)
+    e1, e2 = per_order(g1, g2, o1, o2, gs == 0)
+    assert e1 < TOLMIX and e2 < TOLMIX
+
+
+def test_config1_derivatives_open_box():
+    c = synth.config1(pin=True)
+    (g1, g2, gs), (o1, o2, os_) = mixed_derivs(c)
+    assert np.array_equal(gs, os_)
+    ok = gs == 0
+    inner = ok & interior(c["pos"], c["lam"], c["L"], c["periodic"])
+    e1, e2 = per_order(g1, g2, o1, o2, inner)
+    assert e1 < TOLMIX and e2 < TOLMIX
+    # particles cut by a face: FP32 moments of a lopsided sample
+    e1, e2 = per_order(g1, g2, o1, o2, ok)
+    assert e1 < 1e-3 and e2 < 1e-3
+    assert np.all(np.isnan(g1[:, :, ~ok])) and np.all(np.isnan(g2[:, :, ~ok]))
+
+
+def test_constant_field_and_large_offset():
+    # the data-level centring: a field 1e6 + small signal keeps its
+    # derivatives to the FP32 bound of the signal, not of the offset
+    c = synth.config1()
+    rng = np.random.default_rng(9)
+    x = c["pos"]
+    f = np.stack([np.full(x.shape[1], 3.0), 1e6 + 1e-3 * np.sin(2 * np.pi * x[0]),
+                  x[0] - 0.5 + 0.0 * rng.uniform(size=x.shape[1])])
+    (g1, g2, gs), (o1, o2, os_) = mixed_derivs(c, f)
+    ok = gs == 0
+    assert np.all(g1[0][:, ok] == 0.0) and np.all(g2[0][:, ok] == 0.0)
+    inner = ok & interior(c["pos"], c["lam"], c["L"], (0, 0, 0))
+    e1 = rel_err(g1[1][:, inner], o1[1][:, inner])
+    print("offset field first-order rel err", e1)
+    assert e1 < TOLMIX
+
+
+def test_many_fields_two_chunks_first_order_only():
+    c = synth.random_cloud(3001, seed=5, lam_range=(0.06, 0.1))
+    rng = np.random.default_rng(6)
+    fields = np.concatenate([c["q"], rng.normal(size=(3, 3001))])
+    (g1, g2, gs), (o1, o2, os_) = mixed_derivs(c, fields, second=False)
+    assert g2 is None
+    assert np.array_equal(gs, os_)
+    ok = gs == 0
+    e1 = rel_err(g1[:, :, ok], o1[:, :, ok], axis=(1, 2))
+    print("mixed first-order max rel err per field", e1)
+    assert e1.max() < TOLMIX
+
+
+def test_status_paths():
+    rng = np.random.default_rng(8)
+    n = 1500
+    pos = np.stack([rng.uniform(0, 1, n), rng.uniform(0, 1, n), np.full(n, 0.5)])
+    lam = np.full(n, 0.04)
+    lam[:10] = 0.004
+    c = dict(pos=pos, lam=lam, q=np.ones((8, n)), L=(1, 1, 1), periodic=(1, 1, 1))
+    (g1, g2, gs), (o1, o2, os_) = mixed_derivs(c)
+    assert np.array_equal(gs, os_)
+    assert np.all(np.isnan(g1)) and np.all(np.isnan(g2))
+
+
+@pytest.mark.parametrize("side", [16, 24])
+def test_rhs_fast_wave(side):
+    check_rhs(*rhs_both(synth.config2(side=side), precision=P.PHB_MIXED), TOLMIX)
+
+
+def test_rhs_cp_alfven():
+    check_rhs(*rhs_both(synth.cp_alfven(16), precision=P.PHB_MIXED), TOLMIX)
+
+
+def test_rhs_shear_layer_full_size_sampled():
+    c = synth.config3()
+    rows = np.random.default_rng(4).choice(c["lam"].shape[0], 300, replace=False)
+    check_rhs(*rhs_both(c, rows=rows, precision=P.PHB_MIXED), TOLMIX)
+
+
+def test_rhs_matches_fp64_path():
+    c = synth.config2(side=24)
+    pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
+    s64 = setup_of(c)
+    smx = setup_of(c, precision=P.PHB_MIXED)
+    off, idx = P.neighbors(pos, lam, s64)
+    r64, x64, st64 = P.mhd_rhs(pos, lam, off, idx, q, s64)
+    rmx, xmx, stmx = P.mhd_rhs(pos, lam, off, idx, q, smx)
+    assert np.array_equal(st64.cpu().numpy(), stmx.cpu().numpy())
+    assert np.array_equal(x64.cpu().numpy(), xmx.cpu().numpy())
+    for grp in ([1, 2, 3], [4, 5, 6]):
+        e = rel_err(rmx[grp].cpu().numpy(), r64[grp].cpu().numpy())
+        assert e < TOLMIX
+
+
+@pytest.mark.parametrize("use_tape", [True, False])
+def test_adjoint_matches_oracle(use_tape):
+    c, gbar, xbar = random_set()
+    s = setup_of(c, precision=P.PHB_MIXED)
+    pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
+    off, idx = P.neighbors(pos, lam, s)
+    tr = P.transpose(off, idx)
+    tape = P.mhd_rhs(pos, lam, off, idx, q, s, tape=True)[3] if use_tape else None
+    qb, pb = P.mhd_rhs_adjoint(pos, lam, off, idx, tr, q, dev(gbar), dev(xbar), setup=s,
+                               tape=tape)
+    qb, pb = qb.cpu().numpy(), pb.cpu().numpy()
+    ooff, oidx = oracle.neighbors(c["pos"], c["lam"])
+    oq, op, ost = oracle.mhd_rhs_adjoint(c["pos"], c["lam"], ooff, oidx, c["q"], gbar, xbar)
+    eq = [grad_err(qb[f], oq[f]) for f in range(8)]
+    ep = grad_err(pb, op)
+    print("mixed q_bar rel err per field", eq, "pos_bar rel err", ep)
+    assert max(eq) < TOLMIX and ep < TOLMIX
+
+
+def test_autograd_mixed_matches_fp64():
+    import torch
+    c, gbar, _ = random_set(side=10, seed=7)
+    w = torch.tensor(np.random.default_rng(3).uniform(size=c["lam"].shape[0])).cuda()
+    out = []
+    for prec in (P.PHB_FP64, P.PHB_MIXED):
+        s = setup_of(c, precision=prec)
+        pos = dev(c["pos"]).requires_grad_(True)
+        q = dev(c["q"]).requires_grad_(True)
+        lam = dev(c["lam"])
+        off, idx = P.neighbors(pos.detach(), lam, s)
+        rhs, _, _ = P.MHDRHS.apply(q, pos, lam, off, idx, P.transpose(off, idx), s)
+        loss = (w * (rhs[1:4] ** 2).sum(0)).sum()
+        gq, gp = torch.autograd.grad(loss, (q, pos))
+        out.append((gq.cpu().numpy(), gp.cpu().numpy()))
+    assert grad_err(out[1][0], out[0][0]) < TOLMIX
+    assert grad_err(out[1][1], out[0][1]) < TOLMIX
