@@ -64,7 +64,10 @@ extern "C" {
 
 #define PHB_FP64 0        /* all arithmetic in FP64 */
 #define PHB_MIXED 1       /* FP32 assembly and application, FP64 factor and solve,
-                             one data-level refinement step */
+                             one data-level refinement step; particles whose
+                             FP32 moment matrix is too ill-conditioned for one
+                             step are evaluated in FP64 (see mixed_cond_exp);
+                             the reverse mode assembles its moments in FP64 */
 #define PHB_W_POLY3 0     /* w = (1 - d^2/r_f^2)^3 */
 #define PHB_W_UNIT 1      /* w = 1 */
 #define PHB_FIT_FULL20 0  /* all 20 monomials, constant included */
@@ -182,6 +185,66 @@ int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, double*
                 const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
                 int64_t* nnz_out, int32_t* status);
 
+/* ---- many particle sets in one captured graph -----------------------------
+ * Independent particle sets (each with its own neighbor lists; no set sees
+ * another) are stored one after the other: set s owns the particles
+ * set_offsets[s] .. set_offsets[s+1]-1 of every SoA array, and the CSR lists
+ * hold global indices.  Every stage of an evaluation runs as one launch over
+ * all sets, and the whole forward (+ reverse) pass is captured once into a
+ * HIP graph and replayed with one graph launch.  All sets share phb_params
+ * (box, physics, precision).  A batch holds a private stream on which it
+ * captures and replays; phb_batch_launch orders the replay after the
+ * context stream's earlier work and makes the context stream wait for it.
+ *
+ * phb_batch_create: n_sets > 0 sets; set_offsets (host) int64[n_sets+1],
+ * starting at 0, strictly increasing, total < 2^31.  *out receives the batch.
+ * phb_batch_destroy: waits for the batch stream and frees the batch. */
+typedef struct phb_batch phb_batch;
+int phb_batch_create(phb_ctx* ctx, const phb_params* p, int32_t n_sets,
+                     const int64_t* set_offsets, phb_batch** out);
+int phb_batch_destroy(phb_batch* b);
+/* Neighbor lists of every set (each built as by phb_neighbors_build on that
+ * set alone, indices shifted to global), into offsets int64[n_total+1] and
+ * idx int32[idx_capacity].  *nnz_out (host): total entries; PHB_ECAPACITY
+ * when idx is too small (the batch is then unusable until a call succeeds).
+ * Drops a previously captured graph.  Synchronizes. */
+int phb_batch_neighbors(phb_ctx* ctx, phb_batch* b, const double* pos, const double* lambda,
+                        int64_t* offsets, int32_t* idx, int64_t idx_capacity, int64_t* nnz_out);
+/* The buffers of one pass, all over n_total particles, as for phb_mhd_rhs and
+ * phb_mhd_rhs_adjoint.  q_bar and pos_bar both NULL: forward only (then
+ * rhs_bar, dxdt_bar and the transposed lists may be NULL).  tape may be NULL
+ * (the reverse pass then recomputes it). */
+typedef struct {
+  const double* pos;
+  const double* lambda;
+  const int64_t* offsets;
+  const int32_t* idx;
+  const int64_t* t_offsets;
+  const int32_t* t_src;
+  const int32_t* t_pos;
+  const double* q;
+  double* rhs;
+  double* dxdt;
+  int32_t* status;
+  void* tape;
+  const double* rhs_bar;
+  const double* dxdt_bar;
+  double* q_bar;
+  double* pos_bar;
+} phb_batch_io;
+/* One eager pass on the context stream (the reference for a replay). */
+int phb_batch_run(phb_ctx* ctx, phb_batch* b, const phb_batch_io* io);
+/* Run one eager pass (sizing the workspace, synchronizing), then capture the
+ * same pass into the batch's graph, bound to these buffers: the caller keeps
+ * them alive and in place for as long as it launches the graph.  The graph
+ * runs in a workspace of its own (as large as the context's), held by the
+ * batch until the next capture, neighbor build or destroy.  The schedule knobs
+ * current at capture are baked in.  PHB_ESTATE before the neighbor lists are
+ * built. */
+int phb_batch_capture(phb_ctx* ctx, phb_batch* b, const phb_batch_io* io);
+/* Replay the captured pass (asynchronous).  PHB_ESTATE if none is captured. */
+int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
+
 /* ---- schedule knobs (set by the autotuner; every value gives the same
  * results to rounding) ------------------------------------------------------
  * Keys: "cells_per_rf" (1..4: neighbor-grid cells per minimum r_f),
@@ -198,6 +261,19 @@ int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, double*
  * tolerance, the others only by rounding).  EINVAL for an unknown key or value. */
 int phb_tune_set(phb_ctx* ctx, const char* key, int value);
 int phb_tune_get(phb_ctx* ctx, const char* key, int* value);
+/* Autotuner: times one forward + reverse pass of the given set (or batch
+ * concatenation) for each value of each of lanes_moments, lanes_apply,
+ * lanes_adj_y, lanes_gather, adj_pairs_mode and record_order in turn
+ * (coordinate descent from the current values; median of reps timed passes
+ * after one warm-up; a value must win by 2% to replace the current one) and
+ * leaves the winners set on ctx.  nnz (host) = offsets[n].  cache_path: NULL,
+ * or a text file that, when it exists and was written for the same n, nnz,
+ * precision and weight, supplies the values without timing, and otherwise
+ * receives them.  Allocates its scratch buffers; synchronizes. */
+int phb_tune(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+             const double* lambda, const int64_t* offsets, const int32_t* idx,
+             const int64_t* t_offsets, const int32_t* t_src, const int32_t* t_pos, int64_t nnz,
+             const double* q, int32_t reps, const char* cache_path);
 
 /* ---- instrumentation -----------------------------------------------------
  * phb_profile: enable (1) or disable (0) per-kernel timing on ctx; clears the

@@ -37,6 +37,8 @@ EXPORTS = [
     "phb_last_error", "phb_neighbors_build", "phb_neighbors_transpose", "phb_spatial_order",
     "phb_permute", "phb_mls_derivs", "phb_mhd_rhs", "phb_tape_bytes", "phb_mhd_rhs_adjoint",
     "phb_pc_step", "phb_profile", "phb_profile_read", "phb_tune_set", "phb_tune_get",
+    "phb_tune", "phb_batch_create", "phb_batch_destroy", "phb_batch_neighbors", "phb_batch_run",
+    "phb_batch_capture", "phb_batch_launch",
 ]
 
 
@@ -51,6 +53,13 @@ class Params(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("rf_ratio", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("weight", ctypes.c_int32),
                 ("fit", ctypes.c_int32)]
+
+
+class BatchIO(ctypes.Structure):
+    """phb_batch_io: the buffers of one batched pass."""
+    _fields_ = [(name, ctypes.c_void_p) for name in (
+        "pos", "lambda_", "offsets", "idx", "t_offsets", "t_src", "t_pos", "q", "rhs", "dxdt",
+        "status", "tape", "rhs_bar", "dxdt_bar", "q_bar", "pos_bar")]
 
 
 @dataclass
@@ -113,6 +122,13 @@ def lib():
             "phb_tune_set": (I, [P, ctypes.c_char_p, I]),
             "phb_tune_get": (I, [P, ctypes.c_char_p, ctypes.POINTER(I)]),
             "phb_profile_read": (I, [P, I32, P, P, P, ctypes.POINTER(I32)]),
+            "phb_tune": (I, [P, PP, I64, P, P, P, P, P, P, P, I64, P, I32, ctypes.c_char_p]),
+            "phb_batch_create": (I, [P, PP, I32, ctypes.POINTER(I64), ctypes.POINTER(P)]),
+            "phb_batch_destroy": (I, [P]),
+            "phb_batch_neighbors": (I, [P, P, P, P, P, P, I64, ctypes.POINTER(I64)]),
+            "phb_batch_run": (I, [P, P, ctypes.POINTER(BatchIO)]),
+            "phb_batch_capture": (I, [P, P, ctypes.POINTER(BatchIO)]),
+            "phb_batch_launch": (I, [P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -258,6 +274,17 @@ def phb_tune_get(key, device=None):
     return v.value
 
 
+def phb_tune(setup, pos, lam, offsets, idx, t_offsets, t_src, t_pos, q, reps=3, cache=None):
+    """Autotune the schedule knobs on this set; returns {key: chosen value}."""
+    ctx = context(pos.device.index)
+    p = setup.params()
+    _check(ctx, lib().phb_tune(ctx, ctypes.byref(p), lam.shape[0], _f64(pos), _f64(lam),
+                               _ptr(offsets), _ptr(idx), _ptr(t_offsets), _ptr(t_src),
+                               _ptr(t_pos), idx.shape[0], _f64(q), int(reps),
+                               None if cache is None else os.fsencode(cache)))
+    return {k: phb_tune_get(k, pos.device.index) for k in TUNE_KEYS}
+
+
 def phb_profile(enable, device=None):
     ctx = context(device)
     _check(ctx, lib().phb_profile(ctx, 1 if enable else 0))
@@ -389,3 +416,89 @@ class MHDRHS(torch.autograd.Function):
         q_bar, pos_bar = mhd_rhs_adjoint(pos, lam, offsets, idx, (t_off, t_src, t_pos), q,
                                          g_rhs, g_dxdt, setup=ctx.setup, tape=tp)
         return q_bar, pos_bar, None, None, None, None, None
+
+
+class Batch:
+    """Independent particle sets evaluated as one concatenation and replayed
+    from one captured HIP graph (phb_batch_*).
+
+    sizes: particle count of each set; the sets are stored one after the
+    other in every SoA array.  All sets share `setup`."""
+
+    def __init__(self, sizes, setup=None, device=None):
+        self.setup = setup or Setup()
+        self.sizes = [int(v) for v in sizes]
+        off = [0]
+        for v in self.sizes:
+            off.append(off[-1] + v)
+        self.set_offsets = off
+        self.n = off[-1]
+        self._dev = torch.cuda.current_device() if device is None else int(device)
+        ctx = context(self._dev)
+        arr = (ctypes.c_int64 * len(off))(*off)
+        self._p = self.setup.params()
+        self._h = ctypes.c_void_p()
+        _check(ctx, lib().phb_batch_create(ctx, ctypes.byref(self._p), len(self.sizes), arr,
+                                           ctypes.byref(self._h)))
+        self._bound = None
+        self.nnz = None
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize(self._dev)
+            lib().phb_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._bound = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def neighbors(self, pos, lam, capacity=None):
+        """Global CSR lists of all sets: (offsets int64[n+1], idx int32[nnz])."""
+        ctx = context(self._dev)
+        offsets = torch.empty(self.n + 1, dtype=torch.int64, device=pos.device)
+        cap = capacity if capacity is not None else 64 * self.n
+        for _ in range(2):
+            idx = torch.empty(max(cap, 1), dtype=torch.int32, device=pos.device)
+            nnz = ctypes.c_int64(0)
+            rc = lib().phb_batch_neighbors(ctx, self._h, _f64(pos), _f64(lam), _ptr(offsets),
+                                           _ptr(idx), cap, ctypes.byref(nnz))
+            if rc != PHB_ECAPACITY:
+                break
+            cap = nnz.value
+        _check(ctx, rc)
+        self.nnz = nnz.value
+        return offsets, idx[:nnz.value]
+
+    def _io(self, pos, lam, offsets, idx, q, rhs, dxdt, status, tape=None, trans=None,
+            rhs_bar=None, dxdt_bar=None, q_bar=None, pos_bar=None):
+        t_off, t_src, t_pos = trans if trans is not None else (None, None, None)
+        tensors = dict(pos=pos, lambda_=lam, offsets=offsets, idx=idx, t_offsets=t_off,
+                       t_src=t_src, t_pos=t_pos, q=q, rhs=rhs, dxdt=dxdt, status=status,
+                       tape=tape, rhs_bar=rhs_bar, dxdt_bar=dxdt_bar, q_bar=q_bar,
+                       pos_bar=pos_bar)
+        io = BatchIO(**{k: (None if v is None else _ptr(v).value) for k, v in tensors.items()})
+        return io, tensors
+
+    def run(self, *args, **kw):
+        """One eager pass (arguments as for capture)."""
+        io, _ = self._io(*args, **kw)
+        _check(context(self._dev), lib().phb_batch_run(context(self._dev), self._h,
+                                                       ctypes.byref(io)))
+
+    def capture(self, *args, **kw):
+        """Capture one pass over these tensors (pos, lam, offsets, idx, q, rhs,
+        dxdt, status, tape=, trans=, rhs_bar=, dxdt_bar=, q_bar=, pos_bar=); the
+        batch keeps references so that they stay alive while it may replay."""
+        io, tensors = self._io(*args, **kw)
+        ctx = context(self._dev)
+        _check(ctx, lib().phb_batch_capture(ctx, self._h, ctypes.byref(io)))
+        self._bound = tensors
+
+    def launch(self):
+        """Replay the captured pass on torch's current stream order."""
+        ctx = context(self._dev)
+        _check(ctx, lib().phb_batch_launch(ctx, self._h))

@@ -568,13 +568,14 @@ hipError_t launch_adj_y_g(hipStream_t s, const EvalArgs& a, double gamma, const 
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
-                const double* tape_in) {
+                const double* tape_in, int64_t nnz_known) {
   (void)t_src;
   const int n = a.n;
-  // nnz is needed to size the pair records: read offsets[n] back.
+  // nnz sizes the pair records: unless the caller knows it, read offsets[n]
+  // back (a synchronization, so captured callers pass it).
   int rc;
-  int64_t nnz = 0;
-  {
+  int64_t nnz = nnz_known;
+  if (nnz < 0) {
     int64_t* h = nullptr;
     if (hipHostMalloc((void**)&h, sizeof(int64_t)) != hipSuccess)
       return set_error(ctx, PHB_EHIP, "pinned allocation");

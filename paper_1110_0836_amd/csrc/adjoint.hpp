@@ -10,7 +10,13 @@ namespace phb {
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
-                const double* tape);
+                const double* tape, int64_t nnz_known);
+
+// Time derivatives in the requested precision (FP64 or mixed).
+int eval_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const double* q, double* rhs,
+             double* dxdt, int32_t* status, double* tape);
+int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+              const double* lambda, const int64_t* offsets, const int32_t* idx, EvalArgs* a);
 
 size_t mixed_rhs_bytes(int64_t n);
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a, double gamma, const double* q, double* rhs,

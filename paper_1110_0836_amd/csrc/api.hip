@@ -27,6 +27,8 @@ int Workspace::commit() {
   if (need <= ctx->arena_cap) return PHB_OK;
   if (ctx->arena_base != 0)
     return set_error(ctx, PHB_ESTATE, "nested workspace exceeds the reserved arena");
+  if (ctx->capturing)
+    return set_error(ctx, PHB_ESTATE, "a captured call would grow the workspace");
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_check(ctx, e, "workspace sync");
   if (ctx->arena) hipFree(ctx->arena);
@@ -64,7 +66,7 @@ static int ensure_host(phb_ctx* ctx, size_t bytes) {
   return PHB_OK;
 }
 
-static int check_params(phb_ctx* ctx, const phb_params* p) {
+int check_params(phb_ctx* ctx, const phb_params* p) {
   if (!p) return set_error(ctx, PHB_EINVAL, "params is NULL");
   for (int a = 0; a < 3; ++a)
     if (!(p->L[a] > 0.0) || !isfinite(p->L[a]))
@@ -79,7 +81,7 @@ static int check_params(phb_ctx* ctx, const phb_params* p) {
   return PHB_OK;
 }
 
-static int check_n(phb_ctx* ctx, int64_t n) {
+int check_n(phb_ctx* ctx, int64_t n) {
   if (n <= 0 || n >= (int64_t(1) << 31) - 1)
     return set_error(ctx, PHB_EINVAL, "n must be in [1, 2^31 - 2]");
   return PHB_OK;
@@ -184,6 +186,56 @@ static void plan_rhs(Workspace& ws, int64_t n, int precision) {
   ws.plan((size_t)3 * NBASIS * n * sizeof(double));
   ws.plan((size_t)n * sizeof(double4));
   ws.plan((size_t)n * 8 * sizeof(double));
+}
+
+// The time derivatives in the form p->precision asks for (FP64 here).
+int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double* q, double* rhs,
+             double* dxdt, int32_t* status, double* tape) {
+  if (p->precision == PHB_MIXED) return mixed_rhs(ctx, a0, p->gamma, q, rhs, dxdt, status, tape);
+  EvalArgs a = a0;
+  const int n = a.n;
+  int rc;
+  Workspace ws(ctx);
+  plan_rhs(ws, n, PHB_FP64);
+  if ((rc = ws.commit())) return rc;
+  double* mom = ws.take<double>((size_t)NMOM * n);
+  double* gop = ws.take<double>((size_t)3 * NBASIS * n);
+  double4* geo = ws.take<double4>(n);
+  double* fq = ws.take<double>((size_t)8 * n);
+  // with a tape, the moments go straight into it for the reverse mode
+  if (tape) mom = tape + (size_t)TAPE_MOM * n;
+  a.geo = geo;
+  a.fq = fq;
+  { Prof pf(ctx, "k_pack");
+  if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
+    return rc; }
+  { Prof pf(ctx, "k_moments");
+  if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
+    return rc; }
+  { Prof pf(ctx, "k_factor<3>");
+  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, 3, mom, gop, status), "factor")))
+    return rc; }
+  Prof pf(ctx, "k_apply_rhs");
+  return hip_check(ctx,
+                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, gop, status, q,
+                                    rhs, dxdt, tape),
+                   "apply rhs");
+}
+
+int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+              const double* lambda, const int64_t* offsets, const int32_t* idx, EvalArgs* a) {
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!pos || !lambda || !offsets || !idx) return set_error(ctx, PHB_EINVAL, "null pointer");
+  a->n = (int)n64;
+  a->pos = pos;
+  a->lam = lambda;
+  a->off = offsets;
+  a->idx = idx;
+  a->box = make_box(p);
+  a->rf_ratio = p->rf_ratio;
+  a->wkind = p->weight;
+  return PHB_OK;
 }
 
 }  // namespace phb
@@ -460,22 +512,6 @@ int phb_permute(phb_ctx* ctx, int64_t n64, const int32_t* perm, int32_t ncomp, c
   return hip_check(ctx, launch_permute(ctx->stream, (int)n64, ncomp, perm, src, dst), "permute");
 }
 
-static int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
-                     const double* lambda, const int64_t* offsets, const int32_t* idx,
-                     EvalArgs* a) {
-  int rc;
-  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
-  if (!pos || !lambda || !offsets || !idx) return set_error(ctx, PHB_EINVAL, "null pointer");
-  a->n = (int)n64;
-  a->pos = pos;
-  a->lam = lambda;
-  a->off = offsets;
-  a->idx = idx;
-  a->box = make_box(p);
-  a->rf_ratio = p->rf_ratio;
-  a->wkind = p->weight;
-  return PHB_OK;
-}
 
 int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
                    const double* lambda, const int64_t* offsets, const int32_t* idx, int32_t nf,
@@ -526,34 +562,7 @@ int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* po
   if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
   if (!q || !rhs || !dxdt || !status) return set_error(ctx, PHB_EINVAL, "null pointer");
   hipSetDevice(ctx->device);
-  if (p->precision == PHB_MIXED)
-    return mixed_rhs(ctx, a, p->gamma, q, rhs, dxdt, status, reinterpret_cast<double*>(tape));
-  const int n = a.n;
-  Workspace ws(ctx);
-  plan_rhs(ws, n, PHB_FP64);
-  if ((rc = ws.commit())) return rc;
-  double* mom = ws.take<double>((size_t)NMOM * n);
-  double* gop = ws.take<double>((size_t)3 * NBASIS * n);
-  double4* geo = ws.take<double4>(n);
-  double* fq = ws.take<double>((size_t)8 * n);
-  // with a tape, the moments go straight into it for the reverse mode
-  if (tape) mom = reinterpret_cast<double*>(tape) + (size_t)TAPE_MOM * n;
-  a.geo = geo;
-  a.fq = fq;
-  { Prof pf(ctx, "k_pack");
-  if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, pos, lambda, q, geo, fq), "pack")))
-    return rc; }
-  { Prof pf(ctx, "k_moments");
-  if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
-    return rc; }
-  { Prof pf(ctx, "k_factor<3>");
-  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, 3, mom, gop, status), "factor")))
-    return rc; }
-  Prof pf(ctx, "k_apply_rhs");
-  return hip_check(ctx,
-                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, gop, status, q,
-                                    rhs, dxdt, reinterpret_cast<double*>(tape)),
-                   "apply rhs");
+  return eval_rhs(ctx, a, p, q, rhs, dxdt, status, reinterpret_cast<double*>(tape));
 }
 
 int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
@@ -569,7 +578,7 @@ int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n64, const do
     return set_error(ctx, PHB_EINVAL, "null pointer");
   hipSetDevice(ctx->device);
   return adjoint_rhs(ctx, a, p, t_offsets, t_src, t_pos, q, rhs_bar, dxdt_bar, q_bar, pos_bar,
-                     reinterpret_cast<const double*>(tape));
+                     reinterpret_cast<const double*>(tape), -1);
 }
 
 int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt, double* pos, double* q,

@@ -32,6 +32,7 @@ struct phb_ctx {
   int adj_pairs_mode = 1;  // 0: one lane per entry, 1: one wavefront per owner
   int record_order = 0;    // pair records at 0: transposed positions, 1: forward slots
   // Per-kernel timing (phb_profile): event pairs awaiting read-out and totals.
+  bool capturing = false;  // a graph capture is recording the context stream
   bool prof_on = false;
   struct ProfRec {
     const char* name;
@@ -44,6 +45,8 @@ struct phb_ctx {
 namespace phb {
 
 int set_error(phb_ctx* ctx, int code, const std::string& msg);
+int check_params(phb_ctx* ctx, const phb_params* p);
+int check_n(phb_ctx* ctx, int64_t n);
 int hip_check(phb_ctx* ctx, hipError_t e, const char* what);
 
 // Carves 256-byte aligned pieces out of the context arena.  Sizes are summed

@@ -50,3 +50,15 @@ def test_params_layout_matches_header():
     # double L[3]; int32 periodic[3]; (pad) double gamma; double rf_ratio; int32 x3
     assert ctypes.sizeof(P.Params) == 24 + 12 + 4 + 8 + 8 + 12 + 4
     assert P.Params.gamma.offset == 40
+
+
+def test_batch_io_layout_and_null_batch():
+    import paper_1110_0836_amd as P
+    # sixteen pointers in the order of the header's phb_batch_io
+    assert ctypes.sizeof(P.BatchIO) == 16 * 8
+    assert [f[0] for f in P.BatchIO._fields_][:4] == ["pos", "lambda_", "offsets", "idx"]
+    assert P.BatchIO.pos_bar.offset == 15 * 8
+    lib = P.lib()
+    assert lib.phb_batch_destroy(None) == P.PHB_EINVAL
+    assert lib.phb_batch_launch(None, None) == P.PHB_EINVAL
+    assert lib.phb_batch_create(None, None, 1, None, None) == P.PHB_EINVAL
