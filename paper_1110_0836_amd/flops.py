@@ -27,10 +27,27 @@ k_adj_pairs      per pair: geometry and dw/dq (18), basis (16),
                  basis gradient (25), xibar over the 30 nonzero basis
                  derivatives (30 FMA), dbar (12), sums (10)               = 683
 k_adj_gather     memory bound: 80 B per pair record, 232 B per particle.
+
+Mixed form (FP32 arithmetic after the FP64 displacement, FP64 factor and
+solves; counted the same way, whatever the precision):
+k_moments<fp32>  as k_moments                                            = 187
+k_mixed_b        per pair: geometry and weight (15), basis (16), per field
+                 w df (2) and 20 FMA (40), seven fields                   = 325
+k_mixed_factor   per particle: equilibration + Cholesky (3330), seven
+                 general solves (7 x 820), three unit-vector solves (2234),
+                 inverse-norm estimate (two solves 1640, norms 80),
+                 output scaling (200)                                     = 13224
+k_mixed_resid    per pair: geometry (15), basis (16), per field the FP32
+                 fit (40), residual (3) and dB update (40), seven fields  = 612
+                 per particle: E C + G dB (7 x 3 x 20 FMA + 21)           = 861
+k_mixed_rhs_finish per particle: gradient scaling (21) + right-hand side  = 66
 """
 
 PER_PAIR = {
     "k_moments": 187,
+    "k_moments<fp32>": 187,
+    "k_mixed_b": 325,
+    "k_mixed_resid": 612,
     "k_apply_rhs": 203,
     "k_adj_y": 203,
     "k_adj_pairs": 683,
@@ -38,6 +55,9 @@ PER_PAIR = {
 }
 PER_PARTICLE = {
     "k_factor<3>": 5704,
+    "k_mixed_factor": 13224,
+    "k_mixed_resid": 861,
+    "k_mixed_rhs_finish": 66,
     "k_apply_rhs": 66,
     "k_adj_y": 150,
     "k_adj_factor": 8264,
