@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(THREADS)
             const double* __restrict__ tape, const double* __restrict__ rhs_bar,
             const double* __restrict__ dxdt_bar, double* __restrict__ ybuf,
             double* __restrict__ ubuf, double* __restrict__ qb_direct) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
   const bool valid = i < n;
@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(THREADS)
                   double rf_ratio, int wkind, const double* __restrict__ fq,
                   const double* __restrict__ orec, double* __restrict__ rec,
                   double* __restrict__ own, int slot_order) {
-  const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6));
+  const int i = __builtin_amdgcn_readfirstlane(xcd_block() * (THREADS / 64) + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   if (i >= n) return;  // whole wavefronts leave together
   const int64_t rs = off[i], re = off[i + 1];
@@ -521,7 +521,7 @@ __global__ void __launch_bounds__(THREADS)
                  const double* __restrict__ rec, const double* __restrict__ own,
                  const double* __restrict__ qb_direct, double* __restrict__ q_bar,
                  double* __restrict__ pos_bar) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int tid = xcd_block() * THREADS + threadIdx.x;
   const int j = tid / G;
   const int l = tid % G;
   const bool valid = j < n;

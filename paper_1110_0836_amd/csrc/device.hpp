@@ -125,6 +125,18 @@ __device__ __forceinline__ void basis_grad(T (&gx)[NBASIS], T (&gy)[NBASIS], T (
 // ---------------------------------------------------------------------------
 // Geometry
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched to the eight XCDs round-robin (block b runs on
+// XCD b % 8) and every XCD has its own L2.  Kernels that gather neighbor
+// records number their blocks so that XCD x runs one contiguous range of
+// logical blocks: particles stored in spatial order then share neighbors
+// inside one L2 instead of spreading every neighborhood over eight.
+// A bijection of [0, gridDim.x) for any grid size.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 struct Box {
   double L[3];
   double halfL[3];

@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(THREADS)
     k_mixed_b(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
               const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
               const double* __restrict__ fa, int fb, int nf, double* __restrict__ bout) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
   if (i >= n) return;
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(THREADS)
                   const double* __restrict__ fa, int fb, int nf, const double* __restrict__ cfit,
                   const double* __restrict__ gt, const int32_t* __restrict__ status,
                   const int32_t* __restrict__ flag, double* __restrict__ rows) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
   if (i >= n) return;

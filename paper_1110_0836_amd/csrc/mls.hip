@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(THREADS)
     k_moments(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
               const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
               double* __restrict__ mom) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
   const bool valid = i < n;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(THREADS)
                    const int32_t* __restrict__ status, int nf, int f0,
                    const double* __restrict__ fields, double* __restrict__ out, int out_comp,
                    int comp0, double c0, double c1, double c2, int power) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
   const bool valid = i < n;
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(THREADS)
                 double rf_ratio, int wkind, double gamma, const double* __restrict__ gop,
                 const int32_t* __restrict__ status, double* __restrict__ rhs,
                 double* __restrict__ dxdt, double* __restrict__ tape) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
   const bool valid = i < n;

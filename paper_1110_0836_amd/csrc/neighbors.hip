@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(NB_THREADS)
                 const int32_t* __restrict__ sorted_id, const double4* __restrict__ spos,
                 int32_t* __restrict__ count, const int64_t* __restrict__ offsets,
                 int32_t* __restrict__ out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const double4 pi = spos[t];
   const int i = sorted_id[t];
