@@ -202,34 +202,55 @@ __global__ void __launch_bounds__(THREADS)
   });
 }
 
-// ---- 4. pair contributions, one lane per neighbor entry ----------------------
-// A block covers 256 consecutive CSR entries (slots); every lane finds its
-// owner row in the block's slice of the offsets, computes the pair's
-// contributions and writes them as one record at the pair's transposed
-// position.  The owner's own share (minus the sum of its pair records) is a
-// segmented sum over the wavefront's lanes: rows that lie inside one
-// wavefront are finished here, pieces of longer rows go to per-wavefront
-// partial slots that k_adj_combine adds up in wavefront order.
-__device__ __forceinline__ void poly_val_grad(const double* __restrict__ c,
-                                              const double (&p)[NBASIS], const double (&gx)[NBASIS],
-                                              const double (&gy)[NBASIS],
-                                              const double (&gz)[NBASIS], double& v, double& dx,
-                                              double& dy, double& dz) {
-  double cr[NBASIS];
+// ---- 4. pair contributions ---------------------------------------------------
+// Reverse-mode contributions of one neighbor entry (i, j), j != i, given the
+// owner record o (G rows 0..59, K rows 60..119, Ubar at UOFF):
+//   a = G p, b = Ubar df - K p, dfbar_f = w Ubar_f . a, wbar = a . b,
+//   pbar = G^T b - K^T a,  xibar = w (dp/dxi)^T pbar,
+//   dbar = xibar / lambda + wbar w'(q) 2 d / r^2.
+// v receives dfbar (7) and dbar (3).
+__device__ __forceinline__ void pair_terms(const double* __restrict__ o, double w, double dw,
+                                           double inv_lam, double inv_r2, double dx, double dy,
+                                           double dz, const double* __restrict__ fi,
+                                           const double* __restrict__ fj, double (&v)[REC]) {
+  double p[NBASIS];
+  basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+  double av[3], kp[3];
 #pragma unroll
-  for (int b = 0; b < NBASIS; b += 2) {
-    const double2 t = *reinterpret_cast<const double2*>(c + b);
-    cr[b] = t.x;
-    cr[b + 1] = t.y;
-  }
-  v = dx = dy = dz = 0.0;
+  for (int t = 0; t < 3; ++t) {
+    double a = 0.0, k = 0.0;
 #pragma unroll
-  for (int b = 0; b < NBASIS; ++b) {
-    v = fma(cr[b], p[b], v);
-    dx = fma(cr[b], gx[b], dx);  // the compiler drops the zero entries
-    dy = fma(cr[b], gy[b], dy);
-    dz = fma(cr[b], gz[b], dz);
+    for (int b = 0; b < NBASIS; ++b) {
+      a = fma(o[t * NBASIS + b], p[b], a);
+      k = fma(o[60 + t * NBASIS + b], p[b], k);
+    }
+    av[t] = a;
+    kp[t] = k;
   }
+  double bv[3] = {-kp[0], -kp[1], -kp[2]};
+#pragma unroll
+  for (int f = 0; f < 7; ++f) {
+    const double df = fj[f + 1] - fi[f + 1];
+    const double u0 = o[UOFF + 3 * f], u1 = o[UOFF + 3 * f + 1], u2 = o[UOFF + 3 * f + 2];
+    bv[0] = fma(u0, df, bv[0]);
+    bv[1] = fma(u1, df, bv[1]);
+    bv[2] = fma(u2, df, bv[2]);
+    v[f] = w * (u0 * av[0] + u1 * av[1] + u2 * av[2]);
+  }
+  const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
+  double pb[NBASIS];
+  pb[0] = 0.0;  // the constant's derivative vanishes
+#pragma unroll
+  for (int b = 1; b < NBASIS; ++b)
+    pb[b] = bv[0] * o[b] + bv[1] * o[NBASIS + b] + bv[2] * o[2 * NBASIS + b] -
+            av[0] * o[60 + b] - av[1] * o[60 + NBASIS + b] - av[2] * o[60 + 2 * NBASIS + b];
+  double xg[3];
+  basis_grad_dot(p, pb, xg);
+  const double geo_f = wbar * dw * 2.0 * inv_r2;
+  const double wl = w * inv_lam;
+  v[7] = fma(wl, xg[0], geo_f * dx);
+  v[8] = fma(wl, xg[1], geo_f * dy);
+  v[9] = fma(wl, xg[2], geo_f * dz);
 }
 
 __global__ void __launch_bounds__(PAIRS_PER_BLOCK)
@@ -300,40 +321,8 @@ __global__ void __launch_bounds__(PAIRS_PER_BLOCK)
       const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
       const double w = weight_of(qd, wkind);
       const double dw = weight_dq(qd, wkind);
-      const double ex = dx * inv_lam, ey = dy * inv_lam, ez = dz * inv_lam;
-      double p[NBASIS], gx[NBASIS], gy[NBASIS], gz[NBASIS];
-      basis(p, ex, ey, ez);
-      basis_grad(gx, gy, gz, ex, ey, ez);
-      const double* o = orec + (int64_t)i * OREC;
-      double av[3], ag[3][3], kp[3], kg[3][3];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        poly_val_grad(o + t * NBASIS, p, gx, gy, gz, av[t], ag[t][0], ag[t][1], ag[t][2]);
-        poly_val_grad(o + 60 + t * NBASIS, p, gx, gy, gz, kp[t], kg[t][0], kg[t][1], kg[t][2]);
-      }
-      double bv[3] = {-kp[0], -kp[1], -kp[2]};
-      const double* fi = fq + 8 * (int64_t)i;
-      const double* fj = fq + 8 * (int64_t)j;
-#pragma unroll
-      for (int f = 0; f < 7; ++f) {
-        const double df = fj[f + 1] - fi[f + 1];
-        const double u0 = o[UOFF + 3 * f], u1 = o[UOFF + 3 * f + 1], u2 = o[UOFF + 3 * f + 2];
-        bv[0] = fma(u0, df, bv[0]);
-        bv[1] = fma(u1, df, bv[1]);
-        bv[2] = fma(u2, df, bv[2]);
-        v[f] = w * (u0 * av[0] + u1 * av[1] + u2 * av[2]);
-      }
-      const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
-      const double geo = wbar * dw * 2.0 * inv_r2;
-      // xibar_c = w (b . (G dp/dxi_c) - a . (K dp/dxi_c))
-      double xb[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        xb[c] = w * (bv[0] * ag[0][c] + bv[1] * ag[1][c] + bv[2] * ag[2][c] -
-                     av[0] * kg[0][c] - av[1] * kg[1][c] - av[2] * kg[2][c]);
-      v[7] = xb[0] * inv_lam + geo * dx;
-      v[8] = xb[1] * inv_lam + geo * dy;
-      v[9] = xb[2] * inv_lam + geo * dz;
+      pair_terms(orec + (int64_t)i * OREC, w, dw, inv_lam, inv_r2, dx, dy, dz,
+                 fq + 8 * (int64_t)i, fq + 8 * (int64_t)j, v);
     }
     double2* out = reinterpret_cast<double2*>(rec + (slot_order ? s : (int64_t)t_pos[s]) * REC);
 #pragma unroll
@@ -409,22 +398,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ void poly_val_grad_s(const double* __restrict__ c,
-                                                const double (&p)[NBASIS],
-                                                const double (&gx)[NBASIS],
-                                                const double (&gy)[NBASIS],
-                                                const double (&gz)[NBASIS], double& v, double& dx,
-                                                double& dy, double& dz) {
-  v = dx = dy = dz = 0.0;
-#pragma unroll
-  for (int b = 0; b < NBASIS; ++b) {
-    const double cb = c[b];
-    v = fma(cb, p[b], v);
-    dx = fma(cb, gx[b], dx);
-    dy = fma(cb, gy[b], dy);
-    dz = fma(cb, gz[b], dz);
-  }
-}
 
 __global__ void __launch_bounds__(THREADS)
     k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
@@ -458,36 +431,7 @@ __global__ void __launch_bounds__(THREADS)
       const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
       const double w = weight_of(qd, wkind);
       const double dw = weight_dq(qd, wkind);
-      const double ex = dx * inv_lam, ey = dy * inv_lam, ez = dz * inv_lam;
-      double p[NBASIS], gx[NBASIS], gy[NBASIS], gz[NBASIS];
-      basis(p, ex, ey, ez);
-      basis_grad(gx, gy, gz, ex, ey, ez);
-      double av[3], ag[3][3], kp[3], kg[3][3];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        poly_val_grad_s(o + t * NBASIS, p, gx, gy, gz, av[t], ag[t][0], ag[t][1], ag[t][2]);
-        poly_val_grad_s(o + 60 + t * NBASIS, p, gx, gy, gz, kp[t], kg[t][0], kg[t][1],
-                        kg[t][2]);
-      }
-      double bv[3] = {-kp[0], -kp[1], -kp[2]};
-      const double* fj = fq + 8 * (int64_t)j;
-#pragma unroll
-      for (int f = 0; f < 7; ++f) {
-        const double df = fj[f + 1] - fi[f + 1];
-        const double u0 = o[UOFF + 3 * f], u1 = o[UOFF + 3 * f + 1], u2 = o[UOFF + 3 * f + 2];
-        bv[0] = fma(u0, df, bv[0]);
-        bv[1] = fma(u1, df, bv[1]);
-        bv[2] = fma(u2, df, bv[2]);
-        v[f] = w * (u0 * av[0] + u1 * av[1] + u2 * av[2]);
-      }
-      const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
-      const double geo_f = wbar * dw * 2.0 * inv_r2;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double xb = w * (bv[0] * ag[0][c] + bv[1] * ag[1][c] + bv[2] * ag[2][c] -
-                               av[0] * kg[0][c] - av[1] * kg[1][c] - av[2] * kg[2][c]);
-        v[7 + c] = xb * inv_lam + geo_f * (c == 0 ? dx : (c == 1 ? dy : dz));
-      }
+      pair_terms(o, w, dw, inv_lam, inv_r2, dx, dy, dz, fi, fq + 8 * (int64_t)j, v);
     }
     double2* out = reinterpret_cast<double2*>(rec + (slot_order ? s : (int64_t)t_pos[s]) * REC);
 #pragma unroll

@@ -122,6 +122,20 @@ __device__ __forceinline__ void basis_grad(T (&gx)[NBASIS], T (&gy)[NBASIS], T (
   gz[15] = 2 * xz; gz[16] = 0; gz[17] = yy; gz[18] = 2 * yz; gz[19] = 3 * zz;
 }
 
+// g_axis = sum_k c_k d p_k / d xi_axis, from the basis values p (their
+// degree-1 and degree-2 entries are the derivatives' monomials).
+template <class T>
+__device__ __forceinline__ void basis_grad_dot(const T (&p)[NBASIS], const T (&c)[NBASIS],
+                                               T (&g)[3]) {
+  g[0] = c[1] + T(2) * p[1] * c[4] + p[2] * c[5] + p[3] * c[6] + T(3) * p[4] * c[10] +
+         T(2) * p[5] * c[11] + T(2) * p[6] * c[12] + p[7] * c[13] + p[8] * c[14] + p[9] * c[15];
+  g[1] = c[2] + p[1] * c[5] + T(2) * p[2] * c[7] + p[3] * c[8] + p[4] * c[11] +
+         T(2) * p[5] * c[13] + p[6] * c[14] + T(3) * p[7] * c[16] + T(2) * p[8] * c[17] +
+         p[9] * c[18];
+  g[2] = c[3] + p[1] * c[6] + p[2] * c[8] + T(2) * p[3] * c[9] + p[4] * c[12] + p[5] * c[14] +
+         T(2) * p[6] * c[15] + p[7] * c[17] + T(2) * p[8] * c[18] + T(3) * p[9] * c[19];
+}
+
 // ---------------------------------------------------------------------------
 // Geometry
 // ---------------------------------------------------------------------------
