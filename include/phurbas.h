@@ -255,7 +255,7 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * neighbor entry, 1: one wavefront per owner particle), "record_order" (0:
  * pair records written at their transposed position, 1: written in forward
  * order and gathered through the inverse map), "mixed_cond_exp" (0..12,
- * default 3: in the mixed form a particle whose FP32-assembled moment matrix,
+ * default 2: in the mixed form a particle whose FP32-assembled moment matrix,
  * scaled to unit diagonal, has an estimated ||A^{-1}||_2 above 10^exp is
  * evaluated in FP64 instead; this knob moves results within the mixed
  * tolerance, the others only by rounding).  EINVAL for an unknown key or value. */

@@ -197,16 +197,20 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
-// FP64 moments and right-hand sides of the listed particles, one thread per
-// particle (few per set).
+// FP64 moments and right-hand sides of the listed particles.  Four lanes per
+// particle split its neighbor entries; partial sums meet in quad reductions.
+// A grid-stride loop over the list (its length is read on the device).
 __global__ void __launch_bounds__(THREADS)
     k_mixed_repair(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                    const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
                    const double* __restrict__ fa, int fb, int nf, const int32_t* __restrict__ list,
                    const int32_t* __restrict__ count, double* __restrict__ mom,
                    double* __restrict__ bout) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int l = tid & 3;
   const int total = *count;
-  for (int k = blockIdx.x * THREADS + threadIdx.x; k < total; k += gridDim.x * THREADS) {
+  const int stride = (int)(gridDim.x * (THREADS / 4));
+  for (int k = tid >> 2; k < total; k += stride) {
     const int i = list[k];
     const double4 gi = geo[i];
     const double inv_lam = 1.0 / gi.w;
@@ -216,7 +220,7 @@ __global__ void __launch_bounds__(THREADS)
     double m[NMOM];
 #pragma unroll
     for (int q = 0; q < NMOM; ++q) m[q] = 0.0;
-    for (int64_t s = s0; s < s1; ++s) {
+    for (int64_t s = s0 + l; s < s1; s += 4) {
       const double4 gj = geo[idx[s]];
       const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
       const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
@@ -225,13 +229,20 @@ __global__ void __launch_bounds__(THREADS)
       accumulate_moments(m, w, dx * inv_lam, dy * inv_lam, dz * inv_lam);
     }
 #pragma unroll
-    for (int q = 0; q < NMOM; ++q) mom[(int64_t)q * n + i] = m[q];
-    for (int f = 0; f < nf; ++f) {
-      const double fi = fa[8 * (int64_t)i + fb + f];
-      double acc[NBASIS];
+    for (int q = 0; q < NMOM; ++q) {
+      const double t = group_sum<4>(m[q]);
+      if ((q & 3) == l) mom[(int64_t)q * n + i] = t;
+    }
+    for (int f0 = 0; f0 < nf; f0 += 4) {
+      double fi[4];
+      double acc[4][NBASIS];
 #pragma unroll
-      for (int b = 0; b < NBASIS; ++b) acc[b] = 0.0;
-      for (int64_t s = s0; s < s1; ++s) {
+      for (int f = 0; f < 4; ++f) {
+        fi[f] = f0 + f < nf ? fa[8 * (int64_t)i + fb + f0 + f] : 0.0;
+#pragma unroll
+        for (int b = 0; b < NBASIS; ++b) acc[f][b] = 0.0;
+      }
+      for (int64_t s = s0 + l; s < s1; s += 4) {
         const int j = idx[s];
         const double4 gj = geo[j];
         const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
@@ -240,12 +251,21 @@ __global__ void __launch_bounds__(THREADS)
         const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
         double p[NBASIS];
         basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-        const double wd = w * (fa[8 * (int64_t)j + fb + f] - fi);
 #pragma unroll
-        for (int b = 0; b < NBASIS; ++b) acc[b] = fma(wd, p[b], acc[b]);
+        for (int f = 0; f < 4; ++f) {
+          const double wd = f0 + f < nf ? w * (fa[8 * (int64_t)j + fb + f0 + f] - fi[f]) : 0.0;
+#pragma unroll
+          for (int b = 0; b < NBASIS; ++b) acc[f][b] = fma(wd, p[b], acc[f][b]);
+        }
       }
 #pragma unroll
-      for (int b = 0; b < NBASIS; ++b) bout[((int64_t)f * NBASIS + b) * n + i] = acc[b];
+      for (int f = 0; f < 4; ++f)
+#pragma unroll
+        for (int b = 0; b < NBASIS; ++b) {
+          const double t = group_sum<4>(acc[f][b]);
+          if (f0 + f < nf && ((f * NBASIS + b) & 3) == l)
+            bout[((int64_t)(f0 + f) * NBASIS + b) * n + i] = t;
+        }
     }
   }
 }
@@ -471,7 +491,7 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
                        m.b, m.cfit, m.gt, status, m.flag, ncut, nullptr, m.list, m.count);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed factor"))) return rc; }
   { Prof pf(ctx, "k_mixed_repair");
-    hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS / 4), dim3(THREADS), 0, s, n, a.geo, a.off,
+    hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, a.geo, a.off,
                        a.idx, a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.list, m.count, m.mom, m.b);
     hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, m.mom,
                        a.off, nf, m.b, m.cfit, m.gt, status, m.flag, ncut, m.list, nullptr,

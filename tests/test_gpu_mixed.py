@@ -55,9 +55,10 @@ def test_config1_derivatives_open_box():
     inner = ok & interior(c["pos"], c["lam"], c["L"], c["periodic"])
     e1, e2 = per_order(g1, g2, o1, o2, inner)
     assert e1 < TOLMIX and e2 < TOLMIX
-    # particles cut by a face: FP32 moments of a lopsided sample
+    # particles cut by a face (lopsided samples): the ill-conditioned ones are
+    # screened out of the FP32 path, so the bound holds for them too
     e1, e2 = per_order(g1, g2, o1, o2, ok)
-    assert e1 < 1e-3 and e2 < 1e-3
+    assert e1 < TOLMIX and e2 < TOLMIX
     assert np.all(np.isnan(g1[:, :, ~ok])) and np.all(np.isnan(g2[:, :, ~ok]))
 
 
