@@ -206,46 +206,65 @@ __global__ void __launch_bounds__(THREADS)
 // Reverse-mode contributions of one neighbor entry (i, j), j != i, given the
 // owner record o (G rows 0..59, K rows 60..119, Ubar at UOFF):
 //   a = G p, b = Ubar df - K p, dfbar_f = w Ubar_f . a, wbar = a . b,
-//   pbar = G^T b - K^T a,  xibar = w (dp/dxi)^T pbar,
+//   xibar = w sum_t (b_t grad(G_t . p) - a_t grad(K_t . p)),
 //   dbar = xibar / lambda + wbar w'(q) 2 d / r^2.
-// v receives dfbar (7) and dbar (3).
+// v receives dfbar (7) and dbar (3).  The owner record is read one
+// 20-coefficient row at a time, each row used at once for its value and its
+// gradient; the compiler fences keep the rows' loads from being hoisted
+// together (a wavefront-uniform record is read through the scalar cache, and
+// 141 doubles do not fit the scalar registers).
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+__device__ __forceinline__ void row_value_grad(const double* __restrict__ c,
+                                               const double (&p)[NBASIS], double& v,
+                                               double (&g)[3]) {
+  v = 0.0;
+#pragma unroll
+  for (int b = 0; b < NBASIS; ++b) v = fma(c[b], p[b], v);
+  g[0] = c[1] + 2.0 * p[1] * c[4] + p[2] * c[5] + p[3] * c[6] + 3.0 * p[4] * c[10] +
+         2.0 * p[5] * c[11] + 2.0 * p[6] * c[12] + p[7] * c[13] + p[8] * c[14] + p[9] * c[15];
+  g[1] = c[2] + p[1] * c[5] + 2.0 * p[2] * c[7] + p[3] * c[8] + p[4] * c[11] +
+         2.0 * p[5] * c[13] + p[6] * c[14] + 3.0 * p[7] * c[16] + 2.0 * p[8] * c[17] +
+         p[9] * c[18];
+  g[2] = c[3] + p[1] * c[6] + p[2] * c[8] + 2.0 * p[3] * c[9] + p[4] * c[12] + p[5] * c[14] +
+         2.0 * p[6] * c[15] + p[7] * c[17] + 2.0 * p[8] * c[18] + 3.0 * p[9] * c[19];
+}
+
 __device__ __forceinline__ void pair_terms(const double* __restrict__ o, double w, double dw,
                                            double inv_lam, double inv_r2, double dx, double dy,
                                            double dz, const double* __restrict__ fi,
                                            const double* __restrict__ fj, double (&v)[REC]) {
   double p[NBASIS];
   basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-  double av[3], kp[3];
+  double df[7];
+#pragma unroll
+  for (int f = 0; f < 7; ++f) df[f] = fj[f + 1] - fi[f + 1];
+  double h[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int f = 0; f < 7; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) h[t] = fma(o[UOFF + 3 * f + t], df[f], h[t]);
+  double av[3], bv[3], xg[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
-    double a = 0.0, k = 0.0;
+    compiler_fence();
+    double a, ga[3];
+    row_value_grad(o + t * NBASIS, p, a, ga);
+    compiler_fence();
+    double k, gk[3];
+    row_value_grad(o + 60 + t * NBASIS, p, k, gk);
+    const double b = h[t] - k;
 #pragma unroll
-    for (int b = 0; b < NBASIS; ++b) {
-      a = fma(o[t * NBASIS + b], p[b], a);
-      k = fma(o[60 + t * NBASIS + b], p[b], k);
-    }
+    for (int c = 0; c < 3; ++c) xg[c] = fma(b, ga[c], fma(-a, gk[c], xg[c]));
     av[t] = a;
-    kp[t] = k;
+    bv[t] = b;
   }
-  double bv[3] = {-kp[0], -kp[1], -kp[2]};
+  compiler_fence();
 #pragma unroll
-  for (int f = 0; f < 7; ++f) {
-    const double df = fj[f + 1] - fi[f + 1];
-    const double u0 = o[UOFF + 3 * f], u1 = o[UOFF + 3 * f + 1], u2 = o[UOFF + 3 * f + 2];
-    bv[0] = fma(u0, df, bv[0]);
-    bv[1] = fma(u1, df, bv[1]);
-    bv[2] = fma(u2, df, bv[2]);
-    v[f] = w * (u0 * av[0] + u1 * av[1] + u2 * av[2]);
-  }
+  for (int f = 0; f < 7; ++f)
+    v[f] = w * (o[UOFF + 3 * f] * av[0] + o[UOFF + 3 * f + 1] * av[1] +
+                o[UOFF + 3 * f + 2] * av[2]);
   const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
-  double pb[NBASIS];
-  pb[0] = 0.0;  // the constant's derivative vanishes
-#pragma unroll
-  for (int b = 1; b < NBASIS; ++b)
-    pb[b] = bv[0] * o[b] + bv[1] * o[NBASIS + b] + bv[2] * o[2 * NBASIS + b] -
-            av[0] * o[60 + b] - av[1] * o[60 + NBASIS + b] - av[2] * o[60 + 2 * NBASIS + b];
-  double xg[3];
-  basis_grad_dot(p, pb, xg);
   const double geo_f = wbar * dw * 2.0 * inv_r2;
   const double wl = w * inv_lam;
   v[7] = fma(wl, xg[0], geo_f * dx);
