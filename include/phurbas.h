@@ -185,6 +185,26 @@ int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, double*
                 const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
                 int64_t* nnz_out, int32_t* status);
 
+/* ---- time evolution (Sec. 2; the tests of Sec. 3.1, 3.2) -----------------
+ * nsteps predictor-corrector steps of size dt, as phb_pc_step.  frozen: NULL or
+ * int32[n]; a particle with frozen[i] != 0 keeps its position and fields (a
+ * fixed-value boundary particle, as in the shock-tube and MRI set-ups of
+ * Sec. 3.3 and 3.5) but still serves as a neighbor.  status[i]: the largest
+ * status over all stages of all steps (0 for frozen particles; 0 everywhere when
+ * nsteps == 0).  Errors as phb_pc_step; the state is then that of the last
+ * completed step.  Synchronizes. */
+int phb_evolve(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, int32_t nsteps,
+               double* pos, double* q, const double* lambda, const int32_t* frozen,
+               int64_t* offsets, int32_t* idx, int64_t idx_capacity, int64_t* nnz_out,
+               int32_t* status);
+/* Courant time step: *dt_out (host) = cfl * min over non-frozen i of
+ * lambda_i / (|V_i| + c_f,i), with the fast-speed bound
+ * c_f = sqrt((gamma P + |B|^2) / rho), P = (gamma - 1) sigma (the paper's own
+ * time-step criteria live in its companion paper).  NaN entries are skipped.
+ * EINVAL if every particle is frozen or cfl <= 0.  Synchronizes. */
+int phb_courant_dt(phb_ctx* ctx, const phb_params* p, int64_t n, const double* q,
+                   const double* lambda, const int32_t* frozen, double cfl, double* dt_out);
+
 /* ---- many particle sets in one captured graph -----------------------------
  * Independent particle sets (each with its own neighbor lists; no set sees
  * another) are stored one after the other: set s owns the particles

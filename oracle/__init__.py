@@ -65,6 +65,10 @@ def lib():
                                        P, I]
         L.orc_pc_step.restype = I
         L.orc_pc_step.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, P, I]
+        L.orc_evolve.restype = I
+        L.orc_evolve.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, I, P, P, I]
+        L.orc_courant_dt.restype = D
+        L.orc_courant_dt.argtypes = [I64, P, P, D, P, D]
         _lib = L
     return _lib
 
@@ -252,3 +256,34 @@ def pc_step(pos, lam, q, dt, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5.0 / 
     if rc == -2:
         raise ValueError("orc_pc_step: a particle left the box on a non-periodic axis")
     return pos, q, st
+
+
+def evolve(pos, lam, q, dt, nsteps, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5.0 / 3.0,
+           frozen=None, weight=0, fit=0, threads=0, rf_ratio=RF_RATIO):
+    """nsteps predictor-corrector steps (frozen: optional mask of particles held
+    fixed); returns new (pos, q, status)."""
+    pos = np.array(pos, dtype=np.float64, order="C", copy=True)
+    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    lam = _c(lam, np.float64)
+    n = lam.shape[0]
+    Lb, pb = _box(L, periodic)
+    fz = None if frozen is None else _c(frozen, np.int32)
+    st = np.zeros(n, np.int32)
+    rc = lib().orc_evolve(n, _p(pos), _p(q), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight,
+                          fit, dt, int(nsteps), _p(fz), _p(st), threads)
+    if rc == -1:
+        raise ValueError("orc_evolve: invalid arguments")
+    if rc == -2:
+        raise ValueError("orc_evolve: a particle left the box on a non-periodic axis")
+    return pos, q, st
+
+
+def courant_dt(q, lam, cfl=0.3, gamma=5.0 / 3.0, frozen=None):
+    """cfl * min lambda / (|V| + c_fast) over non-frozen particles."""
+    q = _c(q, np.float64)
+    lam = _c(lam, np.float64)
+    fz = None if frozen is None else _c(frozen, np.int32)
+    dt = lib().orc_courant_dt(lam.shape[0], _p(q), _p(lam), gamma, _p(fz), cfl)
+    if dt < 0:
+        raise ValueError("orc_courant_dt: no particle to time-step")
+    return dt

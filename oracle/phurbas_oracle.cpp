@@ -859,9 +859,64 @@ int orc_adjoint_sampled(int64_t n, const double* pos, const double* lambda, cons
 // wrapped back into [0, L) on periodic axes after each stage.
 // status[i] is the larger of the two stages' statuses.  Returns -2 when a
 // predicted position leaves [0, L) on a non-periodic axis.
+// One Heun step (reading of the second-order predictor-corrector, Sec. 2)
+// with an optional mask of frozen particles, whose time derivatives are taken
+// as zero (fixed-value boundary particles, Sec. 3.3 and 3.5).
+static int pc_step_masked(int64_t n, double* pos, double* q, const double* lambda,
+                          const double* L, const int32_t* periodic, double rf_ratio, double gamma,
+                          int weight, int fit, double dt, const int32_t* frozen, int32_t* status,
+                          int nthreads);
+
 int orc_pc_step(int64_t n, double* pos, double* q, const double* lambda, const double* L,
                 const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
                 double dt, int32_t* status, int nthreads) {
+  return pc_step_masked(n, pos, q, lambda, L, periodic, rf_ratio, gamma, weight, fit, dt,
+                        nullptr, status, nthreads);
+}
+
+// nsteps steps of size dt; status = the largest over all stages and steps
+// (0 for frozen particles).
+int orc_evolve(int64_t n, double* pos, double* q, const double* lambda, const double* L,
+               const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
+               double dt, int nsteps, const int32_t* frozen, int32_t* status, int nthreads) {
+  if (n <= 0 || !pos || !q || !lambda || nsteps < 0) return -1;
+  std::vector<int32_t> st(n, 0), acc(n, 0);
+  for (int k = 0; k < nsteps; ++k) {
+    int rc = pc_step_masked(n, pos, q, lambda, L, periodic, rf_ratio, gamma, weight, fit, dt,
+                            frozen, st.data(), nthreads);
+    if (rc) return rc;
+    for (int64_t i = 0; i < n; ++i) acc[i] = std::max(acc[i], st[i]);
+  }
+  if (status)
+    for (int64_t i = 0; i < n; ++i) status[i] = (frozen && frozen[i]) ? 0 : acc[i];
+  return 0;
+}
+
+// Courant step: cfl * min over non-frozen particles of lambda / (|V| + c_f),
+// c_f = sqrt((gamma P + B^2) / rho) with P = (gamma - 1) sigma (reading: the
+// paper's own criteria are in its companion paper).  Returns -1 if none.
+double orc_courant_dt(int64_t n, const double* q, const double* lambda, double gamma,
+                      const int32_t* frozen, double cfl) {
+  double best = -1.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (frozen && frozen[i]) continue;
+    const double rho = q[i];
+    const double v2 = q[n + i] * q[n + i] + q[2 * n + i] * q[2 * n + i] + q[3 * n + i] * q[3 * n + i];
+    const double b2 = q[4 * n + i] * q[4 * n + i] + q[5 * n + i] * q[5 * n + i] +
+                      q[6 * n + i] * q[6 * n + i];
+    const double P = (gamma - 1.0) * q[7 * n + i];
+    const double cf = std::sqrt((gamma * P + b2) / rho);
+    const double t = lambda[i] / (std::sqrt(v2) + cf);
+    if (std::isnan(t)) continue;
+    if (best < 0.0 || t < best) best = t;
+  }
+  return best < 0.0 ? -1.0 : cfl * best;
+}
+
+static int pc_step_masked(int64_t n, double* pos, double* q, const double* lambda,
+                          const double* L, const int32_t* periodic, double rf_ratio, double gamma,
+                          int weight, int fit, double dt, const int32_t* frozen, int32_t* status,
+                          int nthreads) {
   if (n <= 0 || !pos || !q || !lambda) return -1;
   Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -893,12 +948,22 @@ int orc_pc_step(int64_t n, double* pos, double* q, const double* lambda, const d
   std::vector<double> x0(pos, pos + 3 * n), q0(q, q + 8 * n);
   std::vector<double> f0(8 * n), v0(3 * n), f1(8 * n), v1(3 * n);
   std::vector<int32_t> s0(n), s1(n);
+  auto freeze = [&](std::vector<double>& fq, std::vector<double>& fx) {
+    if (!frozen) return;
+    for (int64_t i = 0; i < n; ++i)
+      if (frozen[i]) {
+        for (int f = 0; f < 8; ++f) fq[f * n + i] = 0.0;
+        for (int a = 0; a < 3; ++a) fx[a * n + i] = 0.0;
+      }
+  };
   eval(x0, q0, f0, v0, s0);
+  freeze(f0, v0);
   std::vector<double> xs(3 * n), qs(8 * n);
   for (int64_t k = 0; k < 3 * n; ++k) xs[k] = x0[k] + dt * v0[k];
   for (int64_t k = 0; k < 8 * n; ++k) qs[k] = q0[k] + dt * f0[k];
   if (!wrap(xs)) return -2;
   eval(xs, qs, f1, v1, s1);
+  freeze(f1, v1);
   for (int64_t k = 0; k < 3 * n; ++k) pos[k] = x0[k] + 0.5 * dt * (v0[k] + v1[k]);
   for (int64_t k = 0; k < 8 * n; ++k) q[k] = q0[k] + 0.5 * dt * (f0[k] + f1[k]);
   std::vector<double> xn(pos, pos + 3 * n);

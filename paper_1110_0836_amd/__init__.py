@@ -37,7 +37,7 @@ EXPORTS = [
     "phb_last_error", "phb_neighbors_build", "phb_neighbors_transpose", "phb_spatial_order",
     "phb_permute", "phb_mls_derivs", "phb_mhd_rhs", "phb_tape_bytes", "phb_mhd_rhs_adjoint",
     "phb_pc_step", "phb_profile", "phb_profile_read", "phb_tune_set", "phb_tune_get",
-    "phb_tune", "phb_batch_create", "phb_batch_destroy", "phb_batch_neighbors", "phb_batch_run",
+    "phb_evolve", "phb_courant_dt", "phb_tune", "phb_batch_create", "phb_batch_destroy", "phb_batch_neighbors", "phb_batch_run",
     "phb_batch_capture", "phb_batch_launch",
 ]
 
@@ -122,6 +122,9 @@ def lib():
             "phb_tune_set": (I, [P, ctypes.c_char_p, I]),
             "phb_tune_get": (I, [P, ctypes.c_char_p, ctypes.POINTER(I)]),
             "phb_profile_read": (I, [P, I32, P, P, P, ctypes.POINTER(I32)]),
+            "phb_evolve": (I, [P, PP, I64, D, I32, P, P, P, P, P, P, I64, ctypes.POINTER(I64),
+                               P]),
+            "phb_courant_dt": (I, [P, PP, I64, P, P, P, D, ctypes.POINTER(D)]),
             "phb_tune": (I, [P, PP, I64, P, P, P, P, P, P, P, I64, P, I32, ctypes.c_char_p]),
             "phb_batch_create": (I, [P, PP, I32, ctypes.POINTER(I64), ctypes.POINTER(P)]),
             "phb_batch_destroy": (I, [P]),
@@ -258,6 +261,27 @@ def phb_pc_step(setup, dt, pos, q, lam, offsets, idx, capacity, status):
     return rc, nnz.value
 
 
+def phb_evolve(setup, dt, nsteps, pos, q, lam, frozen, offsets, idx, capacity, status):
+    ctx = context(pos.device.index)
+    p = setup.params()
+    nnz = ctypes.c_int64(0)
+    rc = lib().phb_evolve(ctx, ctypes.byref(p), lam.shape[0], float(dt), int(nsteps), _f64(pos),
+                          _f64(q), _f64(lam), _ptr(frozen), _ptr(offsets), _ptr(idx), capacity,
+                          ctypes.byref(nnz), _ptr(status))
+    if rc not in (PHB_OK, PHB_ECAPACITY):
+        _check(ctx, rc)
+    return rc, nnz.value
+
+
+def phb_courant_dt(setup, q, lam, frozen, cfl):
+    ctx = context(q.device.index)
+    p = setup.params()
+    dt = ctypes.c_double(0.0)
+    _check(ctx, lib().phb_courant_dt(ctx, ctypes.byref(p), lam.shape[0], _f64(q), _f64(lam),
+                                     _ptr(frozen), float(cfl), ctypes.byref(dt)))
+    return dt.value
+
+
 TUNE_KEYS = ("cells_per_rf", "lanes_moments", "lanes_apply", "lanes_adj_y", "lanes_gather",
              "adj_pairs_mode", "record_order", "mixed_cond_exp")
 
@@ -390,6 +414,27 @@ def pc_step(pos, q, lam, dt, setup=None, capacity=None):
     if rc == PHB_ECAPACITY:
         raise PhurbasError(rc, f"neighbor capacity {cap} < {nnz}; pass capacity=")
     return st, offsets, idx[:nnz]
+
+
+def evolve(pos, q, lam, dt, nsteps, setup=None, frozen=None, capacity=None):
+    """nsteps predictor-corrector steps in place; returns the status (n,)
+    (largest over all stages).  frozen: optional int32 (n,) mask of particles
+    held fixed."""
+    setup = setup or Setup()
+    n = lam.shape[0]
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=pos.device)
+    cap = capacity if capacity is not None else 64 * n
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=pos.device)
+    st = torch.empty(n, dtype=torch.int32, device=pos.device)
+    rc, nnz = phb_evolve(setup, dt, nsteps, pos, q, lam, frozen, offsets, idx, cap, st)
+    if rc == PHB_ECAPACITY:
+        raise PhurbasError(rc, f"neighbor capacity {cap} < {nnz}; pass capacity=")
+    return st
+
+
+def courant_dt(q, lam, cfl=0.3, setup=None, frozen=None):
+    """Courant step cfl * min lambda / (|V| + c_fast) over non-frozen particles."""
+    return phb_courant_dt(setup or Setup(), q, lam, frozen, cfl)
 
 
 class MHDRHS(torch.autograd.Function):

@@ -94,8 +94,21 @@ __global__ void __launch_bounds__(THREADS)
   const double4 gi = geo[ii];
   const double inv_lam = 1.0 / gi.w;
   const int st = (int)tape[(int64_t)21 * n + ii];
-  double qi[8], ub[7][3], qb[8];
-  pointwise_adjoint(n, ii, q, tape, rhs_bar, dxdt_bar, gamma, inv_lam, st, qi, ub, qb);
+  double qi[8], ub[7][3];
+  {
+    double qb[8];
+    pointwise_adjoint(n, ii, q, tape, rhs_bar, dxdt_bar, gamma, inv_lam, st, qi, ub, qb);
+    // the owner's Ubar and direct qbar go out now, so that they are not held
+    // in registers through the neighbor loop
+    if (valid && l == 0) {
+#pragma unroll
+      for (int f = 0; f < 7; ++f)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) ubuf[(int64_t)i * OREC + UOFF + f * 3 + t] = ub[f][t];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) qb_direct[(int64_t)f * n + i] = qb[f];
+    }
+  }
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
   double y[3][NBASIS];
@@ -153,14 +166,6 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
       for (int b = 0; b < NBASIS; ++b)
         if ((t * NBASIS + b) % G == l) ybuf[((int64_t)t * NBASIS + b) * n + i] = y[t][b];
-    if (l == 0) {
-#pragma unroll
-      for (int f = 0; f < 7; ++f)
-#pragma unroll
-        for (int t = 0; t < 3; ++t) ubuf[(int64_t)i * OREC + UOFF + f * 3 + t] = ub[f][t];
-#pragma unroll
-      for (int f = 0; f < 8; ++f) qb_direct[(int64_t)f * n + i] = qb[f];
-    }
   }
 }
 

@@ -25,8 +25,12 @@ int mixed_rhs(phb_ctx* ctx, const EvalArgs& a, double gamma, const double* q, do
 int mixed_derivs(phb_ctx* ctx, const EvalArgs& a, int nf, const double* fields, double* d1,
                  double* d2, int32_t* status);
 
+// One Heun step; frozen (nullable) marks particles held fixed; accumulate:
+// status keeps the maximum over earlier steps.
 int pc_step(phb_ctx* ctx, const phb_params* p, int n, double dt, double* pos, double* q,
-            const double* lambda, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
-            int64_t* nnz_out, int32_t* status);
+            const double* lambda, const int32_t* frozen, int64_t* offsets, int32_t* idx,
+            int64_t idx_capacity, int64_t* nnz_out, int32_t* status, int accumulate);
+int courant_dt(phb_ctx* ctx, const phb_params* p, int n, const double* q, const double* lambda,
+               const int32_t* frozen, double cfl, double* dt_out);
 
 }  // namespace phb

@@ -590,8 +590,38 @@ int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt, doubl
   if (!pos || !q || !lambda || !offsets || !idx || !nnz_out || !status || !isfinite(dt))
     return set_error(ctx, PHB_EINVAL, "bad arguments");
   hipSetDevice(ctx->device);
-  return pc_step(ctx, p, (int)n64, dt, pos, q, lambda, offsets, idx, idx_capacity, nnz_out,
-                 status);
+  return pc_step(ctx, p, (int)n64, dt, pos, q, lambda, nullptr, offsets, idx, idx_capacity,
+                 nnz_out, status, 0);
+}
+
+int phb_evolve(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt, int32_t nsteps,
+               double* pos, double* q, const double* lambda, const int32_t* frozen,
+               int64_t* offsets, int32_t* idx, int64_t idx_capacity, int64_t* nnz_out,
+               int32_t* status) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!pos || !q || !lambda || !offsets || !idx || !nnz_out || !status || !isfinite(dt) ||
+      nsteps < 0)
+    return set_error(ctx, PHB_EINVAL, "bad arguments");
+  hipSetDevice(ctx->device);
+  if (nsteps == 0) return hip_check(ctx, fill_i32(ctx->stream, status, 0, n64), "status clear");
+  for (int k = 0; k < nsteps; ++k)
+    if ((rc = pc_step(ctx, p, (int)n64, dt, pos, q, lambda, frozen, offsets, idx, idx_capacity,
+                      nnz_out, status, k > 0)))
+      return rc;
+  return PHB_OK;
+}
+
+int phb_courant_dt(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* q,
+                   const double* lambda, const int32_t* frozen, double cfl, double* dt_out) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!q || !lambda || !dt_out || !(cfl > 0.0) || !isfinite(cfl))
+    return set_error(ctx, PHB_EINVAL, "bad arguments");
+  hipSetDevice(ctx->device);
+  return courant_dt(ctx, p, (int)n64, q, lambda, frozen, cfl, dt_out);
 }
 
 }  // extern "C"

@@ -194,6 +194,46 @@ def config3(seed: int = 3, n: int = 1 << 20):
                 name=f"shear_layer_adaptive_{n}")
 
 
+def linear_wave(kind: str, side: int, eps: float = 1e-6, seed: int = 6, jitter: float = 0.3):
+    """Linear-wave set of Sec. 3.1: a jittered side^3 lattice in the periodic unit
+    cube, rho = 1, P = 1/gamma (sound speed 1), gamma = 5/3, carrying
+    eps R cos(2 pi x - omega t) at t = 0 with R of unit 2-norm:
+      "sound":  B = 0,             V along x, omega = 2 pi;
+      "alfven": B = (1, 0, 0),     V along y, omega = 2 pi (shear Alfven wave);
+      "fast":   B = (0, 0, sqrt 3), V along x, omega = 4 pi (magnetoacoustic, k
+                perpendicular to B).
+    The other components follow from the linearized equations (App. A with no
+    viscosity): rho = rho0 k.V/omega, P = gamma P0 k.V/omega,
+    B = (B0 k.V - (k.B0) V)/omega, sigma = P/(gamma - 1).  Returns the set with
+    omega, R, eps and the background q0."""
+    rng = np.random.default_rng(seed)
+    pos = jittered_lattice(side, jitter, rng)
+    n = pos.shape[1]
+    lam = np.full(n, 1.0 / side)
+    rho0, P0 = 1.0, 1.0 / GAMMA
+    k = np.array([2 * np.pi, 0.0, 0.0])
+    if kind == "sound":
+        B0, V, speed = np.zeros(3), np.array([1.0, 0.0, 0.0]), 1.0
+    elif kind == "alfven":
+        B0, V, speed = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]), 1.0
+    elif kind == "fast":
+        B0, V, speed = np.array([0.0, 0.0, math.sqrt(3.0)]), np.array([1.0, 0.0, 0.0]), 2.0
+    else:
+        raise ValueError(kind)
+    omega = speed * 2 * np.pi
+    kv = k @ V
+    R = np.concatenate([[rho0 * kv / omega], V, (B0 * kv - (k @ B0) * V) / omega,
+                        [GAMMA * P0 * kv / omega / (GAMMA - 1.0)]])
+    R /= np.linalg.norm(R)
+    q0 = np.zeros(8)
+    q0[0] = rho0
+    q0[4:7] = B0
+    q0[7] = P0 / (GAMMA - 1.0)
+    q = q0[:, None] + eps * R[:, None] * np.cos(2 * np.pi * pos[0])[None, :]
+    return dict(pos=pos, lam=lam, q=q, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=GAMMA,
+                omega=omega, R=R, eps=eps, q0=q0, name=f"{kind}_wave_lattice{side}")
+
+
 def config5(seed: int = 5, n_sets: int = 32, smin: int = 16, smax: int = 64):
     """n_sets independent periodic unit cubes, side n_s ~ U{smin..smax}, jittered
     lattice with lambda = 1/n_s.  Each field a0 + sum_{m=1..3} a_m sin(2 pi k_m.x + phi_m)

@@ -6,7 +6,11 @@ import numpy as np
 
 
 def dev(a, dtype=None):
+    """Copy a numpy array to the GPU (dtype: a numpy or torch dtype)."""
     import torch
+    if dtype is not None and not isinstance(dtype, torch.dtype):
+        a = np.asarray(a, dtype=dtype)
+        dtype = None
     t = torch.from_numpy(np.ascontiguousarray(a))
     if dtype is not None:
         t = t.to(dtype)
