@@ -94,12 +94,16 @@ __global__ void __launch_bounds__(THREADS)
   const double4 gi = geo[ii];
   const double inv_lam = 1.0 / gi.w;
   const int st = (int)tape[(int64_t)21 * n + ii];
-  double qi[8], ub[7][3];
+  // Ubar (21 doubles) waits in LDS during the neighbor loop instead of in
+  // every lane's registers; ush[k][pl] holds entries 2k, 2k+1.
+  constexpr int PPB = THREADS / G;
+  __shared__ double2 ush[11][PPB];
+  const int pl = threadIdx.x / G;
+  double qi[8];
   {
-    double qb[8];
+    double ub[7][3], qb[8];
     pointwise_adjoint(n, ii, q, tape, rhs_bar, dxdt_bar, gamma, inv_lam, st, qi, ub, qb);
-    // the owner's Ubar and direct qbar go out now, so that they are not held
-    // in registers through the neighbor loop
+    // the owner's Ubar and direct qbar go out now
     if (valid && l == 0) {
 #pragma unroll
       for (int f = 0; f < 7; ++f)
@@ -108,7 +112,15 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
       for (int f = 0; f < 8; ++f) qb_direct[(int64_t)f * n + i] = qb[f];
     }
+    if (l == 0) {
+#pragma unroll
+      for (int k = 0; k < 11; ++k) {
+        const int e0 = 2 * k, e1 = 2 * k + 1;
+        ush[k][pl] = make_double2(ub[e0 / 3][e0 % 3], e1 < 21 ? ub[e1 / 3][e1 % 3] : 0.0);
+      }
+    }
   }
+  __syncthreads();
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
   double y[3][NBASIS];
@@ -142,12 +154,17 @@ __global__ void __launch_bounds__(THREADS)
     const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
     double p[NBASIS];
     basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    double df[7];
+#pragma unroll
+    for (int f = 0; f < 7; ++f) df[f] = qj[f + 1] - qi[f + 1];
     double h[3] = {0.0, 0.0, 0.0};
+    asm volatile("" ::: "memory");  // re-read Ubar from LDS (see above)
 #pragma unroll
-    for (int f = 0; f < 7; ++f) {
-      const double df = qj[f + 1] - qi[f + 1];
-#pragma unroll
-      for (int t = 0; t < 3; ++t) h[t] = fma(ub[f][t], df, h[t]);
+    for (int k = 0; k < 11; ++k) {
+      const double2 u = ush[k][pl];
+      const int e0 = 2 * k, e1 = 2 * k + 1;
+      h[e0 % 3] = fma(u.x, df[e0 / 3], h[e0 % 3]);
+      if (e1 < 21) h[e1 % 3] = fma(u.y, df[e1 / 3], h[e1 % 3]);
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {

@@ -33,10 +33,9 @@ constexpr EntryTab make_entry_tab() {
 }
 
 struct QuadChol {
-  double a[60];        // own rows of L (equilibrated)
-  double s_own[5];     // equilibration scale of the own rows
-  double s_all[NBASIS];
-  double inv_ld[NBASIS];
+  double a[60];      // own rows of L (equilibrated)
+  double s_own[5];   // equilibration scale of the own rows
+  double inv_own[5]; // 1 / L_kk of the own rows
   bool ok;
   double ldmin, ldmax;
 };
@@ -64,17 +63,20 @@ __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& ta
     c.s_own[rho] = dg[rho] > 0.0 ? 1.0 / sqrt(dg[rho]) : 1.0;
   });
   c.ok = quad_min(c.ok ? 1.0 : 0.0) > 0.5;  // the same verdict on all four lanes
-  sfor<0, NBASIS>([&](auto C) {
-    constexpr int cc = C;
-    c.s_all[cc] = quad_bcast<cc & 3>(c.s_own[cc >> 2]);
-  });
-  sfor<0, 5>([&](auto R) {
-    constexpr int rho = R;
-    sfor<0, 4 * rho + 4>([&](auto C) {
+  {
+    double s_all[NBASIS];
+    sfor<0, NBASIS>([&](auto C) {
       constexpr int cc = C;
-      c.a[chol_aoff(rho) + cc] *= c.s_own[rho] * c.s_all[cc];
+      s_all[cc] = quad_bcast<cc & 3>(c.s_own[cc >> 2]);
     });
-  });
+    sfor<0, 5>([&](auto R) {
+      constexpr int rho = R;
+      sfor<0, 4 * rho + 4>([&](auto C) {
+        constexpr int cc = C;
+        c.a[chol_aoff(rho) + cc] *= c.s_own[rho] * s_all[cc];
+      });
+    });
+  }
   c.ldmin = 1e300;
   c.ldmax = 0.0;
   sfor<0, NBASIS>([&](auto K) {
@@ -87,7 +89,7 @@ __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& ta
     c.ldmin = fmin(c.ldmin, lkk);
     c.ldmax = fmax(c.ldmax, lkk);
     const double inv = 1.0 / lkk;
-    c.inv_ld[k] = inv;
+    c.inv_own[rk] = (l == o) ? inv : c.inv_own[rk];
     sfor<rk, 5>([&](auto R) {
       constexpr int rho = R;
       c.a[chol_aoff(rho) + k] *= inv;
@@ -127,9 +129,10 @@ __device__ __forceinline__ void quad_chol_solve(const QuadChol& c, int l, double
     constexpr int k = K;
     constexpr int o = k & 3;
     constexpr int rk = k >> 2;
-    double t = quad_bcast<o>(y[rk]);
+    // the owner lane o holds y_k and 1 / L_kk
+    double t = y[rk];
     if constexpr (ADAPT) t += t >= 0.0 ? 1.0 : -1.0;
-    const double yk = t * c.inv_ld[k];
+    const double yk = quad_bcast<o>(t * c.inv_own[rk]);
     sfor<rk + 1, 5>([&](auto R) {
       constexpr int rho = R;
       y[rho] = fma(-c.a[chol_aoff(rho) + k], yk, y[rho]);
@@ -149,7 +152,7 @@ __device__ __forceinline__ void quad_chol_solve(const QuadChol& c, int l, double
     });
     part += (l > o) ? c.a[chol_aoff(rk) + k] * x[rk] : 0.0;
     part = group_sum<4>(part);
-    const double xk = (y[rk] - part) * c.inv_ld[k];
+    const double xk = (y[rk] - part) * c.inv_own[rk];  // valid on the owner lane
     x[rk] = (l == o) ? xk : x[rk];
   });
 }
@@ -158,9 +161,10 @@ __device__ __forceinline__ void quad_chol_solve(const QuadChol& c, int l, double
 template <int T>
 __device__ __forceinline__ void quad_chol_inverse_row(const QuadChol& c, int l, double (&out)[5]) {
   double y[5];
+  const double sT = quad_bcast<T & 3>(c.s_own[T >> 2]);
   sfor<0, 5>([&](auto R) {
     constexpr int rho = R;
-    y[rho] = (4 * rho + l == T) ? c.s_all[T] : 0.0;
+    y[rho] = (4 * rho + l == T) ? sT : 0.0;
   });
   double x[5];
   quad_chol_solve<T>(c, l, y, x);

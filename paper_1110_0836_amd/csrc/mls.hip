@@ -267,11 +267,19 @@ __global__ void __launch_bounds__(THREADS)
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   const int st = status[ii];
-  double g[3][NBASIS];
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) g[t][b] = gop[((int64_t)t * NBASIS + b) * n + ii];
+  // The particle's three operator rows live in LDS, not in each lane's
+  // registers: gsh[k][pl] holds entries 2k, 2k+1 of the 60, and one 16-byte
+  // read serves all lanes of a particle (consecutive particles, consecutive
+  // addresses: no bank conflicts).
+  constexpr int PPB = THREADS / G;
+  __shared__ double2 gsh[3 * NBASIS / 2][PPB];
+  const int pl = threadIdx.x / G;
+  for (int k = l; k < 3 * NBASIS / 2; k += G) {
+    const int t = (2 * k) / NBASIS, b = (2 * k) % NBASIS;
+    gsh[k][pl] = make_double2(gop[((int64_t)t * NBASIS + b) * n + ii],
+                              gop[((int64_t)t * NBASIS + b + 1) * n + ii]);
+  }
+  __syncthreads();
   double qi[8];
   load_fields(fq, ii, qi);
   const double4 gi = geo[ii];
@@ -309,11 +317,18 @@ __global__ void __launch_bounds__(THREADS)
     double p[NBASIS];
     basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
     double gam[3];
+    // re-read the rows from LDS every iteration: hoisted out of the loop they
+    // would occupy 120 registers again
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       double v = 0.0;
 #pragma unroll
-      for (int b = 0; b < NBASIS; ++b) v = fma(g[t][b], p[b], v);
+      for (int b = 0; b < NBASIS; b += 2) {
+        const double2 gg = gsh[(t * NBASIS + b) / 2][pl];
+        v = fma(gg.x, p[b], v);
+        v = fma(gg.y, p[b + 1], v);
+      }
       gam[t] = w * v;
     }
 #pragma unroll
