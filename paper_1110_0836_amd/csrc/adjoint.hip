@@ -440,11 +440,14 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 
+// RT: type of the pair records (double; float in the mixed form, where the
+// records are an application-level quantity and halve the record traffic).
+template <class RT>
 __global__ void __launch_bounds__(THREADS)
     k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                   const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
                   double rf_ratio, int wkind, const double* __restrict__ fq,
-                  const double* __restrict__ orec, double* __restrict__ rec,
+                  const double* __restrict__ orec, RT* __restrict__ rec,
                   double* __restrict__ own, int slot_order) {
   const int i = __builtin_amdgcn_readfirstlane(xcd_block() * (THREADS / 64) + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
@@ -474,9 +477,16 @@ __global__ void __launch_bounds__(THREADS)
       const double dw = weight_dq(qd, wkind);
       pair_terms(o, w, dw, inv_lam, inv_r2, dx, dy, dz, fi, fq + 8 * (int64_t)j, v);
     }
-    double2* out = reinterpret_cast<double2*>(rec + (slot_order ? s : (int64_t)t_pos[s]) * REC);
+    RT* out = rec + (slot_order ? s : (int64_t)t_pos[s]) * REC;
+    if constexpr (sizeof(RT) == 8) {
+      double2* o2 = reinterpret_cast<double2*>(out);
 #pragma unroll
-    for (int c = 0; c < REC; c += 2) out[c / 2] = make_double2(v[c], v[c + 1]);
+      for (int c = 0; c < REC; c += 2) o2[c / 2] = make_double2(v[c], v[c + 1]);
+    } else {
+      float2* o2 = reinterpret_cast<float2*>(out);
+#pragma unroll
+      for (int c = 0; c < REC; c += 2) o2[c / 2] = make_float2((float)v[c], (float)v[c + 1]);
+    }
 #pragma unroll
     for (int c = 0; c < REC; ++c) acc[c] += v[c];
   }
@@ -500,10 +510,10 @@ __global__ void __launch_bounds__(THREADS)
 // ---- 5. gather over the transposed lists ------------------------------------
 // G lanes share one particle's transposed row; their partial sums meet in a
 // quad reduction.  The summation order is fixed for a given G.
-template <int G>
+template <int G, class RT>
 __global__ void __launch_bounds__(THREADS)
     k_adj_gather(int n, const int64_t* __restrict__ t_off, const int32_t* __restrict__ t_slot,
-                 const double* __restrict__ rec, const double* __restrict__ own,
+                 const RT* __restrict__ rec, const double* __restrict__ own,
                  const double* __restrict__ qb_direct, double* __restrict__ q_bar,
                  double* __restrict__ pos_bar) {
   const int tid = xcd_block() * THREADS + threadIdx.x;
@@ -516,13 +526,23 @@ __global__ void __launch_bounds__(THREADS)
   for (int c = 0; c < REC; ++c) acc[c] = 0.0;
   const int64_t k1 = valid ? t_off[jj + 1] : 0;
   for (int64_t k = t_off[jj] + l; k < k1; k += G) {
-    const double2* r =
-        reinterpret_cast<const double2*>(rec + (t_slot ? (int64_t)t_slot[k] : k) * REC);
+    const RT* r = rec + (t_slot ? (int64_t)t_slot[k] : k) * REC;
+    if constexpr (sizeof(RT) == 8) {
+      const double2* r2 = reinterpret_cast<const double2*>(r);
 #pragma unroll
-    for (int c = 0; c < REC; c += 2) {
-      const double2 t = r[c / 2];
-      acc[c] += t.x;
-      acc[c + 1] += t.y;
+      for (int c = 0; c < REC; c += 2) {
+        const double2 t = r2[c / 2];
+        acc[c] += t.x;
+        acc[c + 1] += t.y;
+      }
+    } else {
+      const float2* r2 = reinterpret_cast<const float2*>(r);
+#pragma unroll
+      for (int c = 0; c < REC; c += 2) {
+        const float2 t = r2[c / 2];
+        acc[c] += (double)t.x;
+        acc[c + 1] += (double)t.y;
+      }
     }
   }
 #pragma unroll
@@ -650,11 +670,18 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   hipLaunchKernelGGL(k_adj_factor, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS), 0, s, n,
                      mom, ybuf, tape, orec);
   if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
+  // FP32 pair records in the mixed form (wave-per-owner schedule only)
+  const bool rec32 = p->precision == PHB_MIXED && ctx->adj_pairs_mode == 1;
   if (ctx->adj_pairs_mode == 1) {
     Prof pf(ctx, "k_adj_pairs_w");
-    hipLaunchKernelGGL(k_adj_pairs_w, dim3(grid_for((int64_t)n * 64, THREADS)), dim3(THREADS), 0,
-                       s, n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, rec,
-                       own, slot_order);
+    if (rec32)
+      hipLaunchKernelGGL((k_adj_pairs_w<float>), dim3(grid_for((int64_t)n * 64, THREADS)),
+                         dim3(THREADS), 0, s, n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio,
+                         a.wkind, fq, orec, reinterpret_cast<float*>(rec), own, slot_order);
+    else
+      hipLaunchKernelGGL((k_adj_pairs_w<double>), dim3(grid_for((int64_t)n * 64, THREADS)),
+                         dim3(THREADS), 0, s, n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio,
+                         a.wkind, fq, orec, rec, own, slot_order);
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
   } else {
     if (nnz > 0) {
@@ -679,15 +706,29 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   Prof pf(ctx, "k_adj_gather");
   const int gl = ctx->lanes_gather;
   const unsigned gg = grid_for((int64_t)n * gl, THREADS);
-  if (gl == 1)
-    hipLaunchKernelGGL((k_adj_gather<1>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets, tsl, rec, own,
-                       qbd, q_bar, pos_bar);
-  else if (gl == 2)
-    hipLaunchKernelGGL((k_adj_gather<2>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets, tsl, rec, own,
-                       qbd, q_bar, pos_bar);
-  else
-    hipLaunchKernelGGL((k_adj_gather<4>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets, tsl, rec, own,
-                       qbd, q_bar, pos_bar);
+  const float* rec_f = reinterpret_cast<const float*>(rec);
+  if (gl == 1) {
+    if (rec32)
+      hipLaunchKernelGGL((k_adj_gather<1, float>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
+                         tsl, rec_f, own, qbd, q_bar, pos_bar);
+    else
+      hipLaunchKernelGGL((k_adj_gather<1, double>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
+                         tsl, rec, own, qbd, q_bar, pos_bar);
+  } else if (gl == 2) {
+    if (rec32)
+      hipLaunchKernelGGL((k_adj_gather<2, float>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
+                         tsl, rec_f, own, qbd, q_bar, pos_bar);
+    else
+      hipLaunchKernelGGL((k_adj_gather<2, double>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
+                         tsl, rec, own, qbd, q_bar, pos_bar);
+  } else {
+    if (rec32)
+      hipLaunchKernelGGL((k_adj_gather<4, float>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
+                         tsl, rec_f, own, qbd, q_bar, pos_bar);
+    else
+      hipLaunchKernelGGL((k_adj_gather<4, double>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
+                         tsl, rec, own, qbd, q_bar, pos_bar);
+  }
   return hip_check(ctx, hipGetLastError(), "adjoint gather");
 }
 

@@ -290,11 +290,14 @@ __global__ void __launch_bounds__(THREADS)
   const double4 gi = geo[i];
   const Frame fr = make_frame(gi, box, rf_ratio, wkind);
   const double fi0 = fa[8 * (int64_t)i + fb + f0], fi1 = fa[8 * (int64_t)i + fb + f1];
-  float c0[NBASIS], c1[NBASIS], a0[NBASIS], a1[NBASIS];
+  // this lane's two coefficient vectors wait in LDS (csh[b][thread]), re-read
+  // every neighbor, instead of holding 40 registers through the loop
+  __shared__ float2 csh[NBASIS][THREADS];
+  float a0[NBASIS], a1[NBASIS];
 #pragma unroll
   for (int b = 0; b < NBASIS; ++b) {
-    c0[b] = (float)cfit[((int64_t)f0 * NBASIS + b) * n + i];
-    c1[b] = (float)cfit[((int64_t)f1 * NBASIS + b) * n + i];
+    csh[b][threadIdx.x] = make_float2((float)cfit[((int64_t)f0 * NBASIS + b) * n + i],
+                                      (float)cfit[((int64_t)f1 * NBASIS + b) * n + i]);
     a0[b] = a1[b] = 0.f;
   }
   const bool refine = status[i] == 0 && flag[i] == 0;
@@ -322,10 +325,12 @@ __global__ void __launch_bounds__(THREADS)
     float p[NBASIS];
     basis(p, xs, ys, zs);
     float fit0 = 0.f, fit1 = 0.f;
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b) {
-      fit0 = fmaf(c0[b], p[b], fit0);
-      fit1 = fmaf(c1[b], p[b], fit1);
+      const float2 cb = csh[b][threadIdx.x];
+      fit0 = fmaf(cb.x, p[b], fit0);
+      fit1 = fmaf(cb.y, p[b], fit1);
     }
     const float r0 = w * ((float)(v0 - fi0) - fit0);
     const float r1 = w * ((float)(v1 - fi1) - fit1);
