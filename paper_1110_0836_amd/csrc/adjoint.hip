@@ -294,15 +294,25 @@ __device__ __forceinline__ void pair_terms(const double* __restrict__ o, double 
   v[9] = fma(wl, xg[2], geo_f * dz);
 }
 
+// One lane per neighbor entry: a block takes 256 consecutive entries, so
+// lanes are never idle at row ends.  The owner records of the rows the block
+// touches (at most OWN_MAX of them, contiguous in memory) are staged in LDS
+// by one coalesced copy; blocks touching more rows read them from global
+// memory.  Owner shares are summed by a segmented scan over each wavefront;
+// rows that span wavefronts are finished by k_adj_combine.
+constexpr int OWN_MAX = 24;
+
+template <class RT>
 __global__ void __launch_bounds__(PAIRS_PER_BLOCK)
     k_adj_pairs(int n, int64_t nnz, const double4* __restrict__ geo,
                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
                 const int32_t* __restrict__ t_pos, Box box, double rf_ratio, int wkind,
                 const double* __restrict__ fq, const double* __restrict__ orec,
-                double* __restrict__ rec, double* __restrict__ own, double* __restrict__ wpart,
+                RT* __restrict__ rec, double* __restrict__ own, double* __restrict__ wpart,
                 int slot_order) {
   __shared__ int64_t sh_off[PAIRS_PER_BLOCK + 1];
-  __shared__ int sh_i0;
+  __shared__ int sh_i0, sh_cnt;
+  __shared__ double sh_rec[OWN_MAX * OREC];
   const int64_t S0 = (int64_t)blockIdx.x * PAIRS_PER_BLOCK;
   if (threadIdx.x == 0) {  // last row starting at or before S0
     int lo = 0, hi = n - 1;
@@ -326,11 +336,9 @@ __global__ void __launch_bounds__(PAIRS_PER_BLOCK)
   const bool valid = s < nnz;
   const int lane = threadIdx.x & 63;
   int i = 0x7fffffff;  // owner (sentinel for lanes past the end)
-  double v[REC];
-#pragma unroll
-  for (int c = 0; c < REC; ++c) v[c] = 0.0;
+  int lo = 0;
   if (valid) {
-    int lo = 0, hi = PAIRS_PER_BLOCK;
+    int hi = PAIRS_PER_BLOCK;
     while (lo < hi) {  // last staged row with off <= s
       const int mid = (lo + hi + 1) >> 1;
       if (sh_off[mid] <= s)
@@ -350,6 +358,23 @@ __global__ void __launch_bounds__(PAIRS_PER_BLOCK)
       }
       i = a;
     }
+  }
+  // the last valid lane owns the block's last row
+  const int64_t last = (nnz - 1 - S0) < (PAIRS_PER_BLOCK - 1) ? (nnz - 1 - S0)
+                                                               : (PAIRS_PER_BLOCK - 1);
+  if ((int64_t)threadIdx.x == last) sh_cnt = i - i0 + 1;
+  __syncthreads();
+  const int cnt = sh_cnt;
+  const bool staged = cnt <= OWN_MAX;
+  if (staged) {
+    const double* src = orec + (int64_t)i0 * OREC;
+    for (int k = threadIdx.x; k < cnt * OREC; k += PAIRS_PER_BLOCK) sh_rec[k] = src[k];
+  }
+  __syncthreads();
+  double v[REC];
+#pragma unroll
+  for (int c = 0; c < REC; ++c) v[c] = 0.0;
+  if (valid) {
     const int j = idx[s];
     if (j != i) {
       const double4 gi = geo[i], gj = geo[j];
@@ -362,12 +387,23 @@ __global__ void __launch_bounds__(PAIRS_PER_BLOCK)
       const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
       const double w = weight_of(qd, wkind);
       const double dw = weight_dq(qd, wkind);
-      pair_terms(orec + (int64_t)i * OREC, w, dw, inv_lam, inv_r2, dx, dy, dz,
-                 fq + 8 * (int64_t)i, fq + 8 * (int64_t)j, v);
+      if (staged)
+        pair_terms(sh_rec + (i - i0) * OREC, w, dw, inv_lam, inv_r2, dx, dy, dz,
+                   fq + 8 * (int64_t)i, fq + 8 * (int64_t)j, v);
+      else
+        pair_terms(orec + (int64_t)i * OREC, w, dw, inv_lam, inv_r2, dx, dy, dz,
+                   fq + 8 * (int64_t)i, fq + 8 * (int64_t)j, v);
     }
-    double2* out = reinterpret_cast<double2*>(rec + (slot_order ? s : (int64_t)t_pos[s]) * REC);
+    RT* out = rec + (slot_order ? s : (int64_t)t_pos[s]) * REC;
+    if constexpr (sizeof(RT) == 8) {
+      double2* o2 = reinterpret_cast<double2*>(out);
 #pragma unroll
-    for (int c = 0; c < REC; c += 2) out[c / 2] = make_double2(v[c], v[c + 1]);
+      for (int c = 0; c < REC; c += 2) o2[c / 2] = make_double2(v[c], v[c + 1]);
+    } else {
+      float2* o2 = reinterpret_cast<float2*>(out);
+#pragma unroll
+      for (int c = 0; c < REC; c += 2) o2[c / 2] = make_float2((float)v[c], (float)v[c + 1]);
+    }
   }
   // segmented inclusive sum over the wavefront (owners are non-decreasing)
 #pragma unroll
@@ -670,8 +706,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   hipLaunchKernelGGL(k_adj_factor, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS), 0, s, n,
                      mom, ybuf, tape, orec);
   if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
-  // FP32 pair records in the mixed form (wave-per-owner schedule only)
-  const bool rec32 = p->precision == PHB_MIXED && ctx->adj_pairs_mode == 1;
+  // FP32 pair records in the mixed form
+  const bool rec32 = p->precision == PHB_MIXED;
   if (ctx->adj_pairs_mode == 1) {
     Prof pf(ctx, "k_adj_pairs_w");
     if (rec32)
@@ -686,9 +722,15 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   } else {
     if (nnz > 0) {
       Prof pf(ctx, "k_adj_pairs");
-      hipLaunchKernelGGL(k_adj_pairs, dim3(grid_for(nnz, PAIRS_PER_BLOCK)), dim3(PAIRS_PER_BLOCK),
-                         0, s, n, nnz, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq,
-                         orec, rec, own, wpart, slot_order);
+      if (rec32)
+        hipLaunchKernelGGL((k_adj_pairs<float>), dim3(grid_for(nnz, PAIRS_PER_BLOCK)),
+                           dim3(PAIRS_PER_BLOCK), 0, s, n, nnz, geo, a.off, a.idx, t_pos, a.box,
+                           a.rf_ratio, a.wkind, fq, orec, reinterpret_cast<float*>(rec), own,
+                           wpart, slot_order);
+      else
+        hipLaunchKernelGGL((k_adj_pairs<double>), dim3(grid_for(nnz, PAIRS_PER_BLOCK)),
+                           dim3(PAIRS_PER_BLOCK), 0, s, n, nnz, geo, a.off, a.idx, t_pos, a.box,
+                           a.rf_ratio, a.wkind, fq, orec, rec, own, wpart, slot_order);
       if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
     }
     Prof pf(ctx, "k_adj_combine");
