@@ -200,28 +200,36 @@ __global__ void __launch_bounds__(THREADS)
   QuadChol c;
   quad_chol_factor(c, c_tab_a, mom, n, ii, l);
   const int st = (int)tape[(int64_t)21 * n + ii];
-  // G rows at 0..59 and K rows at 60..119 of the owner record
-  sfor<0, 6>([&](auto RH) {
-    constexpr int rh = RH;
-    double out[5];
-    if constexpr (rh < 3) {
-      quad_chol_inverse_row<1 + rh>(c, l, out);
-    } else {
-      double b[5];
-      sfor<0, 5>([&](auto R) {
-        constexpr int rho = R;
-        b[rho] = ybuf[((int64_t)(rh - 3) * NBASIS + 4 * rho + l) * n + ii];
-      });
-      quad_chol_apply_inverse(c, l, b, out);
-    }
+  // G rows at 0..59 and K rows at 60..119 of the owner record; each group of
+  // three solves runs in lockstep
+  {
+    double out[3][5];
+    quad_chol_inverse_rows<1, 3>(c, l, out);
     if (valid) {
-      sfor<0, 5>([&](auto R) {
-        constexpr int rho = R;
-        const double v = out[rho];
-        gop[(int64_t)i * OREC + rh * NBASIS + 4 * rho + l] = st == 0 ? v : 0.0;
-      });
+#pragma unroll
+      for (int rh = 0; rh < 3; ++rh)
+#pragma unroll
+        for (int rho = 0; rho < 5; ++rho)
+          gop[(int64_t)i * OREC + rh * NBASIS + 4 * rho + l] = st == 0 ? out[rh][rho] : 0.0;
     }
-  });
+  }
+  {
+    double y[3][5], out[3][5];
+#pragma unroll
+    for (int rh = 0; rh < 3; ++rh)
+#pragma unroll
+      for (int rho = 0; rho < 5; ++rho)
+        y[rh][rho] = ybuf[((int64_t)rh * NBASIS + 4 * rho + l) * n + ii] * c.s_own[rho];
+    quad_chol_solve_n<0, 3>(c, l, y, out);
+    if (valid) {
+#pragma unroll
+      for (int rh = 0; rh < 3; ++rh)
+#pragma unroll
+        for (int rho = 0; rho < 5; ++rho)
+          gop[(int64_t)i * OREC + (3 + rh) * NBASIS + 4 * rho + l] =
+              st == 0 ? out[rh][rho] * c.s_own[rho] : 0.0;
+    }
+  }
 }
 
 // ---- 4. pair contributions ---------------------------------------------------

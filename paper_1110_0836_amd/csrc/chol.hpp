@@ -171,6 +171,76 @@ __device__ __forceinline__ void quad_chol_inverse_row(const QuadChol& c, int l, 
   sfor<0, 5>([&](auto R) { out[R] = x[R] * c.s_own[R]; });
 }
 
+// NR independent solves x_r = A_hat^{-1} y_r in lockstep: each elimination
+// step serves all right-hand sides, which gives the scheduler NR independent
+// chains between the quad broadcasts.  K0 as in quad_chol_solve.
+template <int K0, int NR>
+__device__ __forceinline__ void quad_chol_solve_n(const QuadChol& c, int l, double (&y)[NR][5],
+                                                  double (&x)[NR][5]) {
+  sfor<K0, NBASIS>([&](auto K) {
+    constexpr int k = K;
+    constexpr int o = k & 3;
+    constexpr int rk = k >> 2;
+    double yk[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) yk[r] = quad_bcast<o>(y[r][rk] * c.inv_own[rk]);
+    sfor<rk + 1, 5>([&](auto R) {
+      constexpr int rho = R;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) y[r][rho] = fma(-c.a[chol_aoff(rho) + k], yk[r], y[r][rho]);
+    });
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double upd = fma(-c.a[chol_aoff(rk) + k], yk[r], y[r][rk]);
+      y[r][rk] = (l == o) ? yk[r] : ((l > o) ? upd : y[r][rk]);
+    }
+  });
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int rho = 0; rho < 5; ++rho) x[r][rho] = y[r][rho];
+  sfor<0, NBASIS>([&](auto KK) {
+    constexpr int k = NBASIS - 1 - KK;
+    constexpr int o = k & 3;
+    constexpr int rk = k >> 2;
+    double part[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) part[r] = 0.0;
+    sfor<rk + 1, 5>([&](auto R) {
+      constexpr int rho = R;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) part[r] = fma(c.a[chol_aoff(rho) + k], x[r][rho], part[r]);
+    });
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      part[r] += (l > o) ? c.a[chol_aoff(rk) + k] * x[r][rk] : 0.0;
+      part[r] = group_sum<4>(part[r]);
+      const double xk = (y[r][rk] - part[r]) * c.inv_own[rk];  // valid on the owner lane
+      x[r][rk] = (l == o) ? xk : x[r][rk];
+    }
+  });
+}
+
+// Rows T0 .. T0 + NR - 1 of A^{-1} (own entries) by one lockstep solve.
+template <int T0, int NR>
+__device__ __forceinline__ void quad_chol_inverse_rows(const QuadChol& c, int l,
+                                                       double (&out)[NR][5]) {
+  double y[NR][5];
+  sfor<0, NR>([&](auto RI) {
+    constexpr int T = T0 + RI;
+    const double sT = quad_bcast<T & 3>(c.s_own[T >> 2]);
+    sfor<0, 5>([&](auto R) {
+      constexpr int rho = R;
+      y[RI][rho] = (4 * rho + l == T) ? sT : 0.0;
+    });
+  });
+  quad_chol_solve_n<T0, NR>(c, l, y, out);
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int rho = 0; rho < 5; ++rho) out[r][rho] *= c.s_own[rho];
+}
+
 // Estimate of the 2-norm of A_hat^{-1} (the equilibrated matrix), from below
 // and in practice within a small factor: x = A_hat^{-1} e with the signs of e
 // chosen for growth as above, then one power step z = A_hat^{-1} x and

@@ -124,14 +124,17 @@ __global__ void __launch_bounds__(THREADS)
   QuadChol c;
   quad_chol_factor(c, c_tab, mom, n, ii, l);
   const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
-  sfor<0, NT>([&](auto TI) {
-    constexpr int t = 1 + TI;
-    double row[5];
-    quad_chol_inverse_row<t>(c, l, row);
+  // rows in lockstep groups of three
+  sfor<0, NT / 3>([&](auto GI) {
+    constexpr int t0 = 1 + 3 * GI;
+    double rows[3][5];
+    quad_chol_inverse_rows<t0, 3>(c, l, rows);
     if (valid) {
-      sfor<0, 5>([&](auto R) {
-        constexpr int rho = R;
-        gop[((int64_t)TI * NBASIS + 4 * rho + l) * n + i] = row[rho];
+      sfor<0, 3>([&](auto RI) {
+        sfor<0, 5>([&](auto R) {
+          constexpr int rho = R;
+          gop[((int64_t)(3 * GI + RI) * NBASIS + 4 * rho + l) * n + i] = rows[RI][rho];
+        });
       });
     }
   });
