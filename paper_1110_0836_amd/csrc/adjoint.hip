@@ -495,13 +495,21 @@ __global__ void __launch_bounds__(THREADS)
                   double* __restrict__ own, int slot_order) {
   const int i = __builtin_amdgcn_readfirstlane(xcd_block() * (THREADS / 64) + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
+  // the owner record goes to LDS in one coalesced load per wavefront; the
+  // pair terms then read it row by row at LDS latency
+  __shared__ double osh[THREADS / 64][OREC];
+  const int wv = threadIdx.x >> 6;
+  if (i < n) {
+    for (int k = lane; k < OREC; k += 64) osh[wv][k] = orec[(int64_t)i * OREC + k];
+  }
+  __syncthreads();
   if (i >= n) return;  // whole wavefronts leave together
   const int64_t rs = off[i], re = off[i + 1];
   const double4 gi = geo[i];
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
-  const double* o = orec + (int64_t)i * OREC;
+  const double* o = osh[wv];
   const double* fi = fq + 8 * (int64_t)i;
   double acc[REC];
 #pragma unroll
