@@ -53,22 +53,25 @@ def lib():
         L.orc_mls_derivs.restype = I
         L.orc_mls_derivs.argtypes = [I64, P, P, P, P, D, I, I, I64, P, P, P, I, P, P, P, P, I]
         L.orc_mhd_rhs.restype = I
-        L.orc_mhd_rhs.argtypes = [I64, P, P, P, P, D, D, I, I, I64, P, P, P, P, P, P, P, I]
+        L.orc_mhd_rhs.argtypes = [I64, P, P, P, P, D, D, I, I, I64, P, P, P, P, P, P, P, I, P]
         L.orc_mhd_rhs_cstep.restype = I
-        L.orc_mhd_rhs_cstep.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, P, P, D, P, P, P, I]
+        L.orc_mhd_rhs_cstep.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, P, P, D, P, P, P, I,
+                                       P]
         L.orc_mhd_rhs_adjoint.restype = I
-        L.orc_mhd_rhs_adjoint.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, P, P, P, P, P, I]
+        L.orc_mhd_rhs_adjoint.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, P, P, P, P, P, I,
+                                         P]
         L.orc_adjoint_sampled.restype = I
-        L.orc_adjoint_sampled.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, I64, P, P, P, I]
+        L.orc_adjoint_sampled.argtypes = [I64, P, P, P, P, D, D, I, I, P, P, P, I64, P, P, P, I,
+                                         P]
         L.orc_adjoint_rows.restype = I
         L.orc_adjoint_rows.argtypes = [I64, P, P, P, P, D, D, I, I, I64, P, P, P, P, P, P, P,
-                                       P, I]
+                                       P, I, P]
         L.orc_pc_step.restype = I
-        L.orc_pc_step.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, P, I]
+        L.orc_pc_step.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, P, I, P]
         L.orc_evolve.restype = I
-        L.orc_evolve.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, I, P, P, I]
+        L.orc_evolve.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, I, P, P, I, P]
         L.orc_courant_dt.restype = D
-        L.orc_courant_dt.argtypes = [I64, P, P, D, P, D]
+        L.orc_courant_dt.argtypes = [I64, P, P, D, P, D, P]
         _lib = L
     return _lib
 
@@ -83,6 +86,17 @@ def _p(a):
 
 def _box(L, periodic):
     return _c(L, np.float64), _c(periodic, np.int32)
+
+
+def _stab(stab):
+    """None (ideal MHD) or the stabiliser coefficients (visc_grid, visc_adapt,
+    divb_diff) as a float64 array."""
+    if stab is None:
+        return None
+    a = _c(stab, np.float64)
+    if a.shape != (3,):
+        raise ValueError("stab must hold (visc_grid, visc_adapt, divb_diff)")
+    return a
 
 
 def neighbors(pos, lam, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), rows=None, threads=0,
@@ -130,8 +144,9 @@ def mls_derivs(pos, lam, off, idx, fields, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1)
 
 
 def mhd_rhs(pos, lam, off, idx, q, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5.0 / 3.0,
-            rows=None, weight=0, fit=0, threads=0, rf_ratio=RF_RATIO):
-    """Ideal-MHD time derivatives: rhs (8,nrows), dxdt (3,nrows), status (nrows,)."""
+            rows=None, weight=0, fit=0, threads=0, rf_ratio=RF_RATIO, stab=None):
+    """MHD time derivatives: rhs (8,nrows), dxdt (3,nrows), status (nrows,).
+    stab: None (ideal) or (visc_grid, visc_adapt, divb_diff)."""
     pos = _c(pos, np.float64)
     lam = _c(lam, np.float64)
     q = _c(q, np.float64)
@@ -146,7 +161,7 @@ def mhd_rhs(pos, lam, off, idx, q, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=
     st = np.zeros(nrows, np.int32)
     rc = lib().orc_mhd_rhs(n, _p(pos), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight, fit,
                            nrows, _p(rows_a), _p(off), _p(idx), _p(q), _p(rhs), _p(dxdt), _p(st),
-                           threads)
+                           threads, _p(_stab(stab)))
     if rc != 0:
         raise ValueError("orc_mhd_rhs: invalid arguments")
     return rhs, dxdt, st
@@ -154,7 +169,7 @@ def mhd_rhs(pos, lam, off, idx, q, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=
 
 def mhd_rhs_cstep(pos, lam, off, idx, q, dpos=None, dq=None, h=1e-30, L=(1.0, 1.0, 1.0),
                   periodic=(1, 1, 1), gamma=5.0 / 3.0, weight=0, fit=0, threads=0,
-                  rf_ratio=RF_RATIO):
+                  rf_ratio=RF_RATIO, stab=None):
     """Complex-step directional derivative of the RHS along (dpos, dq): (rhs, d rhs, status)."""
     pos = _c(pos, np.float64)
     lam = _c(lam, np.float64)
@@ -168,7 +183,8 @@ def mhd_rhs_cstep(pos, lam, off, idx, q, dpos=None, dq=None, h=1e-30, L=(1.0, 1.
     st = np.zeros(n, np.int32)
     rc = lib().orc_mhd_rhs_cstep(n, _p(pos), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight,
                                  fit, _p(_c(off, np.int64)), _p(_c(idx, np.int32)), _p(q),
-                                 _p(dpos), _p(dq), h, _p(rre), _p(rdir), _p(st), threads)
+                                 _p(dpos), _p(dq), h, _p(rre), _p(rdir), _p(st), threads,
+                                 _p(_stab(stab)))
     if rc != 0:
         raise ValueError("orc_mhd_rhs_cstep: invalid arguments")
     return rre, rdir, st
@@ -176,7 +192,7 @@ def mhd_rhs_cstep(pos, lam, off, idx, q, dpos=None, dq=None, h=1e-30, L=(1.0, 1.
 
 def mhd_rhs_adjoint(pos, lam, off, idx, q, rhs_bar, dxdt_bar=None, L=(1.0, 1.0, 1.0),
                     periodic=(1, 1, 1), gamma=5.0 / 3.0, weight=0, fit=0, threads=0,
-                    rf_ratio=RF_RATIO):
+                    rf_ratio=RF_RATIO, stab=None):
     """Reverse-mode gradient (q_bar (8,n), pos_bar (3,n), status) of rhs_bar.rhs + dxdt_bar.dxdt."""
     pos = _c(pos, np.float64)
     lam = _c(lam, np.float64)
@@ -190,7 +206,8 @@ def mhd_rhs_adjoint(pos, lam, off, idx, q, rhs_bar, dxdt_bar=None, L=(1.0, 1.0, 
     st = np.zeros(n, np.int32)
     rc = lib().orc_mhd_rhs_adjoint(n, _p(pos), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight,
                                    fit, _p(_c(off, np.int64)), _p(_c(idx, np.int32)), _p(q),
-                                   _p(rb), _p(xb), _p(qbar), _p(pbar), _p(st), threads)
+                                   _p(rb), _p(xb), _p(qbar), _p(pbar), _p(st), threads,
+                                   _p(_stab(stab)))
     if rc != 0:
         raise ValueError("orc_mhd_rhs_adjoint: invalid arguments")
     return qbar, pbar, st
@@ -198,7 +215,7 @@ def mhd_rhs_adjoint(pos, lam, off, idx, q, rhs_bar, dxdt_bar=None, L=(1.0, 1.0, 
 
 def adjoint_rows(pos, lam, off, idx, q, rhs_bar, rows, dxdt_bar=None, L=(1.0, 1.0, 1.0),
                  periodic=(1, 1, 1), gamma=5.0 / 3.0, weight=0, fit=0, threads=0,
-                 rf_ratio=RF_RATIO):
+                 rf_ratio=RF_RATIO, stab=None):
     """Contributions of the owner ``rows`` (CSR restricted to them) to (q_bar, pos_bar)."""
     pos = _c(pos, np.float64)
     lam = _c(lam, np.float64)
@@ -212,7 +229,7 @@ def adjoint_rows(pos, lam, off, idx, q, rhs_bar, rows, dxdt_bar=None, L=(1.0, 1.
     rc = lib().orc_adjoint_rows(n, _p(pos), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight, fit,
                                 r.shape[0], _p(r), _p(_c(off, np.int64)), _p(_c(idx, np.int32)),
                                 _p(q), _p(_c(rhs_bar, np.float64)), _p(xb), _p(qbar), _p(pbar),
-                                threads)
+                                threads, _p(_stab(stab)))
     if rc != 0:
         raise ValueError("orc_adjoint_rows: invalid arguments")
     return qbar, pbar
@@ -220,7 +237,7 @@ def adjoint_rows(pos, lam, off, idx, q, rhs_bar, rows, dxdt_bar=None, L=(1.0, 1.
 
 def adjoint_sampled(pos, lam, q, rhs_bar, samples, dxdt_bar=None, L=(1.0, 1.0, 1.0),
                     periodic=(1, 1, 1), gamma=5.0 / 3.0, weight=0, fit=0, threads=0,
-                    rf_ratio=RF_RATIO):
+                    rf_ratio=RF_RATIO, stab=None):
     """Gradient columns (8,ns) and (3,ns) for the sampled particle indices, at any n."""
     pos = _c(pos, np.float64)
     lam = _c(lam, np.float64)
@@ -234,14 +251,14 @@ def adjoint_sampled(pos, lam, q, rhs_bar, samples, dxdt_bar=None, L=(1.0, 1.0, 1
     xb = None if dxdt_bar is None else _c(dxdt_bar, np.float64)
     rc = lib().orc_adjoint_sampled(n, _p(pos), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight,
                                    fit, _p(q), _p(_c(rhs_bar, np.float64)), _p(xb), ns, _p(s),
-                                   _p(qs), _p(ps), threads)
+                                   _p(qs), _p(ps), threads, _p(_stab(stab)))
     if rc != 0:
         raise ValueError("orc_adjoint_sampled: invalid arguments")
     return qs, ps
 
 
 def pc_step(pos, lam, q, dt, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5.0 / 3.0, weight=0,
-            fit=0, threads=0, rf_ratio=RF_RATIO):
+            fit=0, threads=0, rf_ratio=RF_RATIO, stab=None):
     """One predictor-corrector step; returns new (pos, q, status)."""
     pos = np.array(pos, dtype=np.float64, order="C", copy=True)
     q = np.array(q, dtype=np.float64, order="C", copy=True)
@@ -250,7 +267,7 @@ def pc_step(pos, lam, q, dt, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5.0 / 
     Lb, pb = _box(L, periodic)
     st = np.zeros(n, np.int32)
     rc = lib().orc_pc_step(n, _p(pos), _p(q), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight,
-                           fit, dt, _p(st), threads)
+                           fit, dt, _p(st), threads, _p(_stab(stab)))
     if rc == -1:
         raise ValueError("orc_pc_step: invalid arguments")
     if rc == -2:
@@ -259,7 +276,7 @@ def pc_step(pos, lam, q, dt, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5.0 / 
 
 
 def evolve(pos, lam, q, dt, nsteps, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5.0 / 3.0,
-           frozen=None, weight=0, fit=0, threads=0, rf_ratio=RF_RATIO):
+           frozen=None, weight=0, fit=0, threads=0, rf_ratio=RF_RATIO, stab=None):
     """nsteps predictor-corrector steps (frozen: optional mask of particles held
     fixed); returns new (pos, q, status)."""
     pos = np.array(pos, dtype=np.float64, order="C", copy=True)
@@ -270,7 +287,7 @@ def evolve(pos, lam, q, dt, nsteps, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma
     fz = None if frozen is None else _c(frozen, np.int32)
     st = np.zeros(n, np.int32)
     rc = lib().orc_evolve(n, _p(pos), _p(q), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma, weight,
-                          fit, dt, int(nsteps), _p(fz), _p(st), threads)
+                          fit, dt, int(nsteps), _p(fz), _p(st), threads, _p(_stab(stab)))
     if rc == -1:
         raise ValueError("orc_evolve: invalid arguments")
     if rc == -2:
@@ -278,12 +295,13 @@ def evolve(pos, lam, q, dt, nsteps, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma
     return pos, q, st
 
 
-def courant_dt(q, lam, cfl=0.3, gamma=5.0 / 3.0, frozen=None):
-    """cfl * min lambda / (|V| + c_fast) over non-frozen particles."""
+def courant_dt(q, lam, cfl=0.3, gamma=5.0 / 3.0, frozen=None, stab=None):
+    """cfl * min lambda / (|V| + c_fast (1 + 2 sum(stab))) over non-frozen particles."""
     q = _c(q, np.float64)
     lam = _c(lam, np.float64)
     fz = None if frozen is None else _c(frozen, np.int32)
-    dt = lib().orc_courant_dt(lam.shape[0], _p(q), _p(lam), gamma, _p(fz), cfl)
+    dt = lib().orc_courant_dt(lam.shape[0], _p(q), _p(lam), gamma, _p(fz), cfl,
+                              _p(_stab(stab)))
     if dt < 0:
         raise ValueError("orc_courant_dt: no particle to time-step")
     return dt

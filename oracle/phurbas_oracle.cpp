@@ -14,7 +14,9 @@
 //    column-scaled design matrix (a different algorithm from the GPU's
 //    normal-equation Cholesky);
 //  * the ideal-MHD Lagrangian time derivatives from the fitted gradients
-//    (Sec. 2; the evolution equations of App. A with zero viscosity);
+//    (Sec. 2; the evolution equations of App. A with zero viscosity), and
+//    optionally the non-ideal stabilisers of Sec. 2 (bulk viscosity and div-B
+//    diffusion, from the fitted second derivatives);
 //  * the second-order predictor-corrector step (Sec. 2);
 //  * reverse-mode derivatives of the time derivatives (hand-derived matrix
 //    calculus in full 20x20 form) and a complex-step forward evaluation used
@@ -59,6 +61,10 @@ struct Setup {
   double gamma;     // adiabatic index
   int weight;       // 0: (1-q)^3 with q = d^2 / r_f^2 ; 1: unit weight
   int fit;          // 0: full 20-monomial fit; 1: 19-monomial interpolating fit
+  // Non-ideal stabilisers (Sec. 2): coefficients of the grid-scale and the
+  // adaptive bulk viscosity and of the div-B diffusion; all zero is ideal MHD.
+  double visc_grid = 0.0, visc_adapt = 0.0, divb_diff = 0.0;
+  bool stabilised() const { return visc_grid != 0.0 || visc_adapt != 0.0 || divb_diff != 0.0; }
 };
 
 // Minimum-image displacement along one axis: subtract or add one box length
@@ -404,9 +410,93 @@ void mhd_point_adjoint(const double* qv, const double grad[8][3], double gamma,
   for (int b = 0; b < 3; ++b) gb[7][b] += gS_b[b];
 }
 
+// Second-derivative index of d2/dx_a dx_b in the (xx, xy, xz, yy, yz, zz) order.
+const int HIDX[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+
+// Non-ideal stabilising terms at one particle, added to out.  Sec. 2 names
+// them (a bulk viscosity split into a grid-scale and an adaptive coefficient
+// field, and a diffusive div-B correction in the induction equation); App. A
+// fixes the viscous term, grad(zeta div V) per unit mass, which for constant
+// zeta damps compressive modes at the rate zeta k^2 / 2.  The coefficient
+// formulas live in the companion paper, which is not available; readings:
+//   c_f   = sqrt((gamma P + B^2) / rho)                   fast speed
+//   zeta  = lambda c_f (visc_grid + visc_adapt min(1, (lambda |grad rho| / rho)^2))
+//   eta   = divb_diff lambda c_f
+//   dV/dt     += zeta grad(div V)
+//   dB/dt     += eta  grad(div B)
+//   dsigma/dt += rho zeta (div V)^2                      viscous heating
+// with zeta and eta held constant over the neighborhood (App. A's constant-
+// coefficient form; a grad zeta term would need a second neighbor pass).
+// gdiv[0][a] = d_a div V, gdiv[1][a] = d_a div B; grad[f][b] = d q_f / d x_b.
+template <class T>
+void stab_point(const T* qv, const T grad[8][3], const T gdiv[2][3], double lam, const Setup& s,
+                T* out) {
+  const T rho = qv[0], sig = qv[7];
+  const T b2 = qv[4] * qv[4] + qv[5] * qv[5] + qv[6] * qv[6];
+  const T cf = sqrt((s.gamma * (s.gamma - 1.0) * sig + b2) / rho);
+  const T gr2 = grad[0][0] * grad[0][0] + grad[0][1] * grad[0][1] + grad[0][2] * grad[0][2];
+  const T s2 = lam * lam * gr2 / (rho * rho);
+  const T sat = re(s2) < 1.0 ? s2 : T(1.0);
+  const T zeta = lam * cf * (s.visc_grid + s.visc_adapt * sat);
+  const T eta = s.divb_diff * lam * cf;
+  const T divV = grad[1][0] + grad[2][1] + grad[3][2];
+  for (int a = 0; a < 3; ++a) {
+    out[1 + a] += zeta * gdiv[0][a];
+    out[4 + a] += eta * gdiv[1][a];
+  }
+  out[7] += rho * zeta * divV * divV;
+}
+
+// Reverse mode of stab_point: accumulates into qb (8), gb[8][3] (adjoint of
+// grad) and gdb[2][3] (adjoint of gdiv).  min(1, s2) passes no derivative
+// where it is saturated (s2 >= 1).
+void stab_point_adjoint(const double* qv, const double grad[8][3], const double gdiv[2][3],
+                        double lam, const Setup& s, const double* ob, double* qb,
+                        double gb[8][3], double gdb[2][3]) {
+  const double g = s.gamma;
+  const double rho = qv[0], sig = qv[7];
+  const double B[3] = {qv[4], qv[5], qv[6]};
+  const double N = g * (g - 1.0) * sig + B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  const double cf = std::sqrt(N / rho);
+  const double gr2 = grad[0][0] * grad[0][0] + grad[0][1] * grad[0][1] + grad[0][2] * grad[0][2];
+  const double s2 = lam * lam * gr2 / (rho * rho);
+  const double sat = s2 < 1.0 ? s2 : 1.0;
+  const double zeta = lam * cf * (s.visc_grid + s.visc_adapt * sat);
+  const double eta = s.divb_diff * lam * cf;
+  const double divV = grad[1][0] + grad[2][1] + grad[3][2];
+  double zeta_b = ob[7] * rho * divV * divV, eta_b = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    zeta_b += ob[1 + a] * gdiv[0][a];
+    eta_b += ob[4 + a] * gdiv[1][a];
+    gdb[0][a] += zeta * ob[1 + a];
+    gdb[1][a] += eta * ob[4 + a];
+  }
+  qb[0] += ob[7] * zeta * divV * divV;
+  const double divV_b = ob[7] * 2.0 * rho * zeta * divV;
+  gb[1][0] += divV_b;
+  gb[2][1] += divV_b;
+  gb[3][2] += divV_b;
+  const double cf_b = zeta_b * lam * (s.visc_grid + s.visc_adapt * sat) + eta_b * s.divb_diff * lam;
+  if (s2 < 1.0) {
+    const double s2_b = zeta_b * lam * cf * s.visc_adapt;
+    for (int b = 0; b < 3; ++b) gb[0][b] += s2_b * 2.0 * lam * lam * grad[0][b] / (rho * rho);
+    qb[0] += s2_b * (-2.0 * s2 / rho);
+  }
+  // cf = sqrt(N / rho)
+  const double N_b = cf_b / (2.0 * cf * rho);
+  qb[0] += -cf_b * cf / (2.0 * rho);
+  qb[7] += N_b * g * (g - 1.0);
+  for (int a = 0; a < 3; ++a) qb[4 + a] += N_b * 2.0 * B[a];
+}
+
 Setup make_setup(const double* L, const int32_t* periodic, double rf_ratio, double gamma,
-                 int weight, int fit) {
+                 int weight, int fit, const double* stab = nullptr) {
   Setup s;
+  if (stab) {
+    s.visc_grid = stab[0];
+    s.visc_adapt = stab[1];
+    s.divb_diff = stab[2];
+  }
   for (int a = 0; a < 3; ++a) {
     s.L[a] = L[a];
     s.periodic[a] = periodic[a];
@@ -465,9 +555,10 @@ template <class T>
 void rhs_particle(int64_t n, int64_t i, const T* pos, const double* lambda, const int32_t* nb,
                   int m, const T* q, const Setup& s, T* rhs /* 8 */, T* dxdt /* 3 */,
                   int32_t* status) {
-  T d1[8 * 3];
-  int st = fit_particle<T>(n, i, pos, lambda, nb, m, 8, q, s, d1, nullptr, nullptr, nullptr,
-                           nullptr);
+  T d1[8 * 3], d2[8 * 6];
+  const bool stab = s.stabilised();
+  int st = fit_particle<T>(n, i, pos, lambda, nb, m, 8, q, s, d1, stab ? d2 : nullptr, nullptr,
+                           nullptr, nullptr);
   *status = st;
   T qv[8];
   for (int f = 0; f < 8; ++f) qv[f] = q[f * n + i];
@@ -480,6 +571,17 @@ void rhs_particle(int64_t n, int64_t i, const T* pos, const double* lambda, cons
   for (int f = 0; f < 8; ++f)
     for (int a = 0; a < 3; ++a) grad[f][a] = d1[f * 3 + a];
   mhd_point(qv, grad, s.gamma, rhs);
+  if (stab) {
+    // d_a div V = sum_b d2 V_b / dx_a dx_b ;  likewise for B
+    T gdiv[2][3];
+    for (int g = 0; g < 2; ++g)
+      for (int a = 0; a < 3; ++a) {
+        T acc = T(0.0);
+        for (int b = 0; b < 3; ++b) acc += d2[(1 + 3 * g + b) * 6 + HIDX[a][b]];
+        gdiv[g][a] = acc;
+      }
+    stab_point(qv, grad, gdiv, lambda[i], s, rhs);
+  }
 }
 
 // Local reverse-mode contributions of particle i.  For each neighbor slot k
@@ -509,8 +611,10 @@ void adjoint_particle(int64_t n, int64_t i, const double* pos, const double* lam
   Local<double> loc;
   QR<double> qr;
   std::vector<double> coef;  // 20 x 8
-  double d1[8 * 3];
-  int st = fit_particle<double>(n, i, pos, lambda, nb, m, 8, q, s, d1, nullptr, &loc, &qr, &coef);
+  double d1[8 * 3], d2[8 * 6];
+  const bool stab = s.stabilised();
+  int st = fit_particle<double>(n, i, pos, lambda, nb, m, 8, q, s, d1, stab ? d2 : nullptr, &loc,
+                                &qr, &coef);
   out.status = st;
   if (st != 0) return;  // NaN outputs: no gradient flows through them
 
@@ -526,11 +630,31 @@ void adjoint_particle(int64_t n, int64_t i, const double* pos, const double* lam
   // 1. pointwise adjoint
   double gb[8][3] = {{0}};
   mhd_point_adjoint(qv, grad, s.gamma, gbar, out.qb_self, gb);
+  double d2b[8][6] = {{0}};
+  if (stab) {
+    double gdiv[2][3], gdb[2][3] = {{0}};
+    for (int g = 0; g < 2; ++g)
+      for (int a = 0; a < 3; ++a) {
+        double acc = 0.0;
+        for (int b = 0; b < 3; ++b) acc += d2[(1 + 3 * g + b) * 6 + HIDX[a][b]];
+        gdiv[g][a] = acc;
+      }
+    stab_point_adjoint(qv, grad, gdiv, lam, s, gbar, out.qb_self, gb, gdb);
+    for (int g = 0; g < 2; ++g)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) d2b[1 + 3 * g + b][HIDX[a][b]] += gdb[g][a];
+  }
 
-  // 2. grad = E C / lambda  =>  Cbar (20 x F) has rows 1..3 = gb^T / lambda
+  // 2. grad = E C / lambda  =>  Cbar (20 x F) has rows 1..3 = gb^T / lambda;
+  //    second derivatives fac C_(ab) / lambda^2 give rows 4..9
   std::vector<double> Cbar(20 * F, 0.0);
   for (int a = 0; a < 3; ++a)
     for (int f = 0; f < F; ++f) Cbar[(1 + a) * F + f] = gb[f][a] / lam;
+  if (stab) {
+    const double fac[6] = {2.0, 1.0, 1.0, 2.0, 1.0, 2.0};
+    for (int k = 0; k < 6; ++k)
+      for (int f = 0; f < F; ++f) Cbar[(4 + k) * F + f] = fac[k] * d2b[f][k] / (lam * lam);
+  }
 
   // 3. C = A^{-1} Bm  =>  Bbar = A^{-1} Cbar ;  Abar = -Bbar C^T
   std::vector<double> Ainv(400, 0.0);
@@ -666,14 +790,17 @@ int orc_mls_derivs(int64_t n, const double* pos, const double* lambda, const dou
   return 0;
 }
 
-// Ideal-MHD time derivatives for the listed rows.  rhs: [8][nrows],
-// dxdt: [3][nrows], status: [nrows].
+// MHD time derivatives for the listed rows.  rhs: [8][nrows],
+// dxdt: [3][nrows], status: [nrows].  stab: NULL (ideal MHD) or the three
+// stabiliser coefficients (visc_grid, visc_adapt, divb_diff) of stab_point.
+// Every entry point below that takes stab reads it the same way.
 int orc_mhd_rhs(int64_t n, const double* pos, const double* lambda, const double* L,
                 const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
                 int64_t nrows, const int64_t* rows, const int64_t* offsets, const int32_t* idx,
-                const double* q, double* rhs, double* dxdt, int32_t* status, int nthreads) {
+                const double* q, double* rhs, double* dxdt, int32_t* status, int nthreads,
+                const double* stab) {
   if (n <= 0 || !pos || !lambda || !offsets || !idx || !q || !rhs || !dxdt || !status) return -1;
-  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit, stab);
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #pragma omp parallel for schedule(dynamic, 8)
   for (int64_t r = 0; r < nrows; ++r) {
@@ -696,9 +823,9 @@ int orc_mhd_rhs_cstep(int64_t n, const double* pos, const double* lambda, const 
                       const int32_t* periodic, double rf_ratio, double gamma, int weight,
                       int fit, const int64_t* offsets, const int32_t* idx, const double* q,
                       const double* dpos, const double* dq, double h, double* rhs_re,
-                      double* rhs_dir, int32_t* status, int nthreads) {
+                      double* rhs_dir, int32_t* status, int nthreads, const double* stab) {
   if (n <= 0 || !pos || !lambda || !offsets || !idx || !q || !rhs_re || !rhs_dir) return -1;
-  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit, stab);
   if (nthreads > 0) omp_set_num_threads(nthreads);
   std::vector<cd> cpos(3 * n), cq(8 * n);
   for (int64_t k = 0; k < 3 * n; ++k) cpos[k] = cd(pos[k], dpos ? h * dpos[k] : 0.0);
@@ -726,10 +853,10 @@ int orc_mhd_rhs_adjoint(int64_t n, const double* pos, const double* lambda, cons
                         const int32_t* periodic, double rf_ratio, double gamma, int weight,
                         int fit, const int64_t* offsets, const int32_t* idx, const double* q,
                         const double* rhs_bar, const double* dxdt_bar, double* q_bar,
-                        double* pos_bar, int32_t* status, int nthreads) {
+                        double* pos_bar, int32_t* status, int nthreads, const double* stab) {
   if (n <= 0 || !pos || !lambda || !offsets || !idx || !q || !rhs_bar || !q_bar || !pos_bar)
     return -1;
-  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit, stab);
   if (nthreads > 0) omp_set_num_threads(nthreads);
   std::vector<LocalAdj> all(n);
 #pragma omp parallel for schedule(dynamic, 8)
@@ -766,10 +893,11 @@ int orc_adjoint_rows(int64_t n, const double* pos, const double* lambda, const d
                      const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
                      int64_t nrows, const int64_t* rows, const int64_t* offsets,
                      const int32_t* idx, const double* q, const double* rhs_bar,
-                     const double* dxdt_bar, double* q_bar, double* pos_bar, int nthreads) {
+                     const double* dxdt_bar, double* q_bar, double* pos_bar, int nthreads,
+                     const double* stab) {
   if (n <= 0 || nrows <= 0 || !rows || !offsets || !idx || !q || !rhs_bar || !q_bar || !pos_bar)
     return -1;
-  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit, stab);
   if (nthreads > 0) omp_set_num_threads(nthreads);
   std::vector<LocalAdj> all(nrows);
 #pragma omp parallel for schedule(dynamic, 8)
@@ -807,9 +935,9 @@ int orc_adjoint_sampled(int64_t n, const double* pos, const double* lambda, cons
                         const int32_t* periodic, double rf_ratio, double gamma, int weight,
                         int fit, const double* q, const double* rhs_bar,
                         const double* dxdt_bar, int64_t nsamp, const int64_t* samples,
-                        double* q_bar_s, double* pos_bar_s, int nthreads) {
+                        double* q_bar_s, double* pos_bar_s, int nthreads, const double* stab) {
   if (n <= 0 || nsamp <= 0 || !samples || !q_bar_s || !pos_bar_s) return -1;
-  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit, stab);
   if (nthreads > 0) omp_set_num_threads(nthreads);
   for (int64_t t = 0; t < nsamp; ++t) {
     const int64_t jt = samples[t];
@@ -865,25 +993,26 @@ int orc_adjoint_sampled(int64_t n, const double* pos, const double* lambda, cons
 static int pc_step_masked(int64_t n, double* pos, double* q, const double* lambda,
                           const double* L, const int32_t* periodic, double rf_ratio, double gamma,
                           int weight, int fit, double dt, const int32_t* frozen, int32_t* status,
-                          int nthreads);
+                          int nthreads, const double* stab);
 
 int orc_pc_step(int64_t n, double* pos, double* q, const double* lambda, const double* L,
                 const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
-                double dt, int32_t* status, int nthreads) {
+                double dt, int32_t* status, int nthreads, const double* stab) {
   return pc_step_masked(n, pos, q, lambda, L, periodic, rf_ratio, gamma, weight, fit, dt,
-                        nullptr, status, nthreads);
+                        nullptr, status, nthreads, stab);
 }
 
 // nsteps steps of size dt; status = the largest over all stages and steps
 // (0 for frozen particles).
 int orc_evolve(int64_t n, double* pos, double* q, const double* lambda, const double* L,
                const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
-               double dt, int nsteps, const int32_t* frozen, int32_t* status, int nthreads) {
+               double dt, int nsteps, const int32_t* frozen, int32_t* status, int nthreads,
+               const double* stab) {
   if (n <= 0 || !pos || !q || !lambda || nsteps < 0) return -1;
   std::vector<int32_t> st(n, 0), acc(n, 0);
   for (int k = 0; k < nsteps; ++k) {
     int rc = pc_step_masked(n, pos, q, lambda, L, periodic, rf_ratio, gamma, weight, fit, dt,
-                            frozen, st.data(), nthreads);
+                            frozen, st.data(), nthreads, stab);
     if (rc) return rc;
     for (int64_t i = 0; i < n; ++i) acc[i] = std::max(acc[i], st[i]);
   }
@@ -892,11 +1021,16 @@ int orc_evolve(int64_t n, double* pos, double* q, const double* lambda, const do
   return 0;
 }
 
-// Courant step: cfl * min over non-frozen particles of lambda / (|V| + c_f),
+// Courant step: cfl * min over non-frozen particles of
+//   lambda / (|V| + c_f (1 + 2 (visc_grid + visc_adapt + divb_diff))),
 // c_f = sqrt((gamma P + B^2) / rho) with P = (gamma - 1) sigma (reading: the
-// paper's own criteria are in its companion paper).  Returns -1 if none.
+// paper's own criteria are in its companion paper).  The stabilisers'
+// diffusivities zeta, eta <= lambda c_f (coefficients) enter as the speed
+// 2 (zeta + eta) / lambda at their largest, so the step stays pointwise.
+// Returns -1 if no particle qualifies.
 double orc_courant_dt(int64_t n, const double* q, const double* lambda, double gamma,
-                      const int32_t* frozen, double cfl) {
+                      const int32_t* frozen, double cfl, const double* stab) {
+  const double csum = stab ? stab[0] + stab[1] + stab[2] : 0.0;
   double best = -1.0;
   for (int64_t i = 0; i < n; ++i) {
     if (frozen && frozen[i]) continue;
@@ -906,7 +1040,7 @@ double orc_courant_dt(int64_t n, const double* q, const double* lambda, double g
                       q[6 * n + i] * q[6 * n + i];
     const double P = (gamma - 1.0) * q[7 * n + i];
     const double cf = std::sqrt((gamma * P + b2) / rho);
-    const double t = lambda[i] / (std::sqrt(v2) + cf);
+    const double t = lambda[i] / (std::sqrt(v2) + cf * (1.0 + 2.0 * csum));
     if (std::isnan(t)) continue;
     if (best < 0.0 || t < best) best = t;
   }
@@ -916,9 +1050,9 @@ double orc_courant_dt(int64_t n, const double* q, const double* lambda, double g
 static int pc_step_masked(int64_t n, double* pos, double* q, const double* lambda,
                           const double* L, const int32_t* periodic, double rf_ratio, double gamma,
                           int weight, int fit, double dt, const int32_t* frozen, int32_t* status,
-                          int nthreads) {
+                          int nthreads, const double* stab) {
   if (n <= 0 || !pos || !q || !lambda) return -1;
-  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit);
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit, stab);
   if (nthreads > 0) omp_set_num_threads(nthreads);
   auto wrap = [&](std::vector<double>& x) -> bool {
     bool ok = true;
@@ -943,7 +1077,7 @@ static int pc_step_masked(int64_t n, double* pos, double* q, const double* lambd
     orc_neighbors(n, x.data(), lambda, L, periodic, rf_ratio, n, nullptr, off.data(), nb.data(),
                   nnz, nthreads);
     orc_mhd_rhs(n, x.data(), lambda, L, periodic, rf_ratio, gamma, weight, fit, n, nullptr,
-                off.data(), nb.data(), qq.data(), fq.data(), fx.data(), st.data(), nthreads);
+                off.data(), nb.data(), qq.data(), fq.data(), fx.data(), st.data(), nthreads, stab);
   };
   std::vector<double> x0(pos, pos + 3 * n), q0(q, q + 8 * n);
   std::vector<double> f0(8 * n), v0(3 * n), f1(8 * n), v1(3 * n);
