@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU oracle sample")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-stab", action="store_true",
+                    help="skip the forward timing with the non-ideal stabilisers on")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain "
                          "copy of known size, to calibrate hardware byte counters)")
@@ -333,6 +335,36 @@ def main():
                                                  for k, v in kern.items()))
         results[form] = r
 
+    # the same forward evaluation with the non-ideal stabilisers (bulk
+    # viscosity, div-B diffusion) switched on: nine operator rows instead of three
+    stab = None
+    if not args.no_stab:
+        stab = {"coefficients": {"visc_grid": 0.5, "visc_adapt": 0.5, "divb_diff": 0.5}}
+        for form in forms:
+            for k, v in defaults.items():
+                P.phb_tune_set(k, v)
+            ss = P.Setup(L=c["L"], periodic=c["periodic"], gamma=c["gamma"],
+                         precision=P.PHB_MIXED if form == "mixed" else P.PHB_FP64,
+                         **stab["coefficients"])
+
+            def fwd_stab():
+                P.phb_mhd_rhs(ss, pos, lam, off, idx, q, rhs, dxdt, st, tape)
+
+            for _ in range(args.warmup):
+                fwd_stab()
+            ms = time_gpu(fwd_stab, max(3, args.steps // 2), torch)
+            r = {"forward_ms": ms, "forward_updates_per_s": n / (ms / 1e3),
+                 "failed_particles": int((st != 0).sum().item())}
+            if not args.no_profile:
+                P.phb_profile(True)
+                for _ in range(3):
+                    fwd_stab()
+                prof = P.phb_profile_read()
+                P.phb_profile(False)
+                r["kernels_ms"] = {k: v[0] / v[1] for k, v in prof.items()}
+            stab[form] = r
+            log(f"[{form}] stabilised forward {ms:.3f} ms")
+
     # deviation of the mixed form from the FP64 form (both on this GPU)
     deviation = None
     if "mixed" in results and "fp64" in results:
@@ -439,6 +471,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched_graph": batch,
+        "stabilised_forward": stab,
         "extra": {"neighbor_build_ms": nb_ms, "transpose_ms": tr_ms,
                   "spatial_order_setup_ms": order_ms, "source_digest": source_digest()},
     }

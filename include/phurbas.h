@@ -86,6 +86,20 @@ typedef struct {
   int32_t precision;    /* PHB_FP64 or PHB_MIXED */
   int32_t weight;       /* PHB_W_POLY3 or PHB_W_UNIT */
   int32_t fit;          /* PHB_FIT_FULL20 */
+  /* Non-ideal stabilisers (Sec. 2: a bulk viscosity with a grid-scale and an
+   * adaptive coefficient field, and a diffusive div-B term in the induction
+   * equation; App. A: the viscous acceleration grad(zeta div V)).  All zero
+   * (the default) is ideal MHD.  With c_f = sqrt((gamma P + B^2) / rho) and
+   * s = min(1, (lambda |grad rho| / rho)^2):
+   *   zeta = lambda c_f (visc_grid + visc_adapt s),  eta = divb_diff lambda c_f,
+   *   dV/dt += zeta grad div V,  dB/dt += eta grad div B,
+   *   dsigma/dt += rho zeta (div V)^2,
+   * zeta and eta held constant over each neighborhood.  Each must be finite
+   * and >= 0 (else PHB_EINVAL).  The forward calls support them in both
+   * precisions; the reverse mode returns PHB_ENOTIMPL when any is nonzero. */
+  double visc_grid;
+  double visc_adapt;
+  double divb_diff;
 } phb_params;
 
 /* ---- context ------------------------------------------------------------
@@ -198,9 +212,11 @@ int phb_evolve(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, int32_t 
                int64_t* offsets, int32_t* idx, int64_t idx_capacity, int64_t* nnz_out,
                int32_t* status);
 /* Courant time step: *dt_out (host) = cfl * min over non-frozen i of
- * lambda_i / (|V_i| + c_f,i), with the fast-speed bound
- * c_f = sqrt((gamma P + |B|^2) / rho), P = (gamma - 1) sigma (the paper's own
- * time-step criteria live in its companion paper).  NaN entries are skipped.
+ * lambda_i / (|V_i| + c_f,i (1 + 2 (visc_grid + visc_adapt + divb_diff))),
+ * with the fast-speed bound c_f = sqrt((gamma P + |B|^2) / rho),
+ * P = (gamma - 1) sigma (the paper's own time-step criteria live in its
+ * companion paper); the stabilisers' diffusivities enter at their largest as
+ * the speed 2 (zeta + eta) / lambda.  NaN entries are skipped.
  * EINVAL if every particle is frozen or cfl <= 0.  Synchronizes. */
 int phb_courant_dt(phb_ctx* ctx, const phb_params* p, int64_t n, const double* q,
                    const double* lambda, const int32_t* frozen, double cfl, double* dt_out);

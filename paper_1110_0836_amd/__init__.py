@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_double * 3), ("periodic", ctypes.c_int32 * 3),
                 ("gamma", ctypes.c_double), ("rf_ratio", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("weight", ctypes.c_int32),
-                ("fit", ctypes.c_int32)]
+                ("fit", ctypes.c_int32), ("visc_grid", ctypes.c_double),
+                ("visc_adapt", ctypes.c_double), ("divb_diff", ctypes.c_double)]
 
 
 class BatchIO(ctypes.Structure):
@@ -72,6 +73,16 @@ class Setup:
     precision: int = PHB_FP64
     weight: int = PHB_W_POLY3
     fit: int = PHB_FIT_FULL20
+    # non-ideal stabilisers (all zero: ideal MHD); see phb_params
+    visc_grid: float = 0.0
+    visc_adapt: float = 0.0
+    divb_diff: float = 0.0
+
+    @property
+    def stab(self):
+        """(visc_grid, visc_adapt, divb_diff), or None when all are zero."""
+        t = (float(self.visc_grid), float(self.visc_adapt), float(self.divb_diff))
+        return t if any(t) else None
 
     def params(self) -> Params:
         p = Params()
@@ -83,6 +94,9 @@ class Setup:
         p.precision = int(self.precision)
         p.weight = int(self.weight)
         p.fit = int(self.fit)
+        p.visc_grid = float(self.visc_grid)
+        p.visc_adapt = float(self.visc_adapt)
+        p.divb_diff = float(self.divb_diff)
         return p
 
 

@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(THREADS)
   const int ii = valid ? i : n - 1;
   const double4 gi = geo[ii];
   const double inv_lam = 1.0 / gi.w;
-  const int st = (int)tape[(int64_t)21 * n + ii];
+  const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
   // Ubar (21 doubles) waits in LDS during the neighbor loop instead of in
   // every lane's registers; ush[k][pl] holds entries 2k, 2k+1.
   constexpr int PPB = THREADS / G;
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(THREADS)
   const int ii = valid ? i : n - 1;
   QuadChol c;
   quad_chol_factor(c, c_tab_a, mom, n, ii, l);
-  const int st = (int)tape[(int64_t)21 * n + ii];
+  const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
   // G rows at 0..59 and K rows at 60..119 of the owner record; each group of
   // three solves runs in lockstep
   {
@@ -628,6 +628,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
                 const double* tape_in, int64_t nnz_known) {
   (void)t_src;
   const int n = a.n;
+  if (stab_of(p).on())
+    return set_error(ctx, PHB_ENOTIMPL, "reverse mode of the stabilised time derivatives");
   // nnz sizes the pair records: unless the caller knows it, read offsets[n]
   // back (a synchronization, so captured callers pass it).
   int rc;
@@ -698,7 +700,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
       return rc;
     if ((rc = hip_check(ctx, launch_factor(s, ap, 3, tmom, fg, st), "adjoint factor"))) return rc;
     if ((rc = hip_check(ctx,
-                        launch_apply_rhs(s, ap, ctx->lanes_apply, p->gamma, fg, st, q, rs, dx, tp),
+                        launch_apply_rhs(s, ap, ctx->lanes_apply, p->gamma, Stab(), fg, st, rs,
+                                         dx, tp),
                         "adjoint forward")))
       return rc;
     tape = tp;

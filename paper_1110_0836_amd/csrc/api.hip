@@ -78,7 +78,22 @@ int check_params(phb_ctx* ctx, const phb_params* p) {
   if (p->weight != PHB_W_POLY3 && p->weight != PHB_W_UNIT)
     return set_error(ctx, PHB_EINVAL, "unknown weight");
   if (p->fit != PHB_FIT_FULL20) return set_error(ctx, PHB_ENOTIMPL, "only the 20-monomial fit");
+  for (double c : {p->visc_grid, p->visc_adapt, p->divb_diff})
+    if (!(c >= 0.0) || !isfinite(c))
+      return set_error(ctx, PHB_EINVAL, "stabiliser coefficients must be finite and >= 0");
   return PHB_OK;
+}
+
+static_assert(offsetof(phb_params, gamma) == 40 && offsetof(phb_params, visc_grid) == 72 &&
+                  sizeof(phb_params) == 96,
+              "phb_params layout");
+
+Stab stab_of(const phb_params* p) {
+  Stab sb;
+  sb.grid = p->visc_grid;
+  sb.adapt = p->visc_adapt;
+  sb.divb = p->divb_diff;
+  return sb;
 }
 
 int check_n(phb_ctx* ctx, int64_t n) {
@@ -161,7 +176,7 @@ static void plan_neighbors(Workspace& ws, int64_t n, int64_t idx_capacity) {
   ws.plan((size_t)std::max<int64_t>(idx_capacity, 1) * sizeof(int32_t));  // unsorted rows
 }
 
-static void plan_rhs(Workspace& ws, int64_t n, int precision);
+static void plan_rhs(Workspace& ws, int64_t n, int precision, bool stab);
 
 size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity) {
   phb_ctx dummy;
@@ -170,20 +185,20 @@ size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity) {
   return ws.total;
 }
 
-size_t ws_bytes_rhs(int64_t n, int precision) {
+size_t ws_bytes_rhs(int64_t n, const phb_params* p) {
   phb_ctx dummy;
   Workspace ws(&dummy);
-  plan_rhs(ws, n, precision);
+  plan_rhs(ws, n, p->precision, stab_of(p).on());
   return ws.total;
 }
 
-static void plan_rhs(Workspace& ws, int64_t n, int precision) {
+static void plan_rhs(Workspace& ws, int64_t n, int precision, bool stab) {
   if (precision == PHB_MIXED) {
-    ws.plan(mixed_rhs_bytes(n));
+    ws.plan(mixed_rhs_bytes(n, stab));
     return;
   }
   ws.plan((size_t)NMOM * n * sizeof(double));
-  ws.plan((size_t)3 * NBASIS * n * sizeof(double));
+  ws.plan((size_t)(stab ? 9 : 3) * NBASIS * n * sizeof(double));
   ws.plan((size_t)n * sizeof(double4));
   ws.plan((size_t)n * 8 * sizeof(double));
 }
@@ -191,15 +206,18 @@ static void plan_rhs(Workspace& ws, int64_t n, int precision) {
 // The time derivatives in the form p->precision asks for (FP64 here).
 int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double* q, double* rhs,
              double* dxdt, int32_t* status, double* tape) {
-  if (p->precision == PHB_MIXED) return mixed_rhs(ctx, a0, p->gamma, q, rhs, dxdt, status, tape);
+  const Stab sb = stab_of(p);
+  if (p->precision == PHB_MIXED)
+    return mixed_rhs(ctx, a0, p->gamma, sb, q, rhs, dxdt, status, tape);
   EvalArgs a = a0;
   const int n = a.n;
+  const int nrows = sb.on() ? 9 : 3;
   int rc;
   Workspace ws(ctx);
-  plan_rhs(ws, n, PHB_FP64);
+  plan_rhs(ws, n, PHB_FP64, sb.on());
   if ((rc = ws.commit())) return rc;
   double* mom = ws.take<double>((size_t)NMOM * n);
-  double* gop = ws.take<double>((size_t)3 * NBASIS * n);
+  double* gop = ws.take<double>((size_t)nrows * NBASIS * n);
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
   // with a tape, the moments go straight into it for the reverse mode
@@ -212,12 +230,12 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   { Prof pf(ctx, "k_moments");
   if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
     return rc; }
-  { Prof pf(ctx, "k_factor<3>");
-  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, 3, mom, gop, status), "factor")))
+  { Prof pf(ctx, nrows == 9 ? "k_factor<9>" : "k_factor<3>");
+  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, nrows, mom, gop, status), "factor")))
     return rc; }
-  Prof pf(ctx, "k_apply_rhs");
+  Prof pf(ctx, nrows == 9 ? "k_apply_rhs<stab>" : "k_apply_rhs");
   return hip_check(ctx,
-                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, gop, status, q,
+                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, sb, gop, status,
                                     rhs, dxdt, tape),
                    "apply rhs");
 }

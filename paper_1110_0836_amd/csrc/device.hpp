@@ -232,12 +232,28 @@ __device__ __forceinline__ double quad_xor2(double v) { return dpp_f64<QP_XOR2>(
 template <>
 __device__ __forceinline__ float quad_xor2(float v) { return dpp_f32<QP_XOR2>(v); }
 
-// Sum over the G consecutive lanes of a group (G = 1, 2 or 4); every lane of
-// the group receives the total.
+// DPP row controls: lane l of each 8-lane half row reads lane 7 - l; of each
+// 16-lane row, lane 15 - l.
+constexpr int ROW_HALF_MIRROR = 0x141;
+constexpr int ROW_MIRROR = 0x140;
+
+// Sum over the G consecutive lanes of a group (G = 1, 2, 4, 8 or 16); every
+// lane of the group receives the total.  Past the quad, a mirror step pairs
+// each lane with one of the other half of its group, whose partial sum is
+// already complete.
 template <int G, class T>
 __device__ __forceinline__ T group_sum(T v) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group of 1..16 lanes");
   if constexpr (G >= 2) v += quad_xor1(v);
   if constexpr (G >= 4) v += quad_xor2(v);
+  if constexpr (G >= 8) {
+    if constexpr (sizeof(T) == 8) v += dpp_f64<ROW_HALF_MIRROR>(v);
+    else v += dpp_f32<ROW_HALF_MIRROR>(v);
+  }
+  if constexpr (G >= 16) {
+    if constexpr (sizeof(T) == 8) v += dpp_f64<ROW_MIRROR>(v);
+    else v += dpp_f32<ROW_MIRROR>(v);
+  }
   return v;
 }
 

@@ -10,6 +10,7 @@
 
 #include "phurbas.h"
 #include "device.hpp"
+#include "mhd.hpp"
 
 struct phb_ctx {
   int device = 0;
@@ -47,6 +48,8 @@ namespace phb {
 int set_error(phb_ctx* ctx, int code, const std::string& msg);
 int check_params(phb_ctx* ctx, const phb_params* p);
 int check_n(phb_ctx* ctx, int64_t n);
+// The stabiliser coefficients of p (all zero: ideal MHD).
+Stab stab_of(const phb_params* p);
 int hip_check(phb_ctx* ctx, hipError_t e, const char* what);
 
 // Carves 256-byte aligned pieces out of the context arena.  Sizes are summed
@@ -102,7 +105,7 @@ Box make_box(const phb_params* p);
 // Workspace bytes of the composite entry points (used to reserve ahead of
 // nested calls).
 size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity);
-size_t ws_bytes_rhs(int64_t n, int precision);
+size_t ws_bytes_rhs(int64_t n, const phb_params* p);
 
 inline unsigned grid_for(int64_t work, int block) {
   int64_t g = (work + block - 1) / block;

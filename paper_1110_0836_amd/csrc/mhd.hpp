@@ -97,4 +97,99 @@ __device__ __forceinline__ void mhd_point_adjoint(const double (&q)[8],
   gb[2][2] += divb;
 }
 
+// ---------------------------------------------------------------------------
+// Non-ideal stabilisers (Sec. 2: a bulk viscosity whose coefficient has a
+// grid-scale and an adaptive part, and a diffusive div-B correction in the
+// induction equation; App. A: the viscous acceleration grad(zeta div V), which
+// damps compressive modes at zeta k^2 / 2 for constant zeta).  The
+// coefficient formulas are readings (the companion paper that defines them is
+// not available):
+//   c_f  = sqrt((gamma (gamma - 1) sigma + |B|^2) / rho)        fast speed
+//   s    = min(1, (lambda |grad rho| / rho)^2)                  change sensor
+//   zeta = lambda c_f (grid + adapt s),   eta = divb lambda c_f
+//   dV/dt += zeta grad div V,  dB/dt += eta grad div B,  dsigma/dt += rho zeta (div V)^2
+// zeta and eta are taken constant over the neighborhood.
+// ---------------------------------------------------------------------------
+struct Stab {
+  double grid = 0.0;   // grid-scale bulk viscosity coefficient
+  double adapt = 0.0;  // adaptive bulk viscosity coefficient
+  double divb = 0.0;   // div-B diffusion coefficient
+  __host__ __device__ bool on() const { return grid != 0.0 || adapt != 0.0 || divb != 0.0; }
+};
+
+// Adds the stabilising terms to out.  grho = grad rho, gdv = grad div V,
+// gdb = grad div B.
+__device__ __forceinline__ void stab_point(const double (&q)[8], const double (&grho)[3],
+                                           double divV, const double (&gdv)[3],
+                                           const double (&gdb)[3], double lam, double gamma,
+                                           const Stab& sb, double (&out)[8]) {
+  const double rho = q[0];
+  const double inv_rho = 1.0 / rho;
+  const double bb = q[4] * q[4] + q[5] * q[5] + q[6] * q[6];
+  const double cf = sqrt((gamma * (gamma - 1.0) * q[7] + bb) * inv_rho);
+  const double lg = lam * inv_rho;
+  const double sens = lg * lg * (grho[0] * grho[0] + grho[1] * grho[1] + grho[2] * grho[2]);
+  const double sat = sens < 1.0 ? sens : 1.0;
+  const double lcf = lam * cf;
+  const double zeta = lcf * (sb.grid + sb.adapt * sat);
+  const double eta = sb.divb * lcf;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    out[1 + a] += zeta * gdv[a];
+    out[4 + a] += eta * gdb[a];
+  }
+  out[7] += rho * zeta * divV * divV;
+}
+
+// Reverse mode of stab_point: given ob (adjoint of out), adds to qb (8),
+// grho_b, gdv_b, gdb_b and returns the adjoint of div V.  The saturated
+// sensor (s >= 1) passes no derivative.
+__device__ __forceinline__ double stab_point_adjoint(const double (&q)[8], const double (&grho)[3],
+                                                     double divV, const double (&gdv)[3],
+                                                     const double (&gdb)[3], double lam,
+                                                     double gamma, const Stab& sb,
+                                                     const double (&ob)[8], double (&qb)[8],
+                                                     double (&grho_b)[3], double (&gdv_b)[3],
+                                                     double (&gdb_b)[3]) {
+  const double rho = q[0];
+  const double inv_rho = 1.0 / rho;
+  const double gg = gamma * (gamma - 1.0);
+  const double bb = q[4] * q[4] + q[5] * q[5] + q[6] * q[6];
+  const double cf = sqrt((gg * q[7] + bb) * inv_rho);
+  const double lg = lam * inv_rho;
+  const double sens = lg * lg * (grho[0] * grho[0] + grho[1] * grho[1] + grho[2] * grho[2]);
+  const bool live = sens < 1.0;
+  const double sat = live ? sens : 1.0;
+  const double lcf = lam * cf;
+  const double coef = sb.grid + sb.adapt * sat;
+  const double zeta = lcf * coef;
+  const double eta = sb.divb * lcf;
+  double zb = ob[7] * rho * divV * divV;
+  double eb = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    zb += ob[1 + a] * gdv[a];
+    eb += ob[4 + a] * gdb[a];
+    gdv_b[a] += zeta * ob[1 + a];
+    gdb_b[a] += eta * ob[4 + a];
+  }
+  qb[0] += ob[7] * zeta * divV * divV;
+  // zeta = lam cf coef, eta = divb lam cf
+  const double cfb = lam * (zb * coef + eb * sb.divb);
+  if (live) {
+    const double sb_ = zb * lcf * sb.adapt;  // adjoint of the sensor
+    const double k2 = 2.0 * sb_ * lg * lg;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) grho_b[a] += k2 * grho[a];
+    qb[0] += -2.0 * sb_ * sens * inv_rho;
+  }
+  // cf^2 = (gg sigma + bb) / rho
+  const double c2b = cfb / (2.0 * cf);
+  qb[0] += -c2b * cf * cf * inv_rho;
+  qb[7] += c2b * gg * inv_rho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) qb[4 + a] += c2b * 2.0 * q[4 + a] * inv_rho;
+  return ob[7] * 2.0 * rho * zeta * divV;
+}
+
 }  // namespace phb

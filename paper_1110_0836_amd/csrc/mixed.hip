@@ -355,15 +355,22 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
-// Gradients = rows / lambda; pointwise right-hand side; tape.
+// Gradients = rows / lambda; pointwise right-hand side; tape.  Ideal form:
+// rows[f][3][n] of the seven fields V, B, sigma.  STAB: rows[f][9][n] of all
+// eight fields, whose second-derivative rows (xx, xy, xz, yy, yz, zz) give
+// grad div V and grad div B.
+template <bool STAB>
 __global__ void __launch_bounds__(THREADS)
     k_mixed_rhs_finish(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
                        const double* __restrict__ rows, const int32_t* __restrict__ status,
-                       double gamma, double* __restrict__ rhs, double* __restrict__ dxdt,
+                       double gamma, Stab sb, double* __restrict__ rhs, double* __restrict__ dxdt,
                        double* __restrict__ tape) {
+  constexpr int NG = STAB ? 9 : 3;
+  constexpr int F0 = STAB ? 1 : 0;  // row block of field V_x
   const int i = blockIdx.x * THREADS + threadIdx.x;
   if (i >= n) return;
-  const double inv_lam = 1.0 / geo[i].w;
+  const double lam = geo[i].w;
+  const double inv_lam = 1.0 / lam;
   double qi[8];
 #pragma unroll
   for (int f = 0; f < 8; ++f) qi[f] = fq[8 * (int64_t)i + f];
@@ -371,11 +378,30 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
   for (int f = 0; f < 7; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) grad[f][t] = rows[((int64_t)f * 3 + t) * n + i] * inv_lam;
+    for (int t = 0; t < 3; ++t) grad[f][t] = rows[((int64_t)(F0 + f) * NG + t) * n + i] * inv_lam;
   const int st = status[i];
   double out[8];
+  double grho[3] = {0.0, 0.0, 0.0}, gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
   if (st == 0) {
     mhd_point(qi, grad, gamma, out);
+    if constexpr (STAB) {
+      // h[f][k]: second-derivative rows with the diagonal doubled
+      const double il2 = inv_lam * inv_lam;
+      auto h = [&](int f, int k) {
+        const double c = rows[((int64_t)f * NG + 3 + k) * n + i] * il2;
+        return (k == 0 || k == 3 || k == 5) ? 2.0 * c : c;
+      };
+#pragma unroll
+      for (int a = 0; a < 3; ++a) grho[a] = rows[(int64_t)a * n + i] * inv_lam;
+      // d_a div X = sum_b d_a d_b X_b ; k(a,b): xx 0, xy 1, xz 2, yy 3, yz 4, zz 5
+      gdv[0] = h(1, 0) + h(2, 1) + h(3, 2);
+      gdv[1] = h(1, 1) + h(2, 3) + h(3, 4);
+      gdv[2] = h(1, 2) + h(2, 4) + h(3, 5);
+      gdb[0] = h(4, 0) + h(5, 1) + h(6, 2);
+      gdb[1] = h(4, 1) + h(5, 3) + h(6, 4);
+      gdb[2] = h(4, 2) + h(5, 4) + h(6, 5);
+      stab_point(qi, grho, grad[0][0] + grad[1][1] + grad[2][2], gdv, gdb, lam, gamma, sb, out);
+    }
   } else {
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
 #pragma unroll
@@ -390,7 +416,15 @@ __global__ void __launch_bounds__(THREADS)
     for (int f = 0; f < 7; ++f)
 #pragma unroll
       for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + i] = grad[f][t];
-    tape[(int64_t)21 * n + i] = (double)st;
+    tape[(int64_t)TAPE_STATUS * n + i] = (double)st;
+    if constexpr (STAB) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        tape[(int64_t)(TAPE_GRHO + a) * n + i] = grho[a];
+        tape[(int64_t)(TAPE_GDV + a) * n + i] = gdv[a];
+        tape[(int64_t)(TAPE_GDB + a) * n + i] = gdb[a];
+      }
+    }
   }
 }
 
@@ -510,25 +544,29 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
 
 }  // namespace
 
-size_t mixed_rhs_bytes(int64_t n) {
+size_t mixed_rhs_bytes(int64_t n, bool stab) {
   phb_ctx dummy;
   Workspace ws(&dummy);
-  plan_mixed(ws, n, 7, 3);
+  plan_mixed(ws, n, stab ? 8 : 7, stab ? 9 : 3);
   ws.plan((size_t)n * sizeof(double4));
   ws.plan((size_t)8 * n * sizeof(double));
   return ws.total;
 }
 
-int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const double* q, double* rhs,
-              double* dxdt, int32_t* status, double* tape) {
+int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, const double* q,
+              double* rhs, double* dxdt, int32_t* status, double* tape) {
   const int n = a0.n;
+  const bool stab = sb.on();
+  // ideal: V, B, sigma (records 1..7), three rows; stabilised: all eight
+  // fields (rho's gradient feeds the sensor), nine rows
+  const int nf = stab ? 8 : 7, ng = stab ? 9 : 3;
   Workspace ws(ctx);
-  plan_mixed(ws, n, 7, 3);
+  plan_mixed(ws, n, nf, ng);
   ws.plan((size_t)n * sizeof(double4));
   ws.plan((size_t)8 * n * sizeof(double));
   int rc;
   if ((rc = ws.commit())) return rc;
-  MixedBufs m = take_mixed(ws, n, 7, 3);
+  MixedBufs m = take_mixed(ws, n, nf, ng);
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
   if (tape) m.mom = tape + (size_t)TAPE_MOM * n;
@@ -538,11 +576,18 @@ int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const double* q, d
   { Prof pf(ctx, "k_pack");
     if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
       return rc; }
-  // V, B and sigma are entries 1..7 of the packed records
-  if ((rc = mixed_fit<3>(ctx, a, fq, 1, 7, m, status))) return rc;
-  Prof pf(ctx, "k_mixed_rhs_finish");
-  hipLaunchKernelGGL(k_mixed_rhs_finish, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, ctx->stream,
-                     n, geo, fq, m.rows, status, gamma, rhs, dxdt, tape);
+  if (stab) {
+    if ((rc = mixed_fit<9>(ctx, a, fq, 0, 8, m, status))) return rc;
+    Prof pf(ctx, "k_mixed_rhs_finish<stab>");
+    hipLaunchKernelGGL(k_mixed_rhs_finish<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
+                       ctx->stream, n, geo, fq, m.rows, status, gamma, sb, rhs, dxdt, tape);
+  } else {
+    // V, B and sigma are entries 1..7 of the packed records
+    if ((rc = mixed_fit<3>(ctx, a, fq, 1, 7, m, status))) return rc;
+    Prof pf(ctx, "k_mixed_rhs_finish");
+    hipLaunchKernelGGL(k_mixed_rhs_finish<false>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
+                       ctx->stream, n, geo, fq, m.rows, status, gamma, sb, rhs, dxdt, tape);
+  }
   return hip_check(ctx, hipGetLastError(), "mixed rhs");
 }
 

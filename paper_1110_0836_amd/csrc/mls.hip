@@ -255,32 +255,42 @@ __global__ void __launch_bounds__(THREADS)
 }
 
 // ---------------------------------------------------------------------------
-// 3b. ideal-MHD time derivatives
+// 3b. MHD time derivatives
 // ---------------------------------------------------------------------------
-template <int G>
+// Ideal form: the three gradient rows applied to V, B and sigma.  STAB (the
+// non-ideal stabilisers): nine rows (gradient, then xx, xy, xz, yy, yz, zz)
+// applied to all eight fields' gradients (rho's feeds the change sensor) and
+// to grad div V and grad div B, whose entry terms are
+//   d_a div V  <-  sum_b h_ab (V_b,j - V_b,i),   h_ab = w row_(ab) . p_j
+// with the diagonal rows doubled (d^2/dx_a^2 = 2 c_aa / lambda^2).
+template <int G, bool STAB>
 __global__ void __launch_bounds__(THREADS)
     k_apply_rhs(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
-                double rf_ratio, int wkind, double gamma, const double* __restrict__ gop,
+                double rf_ratio, int wkind, double gamma, Stab sb, const double* __restrict__ gop,
                 const int32_t* __restrict__ status, double* __restrict__ rhs,
                 double* __restrict__ dxdt, double* __restrict__ tape) {
+  constexpr int NR = STAB ? 9 : 3;  // operator rows
+  constexpr int NF = STAB ? 8 : 7;  // fields with a gradient: the last NF of eight
+  constexpr int F0 = 8 - NF;
   const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   const int st = status[ii];
-  // The particle's three operator rows live in LDS, not in each lane's
-  // registers: gsh[k][pl] holds entries 2k, 2k+1 of the 60, and one 16-byte
-  // read serves all lanes of a particle (consecutive particles, consecutive
-  // addresses: no bank conflicts).
+  // The particle's operator rows live in LDS, not in each lane's registers:
+  // gsh[k][pl] holds entries 2k, 2k+1, and one 16-byte read serves all lanes
+  // of a particle (consecutive particles, consecutive addresses: no bank
+  // conflicts).
   constexpr int PPB = THREADS / G;
-  __shared__ double2 gsh[3 * NBASIS / 2][PPB];
+  __shared__ double2 gsh[NR * NBASIS / 2][PPB];
   const int pl = threadIdx.x / G;
-  for (int k = l; k < 3 * NBASIS / 2; k += G) {
+  for (int k = l; k < NR * NBASIS / 2; k += G) {
     const int t = (2 * k) / NBASIS, b = (2 * k) % NBASIS;
-    gsh[k][pl] = make_double2(gop[((int64_t)t * NBASIS + b) * n + ii],
-                              gop[((int64_t)t * NBASIS + b + 1) * n + ii]);
+    const double sc = (STAB && (t == 3 || t == 6 || t == 8)) ? 2.0 : 1.0;
+    gsh[k][pl] = make_double2(sc * gop[((int64_t)t * NBASIS + b) * n + ii],
+                              sc * gop[((int64_t)t * NBASIS + b + 1) * n + ii]);
   }
   __syncthreads();
   double qi[8];
@@ -289,11 +299,12 @@ __global__ void __launch_bounds__(THREADS)
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
-  double acc[7][3];
+  double acc[NF][3];
 #pragma unroll
-  for (int f = 0; f < 7; ++f)
+  for (int f = 0; f < NF; ++f)
 #pragma unroll
     for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
+  double gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
   const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
   int64_t s = s0 + l;
   int jc = ii, jn = ii;
@@ -319,12 +330,12 @@ __global__ void __launch_bounds__(THREADS)
     const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
     double p[NBASIS];
     basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-    double gam[3];
+    double gam[NR];
     // re-read the rows from LDS every iteration: hoisted out of the loop they
-    // would occupy 120 registers again
+    // would occupy registers again
     asm volatile("" ::: "memory");
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < NR; ++t) {
       double v = 0.0;
 #pragma unroll
       for (int b = 0; b < NBASIS; b += 2) {
@@ -334,22 +345,49 @@ __global__ void __launch_bounds__(THREADS)
       }
       gam[t] = w * v;
     }
+    double df[8];
 #pragma unroll
-    for (int f = 0; f < 7; ++f) {
-      const double df = qj[f + 1] - qi[f + 1];
+    for (int f = F0; f < 8; ++f) df[f] = qj[f] - qi[f];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) acc[f][t] = fma(gam[t], df, acc[f][t]);
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[f][t] = fma(gam[t], df[F0 + f], acc[f][t]);
+    if constexpr (STAB) {
+      // rows 3..8 = xx, xy, xz, yy, yz, zz
+      gdv[0] += gam[3] * df[1] + gam[4] * df[2] + gam[5] * df[3];
+      gdv[1] += gam[4] * df[1] + gam[6] * df[2] + gam[7] * df[3];
+      gdv[2] += gam[5] * df[1] + gam[7] * df[2] + gam[8] * df[3];
+      gdb[0] += gam[3] * df[4] + gam[4] * df[5] + gam[5] * df[6];
+      gdb[1] += gam[4] * df[4] + gam[6] * df[5] + gam[7] * df[6];
+      gdb[2] += gam[5] * df[4] + gam[7] * df[5] + gam[8] * df[6];
     }
   }
-  double grad[7][3];
+  double grad[NF][3];
 #pragma unroll
-  for (int f = 0; f < 7; ++f)
+  for (int f = 0; f < NF; ++f)
 #pragma unroll
     for (int t = 0; t < 3; ++t) grad[f][t] = group_sum<G>(acc[f][t]) * inv_lam;
+  if constexpr (STAB) {
+    const double il2 = inv_lam * inv_lam;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      gdv[a] = group_sum<G>(gdv[a]) * il2;
+      gdb[a] = group_sum<G>(gdb[a]) * il2;
+    }
+  }
   if (valid && l == 0) {
+    double g7[7][3];
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) g7[f][t] = grad[NF - 7 + f][t];
     double out[8];
     if (st == 0) {
-      mhd_point(qi, grad, gamma, out);
+      mhd_point(qi, g7, gamma, out);
+      if constexpr (STAB) {
+        const double grho[3] = {grad[0][0], grad[0][1], grad[0][2]};
+        stab_point(qi, grho, g7[0][0] + g7[1][1] + g7[2][2], gdv, gdb, gi.w, gamma, sb, out);
+      }
     } else {
       const double nan = __longlong_as_double(0x7ff8000000000000LL);
 #pragma unroll
@@ -359,12 +397,20 @@ __global__ void __launch_bounds__(THREADS)
     for (int f = 0; f < 8; ++f) rhs[(int64_t)f * n + i] = out[f];
 #pragma unroll
     for (int a = 0; a < 3; ++a) dxdt[(int64_t)a * n + i] = qi[1 + a];
-    if (tape) {  // gradients (7 x 3) and the status, for the reverse mode
+    if (tape) {  // what the reverse mode reuses (layout in mls.hpp)
 #pragma unroll
       for (int f = 0; f < 7; ++f)
 #pragma unroll
-        for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + i] = grad[f][t];
-      tape[(int64_t)21 * n + i] = (double)st;
+        for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + i] = g7[f][t];
+      tape[(int64_t)TAPE_STATUS * n + i] = (double)st;
+      if constexpr (STAB) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          tape[(int64_t)(TAPE_GRHO + a) * n + i] = grad[0][a];
+          tape[(int64_t)(TAPE_GDV + a) * n + i] = gdv[a];
+          tape[(int64_t)(TAPE_GDB + a) * n + i] = gdb[a];
+        }
+      }
     }
   }
 }
@@ -451,14 +497,13 @@ hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, cons
   }
 }
 
-template <int G>
-static hipError_t rhs_g(hipStream_t s, const EvalArgs& a, double gamma, const double* gop,
-                        const int32_t* status, const double* q, double* rhs, double* dxdt,
+template <int G, bool STAB>
+static hipError_t rhs_g(hipStream_t s, const EvalArgs& a, double gamma, const Stab& sb,
+                        const double* gop, const int32_t* status, double* rhs, double* dxdt,
                         double* tape) {
-  (void)q;  // read through the packed records a.fq
-  hipLaunchKernelGGL((k_apply_rhs<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0,
-                     s, a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gamma, gop,
-                     status, rhs, dxdt, tape);
+  hipLaunchKernelGGL((k_apply_rhs<G, STAB>), dim3(grid_for((int64_t)a.n * G, THREADS)),
+                     dim3(THREADS), 0, s, a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio,
+                     a.wkind, gamma, sb, gop, status, rhs, dxdt, tape);
   return hipGetLastError();
 }
 
@@ -470,12 +515,15 @@ hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* la
 }
 
 hipError_t launch_apply_rhs(hipStream_t s, const EvalArgs& a, int lanes, double gamma,
-                            const double* gop, const int32_t* status, const double* q,
-                            double* rhs, double* dxdt, double* tape) {
+                            const Stab& sb, const double* gop, const int32_t* status, double* rhs,
+                            double* dxdt, double* tape) {
+  // nine LDS rows per particle: eight lanes per particle keep a block's rows
+  // at 46 KB
+  if (sb.on()) return rhs_g<8, true>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
   switch (lanes) {
-    case 1: return rhs_g<1>(s, a, gamma, gop, status, q, rhs, dxdt, tape);
-    case 2: return rhs_g<2>(s, a, gamma, gop, status, q, rhs, dxdt, tape);
-    default: return rhs_g<4>(s, a, gamma, gop, status, q, rhs, dxdt, tape);
+    case 1: return rhs_g<1, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
+    case 2: return rhs_g<2, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
+    default: return rhs_g<4, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
   }
 }
 

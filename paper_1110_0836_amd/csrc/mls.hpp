@@ -27,9 +27,14 @@ struct EvalArgs {
 };
 
 // Tape of the forward evaluation, per particle (SoA, n entries each):
-// 21 gradients (7 fields x 3), the status, then the 84 moments.
-constexpr int TAPE_MOM = 22;
-constexpr int TAPE_DOUBLES = 22 + NMOM;
+// 21 gradients (V, B, sigma x 3), the status, grad rho, grad div V and
+// grad div B (written only with the stabilisers on), then the 84 moments.
+constexpr int TAPE_STATUS = 21;
+constexpr int TAPE_GRHO = 22;
+constexpr int TAPE_GDV = 25;
+constexpr int TAPE_GDB = 28;
+constexpr int TAPE_MOM = 31;
+constexpr int TAPE_DOUBLES = TAPE_MOM + NMOM;
 
 // geo (and fq when q != null) from the SoA inputs.
 hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* lam,
@@ -45,8 +50,10 @@ hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
 hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,
                                const int32_t* status, int nf, const double* fields, double* d1,
                                double* d2);
+// Time derivatives from the operator rows gop: three rows (ideal), nine with
+// the stabilisers on.
 hipError_t launch_apply_rhs(hipStream_t s, const EvalArgs& a, int lanes, double gamma,
-                            const double* gop, const int32_t* status, const double* q,
-                            double* rhs, double* dxdt, double* tape);
+                            const Stab& sb, const double* gop, const int32_t* status, double* rhs,
+                            double* dxdt, double* tape);
 
 }  // namespace phb

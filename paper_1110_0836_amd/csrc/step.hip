@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(THREADS)
 constexpr int DT_BLOCKS = 512;
 __global__ void __launch_bounds__(THREADS)
     k_courant(int n, const double* __restrict__ q, const double* __restrict__ lam,
-              const int32_t* __restrict__ frozen, double gamma, double* __restrict__ part) {
+              const int32_t* __restrict__ frozen, double gamma, double cmul,
+              double* __restrict__ part) {
   __shared__ double sm[THREADS];
   double m = 1e300;
   for (int i = blockIdx.x * THREADS + threadIdx.x; i < n; i += gridDim.x * THREADS) {
@@ -75,7 +76,7 @@ __global__ void __launch_bounds__(THREADS)
                  bz = q[6 * (int64_t)n + i];
     const double pr = (gamma - 1.0) * q[7 * (int64_t)n + i];
     const double cf = sqrt((gamma * pr + bx * bx + by * by + bz * bz) / rho);
-    const double t = lam[i] / (sqrt(vx * vx + vy * vy + vz * vz) + cf);
+    const double t = lam[i] / (sqrt(vx * vx + vy * vy + vz * vz) + cf * cmul);
     m = fmin(m, t);
   }
   sm[threadIdx.x] = m;
@@ -100,7 +101,7 @@ int pc_step(phb_ctx* ctx, const phb_params* p, int n, double dt, double* pos, do
   ws.plan((size_t)n * sizeof(int32_t));
   ws.plan(64 * sizeof(int32_t));
   const size_t own = ws.total;
-  ws.plan(std::max(ws_bytes_neighbors(n, idx_capacity), ws_bytes_rhs(n, p->precision)));
+  ws.plan(std::max(ws_bytes_neighbors(n, idx_capacity), ws_bytes_rhs(n, p)));
   int rc;
   if ((rc = ws.commit())) return rc;
   double* xs = ws.take<double>(n3);
@@ -162,8 +163,11 @@ int courant_dt(phb_ctx* ctx, const phb_params* p, int n, const double* q, const 
   int rc;
   if ((rc = ws.commit())) return rc;
   double* part = ws.take<double>(DT_BLOCKS);
+  // the stabilisers' diffusivities (at most lambda c_f times their
+  // coefficients) enter as the speed 2 (zeta + eta) / lambda
+  const double cmul = 1.0 + 2.0 * (p->visc_grid + p->visc_adapt + p->divb_diff);
   hipLaunchKernelGGL(k_courant, dim3(DT_BLOCKS), dim3(THREADS), 0, ctx->stream, n, q, lambda,
-                     frozen, p->gamma, part);
+                     frozen, p->gamma, cmul, part);
   if ((rc = hip_check(ctx, hipGetLastError(), "courant"))) return rc;
   double* h = nullptr;
   if (hipHostMalloc((void**)&h, DT_BLOCKS * sizeof(double)) != hipSuccess)

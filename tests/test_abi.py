@@ -37,7 +37,7 @@ def test_host_only_calls():
     import paper_1110_0836_amd as P
     lib = P.lib()
     assert lib.phb_strerror(P.PHB_ECAPACITY) == b"output buffer too small"
-    assert lib.phb_tape_bytes(1000) == 1000 * (22 + 84) * 8
+    assert lib.phb_tape_bytes(1000) == 1000 * (31 + 84) * 8
     assert lib.phb_tape_bytes(0) == 0
     # null arguments are rejected before any device work
     assert lib.phb_create(None, 0, None) == P.PHB_EINVAL
@@ -47,9 +47,11 @@ def test_host_only_calls():
 
 def test_params_layout_matches_header():
     import paper_1110_0836_amd as P
-    # double L[3]; int32 periodic[3]; (pad) double gamma; double rf_ratio; int32 x3
-    assert ctypes.sizeof(P.Params) == 24 + 12 + 4 + 8 + 8 + 12 + 4
+    # double L[3]; int32 periodic[3]; (pad) double gamma; double rf_ratio; int32 x3; (pad)
+    # double visc_grid, visc_adapt, divb_diff
+    assert ctypes.sizeof(P.Params) == 24 + 12 + 4 + 8 + 8 + 12 + 4 + 3 * 8
     assert P.Params.gamma.offset == 40
+    assert P.Params.visc_grid.offset == 72 and P.Params.divb_diff.offset == 88
 
 
 def test_batch_io_layout_and_null_batch():
