@@ -70,6 +70,8 @@ def lib():
         L.orc_pc_step.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, P, I, P]
         L.orc_evolve.restype = I
         L.orc_evolve.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, I, P, P, I, P]
+        L.orc_divb_norm.restype = I
+        L.orc_divb_norm.argtypes = [I64, P, P, P, P, D, I, I, I64, P, P, P, P, P, P, I]
         L.orc_courant_dt.restype = D
         L.orc_courant_dt.argtypes = [I64, P, P, D, P, D, P]
         _lib = L
@@ -305,3 +307,41 @@ def courant_dt(q, lam, cfl=0.3, gamma=5.0 / 3.0, frozen=None, stab=None):
     if dt < 0:
         raise ValueError("orc_courant_dt: no particle to time-step")
     return dt
+
+
+def divb_norm(pos, lam, off, idx, q, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), rows=None,
+              weight=0, fit=0, threads=0, rf_ratio=RF_RATIO):
+    """lambda (div B) / |B| per particle (Sec. 3.3) and the fit status."""
+    pos = _c(pos, np.float64)
+    lam = _c(lam, np.float64)
+    q = _c(q, np.float64)
+    n = lam.shape[0]
+    Lb, pb = _box(L, periodic)
+    rows_a = None if rows is None else _c(rows, np.int64)
+    nrows = n if rows_a is None else rows_a.shape[0]
+    out = np.zeros(nrows)
+    st = np.zeros(nrows, np.int32)
+    rc = lib().orc_divb_norm(n, _p(pos), _p(lam), _p(Lb), _p(pb), rf_ratio, weight, fit, nrows,
+                             _p(rows_a), _p(_c(off, np.int64)), _p(_c(idx, np.int32)), _p(q),
+                             _p(out), _p(st), threads)
+    if rc != 0:
+        raise ValueError("orc_divb_norm: invalid arguments")
+    return out, st
+
+
+def bin_mean(coord, values, x0, width, nbins):
+    """Mean of the finite values per bin [x0 + b width, x0 + (b+1) width) of
+    coord (Sec. 3.3 bins the div-B diagnostic in bins one lambda wide), by
+    plain loops: (mean (nbins,), NaN for empty bins; count (nbins,))."""
+    total = [0.0] * nbins
+    count = [0] * nbins
+    for x, v in zip(np.asarray(coord, dtype=np.float64).tolist(),
+                    np.asarray(values, dtype=np.float64).tolist()):
+        if v != v:
+            continue
+        b = int(np.floor((x - x0) / width))
+        if 0 <= b < nbins:
+            total[b] += v
+            count[b] += 1
+    mean = np.array([t / c if c else np.nan for t, c in zip(total, count)])
+    return mean, np.array(count, dtype=np.int64)

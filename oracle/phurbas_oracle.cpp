@@ -816,6 +816,35 @@ int orc_mhd_rhs(int64_t n, const double* pos, const double* lambda, const double
   return 0;
 }
 
+// Normalized divergence diagnostic of the magnetic field (Sec. 3.3: the
+// fractional field error on the scale of lambda), for the listed rows:
+//   out = lambda_i (div B)_i / |B_i|
+// from the fitted gradients of Bx, By, Bz (q rows 4..6).  NaN where the fit
+// failed or |B_i| = 0.  status: [nrows].
+int orc_divb_norm(int64_t n, const double* pos, const double* lambda, const double* L,
+                  const int32_t* periodic, double rf_ratio, int weight, int fit, int64_t nrows,
+                  const int64_t* rows, const int64_t* offsets, const int32_t* idx,
+                  const double* q, double* out, int32_t* status, int nthreads) {
+  if (n <= 0 || !pos || !lambda || !offsets || !idx || !q || !out || !status) return -1;
+  Setup s = make_setup(L, periodic, rf_ratio, 0.0, weight, fit);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  const double* bfield = q + 4 * n;
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int64_t r = 0; r < nrows; ++r) {
+    const int64_t i = row_of(rows, r);
+    const int m = (int)(offsets[r + 1] - offsets[r]);
+    double d1[3 * 3];
+    const int st = fit_particle<double>(n, i, pos, lambda, idx + offsets[r], m, 3, bfield, s, d1,
+                                        nullptr, nullptr, nullptr, nullptr);
+    status[r] = st;
+    const double bx = bfield[i], by = bfield[n + i], bz = bfield[2 * n + i];
+    const double bmag = std::sqrt(bx * bx + by * by + bz * bz);
+    const double div = d1[0 * 3 + 0] + d1[1 * 3 + 1] + d1[2 * 3 + 2];
+    out[r] = (st == 0 && bmag > 0.0) ? lambda[i] * div / bmag : std::nan("");
+  }
+  return 0;
+}
+
 // Complex-step evaluation: inputs pos + i h dpos, q + i h dq (neighbor sets
 // from the real positions, given in the CSR).  Returns Re(rhs) and
 // Im(rhs)/h, the directional derivative along (dpos, dq), for all rows.
