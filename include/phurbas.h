@@ -71,6 +71,10 @@ extern "C" {
 #define PHB_W_POLY3 0     /* w = (1 - d^2/r_f^2)^3 */
 #define PHB_W_UNIT 1      /* w = 1 */
 #define PHB_FIT_FULL20 0  /* all 20 monomials, constant included */
+#define PHB_FIT_INTERP19 1 /* interpolating fit (acknowledgements of the paper: the tests
+                              use interpolating fits): the 19 monomials without the
+                              constant, so the fit passes through the particle's own
+                              value; same status rules */
 
 #define PHB_STATUS_OK 0
 #define PHB_STATUS_TOO_FEW 1
@@ -85,7 +89,7 @@ typedef struct {
   double rf_ratio;      /* r_f / lambda; the paper uses 2.3 */
   int32_t precision;    /* PHB_FP64 or PHB_MIXED */
   int32_t weight;       /* PHB_W_POLY3 or PHB_W_UNIT */
-  int32_t fit;          /* PHB_FIT_FULL20 */
+  int32_t fit;          /* PHB_FIT_FULL20 or PHB_FIT_INTERP19 */
   /* Non-ideal stabilisers (Sec. 2: a bulk viscosity with a grid-scale and an
    * adaptive coefficient field, and a diffusive div-B term in the induction
    * equation; App. A: the viscous acceleration grad(zeta div V)).  All zero
@@ -220,6 +224,24 @@ int phb_evolve(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, int32_t 
  * EINVAL if every particle is frozen or cfl <= 0.  Synchronizes. */
 int phb_courant_dt(phb_ctx* ctx, const phb_params* p, int64_t n, const double* q,
                    const double* lambda, const int32_t* frozen, double cfl, double* dt_out);
+
+/* ---- diagnostics (Sec. 3.3) ----------------------------------------------
+ * phb_divb_norm: out[i] = lambda_i (div B)_i / |B_i|, the fractional magnetic
+ * field error on the scale of lambda, from the fitted gradients of q rows 4..6
+ * (same fit, precision and status rules as phb_mls_derivs).  out double[n];
+ * status int32[n]; out is NaN where status != 0 or |B_i| = 0.  Device
+ * pointers, asynchronous. */
+int phb_divb_norm(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                  const double* lambda, const int64_t* offsets, const int32_t* idx,
+                  const double* q, double* out, int32_t* status);
+/* phb_bin_mean: mean of the finite values[i] per bin b = floor((coord[i] - x0)
+ * / width), 0 <= b < nbins, taken in FP64 (the paper bins the divergence
+ * diagnostic in bins one lambda wide).  mean double[nbins] (NaN for an empty
+ * bin), count int64[nbins] or NULL.  The sums are accumulated with atomic
+ * adds, so the last bits of a mean may vary from call to call.  EINVAL for
+ * nbins <= 0, width <= 0 or non-finite x0, width. */
+int phb_bin_mean(phb_ctx* ctx, int64_t n, const double* coord, const double* values, double x0,
+                 double width, int32_t nbins, double* mean, int64_t* count);
 
 /* ---- many particle sets in one captured graph -----------------------------
  * Independent particle sets (each with its own neighbor lists; no set sees

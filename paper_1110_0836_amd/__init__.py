@@ -31,6 +31,7 @@ PHB_MIXED = 1
 PHB_W_POLY3 = 0
 PHB_W_UNIT = 1
 PHB_FIT_FULL20 = 0
+PHB_FIT_INTERP19 = 1
 
 EXPORTS = [
     "phb_create", "phb_destroy", "phb_set_stream", "phb_reserve", "phb_strerror",
@@ -38,7 +39,7 @@ EXPORTS = [
     "phb_permute", "phb_mls_derivs", "phb_mhd_rhs", "phb_tape_bytes", "phb_mhd_rhs_adjoint",
     "phb_pc_step", "phb_profile", "phb_profile_read", "phb_tune_set", "phb_tune_get",
     "phb_evolve", "phb_courant_dt", "phb_tune", "phb_batch_create", "phb_batch_destroy", "phb_batch_neighbors", "phb_batch_run",
-    "phb_batch_capture", "phb_batch_launch",
+    "phb_batch_capture", "phb_batch_launch", "phb_divb_norm", "phb_bin_mean",
 ]
 
 
@@ -146,6 +147,8 @@ def lib():
             "phb_batch_run": (I, [P, P, ctypes.POINTER(BatchIO)]),
             "phb_batch_capture": (I, [P, P, ctypes.POINTER(BatchIO)]),
             "phb_batch_launch": (I, [P, P]),
+            "phb_divb_norm": (I, [P, PP, I64, P, P, P, P, P, P, P]),
+            "phb_bin_mean": (I, [P, I64, P, P, D, D, I32, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -449,6 +452,29 @@ def evolve(pos, q, lam, dt, nsteps, setup=None, frozen=None, capacity=None):
 def courant_dt(q, lam, cfl=0.3, setup=None, frozen=None):
     """Courant step cfl * min lambda / (|V| + c_fast) over non-frozen particles."""
     return phb_courant_dt(setup or Setup(), q, lam, frozen, cfl)
+
+
+def divb_norm(pos, lam, offsets, idx, q, setup=None):
+    """lambda (div B) / |B| per particle (Sec. 3.3) and the fit status."""
+    n = lam.shape[0]
+    out = torch.empty(n, dtype=torch.float64, device=q.device)
+    st = torch.empty(n, dtype=torch.int32, device=q.device)
+    ctx = context(q.device.index)
+    p = (setup or Setup()).params()
+    _check(ctx, lib().phb_divb_norm(ctx, ctypes.byref(p), n, _f64(pos), _f64(lam),
+                                    _ptr(offsets), _ptr(idx), _f64(q), _ptr(out), _ptr(st)))
+    return out, st
+
+
+def bin_mean(coord, values, x0, width, nbins):
+    """Mean of the finite values in bins of width `width` from x0 along coord:
+    (mean (nbins,) with NaN for empty bins, count (nbins,) int64)."""
+    mean = torch.empty(nbins, dtype=torch.float64, device=values.device)
+    count = torch.empty(nbins, dtype=torch.int64, device=values.device)
+    ctx = context(values.device.index)
+    _check(ctx, lib().phb_bin_mean(ctx, values.shape[0], _f64(coord), _f64(values), float(x0),
+                                   float(width), int(nbins), _ptr(mean), _ptr(count)))
+    return mean, count
 
 
 class MHDRHS(torch.autograd.Function):

@@ -191,14 +191,14 @@ __constant__ EntryTab c_tab_a = make_entry_tab();
 
 __global__ void __launch_bounds__(THREADS)
     k_adj_factor(int n, const double* __restrict__ mom, const double* __restrict__ ybuf,
-                 const double* __restrict__ tape, double* __restrict__ gop) {
+                 const double* __restrict__ tape, double* __restrict__ gop, int interp) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   QuadChol c;
-  quad_chol_factor(c, c_tab_a, mom, n, ii, l);
+  quad_chol_factor(c, c_tab_a, mom, n, ii, l, interp != 0);
   const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
   // G rows at 0..59 and K rows at 60..119 of the owner record; each group of
   // three solves runs in lockstep
@@ -220,6 +220,10 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
       for (int rho = 0; rho < 5; ++rho)
         y[rh][rho] = ybuf[((int64_t)rh * NBASIS + 4 * rho + l) * n + ii] * c.s_own[rho];
+    // interpolating fit: Y's constant entry belongs to no basis function
+    if (interp && l == 0)
+#pragma unroll
+      for (int rh = 0; rh < 3; ++rh) y[rh][0] = 0.0;
     quad_chol_solve_n<0, 3>(c, l, y, out);
     if (valid) {
 #pragma unroll
@@ -723,7 +727,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   if (rc) return rc; }
   { Prof pf(ctx, "k_adj_factor");
   hipLaunchKernelGGL(k_adj_factor, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS), 0, s, n,
-                     mom, ybuf, tape, orec);
+                     mom, ybuf, tape, orec, (int)(a.fit == PHB_FIT_INTERP19));
   if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;

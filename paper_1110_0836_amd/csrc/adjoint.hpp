@@ -24,6 +24,7 @@ int mixed_rhs(phb_ctx* ctx, const EvalArgs& a, double gamma, const Stab& sb, con
 
 int mixed_derivs(phb_ctx* ctx, const EvalArgs& a, int nf, const double* fields, double* d1,
                  double* d2, int32_t* status);
+size_t mixed_derivs_bytes(int64_t n, bool second);
 
 // One Heun step; frozen (nullable) marks particles held fixed; accumulate:
 // status keeps the maximum over earlier steps.

@@ -77,7 +77,8 @@ int check_params(phb_ctx* ctx, const phb_params* p) {
     return set_error(ctx, PHB_EINVAL, "unknown precision");
   if (p->weight != PHB_W_POLY3 && p->weight != PHB_W_UNIT)
     return set_error(ctx, PHB_EINVAL, "unknown weight");
-  if (p->fit != PHB_FIT_FULL20) return set_error(ctx, PHB_ENOTIMPL, "only the 20-monomial fit");
+  if (p->fit != PHB_FIT_FULL20 && p->fit != PHB_FIT_INTERP19)
+    return set_error(ctx, PHB_EINVAL, "unknown fit");
   for (double c : {p->visc_grid, p->visc_adapt, p->divb_diff})
     if (!(c >= 0.0) || !isfinite(c))
       return set_error(ctx, PHB_EINVAL, "stabiliser coefficients must be finite and >= 0");
@@ -185,6 +186,16 @@ size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity) {
   return ws.total;
 }
 
+size_t ws_bytes_derivs(int64_t n, const phb_params* p, bool second) {
+  if (p->precision == PHB_MIXED) return mixed_derivs_bytes(n, second);
+  phb_ctx dummy;
+  Workspace ws(&dummy);
+  ws.plan((size_t)NMOM * n * sizeof(double));
+  ws.plan((size_t)9 * NBASIS * n * sizeof(double));
+  ws.plan((size_t)n * sizeof(double4));
+  return ws.total;
+}
+
 size_t ws_bytes_rhs(int64_t n, const phb_params* p) {
   phb_ctx dummy;
   Workspace ws(&dummy);
@@ -253,6 +264,7 @@ int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
   a->box = make_box(p);
   a->rf_ratio = p->rf_ratio;
   a->wkind = p->weight;
+  a->fit = p->fit;
   return PHB_OK;
 }
 

@@ -42,10 +42,11 @@ struct QuadChol {
 
 // Loads A from the moments (SoA [84][n]), equilibrates A_hat = S A S with
 // S = diag(1/sqrt(A_rr)) and factors A_hat = L L^T.  tab is the entry->moment
-// table in constant memory.
+// table in constant memory.  interp: the 19-monomial interpolating fit (the
+// constant's row and column replaced by the identity's).
 __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& tab,
                                                  const double* __restrict__ mom, int64_t n,
-                                                 int ii, int l) {
+                                                 int ii, int l, bool interp = false) {
   double dg[5];
   sfor<0, 5>([&](auto R) {
     constexpr int rho = R;
@@ -56,6 +57,17 @@ __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& ta
     });
     dg[rho] = mom[(int64_t)tab.v[r * NBASIS + r] * n + ii];
   });
+  if (interp) {
+    // interpolating fit: the constant monomial leaves the basis.  Its row and
+    // column become those of the identity, which decouples the other 19:
+    // their block is factored as it is, and every inverse row 1.. has a zero
+    // constant entry.
+    sfor<0, 5>([&](auto R) {
+      constexpr int rho = R;
+      c.a[chol_aoff(rho)] = (rho == 0 && l == 0) ? 1.0 : 0.0;
+    });
+    if (l == 0) dg[0] = 1.0;
+  }
   c.ok = true;
   sfor<0, 5>([&](auto R) {
     constexpr int rho = R;

@@ -106,6 +106,7 @@ Box make_box(const phb_params* p);
 // nested calls).
 size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity);
 size_t ws_bytes_rhs(int64_t n, const phb_params* p);
+size_t ws_bytes_derivs(int64_t n, const phb_params* p, bool second);
 
 inline unsigned grid_for(int64_t work, int block) {
   int64_t g = (work + block - 1) / block;

@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(THREADS)
                    const double* __restrict__ bin, double* __restrict__ cfit,
                    double* __restrict__ gt, int32_t* __restrict__ status,
                    int32_t* __restrict__ flag, double ncut, const int32_t* __restrict__ list_in,
-                   int32_t* __restrict__ list_out, int32_t* __restrict__ count) {
+                   int32_t* __restrict__ list_out, int32_t* __restrict__ count, int interp) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int l = tid & 3;
   const int quad = tid >> 2;
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(THREADS)
   for (int k = quad; k < total; k += stride) {
     const int i = listed ? list_in[k] : k;
     QuadChol c;
-    quad_chol_factor(c, c_mtab, mom, n, i, l);
+    quad_chol_factor(c, c_mtab, mom, n, i, l, interp != 0);
     const int nnb = (int)(off[i + 1] - off[i]);
     const int st = quad_chol_status(c, nnb);
     if (!listed) {
@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(THREADS)
         b[rho] = bin[((int64_t)f * NBASIS + 4 * rho + l) * n + i];
       });
       quad_chol_apply_inverse(c, l, b, x);
+      if (interp && l == 0) x[0] = 0.0;  // no constant term: the residuals see p . c of 19
       sfor<0, 5>([&](auto R) {
         constexpr int rho = R;
         cfit[((int64_t)f * NBASIS + 4 * rho + l) * n + i] = st == 0 ? x[rho] : 0.0;
@@ -515,6 +516,7 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
   hipStream_t s = ctx->stream;
   const int n = a.n;
   const double ncut = pow(10.0, (double)ctx->mixed_cond_exp);
+  const int interp = a.fit == PHB_FIT_INTERP19;
   const unsigned gq = grid_for((int64_t)n * 4, THREADS);
   int rc;
   { Prof pf(ctx, "k_moments<fp32>");
@@ -527,14 +529,14 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
   { Prof pf(ctx, "k_mixed_factor");
     hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, nf,
-                       m.b, m.cfit, m.gt, status, m.flag, ncut, nullptr, m.list, m.count);
+                       m.b, m.cfit, m.gt, status, m.flag, ncut, nullptr, m.list, m.count, interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed factor"))) return rc; }
   { Prof pf(ctx, "k_mixed_repair");
     hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, a.geo, a.off,
                        a.idx, a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.list, m.count, m.mom, m.b);
     hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, m.mom,
                        a.off, nf, m.b, m.cfit, m.gt, status, m.flag, ncut, m.list, nullptr,
-                       m.count);
+                       m.count, interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed repair"))) return rc; }
   Prof pf(ctx, "k_mixed_resid");
   hipLaunchKernelGGL((k_mixed_resid<NG>), dim3(gq), dim3(THREADS), 0, s, n, a.geo, a.off, a.idx,
@@ -589,6 +591,15 @@ int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, co
                        ctx->stream, n, geo, fq, m.rows, status, gamma, sb, rhs, dxdt, tape);
   }
   return hip_check(ctx, hipGetLastError(), "mixed rhs");
+}
+
+size_t mixed_derivs_bytes(int64_t n, bool second) {
+  phb_ctx dummy;
+  Workspace ws(&dummy);
+  plan_mixed(ws, n, 8, second ? 9 : 3);
+  ws.plan((size_t)n * sizeof(double4));
+  ws.plan((size_t)8 * n * sizeof(double));
+  return ws.total;
 }
 
 int mixed_derivs(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields, double* d1,

@@ -115,14 +115,14 @@ __constant__ EntryTab c_tab = make_entry_tab();
 template <int NT>
 __global__ void __launch_bounds__(THREADS)
     k_factor(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
-             double* __restrict__ gop, int32_t* __restrict__ status) {
+             double* __restrict__ gop, int32_t* __restrict__ status, int interp) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   QuadChol c;
-  quad_chol_factor(c, c_tab, mom, n, ii, l);
+  quad_chol_factor(c, c_tab, mom, n, ii, l, interp != 0);
   const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
   // rows in lockstep groups of three
   sfor<0, NT / 3>([&](auto GI) {
@@ -147,14 +147,14 @@ template <int NR>
 __global__ void __launch_bounds__(THREADS)
     k_factor_solve(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
                    const double* __restrict__ rhs, double* __restrict__ x,
-                   int32_t* __restrict__ status) {
+                   int32_t* __restrict__ status, int interp) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   QuadChol c;
-  quad_chol_factor(c, c_tab, mom, n, ii, l);
+  quad_chol_factor(c, c_tab, mom, n, ii, l, interp != 0);
   const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
   sfor<0, NR>([&](auto RI) {
     constexpr int r = RI;
@@ -440,17 +440,19 @@ hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* m
 }
 
 hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
-                               const double* mom, const double* rhs, double* x, int32_t* status) {
+                               const double* mom, const double* rhs, double* x, int32_t* status,
+                               int fit) {
   const unsigned grid = grid_for((int64_t)n * 4, THREADS);
+  const int interp = fit == PHB_FIT_INTERP19;
   switch (nr) {
-    case 1: hipLaunchKernelGGL((k_factor_solve<1>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
-    case 2: hipLaunchKernelGGL((k_factor_solve<2>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
-    case 3: hipLaunchKernelGGL((k_factor_solve<3>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
-    case 4: hipLaunchKernelGGL((k_factor_solve<4>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
-    case 5: hipLaunchKernelGGL((k_factor_solve<5>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
-    case 6: hipLaunchKernelGGL((k_factor_solve<6>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
-    case 7: hipLaunchKernelGGL((k_factor_solve<7>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
-    default: hipLaunchKernelGGL((k_factor_solve<8>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status); break;
+    case 1: hipLaunchKernelGGL((k_factor_solve<1>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
+    case 2: hipLaunchKernelGGL((k_factor_solve<2>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
+    case 3: hipLaunchKernelGGL((k_factor_solve<3>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
+    case 4: hipLaunchKernelGGL((k_factor_solve<4>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
+    case 5: hipLaunchKernelGGL((k_factor_solve<5>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
+    case 6: hipLaunchKernelGGL((k_factor_solve<6>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
+    case 7: hipLaunchKernelGGL((k_factor_solve<7>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
+    default: hipLaunchKernelGGL((k_factor_solve<8>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
   }
   return hipGetLastError();
 }
@@ -458,10 +460,13 @@ hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,
                          double* gop, int32_t* status) {
   const unsigned grid = grid_for((int64_t)a.n * 4, THREADS);
+  const int interp = a.fit == PHB_FIT_INTERP19;
   if (ntargets == 3)
-    hipLaunchKernelGGL((k_factor<3>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status);
+    hipLaunchKernelGGL((k_factor<3>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status,
+                       interp);
   else
-    hipLaunchKernelGGL((k_factor<9>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status);
+    hipLaunchKernelGGL((k_factor<9>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status,
+                       interp);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "phurbas.h"
 #include "device.hpp"
 #include "mhd.hpp"
 
@@ -22,6 +23,7 @@ struct EvalArgs {
   Box box;
   double rf_ratio;
   int wkind;
+  int fit = PHB_FIT_FULL20;  // PHB_FIT_FULL20 or PHB_FIT_INTERP19
   const double4* geo = nullptr;
   const double* fq = nullptr;
 };
@@ -46,7 +48,8 @@ hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const d
                          double* gop, int32_t* status);
 // X = A^{-1} R for nr (1..8) right-hand sides given as SoA [nr][20][n].
 hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
-                               const double* mom, const double* rhs, double* x, int32_t* status);
+                               const double* mom, const double* rhs, double* x, int32_t* status,
+                               int fit);
 hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,
                                const int32_t* status, int nf, const double* fields, double* d1,
                                double* d2);
