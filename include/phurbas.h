@@ -216,11 +216,12 @@ int phb_evolve(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, int32_t 
                int64_t* offsets, int32_t* idx, int64_t idx_capacity, int64_t* nnz_out,
                int32_t* status);
 /* Courant time step: *dt_out (host) = cfl * min over non-frozen i of
- * lambda_i / (|V_i| + c_f,i (1 + 2 (visc_grid + visc_adapt + divb_diff))),
- * with the fast-speed bound c_f = sqrt((gamma P + |B|^2) / rho),
- * P = (gamma - 1) sigma (the paper's own time-step criteria live in its
- * companion paper); the stabilisers' diffusivities enter at their largest as
- * the speed 2 (zeta + eta) / lambda.  NaN entries are skipped.
+ * lambda_i / (c_f,i (1 + 2 (visc_grid + visc_adapt + divb_diff))),
+ * with the fast speed c_f = sqrt((gamma P + |B|^2) / rho), P = (gamma - 1)
+ * sigma (the paper's own time-step criteria live in its companion paper;
+ * Sec. 2 states that the steps do not depend on the bulk velocity); the
+ * stabilisers' diffusivities enter at their largest as the speed
+ * 2 (zeta + eta) / lambda.  NaN entries are skipped.
  * EINVAL if every particle is frozen or cfl <= 0.  Synchronizes. */
 int phb_courant_dt(phb_ctx* ctx, const phb_params* p, int64_t n, const double* q,
                    const double* lambda, const int32_t* frozen, double cfl, double* dt_out);

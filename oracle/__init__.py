@@ -298,7 +298,7 @@ def evolve(pos, lam, q, dt, nsteps, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma
 
 
 def courant_dt(q, lam, cfl=0.3, gamma=5.0 / 3.0, frozen=None, stab=None):
-    """cfl * min lambda / (|V| + c_fast (1 + 2 sum(stab))) over non-frozen particles."""
+    """cfl * min lambda / (c_fast (1 + 2 sum(stab))) over non-frozen particles."""
     q = _c(q, np.float64)
     lam = _c(lam, np.float64)
     fz = None if frozen is None else _c(frozen, np.int32)

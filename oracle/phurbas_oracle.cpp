@@ -1051,12 +1051,13 @@ int orc_evolve(int64_t n, double* pos, double* q, const double* lambda, const do
 }
 
 // Courant step: cfl * min over non-frozen particles of
-//   lambda / (|V| + c_f (1 + 2 (visc_grid + visc_adapt + divb_diff))),
+//   lambda / (c_f (1 + 2 (visc_grid + visc_adapt + divb_diff))),
 // c_f = sqrt((gamma P + B^2) / rho) with P = (gamma - 1) sigma (reading: the
-// paper's own criteria are in its companion paper).  The stabilisers'
-// diffusivities zeta, eta <= lambda c_f (coefficients) enter as the speed
-// 2 (zeta + eta) / lambda at their largest, so the step stays pointwise.
-// Returns -1 if no particle qualifies.
+// paper's own criteria are in its companion paper; Sec. 2 says the steps do
+// not depend on the bulk velocity, so the signal speed is c_f alone).  The
+// stabilisers' diffusivities zeta, eta <= lambda c_f (coefficients) enter as
+// the speed 2 (zeta + eta) / lambda at their largest, so the step stays
+// pointwise.  Returns -1 if no particle qualifies.
 double orc_courant_dt(int64_t n, const double* q, const double* lambda, double gamma,
                       const int32_t* frozen, double cfl, const double* stab) {
   const double csum = stab ? stab[0] + stab[1] + stab[2] : 0.0;
@@ -1064,12 +1065,11 @@ double orc_courant_dt(int64_t n, const double* q, const double* lambda, double g
   for (int64_t i = 0; i < n; ++i) {
     if (frozen && frozen[i]) continue;
     const double rho = q[i];
-    const double v2 = q[n + i] * q[n + i] + q[2 * n + i] * q[2 * n + i] + q[3 * n + i] * q[3 * n + i];
     const double b2 = q[4 * n + i] * q[4 * n + i] + q[5 * n + i] * q[5 * n + i] +
                       q[6 * n + i] * q[6 * n + i];
     const double P = (gamma - 1.0) * q[7 * n + i];
     const double cf = std::sqrt((gamma * P + b2) / rho);
-    const double t = lambda[i] / (std::sqrt(v2) + cf * (1.0 + 2.0 * csum));
+    const double t = lambda[i] / (cf * (1.0 + 2.0 * csum));
     if (std::isnan(t)) continue;
     if (best < 0.0 || t < best) best = t;
   }

@@ -249,61 +249,67 @@ __global__ void __launch_bounds__(THREADS)
 // 141 doubles do not fit the scalar registers).
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-__device__ __forceinline__ void row_value_grad(const double* __restrict__ c,
-                                               const double (&p)[NBASIS], double& v,
-                                               double (&g)[3]) {
-  v = 0.0;
+template <class CT>
+__device__ __forceinline__ void row_value_grad(const CT* __restrict__ c, const CT (&p)[NBASIS],
+                                               CT& v, CT (&g)[3]) {
+  v = CT(0);
 #pragma unroll
   for (int b = 0; b < NBASIS; ++b) v = fma(c[b], p[b], v);
-  g[0] = c[1] + 2.0 * p[1] * c[4] + p[2] * c[5] + p[3] * c[6] + 3.0 * p[4] * c[10] +
-         2.0 * p[5] * c[11] + 2.0 * p[6] * c[12] + p[7] * c[13] + p[8] * c[14] + p[9] * c[15];
-  g[1] = c[2] + p[1] * c[5] + 2.0 * p[2] * c[7] + p[3] * c[8] + p[4] * c[11] +
-         2.0 * p[5] * c[13] + p[6] * c[14] + 3.0 * p[7] * c[16] + 2.0 * p[8] * c[17] +
+  const CT two = CT(2), three = CT(3);
+  g[0] = c[1] + two * p[1] * c[4] + p[2] * c[5] + p[3] * c[6] + three * p[4] * c[10] +
+         two * p[5] * c[11] + two * p[6] * c[12] + p[7] * c[13] + p[8] * c[14] + p[9] * c[15];
+  g[1] = c[2] + p[1] * c[5] + two * p[2] * c[7] + p[3] * c[8] + p[4] * c[11] +
+         two * p[5] * c[13] + p[6] * c[14] + three * p[7] * c[16] + two * p[8] * c[17] +
          p[9] * c[18];
-  g[2] = c[3] + p[1] * c[6] + p[2] * c[8] + 2.0 * p[3] * c[9] + p[4] * c[12] + p[5] * c[14] +
-         2.0 * p[6] * c[15] + p[7] * c[17] + 2.0 * p[8] * c[18] + 3.0 * p[9] * c[19];
+  g[2] = c[3] + p[1] * c[6] + p[2] * c[8] + two * p[3] * c[9] + p[4] * c[12] + p[5] * c[14] +
+         two * p[6] * c[15] + p[7] * c[17] + two * p[8] * c[18] + three * p[9] * c[19];
 }
 
-__device__ __forceinline__ void pair_terms(const double* __restrict__ o, double w, double dw,
+// CT: the arithmetic type of the pair terms (FP64, or FP32 in the mixed
+// form).  The displacement, the weight and the field differences are formed
+// in FP64 and rounded once.
+template <class CT>
+__device__ __forceinline__ void pair_terms(const CT* __restrict__ o, double w, double dw,
                                            double inv_lam, double inv_r2, double dx, double dy,
                                            double dz, const double* __restrict__ fi,
-                                           const double* __restrict__ fj, double (&v)[REC]) {
-  double p[NBASIS];
-  basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-  double df[7];
+                                           const double* __restrict__ fj, CT (&v)[REC]) {
+  CT p[NBASIS];
+  basis(p, CT(dx * inv_lam), CT(dy * inv_lam), CT(dz * inv_lam));
+  CT df[7];
 #pragma unroll
-  for (int f = 0; f < 7; ++f) df[f] = fj[f + 1] - fi[f + 1];
-  double h[3] = {0.0, 0.0, 0.0};
+  for (int f = 0; f < 7; ++f) df[f] = CT(fj[f + 1] - fi[f + 1]);
+  CT h[3] = {CT(0), CT(0), CT(0)};
 #pragma unroll
   for (int f = 0; f < 7; ++f)
 #pragma unroll
     for (int t = 0; t < 3; ++t) h[t] = fma(o[UOFF + 3 * f + t], df[f], h[t]);
-  double av[3], bv[3], xg[3] = {0.0, 0.0, 0.0};
+  CT av[3], bv[3], xg[3] = {CT(0), CT(0), CT(0)};
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
     compiler_fence();
-    double a, ga[3];
+    CT a, ga[3];
     row_value_grad(o + t * NBASIS, p, a, ga);
     compiler_fence();
-    double k, gk[3];
+    CT k, gk[3];
     row_value_grad(o + 60 + t * NBASIS, p, k, gk);
-    const double b = h[t] - k;
+    const CT b = h[t] - k;
 #pragma unroll
     for (int c = 0; c < 3; ++c) xg[c] = fma(b, ga[c], fma(-a, gk[c], xg[c]));
     av[t] = a;
     bv[t] = b;
   }
   compiler_fence();
+  const CT wc = CT(w);
 #pragma unroll
   for (int f = 0; f < 7; ++f)
-    v[f] = w * (o[UOFF + 3 * f] * av[0] + o[UOFF + 3 * f + 1] * av[1] +
-                o[UOFF + 3 * f + 2] * av[2]);
-  const double wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
-  const double geo_f = wbar * dw * 2.0 * inv_r2;
-  const double wl = w * inv_lam;
-  v[7] = fma(wl, xg[0], geo_f * dx);
-  v[8] = fma(wl, xg[1], geo_f * dy);
-  v[9] = fma(wl, xg[2], geo_f * dz);
+    v[f] = wc * (o[UOFF + 3 * f] * av[0] + o[UOFF + 3 * f + 1] * av[1] +
+                 o[UOFF + 3 * f + 2] * av[2]);
+  const CT wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
+  const CT geo_f = wbar * CT(dw * 2.0 * inv_r2);
+  const CT wl = CT(w * inv_lam);
+  v[7] = fma(wl, xg[0], geo_f * CT(dx));
+  v[8] = fma(wl, xg[1], geo_f * CT(dy));
+  v[9] = fma(wl, xg[2], geo_f * CT(dz));
 }
 
 // One lane per neighbor entry: a block takes 256 consecutive entries, so
@@ -490,7 +496,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // RT: type of the pair records (double; float in the mixed form, where the
 // records are an application-level quantity and halve the record traffic).
-template <class RT>
+// CT: arithmetic type of the pair terms.  FP64 in both forms: in FP32 the
+// difference b = Ubar df - K p, which is Ubar times the fit's residual, and
+// the cancelling sums of the records over a particle's owners lose up to
+// 1e-3 of the gradient on the 1M shear layer (sharp layers, 4x lambda range).
+template <class RT, class CT = double>
 __global__ void __launch_bounds__(THREADS)
     k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                   const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
@@ -501,10 +511,10 @@ __global__ void __launch_bounds__(THREADS)
   const int lane = threadIdx.x & 63;
   // the owner record goes to LDS in one coalesced load per wavefront; the
   // pair terms then read it row by row at LDS latency
-  __shared__ double osh[THREADS / 64][OREC];
+  __shared__ CT osh[THREADS / 64][OREC];
   const int wv = threadIdx.x >> 6;
   if (i < n) {
-    for (int k = lane; k < OREC; k += 64) osh[wv][k] = orec[(int64_t)i * OREC + k];
+    for (int k = lane; k < OREC; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OREC + k]);
   }
   __syncthreads();
   if (i >= n) return;  // whole wavefronts leave together
@@ -513,16 +523,16 @@ __global__ void __launch_bounds__(THREADS)
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
-  const double* o = osh[wv];
+  const CT* o = osh[wv];
   const double* fi = fq + 8 * (int64_t)i;
   double acc[REC];
 #pragma unroll
   for (int c = 0; c < REC; ++c) acc[c] = 0.0;
   for (int64_t s = rs + lane; s < re; s += 64) {
     const int j = idx[s];
-    double v[REC];
+    CT v[REC];
 #pragma unroll
-    for (int c = 0; c < REC; ++c) v[c] = 0.0;
+    for (int c = 0; c < REC; ++c) v[c] = CT(0);
     if (j != i) {
       const double4 gj = geo[j];
       const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);

@@ -71,12 +71,11 @@ __global__ void __launch_bounds__(THREADS)
   for (int i = blockIdx.x * THREADS + threadIdx.x; i < n; i += gridDim.x * THREADS) {
     if (frozen && frozen[i]) continue;
     const double rho = q[i];
-    const double vx = q[(int64_t)n + i], vy = q[2 * (int64_t)n + i], vz = q[3 * (int64_t)n + i];
     const double bx = q[4 * (int64_t)n + i], by = q[5 * (int64_t)n + i],
                  bz = q[6 * (int64_t)n + i];
     const double pr = (gamma - 1.0) * q[7 * (int64_t)n + i];
     const double cf = sqrt((gamma * pr + bx * bx + by * by + bz * bz) / rho);
-    const double t = lam[i] / (sqrt(vx * vx + vy * vy + vz * vz) + cf * cmul);
+    const double t = lam[i] / (cf * cmul);
     m = fmin(m, t);
   }
   sm[threadIdx.x] = m;

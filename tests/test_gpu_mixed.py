@@ -170,3 +170,28 @@ def test_autograd_mixed_matches_fp64():
         out.append((gq.cpu().numpy(), gp.cpu().numpy()))
     assert grad_err(out[1][0], out[0][0]) < TOLMIX
     assert grad_err(out[1][1], out[0][1]) < TOLMIX
+
+
+def test_adjoint_shear_layer_full_size_matches_fp64():
+    """The whole 1M shear layer (sharp layers, 4x lambda range): the mixed
+    reverse mode of the benchmark loss against the FP64 form, which matches
+    the oracle to 1e-12 on sampled particles."""
+    import torch
+    c = synth.config3()
+    n = c["lam"].shape[0]
+    pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
+    w = torch.tensor(np.random.default_rng(4).uniform(size=n)).cuda()
+    s64 = setup_of(c)
+    off, idx = P.neighbors(pos, lam, s64)
+    tr = P.transpose(off, idx)
+    out = []
+    for prec in (P.PHB_FP64, P.PHB_MIXED):
+        s = setup_of(c, precision=prec)
+        rhs, _, st, tape = P.mhd_rhs(pos, lam, off, idx, q, s, tape=True)
+        gbar = 2.0 * w * rhs
+        gbar[:, st != 0] = 0.0
+        qb, pb = P.mhd_rhs_adjoint(pos, lam, off, idx, tr, q, gbar, None, setup=s, tape=tape)
+        out.append((qb.cpu().numpy(), pb.cpu().numpy()))
+    eq, ep = grad_err(out[1][0], out[0][0]), grad_err(out[1][1], out[0][1])
+    print(f"1M shear layer, mixed vs FP64 reverse mode: q_bar {eq:.2e}, pos_bar {ep:.2e}")
+    assert eq < TOLMIX and ep < TOLMIX
