@@ -60,7 +60,7 @@ def parse():
                     help="target wall time of the CPU oracle sample")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-stab", action="store_true",
-                    help="skip the forward timing with the non-ideal stabilisers on")
+                    help="skip the timing with the non-ideal stabilisers on")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times (a plain "
                          "copy of known size, to calibrate hardware byte counters)")
@@ -350,20 +350,29 @@ def main():
             def fwd_stab():
                 P.phb_mhd_rhs(ss, pos, lam, off, idx, q, rhs, dxdt, st, tape)
 
-            for _ in range(args.warmup):
+            def step_stab():
                 fwd_stab()
+                torch.mul(rhs, w, out=gbar)
+                gbar.mul_(2.0)
+                P.phb_mhd_rhs_adjoint(ss, pos, lam, off, idx, *trans, q, gbar, None, q_bar,
+                                      pos_bar, tape)
+
+            for _ in range(args.warmup):
+                step_stab()
             ms = time_gpu(fwd_stab, max(3, args.steps // 2), torch)
+            ms_step = time_gpu(step_stab, max(3, args.steps // 2), torch)
             r = {"forward_ms": ms, "forward_updates_per_s": n / (ms / 1e3),
+                 "ms_per_step": ms_step, "updates_per_s": n / (ms_step / 1e3),
                  "failed_particles": int((st != 0).sum().item())}
             if not args.no_profile:
                 P.phb_profile(True)
                 for _ in range(3):
-                    fwd_stab()
+                    step_stab()
                 prof = P.phb_profile_read()
                 P.phb_profile(False)
                 r["kernels_ms"] = {k: v[0] / v[1] for k, v in prof.items()}
             stab[form] = r
-            log(f"[{form}] stabilised forward {ms:.3f} ms")
+            log(f"[{form}] stabilised forward {ms:.3f} ms, forward + reverse {ms_step:.3f} ms")
 
     # deviation of the mixed form from the FP64 form (both on this GPU)
     deviation = None
@@ -471,7 +480,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched_graph": batch,
-        "stabilised_forward": stab,
+        "stabilised": stab,
         "extra": {"neighbor_build_ms": nb_ms, "transpose_ms": tr_ms,
                   "spatial_order_setup_ms": order_ms, "source_digest": source_digest()},
     }

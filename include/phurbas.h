@@ -99,8 +99,8 @@ typedef struct {
    *   dV/dt += zeta grad div V,  dB/dt += eta grad div B,
    *   dsigma/dt += rho zeta (div V)^2,
    * zeta and eta held constant over each neighborhood.  Each must be finite
-   * and >= 0 (else PHB_EINVAL).  The forward calls support them in both
-   * precisions; the reverse mode returns PHB_ENOTIMPL when any is nonzero. */
+   * and >= 0 (else PHB_EINVAL).  Every call supports them, in both
+   * precisions, the reverse mode included. */
   double visc_grid;
   double visc_adapt;
   double divb_diff;

@@ -31,12 +31,28 @@ namespace phb {
 namespace {
 
 constexpr int THREADS = 256;
-constexpr int REC = 10;  // doubles per pair record: dfbar (7), dbar (3)
-// Per-owner record of the pair kernel (one 1152-byte block per particle, so a
-// wavefront's lanes that share an owner read a few cache lines):
-// G (3 x 20) at 0, K (3 x 20) at 60, Ubar (7 x 3) at 120, padding to 144.
-constexpr int OREC = 144;
-constexpr int UOFF = 120;
+// Shapes of the reverse pass.  Ideal MHD: three operator rows (the gradient)
+// applied to V, B and sigma.  With the stabilisers: nine rows (the gradient,
+// then xx, xy, xz, yy, yz, zz) applied to all eight fields (rho's gradient
+// feeds the sensor).  Per-owner record of the pair kernel: G (NR x 20) at 0,
+// K (NR x 20) at KOFF, Ubar [NFA][NR] at UOFF; one 1152-byte block per
+// particle in the ideal shape, 3456 bytes with the stabilisers.  Pair record:
+// dfbar (NFA), dbar (3), padded to an even count for paired stores.
+template <bool STAB>
+struct Shape {
+  static constexpr int NR = STAB ? 9 : 3;
+  static constexpr int NFA = STAB ? 8 : 7;
+  static constexpr int F0 = 8 - NFA;
+  static constexpr int REC = STAB ? 12 : 10;
+  static constexpr int KOFF = NR * NBASIS;
+  static constexpr int UOFF = 2 * NR * NBASIS;
+  static constexpr int OREC = STAB ? 432 : 144;
+  static_assert(UOFF + NFA * NR <= OREC && NFA + 3 <= REC && REC % 2 == 0, "record shape");
+};
+// the ideal shape, used by the lane-per-entry schedule
+constexpr int REC = Shape<false>::REC;
+constexpr int OREC = Shape<false>::OREC;
+constexpr int UOFF = Shape<false>::UOFF;
 constexpr int PAIRS_PER_BLOCK = 256;
 
 // Pointwise adjoint of particle i; returns Ubar (coefficient space) and adds
@@ -75,6 +91,81 @@ __device__ __forceinline__ void pointwise_adjoint(int n, int i, const double* __
   for (int f = 0; f < 7; ++f)
 #pragma unroll
     for (int t = 0; t < 3; ++t) ub[f][t] = gb[f][t] * inv_lam;
+}
+
+// The same with the stabilisers: Ubar [8][9] (rows: the gradient, then the
+// second-derivative rows xx, xy, xz, yy, yz, zz, in coefficient space).  With
+// D_k[f] = fac_k (row_k . B_f) / lambda^2 (fac = 2 on the diagonal), grad div V
+// is d_a div V = sum_b D_(ab)[V_b]; its adjoint reaches D_(ab)[V_b] and,
+// for a != b, D_(ab)[V_a].
+__device__ __forceinline__ void pointwise_adjoint_stab(int n, int i, const double* __restrict__ q,
+                                                       const double* __restrict__ tape,
+                                                       const double* __restrict__ rhs_bar,
+                                                       const double* __restrict__ dxdt_bar,
+                                                       double gamma, double lam, const Stab& sb,
+                                                       int st, double (&qi)[8],
+                                                       double (&ub)[8][9], double (&qb)[8]) {
+#pragma unroll
+  for (int f = 0; f < 8; ++f) {
+    qi[f] = q[(int64_t)f * n + i];
+    qb[f] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) ub[f][t] = 0.0;
+  }
+  if (dxdt_bar) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) qb[1 + a] += dxdt_bar[(int64_t)a * n + i];
+  }
+  if (st != 0) return;
+  double grad[7][3], ob[8], grho[3], gdv[3], gdb[3];
+#pragma unroll
+  for (int f = 0; f < 7; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) grad[f][t] = tape[((int64_t)f * 3 + t) * n + i];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    grho[a] = tape[(int64_t)(TAPE_GRHO + a) * n + i];
+    gdv[a] = tape[(int64_t)(TAPE_GDV + a) * n + i];
+    gdb[a] = tape[(int64_t)(TAPE_GDB + a) * n + i];
+  }
+#pragma unroll
+  for (int f = 0; f < 8; ++f) ob[f] = rhs_bar[(int64_t)f * n + i];
+  double gb[7][3];
+  mhd_point_adjoint(qi, grad, gamma, ob, qb, gb);
+  double grho_b[3] = {0.0, 0.0, 0.0}, gdv_b[3] = {0.0, 0.0, 0.0}, gdb_b[3] = {0.0, 0.0, 0.0};
+  const double divv_b = stab_point_adjoint(qi, grho, grad[0][0] + grad[1][1] + grad[2][2], gdv,
+                                           gdb, lam, gamma, sb, ob, qb, grho_b, gdv_b, gdb_b);
+  gb[0][0] += divv_b;
+  gb[1][1] += divv_b;
+  gb[2][2] += divv_b;
+  const double inv_lam = 1.0 / lam;
+  const double il2 = inv_lam * inv_lam;
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    ub[0][t] = grho_b[t] * inv_lam;
+#pragma unroll
+    for (int f = 0; f < 7; ++f) ub[1 + f][t] = gb[f][t] * inv_lam;
+  }
+  // second-derivative row k = (a0, a1)
+  constexpr int A0[6] = {0, 0, 0, 1, 1, 2}, A1[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double fac = (A0[k] == A1[k] ? 2.0 : 1.0) * il2;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      double cv = 0.0, cb = 0.0;
+      if (b == A0[k]) {
+        cv += gdv_b[A1[k]];
+        cb += gdb_b[A1[k]];
+      }
+      if (b == A1[k] && A0[k] != A1[k]) {
+        cv += gdv_b[A0[k]];
+        cb += gdb_b[A0[k]];
+      }
+      ub[1 + b][3 + k] = fac * cv;
+      ub[4 + b][3 + k] = fac * cb;
+    }
+  }
 }
 
 // ---- 2. Y = sum_j w_j p_j (Ubar df_j)^T, plus Ubar and the direct qbar ------
@@ -186,12 +277,112 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
+// The stabilised shape in two steps: k_adj_u (one thread per particle) writes
+// Ubar [8][9] into the owner record and the direct qbar; k_adj_yrows then
+// accumulates three rows of Y at a time (60 accumulators per lane, as in the
+// ideal kernel), launched for rows 0..2, 3..5 and 6..8.
+using S9 = Shape<true>;
+
+__global__ void __launch_bounds__(THREADS)
+    k_adj_u(int n, const double4* __restrict__ geo, double gamma, Stab sb,
+            const double* __restrict__ q, const double* __restrict__ tape,
+            const double* __restrict__ rhs_bar, const double* __restrict__ dxdt_bar,
+            double* __restrict__ orec, double* __restrict__ qb_direct) {
+  const int i = blockIdx.x * THREADS + threadIdx.x;
+  if (i >= n) return;
+  const int st = (int)tape[(int64_t)TAPE_STATUS * n + i];
+  double qi[8], ub[8][9], qb[8];
+  pointwise_adjoint_stab(n, i, q, tape, rhs_bar, dxdt_bar, gamma, geo[i].w, sb, st, qi, ub, qb);
+#pragma unroll
+  for (int f = 0; f < 8; ++f)
+#pragma unroll
+    for (int t = 0; t < 9; ++t) orec[(int64_t)i * S9::OREC + S9::UOFF + f * 9 + t] = ub[f][t];
+#pragma unroll
+  for (int f = 0; f < 8; ++f) qb_direct[(int64_t)f * n + i] = qb[f];
+}
+
+template <int G>
+__global__ void __launch_bounds__(THREADS)
+    k_adj_yrows(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
+                const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
+                double rf_ratio, int wkind, const double* __restrict__ tape,
+                const double* __restrict__ orec, int r0, double* __restrict__ ybuf) {
+  const int tid = xcd_block() * THREADS + threadIdx.x;
+  const int i = tid / G;
+  const int l = tid % G;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  const double4 gi = geo[ii];
+  const double inv_lam = 1.0 / gi.w;
+  const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
+  // Ubar rows r0..r0+2 of the eight fields (24 values) in LDS
+  constexpr int PPB = THREADS / G;
+  __shared__ double2 ush[12][PPB];
+  const int pl = threadIdx.x / G;
+  for (int k = l; k < 12; k += G) {
+    const int e0 = 2 * k, e1 = 2 * k + 1;
+    const double* u = orec + (int64_t)ii * S9::OREC + S9::UOFF;
+    ush[k][pl] = make_double2(u[(e0 / 3) * 9 + r0 + e0 % 3], u[(e1 / 3) * 9 + r0 + e1 % 3]);
+  }
+  __syncthreads();
+  double qi[8];
+  load_fields(fq, ii, qi);
+  const double r = rf_ratio * gi.w;
+  const double inv_r2 = 1.0 / (r * r);
+  double y[3][NBASIS];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) y[t][b] = 0.0;
+  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
+  for (int64_t s = s0 + l; s < s1; s += G) {
+    const int j = idx[s];
+    const double4 gj = geo[j];
+    double qj[8];
+    load_fields(fq, j, qj);
+    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+    const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+    double p[NBASIS];
+    basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    double h[3] = {0.0, 0.0, 0.0};
+    asm volatile("" ::: "memory");  // re-read Ubar from LDS every iteration
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double2 u = ush[k][pl];
+      const int e0 = 2 * k, e1 = 2 * k + 1;
+      h[e0 % 3] = fma(u.x, qj[e0 / 3] - qi[e0 / 3], h[e0 % 3]);
+      h[e1 % 3] = fma(u.y, qj[e1 / 3] - qi[e1 / 3], h[e1 % 3]);
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const double wh = w * h[t];
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b) y[t][b] = fma(wh, p[b], y[t][b]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) y[t][b] = group_sum<G>(y[t][b]);
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b)
+        if ((t * NBASIS + b) % G == l) ybuf[((int64_t)(r0 + t) * NBASIS + b) * n + i] = y[t][b];
+  }
+}
+
 // ---- 3. factor again: G = rows 1..3 of A^{-1}, K_t = A^{-1} Y_t ------------
 __constant__ EntryTab c_tab_a = make_entry_tab();
 
+template <bool STAB>
 __global__ void __launch_bounds__(THREADS)
     k_adj_factor(int n, const double* __restrict__ mom, const double* __restrict__ ybuf,
                  const double* __restrict__ tape, double* __restrict__ gop, int interp) {
+  using SH = Shape<STAB>;
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
@@ -200,26 +391,29 @@ __global__ void __launch_bounds__(THREADS)
   QuadChol c;
   quad_chol_factor(c, c_tab_a, mom, n, ii, l, interp != 0);
   const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
-  // G rows at 0..59 and K rows at 60..119 of the owner record; each group of
-  // three solves runs in lockstep
-  {
+  // G rows at 0 and K rows at KOFF of the owner record, in lockstep groups of
+  // three solves
+  sfor<0, SH::NR / 3>([&](auto GI) {
+    constexpr int g0 = 3 * GI;
     double out[3][5];
-    quad_chol_inverse_rows<1, 3>(c, l, out);
+    quad_chol_inverse_rows<1 + g0, 3>(c, l, out);
     if (valid) {
 #pragma unroll
       for (int rh = 0; rh < 3; ++rh)
 #pragma unroll
         for (int rho = 0; rho < 5; ++rho)
-          gop[(int64_t)i * OREC + rh * NBASIS + 4 * rho + l] = st == 0 ? out[rh][rho] : 0.0;
+          gop[(int64_t)i * SH::OREC + (g0 + rh) * NBASIS + 4 * rho + l] =
+              st == 0 ? out[rh][rho] : 0.0;
     }
-  }
-  {
+  });
+  sfor<0, SH::NR / 3>([&](auto GI) {
+    constexpr int g0 = 3 * GI;
     double y[3][5], out[3][5];
 #pragma unroll
     for (int rh = 0; rh < 3; ++rh)
 #pragma unroll
       for (int rho = 0; rho < 5; ++rho)
-        y[rh][rho] = ybuf[((int64_t)rh * NBASIS + 4 * rho + l) * n + ii] * c.s_own[rho];
+        y[rh][rho] = ybuf[((int64_t)(g0 + rh) * NBASIS + 4 * rho + l) * n + ii] * c.s_own[rho];
     // interpolating fit: Y's constant entry belongs to no basis function
     if (interp && l == 0)
 #pragma unroll
@@ -230,10 +424,10 @@ __global__ void __launch_bounds__(THREADS)
       for (int rh = 0; rh < 3; ++rh)
 #pragma unroll
         for (int rho = 0; rho < 5; ++rho)
-          gop[(int64_t)i * OREC + (3 + rh) * NBASIS + 4 * rho + l] =
+          gop[(int64_t)i * SH::OREC + SH::KOFF + (g0 + rh) * NBASIS + 4 * rho + l] =
               st == 0 ? out[rh][rho] * c.s_own[rho] : 0.0;
     }
-  }
+  });
 }
 
 // ---- 4. pair contributions ---------------------------------------------------
@@ -265,33 +459,37 @@ __device__ __forceinline__ void row_value_grad(const CT* __restrict__ c, const C
          two * p[6] * c[15] + p[7] * c[17] + two * p[8] * c[18] + three * p[9] * c[19];
 }
 
-// CT: the arithmetic type of the pair terms (FP64, or FP32 in the mixed
-// form).  The displacement, the weight and the field differences are formed
-// in FP64 and rounded once.
-template <class CT>
+// CT: the arithmetic type of the pair terms.  The displacement, the weight and
+// the field differences are formed in FP64 and rounded once.  STAB: the
+// stabilised shape (nine rows, eight fields).
+template <class CT, bool STAB = false>
 __device__ __forceinline__ void pair_terms(const CT* __restrict__ o, double w, double dw,
                                            double inv_lam, double inv_r2, double dx, double dy,
                                            double dz, const double* __restrict__ fi,
-                                           const double* __restrict__ fj, CT (&v)[REC]) {
+                                           const double* __restrict__ fj,
+                                           CT (&v)[Shape<STAB>::REC]) {
+  using SH = Shape<STAB>;
   CT p[NBASIS];
   basis(p, CT(dx * inv_lam), CT(dy * inv_lam), CT(dz * inv_lam));
-  CT df[7];
+  CT df[SH::NFA];
 #pragma unroll
-  for (int f = 0; f < 7; ++f) df[f] = CT(fj[f + 1] - fi[f + 1]);
-  CT h[3] = {CT(0), CT(0), CT(0)};
+  for (int f = 0; f < SH::NFA; ++f) df[f] = CT(fj[SH::F0 + f] - fi[SH::F0 + f]);
+  CT h[SH::NR];
 #pragma unroll
-  for (int f = 0; f < 7; ++f)
+  for (int t = 0; t < SH::NR; ++t) h[t] = CT(0);
 #pragma unroll
-    for (int t = 0; t < 3; ++t) h[t] = fma(o[UOFF + 3 * f + t], df[f], h[t]);
-  CT av[3], bv[3], xg[3] = {CT(0), CT(0), CT(0)};
+  for (int f = 0; f < SH::NFA; ++f)
 #pragma unroll
-  for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < SH::NR; ++t) h[t] = fma(o[SH::UOFF + SH::NR * f + t], df[f], h[t]);
+  CT av[SH::NR], bv[SH::NR], xg[3] = {CT(0), CT(0), CT(0)};
+#pragma unroll
+  for (int t = 0; t < SH::NR; ++t) {
     compiler_fence();
     CT a, ga[3];
     row_value_grad(o + t * NBASIS, p, a, ga);
     compiler_fence();
     CT k, gk[3];
-    row_value_grad(o + 60 + t * NBASIS, p, k, gk);
+    row_value_grad(o + SH::KOFF + t * NBASIS, p, k, gk);
     const CT b = h[t] - k;
 #pragma unroll
     for (int c = 0; c < 3; ++c) xg[c] = fma(b, ga[c], fma(-a, gk[c], xg[c]));
@@ -301,15 +499,22 @@ __device__ __forceinline__ void pair_terms(const CT* __restrict__ o, double w, d
   compiler_fence();
   const CT wc = CT(w);
 #pragma unroll
-  for (int f = 0; f < 7; ++f)
-    v[f] = wc * (o[UOFF + 3 * f] * av[0] + o[UOFF + 3 * f + 1] * av[1] +
-                 o[UOFF + 3 * f + 2] * av[2]);
-  const CT wbar = av[0] * bv[0] + av[1] * bv[1] + av[2] * bv[2];
+  for (int f = 0; f < SH::NFA; ++f) {
+    CT u = o[SH::UOFF + SH::NR * f] * av[0];
+#pragma unroll
+    for (int t = 1; t < SH::NR; ++t) u = fma(o[SH::UOFF + SH::NR * f + t], av[t], u);
+    v[f] = wc * u;
+  }
+  CT wbar = av[0] * bv[0];
+#pragma unroll
+  for (int t = 1; t < SH::NR; ++t) wbar = fma(av[t], bv[t], wbar);
   const CT geo_f = wbar * CT(dw * 2.0 * inv_r2);
   const CT wl = CT(w * inv_lam);
-  v[7] = fma(wl, xg[0], geo_f * CT(dx));
-  v[8] = fma(wl, xg[1], geo_f * CT(dy));
-  v[9] = fma(wl, xg[2], geo_f * CT(dz));
+  v[SH::NFA] = fma(wl, xg[0], geo_f * CT(dx));
+  v[SH::NFA + 1] = fma(wl, xg[1], geo_f * CT(dy));
+  v[SH::NFA + 2] = fma(wl, xg[2], geo_f * CT(dz));
+#pragma unroll
+  for (int c = SH::NFA + 3; c < SH::REC; ++c) v[c] = CT(0);
 }
 
 // One lane per neighbor entry: a block takes 256 consecutive entries, so
@@ -500,21 +705,22 @@ __device__ __forceinline__ double wave_sum(double v) {
 // difference b = Ubar df - K p, which is Ubar times the fit's residual, and
 // the cancelling sums of the records over a particle's owners lose up to
 // 1e-3 of the gradient on the 1M shear layer (sharp layers, 4x lambda range).
-template <class RT, class CT = double>
+template <class RT, class CT = double, bool STAB = false>
 __global__ void __launch_bounds__(THREADS)
     k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                   const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
                   double rf_ratio, int wkind, const double* __restrict__ fq,
                   const double* __restrict__ orec, RT* __restrict__ rec,
                   double* __restrict__ own, int slot_order) {
+  constexpr int OR = Shape<STAB>::OREC, RC = Shape<STAB>::REC;
   const int i = __builtin_amdgcn_readfirstlane(xcd_block() * (THREADS / 64) + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   // the owner record goes to LDS in one coalesced load per wavefront; the
   // pair terms then read it row by row at LDS latency
-  __shared__ CT osh[THREADS / 64][OREC];
+  __shared__ CT osh[THREADS / 64][OR];
   const int wv = threadIdx.x >> 6;
   if (i < n) {
-    for (int k = lane; k < OREC; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OREC + k]);
+    for (int k = lane; k < OR; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OR + k]);
   }
   __syncthreads();
   if (i >= n) return;  // whole wavefronts leave together
@@ -525,14 +731,14 @@ __global__ void __launch_bounds__(THREADS)
   const double inv_r2 = 1.0 / (r * r);
   const CT* o = osh[wv];
   const double* fi = fq + 8 * (int64_t)i;
-  double acc[REC];
+  double acc[RC];
 #pragma unroll
-  for (int c = 0; c < REC; ++c) acc[c] = 0.0;
+  for (int c = 0; c < RC; ++c) acc[c] = 0.0;
   for (int64_t s = rs + lane; s < re; s += 64) {
     const int j = idx[s];
-    CT v[REC];
+    CT v[RC];
 #pragma unroll
-    for (int c = 0; c < REC; ++c) v[c] = CT(0);
+    for (int c = 0; c < RC; ++c) v[c] = CT(0);
     if (j != i) {
       const double4 gj = geo[j];
       const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
@@ -541,27 +747,27 @@ __global__ void __launch_bounds__(THREADS)
       const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
       const double w = weight_of(qd, wkind);
       const double dw = weight_dq(qd, wkind);
-      pair_terms(o, w, dw, inv_lam, inv_r2, dx, dy, dz, fi, fq + 8 * (int64_t)j, v);
+      pair_terms<CT, STAB>(o, w, dw, inv_lam, inv_r2, dx, dy, dz, fi, fq + 8 * (int64_t)j, v);
     }
-    RT* out = rec + (slot_order ? s : (int64_t)t_pos[s]) * REC;
+    RT* out = rec + (slot_order ? s : (int64_t)t_pos[s]) * RC;
     if constexpr (sizeof(RT) == 8) {
       double2* o2 = reinterpret_cast<double2*>(out);
 #pragma unroll
-      for (int c = 0; c < REC; c += 2) o2[c / 2] = make_double2(v[c], v[c + 1]);
+      for (int c = 0; c < RC; c += 2) o2[c / 2] = make_double2(v[c], v[c + 1]);
     } else {
       float2* o2 = reinterpret_cast<float2*>(out);
 #pragma unroll
-      for (int c = 0; c < REC; c += 2) o2[c / 2] = make_float2((float)v[c], (float)v[c + 1]);
+      for (int c = 0; c < RC; c += 2) o2[c / 2] = make_float2((float)v[c], (float)v[c + 1]);
     }
 #pragma unroll
-    for (int c = 0; c < REC; ++c) acc[c] += v[c];
+    for (int c = 0; c < RC; ++c) acc[c] += v[c];
   }
 #pragma unroll
-  for (int c = 0; c < REC; ++c) acc[c] = wave_sum(acc[c]);
-  if (lane < REC) {
+  for (int c = 0; c < RC; ++c) acc[c] = wave_sum(acc[c]);
+  if (lane < RC) {
     double mine = acc[0];
 #pragma unroll
-    for (int c = 1; c < REC; ++c) mine = lane == c ? acc[c] : mine;
+    for (int c = 1; c < RC; ++c) mine = lane == c ? acc[c] : mine;
     own[(int64_t)lane * n + i] = -mine;
   }
 }
@@ -576,12 +782,14 @@ __global__ void __launch_bounds__(THREADS)
 // ---- 5. gather over the transposed lists ------------------------------------
 // G lanes share one particle's transposed row; their partial sums meet in a
 // quad reduction.  The summation order is fixed for a given G.
-template <int G, class RT>
+template <int G, class RT, bool STAB = false>
 __global__ void __launch_bounds__(THREADS)
     k_adj_gather(int n, const int64_t* __restrict__ t_off, const int32_t* __restrict__ t_slot,
                  const RT* __restrict__ rec, const double* __restrict__ own,
                  const double* __restrict__ qb_direct, double* __restrict__ q_bar,
                  double* __restrict__ pos_bar) {
+  using SH = Shape<STAB>;
+  constexpr int REC = SH::REC;
   const int tid = xcd_block() * THREADS + threadIdx.x;
   const int j = tid / G;
   const int l = tid % G;
@@ -616,12 +824,12 @@ __global__ void __launch_bounds__(THREADS)
   if (!valid || l != 0) return;
 #pragma unroll
   for (int c = 0; c < REC; ++c) acc[c] += own[(int64_t)c * n + j];
-  q_bar[j] = qb_direct[j];
+  if (SH::F0 == 1) q_bar[j] = qb_direct[j];
 #pragma unroll
-  for (int f = 0; f < 7; ++f)
-    q_bar[(int64_t)(f + 1) * n + j] = qb_direct[(int64_t)(f + 1) * n + j] + acc[f];
+  for (int f = 0; f < SH::NFA; ++f)
+    q_bar[(int64_t)(f + SH::F0) * n + j] = qb_direct[(int64_t)(f + SH::F0) * n + j] + acc[f];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) pos_bar[(int64_t)a * n + j] = acc[7 + a];
+  for (int a = 0; a < 3; ++a) pos_bar[(int64_t)a * n + j] = acc[SH::NFA + a];
 }
 
 template <int G>
@@ -636,14 +844,57 @@ hipError_t launch_adj_y_g(hipStream_t s, const EvalArgs& a, double gamma, const 
 
 }  // namespace
 
+namespace {
+
+// Launch helpers that pick the template instance from run-time choices.
+template <bool STAB, class RT>
+void launch_gather(hipStream_t s, int gl, int n, const int64_t* t_off, const int32_t* tsl,
+                   const RT* rec, const double* own, const double* qbd, double* q_bar,
+                   double* pos_bar) {
+  const unsigned gg = grid_for((int64_t)n * gl, THREADS);
+  if (gl == 1)
+    hipLaunchKernelGGL((k_adj_gather<1, RT, STAB>), dim3(gg), dim3(THREADS), 0, s, n, t_off, tsl,
+                       rec, own, qbd, q_bar, pos_bar);
+  else if (gl == 2)
+    hipLaunchKernelGGL((k_adj_gather<2, RT, STAB>), dim3(gg), dim3(THREADS), 0, s, n, t_off, tsl,
+                       rec, own, qbd, q_bar, pos_bar);
+  else
+    hipLaunchKernelGGL((k_adj_gather<4, RT, STAB>), dim3(gg), dim3(THREADS), 0, s, n, t_off, tsl,
+                       rec, own, qbd, q_bar, pos_bar);
+}
+
+template <bool STAB, class RT>
+void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const double* fq,
+                    const int32_t* t_pos, const double* orec, RT* rec, double* own,
+                    int slot_order) {
+  hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB>), dim3(grid_for((int64_t)a.n * 64, THREADS)),
+                     dim3(THREADS), 0, s, a.n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio,
+                     a.wkind, fq, orec, rec, own, slot_order);
+}
+
+template <int G>
+void launch_yrows(hipStream_t s, const EvalArgs& a, const double* tape, const double* orec,
+                  double* ybuf) {
+  for (int r0 = 0; r0 < 9; r0 += 3)
+    hipLaunchKernelGGL((k_adj_yrows<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS),
+                       0, s, a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio, a.wkind, tape,
+                       orec, r0, ybuf);
+}
+
+}  // namespace
+
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
                 const double* tape_in, int64_t nnz_known) {
   (void)t_src;
   const int n = a.n;
-  if (stab_of(p).on())
-    return set_error(ctx, PHB_ENOTIMPL, "reverse mode of the stabilised time derivatives");
+  const Stab sb = stab_of(p);
+  const bool stab = sb.on();
+  // record shapes of this pass (see Shape)
+  const int NRr = stab ? Shape<true>::NR : Shape<false>::NR;
+  const int ORr = stab ? Shape<true>::OREC : Shape<false>::OREC;
+  const int RCr = stab ? Shape<true>::REC : Shape<false>::REC;
   // nnz sizes the pair records: unless the caller knows it, read offsets[n]
   // back (a synchronization, so captured callers pass it).
   int rc;
@@ -664,17 +915,17 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
   ws.plan((size_t)n * sizeof(double4));  // packed geometry
   ws.plan(8 * nd);                       // packed fields
-  ws.plan(3 * NBASIS * nd);            // Y
-  ws.plan((size_t)OREC * nd);          // owner records: G, K, Ubar
-  ws.plan(8 * nd);                     // direct qbar
-  ws.plan((size_t)REC * nd);           // own sums
-  ws.plan((size_t)std::max<int64_t>(nnz, 1) * REC * sizeof(double));  // pair records
+  ws.plan((size_t)NRr * NBASIS * nd);    // Y
+  ws.plan((size_t)ORr * nd);             // owner records: G, K, Ubar
+  ws.plan(8 * nd);                       // direct qbar
+  ws.plan((size_t)RCr * nd);             // own sums
+  ws.plan((size_t)std::max<int64_t>(nnz, 1) * RCr * sizeof(double));  // pair records
   ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
   const bool need_tape = tape_in == nullptr;
   if (need_tape) {
     ws.plan((size_t)TAPE_DOUBLES * nd);  // tape (gradients, status, moments)
-    ws.plan(3 * NBASIS * nd);            // forward operator
+    ws.plan((size_t)NRr * NBASIS * nd);  // forward operator
     ws.plan(8 * nd);                     // rhs scratch
     ws.plan(3 * nd);                     // dxdt scratch
     ws.plan((size_t)n * sizeof(int32_t));
@@ -688,11 +939,11 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   if ((rc = ws.commit())) return rc;
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
-  double* ybuf = ws.take<double>((size_t)3 * NBASIS * n);
-  double* orec = ws.take<double>((size_t)OREC * n);
+  double* ybuf = ws.take<double>((size_t)NRr * NBASIS * n);
+  double* orec = ws.take<double>((size_t)ORr * n);
   double* qbd = ws.take<double>((size_t)8 * n);
-  double* own = ws.take<double>((size_t)REC * n);
-  double* rec = ws.take<double>((size_t)std::max<int64_t>(nnz, 1) * REC);
+  double* own = ws.take<double>((size_t)RCr * n);
+  double* rec = ws.take<double>((size_t)std::max<int64_t>(nnz, 1) * RCr);
   double* wpart = ws.take<double>((size_t)nwaves * 2 * REC);
   int32_t* t_slot = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
   const int slot_order = ctx->record_order;
@@ -705,17 +956,18 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
   if (need_tape) {  // run the forward pass to fill a private tape
     double* tp = ws.take<double>((size_t)TAPE_DOUBLES * n);
-    double* fg = ws.take<double>((size_t)3 * NBASIS * n);
+    double* fg = ws.take<double>((size_t)NRr * NBASIS * n);
     double* rs = ws.take<double>((size_t)8 * n);
     double* dx = ws.take<double>((size_t)3 * n);
     int32_t* st = ws.take<int32_t>(n);
     double* tmom = tp + (size_t)TAPE_MOM * n;
     if ((rc = hip_check(ctx, launch_moments(s, ap, ctx->lanes_assemble, tmom), "moments")))
       return rc;
-    if ((rc = hip_check(ctx, launch_factor(s, ap, 3, tmom, fg, st), "adjoint factor"))) return rc;
+    if ((rc = hip_check(ctx, launch_factor(s, ap, NRr, tmom, fg, st), "adjoint factor")))
+      return rc;
     if ((rc = hip_check(ctx,
-                        launch_apply_rhs(s, ap, ctx->lanes_apply, p->gamma, Stab(), fg, st, rs,
-                                         dx, tp),
+                        launch_apply_rhs(s, ap, ctx->lanes_apply, p->gamma, sb, fg, st, rs, dx,
+                                         tp),
                         "adjoint forward")))
       return rc;
     tape = tp;
@@ -728,29 +980,49 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
       return rc;
     mom = m64;
   }
-  { Prof pf(ctx, "k_adj_y");
-  switch (ctx->lanes_adj_y) {
-    case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
-    case 2: rc = hip_check(ctx, launch_adj_y_g<2>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
-    default: rc = hip_check(ctx, launch_adj_y_g<4>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+  const int interp = a.fit == PHB_FIT_INTERP19;
+  if (stab) {
+    { Prof pf(ctx, "k_adj_u");
+    hipLaunchKernelGGL(k_adj_u, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
+                       p->gamma, sb, q, tape, rhs_bar, dxdt_bar, orec, qbd);
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Ubar"))) return rc; }
+    { Prof pf(ctx, "k_adj_yrows");
+    switch (ctx->lanes_adj_y) {
+      case 1: launch_yrows<1>(s, ap, tape, orec, ybuf); break;
+      case 2: launch_yrows<2>(s, ap, tape, orec, ybuf); break;
+      default: launch_yrows<4>(s, ap, tape, orec, ybuf); break;
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Y"))) return rc; }
+    { Prof pf(ctx, "k_adj_factor<stab>");
+    hipLaunchKernelGGL(k_adj_factor<true>, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS),
+                       0, s, n, mom, ybuf, tape, orec, interp);
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
+  } else {
+    { Prof pf(ctx, "k_adj_y");
+    switch (ctx->lanes_adj_y) {
+      case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+      case 2: rc = hip_check(ctx, launch_adj_y_g<2>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+      default: rc = hip_check(ctx, launch_adj_y_g<4>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+    }
+    if (rc) return rc; }
+    { Prof pf(ctx, "k_adj_factor");
+    hipLaunchKernelGGL(k_adj_factor<false>, dim3(grid_for((int64_t)n * 4, THREADS)),
+                       dim3(THREADS), 0, s, n, mom, ybuf, tape, orec, interp);
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
   }
-  if (rc) return rc; }
-  { Prof pf(ctx, "k_adj_factor");
-  hipLaunchKernelGGL(k_adj_factor, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS), 0, s, n,
-                     mom, ybuf, tape, orec, (int)(a.fit == PHB_FIT_INTERP19));
-  if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;
-  if (ctx->adj_pairs_mode == 1) {
-    Prof pf(ctx, "k_adj_pairs_w");
-    if (rec32)
-      hipLaunchKernelGGL((k_adj_pairs_w<float>), dim3(grid_for((int64_t)n * 64, THREADS)),
-                         dim3(THREADS), 0, s, n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio,
-                         a.wkind, fq, orec, reinterpret_cast<float*>(rec), own, slot_order);
-    else
-      hipLaunchKernelGGL((k_adj_pairs_w<double>), dim3(grid_for((int64_t)n * 64, THREADS)),
-                         dim3(THREADS), 0, s, n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio,
-                         a.wkind, fq, orec, rec, own, slot_order);
+  float* rec_f = reinterpret_cast<float*>(rec);
+  if (stab || ctx->adj_pairs_mode == 1) {
+    // the stabilised shape runs the wavefront-per-owner schedule only
+    Prof pf(ctx, stab ? "k_adj_pairs_w<stab>" : "k_adj_pairs_w");
+    if (stab) {
+      if (rec32) launch_pairs_w<true>(s, a, geo, fq, t_pos, orec, rec_f, own, slot_order);
+      else launch_pairs_w<true>(s, a, geo, fq, t_pos, orec, rec, own, slot_order);
+    } else {
+      if (rec32) launch_pairs_w<false>(s, a, geo, fq, t_pos, orec, rec_f, own, slot_order);
+      else launch_pairs_w<false>(s, a, geo, fq, t_pos, orec, rec, own, slot_order);
+    }
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
   } else {
     if (nnz > 0) {
@@ -758,8 +1030,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
       if (rec32)
         hipLaunchKernelGGL((k_adj_pairs<float>), dim3(grid_for(nnz, PAIRS_PER_BLOCK)),
                            dim3(PAIRS_PER_BLOCK), 0, s, n, nnz, geo, a.off, a.idx, t_pos, a.box,
-                           a.rf_ratio, a.wkind, fq, orec, reinterpret_cast<float*>(rec), own,
-                           wpart, slot_order);
+                           a.rf_ratio, a.wkind, fq, orec, rec_f, own, wpart, slot_order);
       else
         hipLaunchKernelGGL((k_adj_pairs<double>), dim3(grid_for(nnz, PAIRS_PER_BLOCK)),
                            dim3(PAIRS_PER_BLOCK), 0, s, n, nnz, geo, a.off, a.idx, t_pos, a.box,
@@ -780,29 +1051,12 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   const int32_t* tsl = slot_order ? t_slot : nullptr;
   Prof pf(ctx, "k_adj_gather");
   const int gl = ctx->lanes_gather;
-  const unsigned gg = grid_for((int64_t)n * gl, THREADS);
-  const float* rec_f = reinterpret_cast<const float*>(rec);
-  if (gl == 1) {
-    if (rec32)
-      hipLaunchKernelGGL((k_adj_gather<1, float>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
-                         tsl, rec_f, own, qbd, q_bar, pos_bar);
-    else
-      hipLaunchKernelGGL((k_adj_gather<1, double>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
-                         tsl, rec, own, qbd, q_bar, pos_bar);
-  } else if (gl == 2) {
-    if (rec32)
-      hipLaunchKernelGGL((k_adj_gather<2, float>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
-                         tsl, rec_f, own, qbd, q_bar, pos_bar);
-    else
-      hipLaunchKernelGGL((k_adj_gather<2, double>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
-                         tsl, rec, own, qbd, q_bar, pos_bar);
+  if (stab) {
+    if (rec32) launch_gather<true>(s, gl, n, t_offsets, tsl, (const float*)rec_f, own, qbd, q_bar, pos_bar);
+    else launch_gather<true>(s, gl, n, t_offsets, tsl, (const double*)rec, own, qbd, q_bar, pos_bar);
   } else {
-    if (rec32)
-      hipLaunchKernelGGL((k_adj_gather<4, float>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
-                         tsl, rec_f, own, qbd, q_bar, pos_bar);
-    else
-      hipLaunchKernelGGL((k_adj_gather<4, double>), dim3(gg), dim3(THREADS), 0, s, n, t_offsets,
-                         tsl, rec, own, qbd, q_bar, pos_bar);
+    if (rec32) launch_gather<false>(s, gl, n, t_offsets, tsl, (const float*)rec_f, own, qbd, q_bar, pos_bar);
+    else launch_gather<false>(s, gl, n, t_offsets, tsl, (const double*)rec, own, qbd, q_bar, pos_bar);
   }
   return hip_check(ctx, hipGetLastError(), "adjoint gather");
 }

@@ -232,6 +232,17 @@ __device__ __forceinline__ double quad_xor2(double v) { return dpp_f64<QP_XOR2>(
 template <>
 __device__ __forceinline__ float quad_xor2(float v) { return dpp_f32<QP_XOR2>(v); }
 
+// Eight fields of particle j from the packed records fq[8 j .. 8 j + 7].
+__device__ __forceinline__ void load_fields(const double* __restrict__ fq, int j, double (&v)[8]) {
+  const double2* p = reinterpret_cast<const double2*>(fq + 8 * (int64_t)j);
+#pragma unroll
+  for (int f = 0; f < 8; f += 2) {
+    const double2 t = p[f / 2];
+    v[f] = t.x;
+    v[f + 1] = t.y;
+  }
+}
+
 // DPP row controls: lane l of each 8-lane half row reads lane 7 - l; of each
 // 16-lane row, lane 15 - l.
 constexpr int ROW_HALF_MIRROR = 0x141;

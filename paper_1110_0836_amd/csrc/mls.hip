@@ -45,17 +45,6 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
-// Eight fields of particle j from the packed records.
-__device__ __forceinline__ void load_fields(const double* __restrict__ fq, int j, double (&v)[8]) {
-  const double2* p = reinterpret_cast<const double2*>(fq + 8 * (int64_t)j);
-#pragma unroll
-  for (int f = 0; f < 8; f += 2) {
-    const double2 t = p[f / 2];
-    v[f] = t.x;
-    v[f + 1] = t.y;
-  }
-}
-
 // T is the accumulation type: double, or float for the mixed form (the
 // displacement, its scaling by 1/lambda and the weight are formed in FP64 and
 // only then rounded to FP32).

@@ -2,8 +2,8 @@
 coefficient, div-B diffusion; Sec. 2 and App. A) on the GPU against the
 oracle: the FP64 form element by element within 1e-12 (per physical
 quantity, relative to the size of the terms it is summed from), the mixed
-form within 1e-5; the Courant step; the App. A damping rate of a sound wave
-over half a period; the reverse mode reports that it does not cover them."""
+form within 1e-5; the reverse mode and torch.autograd through it; the Courant
+step; the App. A damping rate of a sound wave over half a period."""
 import numpy as np
 import pytest
 
@@ -154,15 +154,81 @@ def test_courant_step_matches_oracle():
     assert abs(dt - oracle.courant_dt(c["q"], c["lam"], 0.3, stab=TUPLE)) <= 1e-15 * dt
 
 
-def test_reverse_mode_reports_not_implemented():
-    c = synth.cp_alfven(8)
-    s = setup_of(c, **STAB)
+def _adjoint_both(c, gbar, xbar, use_tape=True, **kw):
+    s = setup_of(c, **STAB, **kw)
     pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
     off, idx = P.neighbors(pos, lam, s)
-    n = lam.shape[0]
-    with pytest.raises(P.PhurbasError):
-        P.mhd_rhs_adjoint(pos, lam, off, idx, P.transpose(off, idx), q,
-                          dev(np.ones((8, n))), None, setup=s)
+    tape = P.mhd_rhs(pos, lam, off, idx, q, s, tape=True)[3] if use_tape else None
+    qb, pb = P.mhd_rhs_adjoint(pos, lam, off, idx, P.transpose(off, idx), q, dev(gbar),
+                               None if xbar is None else dev(xbar), setup=s, tape=tape)
+    ooff, oidx = oracle.neighbors(c["pos"], c["lam"], L=c["L"], periodic=c["periodic"])
+    oq, op, ost = oracle.mhd_rhs_adjoint(c["pos"], c["lam"], ooff, oidx, c["q"], gbar, xbar,
+                                         L=c["L"], periodic=c["periodic"], stab=TUPLE,
+                                         fit=kw.get("fit", 0))
+    o0, _, _ = oracle.mhd_rhs_adjoint(c["pos"], c["lam"], ooff, oidx, c["q"], gbar, xbar,
+                                      L=c["L"], periodic=c["periodic"], fit=kw.get("fit", 0))
+    return (qb.cpu().numpy(), pb.cpu().numpy()), (oq, op, ost), o0
+
+
+def _gerr(g, o):
+    return float(np.abs(g - o).max() / max(np.abs(o).max(), 1e-300))
+
+
+@pytest.mark.parametrize("use_tape", [True, False])
+def test_reverse_mode_matches_oracle(use_tape):
+    from test_gpu_adjoint import random_set
+    c, gbar, xbar = random_set(seed=75)
+    (qb, pb), (oq, op, ost), o0 = _adjoint_both(c, gbar, xbar, use_tape=use_tape)
+    assert np.all(ost == 0)
+    eq = max(_gerr(qb[f], oq[f]) for f in range(8))
+    ep = _gerr(pb, op)
+    print(f"stabilised reverse mode vs oracle: q_bar {eq:.2e}, pos_bar {ep:.2e}")
+    assert eq < 1e-12 and ep < 1e-12
+    assert _gerr(o0, oq) > 1e-2   # the stabilisers change the gradient
+
+
+def test_reverse_mode_steep_front_and_interpolating_fit():
+    c = _steep_cloud(2000, seed=76)
+    rng = np.random.default_rng(77)
+    gbar = rng.normal(size=(8, 2000))
+    for fit in (0, 1):
+        (qb, pb), (oq, op, ost), _ = _adjoint_both(c, gbar, None, fit=fit)
+        eq = max(_gerr(qb[f], oq[f]) for f in range(8))
+        ep = _gerr(pb, op)
+        print(f"stabilised reverse mode, steep front, fit {fit}: q_bar {eq:.2e}, "
+              f"pos_bar {ep:.2e}")
+        assert eq < 1e-11 and ep < 1e-11
+
+
+def test_reverse_mode_mixed():
+    from test_gpu_adjoint import random_set
+    c, gbar, xbar = random_set(seed=78)
+    (qb, pb), (oq, op, _), _ = _adjoint_both(c, gbar, xbar, precision=P.PHB_MIXED)
+    eq = max(_gerr(qb[f], oq[f]) for f in range(8))
+    ep = _gerr(pb, op)
+    print(f"stabilised mixed reverse mode vs oracle: q_bar {eq:.2e}, pos_bar {ep:.2e}")
+    assert eq < 1e-5 and ep < 1e-5
+
+
+def test_autograd_with_stabilisers():
+    """torch.autograd through MHDRHS with the stabilisers on equals the
+    oracle's gradient of the same loss."""
+    c = _steep_cloud(3000, seed=79)
+    s = setup_of(c, **STAB)
+    w = np.random.default_rng(80).uniform(size=3000)
+    pos = dev(c["pos"]).requires_grad_(True)
+    q = dev(c["q"]).requires_grad_(True)
+    lam = dev(c["lam"])
+    off, idx = P.neighbors(pos.detach(), lam, s)
+    rhs, _, _ = P.MHDRHS.apply(q, pos, lam, off, idx, P.transpose(off, idx), s)
+    loss = (torch.from_numpy(w).cuda() * (rhs ** 2).sum(0)).sum()
+    gq, gp = torch.autograd.grad(loss, (q, pos))
+    ooff, oidx = oracle.neighbors(c["pos"], c["lam"])
+    orhs, _, ost = oracle.mhd_rhs(c["pos"], c["lam"], ooff, oidx, c["q"], stab=TUPLE)
+    assert np.all(ost == 0) and np.isfinite(loss.item())
+    oq, op, _ = oracle.mhd_rhs_adjoint(c["pos"], c["lam"], ooff, oidx, c["q"], 2 * w * orhs,
+                                       stab=TUPLE)
+    assert _gerr(gq.cpu().numpy(), oq) < 1e-11 and _gerr(gp.cpu().numpy(), op) < 1e-11
 
 
 def test_evolve_matches_oracle():
