@@ -72,6 +72,9 @@ def lib():
         L.orc_evolve.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, I, P, P, I, P]
         L.orc_divb_norm.restype = I
         L.orc_divb_norm.argtypes = [I64, P, P, P, P, D, I, I, I64, P, P, P, P, P, P, I]
+        L.orc_evolve_blocks.restype = I
+        L.orc_evolve_blocks.argtypes = [I64, P, P, P, P, P, D, D, I, I, D, I, D, I, P, P, P, P,
+                                        I, P]
         L.orc_courant_dt.restype = D
         L.orc_courant_dt.argtypes = [I64, P, P, D, P, D, P]
         _lib = L
@@ -345,3 +348,27 @@ def bin_mean(coord, values, x0, width, nbins):
             count[b] += 1
     mean = np.array([t / c if c else np.nan for t, c in zip(total, count)])
     return mean, np.array(count, dtype=np.int64)
+
+
+def evolve_blocks(pos, lam, q, dt_max, nblocks, cfl=0.3, kmax=20, L=(1.0, 1.0, 1.0),
+                  periodic=(1, 1, 1), gamma=5.0 / 3.0, frozen=None, weight=0, fit=0, threads=0,
+                  rf_ratio=RF_RATIO, stab=None):
+    """nblocks periods of dt_max with individual power-of-two steps; returns
+    (pos, q, status, levels (n,), stats (step-end times, particle evaluations))."""
+    pos = np.array(pos, dtype=np.float64, order="C", copy=True)
+    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    lam = _c(lam, np.float64)
+    n = lam.shape[0]
+    Lb, pb = _box(L, periodic)
+    fz = None if frozen is None else _c(frozen, np.int32)
+    st = np.zeros(n, np.int32)
+    lev = np.zeros(n, np.int32)
+    stats = np.zeros(2, np.int64)
+    rc = lib().orc_evolve_blocks(n, _p(pos), _p(q), _p(lam), _p(Lb), _p(pb), rf_ratio, gamma,
+                                 weight, fit, float(dt_max), int(nblocks), float(cfl), int(kmax),
+                                 _p(fz), _p(st), _p(lev), _p(stats), threads, _p(_stab(stab)))
+    if rc == -1:
+        raise ValueError("orc_evolve_blocks: invalid arguments")
+    if rc == -2:
+        raise ValueError("orc_evolve_blocks: a particle left the box on a non-periodic axis")
+    return pos, q, st, lev, stats

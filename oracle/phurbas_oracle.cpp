@@ -36,6 +36,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <climits>
 #include <omp.h>
 
 namespace {
@@ -1074,6 +1075,193 @@ double orc_courant_dt(int64_t n, const double* q, const double* lambda, double g
     if (best < 0.0 || t < best) best = t;
   }
   return best < 0.0 ? -1.0 : cfl * best;
+}
+
+// Individual power-of-two time steps (Sec. 2 and 2.1: each particle has its
+// own step, rounded down to a power of two of the largest in the binary block
+// scheme; neighboring steps may differ only so much; a step may grow only
+// when the times line up).  Readings, since the scheme's details are in the
+// companion paper:
+//  * level k_i: step dt_max / 2^k_i, k_i the smallest k in [0, kmax] whose step
+//    is at most particle i's own Courant step (orc_courant_dt's expression);
+//  * limiter: k_i >= k_j - 1 for every non-frozen neighbor j (neighboring
+//    steps differ by a factor of two at most), enforced at i's step ends;
+//  * synchronization: at its step end (a multiple of the tick dt_max / 2^kmax),
+//    a particle takes at least the level whose step divides the current time;
+//  * integration: Heun over each particle's own step, with every other
+//    particle's state predicted linearly from its last step start,
+//    y_j(t) = y_j(t0_j) + (t - t0_j) F_j(t0_j).  When a set A of particles
+//    ends a step at time t: predict all to t, evaluate F at t for A (the
+//    Heun predictor's derivative), correct A, then evaluate F at t for A at
+//    its corrected state (the next step's starting derivative).
+// With one level for all particles this is orc_evolve with dt = dt_max.
+// Runs nblocks periods of dt_max.  level: the levels of the last step.
+// stats[0]: step-end times, stats[1]: particle evaluations.  Returns -1 for
+// bad arguments, -2 when a position leaves [0, L) on an open axis.
+int orc_evolve_blocks(int64_t n, double* pos, double* q, const double* lambda, const double* L,
+                      const int32_t* periodic, double rf_ratio, double gamma, int weight, int fit,
+                      double dt_max, int nblocks, double cfl, int kmax, const int32_t* frozen,
+                      int32_t* status, int32_t* level, int64_t* stats, int nthreads,
+                      const double* stab) {
+  if (n <= 0 || !pos || !q || !lambda || nblocks < 0 || kmax < 0 || kmax > 30 ||
+      !(dt_max > 0.0) || !(cfl > 0.0))
+    return -1;
+  Setup s = make_setup(L, periodic, rf_ratio, gamma, weight, fit, stab);
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  const double cmul = 1.0 + 2.0 * (s.visc_grid + s.visc_adapt + s.divb_diff);
+  const int64_t T = int64_t(1) << kmax;  // ticks per dt_max
+  const double dtick = std::ldexp(dt_max, -kmax);
+  auto is_frozen = [&](int64_t i) { return frozen && frozen[i]; };
+  auto wrap = [&](double v, int a, bool& ok) {
+    if (s.periodic[a]) {
+      if (v >= s.L[a]) v -= s.L[a];
+      if (v < 0.0) v += s.L[a];
+    } else if (v < 0.0 || v >= s.L[a]) {
+      ok = false;
+    }
+    return v;
+  };
+  auto courant_level = [&](const double* qq, int64_t i) {
+    const double b2 = qq[4 * n + i] * qq[4 * n + i] + qq[5 * n + i] * qq[5 * n + i] +
+                      qq[6 * n + i] * qq[6 * n + i];
+    const double P = (s.gamma - 1.0) * qq[7 * n + i];
+    const double cf = std::sqrt((s.gamma * P + b2) / qq[i]);
+    const double dtc = cfl * (lambda[i] / (cf * cmul));
+    int k = 0;
+    while (k < kmax && !(std::ldexp(dt_max, -k) <= dtc)) ++k;
+    return k;
+  };
+  std::vector<double> x0(pos, pos + 3 * n), q0(q, q + 8 * n), xp(x0), qp(q0);
+  std::vector<double> F0(8 * n, 0.0), V0(3 * n, 0.0);
+  std::vector<int64_t> t0(n, 0);
+  std::vector<int32_t> k(n, 0), stmax(n, 0);
+  int64_t events = 0, evals = 0;
+  // time derivatives of the listed rows at the state (xp, qp)
+  auto eval_rows = [&](const std::vector<int64_t>& rows, std::vector<int64_t>& off,
+                       std::vector<int32_t>& nb, std::vector<double>& f,
+                       std::vector<double>& v, std::vector<int32_t>& st) {
+    const int64_t m = (int64_t)rows.size();
+    off.assign(m + 1, 0);
+    const int64_t nnz = orc_neighbors(n, xp.data(), lambda, L, periodic, rf_ratio, m, rows.data(),
+                                      off.data(), nullptr, 0, nthreads);
+    nb.assign(std::max<int64_t>(nnz, 1), 0);
+    orc_neighbors(n, xp.data(), lambda, L, periodic, rf_ratio, m, rows.data(), off.data(),
+                  nb.data(), nnz, nthreads);
+    f.assign(8 * m, 0.0);
+    v.assign(3 * m, 0.0);
+    st.assign(m, 0);
+    orc_mhd_rhs(n, xp.data(), lambda, L, periodic, rf_ratio, gamma, weight, fit, m, rows.data(),
+                off.data(), nb.data(), qp.data(), f.data(), v.data(), st.data(), nthreads, stab);
+    evals += m;
+  };
+  // levels of the rows (Courant, limiter among them against the others'
+  // current levels, synchronization with the time `tick`)
+  auto set_levels = [&](const std::vector<int64_t>& rows, const std::vector<int64_t>& off,
+                        const std::vector<int32_t>& nb, int64_t tick) {
+    const int64_t m = (int64_t)rows.size();
+    std::vector<int32_t> kn(m);
+    std::vector<int64_t> rpos(n, -1);
+    for (int64_t r = 0; r < m; ++r) {
+      kn[r] = courant_level(q0.data(), rows[r]);
+      rpos[rows[r]] = r;
+    }
+    bool changed = true;
+    while (changed) {
+      changed = false;
+      for (int64_t r = 0; r < m; ++r)
+        for (int64_t e = off[r]; e < off[r + 1]; ++e) {
+          const int64_t j = nb[e];
+          if (j == rows[r] || is_frozen(j)) continue;
+          const int kj = rpos[j] >= 0 ? kn[rpos[j]] : k[j];
+          if (kj - 1 > kn[r]) {
+            kn[r] = kj - 1;
+            changed = true;
+          }
+        }
+    }
+    int ksync = 0;
+    if (tick > 0) {
+      int tz = 0;
+      while (tz < kmax && ((tick >> tz) & 1) == 0) ++tz;
+      ksync = kmax - tz;
+    }
+    for (int64_t r = 0; r < m; ++r) k[rows[r]] = std::max(kn[r], ksync);
+  };
+  std::vector<int64_t> act, off;
+  std::vector<int32_t> nb, st;
+  std::vector<double> f, v;
+  for (int64_t i = 0; i < n; ++i)
+    if (!is_frozen(i)) act.push_back(i);
+  if (act.empty() || nblocks == 0) {
+    if (status) for (int64_t i = 0; i < n; ++i) status[i] = 0;
+    if (level) for (int64_t i = 0; i < n; ++i) level[i] = 0;
+    if (stats) { stats[0] = 0; stats[1] = 0; }
+    return 0;
+  }
+  // start: every particle's derivative and level at time 0
+  eval_rows(act, off, nb, f, v, st);
+  for (size_t r = 0; r < act.size(); ++r) {
+    const int64_t i = act[r];
+    for (int c = 0; c < 8; ++c) F0[c * n + i] = f[c * act.size() + r];
+    for (int a = 0; a < 3; ++a) V0[a * n + i] = v[a * act.size() + r];
+    stmax[i] = std::max(stmax[i], st[r]);
+  }
+  set_levels(act, off, nb, 0);
+  const int64_t tick_end = (int64_t)nblocks * T;
+  for (;;) {
+    int64_t tick = INT64_MAX;
+    for (int64_t i = 0; i < n; ++i)
+      if (!is_frozen(i)) tick = std::min(tick, t0[i] + (T >> k[i]));
+    act.clear();
+    for (int64_t i = 0; i < n; ++i)
+      if (!is_frozen(i) && t0[i] + (T >> k[i]) == tick) act.push_back(i);
+    ++events;
+    // predict every particle to tick
+    bool ok = true;
+    for (int64_t i = 0; i < n; ++i) {
+      const double tau = (double)(tick - t0[i]) * dtick;
+      for (int a = 0; a < 3; ++a) xp[a * n + i] = wrap(x0[a * n + i] + tau * V0[a * n + i], a, ok);
+      for (int c = 0; c < 8; ++c) qp[c * n + i] = q0[c * n + i] + tau * F0[c * n + i];
+    }
+    if (!ok) return -2;
+    eval_rows(act, off, nb, f, v, st);
+    const int64_t m = (int64_t)act.size();
+    for (int64_t r = 0; r < m; ++r) {
+      const int64_t i = act[r];
+      const double dt = (double)(T >> k[i]) * dtick;
+      for (int c = 0; c < 8; ++c) {
+        q0[c * n + i] = q0[c * n + i] + 0.5 * dt * (F0[c * n + i] + f[c * m + r]);
+        qp[c * n + i] = q0[c * n + i];
+      }
+      for (int a = 0; a < 3; ++a) {
+        x0[a * n + i] = wrap(x0[a * n + i] + 0.5 * dt * (V0[a * n + i] + v[a * m + r]), a, ok);
+        xp[a * n + i] = x0[a * n + i];
+      }
+      t0[i] = tick;
+      stmax[i] = std::max(stmax[i], st[r]);
+    }
+    if (!ok) return -2;
+    if (tick >= tick_end) break;
+    eval_rows(act, off, nb, f, v, st);
+    for (int64_t r = 0; r < m; ++r) {
+      const int64_t i = act[r];
+      for (int c = 0; c < 8; ++c) F0[c * n + i] = f[c * m + r];
+      for (int a = 0; a < 3; ++a) V0[a * n + i] = v[a * m + r];
+      stmax[i] = std::max(stmax[i], st[r]);
+    }
+    set_levels(act, off, nb, tick);
+  }
+  std::copy(x0.begin(), x0.end(), pos);
+  std::copy(q0.begin(), q0.end(), q);
+  if (status)
+    for (int64_t i = 0; i < n; ++i) status[i] = is_frozen(i) ? 0 : stmax[i];
+  if (level)
+    for (int64_t i = 0; i < n; ++i) level[i] = k[i];
+  if (stats) {
+    stats[0] = events;
+    stats[1] = evals;
+  }
+  return 0;
 }
 
 static int pc_step_masked(int64_t n, double* pos, double* q, const double* lambda,
