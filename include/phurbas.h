@@ -132,6 +132,13 @@ const char* phb_last_error(phb_ctx* ctx);
 int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                         const double* lambda, int64_t* offsets, int32_t* idx,
                         int64_t idx_capacity, int64_t* nnz_out);
+/* The lists of the m particles rows[0 .. m) (int32, in [0, n); m may be 0)
+ * among all n: offsets int64[m+1], idx as for phb_neighbors_build, rows in
+ * the given order, each sorted ascending.  The same errors. */
+int phb_neighbors_build_rows(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                             const double* lambda, int64_t m, const int32_t* rows,
+                             int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+                             int64_t* nnz_out);
 
 /* Transposed lists for the reverse-mode kernels: t_offsets int64[n+1],
  * t_src int32[nnz] (row j lists, ascending, every i whose row holds j),
@@ -175,6 +182,17 @@ int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                 const double* lambda, const int64_t* offsets, const int32_t* idx,
                 const double* q, double* rhs, double* dxdt, int32_t* status, void* tape);
 int64_t phb_tape_bytes(int64_t n);
+/* Active-subset evaluation (Sec. 2: each particle has its own time step, so
+ * only some particles need new time derivatives at a time): the time
+ * derivatives of the m particles rows[0 .. m) (int32, distinct, in [0, n)),
+ * each from its neighbors among all n particles.  offsets int64[m+1] and
+ * idx hold the lists of those rows (phb_neighbors_build_rows); rhs[8][m],
+ * dxdt[3][m], status int32[m] are per row.  FP64 form only: PHB_ENOTIMPL
+ * with PHB_MIXED.  EINVAL for m outside [1, n]. */
+int phb_mhd_rhs_rows(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                     const double* lambda, int64_t m, const int32_t* rows,
+                     const int64_t* offsets, const int32_t* idx, const double* q, double* rhs,
+                     double* dxdt, int32_t* status);
 
 /* ---- reverse mode --------------------------------------------------------
  * Gradient of  S = sum_i rhs_bar_i . rhs_i + dxdt_bar_i . dxdt_i  with respect
@@ -215,6 +233,27 @@ int phb_evolve(phb_ctx* ctx, const phb_params* p, int64_t n, double dt, int32_t 
                double* pos, double* q, const double* lambda, const int32_t* frozen,
                int64_t* offsets, int32_t* idx, int64_t idx_capacity, int64_t* nnz_out,
                int32_t* status);
+/* Individual power-of-two time steps (Sec. 2 and 2.1): nblocks periods of
+ * dt_max in which particle i takes steps of dt_max / 2^k_i.  k_i is the
+ * smallest level in [0, kmax] whose step is at most cfl times i's own
+ * Courant step (the expression of phb_courant_dt); neighbors' levels differ
+ * by at most one (k_i >= k_j - 1, enforced at i's step ends); a step grows
+ * only where the current time is a multiple of the longer step.  Each step is
+ * Heun's over the particle's own step, every other particle's state being
+ * predicted linearly from its last step start; the particles ending a step
+ * at a time are evaluated as a compacted row list (phb_neighbors_build_rows,
+ * phb_mhd_rhs_rows).  With one level throughout this is phb_evolve with
+ * dt = dt_max.  pos, q: updated in place (all particles end synchronized).
+ * offsets int64[n+1], idx int32[idx_capacity]: list scratch, as for
+ * phb_pc_step.  status int32[n]: the largest over all evaluations (0 for
+ * frozen particles).  level int32[n] or NULL: the levels of the last steps.
+ * stats: NULL or host int64[2] = (step-end times, particle evaluations).
+ * FP64 form only (PHB_ENOTIMPL otherwise).  Synchronizes repeatedly. */
+int phb_evolve_blocks(phb_ctx* ctx, const phb_params* p, int64_t n, double dt_max,
+                      int32_t nblocks, double cfl, int32_t kmax, double* pos, double* q,
+                      const double* lambda, const int32_t* frozen, int64_t* offsets,
+                      int32_t* idx, int64_t idx_capacity, int32_t* status, int32_t* level,
+                      int64_t* stats);
 /* Courant time step: *dt_out (host) = cfl * min over non-frozen i of
  * lambda_i / (c_f,i (1 + 2 (visc_grid + visc_adapt + divb_diff))),
  * with the fast speed c_f = sqrt((gamma P + |B|^2) / rho), P = (gamma - 1)

@@ -40,6 +40,7 @@ EXPORTS = [
     "phb_pc_step", "phb_profile", "phb_profile_read", "phb_tune_set", "phb_tune_get",
     "phb_evolve", "phb_courant_dt", "phb_tune", "phb_batch_create", "phb_batch_destroy", "phb_batch_neighbors", "phb_batch_run",
     "phb_batch_capture", "phb_batch_launch", "phb_divb_norm", "phb_bin_mean",
+    "phb_neighbors_build_rows", "phb_mhd_rhs_rows", "phb_evolve_blocks",
 ]
 
 
@@ -148,6 +149,11 @@ def lib():
             "phb_batch_capture": (I, [P, P, ctypes.POINTER(BatchIO)]),
             "phb_batch_launch": (I, [P, P]),
             "phb_divb_norm": (I, [P, PP, I64, P, P, P, P, P, P, P]),
+            "phb_neighbors_build_rows": (I, [P, PP, I64, P, P, I64, P, P, P, I64,
+                                             ctypes.POINTER(I64)]),
+            "phb_mhd_rhs_rows": (I, [P, PP, I64, P, P, I64, P, P, P, P, P, P, P]),
+            "phb_evolve_blocks": (I, [P, PP, I64, D, I32, D, I32, P, P, P, P, P, P, I64, P, P,
+                                      P]),
             "phb_bin_mean": (I, [P, I64, P, P, D, D, I32, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -363,6 +369,41 @@ def neighbors(pos, lam, setup=None, capacity=None):
     return offsets, idx[:nnz]
 
 
+def neighbors_rows(pos, lam, rows, setup=None, capacity=None):
+    """CSR lists of the particles rows (int32) among all: (offsets int64[m+1], idx)."""
+    setup = setup or Setup()
+    m = rows.shape[0]
+    ctx = context(pos.device.index)
+    p = setup.params()
+    offsets = torch.empty(m + 1, dtype=torch.int64, device=pos.device)
+    cap = capacity if capacity is not None else 64 * max(m, 1)
+    for _ in range(2):
+        idx = torch.empty(max(cap, 1), dtype=torch.int32, device=pos.device)
+        nnz = ctypes.c_int64(0)
+        rc = lib().phb_neighbors_build_rows(ctx, ctypes.byref(p), lam.shape[0], _f64(pos),
+                                            _f64(lam), m, _ptr(rows), _ptr(offsets), _ptr(idx),
+                                            cap, ctypes.byref(nnz))
+        if rc != PHB_ECAPACITY:
+            break
+        cap = nnz.value
+    _check(ctx, rc)
+    return offsets, idx[:nnz.value]
+
+
+def mhd_rhs_rows(pos, lam, rows, offsets, idx, q, setup=None):
+    """Time derivatives of the particles rows only: rhs (8,m), dxdt (3,m), status (m,)."""
+    m = rows.shape[0]
+    rhs = torch.empty((8, m), dtype=torch.float64, device=q.device)
+    dxdt = torch.empty((3, m), dtype=torch.float64, device=q.device)
+    st = torch.empty(m, dtype=torch.int32, device=q.device)
+    ctx = context(q.device.index)
+    p = (setup or Setup()).params()
+    _check(ctx, lib().phb_mhd_rhs_rows(ctx, ctypes.byref(p), lam.shape[0], _f64(pos), _f64(lam),
+                                       m, _ptr(rows), _ptr(offsets), _ptr(idx), _f64(q),
+                                       _ptr(rhs), _ptr(dxdt), _ptr(st)))
+    return rhs, dxdt, st
+
+
 def transpose(offsets, idx):
     n = offsets.shape[0] - 1
     t_off = torch.empty(n + 1, dtype=torch.int64, device=offsets.device)
@@ -447,6 +488,28 @@ def evolve(pos, q, lam, dt, nsteps, setup=None, frozen=None, capacity=None):
     if rc == PHB_ECAPACITY:
         raise PhurbasError(rc, f"neighbor capacity {cap} < {nnz}; pass capacity=")
     return st
+
+
+def evolve_blocks(pos, q, lam, dt_max, nblocks, cfl=0.3, kmax=20, setup=None, frozen=None,
+                  capacity=None):
+    """nblocks periods of dt_max with individual power-of-two steps, in place on
+    pos and q; returns (status (n,), levels (n,), (step-end times, particle
+    evaluations))."""
+    setup = setup or Setup()
+    n = lam.shape[0]
+    ctx = context(pos.device.index)
+    p = setup.params()
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=pos.device)
+    cap = capacity if capacity is not None else 128 * n
+    idx = torch.empty(max(cap, 1), dtype=torch.int32, device=pos.device)
+    st = torch.empty(n, dtype=torch.int32, device=pos.device)
+    lev = torch.empty(n, dtype=torch.int32, device=pos.device)
+    stats = (ctypes.c_int64 * 2)()
+    _check(ctx, lib().phb_evolve_blocks(ctx, ctypes.byref(p), n, float(dt_max), int(nblocks),
+                                        float(cfl), int(kmax), _f64(pos), _f64(q), _f64(lam),
+                                        _ptr(frozen), _ptr(offsets), _ptr(idx), cap, _ptr(st),
+                                        _ptr(lev), stats))
+    return st, lev, (int(stats[0]), int(stats[1]))
 
 
 def courant_dt(q, lam, cfl=0.3, setup=None, frozen=None):

@@ -33,5 +33,15 @@ int pc_step(phb_ctx* ctx, const phb_params* p, int n, double dt, double* pos, do
             int64_t idx_capacity, int64_t* nnz_out, int32_t* status, int accumulate);
 int courant_dt(phb_ctx* ctx, const phb_params* p, int n, const double* q, const double* lambda,
                const int32_t* frozen, double cfl, double* dt_out);
+// Lists of rows built by the library itself (no range check of rows).
+int neighbors_rows_unchecked(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                             const double* lambda, int64_t m, const int32_t* rows,
+                             int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+                             int64_t* nnz_out);
+// Individual power-of-two time steps (phb_evolve_blocks).
+int evolve_blocks(phb_ctx* ctx, const phb_params* p, int n, double* pos, double* q,
+                  const double* lambda, const int32_t* frozen, double dt_max, int nblocks,
+                  double cfl, int kmax, int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+                  int32_t* status, int32_t* level, int64_t* stats);
 
 }  // namespace phb

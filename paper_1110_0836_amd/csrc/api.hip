@@ -66,6 +66,37 @@ static int ensure_host(phb_ctx* ctx, size_t bytes) {
   return PHB_OK;
 }
 
+// Row lists handed in by a caller index particle arrays in the kernels: every
+// entry must lie in [0, n) before any of them runs.
+__global__ void k_rows_out_of_range(int m, const int32_t* __restrict__ rows, int n,
+                                    int32_t* __restrict__ bad) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < m && (rows[r] < 0 || rows[r] >= n)) bad[0] = 1;
+}
+
+static int check_rows(phb_ctx* ctx, int64_t m, const int32_t* rows, int64_t n) {
+  if (m <= 0) return PHB_OK;
+  Workspace ws(ctx);
+  ws.plan(sizeof(int32_t));
+  int rc;
+  if ((rc = ws.commit())) return rc;
+  int32_t* bad = ws.take<int32_t>(1);
+  if ((rc = hip_check(ctx, fill_i32(ctx->stream, bad, 0, 1), "row check clear"))) return rc;
+  hipLaunchKernelGGL(k_rows_out_of_range, dim3(grid_for(m, 256)), dim3(256), 0, ctx->stream,
+                     (int)m, rows, (int)n, bad);
+  if ((rc = hip_check(ctx, hipGetLastError(), "row check"))) return rc;
+  if ((rc = ensure_host(ctx, 64))) return rc;
+  if ((rc = hip_check(ctx,
+                      hipMemcpyAsync(ctx->host, bad, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                     ctx->stream),
+                      "row check read-back")))
+    return rc;
+  if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "row check sync"))) return rc;
+  if (*reinterpret_cast<int32_t*>(ctx->host))
+    return set_error(ctx, PHB_EINVAL, "a row index is outside [0, n)");
+  return PHB_OK;
+}
+
 int check_params(phb_ctx* ctx, const phb_params* p) {
   if (!p) return set_error(ctx, PHB_EINVAL, "params is NULL");
   for (int a = 0; a < 3; ++a)
@@ -177,7 +208,7 @@ static void plan_neighbors(Workspace& ws, int64_t n, int64_t idx_capacity) {
   ws.plan((size_t)std::max<int64_t>(idx_capacity, 1) * sizeof(int32_t));  // unsorted rows
 }
 
-static void plan_rhs(Workspace& ws, int64_t n, int precision, bool stab);
+static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, bool stab);
 
 size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity) {
   phb_ctx dummy;
@@ -199,44 +230,48 @@ size_t ws_bytes_derivs(int64_t n, const phb_params* p, bool second) {
 size_t ws_bytes_rhs(int64_t n, const phb_params* p) {
   phb_ctx dummy;
   Workspace ws(&dummy);
-  plan_rhs(ws, n, p->precision, stab_of(p).on());
+  plan_rhs(ws, n, n, p->precision, stab_of(p).on());
   return ws.total;
 }
 
-static void plan_rhs(Workspace& ws, int64_t n, int precision, bool stab) {
+// n rows of n_all particles
+static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, bool stab) {
   if (precision == PHB_MIXED) {
     ws.plan(mixed_rhs_bytes(n, stab));
     return;
   }
   ws.plan((size_t)NMOM * n * sizeof(double));
   ws.plan((size_t)(stab ? 9 : 3) * NBASIS * n * sizeof(double));
-  ws.plan((size_t)n * sizeof(double4));
-  ws.plan((size_t)n * 8 * sizeof(double));
+  ws.plan((size_t)n_all * sizeof(double4));
+  ws.plan((size_t)n_all * 8 * sizeof(double));
 }
 
 // The time derivatives in the form p->precision asks for (FP64 here).
 int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double* q, double* rhs,
              double* dxdt, int32_t* status, double* tape) {
   const Stab sb = stab_of(p);
-  if (p->precision == PHB_MIXED)
+  if (p->precision == PHB_MIXED) {
+    if (a0.rows) return set_error(ctx, PHB_ENOTIMPL, "row subsets in the mixed form");
     return mixed_rhs(ctx, a0, p->gamma, sb, q, rhs, dxdt, status, tape);
+  }
   EvalArgs a = a0;
-  const int n = a.n;
+  const int n = a.n;                        // rows
+  const int na = a.rows ? a.n_all : n;      // particles
   const int nrows = sb.on() ? 9 : 3;
   int rc;
   Workspace ws(ctx);
-  plan_rhs(ws, n, PHB_FP64, sb.on());
+  plan_rhs(ws, n, na, PHB_FP64, sb.on());
   if ((rc = ws.commit())) return rc;
   double* mom = ws.take<double>((size_t)NMOM * n);
   double* gop = ws.take<double>((size_t)nrows * NBASIS * n);
-  double4* geo = ws.take<double4>(n);
-  double* fq = ws.take<double>((size_t)8 * n);
+  double4* geo = ws.take<double4>(na);
+  double* fq = ws.take<double>((size_t)8 * na);
   // with a tape, the moments go straight into it for the reverse mode
   if (tape) mom = tape + (size_t)TAPE_MOM * n;
   a.geo = geo;
   a.fq = fq;
   { Prof pf(ctx, "k_pack");
-  if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
+  if ((rc = hip_check(ctx, launch_pack(ctx->stream, na, a.pos, a.lam, q, geo, fq), "pack")))
     return rc; }
   { Prof pf(ctx, "k_moments");
   if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
@@ -405,16 +440,24 @@ int phb_tune_get(phb_ctx* ctx, const char* key, int* value) {
 
 int64_t phb_tape_bytes(int64_t n) { return n <= 0 ? 0 : n * TAPE_DOUBLES * (int64_t)sizeof(double); }
 
-int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
-                        const double* lambda, int64_t* offsets, int32_t* idx,
-                        int64_t idx_capacity, int64_t* nnz_out) {
+}  // extern "C"
+
+// Neighbor lists of all n particles (rows == nullptr) or of the m particles
+// rows[0 .. m), into offsets[m + 1] and idx.
+static int neighbors_build_impl(phb_ctx* ctx, const phb_params* p, int64_t n64,
+                                const double* pos, const double* lambda, int64_t m64,
+                                const int32_t* rows, int64_t* offsets, int32_t* idx,
+                                int64_t idx_capacity, int64_t* nnz_out, bool check_rows_) {
   if (!ctx) return PHB_EINVAL;
   int rc;
   if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
   if (!pos || !lambda || !offsets || !nnz_out || idx_capacity < 0 || (idx_capacity > 0 && !idx))
     return set_error(ctx, PHB_EINVAL, "null pointer or negative capacity");
+  if (rows && (m64 < 0 || m64 > n64)) return set_error(ctx, PHB_EINVAL, "bad row count");
   hipSetDevice(ctx->device);
+  if (rows && check_rows_ && (rc = check_rows(ctx, m64, rows, n64))) return rc;
   const int n = (int)n64;
+  const int m = rows ? (int)m64 : n;
   const Box box = make_box(p);
   const int64_t max_cells = kMaxCells;
   Workspace ws(ctx);
@@ -439,17 +482,26 @@ int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n64, const do
                                             cscan, sid, spos),
                       "cell sort")))
     return rc;
+  if (m == 0) {  // no rows: an empty list
+    *nnz_out = 0;
+    // int64 zero is the bit pattern of 0.0
+    return hip_check(ctx, fill_f64(ctx->stream, reinterpret_cast<double*>(offsets), 0.0, 1),
+                     "empty offsets");
+  }
   { Prof pf(ctx, "k_neighbors<false>");
-  if ((rc = hip_check(ctx, launch_neighbor_count(ctx->stream, n, box, g, p->rf_ratio, cstart, sid,
-                                                 spos, cnt),
+  if ((rc = hip_check(ctx,
+                      rows ? launch_neighbor_count_rows(ctx->stream, m, rows, n, pos, lambda, box,
+                                                        g, p->rf_ratio, cstart, sid, spos, cnt)
+                           : launch_neighbor_count(ctx->stream, n, box, g, p->rf_ratio, cstart,
+                                                   sid, spos, cnt),
                       "neighbor count")))
     return rc; }
-  if ((rc = hip_check(ctx, exclusive_scan_i32_to_i64(ctx->stream, cnt, n, offsets, oscan),
+  if ((rc = hip_check(ctx, exclusive_scan_i32_to_i64(ctx->stream, cnt, m, offsets, oscan),
                       "offset scan")))
     return rc;
   if ((rc = ensure_host(ctx, 64))) return rc;
   if ((rc = hip_check(ctx,
-                      hipMemcpyAsync(ctx->host, offsets + n, sizeof(int64_t),
+                      hipMemcpyAsync(ctx->host, offsets + m, sizeof(int64_t),
                                      hipMemcpyDeviceToHost, ctx->stream),
                       "nnz read-back")))
     return rc;
@@ -460,12 +512,44 @@ int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n64, const do
     return set_error(ctx, PHB_ECAPACITY, "idx capacity " + std::to_string(idx_capacity) +
                                              " < required " + std::to_string(nnz));
   { Prof pf(ctx, "k_neighbors<true>");
-  if ((rc = hip_check(ctx, launch_neighbor_fill(ctx->stream, n, box, g, p->rf_ratio, cstart, sid,
-                                                spos, offsets, tmp),
+  if ((rc = hip_check(ctx,
+                      rows ? launch_neighbor_fill_rows(ctx->stream, m, rows, n, pos, lambda, box,
+                                                       g, p->rf_ratio, cstart, sid, spos, offsets,
+                                                       tmp)
+                           : launch_neighbor_fill(ctx->stream, n, box, g, p->rf_ratio, cstart,
+                                                  sid, spos, offsets, tmp),
                       "neighbor fill")))
     return rc; }
   Prof pf_rs(ctx, "k_row_sort");
-  return hip_check(ctx, launch_row_sort(ctx->stream, n, offsets, tmp, idx), "row sort");
+  return hip_check(ctx, launch_row_sort(ctx->stream, m, offsets, tmp, idx), "row sort");
+}
+
+namespace phb {
+int neighbors_rows_unchecked(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                             const double* lambda, int64_t m, const int32_t* rows,
+                             int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+                             int64_t* nnz_out) {
+  return neighbors_build_impl(ctx, p, n, pos, lambda, m, rows, offsets, idx, idx_capacity,
+                              nnz_out, false);
+}
+}  // namespace phb
+
+extern "C" {
+
+int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                        const double* lambda, int64_t* offsets, int32_t* idx,
+                        int64_t idx_capacity, int64_t* nnz_out) {
+  return neighbors_build_impl(ctx, p, n64, pos, lambda, n64, nullptr, offsets, idx, idx_capacity,
+                              nnz_out, false);
+}
+
+int phb_neighbors_build_rows(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                             const double* lambda, int64_t m, const int32_t* rows,
+                             int64_t* offsets, int32_t* idx, int64_t idx_capacity,
+                             int64_t* nnz_out) {
+  if (!rows) return ctx ? set_error(ctx, PHB_EINVAL, "null rows") : PHB_EINVAL;
+  return neighbors_build_impl(ctx, p, n64, pos, lambda, m, rows, offsets, idx, idx_capacity,
+                              nnz_out, true);
 }
 
 int phb_neighbors_transpose(phb_ctx* ctx, int64_t n64, int64_t nnz, const int64_t* offsets,
@@ -595,6 +679,24 @@ int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* po
   return eval_rhs(ctx, a, p, q, rhs, dxdt, status, reinterpret_cast<double*>(tape));
 }
 
+int phb_mhd_rhs_rows(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                     const double* lambda, int64_t m, const int32_t* rows,
+                     const int64_t* offsets, const int32_t* idx, const double* q, double* rhs,
+                     double* dxdt, int32_t* status) {
+  if (!ctx) return PHB_EINVAL;
+  EvalArgs a;
+  int rc;
+  if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
+  if (!rows || !q || !rhs || !dxdt || !status) return set_error(ctx, PHB_EINVAL, "null pointer");
+  if (m <= 0 || m > n64) return set_error(ctx, PHB_EINVAL, "row count must be in [1, n]");
+  hipSetDevice(ctx->device);
+  if ((rc = check_rows(ctx, m, rows, n64))) return rc;
+  a.n_all = a.n;
+  a.n = (int)m;
+  a.rows = rows;
+  return eval_rhs(ctx, a, p, q, rhs, dxdt, status, nullptr);
+}
+
 int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
                         const double* lambda, const int64_t* offsets, const int32_t* idx,
                         const int64_t* t_offsets, const int32_t* t_src, const int32_t* t_pos,
@@ -622,6 +724,25 @@ int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt, doubl
   hipSetDevice(ctx->device);
   return pc_step(ctx, p, (int)n64, dt, pos, q, lambda, nullptr, offsets, idx, idx_capacity,
                  nnz_out, status, 0);
+}
+
+int phb_evolve_blocks(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt_max,
+                      int32_t nblocks, double cfl, int32_t kmax, double* pos, double* q,
+                      const double* lambda, const int32_t* frozen, int64_t* offsets,
+                      int32_t* idx, int64_t idx_capacity, int32_t* status, int32_t* level,
+                      int64_t* stats) {
+  if (!ctx) return PHB_EINVAL;
+  int rc;
+  if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
+  if (!pos || !q || !lambda || !offsets || !idx || !status || !(dt_max > 0.0) ||
+      !isfinite(dt_max) || nblocks < 0 || !(cfl > 0.0) || !isfinite(cfl) || kmax < 0 ||
+      kmax > 30)
+    return set_error(ctx, PHB_EINVAL, "bad arguments");
+  if (p->precision != PHB_FP64)
+    return set_error(ctx, PHB_ENOTIMPL, "individual time steps in the mixed form");
+  hipSetDevice(ctx->device);
+  return evolve_blocks(ctx, p, (int)n64, pos, q, lambda, frozen, dt_max, nblocks, cfl, kmax,
+                       offsets, idx, idx_capacity, status, level, stats);
 }
 
 int phb_evolve(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt, int32_t nsteps,

@@ -52,7 +52,7 @@ template <int G, class T = double>
 __global__ void __launch_bounds__(THREADS)
     k_moments(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
               const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
-              double* __restrict__ mom) {
+              double* __restrict__ mom, const int32_t* __restrict__ rows) {
   const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(THREADS)
   T m[NMOM];
 #pragma unroll
   for (int k = 0; k < NMOM; ++k) m[k] = T(0);
-  const double4 gi = geo[ii];
+  const double4 gi = geo[rows ? rows[ii] : ii];  // row ii's own particle
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
@@ -258,7 +258,8 @@ __global__ void __launch_bounds__(THREADS)
                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
                 double rf_ratio, int wkind, double gamma, Stab sb, const double* __restrict__ gop,
                 const int32_t* __restrict__ status, double* __restrict__ rhs,
-                double* __restrict__ dxdt, double* __restrict__ tape) {
+                double* __restrict__ dxdt, double* __restrict__ tape,
+                const int32_t* __restrict__ rows) {
   constexpr int NR = STAB ? 9 : 3;  // operator rows
   constexpr int NF = STAB ? 8 : 7;  // fields with a gradient: the last NF of eight
   constexpr int F0 = 8 - NF;
@@ -282,9 +283,10 @@ __global__ void __launch_bounds__(THREADS)
                               sc * gop[((int64_t)t * NBASIS + b + 1) * n + ii]);
   }
   __syncthreads();
+  const int me = rows ? rows[ii] : ii;  // row ii's own particle
   double qi[8];
-  load_fields(fq, ii, qi);
-  const double4 gi = geo[ii];
+  load_fields(fq, me, qi);
+  const double4 gi = geo[me];
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(THREADS)
   double gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
   const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
   int64_t s = s0 + l;
-  int jc = ii, jn = ii;
+  int jc = me, jn = me;
   double4 gn = gi;
   if (s < s1) {
     jc = idx[s];
@@ -407,7 +409,7 @@ __global__ void __launch_bounds__(THREADS)
 template <int G, class T>
 hipError_t launch_moments_g(hipStream_t s, const EvalArgs& a, double* mom) {
   hipLaunchKernelGGL((k_moments<G, T>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0,
-                     s, a.n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind, mom);
+                     s, a.n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind, mom, a.rows);
   return hipGetLastError();
 }
 
@@ -497,7 +499,7 @@ static hipError_t rhs_g(hipStream_t s, const EvalArgs& a, double gamma, const St
                         double* tape) {
   hipLaunchKernelGGL((k_apply_rhs<G, STAB>), dim3(grid_for((int64_t)a.n * G, THREADS)),
                      dim3(THREADS), 0, s, a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio,
-                     a.wkind, gamma, sb, gop, status, rhs, dxdt, tape);
+                     a.wkind, gamma, sb, gop, status, rhs, dxdt, tape, a.rows);
   return hipGetLastError();
 }
 

@@ -26,6 +26,11 @@ struct EvalArgs {
   int fit = PHB_FIT_FULL20;  // PHB_FIT_FULL20 or PHB_FIT_INTERP19
   const double4* geo = nullptr;
   const double* fq = nullptr;
+  // Row subset: n rows whose own particles are rows[0 .. n) out of n_all
+  // (the lists off/idx and every per-row output then have n rows); null
+  // rows: row i is particle i and n_all = n.
+  const int32_t* rows = nullptr;
+  int n_all = 0;
 };
 
 // Tape of the forward evaluation, per particle (SoA, n entries each):

@@ -186,6 +186,36 @@ __global__ void __launch_bounds__(NB_THREADS)
   }
 }
 
+// The same for a list of rows: thread r handles particle rows[r] (read from
+// the unsorted SoA positions, which the sorted copy holds bit for bit) and
+// writes its count or its entries at row r.
+template <bool FILL>
+__global__ void __launch_bounds__(NB_THREADS)
+    k_neighbors_rows(int m, const int32_t* __restrict__ rows, int n,
+                     const double* __restrict__ pos, const double* __restrict__ lam, Box box,
+                     Grid g, double rf_ratio, const int32_t* __restrict__ cell_start,
+                     const int32_t* __restrict__ sorted_id, const double4* __restrict__ spos,
+                     int32_t* __restrict__ count, const int64_t* __restrict__ offsets,
+                     int32_t* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const int i = rows[r];
+  const double xi = pos[i], yi = pos[(int64_t)n + i], zi = pos[2 * (int64_t)n + i];
+  const double li = lam[i];
+  const double r2 = radius2_nofma(rf_ratio, li);
+  const double rad = rf_ratio * li;
+  if (!FILL) {
+    int c = 0;
+    for_each_neighbor(xi, yi, zi, rad, r2, box, g, cell_start, sorted_id, spos,
+                      [&](int, int) { ++c; });
+    count[r] = c;
+  } else {
+    int64_t o = offsets[r];
+    for_each_neighbor(xi, yi, zi, rad, r2, box, g, cell_start, sorted_id, spos,
+                      [&](int, int j) { out[o++] = j; });
+  }
+}
+
 // ---- per-row ascending sort ------------------------------------------------
 // One wavefront per row; rows up to ROW_LDS entries are bitonic-sorted in
 // LDS, longer rows by rank counting straight from global memory.
@@ -371,6 +401,28 @@ hipError_t launch_neighbor_fill(hipStream_t s, int n, const Box& box, const Grid
                                 const int64_t* offsets, int32_t* tmp) {
   hipLaunchKernelGGL((k_neighbors<true>), dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s,
                      n, box, g, rf_ratio, cell_start, sorted_id, spos, nullptr, offsets, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_neighbor_count_rows(hipStream_t s, int m, const int32_t* rows, int n,
+                                      const double* pos, const double* lam, const Box& box,
+                                      const Grid& g, double rf_ratio, const int32_t* cell_start,
+                                      const int32_t* sorted_id, const double4* spos,
+                                      int32_t* count) {
+  hipLaunchKernelGGL((k_neighbors_rows<false>), dim3(grid_for(m, NB_THREADS)), dim3(NB_THREADS),
+                     0, s, m, rows, n, pos, lam, box, g, rf_ratio, cell_start, sorted_id, spos,
+                     count, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_neighbor_fill_rows(hipStream_t s, int m, const int32_t* rows, int n,
+                                     const double* pos, const double* lam, const Box& box,
+                                     const Grid& g, double rf_ratio, const int32_t* cell_start,
+                                     const int32_t* sorted_id, const double4* spos,
+                                     const int64_t* offsets, int32_t* tmp) {
+  hipLaunchKernelGGL((k_neighbors_rows<true>), dim3(grid_for(m, NB_THREADS)), dim3(NB_THREADS),
+                     0, s, m, rows, n, pos, lam, box, g, rf_ratio, cell_start, sorted_id, spos,
+                     nullptr, offsets, tmp);
   return hipGetLastError();
 }
 

@@ -28,6 +28,17 @@ hipError_t launch_neighbor_fill(hipStream_t s, int n, const Box& box, const Grid
                                 double rf_ratio, const int32_t* cell_start,
                                 const int32_t* sorted_id, const double4* spos,
                                 const int64_t* offsets, int32_t* tmp);
+// The same for the particles rows[0 .. m): counts and entries per row.
+hipError_t launch_neighbor_count_rows(hipStream_t s, int m, const int32_t* rows, int n,
+                                      const double* pos, const double* lam, const Box& box,
+                                      const Grid& g, double rf_ratio, const int32_t* cell_start,
+                                      const int32_t* sorted_id, const double4* spos,
+                                      int32_t* count);
+hipError_t launch_neighbor_fill_rows(hipStream_t s, int m, const int32_t* rows, int n,
+                                     const double* pos, const double* lam, const Box& box,
+                                     const Grid& g, double rf_ratio, const int32_t* cell_start,
+                                     const int32_t* sorted_id, const double4* spos,
+                                     const int64_t* offsets, int32_t* tmp);
 hipError_t launch_row_sort(hipStream_t s, int64_t nrows, const int64_t* off, const int32_t* in,
                            int32_t* out);
 hipError_t launch_transpose(hipStream_t s, int n, int64_t nnz, const int64_t* off,
