@@ -55,7 +55,7 @@ Box make_box(const phb_params* p) {
   return b;
 }
 
-static int ensure_host(phb_ctx* ctx, size_t bytes) {
+int ensure_host(phb_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->host_cap) return PHB_OK;
   if (ctx->host) hipHostFree(ctx->host);
   ctx->host = nullptr;

@@ -47,6 +47,8 @@ namespace phb {
 
 int set_error(phb_ctx* ctx, int code, const std::string& msg);
 int check_params(phb_ctx* ctx, const phb_params* p);
+// Grows the context's pinned host staging buffer (ctx->host) to bytes.
+int ensure_host(phb_ctx* ctx, size_t bytes);
 int check_n(phb_ctx* ctx, int64_t n);
 // The stabiliser coefficients of p (all zero: ideal MHD).
 Stab stab_of(const phb_params* p);

@@ -431,14 +431,11 @@ int evolve_blocks(phb_ctx* ctx, const phb_params* p, int n, double* pos, double*
   const unsigned gn = grid_for(n, THREADS);
   int64_t events = 0, evals = 0;
 
+  if ((rc = ensure_host(ctx, DT_BLOCKS * sizeof(int64_t)))) return rc;
   auto read_back = [&](void* dst, const void* src, size_t bytes) -> int {
-    void* h = nullptr;
-    if (hipHostMalloc(&h, bytes) != hipSuccess)
-      return set_error(ctx, PHB_EHIP, "pinned read-back allocation");
-    hipError_t e = hipMemcpyAsync(h, src, bytes, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(ctx->host, src, bytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) std::memcpy(dst, h, bytes);
-    hipHostFree(h);
+    if (e == hipSuccess) std::memcpy(dst, ctx->host, bytes);
     return hip_check(ctx, e, "block-step read-back");
   };
   // rows <- the flagged particles; returns their count in *m
@@ -530,10 +527,11 @@ int evolve_blocks(phb_ctx* ctx, const phb_params* p, int n, double* pos, double*
       if ((rc = compact(tick, 0, &m))) return rc;
       ++events;
       if ((rc = hip_check(ctx, fill_i32(s, hflag + 1, 0, 1), "flag clear"))) return rc;
+      // a predicted position off an open axis fails the list build's input
+      // check; the flag is read once, after the corrector
       hipLaunchKernelGGL(k_blk_predict, dim3(gn), dim3(THREADS), 0, s, n, box, pos, q, V0, F0, t0,
                          tick, dtick, xp, qp, hflag + 1);
       if ((rc = hip_check(ctx, hipGetLastError(), "predict"))) return rc;
-      if ((rc = check_left())) return rc;
       if ((rc = eval_rows(m))) return rc;
       hipLaunchKernelGGL(k_blk_correct, dim3(grid_for(m, THREADS)), dim3(THREADS), 0, s, m, rows,
                          n, box, T, lev, dtick, tick, f, v, st, F0, V0, pos, q, xp, qp, t0, stmax,

@@ -299,3 +299,27 @@ def random_cloud(n: int, seed: int, box=(1.0, 1.0, 1.0), lam_range=(0.08, 0.12),
             q[f] += am * np.sin(2 * np.pi * ((km / box) @ pos) + ph)
     return dict(pos=pos, lam=lam, q=q, L=tuple(box), periodic=tuple(periodic), gamma=GAMMA,
                 name=f"cloud_{n}")
+
+
+def graded_lattice(side: int = 10, seed: int = 101, wave: bool = True):
+    """A jittered side^3 lattice in the periodic unit cube whose resolution
+    varies smoothly, lambda = h (1.25 + 0.35 sin 2 pi x) with h = 1/side (0.9 to
+    1.6 spacings), so that individual time steps spread over levels.  It
+    carries a small sound wave (the set of linear_wave("sound"), eps = 1e-3)
+    or smooth random-phase fields."""
+    h = 1.0 / side
+    if wave:
+        c = linear_wave("sound", side, eps=1e-3, seed=seed)
+        pos, q = c["pos"], c["q"]
+    else:
+        rng = np.random.default_rng(seed)
+        pos = jittered_lattice(side, 0.3, rng)
+        n = pos.shape[1]
+        q = np.zeros((8, n))
+        q[0] = 1.0 + 0.1 * np.sin(2 * np.pi * (pos[1] + 0.2))
+        q[1:4] = 0.05 * np.cos(2 * np.pi * pos[[2, 0, 1]])
+        q[4:7] = np.array([0.5, -0.2, 0.3])[:, None] + 0.05 * np.sin(2 * np.pi * pos)
+        q[7] = 1.5 + 0.1 * np.cos(2 * np.pi * pos[2])
+    lam = h * (1.25 + 0.35 * np.sin(2 * np.pi * pos[0]))
+    return dict(pos=pos, lam=lam, q=q, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=GAMMA,
+                name=f"graded_lattice{side}")

@@ -17,26 +17,7 @@ import oracle
 from paper_1110_0836_amd import synth
 
 
-def graded_set(side=10, seed=101, wave=True):
-    """Jittered lattice with lambda = h (1.25 + 0.35 sin 2 pi x) carrying a
-    small sound wave (or smooth random fields)."""
-    rng = np.random.default_rng(seed)
-    pos = synth.jittered_lattice(side, 0.3, rng)
-    n = pos.shape[1]
-    h = 1.0 / side
-    lam = h * (1.25 + 0.35 * np.sin(2 * np.pi * pos[0]))
-    if wave:
-        c = synth.linear_wave("sound", side, eps=1e-3, seed=seed)
-        q = c["q"]
-        pos = c["pos"]
-        lam = h * (1.25 + 0.35 * np.sin(2 * np.pi * pos[0]))
-    else:
-        q = np.zeros((8, n))
-        q[0] = 1.0 + 0.1 * np.sin(2 * np.pi * (pos[1] + 0.2))
-        q[1:4] = 0.05 * np.cos(2 * np.pi * pos[[2, 0, 1]])
-        q[4:7] = np.array([0.5, -0.2, 0.3])[:, None] + 0.05 * np.sin(2 * np.pi * pos)
-        q[7] = 1.5 + 0.1 * np.cos(2 * np.pi * pos[2])
-    return dict(pos=pos, lam=lam, q=q, L=(1.0, 1.0, 1.0), periodic=(1, 1, 1), gamma=5 / 3)
+graded_set = synth.graded_lattice
 
 
 @pytest.mark.parametrize("stab", [None, (0.3, 0.3, 0.3)])
