@@ -719,13 +719,26 @@ __global__ void __launch_bounds__(THREADS)
   // pair terms then read it row by row at LDS latency
   __shared__ CT osh[THREADS / 64][OR];
   const int wv = threadIdx.x >> 6;
+  // Each lane's first entry (index, neighbor geometry, transposed position)
+  // is fetched before the barrier, so that this dependent chain of loads
+  // overlaps the staging of the owner record; later entries are fetched one
+  // iteration ahead.
+  int64_t rs = 0, re = 0;
+  double4 gi = make_double4(0.0, 0.0, 0.0, 1.0), gjn = gi;
+  int jn = 0, tpn = 0;
   if (i < n) {
+    rs = off[i];
+    re = off[i + 1];
+    gi = geo[i];
+    if (rs + lane < re) {
+      jn = idx[rs + lane];
+      gjn = geo[jn];
+      if (!slot_order) tpn = t_pos[rs + lane];
+    }
     for (int k = lane; k < OR; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OR + k]);
   }
   __syncthreads();
   if (i >= n) return;  // whole wavefronts leave together
-  const int64_t rs = off[i], re = off[i + 1];
-  const double4 gi = geo[i];
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
@@ -735,12 +748,18 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
   for (int c = 0; c < RC; ++c) acc[c] = 0.0;
   for (int64_t s = rs + lane; s < re; s += 64) {
-    const int j = idx[s];
+    const int j = jn;
+    const double4 gj = gjn;
+    const int tp = tpn;
+    if (s + 64 < re) {
+      jn = idx[s + 64];
+      gjn = geo[jn];
+      if (!slot_order) tpn = t_pos[s + 64];
+    }
     CT v[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) v[c] = CT(0);
     if (j != i) {
-      const double4 gj = geo[j];
       const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
       const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
       const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
@@ -749,7 +768,7 @@ __global__ void __launch_bounds__(THREADS)
       const double dw = weight_dq(qd, wkind);
       pair_terms<CT, STAB>(o, w, dw, inv_lam, inv_r2, dx, dy, dz, fi, fq + 8 * (int64_t)j, v);
     }
-    RT* out = rec + (slot_order ? s : (int64_t)t_pos[s]) * RC;
+    RT* out = rec + (slot_order ? s : (int64_t)tp) * RC;
     if constexpr (sizeof(RT) == 8) {
       double2* o2 = reinterpret_cast<double2*>(out);
 #pragma unroll
