@@ -190,6 +190,17 @@ __global__ void __launch_bounds__(THREADS)
   constexpr int PPB = THREADS / G;
   __shared__ double2 ush[11][PPB];
   const int pl = threadIdx.x / G;
+  // the first neighbor entry is fetched before the pointwise part and the
+  // barrier, whose work then covers its latency
+  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
+  int64_t s = s0 + l;
+  int jc = ii, jn = ii;
+  double4 gn = gi;
+  if (s < s1) {
+    jc = idx[s];
+    gn = geo[jc];
+  }
+  if (s + G < s1) jn = idx[s + G];
   double qi[8];
   {
     double ub[7][3], qb[8];
@@ -219,15 +230,6 @@ __global__ void __launch_bounds__(THREADS)
   for (int t = 0; t < 3; ++t)
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b) y[t][b] = 0.0;
-  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
-  int64_t s = s0 + l;
-  int jc = ii, jn = ii;
-  double4 gn = gi;
-  if (s < s1) {
-    jc = idx[s];
-    gn = geo[jc];
-  }
-  if (s + G < s1) jn = idx[s + G];
   for (; s < s1; s += G) {
     const double4 gj = gn;
     const int j = jc;
@@ -319,6 +321,16 @@ __global__ void __launch_bounds__(THREADS)
   constexpr int PPB = THREADS / G;
   __shared__ double2 ush[12][PPB];
   const int pl = threadIdx.x / G;
+  // first neighbor entry ahead of the staging and the barrier
+  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
+  int64_t s = s0 + l;
+  int jc = ii, jn = ii;
+  double4 gn = gi;
+  if (s < s1) {
+    jc = idx[s];
+    gn = geo[jc];
+  }
+  if (s + G < s1) jn = idx[s + G];
   for (int k = l; k < 12; k += G) {
     const int e0 = 2 * k, e1 = 2 * k + 1;
     const double* u = orec + (int64_t)ii * S9::OREC + S9::UOFF;
@@ -334,10 +346,14 @@ __global__ void __launch_bounds__(THREADS)
   for (int t = 0; t < 3; ++t)
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b) y[t][b] = 0.0;
-  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
-  for (int64_t s = s0 + l; s < s1; s += G) {
-    const int j = idx[s];
-    const double4 gj = geo[j];
+  for (; s < s1; s += G) {
+    const double4 gj = gn;
+    const int j = jc;
+    if (s + G < s1) {
+      gn = geo[jn];
+      jc = jn;
+      if (s + 2 * G < s1) jn = idx[s + 2 * G];
+    }
     double qj[8];
     load_fields(fq, j, qj);
     const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);

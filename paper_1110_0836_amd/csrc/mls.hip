@@ -276,26 +276,11 @@ __global__ void __launch_bounds__(THREADS)
   constexpr int PPB = THREADS / G;
   __shared__ double2 gsh[NR * NBASIS / 2][PPB];
   const int pl = threadIdx.x / G;
-  for (int k = l; k < NR * NBASIS / 2; k += G) {
-    const int t = (2 * k) / NBASIS, b = (2 * k) % NBASIS;
-    const double sc = (STAB && (t == 3 || t == 6 || t == 8)) ? 2.0 : 1.0;
-    gsh[k][pl] = make_double2(sc * gop[((int64_t)t * NBASIS + b) * n + ii],
-                              sc * gop[((int64_t)t * NBASIS + b + 1) * n + ii]);
-  }
-  __syncthreads();
+  // The lane's own data and its first neighbor entry are fetched before the
+  // rows are staged, so that their latency overlaps the staging and the
+  // barrier.
   const int me = rows ? rows[ii] : ii;  // row ii's own particle
-  double qi[8];
-  load_fields(fq, me, qi);
   const double4 gi = geo[me];
-  const double inv_lam = 1.0 / gi.w;
-  const double r = rf_ratio * gi.w;
-  const double inv_r2 = 1.0 / (r * r);
-  double acc[NF][3];
-#pragma unroll
-  for (int f = 0; f < NF; ++f)
-#pragma unroll
-    for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
-  double gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
   const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
   int64_t s = s0 + l;
   int jc = me, jn = me;
@@ -305,6 +290,24 @@ __global__ void __launch_bounds__(THREADS)
     gn = geo[jc];
   }
   if (s + G < s1) jn = idx[s + G];
+  double qi[8];
+  load_fields(fq, me, qi);
+  for (int k = l; k < NR * NBASIS / 2; k += G) {
+    const int t = (2 * k) / NBASIS, b = (2 * k) % NBASIS;
+    const double sc = (STAB && (t == 3 || t == 6 || t == 8)) ? 2.0 : 1.0;
+    gsh[k][pl] = make_double2(sc * gop[((int64_t)t * NBASIS + b) * n + ii],
+                              sc * gop[((int64_t)t * NBASIS + b + 1) * n + ii]);
+  }
+  __syncthreads();
+  const double inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
+  const double inv_r2 = 1.0 / (r * r);
+  double acc[NF][3];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
+  double gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
   for (; s < s1; s += G) {
     const double4 gj = gn;
     const int j = jc;
