@@ -64,10 +64,12 @@ extern "C" {
 
 #define PHB_FP64 0        /* all arithmetic in FP64 */
 #define PHB_MIXED 1       /* FP32 assembly and application, FP64 factor and solve,
-                             one data-level refinement step; particles whose
-                             FP32 moment matrix is too ill-conditioned for one
-                             step are evaluated in FP64 (see mixed_cond_exp);
-                             the reverse mode assembles its moments in FP64 */
+                             one refinement step (see mixed_refine: by default
+                             one Newton step on the operator rows with an FP64
+                             residual product); particles whose FP32 moment
+                             matrix is too ill-conditioned for one step are
+                             evaluated in FP64 (see mixed_cond_exp); the
+                             reverse mode assembles its moments in FP64 */
 #define PHB_W_POLY3 0     /* w = (1 - d^2/r_f^2)^3 */
 #define PHB_W_UNIT 1      /* w = 1 */
 #define PHB_FIT_FULL20 0  /* all 20 monomials, constant included */
@@ -356,7 +358,14 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * default 2: in the mixed form a particle whose FP32-assembled moment matrix,
  * scaled to unit diagonal, has an estimated ||A^{-1}||_2 above 10^exp is
  * evaluated in FP64 instead; this knob moves results within the mixed
- * tolerance, the others only by rounding).  EINVAL for an unknown key or value. */
+ * tolerance, the others only by rounding), "mixed_refine" (mixed form's
+ * refinement step; 1, the default: the rows G~ = E A~^{-1} of the inverse of
+ * the FP32-assembled matrix are refined once, G^ = 2 G~ - (G~ A) A~^{-1}, with
+ * the product G~ A formed in FP64 over the neighbors, and G^ is applied to
+ * the fields in FP32; 0: each field's coefficients are solved for and refined
+ * once from their residuals at the neighbors, all sums in FP32 (corrected
+ * seminormal equations); the two agree within the mixed tolerance).  EINVAL
+ * for an unknown key or value. */
 int phb_tune_set(phb_ctx* ctx, const char* key, int value);
 int phb_tune_get(phb_ctx* ctx, const char* key, int* value);
 /* Autotuner: times one forward + reverse pass of the given set (or batch

@@ -356,6 +356,133 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
+// ---- operator-level refinement ----------------------------------------------
+// With G~ = E A~^{-1} from the FP32-assembled moments, one Newton step on the
+// operator rows gives
+//   G^ = G~ (2 I - A A~^{-1}) = 2 G~ - (G~ A) A~^{-1},
+// whose error is quadratic in that of G~: G^ - E A^{-1} =
+// -E (A~^{-1} - A^{-1}) A (A~^{-1} - A^{-1}).  The product G~ A is the
+// residual of the step and must be formed more accurately than the error it
+// removes, so this pass runs in FP64:
+//   M_t = sum_j w_j (G~_t . p_j) p_j^T
+// for three rows r0 .. r0 + 2 at a time (60 accumulators per lane).  The
+// particle's three rows of G~ wait in LDS.  Particles with a nonzero status
+// or on the FP64 list skip the neighbor loop (their rows are final).
+template <int G>
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_gta(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
+                const double* __restrict__ gt, int r0, const int32_t* __restrict__ status,
+                const int32_t* __restrict__ flag, double* __restrict__ mbuf) {
+  const int tid = xcd_block() * THREADS + threadIdx.x;
+  const int i = tid / G;
+  const int l = tid % G;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  const double4 gi = geo[ii];
+  const bool go = valid && status[ii] == 0 && flag[ii] == 0;
+  // the first neighbor entry is fetched ahead of the staging and the barrier
+  const int64_t s0 = off[ii], s1 = go ? off[ii + 1] : s0;
+  int64_t s = s0 + l;
+  int jn = ii;
+  double4 gn = gi;
+  if (s < s1) gn = geo[idx[s]];
+  if (s + G < s1) jn = idx[s + G];
+  constexpr int PPB = THREADS / G;
+  __shared__ double2 gsh[3 * NBASIS / 2][PPB];
+  const int pl = threadIdx.x / G;
+  for (int k = l; k < 3 * NBASIS / 2; k += G) {
+    const int t = (2 * k) / NBASIS, b = (2 * k) % NBASIS;
+    gsh[k][pl] = make_double2(gt[((int64_t)(r0 + t) * NBASIS + b) * n + ii],
+                              gt[((int64_t)(r0 + t) * NBASIS + b + 1) * n + ii]);
+  }
+  __syncthreads();
+  const double inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
+  const double inv_r2 = 1.0 / (r * r);
+  double m[3][NBASIS];
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) m[t][b] = 0.0;
+  for (; s < s1; s += G) {
+    const double4 gj = gn;
+    if (s + G < s1) {
+      gn = geo[jn];
+      if (s + 2 * G < s1) jn = idx[s + 2 * G];
+    }
+    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+    const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+    double p[NBASIS];
+    basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    asm volatile("" ::: "memory");  // re-read the rows from LDS every iteration
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      double v = 0.0;
+#pragma unroll
+      for (int b = 0; b < NBASIS; b += 2) {
+        const double2 gg = gsh[(t * NBASIS + b) / 2][pl];
+        v = fma(gg.x, p[b], v);
+        v = fma(gg.y, p[b + 1], v);
+      }
+      const double a = w * v;
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b) m[t][b] = fma(a, p[b], m[t][b]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 3; ++t)
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) m[t][b] = group_sum<G>(m[t][b]);
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b)
+        if ((t * NBASIS + b) % G == l) mbuf[((int64_t)(r0 + t) * NBASIS + b) * n + i] = m[t][b];
+  }
+}
+
+// The Newton step G^_t = 2 G~_t - A~^{-1} M_t for rows 1..NG (quad per
+// particle; A~ factored again, as in the screening).  In the interpolating
+// fit the constant's row and column of A are the identity's: M_t's constant
+// entry is dropped, which keeps G^_t's constant entry at zero.
+template <int NG>
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_refine(int n, const double* __restrict__ mom, const double* __restrict__ mbuf,
+                   double* __restrict__ gt, const int32_t* __restrict__ status,
+                   const int32_t* __restrict__ flag, int interp) {
+  static_assert(NG % 3 == 0, "rows in groups of three");
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int l = tid & 3;
+  const int i = tid >> 2;
+  if (i >= n) return;  // whole quads leave together
+  if (status[i] != 0 || flag[i] != 0) return;
+  QuadChol c;
+  quad_chol_factor(c, c_mtab, mom, n, i, l, interp != 0);
+  sfor<0, NG / 3>([&](auto GI) {
+    constexpr int t0 = 3 * GI;
+    double y[3][5], x[3][5];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int rho = 0; rho < 5; ++rho) {
+        const double b = mbuf[((int64_t)(t0 + r) * NBASIS + 4 * rho + l) * n + i];
+        y[r][rho] = (interp && rho == 0 && l == 0) ? 0.0 : b * c.s_own[rho];
+      }
+    quad_chol_solve_n<0, 3>(c, l, y, x);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int rho = 0; rho < 5; ++rho) {
+        const int64_t k = ((int64_t)(t0 + r) * NBASIS + 4 * rho + l) * n + i;
+        gt[k] = fma(-x[r][rho], c.s_own[rho], 2.0 * gt[k]);
+      }
+  });
+}
+
 // Gradients = rows / lambda; pointwise right-hand side; tape.  Ideal form:
 // rows[f][3][n] of the seven fields V, B, sigma.  STAB: rows[f][9][n] of all
 // eight fields, whose second-derivative rows (xx, xy, xz, yy, yz, zz) give
@@ -544,19 +671,133 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
   return hip_check(ctx, hipGetLastError(), "mixed residual");
 }
 
+struct OpBufs {
+  double* mom;
+  double* gt;
+  double* mb;
+  int32_t* flag;
+  int32_t* list;
+  int32_t* count;
+};
+
+void plan_op(Workspace& ws, int64_t n, int ng) {
+  const size_t nd = (size_t)n * sizeof(double);
+  ws.plan(NMOM * nd);
+  ws.plan((size_t)ng * NBASIS * nd);
+  ws.plan((size_t)ng * NBASIS * nd);
+  ws.plan((size_t)n * sizeof(int32_t));
+  ws.plan((size_t)n * sizeof(int32_t));
+  ws.plan(sizeof(int32_t));
+}
+
+OpBufs take_op(Workspace& ws, int64_t n, int ng) {
+  OpBufs m;
+  m.mom = ws.take<double>((size_t)NMOM * n);
+  m.gt = ws.take<double>((size_t)ng * NBASIS * n);
+  m.mb = ws.take<double>((size_t)ng * NBASIS * n);
+  m.flag = ws.take<int32_t>(n);
+  m.list = ws.take<int32_t>(n);
+  m.count = ws.take<int32_t>(1);
+  return m;
+}
+
+constexpr int GTA_LANES = 2;  // lanes sharing a particle in k_mixed_gta
+
+// Refined operator rows 1..NG of A^{-1} into m.gt: FP32 moments (FP64 for the
+// particles the screen lists), the FP64 factor with the screen, the FP64
+// residual product G~ A and the Newton step.
+template <int NG>
+int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* status) {
+  hipStream_t s = ctx->stream;
+  const int n = a.n;
+  const double ncut = pow(10.0, (double)ctx->mixed_cond_exp);
+  const int interp = a.fit == PHB_FIT_INTERP19;
+  const unsigned gq = grid_for((int64_t)n * 4, THREADS);
+  int rc;
+  { Prof pf(ctx, "k_moments<fp32>");
+    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, m.mom, true), "moments")))
+      return rc; }
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
+  { Prof pf(ctx, "k_mixed_factor");
+    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, 0,
+                       nullptr, nullptr, m.gt, status, m.flag, ncut, nullptr, m.list, m.count,
+                       interp);
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed factor"))) return rc; }
+  { Prof pf(ctx, "k_mixed_repair");
+    hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, a.geo, a.off,
+                       a.idx, a.box, a.rf_ratio, a.wkind, nullptr, 0, 0, m.list, m.count, m.mom,
+                       nullptr);
+    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, m.mom,
+                       a.off, 0, nullptr, nullptr, m.gt, status, m.flag, ncut, m.list, nullptr,
+                       m.count, interp);
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed repair"))) return rc; }
+  { Prof pf(ctx, "k_mixed_gta");
+    for (int r0 = 0; r0 < NG; r0 += 3)
+      hipLaunchKernelGGL((k_mixed_gta<GTA_LANES>), dim3(grid_for((int64_t)n * GTA_LANES, THREADS)),
+                         dim3(THREADS), 0, s, n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind,
+                         m.gt, r0, status, m.flag, m.mb);
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed residual product"))) return rc; }
+  Prof pf(ctx, "k_mixed_refine");
+  hipLaunchKernelGGL((k_mixed_refine<NG>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, m.mb, m.gt,
+                     status, m.flag, interp);
+  return hip_check(ctx, hipGetLastError(), "mixed refinement");
+}
+
 }  // namespace
 
 size_t mixed_rhs_bytes(int64_t n, bool stab) {
   phb_ctx dummy;
   Workspace ws(&dummy);
+  // the larger of the two refinement forms
   plan_mixed(ws, n, stab ? 8 : 7, stab ? 9 : 3);
   ws.plan((size_t)n * sizeof(double4));
   ws.plan((size_t)8 * n * sizeof(double));
   return ws.total;
 }
 
+// Operator-level form of mixed_rhs: the refined rows applied in FP32.
+static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb,
+                        const double* q, double* rhs, double* dxdt, int32_t* status,
+                        double* tape) {
+  const int n = a0.n;
+  const bool stab = sb.on();
+  const int ng = stab ? 9 : 3;
+  Workspace ws(ctx);
+  plan_op(ws, n, ng);
+  ws.plan((size_t)n * sizeof(double4));
+  ws.plan((size_t)8 * n * sizeof(double));
+  int rc;
+  if ((rc = ws.commit())) return rc;
+  OpBufs m = take_op(ws, n, ng);
+  double4* geo = ws.take<double4>(n);
+  double* fq = ws.take<double>((size_t)8 * n);
+  if (tape) m.mom = tape + (size_t)TAPE_MOM * n;
+  EvalArgs a = a0;
+  a.geo = geo;
+  a.fq = fq;
+  { Prof pf(ctx, "k_pack");
+    if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
+      return rc; }
+  rc = stab ? mixed_operator<9>(ctx, a, m, status) : mixed_operator<3>(ctx, a, m, status);
+  if (rc) return rc;
+  { Prof pf(ctx, stab ? "k_apply_rhs<fp32, stab>" : "k_apply_rhs<fp32>");
+    if ((rc = hip_check(ctx,
+                        launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, gamma, sb, m.gt,
+                                         status, rhs, dxdt, tape, true),
+                        "mixed apply")))
+      return rc; }
+  // the listed (ill-conditioned) particles again, in FP64: applied in FP32,
+  // their operator would lose kappa eps_32
+  Prof pf(ctx, "k_apply_rhs<list>");
+  return hip_check(ctx,
+                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, gamma, sb, m.gt, status,
+                                    rhs, dxdt, tape, false, m.list, m.count),
+                   "mixed apply (listed)");
+}
+
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, const double* q,
               double* rhs, double* dxdt, int32_t* status, double* tape) {
+  if (ctx->mixed_refine == 1) return mixed_rhs_op(ctx, a0, gamma, sb, q, rhs, dxdt, status, tape);
   const int n = a0.n;
   const bool stab = sb.on();
   // ideal: V, B, sigma (records 1..7), three rows; stabilised: all eight
@@ -602,8 +843,41 @@ size_t mixed_derivs_bytes(int64_t n, bool second) {
   return ws.total;
 }
 
+// Operator-level form of mixed_derivs: one refined operator serves every
+// field.
+static int mixed_derivs_op(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields,
+                           double* d1, double* d2, int32_t* status) {
+  const int n = a0.n;
+  const int ng = d2 ? 9 : 3;
+  Workspace ws(ctx);
+  plan_op(ws, n, ng);
+  ws.plan((size_t)n * sizeof(double4));
+  int rc;
+  if ((rc = ws.commit())) return rc;
+  OpBufs m = take_op(ws, n, ng);
+  double4* geo = ws.take<double4>(n);
+  EvalArgs a = a0;
+  a.geo = geo;
+  if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, nullptr, geo, nullptr),
+                      "pack")))
+    return rc;
+  rc = d2 ? mixed_operator<9>(ctx, a, m, status) : mixed_operator<3>(ctx, a, m, status);
+  if (rc) return rc;
+  if ((rc = hip_check(ctx,
+                      launch_apply_derivs(ctx->stream, a, ctx->lanes_apply, m.gt, status, nf,
+                                          fields, d1, d2, true),
+                      "mixed derivatives")))
+    return rc;
+  // the listed particles again in FP64 (as in mixed_rhs_op)
+  return hip_check(ctx,
+                   launch_apply_derivs(ctx->stream, a, ctx->lanes_apply, m.gt, status, nf, fields,
+                                       d1, d2, false, m.list, m.count),
+                   "mixed derivatives (listed)");
+}
+
 int mixed_derivs(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields, double* d1,
                  double* d2, int32_t* status) {
+  if (ctx->mixed_refine == 1) return mixed_derivs_op(ctx, a0, nf, fields, d1, d2, status);
   const int n = a0.n;
   const int ng = d2 ? 9 : 3;
   Workspace ws(ctx);

@@ -168,19 +168,25 @@ __global__ void __launch_bounds__(THREADS)
 // ---------------------------------------------------------------------------
 constexpr int FCHUNK = 8;
 
-template <int G>
+// CT as in k_apply_rhs (float: the mixed form's FP32 application of operator
+// weights formed in FP64).
+template <int G, class CT = double>
 __global__ void __launch_bounds__(THREADS)
     k_apply_derivs(int n, const double* __restrict__ pos, const double* __restrict__ lam,
                    const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
                    double rf_ratio, int wkind, const double* __restrict__ gop, int row0,
                    const int32_t* __restrict__ status, int nf, int f0,
                    const double* __restrict__ fields, double* __restrict__ out, int out_comp,
-                   int comp0, double c0, double c1, double c2, int power) {
+                   int comp0, double c0, double c1, double c2, int power,
+                   const int32_t* __restrict__ list, const int32_t* __restrict__ count) {
   const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
+  // list form: only the particles list[0 .. *count) (count read on the device)
+  const int m = count ? *count : n;
+  if (m == 0) return;
+  const bool valid = i < m;
+  const int ii = list ? list[valid ? i : m - 1] : (valid ? i : m - 1);
   const int st = status[ii];
   double g[3][NBASIS];
 #pragma unroll
@@ -196,11 +202,11 @@ __global__ void __launch_bounds__(THREADS)
   const double inv_lam = 1.0 / li;
   const double r = rf_ratio * li;
   const double inv_r2 = 1.0 / (r * r);
-  double acc[FCHUNK][3];
+  CT acc[FCHUNK][3];
 #pragma unroll
   for (int f = 0; f < FCHUNK; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
+    for (int t = 0; t < 3; ++t) acc[f][t] = CT(0);
   const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
   for (int64_t s = s0 + l; s < s1; s += G) {
     const int j = idx[s];
@@ -211,35 +217,36 @@ __global__ void __launch_bounds__(THREADS)
     const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
     double p[NBASIS];
     basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-    double gam[3];
+    CT gam[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       double v = 0.0;
 #pragma unroll
       for (int b = 0; b < NBASIS; ++b) v = fma(g[t][b], p[b], v);
-      gam[t] = w * v;
+      gam[t] = CT(w * v);
     }
 #pragma unroll
     for (int f = 0; f < FCHUNK; ++f) {
       if (f < nfc) {
-        const double df = fields[(int64_t)(f0 + f) * n + j] - fi[f];
+        const CT df = CT(fields[(int64_t)(f0 + f) * n + j] - fi[f]);
 #pragma unroll
         for (int t = 0; t < 3; ++t) acc[f][t] = fma(gam[t], df, acc[f][t]);
       }
     }
   }
+  double sum[FCHUNK][3];
 #pragma unroll
   for (int f = 0; f < FCHUNK; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) acc[f][t] = group_sum<G>(acc[f][t]);
+    for (int t = 0; t < 3; ++t) sum[f][t] = group_sum<G>(double(acc[f][t]));
   if (valid && l == 0) {
     const double scale = power == 1 ? inv_lam : inv_lam * inv_lam;
     const double cf[3] = {c0, c1, c2};
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
     for (int f = 0; f < nfc; ++f)
       for (int t = 0; t < 3; ++t)
-        out[((int64_t)(f0 + f) * out_comp + comp0 + t) * n + i] =
-            st == 0 ? cf[t] * acc[f][t] * scale : nan;
+        out[((int64_t)(f0 + f) * out_comp + comp0 + t) * n + ii] =
+            st == 0 ? cf[t] * sum[f][t] * scale : nan;
   }
 }
 
@@ -252,28 +259,39 @@ __global__ void __launch_bounds__(THREADS)
 // to grad div V and grad div B, whose entry terms are
 //   d_a div V  <-  sum_b h_ab (V_b,j - V_b,i),   h_ab = w row_(ab) . p_j
 // with the diagonal rows doubled (d^2/dx_a^2 = 2 c_aa / lambda^2).
-template <int G, bool STAB>
+// CT: the arithmetic of the field application.  double; float in the mixed
+// form, where each operator weight gamma_j is formed in FP64 and rounded once
+// (in FP32 its rounding would be amplified by the cancellation inside
+// G . p_j, which grows with the condition of the moment matrix), the field
+// differences are formed in FP64 and rounded once, the sums over neighbors
+// are FP32, and the lanes' partial sums meet in FP64.
+template <int G, bool STAB, class CT = double>
 __global__ void __launch_bounds__(THREADS)
     k_apply_rhs(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
                 double rf_ratio, int wkind, double gamma, Stab sb, const double* __restrict__ gop,
                 const int32_t* __restrict__ status, double* __restrict__ rhs,
                 double* __restrict__ dxdt, double* __restrict__ tape,
-                const int32_t* __restrict__ rows) {
+                const int32_t* __restrict__ rows, const int32_t* __restrict__ list,
+                const int32_t* __restrict__ count) {
   constexpr int NR = STAB ? 9 : 3;  // operator rows
   constexpr int NF = STAB ? 8 : 7;  // fields with a gradient: the last NF of eight
   constexpr int F0 = 8 - NF;
+  constexpr int PPB = THREADS / G;
   const int tid = xcd_block() * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
+  // List form: only the particles list[0 .. *count) (count read on the
+  // device); blocks past the list's end leave before the barrier, together.
+  const int m = count ? *count : n;
+  if (xcd_block() * PPB >= m) return;
+  const bool valid = i < m;
+  const int ii = list ? list[valid ? i : m - 1] : (valid ? i : m - 1);
   const int st = status[ii];
   // The particle's operator rows live in LDS, not in each lane's registers:
   // gsh[k][pl] holds entries 2k, 2k+1, and one 16-byte read serves all lanes
   // of a particle (consecutive particles, consecutive addresses: no bank
   // conflicts).
-  constexpr int PPB = THREADS / G;
   __shared__ double2 gsh[NR * NBASIS / 2][PPB];
   const int pl = threadIdx.x / G;
   // The lane's own data and its first neighbor entry are fetched before the
@@ -302,12 +320,12 @@ __global__ void __launch_bounds__(THREADS)
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
-  double acc[NF][3];
+  CT acc[NF][3];
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) acc[f][t] = 0.0;
-  double gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
+    for (int t = 0; t < 3; ++t) acc[f][t] = CT(0);
+  CT adv[3] = {CT(0), CT(0), CT(0)}, adb[3] = {CT(0), CT(0), CT(0)};
   for (; s < s1; s += G) {
     const double4 gj = gn;
     const int j = jc;
@@ -324,7 +342,7 @@ __global__ void __launch_bounds__(THREADS)
     const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
     double p[NBASIS];
     basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-    double gam[NR];
+    CT gam[NR];
     // re-read the rows from LDS every iteration: hoisted out of the loop they
     // would occupy registers again
     asm volatile("" ::: "memory");
@@ -337,36 +355,37 @@ __global__ void __launch_bounds__(THREADS)
         v = fma(gg.x, p[b], v);
         v = fma(gg.y, p[b + 1], v);
       }
-      gam[t] = w * v;
+      gam[t] = CT(w * v);
     }
-    double df[8];
+    CT df[8];
 #pragma unroll
-    for (int f = F0; f < 8; ++f) df[f] = qj[f] - qi[f];
+    for (int f = F0; f < 8; ++f) df[f] = CT(qj[f] - qi[f]);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int t = 0; t < 3; ++t) acc[f][t] = fma(gam[t], df[F0 + f], acc[f][t]);
     if constexpr (STAB) {
       // rows 3..8 = xx, xy, xz, yy, yz, zz
-      gdv[0] += gam[3] * df[1] + gam[4] * df[2] + gam[5] * df[3];
-      gdv[1] += gam[4] * df[1] + gam[6] * df[2] + gam[7] * df[3];
-      gdv[2] += gam[5] * df[1] + gam[7] * df[2] + gam[8] * df[3];
-      gdb[0] += gam[3] * df[4] + gam[4] * df[5] + gam[5] * df[6];
-      gdb[1] += gam[4] * df[4] + gam[6] * df[5] + gam[7] * df[6];
-      gdb[2] += gam[5] * df[4] + gam[7] * df[5] + gam[8] * df[6];
+      adv[0] += gam[3] * df[1] + gam[4] * df[2] + gam[5] * df[3];
+      adv[1] += gam[4] * df[1] + gam[6] * df[2] + gam[7] * df[3];
+      adv[2] += gam[5] * df[1] + gam[7] * df[2] + gam[8] * df[3];
+      adb[0] += gam[3] * df[4] + gam[4] * df[5] + gam[5] * df[6];
+      adb[1] += gam[4] * df[4] + gam[6] * df[5] + gam[7] * df[6];
+      adb[2] += gam[5] * df[4] + gam[7] * df[5] + gam[8] * df[6];
     }
   }
   double grad[NF][3];
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) grad[f][t] = group_sum<G>(acc[f][t]) * inv_lam;
+    for (int t = 0; t < 3; ++t) grad[f][t] = group_sum<G>(double(acc[f][t])) * inv_lam;
+  double gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
   if constexpr (STAB) {
     const double il2 = inv_lam * inv_lam;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      gdv[a] = group_sum<G>(gdv[a]) * il2;
-      gdb[a] = group_sum<G>(gdb[a]) * il2;
+      gdv[a] = group_sum<G>(double(adv[a])) * il2;
+      gdb[a] = group_sum<G>(double(adb[a])) * il2;
     }
   }
   if (valid && l == 0) {
@@ -388,21 +407,21 @@ __global__ void __launch_bounds__(THREADS)
       for (int f = 0; f < 8; ++f) out[f] = nan;
     }
 #pragma unroll
-    for (int f = 0; f < 8; ++f) rhs[(int64_t)f * n + i] = out[f];
+    for (int f = 0; f < 8; ++f) rhs[(int64_t)f * n + ii] = out[f];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dxdt[(int64_t)a * n + i] = qi[1 + a];
+    for (int a = 0; a < 3; ++a) dxdt[(int64_t)a * n + ii] = qi[1 + a];
     if (tape) {  // what the reverse mode reuses (layout in mls.hpp)
 #pragma unroll
       for (int f = 0; f < 7; ++f)
 #pragma unroll
-        for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + i] = g7[f][t];
-      tape[(int64_t)TAPE_STATUS * n + i] = (double)st;
+        for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + ii] = g7[f][t];
+      tape[(int64_t)TAPE_STATUS * n + ii] = (double)st;
       if constexpr (STAB) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          tape[(int64_t)(TAPE_GRHO + a) * n + i] = grad[0][a];
-          tape[(int64_t)(TAPE_GDV + a) * n + i] = gdv[a];
-          tape[(int64_t)(TAPE_GDB + a) * n + i] = gdb[a];
+          tape[(int64_t)(TAPE_GRHO + a) * n + ii] = grad[0][a];
+          tape[(int64_t)(TAPE_GDV + a) * n + ii] = gdv[a];
+          tape[(int64_t)(TAPE_GDB + a) * n + ii] = gdb[a];
         }
       }
     }
@@ -464,23 +483,23 @@ hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const d
   return hipGetLastError();
 }
 
-template <int G>
+template <int G, class CT>
 static hipError_t derivs_g(hipStream_t s, const EvalArgs& a, const double* gop,
                            const int32_t* status, int nf, const double* fields, double* d1,
-                           double* d2) {
+                           double* d2, const int32_t* list, const int32_t* count) {
   const unsigned grid = grid_for((int64_t)a.n * G, THREADS);
   for (int f0 = 0; f0 < nf; f0 += FCHUNK) {
-    hipLaunchKernelGGL((k_apply_derivs<G>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
+    hipLaunchKernelGGL((k_apply_derivs<G, CT>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
                        a.off, a.idx, a.box, a.rf_ratio, a.wkind, gop, 0, status, nf, f0, fields,
-                       d1, 3, 0, 1.0, 1.0, 1.0, 1);
+                       d1, 3, 0, 1.0, 1.0, 1.0, 1, list, count);
     if (d2) {
       // rows 4..6: xx (2 c), xy, xz ; rows 7..9: yy (2 c), yz, zz (2 c)
-      hipLaunchKernelGGL((k_apply_derivs<G>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
+      hipLaunchKernelGGL((k_apply_derivs<G, CT>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
                          a.off, a.idx, a.box, a.rf_ratio, a.wkind, gop, 3, status, nf, f0, fields,
-                         d2, 6, 0, 2.0, 1.0, 1.0, 2);
-      hipLaunchKernelGGL((k_apply_derivs<G>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
+                         d2, 6, 0, 2.0, 1.0, 1.0, 2, list, count);
+      hipLaunchKernelGGL((k_apply_derivs<G, CT>), dim3(grid), dim3(THREADS), 0, s, a.n, a.pos, a.lam,
                          a.off, a.idx, a.box, a.rf_ratio, a.wkind, gop, 6, status, nf, f0, fields,
-                         d2, 6, 3, 2.0, 1.0, 2.0, 2);
+                         d2, 6, 3, 2.0, 1.0, 2.0, 2, list, count);
     }
   }
   return hipGetLastError();
@@ -488,21 +507,28 @@ static hipError_t derivs_g(hipStream_t s, const EvalArgs& a, const double* gop,
 
 hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,
                                const int32_t* status, int nf, const double* fields, double* d1,
-                               double* d2) {
+                               double* d2, bool fp32, const int32_t* list, const int32_t* count) {
+  if (fp32) {
+    switch (lanes) {
+      case 1: return derivs_g<1, float>(s, a, gop, status, nf, fields, d1, d2, list, count);
+      case 2: return derivs_g<2, float>(s, a, gop, status, nf, fields, d1, d2, list, count);
+      default: return derivs_g<4, float>(s, a, gop, status, nf, fields, d1, d2, list, count);
+    }
+  }
   switch (lanes) {
-    case 1: return derivs_g<1>(s, a, gop, status, nf, fields, d1, d2);
-    case 2: return derivs_g<2>(s, a, gop, status, nf, fields, d1, d2);
-    default: return derivs_g<4>(s, a, gop, status, nf, fields, d1, d2);
+    case 1: return derivs_g<1, double>(s, a, gop, status, nf, fields, d1, d2, list, count);
+    case 2: return derivs_g<2, double>(s, a, gop, status, nf, fields, d1, d2, list, count);
+    default: return derivs_g<4, double>(s, a, gop, status, nf, fields, d1, d2, list, count);
   }
 }
 
-template <int G, bool STAB>
+template <int G, bool STAB, class CT = double>
 static hipError_t rhs_g(hipStream_t s, const EvalArgs& a, double gamma, const Stab& sb,
                         const double* gop, const int32_t* status, double* rhs, double* dxdt,
-                        double* tape) {
-  hipLaunchKernelGGL((k_apply_rhs<G, STAB>), dim3(grid_for((int64_t)a.n * G, THREADS)),
+                        double* tape, const int32_t* list, const int32_t* count) {
+  hipLaunchKernelGGL((k_apply_rhs<G, STAB, CT>), dim3(grid_for((int64_t)a.n * G, THREADS)),
                      dim3(THREADS), 0, s, a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio,
-                     a.wkind, gamma, sb, gop, status, rhs, dxdt, tape, a.rows);
+                     a.wkind, gamma, sb, gop, status, rhs, dxdt, tape, a.rows, list, count);
   return hipGetLastError();
 }
 
@@ -515,14 +541,23 @@ hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* la
 
 hipError_t launch_apply_rhs(hipStream_t s, const EvalArgs& a, int lanes, double gamma,
                             const Stab& sb, const double* gop, const int32_t* status, double* rhs,
-                            double* dxdt, double* tape) {
+                            double* dxdt, double* tape, bool fp32,
+                            const int32_t* list, const int32_t* count) {
   // nine LDS rows per particle: eight lanes per particle keep a block's rows
-  // at 46 KB
-  if (sb.on()) return rhs_g<8, true>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
+  // at 46 KB (FP64)
+  if (fp32) {
+    if (sb.on()) return rhs_g<8, true, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+    switch (lanes) {
+      case 1: return rhs_g<1, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+      case 2: return rhs_g<2, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+      default: return rhs_g<4, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+    }
+  }
+  if (sb.on()) return rhs_g<8, true>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
   switch (lanes) {
-    case 1: return rhs_g<1, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
-    case 2: return rhs_g<2, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
-    default: return rhs_g<4, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape);
+    case 1: return rhs_g<1, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+    case 2: return rhs_g<2, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+    default: return rhs_g<4, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
   }
 }
 

@@ -55,13 +55,18 @@ hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const d
 hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
                                const double* mom, const double* rhs, double* x, int32_t* status,
                                int fit);
+// fp32: the neighbor loop in FP32 (the mixed form).  list, count (device):
+// only the particles list[0 .. *count), outputs at their own indices.
 hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,
                                const int32_t* status, int nf, const double* fields, double* d1,
-                               double* d2);
+                               double* d2, bool fp32 = false, const int32_t* list = nullptr,
+                               const int32_t* count = nullptr);
 // Time derivatives from the operator rows gop: three rows (ideal), nine with
-// the stabilisers on.
+// the stabilisers on.  fp32: the neighbor loop in FP32 (the mixed form).
+// list, count as for launch_apply_derivs (not with a.rows).
 hipError_t launch_apply_rhs(hipStream_t s, const EvalArgs& a, int lanes, double gamma,
                             const Stab& sb, const double* gop, const int32_t* status, double* rhs,
-                            double* dxdt, double* tape);
+                            double* dxdt, double* tape, bool fp32 = false,
+                            const int32_t* list = nullptr, const int32_t* count = nullptr);
 
 }  // namespace phb

@@ -11,3 +11,13 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the C-ABI on cuda:0)")
     config.addinivalue_line("markers", "slow: CPU test that takes more than a few seconds")
+
+
+@pytest.fixture(params=[1, 0], ids=["refine-operator", "refine-data"])
+def mixed_refine(request):
+    """Runs a mixed-form test under both refinement steps (the knob is reset to
+    its default afterwards)."""
+    import paper_1110_0836_amd as P
+    P.phb_tune_set("mixed_refine", request.param)
+    yield request.param
+    P.phb_tune_set("mixed_refine", 1)

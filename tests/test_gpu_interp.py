@@ -27,7 +27,7 @@ def _noisy(c, seed):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_derivatives_match_oracle(precision):
+def test_derivatives_match_oracle(precision, mixed_refine):
     c = _noisy(synth.random_cloud(3001, seed=91, lam_range=(0.06, 0.1)), 92)
     s = setup_of(c, fit=INTERP, precision=precision)
     pos, lam = dev(c["pos"]), dev(c["lam"])
@@ -54,7 +54,7 @@ def test_derivatives_match_oracle(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-def test_rhs_matches_oracle(precision):
+def test_rhs_matches_oracle(precision, mixed_refine):
     for c in (_noisy(synth.cp_alfven(16), 93), _noisy(synth.config2(side=16), 94)):
         s = setup_of(c, fit=INTERP, precision=precision)
         pos, lam = dev(c["pos"]), dev(c["lam"])

@@ -1,8 +1,9 @@
 """Mixed-precision form (FP32 assembly and application of displacement- and
-field-differences formed in FP64, FP64 factor and solves, one data-level
-refinement step) against the FP64 oracle: max relative error per field and
-derivative order at most 1e-5, for derivatives, time derivatives and the
-reverse mode."""
+field-differences formed in FP64, FP64 factor and solves, one refinement step:
+a Newton step on the operator rows, or a data-level step on each field's
+coefficients; every test runs under both) against the FP64 oracle: max
+relative error per field and derivative order at most 1e-5, for derivatives,
+time derivatives and the reverse mode."""
 import numpy as np
 import pytest
 
@@ -12,7 +13,7 @@ from _common import dev, setup_of, rel_err, interior
 from test_gpu_mls import check_rhs, rhs_both
 from test_gpu_adjoint import grad_err, random_set
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("mixed_refine")]
 P = pytest.importorskip("paper_1110_0836_amd")
 
 TOLMIX = 1e-5

@@ -122,7 +122,7 @@ def test_fp64_shear_layer_full_size_sampled():
 
 
 @pytest.mark.parametrize("name", ["cp_alfven", "steep"])
-def test_mixed_matches_oracle(name):
+def test_mixed_matches_oracle(name, mixed_refine):
     c = synth.cp_alfven(16) if name == "cp_alfven" else _steep_cloud()
     e = check(c, 1e-5, precision=P.PHB_MIXED)
     print(name, "mixed", e)
