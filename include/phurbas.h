@@ -68,7 +68,7 @@ extern "C" {
                              one Newton step on the operator rows with an FP64
                              residual product); particles whose FP32 moment
                              matrix is too ill-conditioned for one step are
-                             evaluated in FP64 (see mixed_cond_exp); the
+                             evaluated in FP64 (see mixed_cond_x10); the
                              reverse mode assembles its moments in FP64 */
 #define PHB_W_POLY3 0     /* w = (1 - d^2/r_f^2)^3 */
 #define PHB_W_UNIT 1      /* w = 1 */
@@ -354,17 +354,22 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * transposed row in the reverse mode), "adj_pairs_mode" (0: one lane per
  * neighbor entry, 1: one wavefront per owner particle), "record_order" (0:
  * pair records written at their transposed position, 1: written in forward
- * order and gathered through the inverse map), "mixed_cond_exp" (0..12,
- * default 2: in the mixed form a particle whose FP32-assembled moment matrix,
- * scaled to unit diagonal, has an estimated ||A^{-1}||_2 above 10^exp is
- * evaluated in FP64 instead; this knob moves results within the mixed
- * tolerance, the others only by rounding), "mixed_refine" (mixed form's
- * refinement step; 1, the default: the rows G~ = E A~^{-1} of the inverse of
- * the FP32-assembled matrix are refined once, G^ = 2 G~ - (G~ A) A~^{-1}, with
- * the product G~ A formed in FP64 over the neighbors, and G^ is applied to
- * the fields in FP32; 0: each field's coefficients are solved for and refined
- * once from their residuals at the neighbors, all sums in FP32 (corrected
- * seminormal equations); the two agree within the mixed tolerance).  EINVAL
+ * order and gathered through the inverse map), "mixed_cond_x10" (-1..120:
+ * in the mixed form a particle whose FP32-assembled moment matrix, scaled to
+ * unit diagonal, has an estimated ||A^{-1}||_2 above 10^(value / 10) is
+ * evaluated in FP64 instead; -1, the default, takes the refinement form's own
+ * threshold, 10^2.5 for the operator-level step and 10^2 for the data-level
+ * step; this knob moves results within the mixed tolerance, the others only
+ * by rounding), "mixed_refine"
+ * (mixed form's refinement step; 1: the rows G~ = E A~^{-1} of the inverse of
+ * the FP32-assembled matrix are refined once, G^ = 2 G~ - (G~ A) A~^{-1},
+ * with the product G~ A formed in FP64 over the neighbors, and G^ is applied
+ * to the fields in FP32 (each operator weight formed in FP64, the sums in
+ * FP32); 0: each field's coefficients are solved for and refined once from
+ * their residuals at the neighbors, all sums in FP32 (corrected seminormal
+ * equations); 2, the default: 1 for the three gradient rows (the ideal
+ * right-hand side, first derivatives), 0 with nine rows (the stabilisers,
+ * second derivatives); the forms agree within the mixed tolerance).  EINVAL
  * for an unknown key or value. */
 int phb_tune_set(phb_ctx* ctx, const char* key, int value);
 int phb_tune_get(phb_ctx* ctx, const char* key, int* value);

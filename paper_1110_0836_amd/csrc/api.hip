@@ -409,7 +409,7 @@ static int* tune_slot(phb_ctx* ctx, const char* key) {
   if (!strcmp(key, "lanes_apply")) return &ctx->lanes_apply;
   if (!strcmp(key, "lanes_adj_y")) return &ctx->lanes_adj_y;
   if (!strcmp(key, "lanes_gather")) return &ctx->lanes_gather;
-  if (!strcmp(key, "mixed_cond_exp")) return &ctx->mixed_cond_exp;
+  if (!strcmp(key, "mixed_cond_x10")) return &ctx->mixed_cond_x10;
   if (!strcmp(key, "mixed_refine")) return &ctx->mixed_refine;
   if (!strcmp(key, "adj_pairs_mode")) return &ctx->adj_pairs_mode;
   if (!strcmp(key, "record_order")) return &ctx->record_order;
@@ -421,10 +421,11 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
   int* slot = tune_slot(ctx, key);
   if (!slot) return set_error(ctx, PHB_EINVAL, std::string("unknown tuning key ") + key);
   const bool lanes = strncmp(key, "lanes_", 6) == 0;
-  const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order") ||
-                    !strcmp(key, "mixed_refine");
-  const bool cut = !strcmp(key, "mixed_cond_exp");
-  if (cut ? !(value >= 0 && value <= 12)
+  const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order");
+  const bool cut = !strcmp(key, "mixed_cond_x10");
+  const bool refine = !strcmp(key, "mixed_refine");
+  if (cut ? !(value >= -1 && value <= 120)
+          : refine ? !(value >= 0 && value <= 2)
           : lanes ? !(value == 1 || value == 2 || value == 4)
                   : (mode ? !(value == 0 || value == 1) : !(value >= 1 && value <= 4)))
     return set_error(ctx, PHB_EINVAL, std::string("bad value for ") + key);

@@ -143,36 +143,30 @@ __global__ void __launch_bounds__(THREADS)
 // list_out; its outputs are left to the list form.  (The refinement step
 // contracts the error by about kappa * eps_32 * sqrt(n); the equilibrated
 // matrix has unit diagonal, so kappa <= 20 ||A_hat^{-1}||.)  List form: the
-// particles list_in[0 .. *count) (FP64 moments by then), a grid-stride loop
-// over quads.
-template <int NG>
-__global__ void __launch_bounds__(THREADS)
-    k_mixed_factor(int n, const double* __restrict__ mom, const int64_t* __restrict__ off, int nf,
-                   const double* __restrict__ bin, double* __restrict__ cfit,
-                   double* __restrict__ gt, int32_t* __restrict__ status,
-                   int32_t* __restrict__ flag, double ncut, const int32_t* __restrict__ list_in,
-                   int32_t* __restrict__ list_out, int32_t* __restrict__ count, int interp) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
-  const int l = tid & 3;
-  const int quad = tid >> 2;
-  const bool listed = list_in != nullptr;
-  const int total = listed ? *count : n;
-  const int stride = listed ? (int)(gridDim.x * (THREADS / 4)) : total;
-  for (int k = quad; k < total; k += stride) {
-    const int i = listed ? list_in[k] : k;
-    QuadChol c;
-    quad_chol_factor(c, c_mtab, mom, n, i, l, interp != 0);
-    const int nnb = (int)(off[i + 1] - off[i]);
-    const int st = quad_chol_status(c, nnb);
-    if (!listed) {
-      const bool bad = nnb >= NBASIS && (st != 0 || !(quad_chol_inv_norm_est(c, l) <= ncut));
-      if (l == 0) flag[i] = bad ? 1 : 0;
-      if (bad) {
-        if (l == 0) list_out[atomicAdd(count, 1)] = i;
-        continue;
-      }
+// particles list_in[0 .. *count) (FP64 moments by then).
+template <int NG, bool SOLVE, bool LISTED>
+__device__ __forceinline__ void mixed_factor_one(int n, int i, int l, const double* __restrict__ mom,
+                                                 const int64_t* __restrict__ off, int nf,
+                                                 const double* __restrict__ bin,
+                                                 double* __restrict__ cfit, double* __restrict__ gt,
+                                                 int32_t* __restrict__ status,
+                                                 int32_t* __restrict__ flag, double ncut,
+                                                 int32_t* __restrict__ list_out,
+                                                 int32_t* __restrict__ count, int interp) {
+  QuadChol c;
+  quad_chol_factor(c, c_mtab, mom, n, i, l, interp != 0);
+  const int nnb = (int)(off[i + 1] - off[i]);
+  const int st = quad_chol_status(c, nnb);
+  if constexpr (!LISTED) {
+    const bool bad = nnb >= NBASIS && (st != 0 || !(quad_chol_inv_norm_est(c, l) <= ncut));
+    if (l == 0) flag[i] = bad ? 1 : 0;
+    if (bad) {
+      if (l == 0) list_out[atomicAdd(count, 1)] = i;
+      return;
     }
-    if (l == 0) status[i] = st;
+  }
+  if (l == 0) status[i] = st;
+  if constexpr (SOLVE) {
     for (int f = 0; f < nf; ++f) {
       double b[5], x[5];
       sfor<0, 5>([&](auto R) {
@@ -186,15 +180,41 @@ __global__ void __launch_bounds__(THREADS)
         cfit[((int64_t)f * NBASIS + 4 * rho + l) * n + i] = st == 0 ? x[rho] : 0.0;
       });
     }
-    sfor<0, NG>([&](auto TI) {
-      constexpr int t = 1 + TI;
-      double row[5];
-      quad_chol_inverse_row<t>(c, l, row);
-      sfor<0, 5>([&](auto R) {
-        constexpr int rho = R;
-        gt[((int64_t)TI * NBASIS + 4 * rho + l) * n + i] = st == 0 ? row[rho] : 0.0;
-      });
+  }
+  sfor<0, NG>([&](auto TI) {
+    constexpr int t = 1 + TI;
+    double row[5];
+    quad_chol_inverse_row<t>(c, l, row);
+    sfor<0, 5>([&](auto R) {
+      constexpr int rho = R;
+      gt[((int64_t)TI * NBASIS + 4 * rho + l) * n + i] = st == 0 ? row[rho] : 0.0;
     });
+  });
+}
+
+// LISTED false: the screening form; LISTED true: the listed particles, quad
+// k taking list_in[k] for k < *count (the launch covers n quads; a loop
+// instead would double the register footprint).  SOLVE false compiles the
+// field solves out (nf must then be 0: the operator-level refinement needs
+// only G~).
+template <int NG, bool SOLVE, bool LISTED>
+__global__ void __launch_bounds__(THREADS)
+    k_mixed_factor(int n, const double* __restrict__ mom, const int64_t* __restrict__ off, int nf,
+                   const double* __restrict__ bin, double* __restrict__ cfit,
+                   double* __restrict__ gt, int32_t* __restrict__ status,
+                   int32_t* __restrict__ flag, double ncut, const int32_t* __restrict__ list_in,
+                   int32_t* __restrict__ list_out, int32_t* __restrict__ count, int interp) {
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int l = tid & 3;
+  const int quad = tid >> 2;
+  if constexpr (!LISTED) {
+    if (quad >= n) return;  // whole quads leave together
+    mixed_factor_one<NG, SOLVE, false>(n, quad, l, mom, off, nf, bin, cfit, gt, status, flag, ncut,
+                                       list_out, count, interp);
+  } else {
+    if (quad >= *count) return;
+    mixed_factor_one<NG, SOLVE, true>(n, list_in[quad], l, mom, off, nf, bin, cfit, gt, status,
+                                      flag, ncut, list_out, count, interp);
   }
 }
 
@@ -598,6 +618,15 @@ __global__ void k_zero_i32(int32_t* p, int m) {
   if (k < m) p[k] = 0;
 }
 
+// Screen threshold on the estimated ||A_hat^{-1}||: 10^(x10 / 10), x10 from
+// the context or, when unset (-1), the form's own: one Newton step on the
+// operator rows leaves an error quadratic in kappa eps_32 and tolerates
+// 10^2.5; the data-level step 10^2.
+double screen_cut(const phb_ctx* ctx, int x10_default) {
+  const int x10 = ctx->mixed_cond_x10 >= 0 ? ctx->mixed_cond_x10 : x10_default;
+  return pow(10.0, 0.1 * x10);
+}
+
 struct MixedBufs {
   double* mom;
   double* b;
@@ -642,7 +671,7 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
               const MixedBufs& m, int32_t* status) {
   hipStream_t s = ctx->stream;
   const int n = a.n;
-  const double ncut = pow(10.0, (double)ctx->mixed_cond_exp);
+  const double ncut = screen_cut(ctx, 20);
   const int interp = a.fit == PHB_FIT_INTERP19;
   const unsigned gq = grid_for((int64_t)n * 4, THREADS);
   int rc;
@@ -655,13 +684,13 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed B"))) return rc; }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
   { Prof pf(ctx, "k_mixed_factor");
-    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, nf,
+    hipLaunchKernelGGL((k_mixed_factor<NG, true, false>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, nf,
                        m.b, m.cfit, m.gt, status, m.flag, ncut, nullptr, m.list, m.count, interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed factor"))) return rc; }
   { Prof pf(ctx, "k_mixed_repair");
     hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, a.geo, a.off,
                        a.idx, a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.list, m.count, m.mom, m.b);
-    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, m.mom,
+    hipLaunchKernelGGL((k_mixed_factor<NG, true, true>), dim3(gq), dim3(THREADS), 0, s, n, m.mom,
                        a.off, nf, m.b, m.cfit, m.gt, status, m.flag, ncut, m.list, nullptr,
                        m.count, interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed repair"))) return rc; }
@@ -710,7 +739,7 @@ template <int NG>
 int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* status) {
   hipStream_t s = ctx->stream;
   const int n = a.n;
-  const double ncut = pow(10.0, (double)ctx->mixed_cond_exp);
+  const double ncut = screen_cut(ctx, 25);
   const int interp = a.fit == PHB_FIT_INTERP19;
   const unsigned gq = grid_for((int64_t)n * 4, THREADS);
   int rc;
@@ -719,7 +748,7 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
       return rc; }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
   { Prof pf(ctx, "k_mixed_factor");
-    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, 0,
+    hipLaunchKernelGGL((k_mixed_factor<NG, false, false>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, 0,
                        nullptr, nullptr, m.gt, status, m.flag, ncut, nullptr, m.list, m.count,
                        interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed factor"))) return rc; }
@@ -727,7 +756,7 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
     hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, a.geo, a.off,
                        a.idx, a.box, a.rf_ratio, a.wkind, nullptr, 0, 0, m.list, m.count, m.mom,
                        nullptr);
-    hipLaunchKernelGGL((k_mixed_factor<NG>), dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, m.mom,
+    hipLaunchKernelGGL((k_mixed_factor<NG, false, true>), dim3(gq), dim3(THREADS), 0, s, n, m.mom,
                        a.off, 0, nullptr, nullptr, m.gt, status, m.flag, ncut, m.list, nullptr,
                        m.count, interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed repair"))) return rc; }
@@ -797,7 +826,11 @@ static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const St
 
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, const double* q,
               double* rhs, double* dxdt, int32_t* status, double* tape) {
-  if (ctx->mixed_refine == 1) return mixed_rhs_op(ctx, a0, gamma, sb, q, rhs, dxdt, status, tape);
+  // by shape (2): the operator-level step for the three gradient rows; with
+  // the stabilisers' nine rows it needs three residual-product passes, and
+  // the data-level step's two passes over the eight fields cost less
+  const int form = ctx->mixed_refine == 2 ? (sb.on() ? 0 : 1) : ctx->mixed_refine;
+  if (form == 1) return mixed_rhs_op(ctx, a0, gamma, sb, q, rhs, dxdt, status, tape);
   const int n = a0.n;
   const bool stab = sb.on();
   // ideal: V, B, sigma (records 1..7), three rows; stabilised: all eight
@@ -877,7 +910,8 @@ static int mixed_derivs_op(phb_ctx* ctx, const EvalArgs& a0, int nf, const doubl
 
 int mixed_derivs(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields, double* d1,
                  double* d2, int32_t* status) {
-  if (ctx->mixed_refine == 1) return mixed_derivs_op(ctx, a0, nf, fields, d1, d2, status);
+  const int form = ctx->mixed_refine == 2 ? (d2 ? 0 : 1) : ctx->mixed_refine;
+  if (form == 1) return mixed_derivs_op(ctx, a0, nf, fields, d1, d2, status);
   const int n = a0.n;
   const int ng = d2 ? 9 : 3;
   Workspace ws(ctx);

@@ -18,6 +18,7 @@ def mixed_refine(request):
     """Runs a mixed-form test under both refinement steps (the knob is reset to
     its default afterwards)."""
     import paper_1110_0836_amd as P
+    saved = P.phb_tune_get("mixed_refine")
     P.phb_tune_set("mixed_refine", request.param)
     yield request.param
-    P.phb_tune_set("mixed_refine", 1)
+    P.phb_tune_set("mixed_refine", saved)
