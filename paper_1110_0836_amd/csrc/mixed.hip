@@ -747,7 +747,7 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
     if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, m.mom, true), "moments")))
       return rc; }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
-  { Prof pf(ctx, "k_mixed_factor");
+  { Prof pf(ctx, "k_mixed_screen");
     hipLaunchKernelGGL((k_mixed_factor<NG, false, false>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, a.off, 0,
                        nullptr, nullptr, m.gt, status, m.flag, ncut, nullptr, m.list, m.count,
                        interp);

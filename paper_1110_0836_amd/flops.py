@@ -41,6 +41,18 @@ k_mixed_resid    per pair: geometry (15), basis (16), per field the FP32
                  fit (40), residual (3) and dB update (40), seven fields  = 612
                  per particle: E C + G dB (7 x 3 x 20 FMA + 21)           = 861
 k_mixed_rhs_finish per particle: gradient scaling (21) + right-hand side  = 66
+
+Operator-level refinement (the mixed form's default for three rows):
+k_mixed_screen   per particle: equilibration + Cholesky (3330), three
+                 unit-vector solves (2234), inverse-norm estimate (1720),
+                 output scaling (120)                                     = 7404
+k_mixed_gta      per pair and pass of three rows: geometry and weight (15),
+                 basis (16), G~ p (60 FMA), w G~ p (3), M update (60 FMA) = 274
+k_mixed_refine   per particle and three rows: equilibration + Cholesky
+                 (3330), scaling in (60), three general solves (2460),
+                 2 G~ - S x (60 mul, 60 FMA)                              = 6030
+k_apply_rhs<fp32> as k_apply_rhs (FP64 operator weights, FP32 sums)       = 203
+                 per particle                                             = 66
 """
 
 PER_PAIR = {
@@ -49,6 +61,8 @@ PER_PAIR = {
     "k_mixed_b": 325,
     "k_mixed_resid": 612,
     "k_apply_rhs": 203,
+    "k_apply_rhs<fp32>": 203,
+    "k_mixed_gta": 274,
     "k_adj_y": 203,
     "k_adj_pairs": 683,
     "k_adj_pairs_w": 683,
@@ -59,6 +73,9 @@ PER_PARTICLE = {
     "k_mixed_resid": 861,
     "k_mixed_rhs_finish": 66,
     "k_apply_rhs": 66,
+    "k_apply_rhs<fp32>": 66,
+    "k_mixed_screen": 7404,
+    "k_mixed_refine": 6030,
     "k_adj_y": 150,
     "k_adj_factor": 8264,
 }

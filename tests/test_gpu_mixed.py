@@ -196,3 +196,20 @@ def test_adjoint_shear_layer_full_size_matches_fp64():
     eq, ep = grad_err(out[1][0], out[0][0]), grad_err(out[1][1], out[0][1])
     print(f"1M shear layer, mixed vs FP64 reverse mode: q_bar {eq:.2e}, pos_bar {ep:.2e}")
     assert eq < TOLMIX and ep < TOLMIX
+
+
+def test_refinement_knobs():
+    """Defaults and limits of the screen threshold and the refinement form;
+    a threshold so high that nothing is screened still holds the bar on a
+    well-conditioned set."""
+    assert P.phb_tune_get("mixed_cond_x10") == -1
+    assert P.phb_tune_get("mixed_refine") in (0, 1, 2)
+    for key, bad in (("mixed_cond_x10", -2), ("mixed_cond_x10", 121), ("mixed_refine", 3),
+                     ("mixed_refine", -1)):
+        with pytest.raises(P.PhurbasError):
+            P.phb_tune_set(key, bad)
+    P.phb_tune_set("mixed_cond_x10", 120)
+    try:
+        check_rhs(*rhs_both(synth.config2(side=16), precision=P.PHB_MIXED), TOLMIX)
+    finally:
+        P.phb_tune_set("mixed_cond_x10", -1)
