@@ -736,9 +736,9 @@ __global__ void __launch_bounds__(THREADS)
   __shared__ CT osh[THREADS / 64][OR];
   const int wv = threadIdx.x >> 6;
   // Each lane's first entry (index, neighbor geometry, transposed position)
-  // is fetched before the barrier, so that this dependent chain of loads
-  // overlaps the staging of the owner record; later entries are fetched one
-  // iteration ahead.
+  // is fetched before the record is staged, so that this dependent chain of
+  // loads overlaps the staging; later entries are fetched one iteration
+  // ahead.
   int64_t rs = 0, re = 0;
   double4 gi = make_double4(0.0, 0.0, 0.0, 1.0), gjn = gi;
   int jn = 0, tpn = 0;
@@ -753,8 +753,9 @@ __global__ void __launch_bounds__(THREADS)
     }
     for (int k = lane; k < OR; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OR + k]);
   }
-  __syncthreads();
   if (i >= n) return;  // whole wavefronts leave together
+  // each wavefront reads only its own record: no block barrier
+  wave_lds_sync();
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);

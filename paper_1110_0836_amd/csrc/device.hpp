@@ -268,6 +268,16 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Makes a wavefront's LDS writes visible to its own later LDS reads from any
+// of its lanes (the lanes run in lockstep: the writes only have to complete
+// and stay ordered before the reads).  Wavefronts of the same block are not
+// waited for.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int O>
 __device__ __forceinline__ double quad_bcast(double v) {
   return dpp_f64<qp_bcast<O>()>(v);
