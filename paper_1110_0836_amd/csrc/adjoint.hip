@@ -701,19 +701,10 @@ __global__ void __launch_bounds__(THREADS)
 }
 
 // ---- 4b. pair contributions, one wavefront per owner ------------------------
-// The owner's G, K and Ubar are wavefront-uniform (scalar loads into SGPRs);
-// lanes take the owner's neighbor entries 64 at a time; the owner's own share
-// is one wavefront reduction at the end.  Rows longer than 64 entries loop.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += quad_xor1(v);
-  v += quad_xor2(v);
-  v += dpp_f64<0x124>(v);  // row_ror:4
-  v += dpp_f64<0x128>(v);  // row_ror:8
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
-}
-
+// The owner's G, K and Ubar are wavefront-uniform and staged in LDS; lanes
+// take the owner's neighbor entries 64 at a time (rows longer than 64
+// entries loop); the owner's own share is one transposed wavefront sum of the
+// record's components at the end.
 
 // RT: type of the pair records (double; float in the mixed form, where the
 // records are an application-level quantity and halve the record traffic).
@@ -798,14 +789,10 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] += v[c];
   }
-#pragma unroll
-  for (int c = 0; c < RC; ++c) acc[c] = wave_sum(acc[c]);
-  if (lane < RC) {
-    double mine = acc[0];
-#pragma unroll
-    for (int c = 1; c < RC; ++c) mine = lane == c ? acc[c] : mine;
-    own[(int64_t)lane * n + i] = -mine;
-  }
+  double tot;
+  int comp;
+  wave_sum_transposed<RC>(acc, tot, comp);
+  if (comp >= 0) own[(int64_t)comp * n + i] = -tot;
 }
 
 // Inverse of t_pos: for transposed entry k, the forward entry it came from.

@@ -278,6 +278,73 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane-half exchanges of gfx950 on a double, one 32-bit half at a time.
+// swap32: lanes 32..63 of a trade places with lanes 0..31 of b.  swap16: in
+// each half of the wavefront, lanes 16..31 of a trade places with lanes 0..15
+// of b.
+__device__ __forceinline__ void swap32(double& a, double& b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap16(double& a, double& b) {
+  const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
+// Sums over the 64 lanes of a wavefront of N = 10 or 12 values per lane,
+// transposed on the way so that the additions are shared: a lane-half swap
+// pairs values 2k and 2k + 1 (one half of the wavefront then holds partial
+// sums of each), a row swap pairs two such registers (each 16-lane row then
+// holds one value's partial sums), and three 16-lane row sums finish.  About
+// a third of the instructions of N separate wavefront sums.  On return lane
+// l holds the total of value comp (comp < 0: none); every value is on
+// exactly one lane.
+template <int N>
+__device__ __forceinline__ void wave_sum_transposed(const double (&v)[N], double& out, int& comp) {
+  static_assert(N == 10 || N == 12, "ten or twelve values");
+  constexpr int NC = N / 2;
+  double c[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double x = v[2 * k], y = v[2 * k + 1];
+    swap32(x, y);
+    c[k] = x + y;  // half 0: value 2k, half 1: value 2k + 1
+  }
+  double e[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double x = c[2 * k < NC ? 2 * k : NC - 1];
+    double y = 2 * k + 1 < NC ? c[2 * k + 1] : x;  // N = 10: c[4] pairs with itself
+    swap16(x, y);
+    e[k] = x + y;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double t = e[k];
+    t += quad_xor1(t);
+    t += quad_xor2(t);
+    t += dpp_f64<0x124>(t);  // row_ror:4
+    t += dpp_f64<0x128>(t);  // row_ror:8
+    e[k] = t;
+  }
+  const int lane = __lane_id();
+  const int q = lane >> 4, p = lane & 15;
+  // rows of e[k] for a pair: values 4k, 4k + 2, 4k + 1, 4k + 3
+  const int perm = (q == 0) ? 0 : (q == 1) ? 2 : (q == 2) ? 1 : 3;
+  out = p == 0 ? e[0] : (p == 1 ? e[1] : e[2]);
+  comp = -1;
+  if (p < 2 || (p == 2 && N == 12)) comp = 4 * p + perm;
+  else if (p == 2 && (q & 1) == 0) comp = 8 + (q >> 1);
+}
+
 template <int O>
 __device__ __forceinline__ double quad_bcast(double v) {
   return dpp_f64<qp_bcast<O>()>(v);
