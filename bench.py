@@ -84,6 +84,15 @@ def time_gpu(fn, reps, torch):
     return out[len(out) // 2]
 
 
+# the kernels of one forward evaluation, per form (the rest of a step is the
+# reverse mode)
+FORWARD_KERNELS = {
+    "fp64": ("k_pack", "k_moments", "k_factor<3>", "k_apply_rhs"),
+    "mixed": ("k_pack", "k_moments<fp32>", "k_mixed_screen", "k_mixed_repair", "k_mixed_gta",
+              "k_mixed_refine", "k_apply_rhs<fp32>", "k_apply_rhs<list>"),
+}
+
+
 def source_digest():
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1110_0836_amd", "csrc", "*"))):
@@ -335,6 +344,24 @@ def main():
             r["kernels"] = kern
             log(f"[{form}] kernels: " + ", ".join(f"{k} {v['avg_ms']:.3f}"
                                                  for k, v in kern.items()))
+            # whole-path roofline: the counted kernels' algorithmic flops per
+            # step over the whole step time (packing, gathers and the FP64
+            # list passes add time and no flops)
+            fwd_names = FORWARD_KERNELS[form]
+            fl_all = sum(F.flops(k, n, nnz) * v["launches"] / reps for k, v in kern.items())
+            fl_fwd = sum(F.flops(k, n, nnz) * v["launches"] / reps for k, v in kern.items()
+                         if k in fwd_names)
+            peak = F.PEAK_FP64_VALU / 1e12
+            r["path_roofline"] = {
+                "bound": "alu", "peak": peak, "unit": "TFLOP/s",
+                "fwd_bwd": {"gflop_per_step": fl_all / 1e9,
+                            "achieved": fl_all / (ms_step / 1e3) / 1e12,
+                            "frac": fl_all / (ms_step / 1e3) / 1e12 / peak},
+                "forward": {"gflop_per_step": fl_fwd / 1e9,
+                            "achieved": fl_fwd / (fwd_ms / 1e3) / 1e12,
+                            "frac": fl_fwd / (fwd_ms / 1e3) / 1e12 / peak}}
+            log(f"[{form}] whole path: fwd+bwd {100 * r['path_roofline']['fwd_bwd']['frac']:.1f} %, "
+                f"forward {100 * r['path_roofline']['forward']['frac']:.1f} % of FP64 VALU peak")
         results[form] = r
 
     # the same forward evaluation with the non-ideal stabilisers (bulk
