@@ -124,21 +124,42 @@ __device__ __forceinline__ void for_each_neighbor(double xi, double yi, double z
                                                   const int32_t* __restrict__ cell_start,
                                                   const int32_t* __restrict__ sorted_id,
                                                   const double4* __restrict__ spos, F&& f) {
-  const Range rx = axis_range(xi, r, g.margin, g.inv_h[0], g.nc[0], box.periodic[0]);
   const Range ry = axis_range(yi, r, g.margin, g.inv_h[1], g.nc[1], box.periodic[1]);
   const Range rz = axis_range(zi, r, g.margin, g.inv_h[2], g.nc[2], box.periodic[2]);
-  // x runs: at most two contiguous pieces after wrapping
-  int xa0, xb0, xa1 = 0, xb1 = -1;
-  if (rx.lo < 0) {
-    xa0 = rx.lo + g.nc[0]; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi;
-  } else if (rx.hi >= g.nc[0]) {
-    xa0 = rx.lo; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi - g.nc[0];
-  } else {
-    xa0 = rx.lo; xb0 = rx.hi;
-  }
+  // Rows of cells (fixed y and z) are culled to the sphere: a neighbor in a
+  // row is at least the row's distance (dy_min, dz_min) away in y and z, so
+  // |dx|^2 < r^2 - dy_min^2 - dz_min^2.  Rows where that bound is empty are
+  // skipped, the others scan only the cells under the chord.  The bound uses
+  // r + margin, which covers the rounding of the cell binning and of the
+  // distance test; the lists are those of the full box.
+  // A periodic axis whose range was clipped to the whole axis has lost the
+  // image each cell index stood for: it is not culled.
+  const double hy = 1.0 / g.inv_h[1], hz = 1.0 / g.inv_h[2];
+  const bool cull_y = !(box.periodic[1] && ry.lo == 0 && ry.hi == g.nc[1] - 1);
+  const bool cull_z = !(box.periodic[2] && rz.lo == 0 && rz.hi == g.nc[2] - 1);
+  const double rc = r + g.margin;
+  const double rc2 = rc * rc;
   for (int cz = rz.lo; cz <= rz.hi; ++cz) {
+    const double z0 = cz * hz;
+    const double dzm = cull_z ? fmax(0.0, fmax(z0 - zi, zi - (z0 + hz))) : 0.0;
+    const double remz = rc2 - dzm * dzm;
+    if (!(remz > 0.0)) continue;
     const int wz = wrap_cell(cz, g.nc[2]);
     for (int cy = ry.lo; cy <= ry.hi; ++cy) {
+      const double y0 = cy * hy;
+      const double dym = cull_y ? fmax(0.0, fmax(y0 - yi, yi - (y0 + hy))) : 0.0;
+      const double rem = remz - dym * dym;
+      if (!(rem > 0.0)) continue;
+      const Range rx = axis_range(xi, sqrt(rem), g.margin, g.inv_h[0], g.nc[0], box.periodic[0]);
+      // x runs: at most two contiguous pieces after wrapping
+      int xa0, xb0, xa1 = 0, xb1 = -1;
+      if (rx.lo < 0) {
+        xa0 = rx.lo + g.nc[0]; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi;
+      } else if (rx.hi >= g.nc[0]) {
+        xa0 = rx.lo; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi - g.nc[0];
+      } else {
+        xa0 = rx.lo; xb0 = rx.hi;
+      }
       const int wy = wrap_cell(cy, g.nc[1]);
       const int row = g.nc[0] * (wy + g.nc[1] * wz);
       for (int piece = 0; piece < 2; ++piece) {

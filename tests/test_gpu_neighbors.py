@@ -57,6 +57,16 @@ def test_ragged_random_sets(n, periodic):
     assert_same(c)
 
 
+@pytest.mark.parametrize("periodic", [(1, 1, 1), (0, 1, 0), (1, 0, 1)])
+def test_wide_spheres_in_few_cells(periodic):
+    """Radii close to half the box: few cells per axis, and periodic ranges that
+    wrap past either end or cover a whole axis (where the search visits every
+    cell row of that axis, since a row index no longer names one image)."""
+    c = synth.random_cloud(900, seed=31, box=(1.0, 0.8, 1.1), lam_range=(0.1, 0.17),
+                           periodic=periodic)
+    assert_same(c)
+
+
 def test_long_rows_use_the_fallback_sort():
     # ~1500 neighbors per particle: rows longer than the LDS sort buffer
     c = synth.random_cloud(3000, seed=7, lam_range=(0.2, 0.21))
