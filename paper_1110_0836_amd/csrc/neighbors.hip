@@ -291,13 +291,18 @@ __global__ void __launch_bounds__(NB_THREADS)
   if (s < nnz) atomicAdd(&tcount[idx[s]], 1);
 }
 
+// k_t_fill and k_t_pos: TL lanes share a row, so that its entries are read
+// coalesced and the rows' lengths even out over the lanes.
+constexpr int TL = 16;
+
 __global__ void __launch_bounds__(NB_THREADS)
     k_t_fill(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
              const int64_t* __restrict__ toff, int32_t* __restrict__ cursor,
              int32_t* __restrict__ tmp) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / TL);
   if (i >= n) return;
-  for (int64_t s = off[i]; s < off[i + 1]; ++s) {
+  for (int64_t s = off[i] + t % TL; s < off[i + 1]; s += TL) {
     const int j = idx[s];
     const int p = atomicAdd(&cursor[j], 1);
     tmp[toff[j] + p] = i;
@@ -308,9 +313,10 @@ __global__ void __launch_bounds__(NB_THREADS)
     k_t_pos(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
             const int64_t* __restrict__ toff, const int32_t* __restrict__ tsrc,
             int32_t* __restrict__ tpos) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(t / TL);
   if (i >= n) return;
-  for (int64_t s = off[i]; s < off[i + 1]; ++s) {
+  for (int64_t s = off[i] + t % TL; s < off[i + 1]; s += TL) {
     const int j = idx[s];
     int64_t lo = toff[j], hi = toff[j + 1] - 1;
     while (lo < hi) {  // first position with tsrc >= i (i is present)
@@ -466,12 +472,12 @@ hipError_t launch_transpose(hipStream_t s, int n, int64_t nnz, const int64_t* of
   if (e != hipSuccess) return e;
   e = fill_i32(s, count, 0, n);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_t_fill, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, off, idx,
-                     toff, count, tmp);
+  hipLaunchKernelGGL(k_t_fill, dim3(grid_for((int64_t)n * TL, NB_THREADS)), dim3(NB_THREADS), 0, s,
+                     n, off, idx, toff, count, tmp);
   e = launch_row_sort(s, n, toff, tmp, tsrc);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_t_pos, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, off, idx,
-                     toff, tsrc, tpos);
+  hipLaunchKernelGGL(k_t_pos, dim3(grid_for((int64_t)n * TL, NB_THREADS)), dim3(NB_THREADS), 0, s,
+                     n, off, idx, toff, tsrc, tpos);
   return hipGetLastError();
 }
 
