@@ -480,11 +480,11 @@ static int neighbors_build_impl(phb_ctx* ctx, const phb_params* p, int64_t n64,
   double lmin, lmax;
   if ((rc = validate_inputs(ctx, p, n, pos, lambda, part, &lmin, &lmax))) return rc;
   const Grid g = make_grid(p, p->rf_ratio * lmin, ctx->cells_per_rf, max_cells, 1024);
-  Prof pf_sort(ctx, "neighbors_cell_sort");
+  { Prof pf_sort(ctx, "neighbors_cell_sort");
   if ((rc = hip_check(ctx, launch_cell_sort(ctx->stream, n, pos, lambda, g, key, ccount, cstart,
                                             cscan, sid, spos),
                       "cell sort")))
-    return rc;
+    return rc; }
   if (m == 0) {  // no rows: an empty list
     *nnz_out = 0;
     // int64 zero is the bit pattern of 0.0
