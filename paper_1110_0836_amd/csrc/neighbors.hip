@@ -242,14 +242,94 @@ __global__ void __launch_bounds__(NB_THREADS)
 // LDS, longer rows by rank counting straight from global memory.
 constexpr int ROW_LDS = 1024;
 
+// Rows of up to SHORT_ROW entries, one wavefront each, sorted in registers:
+// entry k of the row, padded to m = 2^p slots, sits on lane k % 64 in
+// register k / 64, and a bitonic network exchanges partners across lanes
+// with shuffles and across registers within a lane (distances 64 and 128).
+// Entries are distinct, so the sort is a permutation.
+constexpr int SHORT_ROW = 256;
+
+__device__ __forceinline__ int32_t bitonic_keep(int32_t v, int32_t w, int i, int j, int k) {
+  const bool lower = (i & j) == 0, up = (i & k) == 0;
+  return (lower == up) ? min(v, w) : max(v, w);
+}
+
+// compare-exchange of registers a (lower index i) and b (index i + j >= 64)
+__device__ __forceinline__ void bitonic_regs(int32_t& a, int32_t& b, int i, int k) {
+  const bool up = (i & k) == 0;
+  const int32_t lo = min(a, b), hi = max(a, b);
+  a = up ? lo : hi;
+  b = up ? hi : lo;
+}
+
+template <int R>
+__device__ __forceinline__ void wave_bitonic(int32_t (&v)[R], int m, int lane) {
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        if constexpr (R == 2) {
+          bitonic_regs(v[0], v[1], lane, k);
+        } else if constexpr (R == 4) {
+          if (j == 64) {
+            bitonic_regs(v[0], v[1], lane, k);
+            bitonic_regs(v[2], v[3], lane + 128, k);
+          } else {
+            bitonic_regs(v[0], v[2], lane, k);
+            bitonic_regs(v[1], v[3], lane + 64, k);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (64 * r < m) {
+            const int32_t w = __shfl_xor(v[r], j, 64);
+            v[r] = bitonic_keep(v[r], w, lane + 64 * r, j, k);
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void sort_row_in_registers(const int32_t* __restrict__ in,
+                                                      int32_t* __restrict__ out, int64_t b,
+                                                      int len, int lane) {
+  int m = 1;
+  while (m < len) m <<= 1;
+  int32_t v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = lane + 64 * r < len ? in[b + 64 * r + lane] : 0x7fffffff;
+  wave_bitonic<R>(v, m, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (lane + 64 * r < len) out[b + 64 * r + lane] = v[r];
+}
+
+__global__ void __launch_bounds__(256)
+    k_row_sort_short(int64_t nrows, const int64_t* __restrict__ off,
+                     const int32_t* __restrict__ in, int32_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < nrows;
+       r += waves) {
+    const int64_t b = off[r];
+    const int len = (int)(off[r + 1] - b);  // wavefront-uniform
+    if (len <= 64) sort_row_in_registers<1>(in, out, b, len, lane);
+    else if (len <= 128) sort_row_in_registers<2>(in, out, b, len, lane);
+    else if (len <= SHORT_ROW) sort_row_in_registers<4>(in, out, b, len, lane);
+  }
+}
+
 __global__ void __launch_bounds__(64)
     k_row_sort(int64_t nrows, const int64_t* __restrict__ off, const int32_t* __restrict__ in,
-               int32_t* __restrict__ out) {
+               int32_t* __restrict__ out, int min_len) {
   __shared__ int32_t buf[ROW_LDS];
   const int lane = threadIdx.x;
   for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
     const int64_t b = off[r];
     const int len = (int)(off[r + 1] - b);
+    if (len < min_len) continue;  // sorted by k_row_sort_short
     if (len <= ROW_LDS) {
       int m = 1;
       while (m < len) m <<= 1;
@@ -455,8 +535,14 @@ hipError_t launch_neighbor_fill_rows(hipStream_t s, int m, const int32_t* rows, 
 
 hipError_t launch_row_sort(hipStream_t s, int64_t nrows, const int64_t* off, const int32_t* in,
                            int32_t* out) {
-  const int64_t blocks = nrows < 262144 ? (nrows > 0 ? nrows : 1) : 262144;
-  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)blocks), dim3(64), 0, s, nrows, off, in, out);
+  const int64_t sblocks = std::min<int64_t>(std::max<int64_t>((nrows + 3) / 4, 1), 65536);
+  hipLaunchKernelGGL(k_row_sort_short, dim3((unsigned)sblocks), dim3(256), 0, s, nrows, off, in,
+                     out);
+  // rows longer than SHORT_ROW are rare: a small grid strides over all rows
+  // and sorts only those
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>(nrows, 1), 2048);
+  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)blocks), dim3(64), 0, s, nrows, off, in, out,
+                     SHORT_ROW + 1);
   return hipGetLastError();
 }
 
