@@ -200,15 +200,19 @@ __device__ __forceinline__ T weight_dq(T q, int kind) {
 // ---------------------------------------------------------------------------
 // Cross-lane exchange inside groups of 4 lanes (DPP quad permutes).
 // ---------------------------------------------------------------------------
+// Every pattern used here (quad permutes, row rotations and mirrors, all
+// rows and banks enabled) reads a valid lane, so no "old" value is needed:
+// mov_dpp with bound_ctrl set is one instruction per 32 bits, where
+// update_dpp with an old value first initialises the destination.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
 // quad_perm selectors: lane l of each quad reads lane sel[l].
