@@ -145,11 +145,11 @@ __device__ __forceinline__ void basis_grad_dot(const T (&p)[NBASIS], const T (&c
 // logical blocks: particles stored in spatial order then share neighbors
 // inside one L2 instead of spreading every neighborhood over eight.
 // A bijection of [0, gridDim.x) for any grid size.
-__device__ __forceinline__ int xcd_block() {
-  const int b = blockIdx.x, nb = gridDim.x;
+__device__ __forceinline__ int xcd_block_of(int b, int nb) {
   const int q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + (x < r ? x : r) + (b >> 3);
 }
+__device__ __forceinline__ int xcd_block() { return xcd_block_of(blockIdx.x, gridDim.x); }
 
 struct Box {
   double L[3];

@@ -179,12 +179,15 @@ __global__ void __launch_bounds__(THREADS)
                    const double* __restrict__ fields, double* __restrict__ out, int out_comp,
                    int comp0, double c0, double c1, double c2, int power,
                    const int32_t* __restrict__ list, const int32_t* __restrict__ count) {
-  const int tid = xcd_block() * THREADS + threadIdx.x;
+  // list form: only the particles list[0 .. *count) (count read on the
+  // device); the launch covers n, and the first blocks the list needs keep
+  // the XCD-aware order among themselves
+  const int m = count ? *count : n;
+  const int nbk = count ? (m + THREADS / G - 1) / (THREADS / G) : (int)gridDim.x;
+  if ((int)blockIdx.x >= nbk) return;
+  const int tid = xcd_block_of(blockIdx.x, nbk) * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
-  // list form: only the particles list[0 .. *count) (count read on the device)
-  const int m = count ? *count : n;
-  if (m == 0) return;
   const bool valid = i < m;
   const int ii = list ? list[valid ? i : m - 1] : (valid ? i : m - 1);
   const int st = status[ii];
@@ -278,13 +281,16 @@ __global__ void __launch_bounds__(THREADS)
   constexpr int NF = STAB ? 8 : 7;  // fields with a gradient: the last NF of eight
   constexpr int F0 = 8 - NF;
   constexpr int PPB = THREADS / G;
-  const int tid = xcd_block() * THREADS + threadIdx.x;
+  // List form: only the particles list[0 .. *count) (count read on the
+  // device).  The launch covers n; the first blocks the list needs keep the
+  // XCD-aware order among themselves, the rest leave (before the barrier,
+  // whole blocks together).
+  const int m = count ? *count : n;
+  const int nbk = count ? (m + PPB - 1) / PPB : (int)gridDim.x;
+  if ((int)blockIdx.x >= nbk) return;
+  const int tid = xcd_block_of(blockIdx.x, nbk) * THREADS + threadIdx.x;
   const int i = tid / G;
   const int l = tid % G;
-  // List form: only the particles list[0 .. *count) (count read on the
-  // device); blocks past the list's end leave before the barrier, together.
-  const int m = count ? *count : n;
-  if (xcd_block() * PPB >= m) return;
   const bool valid = i < m;
   const int ii = list ? list[valid ? i : m - 1] : (valid ? i : m - 1);
   const int st = status[ii];
