@@ -55,6 +55,14 @@ Box make_box(const phb_params* p) {
   return b;
 }
 
+int ensure_aux(phb_ctx* ctx) {
+  if (ctx->aux) return PHB_OK;
+  hipError_t e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
+  return hip_check(ctx, e, "second stream");
+}
+
 int ensure_host(phb_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->host_cap) return PHB_OK;
   if (ctx->host) hipHostFree(ctx->host);
@@ -341,6 +349,12 @@ int phb_destroy(phb_ctx* ctx) {
   if (!ctx) return PHB_EINVAL;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  if (ctx->aux) {
+    hipStreamSynchronize(ctx->aux);
+    hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   if (ctx->arena) hipFree(ctx->arena);
   if (ctx->host) hipHostFree(ctx->host);
   delete ctx;
