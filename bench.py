@@ -89,7 +89,7 @@ def time_gpu(fn, reps, torch):
 FORWARD_KERNELS = {
     "fp64": ("k_pack", "k_moments", "k_factor<3>", "k_apply_rhs"),
     "mixed": ("k_pack", "k_moments<fp32>", "k_mixed_screen", "k_mixed_repair", "k_mixed_gta",
-              "k_mixed_refine", "k_apply_rhs<fp32>", "k_apply_rhs<list>"),
+              "k_mixed_refine", "k_apply_rhs<fp32>", "k_apply_rhs<list>", "k_moments<tape>"),
 }
 
 

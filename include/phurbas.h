@@ -68,8 +68,10 @@ extern "C" {
                              one Newton step on the operator rows with an FP64
                              residual product); particles whose FP32 moment
                              matrix is too ill-conditioned for one step are
-                             evaluated in FP64 (see mixed_cond_x10); the
-                             reverse mode assembles its moments in FP64 */
+                             evaluated in FP64 (see mixed_cond_x10); with a
+                             tape the forward call also assembles the FP64
+                             moments the reverse mode solves with (on a
+                             second stream, joined before it returns) */
 #define PHB_W_POLY3 0     /* w = (1 - d^2/r_f^2)^3 */
 #define PHB_W_UNIT 1      /* w = 1 */
 #define PHB_FIT_FULL20 0  /* all 20 monomials, constant included */

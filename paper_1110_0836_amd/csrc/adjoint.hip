@@ -953,12 +953,10 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     ws.plan(3 * nd);                     // dxdt scratch
     ws.plan((size_t)n * sizeof(int32_t));
   }
-  // The mixed form's tape holds FP32-assembled moments.  Its forward pass
-  // refines them away at the data level, but the reverse mode solves with
-  // right-hand sides built from the incoming gradients, which carry no such
-  // structure: it assembles the moments again in FP64.
-  const bool fresh_mom = !need_tape && p->precision == PHB_MIXED;
-  if (fresh_mom) ws.plan((size_t)NMOM * nd);
+  // Every tape holds FP64 moments: the mixed forward assembles them for the
+  // tape beside its own FP32 ones, since the reverse mode solves with
+  // right-hand sides built from the incoming gradients, which carry no
+  // smooth-data structure to refine FP32 assembly error away.
   if ((rc = ws.commit())) return rc;
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
@@ -996,31 +994,6 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     tape = tp;
   }
   const double* mom = tape + (size_t)TAPE_MOM * n;
-  // The FP64 moments do not depend on the reverse pass's first kernels
-  // (Ubar, Y): they run beside them on the second stream, joined before the
-  // factorization.  While per-kernel profiling is on they run in order, so
-  // that each kernel's time is its own.
-  bool forked = false;
-  if (fresh_mom) {
-    double* m64 = ws.take<double>((size_t)NMOM * n);
-    if (!ctx->prof_on) {
-      if ((rc = ensure_aux(ctx))) return rc;
-      hipError_t e = hipEventRecord(ctx->ev_fork, s);
-      if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
-      if (e == hipSuccess) e = launch_moments(ctx->aux, ap, ctx->lanes_assemble, m64);
-      if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, ctx->aux);
-      if ((rc = hip_check(ctx, e, "moments beside the reverse pass"))) return rc;
-      forked = true;
-    } else {
-      Prof pf(ctx, "k_moments");
-      if ((rc = hip_check(ctx, launch_moments(s, ap, ctx->lanes_assemble, m64), "moments")))
-        return rc;
-    }
-    mom = m64;
-  }
-  auto join = [&]() -> int {
-    return forked ? hip_check(ctx, hipStreamWaitEvent(s, ctx->ev_join, 0), "join") : PHB_OK;
-  };
   const int interp = a.fit == PHB_FIT_INTERP19;
   if (stab) {
     { Prof pf(ctx, "k_adj_u");
@@ -1034,7 +1007,6 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
       default: launch_yrows<4>(s, ap, tape, orec, ybuf); break;
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Y"))) return rc; }
-    if ((rc = join())) return rc;
     { Prof pf(ctx, "k_adj_factor<stab>");
     hipLaunchKernelGGL(k_adj_factor<true>, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS),
                        0, s, n, mom, ybuf, tape, orec, interp);
@@ -1047,7 +1019,6 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
       default: rc = hip_check(ctx, launch_adj_y_g<4>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
     }
     if (rc) return rc; }
-    if ((rc = join())) return rc;
     { Prof pf(ctx, "k_adj_factor");
     hipLaunchKernelGGL(k_adj_factor<false>, dim3(grid_for((int64_t)n * 4, THREADS)),
                        dim3(THREADS), 0, s, n, mom, ybuf, tape, orec, interp);

@@ -772,6 +772,37 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
   return hip_check(ctx, hipGetLastError(), "mixed refinement");
 }
 
+// With a tape, the reverse mode needs FP64 moments (its right-hand sides,
+// built from incoming gradients, would see the FP32 assembly error
+// unrefined).  They depend on the packed geometry only: the pass runs on the
+// second stream beside the forward's own chain and is joined before the
+// forward returns (in order while per-kernel profiling is on).
+int fork_tape_moments(phb_ctx* ctx, const EvalArgs& a, double* tape, bool& forked) {
+  forked = false;
+  if (!tape) return PHB_OK;
+  double* dst = tape + (size_t)TAPE_MOM * a.n;
+  if (ctx->prof_on) {
+    Prof pf(ctx, "k_moments<tape>");
+    return hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, dst),
+                     "tape moments");
+  }
+  int rc;
+  if ((rc = ensure_aux(ctx))) return rc;
+  hipError_t e = hipEventRecord(ctx->ev_fork, ctx->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
+  if (e == hipSuccess) e = launch_moments(ctx->aux, a, ctx->lanes_assemble, dst);
+  if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, ctx->aux);
+  if ((rc = hip_check(ctx, e, "tape moments"))) return rc;
+  forked = true;
+  return PHB_OK;
+}
+
+int join_aux(phb_ctx* ctx, bool forked, int rc) {
+  if (!forked) return rc;
+  const int rj = hip_check(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "join");
+  return rc ? rc : rj;
+}
+
 }  // namespace
 
 size_t mixed_rhs_bytes(int64_t n, bool stab) {
@@ -800,28 +831,30 @@ static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const St
   OpBufs m = take_op(ws, n, ng);
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
-  if (tape) m.mom = tape + (size_t)TAPE_MOM * n;
   EvalArgs a = a0;
   a.geo = geo;
   a.fq = fq;
   { Prof pf(ctx, "k_pack");
     if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
       return rc; }
+  bool forked = false;
+  if ((rc = fork_tape_moments(ctx, a, tape, forked))) return rc;
   rc = stab ? mixed_operator<9>(ctx, a, m, status) : mixed_operator<3>(ctx, a, m, status);
-  if (rc) return rc;
+  if (rc) return join_aux(ctx, forked, rc);
   { Prof pf(ctx, stab ? "k_apply_rhs<fp32, stab>" : "k_apply_rhs<fp32>");
     if ((rc = hip_check(ctx,
                         launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, gamma, sb, m.gt,
                                          status, rhs, dxdt, tape, true),
                         "mixed apply")))
-      return rc; }
+      return join_aux(ctx, forked, rc); }
   // the listed (ill-conditioned) particles again, in FP64: applied in FP32,
   // their operator would lose kappa eps_32
-  Prof pf(ctx, "k_apply_rhs<list>");
-  return hip_check(ctx,
+  { Prof pf(ctx, "k_apply_rhs<list>");
+    rc = hip_check(ctx,
                    launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, gamma, sb, m.gt, status,
                                     rhs, dxdt, tape, false, m.list, m.count),
-                   "mixed apply (listed)");
+                   "mixed apply (listed)"); }
+  return join_aux(ctx, forked, rc);
 }
 
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, const double* q,
@@ -845,26 +878,27 @@ int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, co
   MixedBufs m = take_mixed(ws, n, nf, ng);
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
-  if (tape) m.mom = tape + (size_t)TAPE_MOM * n;
   EvalArgs a = a0;
   a.geo = geo;
   a.fq = fq;
   { Prof pf(ctx, "k_pack");
     if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
       return rc; }
+  bool forked = false;
+  if ((rc = fork_tape_moments(ctx, a, tape, forked))) return rc;
   if (stab) {
-    if ((rc = mixed_fit<9>(ctx, a, fq, 0, 8, m, status))) return rc;
+    if ((rc = mixed_fit<9>(ctx, a, fq, 0, 8, m, status))) return join_aux(ctx, forked, rc);
     Prof pf(ctx, "k_mixed_rhs_finish<stab>");
     hipLaunchKernelGGL(k_mixed_rhs_finish<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
                        ctx->stream, n, geo, fq, m.rows, status, gamma, sb, rhs, dxdt, tape);
   } else {
     // V, B and sigma are entries 1..7 of the packed records
-    if ((rc = mixed_fit<3>(ctx, a, fq, 1, 7, m, status))) return rc;
+    if ((rc = mixed_fit<3>(ctx, a, fq, 1, 7, m, status))) return join_aux(ctx, forked, rc);
     Prof pf(ctx, "k_mixed_rhs_finish");
     hipLaunchKernelGGL(k_mixed_rhs_finish<false>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
                        ctx->stream, n, geo, fq, m.rows, status, gamma, sb, rhs, dxdt, tape);
   }
-  return hip_check(ctx, hipGetLastError(), "mixed rhs");
+  return join_aux(ctx, forked, hip_check(ctx, hipGetLastError(), "mixed rhs"));
 }
 
 size_t mixed_derivs_bytes(int64_t n, bool second) {

@@ -35,7 +35,8 @@ struct EvalArgs {
 
 // Tape of the forward evaluation, per particle (SoA, n entries each):
 // 21 gradients (V, B, sigma x 3), the status, grad rho, grad div V and
-// grad div B (written only with the stabilisers on), then the 84 moments.
+// grad div B (written only with the stabilisers on), then the 84 moments,
+// FP64-assembled in both forms.
 constexpr int TAPE_STATUS = 21;
 constexpr int TAPE_GRHO = 22;
 constexpr int TAPE_GDV = 25;

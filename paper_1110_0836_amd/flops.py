@@ -31,6 +31,8 @@ k_adj_gather     memory bound: 80 B per pair record, 232 B per particle.
 Mixed form (FP32 arithmetic after the FP64 displacement, FP64 factor and
 solves; counted the same way, whatever the precision):
 k_moments<fp32>  as k_moments                                            = 187
+k_moments<tape>  the FP64 moments a forward call with a tape assembles for the
+                 reverse mode, as k_moments                               = 187
 k_mixed_b        per pair: geometry and weight (15), basis (16), per field
                  w df (2) and 20 FMA (40), seven fields                   = 325
 k_mixed_factor   per particle: equilibration + Cholesky (3330), seven
@@ -58,6 +60,7 @@ k_apply_rhs<fp32> as k_apply_rhs (FP64 operator weights, FP32 sums)       = 203
 PER_PAIR = {
     "k_moments": 187,
     "k_moments<fp32>": 187,
+    "k_moments<tape>": 187,
     "k_mixed_b": 325,
     "k_mixed_resid": 612,
     "k_apply_rhs": 203,
