@@ -352,7 +352,8 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * Keys: "cells_per_rf" (1..4: neighbor-grid cells per minimum r_f),
  * "lanes_moments", "lanes_apply", "lanes_adj_y" (1, 2 or 4 lanes sharing one
  * particle's neighbor loop in the moment, application and reverse-mode
- * assembly kernels), "lanes_gather" (1, 2 or 4 lanes summing one particle's
+ * assembly kernels; lanes_adj_y also sets the mixed form's residual-product
+ * kernel, of the same shape), "lanes_gather" (1, 2 or 4 lanes summing one particle's
  * transposed row in the reverse mode), "adj_pairs_mode" (0: one lane per
  * neighbor entry, 1: one wavefront per owner particle), "record_order" (0:
  * pair records written at their transposed position, 1: written in forward

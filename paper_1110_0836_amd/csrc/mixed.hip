@@ -730,7 +730,14 @@ OpBufs take_op(Workspace& ws, int64_t n, int ng) {
   return m;
 }
 
-constexpr int GTA_LANES = 2;  // lanes sharing a particle in k_mixed_gta
+template <int G>
+void launch_gta(hipStream_t s, const EvalArgs& a, const double* gt, int ng,
+                const int32_t* status, const int32_t* flag, double* mb) {
+  for (int r0 = 0; r0 < ng; r0 += 3)
+    hipLaunchKernelGGL((k_mixed_gta<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0,
+                       s, a.n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gt, r0, status,
+                       flag, mb);
+}
 
 // Refined operator rows 1..NG of A^{-1} into m.gt: FP32 moments (FP64 for the
 // particles the screen lists), the FP64 factor with the screen, the FP64
@@ -761,10 +768,13 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
                        m.count, interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed repair"))) return rc; }
   { Prof pf(ctx, "k_mixed_gta");
-    for (int r0 = 0; r0 < NG; r0 += 3)
-      hipLaunchKernelGGL((k_mixed_gta<GTA_LANES>), dim3(grid_for((int64_t)n * GTA_LANES, THREADS)),
-                         dim3(THREADS), 0, s, n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind,
-                         m.gt, r0, status, m.flag, m.mb);
+    // the reverse-mode Y kernel's shape (60 FP64 sums per lane): its lane
+    // count applies
+    switch (ctx->lanes_adj_y) {
+      case 1: launch_gta<1>(s, a, m.gt, NG, status, m.flag, m.mb); break;
+      case 2: launch_gta<2>(s, a, m.gt, NG, status, m.flag, m.mb); break;
+      default: launch_gta<4>(s, a, m.gt, NG, status, m.flag, m.mb); break;
+    }
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed residual product"))) return rc; }
   Prof pf(ctx, "k_mixed_refine");
   hipLaunchKernelGGL((k_mixed_refine<NG>), dim3(gq), dim3(THREADS), 0, s, n, m.mom, m.mb, m.gt,
