@@ -213,3 +213,21 @@ def test_refinement_knobs():
         check_rhs(*rhs_both(synth.config2(side=16), precision=P.PHB_MIXED), TOLMIX)
     finally:
         P.phb_tune_set("mixed_cond_x10", -1)
+
+
+@pytest.mark.parametrize("stab", [{}, dict(visc_grid=0.3, visc_adapt=0.3, divb_diff=0.3)])
+def test_tape_holds_fp64_moments(stab):
+    """A mixed forward call with a tape assembles the reverse mode's FP64
+    moments into it (on the second stream): the same moments, bit for bit, as
+    the FP64 form's tape; the tape's other entries are the mixed form's."""
+    c = synth.cp_alfven(12)
+    pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
+    s64 = setup_of(c, **stab)
+    smx = setup_of(c, precision=P.PHB_MIXED, **stab)
+    off, idx = P.neighbors(pos, lam, s64)
+    n = c["lam"].shape[0]
+    t64 = P.mhd_rhs(pos, lam, off, idx, q, s64, tape=True)[3].cpu().numpy().reshape(-1, n)
+    tmx = P.mhd_rhs(pos, lam, off, idx, q, smx, tape=True)[3].cpu().numpy().reshape(-1, n)
+    assert np.array_equal(tmx[-84:], t64[-84:])
+    assert np.array_equal(tmx[21], t64[21])  # status
+    assert 0 < np.abs(tmx[:21] - t64[:21]).max() < 1e-5 * np.abs(t64[:21]).max()
