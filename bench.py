@@ -163,7 +163,7 @@ def batched_graph(P, torch, steps, warmup):
     reverse pass, timed per graph launch."""
     import numpy as np
     from paper_1110_0836_amd import synth
-    cfg = synth.config5()
+    cfg = synth.batched_cubes()
     sets = cfg["sets"]
     pos = torch.from_numpy(np.concatenate([s["pos"] for s in sets], axis=1)).cuda()
     lam = torch.from_numpy(np.concatenate([s["lam"] for s in sets])).cuda()
@@ -223,7 +223,7 @@ def main():
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     assert forms and all(f in ("mixed", "fp64") for f in forms), forms
     log("generating the shear-layer set")
-    c = synth.config3(n=args.n)
+    c = synth.shear_layer(n=args.n)
     n = c["lam"].shape[0]
     rng = np.random.default_rng(4)
     w_np = rng.uniform(0.0, 1.0, n)

@@ -65,7 +65,7 @@ def nonzero_mode(rng):
             return m
 
 
-def config1(seed: int = 1, pin: bool = False):
+def cubic_set(seed: int = 1, pin: bool = False):
     """4,096 particles on a jittered 16^3 lattice, lambda = 1/16, periodic unit cube.
     Fields: random cubic polynomials in (x - 1/2) plus 1e-3 sin(2 pi m.x + phi).
     ``pin=True``: no sine and an open (non-periodic) box, so that the fields are
@@ -123,7 +123,7 @@ def wave_background(n, rho0=1.0, sigma0=1.5, B0=B0_WAVE):
     return q
 
 
-def config2(seed: int = 2, side: int = 64, eps: float = 1e-6):
+def fast_wave_set(seed: int = 2, side: int = 64, eps: float = 1e-6):
     """side^3 jittered lattice (lambda = 1/side) in a periodic unit cube carrying a
     fast-magnetosonic plane wave of amplitude eps along x on the background
     rho = 1, sigma = 1/(gamma - 1), V = 0, B = (1, sqrt 2, 0.5)."""
@@ -141,9 +141,9 @@ def config2(seed: int = 2, side: int = 64, eps: float = 1e-6):
                 name=f"fastwave_lattice{side}")
 
 
-def config4(seed: int = 4, side: int = 64):
-    """The wave set of config2 plus loss weights w_i ~ U(0, 1)."""
-    c = config2(seed=2, side=side)
+def weighted_wave_set(seed: int = 4, side: int = 64):
+    """The wave set of fast_wave_set plus loss weights w_i ~ U(0, 1)."""
+    c = fast_wave_set(seed=2, side=side)
     rng = np.random.default_rng(seed)
     c["w"] = rng.uniform(0.0, 1.0, size=c["lam"].shape[0])
     c["name"] = f"fastwave_adjoint_lattice{side}"
@@ -162,7 +162,7 @@ def shear_g(y):
     return 1.0 - 0.75 * np.maximum(s1, s2)
 
 
-def config3(seed: int = 3, n: int = 1 << 20):
+def shear_layer(seed: int = 3, n: int = 1 << 20):
     """Adaptive shear-layer set: x, z ~ U(0,1); y drawn from the density
     proportional to g(y)^-3 (exactly n draws); lambda = s g(y) with s fixed by
     one particle per lambda^3 on average.  Fields: tanh shear V_x = 0.5 T(y),
@@ -234,7 +234,7 @@ def linear_wave(kind: str, side: int, eps: float = 1e-6, seed: int = 6, jitter: 
                 omega=omega, R=R, eps=eps, q0=q0, name=f"{kind}_wave_lattice{side}")
 
 
-def config5(seed: int = 5, n_sets: int = 32, smin: int = 16, smax: int = 64):
+def batched_cubes(seed: int = 5, n_sets: int = 32, smin: int = 16, smax: int = 64):
     """n_sets independent periodic unit cubes, side n_s ~ U{smin..smax}, jittered
     lattice with lambda = 1/n_s.  Each field a0 + sum_{m=1..3} a_m sin(2 pi k_m.x + phi_m)
     with k_m in {-2..2}^3 \\ 0, a_m ~ U(-0.05, 0.05); a0 = 1 (rho), 1.5 (sigma), else 0."""

@@ -87,7 +87,7 @@ def loss_bar_oracle(c, w):
 
 
 def test_wave_loss_gradient_small():
-    c = synth.config4(side=16)
+    c = synth.weighted_wave_set(side=16)
     gbar = loss_bar_oracle(c, c["w"])
     qb, pb = gpu_adjoint(c, gbar)
     off, idx = oracle.neighbors(c["pos"], c["lam"])
@@ -122,7 +122,7 @@ def gpu_loss_terms(c, w, pos_np, q_np):
 
 
 def test_autograd_full_size_vs_oracle_samples_and_fd():
-    c = synth.config4()  # 262,144 particles
+    c = synth.weighted_wave_set()  # 262,144 particles
     w = c["w"]
     qg, pg, rhs_gpu = autograd_grads(c, w)
     n = c["lam"].shape[0]
@@ -182,7 +182,7 @@ def test_autograd_full_size_vs_oracle_samples_and_fd():
 
 
 def test_shear_layer_full_size_samples():
-    c = synth.config3()
+    c = synth.shear_layer()
     n = c["lam"].shape[0]
     rng = np.random.default_rng(5)
     gbar = np.zeros((8, n))

@@ -31,7 +31,7 @@ def concat(sets):
 
 
 def small_sets(seed=11, n_sets=4):
-    return synth.config5(seed=seed, n_sets=n_sets, smin=8, smax=12)["sets"]
+    return synth.batched_cubes(seed=seed, n_sets=n_sets, smin=8, smax=12)["sets"]
 
 
 class Pass:
@@ -192,7 +192,7 @@ def test_capture_before_neighbors_is_refused():
 
 
 def test_tuner_choices_cache_and_results(tmp_path):
-    c = synth.config2(side=20)
+    c = synth.fast_wave_set(side=20)
     s = P.Setup()
     pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
     off, idx = P.neighbors(pos, lam, s)
@@ -224,7 +224,7 @@ def test_full_batched_sets_graph_sampled():
     """32 sets, sides 16..64 (about 2.8M particles): mixed forward and reverse
     pass in one graph, replayed twice, checked on sampled particles of every
     set against the oracle."""
-    cfg = synth.config5()
+    cfg = synth.batched_cubes()
     sets = cfg["sets"]
     pos, lam, q = concat(sets)
     n = lam.shape[0]

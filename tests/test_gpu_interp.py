@@ -55,7 +55,7 @@ def test_derivatives_match_oracle(precision, mixed_refine):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_rhs_matches_oracle(precision, mixed_refine):
-    for c in (_noisy(synth.cp_alfven(16), 93), _noisy(synth.config2(side=16), 94)):
+    for c in (_noisy(synth.cp_alfven(16), 93), _noisy(synth.fast_wave_set(side=16), 94)):
         s = setup_of(c, fit=INTERP, precision=precision)
         pos, lam = dev(c["pos"]), dev(c["lam"])
         off, idx = P.neighbors(pos, lam, s)
@@ -136,7 +136,7 @@ def test_divb_norm_solenoidal_cubic_field_is_roundoff():
     the fit reproduces exactly: the diagnostic is roundoff at whole-sphere
     particles, in both fits."""
     from test_oracle_interp import _quartic_curl
-    c = synth.config1(pin=True)
+    c = synth.cubic_set(pin=True)
     q = np.ones((8, c["pos"].shape[1]))
     q[4:7] = np.array([2.0, -1.0, 1.5])[:, None] + 0.3 * _quartic_curl(
         c["pos"], np.random.default_rng(97))

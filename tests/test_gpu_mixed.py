@@ -40,16 +40,16 @@ def per_order(g1, g2, o1, o2, sel):
     return e1.max(), e2.max()
 
 
-def test_config1_derivatives_periodic():
-    c = synth.config1()
+def test_cubic_set_derivatives_periodic():
+    c = synth.cubic_set()
     (g1, g2, gs), (o1, o2, os_) = mixed_derivs(c)
     assert np.array_equal(gs, os_)
     e1, e2 = per_order(g1, g2, o1, o2, gs == 0)
     assert e1 < TOLMIX and e2 < TOLMIX
 
 
-def test_config1_derivatives_open_box():
-    c = synth.config1(pin=True)
+def test_cubic_set_derivatives_open_box():
+    c = synth.cubic_set(pin=True)
     (g1, g2, gs), (o1, o2, os_) = mixed_derivs(c)
     assert np.array_equal(gs, os_)
     ok = gs == 0
@@ -66,7 +66,7 @@ def test_config1_derivatives_open_box():
 def test_constant_field_and_large_offset():
     # the data-level centring: a field 1e6 + small signal keeps its
     # derivatives to the FP32 bound of the signal, not of the offset
-    c = synth.config1()
+    c = synth.cubic_set()
     rng = np.random.default_rng(9)
     x = c["pos"]
     f = np.stack([np.full(x.shape[1], 3.0), 1e6 + 1e-3 * np.sin(2 * np.pi * x[0]),
@@ -107,7 +107,7 @@ def test_status_paths():
 
 @pytest.mark.parametrize("side", [16, 24])
 def test_rhs_fast_wave(side):
-    check_rhs(*rhs_both(synth.config2(side=side), precision=P.PHB_MIXED), TOLMIX)
+    check_rhs(*rhs_both(synth.fast_wave_set(side=side), precision=P.PHB_MIXED), TOLMIX)
 
 
 def test_rhs_cp_alfven():
@@ -115,13 +115,13 @@ def test_rhs_cp_alfven():
 
 
 def test_rhs_shear_layer_full_size_sampled():
-    c = synth.config3()
+    c = synth.shear_layer()
     rows = np.random.default_rng(4).choice(c["lam"].shape[0], 300, replace=False)
     check_rhs(*rhs_both(c, rows=rows, precision=P.PHB_MIXED), TOLMIX)
 
 
 def test_rhs_matches_fp64_path():
-    c = synth.config2(side=24)
+    c = synth.fast_wave_set(side=24)
     pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
     s64 = setup_of(c)
     smx = setup_of(c, precision=P.PHB_MIXED)
@@ -178,7 +178,7 @@ def test_adjoint_shear_layer_full_size_matches_fp64():
     reverse mode of the benchmark loss against the FP64 form, which matches
     the oracle to 1e-12 on sampled particles."""
     import torch
-    c = synth.config3()
+    c = synth.shear_layer()
     n = c["lam"].shape[0]
     pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
     w = torch.tensor(np.random.default_rng(4).uniform(size=n)).cuda()
@@ -210,7 +210,7 @@ def test_refinement_knobs():
             P.phb_tune_set(key, bad)
     P.phb_tune_set("mixed_cond_x10", 120)
     try:
-        check_rhs(*rhs_both(synth.config2(side=16), precision=P.PHB_MIXED), TOLMIX)
+        check_rhs(*rhs_both(synth.fast_wave_set(side=16), precision=P.PHB_MIXED), TOLMIX)
     finally:
         P.phb_tune_set("mixed_cond_x10", -1)
 

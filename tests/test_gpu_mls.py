@@ -35,8 +35,8 @@ def derivs_both(c, fields=None):
 
 
 @pytest.mark.parametrize("pin", [False, True])
-def test_config1_derivatives(pin):
-    c = synth.config1(pin=pin)
+def test_cubic_set_derivatives(pin):
+    c = synth.cubic_set(pin=pin)
     (g1, g2, gs), (o1, o2, os_) = derivs_both(c)
     assert np.array_equal(gs, os_)
     ok = gs == 0
@@ -119,7 +119,7 @@ def check_rhs(g, o, qs, tol, sel=None, gamma=5.0 / 3.0):
 
 @pytest.mark.parametrize("side", [16, 24])
 def test_rhs_fast_wave_small(side):
-    check_rhs(*rhs_both(synth.config2(side=side)), TOL64)
+    check_rhs(*rhs_both(synth.fast_wave_set(side=side)), TOL64)
 
 
 def test_rhs_cp_alfven():
@@ -135,7 +135,7 @@ def test_rhs_random_open_box():
 
 
 def test_rhs_unit_weight():
-    c = synth.config2(side=16)
+    c = synth.fast_wave_set(side=16)
     g, o, qs = rhs_both(c, weight=P.PHB_W_UNIT)
     orhs, _, _ = oracle.mhd_rhs(c["pos"], c["lam"], *oracle.neighbors(c["pos"], c["lam"]),
                                 c["q"], weight=1)
@@ -144,19 +144,19 @@ def test_rhs_unit_weight():
 
 
 def test_rhs_fast_wave_full_size_sampled():
-    c = synth.config2()
+    c = synth.fast_wave_set()
     rows = np.random.default_rng(3).choice(c["lam"].shape[0], 2000, replace=False)
     check_rhs(*rhs_both(c, rows=rows), TOL64)
 
 
 def test_rhs_shear_layer_full_size_sampled():
-    c = synth.config3()
+    c = synth.shear_layer()
     rows = np.random.default_rng(4).choice(c["lam"].shape[0], 300, replace=False)
     check_rhs(*rhs_both(c, rows=rows), TOL64)
 
 
 def test_tape_holds_gradients():
-    c = synth.config2(side=16)
+    c = synth.fast_wave_set(side=16)
     s = setup_of(c)
     pos, lam = dev(c["pos"]), dev(c["lam"])
     off, idx = P.neighbors(pos, lam, s)

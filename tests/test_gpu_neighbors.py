@@ -44,9 +44,9 @@ def test_golden_tiny():
     assert [list(r) for r in csr_rows(goff, gidx)] == g["rows"]
 
 
-def test_config1_lattice():
-    assert_same(synth.config1())
-    assert_same(synth.config1(pin=True))
+def test_cubic_set_lattice():
+    assert_same(synth.cubic_set())
+    assert_same(synth.cubic_set(pin=True))
 
 
 @pytest.mark.parametrize("n", [1, 2, 7, 333, 2049, 5003])
@@ -76,18 +76,18 @@ def test_long_rows_use_the_fallback_sort():
 
 
 def test_shear_layer_reduced():
-    c = synth.config3(n=1 << 15)
+    c = synth.shear_layer(n=1 << 15)
     assert_same(c)
 
 
 def test_fast_wave_full_size_sampled():
-    c = synth.config2()
+    c = synth.fast_wave_set()
     rows = np.random.default_rng(1).choice(c["lam"].shape[0], 1500, replace=False)
     assert_same(c, rows=rows)
 
 
 def test_shear_layer_full_size_sampled():
-    c = synth.config3()
+    c = synth.shear_layer()
     rows = np.random.default_rng(2).choice(c["lam"].shape[0], 300, replace=False)
     assert_same(c, rows=rows)
 
@@ -111,7 +111,7 @@ def test_transpose():
 
 def test_capacity_and_input_errors():
     import torch
-    c = synth.config1()
+    c = synth.cubic_set()
     pos, lam = dev(c["pos"]), dev(c["lam"])
     s = setup_of(c)
     off = torch.empty(lam.shape[0] + 1, dtype=torch.int64, device="cuda")
@@ -136,7 +136,7 @@ def test_capacity_and_input_errors():
 
 
 def test_spatial_order_is_a_permutation_and_local():
-    c = synth.config3(n=1 << 16)
+    c = synth.shear_layer(n=1 << 16)
     perm = P.spatial_order(dev(c["pos"]), dev(c["lam"]), setup_of(c)).cpu().numpy()
     assert np.array_equal(np.sort(perm), np.arange(len(perm)))
     p = c["pos"][:, perm]

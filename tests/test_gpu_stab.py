@@ -92,7 +92,7 @@ def _steep_cloud(n=3000, seed=71, periodic=(1, 1, 1)):
 
 
 def test_fp64_periodic_sets():
-    for c in (synth.cp_alfven(16), synth.config2(side=16), _steep_cloud()):
+    for c in (synth.cp_alfven(16), synth.fast_wave_set(side=16), _steep_cloud()):
         check(c, 1e-12)
 
 
@@ -116,7 +116,7 @@ def test_fp64_open_box():
 
 
 def test_fp64_shear_layer_full_size_sampled():
-    c = synth.config3()
+    c = synth.shear_layer()
     rows = np.random.default_rng(73).choice(c["lam"].shape[0], 300, replace=False)
     check(c, 1e-12, rows=rows)
 

@@ -29,7 +29,7 @@ def oracle_steps(c, dt, nsteps):
 
 @pytest.mark.parametrize("name", ["cp_alfven", "fast_wave"])
 def test_steps_match_oracle(name):
-    c = synth.cp_alfven(12) if name == "cp_alfven" else synth.config2(side=16)
+    c = synth.cp_alfven(12) if name == "cp_alfven" else synth.fast_wave_set(side=16)
     dt = 0.01
     gp, gq, gs, _, _ = gpu_steps(c, dt, 3)
     op, oq, os_ = oracle_steps(c, dt, 3)
@@ -44,7 +44,7 @@ def test_steps_match_oracle(name):
 
 
 def test_uniform_flow_translates_exactly():
-    c = synth.config1()
+    c = synth.cubic_set()
     n = c["pos"].shape[1]
     q = synth.wave_background(n, 1.0, 1.5)
     q[1:4] = np.array([0.3, -0.2, 0.45])[:, None]

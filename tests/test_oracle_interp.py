@@ -19,7 +19,7 @@ from test_oracle_mls import _analytic
 
 
 def test_interpolating_fit_reproduces_cubics():
-    c = synth.config1(pin=True)
+    c = synth.cubic_set(pin=True)
     off, idx = oracle.neighbors(c["pos"], c["lam"], periodic=c["periodic"])
     d1, d2, st = oracle.mls_derivs(c["pos"], c["lam"], off, idx, c["q"], periodic=c["periodic"],
                                    fit=1)
@@ -108,7 +108,7 @@ def _quartic_curl(pos, rng):
 
 
 def test_divb_zero_for_solenoidal_cubic_field():
-    c = synth.config1(pin=True)
+    c = synth.cubic_set(pin=True)
     rng = np.random.default_rng(84)
     q = np.ones((8, c["pos"].shape[1]))
     q[4:7] = np.array([2.0, -1.0, 1.5])[:, None] + 0.3 * _quartic_curl(c["pos"], rng)

@@ -113,7 +113,7 @@ def test_cp_alfven_exact_rhs():
 
 
 def test_galilean_invariance():
-    c = synth.config1()
+    c = synth.cubic_set()
     q = c["q"].copy()
     q[0] = 1.0 + 0.2 * np.abs(q[0])  # positive density
     q[7] = 1.0 + 0.2 * np.abs(q[7])

@@ -48,7 +48,7 @@ def _analytic(pos, coef, expo, center=0.5):
 
 @pytest.mark.parametrize("weight", [0, 1])
 def test_cubic_fields_exact(weight):
-    c = synth.config1(pin=True)
+    c = synth.cubic_set(pin=True)
     off, idx = oracle.neighbors(c["pos"], c["lam"], periodic=c["periodic"])
     d1, d2, st = oracle.mls_derivs(c["pos"], c["lam"], off, idx, c["q"],
                                    periodic=c["periodic"], weight=weight)
@@ -67,7 +67,7 @@ def test_cubic_fields_exact(weight):
 
 
 def test_constant_and_linear_fields():
-    c = synth.config1(pin=True)
+    c = synth.cubic_set(pin=True)
     pos = c["pos"]
     off, idx = oracle.neighbors(pos, c["lam"], periodic=c["periodic"])
     a = np.array([0.3, -1.7, 2.2])

@@ -86,7 +86,7 @@ def test_mean_count_closed_form():
 
 
 def test_jittered_lattice_count_near_expectation():
-    c = synth.config1()
+    c = synth.cubic_set()
     off, idx = oracle.neighbors(c["pos"], c["lam"])
     counts = np.diff(off)
     # self plus ~50.97 others; the jittered lattice is not Poisson, so only a loose band

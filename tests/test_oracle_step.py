@@ -14,7 +14,7 @@ from paper_1110_0836_amd import synth
 
 
 def test_uniform_state_translates():
-    c = synth.config1()
+    c = synth.cubic_set()
     n = c["pos"].shape[1]
     q = synth.wave_background(n, 1.0, 1.5)
     V = np.array([0.3, -0.2, 0.45])
