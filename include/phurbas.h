@@ -152,10 +152,11 @@ int phb_neighbors_transpose(phb_ctx* ctx, int64_t n, int64_t nnz, const int64_t*
                             const int32_t* idx, int64_t* t_offsets, int32_t* t_src,
                             int32_t* t_pos);
 
-/* A spatially coherent particle order (Morton order of cells about r_f,min
- * wide, ties by index): perm int32[n] lists caller indices in that order.
- * The analogue of the Peano-Hilbert ordering of the paper's framework
- * (Sec. 2.1); kernels run fastest on data permuted into it.  Synchronizes. */
+/* A spatially coherent particle order: the Peano-Hilbert order of the
+ * particles' cells on a 1024^3 grid over the box (Sec. 2.1 orders particles
+ * along the same curve), ties by index.  perm int32[n] lists caller indices
+ * in that order; kernels run fastest on data permuted into it.  Positions
+ * and lambdas are validated as for the neighbor build.  Synchronizes. */
 int phb_spatial_order(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                       const double* lambda, int32_t* perm);
 

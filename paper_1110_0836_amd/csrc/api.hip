@@ -601,8 +601,7 @@ int phb_spatial_order(phb_ctx* ctx, const phb_params* p, int64_t n64, const doub
   if (!pos || !lambda || !perm) return set_error(ctx, PHB_EINVAL, "null pointer");
   hipSetDevice(ctx->device);
   const int n = (int)n64;
-  const int max_bits = 7;
-  const int64_t nbins_max = int64_t(1) << (3 * max_bits);
+  const int64_t nbins_max = int64_t(1) << 21;  // the counting sort's bins (2^7 per axis)
   Workspace ws(ctx);
   ws.plan(3 * VALIDATE_BLOCKS * sizeof(double));
   ws.plan((size_t)n * sizeof(int32_t));
@@ -617,19 +616,8 @@ int phb_spatial_order(phb_ctx* ctx, const phb_params* p, int64_t n64, const doub
   int32_t* bscan = ws.take<int32_t>(scan_tmp_elems(nbins_max));
   double lmin, lmax;
   if ((rc = validate_inputs(ctx, p, n, pos, lambda, part, &lmin, &lmax))) return rc;
-  // power-of-two cells per axis, about r_f,min wide
-  const double rmin = p->rf_ratio * lmin;
-  const double lmaxbox = std::max(p->L[0], std::max(p->L[1], p->L[2]));
-  int bits = 0;
-  while (bits < max_bits && lmaxbox / (1 << (bits + 1)) >= rmin) ++bits;
-  Grid g;
-  for (int a = 0; a < 3; ++a) {
-    g.nc[a] = 1 << bits;
-    g.inv_h[a] = g.nc[a] / p->L[a];
-  }
-  g.margin = 0.0;
-  return hip_check(ctx, launch_morton_order(ctx->stream, n, pos, g, key, bcount, bstart, bscan,
-                                            perm),
+  return hip_check(ctx, launch_hilbert_order(ctx->stream, n, pos, p->L, key, bcount, bstart, bscan,
+                                             perm),
                    "spatial order");
 }
 

@@ -1,5 +1,5 @@
 // Fixed-radius, non-mutual neighbor search (paper II, Sec. 2 and 2.1) on a
-// uniform cell grid, its transpose, a Morton-order particle ordering, and the
+// uniform cell grid, its transpose, a Peano-Hilbert particle ordering, and the
 // gather kernel used to apply an ordering.
 //
 // Pipeline of the search:
@@ -410,7 +410,20 @@ __global__ void __launch_bounds__(NB_THREADS)
   }
 }
 
-// ---- Morton ordering -------------------------------------------------------
+// ---- Peano-Hilbert ordering ------------------------------------------------
+// Each particle's cell on a 2^HB-per-axis grid over the box gets its index
+// along the Hilbert curve of that grid.  The index is computed by Skilling's
+// transpose method (J. Skilling, "Programming the Hilbert curve", AIP Conf.
+// Proc. 707, 381, 2004): the cell coordinates are turned into the curve's
+// "transposed" index (undo the rotations level by level, then Gray-encode),
+// whose bits, interleaved, are the index.  Consecutive cells along the curve
+// share a face, and the top 3k bits of the index are the index of the
+// enclosing cell of the 2^k grid, so a counting sort on a prefix followed by a
+// sort inside each bin orders by the whole index.
+constexpr int HB = 10;                     // bits per axis of the fine grid
+constexpr int HB_BIN = 7;                  // bits per axis of the counting-sort bins
+constexpr int HB_SHIFT = 3 * (HB - HB_BIN);
+
 __device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
   v &= 0x3ff;
   v = (v | (v << 16)) & 0x030000FF;
@@ -420,17 +433,44 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every t
   return v;
 }
 
+__device__ __forceinline__ uint32_t hilbert_index(uint32_t x, uint32_t y, uint32_t z) {
+  uint32_t X[3] = {x, y, z};
+  for (uint32_t q = 1u << (HB - 1); q > 1; q >>= 1) {
+    const uint32_t low = q - 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (X[a] & q) {
+        X[0] ^= low;  // reflect the low bits
+      } else {        // swap the low bits of axis 0 and axis a
+        const uint32_t t = (X[0] ^ X[a]) & low;
+        X[0] ^= t;
+        X[a] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t q = 1u << (HB - 1); q > 1; q >>= 1)
+    if (X[2] & q) t ^= q - 1;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  return (spread3(X[0]) << 2) | (spread3(X[1]) << 1) | spread3(X[2]);
+}
+
+// key = the full Hilbert index; the bin counted is its top 3 HB_BIN bits.
 __global__ void __launch_bounds__(NB_THREADS)
-    k_morton_key(int n, const double* __restrict__ pos, Grid g, int32_t* __restrict__ key,
-                 int32_t* __restrict__ count) {
+    k_hilbert_key(int n, const double* __restrict__ pos, Grid g, int32_t* __restrict__ key,
+                  int32_t* __restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint32_t cx = cell_of(pos[i], g.inv_h[0], g.nc[0]);
   const uint32_t cy = cell_of(pos[(int64_t)n + i], g.inv_h[1], g.nc[1]);
   const uint32_t cz = cell_of(pos[2 * (int64_t)n + i], g.inv_h[2], g.nc[2]);
-  const int k = (int)(spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2));
+  const int k = (int)hilbert_index(cx, cy, cz);
   key[i] = k;
-  atomicAdd(&count[k], 1);
+  atomicAdd(&count[k >> HB_SHIFT], 1);
 }
 
 __global__ void __launch_bounds__(NB_THREADS)
@@ -438,21 +478,27 @@ __global__ void __launch_bounds__(NB_THREADS)
                   int32_t* __restrict__ cursor, int32_t* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int k = key[i];
+  const int k = key[i] >> HB_SHIFT;
   out[start[k] + atomicAdd(&cursor[k], 1)] = i;
 }
 
-// Sort the members of each bin ascending (bins hold a handful of entries).
+// Sort the members of each bin by (key, index) (bins hold a handful of
+// entries).
 __global__ void __launch_bounds__(NB_THREADS)
-    k_bin_sort_small(int nbins, const int32_t* __restrict__ start, int32_t* __restrict__ v) {
+    k_bin_sort_small(int nbins, const int32_t* __restrict__ start, const int32_t* __restrict__ key,
+                     int32_t* __restrict__ v) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
   const int s0 = start[b], s1 = start[b + 1];
   for (int k = s0 + 1; k < s1; ++k) {  // insertion sort
     const int32_t x = v[k];
+    const int32_t kx = key[x];
     int u = k - 1;
-    while (u >= s0 && v[u] > x) {
-      v[u + 1] = v[u];
+    while (u >= s0) {
+      const int32_t y = v[u];
+      const int32_t ky = key[y];
+      if (ky < kx || (ky == kx && y < x)) break;
+      v[u + 1] = y;
       --u;
     }
     v[u + 1] = x;
@@ -567,13 +613,19 @@ hipError_t launch_transpose(hipStream_t s, int n, int64_t nnz, const int64_t* of
   return hipGetLastError();
 }
 
-hipError_t launch_morton_order(hipStream_t s, int n, const double* pos, const Grid& g,
-                               int32_t* key, int32_t* bin_count, int32_t* bin_start,
-                               int32_t* scan_tmp, int32_t* perm) {
-  const int nbins = g.nc[0] * g.nc[1] * g.nc[2];  // a power of two cube
+hipError_t launch_hilbert_order(hipStream_t s, int n, const double* pos, const double* L,
+                                int32_t* key, int32_t* bin_count, int32_t* bin_start,
+                                int32_t* scan_tmp, int32_t* perm) {
+  Grid g;
+  for (int a = 0; a < 3; ++a) {
+    g.nc[a] = 1 << HB;
+    g.inv_h[a] = g.nc[a] / L[a];
+  }
+  g.margin = 0.0;
+  const int nbins = 1 << (3 * HB_BIN);
   hipError_t e = fill_i32(s, bin_count, 0, nbins);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_morton_key, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, pos,
+  hipLaunchKernelGGL(k_hilbert_key, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, pos,
                      g, key, bin_count);
   e = exclusive_scan_i32_to_i32(s, bin_count, nbins, bin_start, scan_tmp);
   if (e != hipSuccess) return e;
@@ -582,7 +634,7 @@ hipError_t launch_morton_order(hipStream_t s, int n, const double* pos, const Gr
   hipLaunchKernelGGL(k_bin_scatter, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, key,
                      bin_start, bin_count, perm);
   hipLaunchKernelGGL(k_bin_sort_small, dim3(grid_for(nbins, NB_THREADS)), dim3(NB_THREADS), 0, s,
-                     nbins, bin_start, perm);
+                     nbins, bin_start, key, perm);
   return hipGetLastError();
 }
 

@@ -44,9 +44,12 @@ hipError_t launch_row_sort(hipStream_t s, int64_t nrows, const int64_t* off, con
 hipError_t launch_transpose(hipStream_t s, int n, int64_t nnz, const int64_t* off,
                             const int32_t* idx, int64_t* toff, int32_t* tsrc, int32_t* tpos,
                             int32_t* count, int64_t* scan_tmp, int32_t* tmp);
-hipError_t launch_morton_order(hipStream_t s, int n, const double* pos, const Grid& g,
-                               int32_t* key, int32_t* bin_count, int32_t* bin_start,
-                               int32_t* scan_tmp, int32_t* perm);
+// perm = the particles in the order of their cells' Hilbert indices on a
+// 1024^3 grid over the box of side lengths L (ties by index).  bin_count and
+// bin_start hold 2^21 + 1 entries, scan_tmp scan_tmp_elems(2^21).
+hipError_t launch_hilbert_order(hipStream_t s, int n, const double* pos, const double* L,
+                                int32_t* key, int32_t* bin_count, int32_t* bin_start,
+                                int32_t* scan_tmp, int32_t* perm);
 hipError_t launch_permute(hipStream_t s, int n, int ncomp, const int32_t* perm, const double* src,
                           double* dst);
 

@@ -148,3 +148,24 @@ def test_spatial_order_is_a_permutation_and_local():
     src = dev(c["q"])
     got = P.permute(dev(perm.astype(np.int32)), src).cpu().numpy()
     assert np.array_equal(got, c["q"][:, perm])
+
+
+@pytest.mark.parametrize("L", [(1.0, 1.0, 1.0), (1.0, 0.8, 1.1)])
+def test_spatial_order_walks_a_lattice_by_face_steps(L):
+    """On a 16^3 lattice of cell centres (shuffled) the order is a Hilbert
+    walk: it starts at the corner cell and every step moves to a lattice
+    neighbour sharing a face (a Morton order jumps)."""
+    side = 16
+    g = np.stack(np.meshgrid(*[np.arange(side)] * 3, indexing="ij")).reshape(3, -1)
+    shuffle = np.random.default_rng(11).permutation(g.shape[1])
+    g = g[:, shuffle]
+    Ls = np.array(L)[:, None]
+    pos = (g + 0.5) / side * Ls
+    lam = np.full(g.shape[1], 1.0 / side)
+    s = P.Setup(L=L, periodic=(1, 1, 1))
+    perm = P.spatial_order(dev(pos), dev(lam), s).cpu().numpy()
+    assert np.array_equal(np.sort(perm), np.arange(g.shape[1]))
+    walk = g[:, perm]
+    assert np.array_equal(walk[:, 0], [0, 0, 0])
+    step = np.abs(np.diff(walk, axis=1))
+    assert np.all(step.sum(0) == 1)
