@@ -17,9 +17,27 @@ __device__ __forceinline__ void sfor(F&& f) {
   }
 }
 
+// 1 / sqrt(d) for d > 0 (normal): the hardware estimate, then two Newton
+// steps r <- r + (r / 2)(1 - d r^2).  Each step squares the relative error, so
+// the result is within a few units in the last place.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double r = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * r, r, 1.0);
+    r = fma(0.5 * r, e, r);
+  }
+  return r;
+}
+
+// Pivots and diagonal entries at or below this are treated as non-positive.
+constexpr double CHOL_TINY = 1e-280;
+
 // Row rho of a lane lives at a[aoff(rho) .. aoff(rho) + 4 rho + 3]: the
-// longest row any lane can own among rows 4 rho .. 4 rho + 3.  Entries right
-// of a lane's own diagonal hold scratch values that are never read.
+// longest row any lane can own among rows 4 rho .. 4 rho + 3.  Once the
+// factorization is done, the entries on and right of a lane's own diagonal
+// are zero (the diagonal's reciprocal is kept in inv_own), so the solves can
+// apply every entry of a column without asking which lane owns the pivot.
 __host__ __device__ constexpr int chol_aoff(int rho) { return 2 * rho * (rho + 1); }
 
 struct EntryTab {
@@ -71,8 +89,8 @@ __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& ta
   c.ok = true;
   sfor<0, 5>([&](auto R) {
     constexpr int rho = R;
-    c.ok = c.ok && (dg[rho] > 0.0);
-    c.s_own[rho] = dg[rho] > 0.0 ? 1.0 / sqrt(dg[rho]) : 1.0;
+    c.ok = c.ok && (dg[rho] > CHOL_TINY);
+    c.s_own[rho] = rsqrt_nr(dg[rho] > CHOL_TINY ? dg[rho] : 1.0);
   });
   c.ok = quad_min(c.ok ? 1.0 : 0.0) > 0.5;  // the same verdict on all four lanes
   {
@@ -96,11 +114,12 @@ __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& ta
     constexpr int o = k & 3;
     constexpr int rk = k >> 2;
     const double dkk = quad_bcast<o>(c.a[chol_aoff(rk) + k]);
-    c.ok = c.ok && (dkk > 0.0);
-    const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0);
+    c.ok = c.ok && (dkk > CHOL_TINY);
+    const double dpos = dkk > CHOL_TINY ? dkk : 1.0;
+    const double inv = rsqrt_nr(dpos);
+    const double lkk = dpos * inv;
     c.ldmin = fmin(c.ldmin, lkk);
     c.ldmax = fmax(c.ldmax, lkk);
-    const double inv = 1.0 / lkk;
     c.inv_own[rk] = (l == o) ? inv : c.inv_own[rk];
     sfor<rk, 5>([&](auto R) {
       constexpr int rho = R;
@@ -117,6 +136,14 @@ __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& ta
         constexpr int cc = C;
         c.a[chol_aoff(rho) + cc] = fma(-c.a[chol_aoff(rho) + k], colk[cc], c.a[chol_aoff(rho) + cc]);
       });
+    });
+  });
+  // row 4 rho + l keeps columns < 4 rho + l only
+  sfor<0, 5>([&](auto R) {
+    constexpr int rho = R;
+    sfor<0, 4>([&](auto C) {
+      constexpr int cc = C;
+      if (l <= cc) c.a[chol_aoff(rho) + 4 * rho + cc] = 0.0;
     });
   });
 }
@@ -149,8 +176,8 @@ __device__ __forceinline__ void quad_chol_solve(const QuadChol& c, int l, double
       constexpr int rho = R;
       y[rho] = fma(-c.a[chol_aoff(rho) + k], yk, y[rho]);
     });
-    const double upd = fma(-c.a[chol_aoff(rk) + k], yk, y[rk]);
-    y[rk] = (l == o) ? yk : ((l > o) ? upd : y[rk]);
+    const double upd = fma(-c.a[chol_aoff(rk) + k], yk, y[rk]);  // no change for l < o
+    y[rk] = (l == o) ? yk : upd;
   });
   sfor<0, 5>([&](auto R) { x[R] = y[R]; });
   sfor<0, NBASIS>([&](auto KK) {
@@ -158,11 +185,10 @@ __device__ __forceinline__ void quad_chol_solve(const QuadChol& c, int l, double
     constexpr int o = k & 3;
     constexpr int rk = k >> 2;
     double part = 0.0;
-    sfor<rk + 1, 5>([&](auto R) {
+    sfor<rk, 5>([&](auto R) {  // row block rk adds zeros on lanes l <= o
       constexpr int rho = R;
       part = fma(c.a[chol_aoff(rho) + k], x[rho], part);
     });
-    part += (l > o) ? c.a[chol_aoff(rk) + k] * x[rk] : 0.0;
     part = group_sum<4>(part);
     const double xk = (y[rk] - part) * c.inv_own[rk];  // valid on the owner lane
     x[rk] = (l == o) ? xk : x[rk];
@@ -203,8 +229,8 @@ __device__ __forceinline__ void quad_chol_solve_n(const QuadChol& c, int l, doub
     });
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double upd = fma(-c.a[chol_aoff(rk) + k], yk[r], y[r][rk]);
-      y[r][rk] = (l == o) ? yk[r] : ((l > o) ? upd : y[r][rk]);
+      const double upd = fma(-c.a[chol_aoff(rk) + k], yk[r], y[r][rk]);  // no change for l < o
+      y[r][rk] = (l == o) ? yk[r] : upd;
     }
   });
 #pragma unroll
@@ -218,14 +244,13 @@ __device__ __forceinline__ void quad_chol_solve_n(const QuadChol& c, int l, doub
     double part[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) part[r] = 0.0;
-    sfor<rk + 1, 5>([&](auto R) {
+    sfor<rk, 5>([&](auto R) {  // row block rk adds zeros on lanes l <= o
       constexpr int rho = R;
 #pragma unroll
       for (int r = 0; r < NR; ++r) part[r] = fma(c.a[chol_aoff(rho) + k], x[r][rho], part[r]);
     });
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      part[r] += (l > o) ? c.a[chol_aoff(rk) + k] * x[r][rk] : 0.0;
       part[r] = group_sum<4>(part[r]);
       const double xk = (y[r][rk] - part[r]) * c.inv_own[rk];  // valid on the owner lane
       x[r][rk] = (l == o) ? xk : x[r][rk];

@@ -73,6 +73,17 @@ __device__ __forceinline__ void accumulate_moments(T (&m)[NMOM], T w, T x, T y, 
   }
 }
 
+// Widens an FP32 value to FP64 through a register copy.  Without the copy
+// the register allocator places every float that is widened at the end of a
+// loop in the low half of an aligned pair (the widening's destination), so an
+// array of FP32 accumulators occupies twice its registers.
+__device__ __forceinline__ double widen(float v) {
+  float c;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(c) : "v"(v));
+  return (double)c;
+}
+__device__ __forceinline__ double widen(double v) { return v; }
+
 // The 20 basis monomials at (x, y, z).
 template <class T>
 __device__ __forceinline__ void basis(T (&p)[NBASIS], T x, T y, T z) {

@@ -125,12 +125,12 @@ __global__ void __launch_bounds__(THREADS)
   }
   if (has0) {
 #pragma unroll
-    for (int b = 0; b < NBASIS; ++b) bout[((int64_t)l * NBASIS + b) * n + i] = (double)acc0[b];
+    for (int b = 0; b < NBASIS; ++b) bout[((int64_t)l * NBASIS + b) * n + i] = widen(acc0[b]);
   }
   if (has1) {
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b)
-      bout[((int64_t)(l + 4) * NBASIS + b) * n + i] = (double)acc1[b];
+      bout[((int64_t)(l + 4) * NBASIS + b) * n + i] = widen(acc1[b]);
   }
 }
 

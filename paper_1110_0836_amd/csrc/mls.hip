@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(THREADS)
   if (valid) {
 #pragma unroll
     for (int k = 0; k < NMOM; ++k)
-      if (k % G == l) mom[(int64_t)k * n + i] = (double)m[k];
+      if (k % G == l) mom[(int64_t)k * n + i] = widen(m[k]);
   }
 }
 
@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
   for (int f = 0; f < FCHUNK; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) sum[f][t] = group_sum<G>(double(acc[f][t]));
+    for (int t = 0; t < 3; ++t) sum[f][t] = group_sum<G>(widen(acc[f][t]));
   if (valid && l == 0) {
     const double scale = power == 1 ? inv_lam : inv_lam * inv_lam;
     const double cf[3] = {c0, c1, c2};
@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) grad[f][t] = group_sum<G>(double(acc[f][t])) * inv_lam;
+    for (int t = 0; t < 3; ++t) grad[f][t] = group_sum<G>(widen(acc[f][t])) * inv_lam;
   double gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
   if constexpr (STAB) {
     const double il2 = inv_lam * inv_lam;
