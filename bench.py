@@ -325,7 +325,7 @@ def main():
              "updates_per_s": n / (ms_step / 1e3), "forward_ms": fwd_ms,
              "forward_updates_per_s": n / (fwd_ms / 1e3),
              "failed_particles": int((st != 0).sum().item()), "knobs": knobs,
-             "_rhs": rhs.clone(), "_grads": tape[:21 * n].view(7, 3, n).clone(),
+             "_rhs": rhs.clone(), "_grads": P.tape_rows(tape, n)[:21].reshape(7, 3, n).clone(),
              "_qbar": q_bar.clone(), "_pbar": pos_bar.clone()}
         log(f"[{form}] {ms_step:.3f} ms/step, forward {fwd_ms:.3f} ms")
         if not args.no_profile:

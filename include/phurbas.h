@@ -181,8 +181,11 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* p
  *   drho/dt = -rho div V ; dV/dt = (-(gamma-1) grad sigma + (curl B) x B) / rho ;
  *   dB/dt = (B . grad) V - B div V ; dsigma/dt = -gamma sigma div V ;
  * dxdt[3][n] = V.  status int32[n].  tape: NULL or a device buffer of
- * phb_tape_bytes(n) bytes that keeps what the reverse-mode call reuses.
- * Asynchronous. */
+ * phb_tape_bytes(n) bytes that keeps what the reverse-mode call reuses:
+ * 115 rows of ld = phb_tape_bytes(n) / 920 doubles each (ld >= n, padded so
+ * that the row stride is not a power of two), particle i at [row][i]; rows
+ * 0..20 the gradients of V, B, sigma (3 each), 21 the status, 31..114 the
+ * 84 FP64 moments.  Asynchronous. */
 int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                 const double* lambda, const int64_t* offsets, const int32_t* idx,
                 const double* q, double* rhs, double* dxdt, int32_t* status, void* tape);

@@ -261,6 +261,16 @@ def phb_tape_bytes(n):
     return lib().phb_tape_bytes(n)
 
 
+TAPE_ROWS = 31 + 84  # per-particle quantities a tape holds
+
+
+def tape_rows(tape, n):
+    """The tape's (TAPE_ROWS, n) rows as a view: the library pads each row to
+    phb_tape_bytes(n) / 8 / TAPE_ROWS entries."""
+    ld = phb_tape_bytes(n) // 8 // TAPE_ROWS
+    return tape.view(TAPE_ROWS, ld)[:, :n]
+
+
 def phb_mhd_rhs_adjoint(setup, pos, lam, offsets, idx, t_offsets, t_src, t_pos, q, rhs_bar,
                         dxdt_bar, q_bar, pos_bar, tape=None):
     ctx = context(pos.device.index)

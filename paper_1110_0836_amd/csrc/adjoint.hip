@@ -82,7 +82,7 @@ __device__ __forceinline__ void pointwise_adjoint(int n, int i, const double* __
 #pragma unroll
   for (int f = 0; f < 7; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) grad[f][t] = tape[((int64_t)f * 3 + t) * n + i];
+    for (int t = 0; t < 3; ++t) grad[f][t] = tape[((int64_t)f * 3 + t) * soa_ld(n) + i];
 #pragma unroll
   for (int f = 0; f < 8; ++f) ob[f] = rhs_bar[(int64_t)f * n + i];
   double gb[7][3];
@@ -121,12 +121,12 @@ __device__ __forceinline__ void pointwise_adjoint_stab(int n, int i, const doubl
 #pragma unroll
   for (int f = 0; f < 7; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) grad[f][t] = tape[((int64_t)f * 3 + t) * n + i];
+    for (int t = 0; t < 3; ++t) grad[f][t] = tape[((int64_t)f * 3 + t) * soa_ld(n) + i];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    grho[a] = tape[(int64_t)(TAPE_GRHO + a) * n + i];
-    gdv[a] = tape[(int64_t)(TAPE_GDV + a) * n + i];
-    gdb[a] = tape[(int64_t)(TAPE_GDB + a) * n + i];
+    grho[a] = tape[(int64_t)(TAPE_GRHO + a) * soa_ld(n) + i];
+    gdv[a] = tape[(int64_t)(TAPE_GDV + a) * soa_ld(n) + i];
+    gdb[a] = tape[(int64_t)(TAPE_GDB + a) * soa_ld(n) + i];
   }
 #pragma unroll
   for (int f = 0; f < 8; ++f) ob[f] = rhs_bar[(int64_t)f * n + i];
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(THREADS)
   const int ii = valid ? i : n - 1;
   const double4 gi = geo[ii];
   const double inv_lam = 1.0 / gi.w;
-  const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
+  const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii];
   // Ubar (21 doubles) waits in LDS during the neighbor loop instead of in
   // every lane's registers; ush[k][pl] holds entries 2k, 2k+1.
   constexpr int PPB = THREADS / G;
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(THREADS)
     for (int t = 0; t < 3; ++t)
 #pragma unroll
       for (int b = 0; b < NBASIS; ++b)
-        if ((t * NBASIS + b) % G == l) ybuf[((int64_t)t * NBASIS + b) * n + i] = y[t][b];
+        if ((t * NBASIS + b) % G == l) ybuf[((int64_t)t * NBASIS + b) * soa_ld(n) + i] = y[t][b];
   }
 }
 
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(THREADS)
             double* __restrict__ orec, double* __restrict__ qb_direct) {
   const int i = blockIdx.x * THREADS + threadIdx.x;
   if (i >= n) return;
-  const int st = (int)tape[(int64_t)TAPE_STATUS * n + i];
+  const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + i];
   double qi[8], ub[8][9], qb[8];
   pointwise_adjoint_stab(n, i, q, tape, rhs_bar, dxdt_bar, gamma, geo[i].w, sb, st, qi, ub, qb);
 #pragma unroll
@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(THREADS)
   const int ii = valid ? i : n - 1;
   const double4 gi = geo[ii];
   const double inv_lam = 1.0 / gi.w;
-  const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
+  const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii];
   // Ubar rows r0..r0+2 of the eight fields (24 values) in LDS
   constexpr int PPB = THREADS / G;
   __shared__ double2 ush[12][PPB];
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(THREADS)
     for (int t = 0; t < 3; ++t)
 #pragma unroll
       for (int b = 0; b < NBASIS; ++b)
-        if ((t * NBASIS + b) % G == l) ybuf[((int64_t)(r0 + t) * NBASIS + b) * n + i] = y[t][b];
+        if ((t * NBASIS + b) % G == l) ybuf[((int64_t)(r0 + t) * NBASIS + b) * soa_ld(n) + i] = y[t][b];
   }
 }
 
@@ -405,8 +405,8 @@ __global__ void __launch_bounds__(THREADS)
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   QuadChol c;
-  quad_chol_factor(c, c_tab_a, mom, n, ii, l, interp != 0);
-  const int st = (int)tape[(int64_t)TAPE_STATUS * n + ii];
+  quad_chol_factor(c, c_tab_a, mom, soa_ld(n), ii, l, interp != 0);
+  const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii];
   // G rows at 0 and K rows at KOFF of the owner record, in lockstep groups of
   // three solves
   sfor<0, SH::NR / 3>([&](auto GI) {
@@ -429,7 +429,7 @@ __global__ void __launch_bounds__(THREADS)
     for (int rh = 0; rh < 3; ++rh)
 #pragma unroll
       for (int rho = 0; rho < 5; ++rho)
-        y[rh][rho] = ybuf[((int64_t)(g0 + rh) * NBASIS + 4 * rho + l) * n + ii] * c.s_own[rho];
+        y[rh][rho] = ybuf[((int64_t)(g0 + rh) * NBASIS + 4 * rho + l) * soa_ld(n) + ii] * c.s_own[rho];
     // interpolating fit: Y's constant entry belongs to no basis function
     if (interp && l == 0)
 #pragma unroll
@@ -935,10 +935,11 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   }
   Workspace ws(ctx);
   const size_t nd = (size_t)n * sizeof(double);
+  const size_t ndl = (size_t)soa_ld(n) * sizeof(double);  // the padded stride's rows
   const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
   ws.plan((size_t)n * sizeof(double4));  // packed geometry
   ws.plan(8 * nd);                       // packed fields
-  ws.plan((size_t)NRr * NBASIS * nd);    // Y
+  ws.plan((size_t)NRr * NBASIS * ndl);   // Y
   ws.plan((size_t)ORr * nd);             // owner records: G, K, Ubar
   ws.plan(8 * nd);                       // direct qbar
   ws.plan((size_t)RCr * nd);             // own sums
@@ -947,8 +948,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
   const bool need_tape = tape_in == nullptr;
   if (need_tape) {
-    ws.plan((size_t)TAPE_DOUBLES * nd);  // tape (gradients, status, moments)
-    ws.plan((size_t)NRr * NBASIS * nd);  // forward operator
+    ws.plan((size_t)TAPE_DOUBLES * ndl);  // tape (gradients, status, moments)
+    ws.plan((size_t)NRr * NBASIS * ndl);  // forward operator
     ws.plan(8 * nd);                     // rhs scratch
     ws.plan(3 * nd);                     // dxdt scratch
     ws.plan((size_t)n * sizeof(int32_t));
@@ -960,7 +961,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   if ((rc = ws.commit())) return rc;
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
-  double* ybuf = ws.take<double>((size_t)NRr * NBASIS * n);
+  double* ybuf = ws.take<double>((size_t)NRr * NBASIS * soa_ld(n));
   double* orec = ws.take<double>((size_t)ORr * n);
   double* qbd = ws.take<double>((size_t)8 * n);
   double* own = ws.take<double>((size_t)RCr * n);
@@ -976,12 +977,12 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   { Prof pf(ctx, "k_pack");
   if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
   if (need_tape) {  // run the forward pass to fill a private tape
-    double* tp = ws.take<double>((size_t)TAPE_DOUBLES * n);
-    double* fg = ws.take<double>((size_t)NRr * NBASIS * n);
+    double* tp = ws.take<double>((size_t)TAPE_DOUBLES * soa_ld(n));
+    double* fg = ws.take<double>((size_t)NRr * NBASIS * soa_ld(n));
     double* rs = ws.take<double>((size_t)8 * n);
     double* dx = ws.take<double>((size_t)3 * n);
     int32_t* st = ws.take<int32_t>(n);
-    double* tmom = tp + (size_t)TAPE_MOM * n;
+    double* tmom = tp + (size_t)TAPE_MOM * soa_ld(n);
     if ((rc = hip_check(ctx, launch_moments(s, ap, ctx->lanes_assemble, tmom), "moments")))
       return rc;
     if ((rc = hip_check(ctx, launch_factor(s, ap, NRr, tmom, fg, st), "adjoint factor")))
@@ -993,7 +994,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
       return rc;
     tape = tp;
   }
-  const double* mom = tape + (size_t)TAPE_MOM * n;
+  const double* mom = tape + (size_t)TAPE_MOM * soa_ld(n);
   const int interp = a.fit == PHB_FIT_INTERP19;
   if (stab) {
     { Prof pf(ctx, "k_adj_u");

@@ -229,8 +229,8 @@ size_t ws_bytes_derivs(int64_t n, const phb_params* p, bool second) {
   if (p->precision == PHB_MIXED) return mixed_derivs_bytes(n, second);
   phb_ctx dummy;
   Workspace ws(&dummy);
-  ws.plan((size_t)NMOM * n * sizeof(double));
-  ws.plan((size_t)9 * NBASIS * n * sizeof(double));
+  ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
+  ws.plan((size_t)9 * NBASIS * soa_ld(n) * sizeof(double));
   ws.plan((size_t)n * sizeof(double4));
   return ws.total;
 }
@@ -248,8 +248,8 @@ static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, boo
     ws.plan(mixed_rhs_bytes(n, stab));
     return;
   }
-  ws.plan((size_t)NMOM * n * sizeof(double));
-  ws.plan((size_t)(stab ? 9 : 3) * NBASIS * n * sizeof(double));
+  ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
+  ws.plan((size_t)(stab ? 9 : 3) * NBASIS * soa_ld(n) * sizeof(double));
   ws.plan((size_t)n_all * sizeof(double4));
   ws.plan((size_t)n_all * 8 * sizeof(double));
 }
@@ -270,12 +270,12 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   Workspace ws(ctx);
   plan_rhs(ws, n, na, PHB_FP64, sb.on());
   if ((rc = ws.commit())) return rc;
-  double* mom = ws.take<double>((size_t)NMOM * n);
-  double* gop = ws.take<double>((size_t)nrows * NBASIS * n);
+  double* mom = ws.take<double>((size_t)NMOM * soa_ld(n));
+  double* gop = ws.take<double>((size_t)nrows * NBASIS * soa_ld(n));
   double4* geo = ws.take<double4>(na);
   double* fq = ws.take<double>((size_t)8 * na);
   // with a tape, the moments go straight into it for the reverse mode
-  if (tape) mom = tape + (size_t)TAPE_MOM * n;
+  if (tape) mom = tape + (size_t)TAPE_MOM * soa_ld(n);
   a.geo = geo;
   a.fq = fq;
   { Prof pf(ctx, "k_pack");
@@ -455,7 +455,9 @@ int phb_tune_get(phb_ctx* ctx, const char* key, int* value) {
   return PHB_OK;
 }
 
-int64_t phb_tape_bytes(int64_t n) { return n <= 0 ? 0 : n * TAPE_DOUBLES * (int64_t)sizeof(double); }
+int64_t phb_tape_bytes(int64_t n) {
+  return n <= 0 ? 0 : soa_ld(n) * TAPE_DOUBLES * (int64_t)sizeof(double);
+}
 
 }  // extern "C"
 
@@ -648,12 +650,12 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double*
     return mixed_derivs(ctx, a, nf, fields, d1, max_order == 2 ? d2 : nullptr, status);
   const int n = a.n;
   Workspace ws(ctx);
-  ws.plan((size_t)NMOM * n * sizeof(double));
-  ws.plan((size_t)9 * NBASIS * n * sizeof(double));
+  ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
+  ws.plan((size_t)9 * NBASIS * soa_ld(n) * sizeof(double));
   ws.plan((size_t)n * sizeof(double4));
   if ((rc = ws.commit())) return rc;
-  double* mom = ws.take<double>((size_t)NMOM * n);
-  double* gop = ws.take<double>((size_t)9 * NBASIS * n);
+  double* mom = ws.take<double>((size_t)NMOM * soa_ld(n));
+  double* gop = ws.take<double>((size_t)9 * NBASIS * soa_ld(n));
   double4* geo = ws.take<double4>(n);
   a.geo = geo;
   if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, pos, lambda, nullptr, geo, nullptr),

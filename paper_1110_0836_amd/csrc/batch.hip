@@ -331,7 +331,7 @@ int phb_tune(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
   int32_t* st = nullptr;
   hipError_t e = hipMalloc((void**)&rhs, (size_t)8 * n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&dxdt, (size_t)3 * n * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&tape, (size_t)TAPE_DOUBLES * n * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tape, (size_t)TAPE_DOUBLES * soa_ld(n) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&gbar, (size_t)8 * n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&qb, (size_t)8 * n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&pb, (size_t)3 * n * sizeof(double));

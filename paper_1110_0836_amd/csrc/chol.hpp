@@ -58,12 +58,12 @@ struct QuadChol {
   double ldmin, ldmax;
 };
 
-// Loads A from the moments (SoA [84][n]), equilibrates A_hat = S A S with
+// Loads A from the moments (SoA [84][ld]), equilibrates A_hat = S A S with
 // S = diag(1/sqrt(A_rr)) and factors A_hat = L L^T.  tab is the entry->moment
 // table in constant memory.  interp: the 19-monomial interpolating fit (the
 // constant's row and column replaced by the identity's).
 __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& tab,
-                                                 const double* __restrict__ mom, int64_t n,
+                                                 const double* __restrict__ mom, int64_t ld,
                                                  int ii, int l, bool interp = false) {
   double dg[5];
   sfor<0, 5>([&](auto R) {
@@ -71,9 +71,9 @@ __device__ __forceinline__ void quad_chol_factor(QuadChol& c, const EntryTab& ta
     const int r = 4 * rho + l;
     sfor<0, 4 * rho + 4>([&](auto C) {
       constexpr int cc = C;
-      c.a[chol_aoff(rho) + cc] = mom[(int64_t)tab.v[r * NBASIS + cc] * n + ii];
+      c.a[chol_aoff(rho) + cc] = mom[(int64_t)tab.v[r * NBASIS + cc] * ld + ii];
     });
-    dg[rho] = mom[(int64_t)tab.v[r * NBASIS + r] * n + ii];
+    dg[rho] = mom[(int64_t)tab.v[r * NBASIS + r] * ld + ii];
   });
   if (interp) {
     // interpolating fit: the constant monomial leaves the basis.  Its row and

@@ -40,6 +40,13 @@ __host__ __device__ constexpr int moment_index(int a, int b, int c) {
 constexpr int NMOM = 84;
 constexpr int NBASIS = 20;
 
+// Leading dimension of the library's own per-particle SoA arrays (workspace
+// and tape; callers' arrays keep n): n rounded up to 64, plus 104.  With a
+// power-of-two row stride (n = 2^20: 8 MiB) every row of an array falls on
+// the same HBM channels and the kernels that read or write many rows at once
+// (the factorizations) slow down by a fifth; the skew of 832 B spreads them.
+__host__ __device__ constexpr int64_t soa_ld(int64_t n) { return ((n + 63) / 64) * 64 + 104; }
+
 __host__ __device__ constexpr int entry_moment(int r, int s) {
   return moment_index(basis_expo(r).a + basis_expo(s).a, basis_expo(r).b + basis_expo(s).b,
                       basis_expo(r).c + basis_expo(s).c);

@@ -125,12 +125,12 @@ __global__ void __launch_bounds__(THREADS)
   }
   if (has0) {
 #pragma unroll
-    for (int b = 0; b < NBASIS; ++b) bout[((int64_t)l * NBASIS + b) * n + i] = widen(acc0[b]);
+    for (int b = 0; b < NBASIS; ++b) bout[((int64_t)l * NBASIS + b) * soa_ld(n) + i] = widen(acc0[b]);
   }
   if (has1) {
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b)
-      bout[((int64_t)(l + 4) * NBASIS + b) * n + i] = widen(acc1[b]);
+      bout[((int64_t)(l + 4) * NBASIS + b) * soa_ld(n) + i] = widen(acc1[b]);
   }
 }
 
@@ -154,7 +154,7 @@ __device__ __forceinline__ void mixed_factor_one(int n, int i, int l, const doub
                                                  int32_t* __restrict__ list_out,
                                                  int32_t* __restrict__ count, int interp) {
   QuadChol c;
-  quad_chol_factor(c, c_mtab, mom, n, i, l, interp != 0);
+  quad_chol_factor(c, c_mtab, mom, soa_ld(n), i, l, interp != 0);
   const int nnb = (int)(off[i + 1] - off[i]);
   const int st = quad_chol_status(c, nnb);
   if constexpr (!LISTED) {
@@ -171,13 +171,13 @@ __device__ __forceinline__ void mixed_factor_one(int n, int i, int l, const doub
       double b[5], x[5];
       sfor<0, 5>([&](auto R) {
         constexpr int rho = R;
-        b[rho] = bin[((int64_t)f * NBASIS + 4 * rho + l) * n + i];
+        b[rho] = bin[((int64_t)f * NBASIS + 4 * rho + l) * soa_ld(n) + i];
       });
       quad_chol_apply_inverse(c, l, b, x);
       if (interp && l == 0) x[0] = 0.0;  // no constant term: the residuals see p . c of 19
       sfor<0, 5>([&](auto R) {
         constexpr int rho = R;
-        cfit[((int64_t)f * NBASIS + 4 * rho + l) * n + i] = st == 0 ? x[rho] : 0.0;
+        cfit[((int64_t)f * NBASIS + 4 * rho + l) * soa_ld(n) + i] = st == 0 ? x[rho] : 0.0;
       });
     }
   }
@@ -187,7 +187,7 @@ __device__ __forceinline__ void mixed_factor_one(int n, int i, int l, const doub
     quad_chol_inverse_row<t>(c, l, row);
     sfor<0, 5>([&](auto R) {
       constexpr int rho = R;
-      gt[((int64_t)TI * NBASIS + 4 * rho + l) * n + i] = st == 0 ? row[rho] : 0.0;
+      gt[((int64_t)TI * NBASIS + 4 * rho + l) * soa_ld(n) + i] = st == 0 ? row[rho] : 0.0;
     });
   });
 }
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
     for (int q = 0; q < NMOM; ++q) {
       const double t = group_sum<4>(m[q]);
-      if ((q & 3) == l) mom[(int64_t)q * n + i] = t;
+      if ((q & 3) == l) mom[(int64_t)q * soa_ld(n) + i] = t;
     }
     for (int f0 = 0; f0 < nf; f0 += 4) {
       double fi[4];
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(THREADS)
         for (int b = 0; b < NBASIS; ++b) {
           const double t = group_sum<4>(acc[f][b]);
           if (f0 + f < nf && ((f * NBASIS + b) & 3) == l)
-            bout[((int64_t)(f0 + f) * NBASIS + b) * n + i] = t;
+            bout[((int64_t)(f0 + f) * NBASIS + b) * soa_ld(n) + i] = t;
         }
     }
   }
@@ -317,8 +317,8 @@ __global__ void __launch_bounds__(THREADS)
   float a0[NBASIS], a1[NBASIS];
 #pragma unroll
   for (int b = 0; b < NBASIS; ++b) {
-    csh[b][threadIdx.x] = make_float2((float)cfit[((int64_t)f0 * NBASIS + b) * n + i],
-                                      (float)cfit[((int64_t)f1 * NBASIS + b) * n + i]);
+    csh[b][threadIdx.x] = make_float2((float)cfit[((int64_t)f0 * NBASIS + b) * soa_ld(n) + i],
+                                      (float)cfit[((int64_t)f1 * NBASIS + b) * soa_ld(n) + i]);
     a0[b] = a1[b] = 0.f;
   }
   const bool refine = status[i] == 0 && flag[i] == 0;
@@ -363,16 +363,16 @@ __global__ void __launch_bounds__(THREADS)
   }
 #pragma unroll
   for (int t = 0; t < NG; ++t) {
-    double u0 = cfit[((int64_t)f0 * NBASIS + 1 + t) * n + i];
-    double u1 = cfit[((int64_t)f1 * NBASIS + 1 + t) * n + i];
+    double u0 = cfit[((int64_t)f0 * NBASIS + 1 + t) * soa_ld(n) + i];
+    double u1 = cfit[((int64_t)f1 * NBASIS + 1 + t) * soa_ld(n) + i];
 #pragma unroll
     for (int b = 0; b < NBASIS; ++b) {
-      const double g = gt[((int64_t)t * NBASIS + b) * n + i];
+      const double g = gt[((int64_t)t * NBASIS + b) * soa_ld(n) + i];
       u0 = fma(g, (double)a0[b], u0);
       u1 = fma(g, (double)a1[b], u1);
     }
-    if (has0) rows[((int64_t)f0 * NG + t) * n + i] = u0;
-    if (has1) rows[((int64_t)f1 * NG + t) * n + i] = u1;
+    if (has0) rows[((int64_t)f0 * NG + t) * soa_ld(n) + i] = u0;
+    if (has1) rows[((int64_t)f1 * NG + t) * soa_ld(n) + i] = u1;
   }
 }
 
@@ -413,8 +413,8 @@ __global__ void __launch_bounds__(THREADS)
   const int pl = threadIdx.x / G;
   for (int k = l; k < 3 * NBASIS / 2; k += G) {
     const int t = (2 * k) / NBASIS, b = (2 * k) % NBASIS;
-    gsh[k][pl] = make_double2(gt[((int64_t)(r0 + t) * NBASIS + b) * n + ii],
-                              gt[((int64_t)(r0 + t) * NBASIS + b + 1) * n + ii]);
+    gsh[k][pl] = make_double2(gt[((int64_t)(r0 + t) * NBASIS + b) * soa_ld(n) + ii],
+                              gt[((int64_t)(r0 + t) * NBASIS + b + 1) * soa_ld(n) + ii]);
   }
   __syncthreads();
   const double inv_lam = 1.0 / gi.w;
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(THREADS)
     for (int t = 0; t < 3; ++t)
 #pragma unroll
       for (int b = 0; b < NBASIS; ++b)
-        if ((t * NBASIS + b) % G == l) mbuf[((int64_t)(r0 + t) * NBASIS + b) * n + i] = m[t][b];
+        if ((t * NBASIS + b) % G == l) mbuf[((int64_t)(r0 + t) * NBASIS + b) * soa_ld(n) + i] = m[t][b];
   }
 }
 
@@ -481,7 +481,7 @@ __global__ void __launch_bounds__(THREADS)
   if (i >= n) return;  // whole quads leave together
   if (status[i] != 0 || flag[i] != 0) return;
   QuadChol c;
-  quad_chol_factor(c, c_mtab, mom, n, i, l, interp != 0);
+  quad_chol_factor(c, c_mtab, mom, soa_ld(n), i, l, interp != 0);
   sfor<0, NG / 3>([&](auto GI) {
     constexpr int t0 = 3 * GI;
     double y[3][5], x[3][5];
@@ -489,7 +489,7 @@ __global__ void __launch_bounds__(THREADS)
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int rho = 0; rho < 5; ++rho) {
-        const double b = mbuf[((int64_t)(t0 + r) * NBASIS + 4 * rho + l) * n + i];
+        const double b = mbuf[((int64_t)(t0 + r) * NBASIS + 4 * rho + l) * soa_ld(n) + i];
         y[r][rho] = (interp && rho == 0 && l == 0) ? 0.0 : b * c.s_own[rho];
       }
     quad_chol_solve_n<0, 3>(c, l, y, x);
@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(THREADS)
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int rho = 0; rho < 5; ++rho) {
-        const int64_t k = ((int64_t)(t0 + r) * NBASIS + 4 * rho + l) * n + i;
+        const int64_t k = ((int64_t)(t0 + r) * NBASIS + 4 * rho + l) * soa_ld(n) + i;
         gt[k] = fma(-x[r][rho], c.s_own[rho], 2.0 * gt[k]);
       }
   });
@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
   for (int f = 0; f < 7; ++f)
 #pragma unroll
-    for (int t = 0; t < 3; ++t) grad[f][t] = rows[((int64_t)(F0 + f) * NG + t) * n + i] * inv_lam;
+    for (int t = 0; t < 3; ++t) grad[f][t] = rows[((int64_t)(F0 + f) * NG + t) * soa_ld(n) + i] * inv_lam;
   const int st = status[i];
   double out[8];
   double grho[3] = {0.0, 0.0, 0.0}, gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
@@ -536,11 +536,11 @@ __global__ void __launch_bounds__(THREADS)
       // h[f][k]: second-derivative rows with the diagonal doubled
       const double il2 = inv_lam * inv_lam;
       auto h = [&](int f, int k) {
-        const double c = rows[((int64_t)f * NG + 3 + k) * n + i] * il2;
+        const double c = rows[((int64_t)f * NG + 3 + k) * soa_ld(n) + i] * il2;
         return (k == 0 || k == 3 || k == 5) ? 2.0 * c : c;
       };
 #pragma unroll
-      for (int a = 0; a < 3; ++a) grho[a] = rows[(int64_t)a * n + i] * inv_lam;
+      for (int a = 0; a < 3; ++a) grho[a] = rows[(int64_t)a * soa_ld(n) + i] * inv_lam;
       // d_a div X = sum_b d_a d_b X_b ; k(a,b): xx 0, xy 1, xz 2, yy 3, yz 4, zz 5
       gdv[0] = h(1, 0) + h(2, 1) + h(3, 2);
       gdv[1] = h(1, 1) + h(2, 3) + h(3, 4);
@@ -563,14 +563,14 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
     for (int f = 0; f < 7; ++f)
 #pragma unroll
-      for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + i] = grad[f][t];
-    tape[(int64_t)TAPE_STATUS * n + i] = (double)st;
+      for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * soa_ld(n) + i] = grad[f][t];
+    tape[(int64_t)TAPE_STATUS * soa_ld(n) + i] = (double)st;
     if constexpr (STAB) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        tape[(int64_t)(TAPE_GRHO + a) * n + i] = grho[a];
-        tape[(int64_t)(TAPE_GDV + a) * n + i] = gdv[a];
-        tape[(int64_t)(TAPE_GDB + a) * n + i] = gdb[a];
+        tape[(int64_t)(TAPE_GRHO + a) * soa_ld(n) + i] = grho[a];
+        tape[(int64_t)(TAPE_GDV + a) * soa_ld(n) + i] = gdv[a];
+        tape[(int64_t)(TAPE_GDB + a) * soa_ld(n) + i] = gdb[a];
       }
     }
   }
@@ -593,12 +593,12 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
     for (int t = 0; t < 3; ++t)
       d1[((int64_t)(f0 + f) * 3 + t) * n + i] =
-          ok ? rows[((int64_t)f * NG + t) * n + i] * inv_lam : nan;
+          ok ? rows[((int64_t)f * NG + t) * soa_ld(n) + i] * inv_lam : nan;
     if constexpr (NG == 9) {
 #pragma unroll
       for (int t = 0; t < 6; ++t)
         d2[((int64_t)(f0 + f) * 6 + t) * n + i] =
-            ok ? fac[t] * rows[((int64_t)f * NG + 3 + t) * n + i] * inv_lam * inv_lam : nan;
+            ok ? fac[t] * rows[((int64_t)f * NG + 3 + t) * soa_ld(n) + i] * inv_lam * inv_lam : nan;
     }
   }
 }
@@ -639,7 +639,7 @@ struct MixedBufs {
 };
 
 void plan_mixed(Workspace& ws, int64_t n, int nf, int ng) {
-  const size_t nd = (size_t)n * sizeof(double);
+  const size_t nd = (size_t)soa_ld(n) * sizeof(double);  // rows of the padded stride
   ws.plan(NMOM * nd);
   ws.plan((size_t)nf * NBASIS * nd);
   ws.plan((size_t)nf * NBASIS * nd);
@@ -652,11 +652,12 @@ void plan_mixed(Workspace& ws, int64_t n, int nf, int ng) {
 
 MixedBufs take_mixed(Workspace& ws, int64_t n, int nf, int ng) {
   MixedBufs m;
-  m.mom = ws.take<double>((size_t)NMOM * n);
-  m.b = ws.take<double>((size_t)nf * NBASIS * n);
-  m.cfit = ws.take<double>((size_t)nf * NBASIS * n);
-  m.gt = ws.take<double>((size_t)ng * NBASIS * n);
-  m.rows = ws.take<double>((size_t)nf * ng * n);
+  const size_t ld = soa_ld(n);
+  m.mom = ws.take<double>((size_t)NMOM * ld);
+  m.b = ws.take<double>((size_t)nf * NBASIS * ld);
+  m.cfit = ws.take<double>((size_t)nf * NBASIS * ld);
+  m.gt = ws.take<double>((size_t)ng * NBASIS * ld);
+  m.rows = ws.take<double>((size_t)nf * ng * ld);
   m.flag = ws.take<int32_t>(n);
   m.list = ws.take<int32_t>(n);
   m.count = ws.take<int32_t>(1);
@@ -710,7 +711,7 @@ struct OpBufs {
 };
 
 void plan_op(Workspace& ws, int64_t n, int ng) {
-  const size_t nd = (size_t)n * sizeof(double);
+  const size_t nd = (size_t)soa_ld(n) * sizeof(double);  // rows of the padded stride
   ws.plan(NMOM * nd);
   ws.plan((size_t)ng * NBASIS * nd);
   ws.plan((size_t)ng * NBASIS * nd);
@@ -721,9 +722,10 @@ void plan_op(Workspace& ws, int64_t n, int ng) {
 
 OpBufs take_op(Workspace& ws, int64_t n, int ng) {
   OpBufs m;
-  m.mom = ws.take<double>((size_t)NMOM * n);
-  m.gt = ws.take<double>((size_t)ng * NBASIS * n);
-  m.mb = ws.take<double>((size_t)ng * NBASIS * n);
+  const size_t ld = soa_ld(n);
+  m.mom = ws.take<double>((size_t)NMOM * ld);
+  m.gt = ws.take<double>((size_t)ng * NBASIS * ld);
+  m.mb = ws.take<double>((size_t)ng * NBASIS * ld);
   m.flag = ws.take<int32_t>(n);
   m.list = ws.take<int32_t>(n);
   m.count = ws.take<int32_t>(1);
@@ -790,7 +792,7 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
 int fork_tape_moments(phb_ctx* ctx, const EvalArgs& a, double* tape, bool& forked) {
   forked = false;
   if (!tape) return PHB_OK;
-  double* dst = tape + (size_t)TAPE_MOM * a.n;
+  double* dst = tape + (size_t)TAPE_MOM * soa_ld(a.n);
   if (ctx->prof_on) {
     Prof pf(ctx, "k_moments<tape>");
     return hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, dst),

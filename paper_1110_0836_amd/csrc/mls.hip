@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(THREADS)
   if (valid) {
 #pragma unroll
     for (int k = 0; k < NMOM; ++k)
-      if (k % G == l) mom[(int64_t)k * n + i] = widen(m[k]);
+      if (k % G == l) mom[(int64_t)k * soa_ld(n) + i] = widen(m[k]);
   }
 }
 
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(THREADS)
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   QuadChol c;
-  quad_chol_factor(c, c_tab, mom, n, ii, l, interp != 0);
+  quad_chol_factor(c, c_tab, mom, soa_ld(n), ii, l, interp != 0);
   const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
   // rows in lockstep groups of three
   sfor<0, NT / 3>([&](auto GI) {
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(THREADS)
       sfor<0, 3>([&](auto RI) {
         sfor<0, 5>([&](auto R) {
           constexpr int rho = R;
-          gop[((int64_t)(3 * GI + RI) * NBASIS + 4 * rho + l) * n + i] = rows[RI][rho];
+          gop[((int64_t)(3 * GI + RI) * NBASIS + 4 * rho + l) * soa_ld(n) + i] = rows[RI][rho];
         });
       });
     }
@@ -143,20 +143,20 @@ __global__ void __launch_bounds__(THREADS)
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
   QuadChol c;
-  quad_chol_factor(c, c_tab, mom, n, ii, l, interp != 0);
+  quad_chol_factor(c, c_tab, mom, soa_ld(n), ii, l, interp != 0);
   const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
   sfor<0, NR>([&](auto RI) {
     constexpr int r = RI;
     double b[5], out[5];
     sfor<0, 5>([&](auto R) {
       constexpr int rho = R;
-      b[rho] = rhs[((int64_t)r * NBASIS + 4 * rho + l) * n + ii];
+      b[rho] = rhs[((int64_t)r * NBASIS + 4 * rho + l) * soa_ld(n) + ii];
     });
     quad_chol_apply_inverse(c, l, b, out);
     if (valid) {
       sfor<0, 5>([&](auto R) {
         constexpr int rho = R;
-        x[((int64_t)r * NBASIS + 4 * rho + l) * n + i] = st == 0 ? out[rho] : 0.0;
+        x[((int64_t)r * NBASIS + 4 * rho + l) * soa_ld(n) + i] = st == 0 ? out[rho] : 0.0;
       });
     }
   });
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
   for (int t = 0; t < 3; ++t)
 #pragma unroll
-    for (int b = 0; b < NBASIS; ++b) g[t][b] = gop[((int64_t)(row0 + t) * NBASIS + b) * n + ii];
+    for (int b = 0; b < NBASIS; ++b) g[t][b] = gop[((int64_t)(row0 + t) * NBASIS + b) * soa_ld(n) + ii];
   const int nfc = (nf - f0) < FCHUNK ? (nf - f0) : FCHUNK;
   double fi[FCHUNK];
 #pragma unroll
@@ -319,8 +319,8 @@ __global__ void __launch_bounds__(THREADS)
   for (int k = l; k < NR * NBASIS / 2; k += G) {
     const int t = (2 * k) / NBASIS, b = (2 * k) % NBASIS;
     const double sc = (STAB && (t == 3 || t == 6 || t == 8)) ? 2.0 : 1.0;
-    gsh[k][pl] = make_double2(sc * gop[((int64_t)t * NBASIS + b) * n + ii],
-                              sc * gop[((int64_t)t * NBASIS + b + 1) * n + ii]);
+    gsh[k][pl] = make_double2(sc * gop[((int64_t)t * NBASIS + b) * soa_ld(n) + ii],
+                              sc * gop[((int64_t)t * NBASIS + b + 1) * soa_ld(n) + ii]);
   }
   __syncthreads();
   const double inv_lam = 1.0 / gi.w;
@@ -420,14 +420,14 @@ __global__ void __launch_bounds__(THREADS)
 #pragma unroll
       for (int f = 0; f < 7; ++f)
 #pragma unroll
-        for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * n + ii] = g7[f][t];
-      tape[(int64_t)TAPE_STATUS * n + ii] = (double)st;
+        for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * soa_ld(n) + ii] = g7[f][t];
+      tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii] = (double)st;
       if constexpr (STAB) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          tape[(int64_t)(TAPE_GRHO + a) * n + ii] = grad[0][a];
-          tape[(int64_t)(TAPE_GDV + a) * n + ii] = gdv[a];
-          tape[(int64_t)(TAPE_GDB + a) * n + ii] = gdb[a];
+          tape[(int64_t)(TAPE_GRHO + a) * soa_ld(n) + ii] = grad[0][a];
+          tape[(int64_t)(TAPE_GDV + a) * soa_ld(n) + ii] = gdv[a];
+          tape[(int64_t)(TAPE_GDB + a) * soa_ld(n) + ii] = gdb[a];
         }
       }
     }

@@ -226,8 +226,8 @@ def test_tape_holds_fp64_moments(stab):
     smx = setup_of(c, precision=P.PHB_MIXED, **stab)
     off, idx = P.neighbors(pos, lam, s64)
     n = c["lam"].shape[0]
-    t64 = P.mhd_rhs(pos, lam, off, idx, q, s64, tape=True)[3].cpu().numpy().reshape(-1, n)
-    tmx = P.mhd_rhs(pos, lam, off, idx, q, smx, tape=True)[3].cpu().numpy().reshape(-1, n)
+    t64 = P.tape_rows(P.mhd_rhs(pos, lam, off, idx, q, s64, tape=True)[3], n).cpu().numpy()
+    tmx = P.tape_rows(P.mhd_rhs(pos, lam, off, idx, q, smx, tape=True)[3], n).cpu().numpy()
     assert np.array_equal(tmx[-84:], t64[-84:])
     assert np.array_equal(tmx[21], t64[21])  # status
     assert 0 < np.abs(tmx[:21] - t64[:21]).max() < 1e-5 * np.abs(t64[:21]).max()

@@ -93,7 +93,7 @@ def rhs_both(c, rows=None, **kw):
     od1, _, _ = oracle.mls_derivs(c["pos"], c["lam"], ooff, oidx, c["q"], L=c["L"],
                                   periodic=c["periodic"], rows=rows, second=False,
                                   weight=kw.get("weight", 0))
-    grads = tape[:21 * n].view(7, 3, n).cpu().numpy()
+    grads = P.tape_rows(tape, n)[:21].reshape(7, 3, n).cpu().numpy()
     g = (rhs.cpu().numpy(), dxdt.cpu().numpy(), st.cpu().numpy(), grads)
     qs = c["q"]
     if rows is not None:
@@ -163,5 +163,5 @@ def test_tape_holds_gradients():
     rhs, dxdt, st, tape = P.mhd_rhs(pos, lam, off, idx, dev(c["q"]), s, tape=True)
     d1, _, _ = P.mls_derivs(pos, lam, off, idx, dev(c["q"][1:]), s, second=False)
     n = lam.shape[0]
-    assert np.allclose(tape[:21 * n].view(7, 3, n).cpu().numpy(), d1.cpu().numpy(), rtol=1e-13,
+    assert np.allclose(P.tape_rows(tape, n)[:21].reshape(7, 3, n).cpu().numpy(), d1.cpu().numpy(), rtol=1e-13,
                        atol=1e-20)
