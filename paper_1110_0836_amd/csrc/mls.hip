@@ -270,6 +270,7 @@ __global__ void __launch_bounds__(THREADS)
 // are FP32, and the lanes' partial sums meet in FP64.
 template <int G, bool STAB, class CT = double>
 __global__ void __launch_bounds__(THREADS)
+    __attribute__((amdgpu_waves_per_eu(!STAB && sizeof(CT) == 4 ? 4 : 1)))
     k_apply_rhs(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
                 const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
                 double rf_ratio, int wkind, double gamma, Stab sb, const double* __restrict__ gop,
