@@ -29,7 +29,7 @@ struct phb_ctx {
   std::string last_error;
   // Tunables (see phb_tune_* in the binding).
   int cells_per_rf = 2;      // neighbor grid cells per minimum r_f
-  int lanes_assemble = 1;    // lanes per particle in neighbor loops (1, 2, 4)
+  int lanes_assemble = 4;    // lanes per particle in the moment loops (1, 2, 4)
   int lanes_apply = 4;
   int lanes_adj_y = 2;
   int lanes_gather = 4;

@@ -85,8 +85,15 @@ __global__ void __launch_bounds__(THREADS)
     const double w = weight_of(qd, wkind);
     accumulate_moments(m, T(w), T(dx * inv_lam), T(dy * inv_lam), T(dz * inv_lam));
   }
+  // The lane sums retire one moment at a time: each next moment is tied to
+  // the previous sum, so the exchanged copies of all 84 moments are never
+  // live together (hoisted, they double the register footprint).
 #pragma unroll
-  for (int k = 0; k < NMOM; ++k) m[k] = group_sum<G>(m[k]);
+  for (int k = 0; k < NMOM; ++k) {
+    m[k] = group_sum<G>(m[k]);
+    if constexpr (G > 1)
+      if (k + 1 < NMOM) asm volatile("" : "+v"(m[k + 1]) : "v"(m[k]));
+  }
   if (valid) {
 #pragma unroll
     for (int k = 0; k < NMOM; ++k)
