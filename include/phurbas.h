@@ -80,6 +80,10 @@ extern "C" {
                               constant, so the fit passes through the particle's own
                               value; same status rules */
 
+/* Largest number of neighbor entries the reverse mode and the transposed
+ * lists handle: their positions (t_src, t_pos) are int32. */
+#define PHB_NNZ_MAX 2147483647LL
+
 #define PHB_STATUS_OK 0
 #define PHB_STATUS_TOO_FEW 1
 #define PHB_STATUS_SINGULAR 2
@@ -147,7 +151,8 @@ int phb_neighbors_build_rows(phb_ctx* ctx, const phb_params* p, int64_t n, const
 /* Transposed lists for the reverse-mode kernels: t_offsets int64[n+1],
  * t_src int32[nnz] (row j lists, ascending, every i whose row holds j),
  * t_pos int32[nnz] (for forward entry s = (i, j): the index into t_src at
- * which i appears in row j).  nnz = offsets[n].  Asynchronous. */
+ * which i appears in row j).  nnz = offsets[n].  PHB_EINVAL if nnz exceeds
+ * PHB_NNZ_MAX (the positions are int32).  Asynchronous. */
 int phb_neighbors_transpose(phb_ctx* ctx, int64_t n, int64_t nnz, const int64_t* offsets,
                             const int32_t* idx, int64_t* t_offsets, int32_t* t_src,
                             int32_t* t_pos);

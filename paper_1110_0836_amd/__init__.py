@@ -523,7 +523,8 @@ def evolve_blocks(pos, q, lam, dt_max, nblocks, cfl=0.3, kmax=20, setup=None, fr
 
 
 def courant_dt(q, lam, cfl=0.3, setup=None, frozen=None):
-    """Courant step cfl * min lambda / (|V| + c_fast) over non-frozen particles."""
+    """Courant step cfl * min lambda / c_fast over non-frozen particles: the fast
+    signal speed alone, so a uniform velocity shift leaves the step unchanged."""
     return phb_courant_dt(setup or Setup(), q, lam, frozen, cfl)
 
 

@@ -933,6 +933,9 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     hipHostFree(h);
     if ((rc = hip_check(ctx, e, "nnz read-back"))) return rc;
   }
+  // transposed positions and pair-record slots are int32
+  if (nnz > PHB_NNZ_MAX)
+    return set_error(ctx, PHB_EINVAL, "nnz exceeds the int32 positions of the transposed lists");
   Workspace ws(ctx);
   const size_t nd = (size_t)n * sizeof(double);
   const size_t ndl = (size_t)soa_ld(n) * sizeof(double);  // the padded stride's rows

@@ -579,6 +579,8 @@ int phb_neighbors_transpose(phb_ctx* ctx, int64_t n64, int64_t nnz, const int64_
   if ((rc = check_n(ctx, n64))) return rc;
   if (nnz < 0 || !offsets || !t_offsets || (nnz > 0 && (!idx || !t_src || !t_pos)))
     return set_error(ctx, PHB_EINVAL, "null pointer or negative nnz");
+  if (nnz > PHB_NNZ_MAX)
+    return set_error(ctx, PHB_EINVAL, "nnz exceeds the int32 positions of the transposed lists");
   hipSetDevice(ctx->device);
   const int n = (int)n64;
   Workspace ws(ctx);

@@ -202,6 +202,8 @@ int phb_batch_neighbors(phb_ctx* ctx, phb_batch* b, const double* pos, const dou
     base += got;
   }
   *nnz_out = base;
+  if (base > PHB_NNZ_MAX)
+    return set_error(ctx, PHB_EINVAL, "nnz exceeds the int32 positions of the transposed lists");
   if (short_cap)
     return set_error(ctx, PHB_ECAPACITY, "idx capacity " + std::to_string(idx_capacity) +
                                              " < " + std::to_string(base));

@@ -120,3 +120,24 @@ def test_zero_particles_are_rejected():
                              P._ptr(buf), P._ptr(buf), P._ptr(buf), P._ptr(buf), P._ptr(buf),
                              None)
     assert rc == P.PHB_EINVAL
+
+
+def test_transpose_rejects_nnz_beyond_int32_positions():
+    # the transposed positions are int32: a list of more than 2^31 - 1 entries
+    # is refused on the host, before any kernel reads the (small) buffers
+    off = torch.zeros(5, dtype=torch.int64, device="cuda")
+    idx = torch.zeros(4, dtype=torch.int32, device="cuda")
+    t_off = torch.empty_like(off)
+    t_src = torch.empty_like(idx)
+    t_pos = torch.empty_like(idx)
+    ctx = P.context()
+    lib = P.lib()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    rc = lib.phb_neighbors_transpose(ctx, 4, 1 << 31, p(off), p(idx), p(t_off), p(t_src),
+                                     p(t_pos))
+    assert rc == P.PHB_EINVAL
+    assert b"int32" in lib.phb_last_error(ctx)
+    # at the limit's edge the same call is accepted (an empty list here)
+    assert lib.phb_neighbors_transpose(ctx, 4, 0, p(off), p(idx), p(t_off), p(t_src),
+                                       p(t_pos)) == P.PHB_OK
+    torch.cuda.synchronize()

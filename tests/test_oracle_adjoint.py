@@ -120,3 +120,50 @@ def test_failed_particles_pass_no_gradient():
     g2[:, 5] = 0.0
     qb2, pb2, _ = oracle.mhd_rhs_adjoint(pos, lam, off, idx, q, g2)
     assert np.array_equal(qb, qb2) and np.array_equal(pb, pb2)
+
+
+def _restrict(off, idx, rows):
+    """The CSR lists of the given rows only, in that order."""
+    counts = np.array([off[r + 1] - off[r] for r in rows], np.int64)
+    roff = np.concatenate([[0], np.cumsum(counts)])
+    ridx = np.concatenate([idx[off[r]:off[r + 1]] for r in rows]).astype(np.int32)
+    return roff, ridx
+
+
+def test_rows_all_equals_full():
+    # every owner row listed in order: the same sums in the same order as the
+    # full reverse mode, so the results are equal bit for bit
+    pos, lam, q, gbar, xbar = _set(seed=49)
+    off, idx = oracle.neighbors(pos, lam)
+    qb, pb, _ = oracle.mhd_rhs_adjoint(pos, lam, off, idx, q, gbar, xbar)
+    rows = np.arange(lam.shape[0])
+    qr, pr = oracle.adjoint_rows(pos, lam, off, idx, q, gbar, rows, dxdt_bar=xbar)
+    assert np.array_equal(qr, qb) and np.array_equal(pr, pb)
+
+
+@pytest.mark.parametrize("stab", [None, (0.5, 0.5, 0.5)])
+def test_rows_partition_sums_to_full(stab):
+    # the reverse mode is a sum over owners: two disjoint row sets, listed in
+    # shuffled order with their own restricted lists, add up to the full
+    # gradient (an owner paired with another owner's list, or a neighbor entry
+    # indexed through the wrong row, breaks this)
+    pos, lam, q, gbar, xbar = _set(seed=50)
+    n = lam.shape[0]
+    off, idx = oracle.neighbors(pos, lam)
+    qb, pb, _ = oracle.mhd_rhs_adjoint(pos, lam, off, idx, q, gbar, xbar, stab=stab)
+    perm = np.random.default_rng(51).permutation(n)
+    parts = (perm[: n // 3], perm[n // 3:])
+    qs, ps = np.zeros_like(qb), np.zeros_like(pb)
+    for rows in parts:
+        roff, ridx = _restrict(off, idx, rows)
+        qr, pr = oracle.adjoint_rows(pos, lam, roff, ridx, q, gbar, rows, dxdt_bar=xbar,
+                                     stab=stab)
+        qs += qr
+        ps += pr
+    assert np.abs(qs - qb).max() <= 1e-12 * np.abs(qb).max()
+    assert np.abs(ps - pb).max() <= 1e-12 * np.abs(pb).max()
+    # one part alone is not the whole gradient
+    roff, ridx = _restrict(off, idx, parts[0])
+    q0, _ = oracle.adjoint_rows(pos, lam, roff, ridx, q, gbar, parts[0], dxdt_bar=xbar,
+                                stab=stab)
+    assert np.abs(q0 - qb).max() > 1e-3 * np.abs(qb).max()
