@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphurbas.so")
 SOURCES = ["api.hip", "scan.hip", "neighbors.hip", "mls.hip", "mixed.hip", "adjoint.hip", "step.hip", "batch.hip",
-           "diag.hip"]
+           "diag.hip", "refine.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

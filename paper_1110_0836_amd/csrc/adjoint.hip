@@ -26,6 +26,7 @@
 #include "chol.hpp"
 #include "mhd.hpp"
 #include "neighbors.hpp"
+#include "refine.hpp"
 
 namespace phb {
 namespace {
@@ -394,10 +395,14 @@ __global__ void __launch_bounds__(THREADS)
 // ---- 3. factor again: G = rows 1..3 of A^{-1}, K_t = A^{-1} Y_t ------------
 __constant__ EntryTab c_tab_a = make_entry_tab();
 
+// Screen (list != null): owners with status 0 whose equilibrated inverse has
+// an operator row of 2-norm above rcut are appended to list (count cleared
+// by the caller); their G and K are refined afterwards.
 template <bool STAB>
 __global__ void __launch_bounds__(THREADS)
     k_adj_factor(int n, const double* __restrict__ mom, const double* __restrict__ ybuf,
-                 const double* __restrict__ tape, double* __restrict__ gop, int interp) {
+                 const double* __restrict__ tape, double* __restrict__ gop, int interp,
+                 double rcut, int32_t* __restrict__ list, int32_t* __restrict__ count) {
   using SH = Shape<STAB>;
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
@@ -407,12 +412,14 @@ __global__ void __launch_bounds__(THREADS)
   QuadChol c;
   quad_chol_factor(c, c_tab_a, mom, soa_ld(n), ii, l, interp != 0);
   const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii];
+  double rmax2 = 0.0;
   // G rows at 0 and K rows at KOFF of the owner record, in lockstep groups of
   // three solves
   sfor<0, SH::NR / 3>([&](auto GI) {
     constexpr int g0 = 3 * GI;
     double out[3][5];
     quad_chol_inverse_rows<1 + g0, 3>(c, l, out);
+    if (list) rmax2 = fmax(rmax2, quad_rows_hat_norm2<1 + g0, 3>(c, l, out));
     if (valid) {
 #pragma unroll
       for (int rh = 0; rh < 3; ++rh)
@@ -444,6 +451,7 @@ __global__ void __launch_bounds__(THREADS)
               st == 0 ? out[rh][rho] * c.s_own[rho] : 0.0;
     }
   });
+  if (list && valid && l == 0 && st == 0 && !(rmax2 <= rcut * rcut)) list[atomicAdd(count, 1)] = i;
 }
 
 // ---- 4. pair contributions ---------------------------------------------------
@@ -949,6 +957,11 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * RCr * sizeof(double));  // pair records
   ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
+  const int NFAr = stab ? Shape<true>::NFA : Shape<false>::NFA;
+  // screened owners (and fits of a private forward); the residual sums also
+  // hold the operator rows' residual products, NRr x 20 of them
+  const int NRFr = std::max(NFAr, NRr);
+  plan_refine(ws, n, NRFr);
   const bool need_tape = tape_in == nullptr;
   if (need_tape) {
     ws.plan((size_t)TAPE_DOUBLES * ndl);  // tape (gradients, status, moments)
@@ -971,6 +984,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   double* rec = ws.take<double>((size_t)std::max<int64_t>(nnz, 1) * RCr);
   double* wpart = ws.take<double>((size_t)nwaves * 2 * REC);
   int32_t* t_slot = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  const RefineBufs rb = take_refine(ws, n, NRFr);
+  const double rcut = fp64_screen_cut(ctx, NRr);
   const int slot_order = ctx->record_order;
   const double* tape = tape_in;
   hipStream_t s = ctx->stream;
@@ -988,15 +1003,25 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     double* tmom = tp + (size_t)TAPE_MOM * soa_ld(n);
     if ((rc = hip_check(ctx, launch_moments(s, ap, ctx->lanes_assemble, tmom), "moments")))
       return rc;
-    if ((rc = hip_check(ctx, launch_factor(s, ap, NRr, tmom, fg, st), "adjoint factor")))
+    if ((rc = hip_check(ctx, fill_i32(s, rb.count, 0, 1), "clear list")) ||
+        (rc = hip_check(ctx, launch_factor(s, ap, NRr, tmom, fg, st, NRr, rcut, rb.list, rb.count),
+                        "adjoint factor")))
       return rc;
     if ((rc = hip_check(ctx,
                         launch_apply_rhs(s, ap, ctx->lanes_apply, p->gamma, sb, fg, st, rs, dx,
                                          tp),
                         "adjoint forward")))
       return rc;
+    // the screened fits' gradients, refined, into the tape
+    if ((rc = refine_fits(ctx, ap, fq, stab ? 0 : 1, NFAr, tmom, rb))) return rc;
+    if ((rc = hip_check(ctx,
+                        launch_rows_rhs_finish(s, ap, stab, rb.cbuf, NBASIS, 1, rb.ldc, rb.list,
+                                               rb.count, st, p->gamma, sb, rs, dx, tp),
+                        "adjoint forward (refined)")))
+      return rc;
     tape = tp;
   }
+  if ((rc = hip_check(ctx, fill_i32(s, rb.count, 0, 1), "clear list"))) return rc;
   const double* mom = tape + (size_t)TAPE_MOM * soa_ld(n);
   const int interp = a.fit == PHB_FIT_INTERP19;
   if (stab) {
@@ -1013,7 +1038,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Y"))) return rc; }
     { Prof pf(ctx, "k_adj_factor<stab>");
     hipLaunchKernelGGL(k_adj_factor<true>, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS),
-                       0, s, n, mom, ybuf, tape, orec, interp);
+                       0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list, rb.count);
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
   } else {
     { Prof pf(ctx, "k_adj_y");
@@ -1025,8 +1050,18 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     if (rc) return rc; }
     { Prof pf(ctx, "k_adj_factor");
     hipLaunchKernelGGL(k_adj_factor<false>, dim3(grid_for((int64_t)n * 4, THREADS)),
-                       dim3(THREADS), 0, s, n, mom, ybuf, tape, orec, interp);
+                       dim3(THREADS), 0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list,
+                       rb.count);
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
+  }
+  // the screened owners' G and K, refined on the data
+  if (stab) {
+    if ((rc = refine_adjoint(ctx, ap, true, mom, rb, orec, Shape<true>::OREC, Shape<true>::KOFF,
+                             Shape<true>::UOFF)))
+      return rc;
+  } else if ((rc = refine_adjoint(ctx, ap, false, mom, rb, orec, Shape<false>::OREC,
+                                  Shape<false>::KOFF, Shape<false>::UOFF))) {
+    return rc;
   }
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;

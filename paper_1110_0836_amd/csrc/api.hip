@@ -9,6 +9,7 @@
 #include "mls.hpp"
 #include "neighbors.hpp"
 #include "adjoint.hpp"
+#include "refine.hpp"
 
 namespace phb {
 
@@ -225,13 +226,19 @@ size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity) {
   return ws.total;
 }
 
+static void plan_derivs(Workspace& ws, int64_t n) {
+  ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
+  ws.plan((size_t)9 * NBASIS * soa_ld(n) * sizeof(double));
+  ws.plan((size_t)n * sizeof(double4));
+  ws.plan((size_t)8 * n * sizeof(double));  // packed field chunk
+  plan_refine(ws, n, 8);
+}
+
 size_t ws_bytes_derivs(int64_t n, const phb_params* p, bool second) {
   if (p->precision == PHB_MIXED) return mixed_derivs_bytes(n, second);
   phb_ctx dummy;
   Workspace ws(&dummy);
-  ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
-  ws.plan((size_t)9 * NBASIS * soa_ld(n) * sizeof(double));
-  ws.plan((size_t)n * sizeof(double4));
+  plan_derivs(ws, n);
   return ws.total;
 }
 
@@ -252,6 +259,7 @@ static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, boo
   ws.plan((size_t)(stab ? 9 : 3) * NBASIS * soa_ld(n) * sizeof(double));
   ws.plan((size_t)n_all * sizeof(double4));
   ws.plan((size_t)n_all * 8 * sizeof(double));
+  plan_refine(ws, n, stab ? 8 : 7);
 }
 
 // The time derivatives in the form p->precision asks for (FP64 here).
@@ -274,6 +282,8 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   double* gop = ws.take<double>((size_t)nrows * NBASIS * soa_ld(n));
   double4* geo = ws.take<double4>(na);
   double* fq = ws.take<double>((size_t)8 * na);
+  const int nf = sb.on() ? 8 : 7;  // fields with a gradient (V, B, sigma; rho too when stabilised)
+  const RefineBufs rb = take_refine(ws, n, nf);
   // with a tape, the moments go straight into it for the reverse mode
   if (tape) mom = tape + (size_t)TAPE_MOM * soa_ld(n);
   a.geo = geo;
@@ -285,13 +295,27 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
     return rc; }
   { Prof pf(ctx, nrows == 9 ? "k_factor<9>" : "k_factor<3>");
-  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, nrows, mom, gop, status), "factor")))
+  if ((rc = hip_check(ctx, fill_i32(ctx->stream, rb.count, 0, 1), "clear list")) ||
+      (rc = hip_check(ctx,
+                      launch_factor(ctx->stream, a, nrows, mom, gop, status, nrows,
+                                    fp64_screen_cut(ctx, nrows), rb.list, rb.count),
+                      "factor")))
     return rc; }
-  Prof pf(ctx, nrows == 9 ? "k_apply_rhs<stab>" : "k_apply_rhs");
+  { Prof pf(ctx, nrows == 9 ? "k_apply_rhs<stab>" : "k_apply_rhs");
+  if ((rc = hip_check(ctx,
+                      launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, sb, gop,
+                                       status, rhs, dxdt, tape),
+                      "apply rhs")))
+    return rc; }
+  // the screened fits again, refined on the data; their outputs replace the
+  // operator form's
+  if ((rc = refine_fits(ctx, a, fq, sb.on() ? 0 : 1, nf, mom, rb))) return rc;
+  Prof pf(ctx, "k_rows_rhs_finish<list>");
   return hip_check(ctx,
-                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, sb, gop, status,
-                                    rhs, dxdt, tape),
-                   "apply rhs");
+                   launch_rows_rhs_finish(ctx->stream, a, sb.on(), rb.cbuf, NBASIS, 1, rb.ldc,
+                                          rb.list, rb.count, status, p->gamma, sb, rhs, dxdt,
+                                          tape),
+                   "refined rhs");
 }
 
 int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
@@ -427,6 +451,7 @@ static int* tune_slot(phb_ctx* ctx, const char* key) {
   if (!strcmp(key, "mixed_refine")) return &ctx->mixed_refine;
   if (!strcmp(key, "adj_pairs_mode")) return &ctx->adj_pairs_mode;
   if (!strcmp(key, "record_order")) return &ctx->record_order;
+  if (!strcmp(key, "fp64_cut_x10")) return &ctx->fp64_cut_x10;
   return nullptr;
 }
 
@@ -438,7 +463,9 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
   const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order");
   const bool cut = !strcmp(key, "mixed_cond_x10");
   const bool refine = !strcmp(key, "mixed_refine");
-  if (cut ? !(value >= -1 && value <= 120)
+  const bool cut64 = !strcmp(key, "fp64_cut_x10");
+  if (cut64 ? !(value >= -1 && value <= 999)
+      : cut ? !(value >= -1 && value <= 120)
           : refine ? !(value >= 0 && value <= 2)
           : lanes ? !(value == 1 || value == 2 || value == 4)
                   : (mode ? !(value == 0 || value == 1) : !(value >= 1 && value <= 4)))
@@ -651,14 +678,15 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double*
   if (p->precision == PHB_MIXED)
     return mixed_derivs(ctx, a, nf, fields, d1, max_order == 2 ? d2 : nullptr, status);
   const int n = a.n;
+  const int ng = max_order == 2 ? 9 : 3;
   Workspace ws(ctx);
-  ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
-  ws.plan((size_t)9 * NBASIS * soa_ld(n) * sizeof(double));
-  ws.plan((size_t)n * sizeof(double4));
+  plan_derivs(ws, n);
   if ((rc = ws.commit())) return rc;
   double* mom = ws.take<double>((size_t)NMOM * soa_ld(n));
   double* gop = ws.take<double>((size_t)9 * NBASIS * soa_ld(n));
   double4* geo = ws.take<double4>(n);
+  double* fa = ws.take<double>((size_t)8 * n);
+  const RefineBufs rb = take_refine(ws, n, 8);
   a.geo = geo;
   if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, pos, lambda, nullptr, geo, nullptr),
                       "pack")))
@@ -667,13 +695,32 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double*
   if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
     return rc; }
   { Prof pf(ctx, "k_factor<9>");
-  if ((rc = hip_check(ctx, launch_factor(ctx->stream, a, 9, mom, gop, status), "factor")))
+  if ((rc = hip_check(ctx, fill_i32(ctx->stream, rb.count, 0, 1), "clear list")) ||
+      (rc = hip_check(ctx,
+                      launch_factor(ctx->stream, a, 9, mom, gop, status, ng,
+                                    fp64_screen_cut(ctx, ng), rb.list, rb.count),
+                      "factor")))
     return rc; }
-  Prof pf(ctx, "k_apply_derivs");
-  return hip_check(ctx,
-                   launch_apply_derivs(ctx->stream, a, ctx->lanes_apply, gop, status, nf, fields,
-                                       d1, max_order == 2 ? d2 : nullptr),
-                   "apply derivatives");
+  { Prof pf(ctx, "k_apply_derivs");
+  if ((rc = hip_check(ctx,
+                      launch_apply_derivs(ctx->stream, a, ctx->lanes_apply, gop, status, nf,
+                                          fields, d1, max_order == 2 ? d2 : nullptr),
+                      "apply derivatives")))
+    return rc; }
+  // the screened fits again, refined on the data, eight fields at a time
+  for (int f0 = 0; f0 < nf; f0 += 8) {
+    const int nfc = nf - f0 < 8 ? nf - f0 : 8;
+    if ((rc = hip_check(ctx, launch_pack_chunk(ctx->stream, n, fields, f0, nfc, fa), "pack")))
+      return rc;
+    if ((rc = refine_fits(ctx, a, fa, 0, nfc, mom, rb))) return rc;
+    if ((rc = hip_check(ctx,
+                        launch_rows_derivs_finish(ctx->stream, a, ng, rb.cbuf, NBASIS, 1, rb.ldc,
+                                                  rb.list, rb.count, status, nfc, f0, d1,
+                                                  max_order == 2 ? d2 : nullptr),
+                        "refined derivatives")))
+      return rc;
+  }
+  return PHB_OK;
 }
 
 int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,

@@ -278,6 +278,28 @@ __device__ __forceinline__ void quad_chol_inverse_rows(const QuadChol& c, int l,
     for (int rho = 0; rho < 5; ++rho) out[r][rho] *= c.s_own[rho];
 }
 
+// Largest squared 2-norm among rows T0 .. T0 + NR - 1 of the equilibrated
+// inverse A_hat^{-1}, given those rows of A^{-1} (own entries, as returned by
+// quad_chol_inverse_rows): A_hat^{-1}[T][b] = A^{-1}[T][b] / (s_T s_b).  The
+// same value on all four lanes.
+template <int T0, int NR>
+__device__ __forceinline__ double quad_rows_hat_norm2(const QuadChol& c, int l,
+                                                      const double (&rows)[NR][5]) {
+  double m = 0.0;
+  sfor<0, NR>([&](auto RI) {
+    constexpr int T = T0 + RI;
+    double part = 0.0;
+    sfor<0, 5>([&](auto R) {
+      const double e = rows[RI][R] / c.s_own[R];
+      part = fma(e, e, part);
+    });
+    part = group_sum<4>(part);
+    const double sT = quad_bcast<T & 3>(c.s_own[T >> 2]);
+    m = fmax(m, part / (sT * sT));
+  });
+  return m;
+}
+
 // Estimate of the 2-norm of A_hat^{-1} (the equilibrated matrix), from below
 // and in practice within a small factor: x = A_hat^{-1} e with the signs of e
 // chosen for growth as above, then one power step z = A_hat^{-1} x and

@@ -35,6 +35,8 @@ struct phb_ctx {
   int lanes_gather = 4;
   int mixed_cond_x10 = -1;  // mixed form: FP64 path above ||A_hat^-1|| ~ 10^(x10 / 10)
   int mixed_refine = 2;     // mixed form: 1 operator-level, 0 data-level, 2 by shape
+  int fp64_cut_x10 = -1;    // refinement of fits whose inverse has a row norm above
+                            // 10^(x10 / 10); -1: the shape's default, 999: never
   int adj_pairs_mode = 1;  // 0: one lane per entry, 1: one wavefront per owner
   int record_order = 0;    // pair records at 0: transposed positions, 1: forward slots
   // Per-kernel timing (phb_profile): event pairs awaiting read-out and totals.

@@ -13,25 +13,30 @@
 //
 // A particle whose FP32-assembled matrix is too ill-conditioned for one step
 // to converge (estimated norm of the inverse of the equilibrated matrix above
-// a cut, or a failed pivot) is recomputed entirely in FP64: its moments and
-// right-hand sides are re-assembled in FP64 and factored again, so that its
-// status and result are those of the FP64 form.  Such particles are collected into a
-// list (order irrelevant: each is processed on its own).
+// a cut, or a failed pivot) is recomputed entirely in FP64: its moments are
+// re-assembled in FP64 and factored again (its status is that of the FP64
+// form), and its fit is solved by the FP64 refinement on the data that the
+// FP64 form applies to its own ill-conditioned fits.  Such particles are
+// collected into a list (order irrelevant: each is processed on its own).
 //
 // Kernels, per evaluation of up to 8 fields:
 //   k_moments<fp32>   84 moments, FP32 accumulation            (mls.hip)
 //   k_mixed_b         B~ = sum w p df, quad per particle, lane l owns fields
 //                     l and l + 4
 //   k_mixed_factor    FP64 equilibrated Cholesky of A~, screening, C~ and G~
-//   k_mixed_repair    FP64 moments and B of the listed particles
-//   k_mixed_factor    (list form) FP64 factor and solves of the listed ones
+//   k_mixed_repair    FP64 moments of the listed particles
+//   k_mixed_factor    (list form) FP64 factor and status of the listed ones
 //   k_mixed_resid     dB in FP32 and the refined rows E C~ + G~ dB
+//   refine_fits       FP64 refinement of the listed fits (refine.hip)
 //   finish            scaling by powers of 1/lambda, the MHD right-hand side
+#include <algorithm>
+
 #include "adjoint.hpp"
 #include "chol.hpp"
 #include "internal.hpp"
 #include "mhd.hpp"
 #include "mls.hpp"
+#include "refine.hpp"
 
 namespace phb {
 namespace {
@@ -503,116 +508,6 @@ __global__ void __launch_bounds__(THREADS)
   });
 }
 
-// Gradients = rows / lambda; pointwise right-hand side; tape.  Ideal form:
-// rows[f][3][n] of the seven fields V, B, sigma.  STAB: rows[f][9][n] of all
-// eight fields, whose second-derivative rows (xx, xy, xz, yy, yz, zz) give
-// grad div V and grad div B.
-template <bool STAB>
-__global__ void __launch_bounds__(THREADS)
-    k_mixed_rhs_finish(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
-                       const double* __restrict__ rows, const int32_t* __restrict__ status,
-                       double gamma, Stab sb, double* __restrict__ rhs, double* __restrict__ dxdt,
-                       double* __restrict__ tape) {
-  constexpr int NG = STAB ? 9 : 3;
-  constexpr int F0 = STAB ? 1 : 0;  // row block of field V_x
-  const int i = blockIdx.x * THREADS + threadIdx.x;
-  if (i >= n) return;
-  const double lam = geo[i].w;
-  const double inv_lam = 1.0 / lam;
-  double qi[8];
-#pragma unroll
-  for (int f = 0; f < 8; ++f) qi[f] = fq[8 * (int64_t)i + f];
-  double grad[7][3];
-#pragma unroll
-  for (int f = 0; f < 7; ++f)
-#pragma unroll
-    for (int t = 0; t < 3; ++t) grad[f][t] = rows[((int64_t)(F0 + f) * NG + t) * soa_ld(n) + i] * inv_lam;
-  const int st = status[i];
-  double out[8];
-  double grho[3] = {0.0, 0.0, 0.0}, gdv[3] = {0.0, 0.0, 0.0}, gdb[3] = {0.0, 0.0, 0.0};
-  if (st == 0) {
-    mhd_point(qi, grad, gamma, out);
-    if constexpr (STAB) {
-      // h[f][k]: second-derivative rows with the diagonal doubled
-      const double il2 = inv_lam * inv_lam;
-      auto h = [&](int f, int k) {
-        const double c = rows[((int64_t)f * NG + 3 + k) * soa_ld(n) + i] * il2;
-        return (k == 0 || k == 3 || k == 5) ? 2.0 * c : c;
-      };
-#pragma unroll
-      for (int a = 0; a < 3; ++a) grho[a] = rows[(int64_t)a * soa_ld(n) + i] * inv_lam;
-      // d_a div X = sum_b d_a d_b X_b ; k(a,b): xx 0, xy 1, xz 2, yy 3, yz 4, zz 5
-      gdv[0] = h(1, 0) + h(2, 1) + h(3, 2);
-      gdv[1] = h(1, 1) + h(2, 3) + h(3, 4);
-      gdv[2] = h(1, 2) + h(2, 4) + h(3, 5);
-      gdb[0] = h(4, 0) + h(5, 1) + h(6, 2);
-      gdb[1] = h(4, 1) + h(5, 3) + h(6, 4);
-      gdb[2] = h(4, 2) + h(5, 4) + h(6, 5);
-      stab_point(qi, grho, grad[0][0] + grad[1][1] + grad[2][2], gdv, gdb, lam, gamma, sb, out);
-    }
-  } else {
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
-#pragma unroll
-    for (int f = 0; f < 8; ++f) out[f] = nan;
-  }
-#pragma unroll
-  for (int f = 0; f < 8; ++f) rhs[(int64_t)f * n + i] = out[f];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) dxdt[(int64_t)a * n + i] = qi[1 + a];
-  if (tape) {
-#pragma unroll
-    for (int f = 0; f < 7; ++f)
-#pragma unroll
-      for (int t = 0; t < 3; ++t) tape[((int64_t)f * 3 + t) * soa_ld(n) + i] = grad[f][t];
-    tape[(int64_t)TAPE_STATUS * soa_ld(n) + i] = (double)st;
-    if constexpr (STAB) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        tape[(int64_t)(TAPE_GRHO + a) * soa_ld(n) + i] = grho[a];
-        tape[(int64_t)(TAPE_GDV + a) * soa_ld(n) + i] = gdv[a];
-        tape[(int64_t)(TAPE_GDB + a) * soa_ld(n) + i] = gdb[a];
-      }
-    }
-  }
-}
-
-// First (rows 0..2) and second (rows 3..8: xx, xy, xz, yy, yz, zz) physical
-// derivatives of a chunk of fields.
-template <int NG>
-__global__ void __launch_bounds__(THREADS)
-    k_mixed_derivs_finish(int n, const double4* __restrict__ geo, const double* __restrict__ rows,
-                          const int32_t* __restrict__ status, int nfc, int f0,
-                          double* __restrict__ d1, double* __restrict__ d2) {
-  const int i = blockIdx.x * THREADS + threadIdx.x;
-  if (i >= n) return;
-  const double inv_lam = 1.0 / geo[i].w;
-  const bool ok = status[i] == 0;
-  const double nan = __longlong_as_double(0x7ff8000000000000LL);
-  const double fac[6] = {2.0, 1.0, 1.0, 2.0, 1.0, 2.0};
-  for (int f = 0; f < nfc; ++f) {
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-      d1[((int64_t)(f0 + f) * 3 + t) * n + i] =
-          ok ? rows[((int64_t)f * NG + t) * soa_ld(n) + i] * inv_lam : nan;
-    if constexpr (NG == 9) {
-#pragma unroll
-      for (int t = 0; t < 6; ++t)
-        d2[((int64_t)(f0 + f) * 6 + t) * n + i] =
-            ok ? fac[t] * rows[((int64_t)f * NG + 3 + t) * soa_ld(n) + i] * inv_lam * inv_lam : nan;
-    }
-  }
-}
-
-// fa[8 i + f] = fields[f0 + f][i] for f < nfc.
-__global__ void __launch_bounds__(THREADS)
-    k_pack_chunk(int n, const double* __restrict__ fields, int f0, int nfc,
-                 double* __restrict__ fa) {
-  const int i = blockIdx.x * THREADS + threadIdx.x;
-  if (i >= n) return;
-  for (int f = 0; f < 8; ++f)
-    fa[8 * (int64_t)i + f] = f < nfc ? fields[(int64_t)(f0 + f) * n + i] : 0.0;
-}
-
 __global__ void k_zero_i32(int32_t* p, int m) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < m) p[k] = 0;
@@ -636,6 +531,7 @@ struct MixedBufs {
   int32_t* flag;
   int32_t* list;
   int32_t* count;
+  RefineBufs ref;  // the listed fits' refinement state
 };
 
 void plan_mixed(Workspace& ws, int64_t n, int nf, int ng) {
@@ -648,6 +544,19 @@ void plan_mixed(Workspace& ws, int64_t n, int nf, int ng) {
   ws.plan((size_t)n * sizeof(int32_t));
   ws.plan((size_t)n * sizeof(int32_t));
   ws.plan(sizeof(int32_t));
+  plan_refine_state(ws, n);
+}
+
+// The refinement of the listed particles reuses B~ (residual sums) and C~
+// (coefficients) once the FP32 fit is done with them.
+RefineBufs listed_refine(const MixedBufs& m, int64_t n) {
+  RefineBufs r = m.ref;
+  r.list = m.list;
+  r.count = m.count;
+  r.cbuf = m.cfit;
+  r.dbuf = m.b;
+  r.ldc = soa_ld(n);
+  return r;
 }
 
 MixedBufs take_mixed(Workspace& ws, int64_t n, int nf, int ng) {
@@ -661,12 +570,15 @@ MixedBufs take_mixed(Workspace& ws, int64_t n, int nf, int ng) {
   m.flag = ws.take<int32_t>(n);
   m.list = ws.take<int32_t>(n);
   m.count = ws.take<int32_t>(1);
+  take_refine_state(ws, n, m.ref);
   return m;
 }
 
 // Refined coefficient rows 1..NG (unscaled) of nf <= 8 fields stored in the
-// records fa[8 j + fb + f]; m.mom receives the moments (FP32-assembled, FP64
-// for the listed particles).
+// records fa[8 j + fb + f] into m.rows; m.mom receives the moments
+// (FP32-assembled, FP64 for the listed particles).  The listed particles'
+// rows in m.rows are those of the plain FP64 solve; their refined
+// coefficients are left in listed_coef() by list position.
 template <int NG>
 int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
               const MixedBufs& m, int32_t* status) {
@@ -690,15 +602,19 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed factor"))) return rc; }
   { Prof pf(ctx, "k_mixed_repair");
     hipLaunchKernelGGL(k_mixed_repair, dim3(LIST_BLOCKS), dim3(THREADS), 0, s, n, a.geo, a.off,
-                       a.idx, a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.list, m.count, m.mom, m.b);
+                       a.idx, a.box, a.rf_ratio, a.wkind, nullptr, 0, 0, m.list, m.count, m.mom,
+                       nullptr);
     hipLaunchKernelGGL((k_mixed_factor<NG, true, true>), dim3(gq), dim3(THREADS), 0, s, n, m.mom,
                        a.off, nf, m.b, m.cfit, m.gt, status, m.flag, ncut, m.list, nullptr,
                        m.count, interp);
     if ((rc = hip_check(ctx, hipGetLastError(), "mixed repair"))) return rc; }
-  Prof pf(ctx, "k_mixed_resid");
-  hipLaunchKernelGGL((k_mixed_resid<NG>), dim3(gq), dim3(THREADS), 0, s, n, a.geo, a.off, a.idx,
-                     a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.cfit, m.gt, status, m.flag, m.rows);
-  return hip_check(ctx, hipGetLastError(), "mixed residual");
+  { Prof pf(ctx, "k_mixed_resid");
+    hipLaunchKernelGGL((k_mixed_resid<NG>), dim3(gq), dim3(THREADS), 0, s, n, a.geo, a.off, a.idx,
+                       a.box, a.rf_ratio, a.wkind, fa, fb, nf, m.cfit, m.gt, status, m.flag,
+                       m.rows);
+    if ((rc = hip_check(ctx, hipGetLastError(), "mixed residual"))) return rc; }
+  // B~ and C~ are dead now: they hold the listed fits' refinement
+  return refine_fits(ctx, a, fa, fb, nf, m.mom, listed_refine(m, n));
 }
 
 struct OpBufs {
@@ -817,14 +733,38 @@ int join_aux(phb_ctx* ctx, bool forked, int rc) {
 
 }  // namespace
 
-size_t mixed_rhs_bytes(int64_t n, bool stab) {
-  phb_ctx dummy;
-  Workspace ws(&dummy);
-  // the larger of the two refinement forms
-  plan_mixed(ws, n, stab ? 8 : 7, stab ? 9 : 3);
+// Workspace of the operator-level form: its buffers, the packed records and
+// the listed fits' refinement (coefficients and residual sums of nf fields).
+static void plan_op_form(Workspace& ws, int64_t n, int ng, int nf) {
+  plan_op(ws, n, ng);
   ws.plan((size_t)n * sizeof(double4));
   ws.plan((size_t)8 * n * sizeof(double));
-  return ws.total;
+  ws.plan((size_t)2 * nf * NBASIS * soa_ld(n) * sizeof(double));
+  plan_refine_state(ws, n);
+}
+
+static RefineBufs take_op_refine(Workspace& ws, const OpBufs& m, int64_t n, int nf) {
+  RefineBufs r;
+  r.ldc = soa_ld(n);
+  r.list = m.list;
+  r.count = m.count;
+  r.cbuf = ws.take<double>((size_t)nf * NBASIS * r.ldc);
+  r.dbuf = ws.take<double>((size_t)nf * NBASIS * r.ldc);
+  take_refine_state(ws, n, r);
+  return r;
+}
+
+size_t mixed_rhs_bytes(int64_t n, bool stab) {
+  phb_ctx dummy;
+  const int nf = stab ? 8 : 7, ng = stab ? 9 : 3;
+  // the larger of the two refinement forms
+  Workspace wd(&dummy);
+  plan_mixed(wd, n, nf, ng);
+  wd.plan((size_t)n * sizeof(double4));
+  wd.plan((size_t)8 * n * sizeof(double));
+  Workspace wo(&dummy);
+  plan_op_form(wo, n, ng, nf);
+  return std::max(wd.total, wo.total);
 }
 
 // Operator-level form of mixed_rhs: the refined rows applied in FP32.
@@ -833,16 +773,15 @@ static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const St
                         double* tape) {
   const int n = a0.n;
   const bool stab = sb.on();
-  const int ng = stab ? 9 : 3;
+  const int ng = stab ? 9 : 3, nf = stab ? 8 : 7;
   Workspace ws(ctx);
-  plan_op(ws, n, ng);
-  ws.plan((size_t)n * sizeof(double4));
-  ws.plan((size_t)8 * n * sizeof(double));
+  plan_op_form(ws, n, ng, nf);
   int rc;
   if ((rc = ws.commit())) return rc;
   OpBufs m = take_op(ws, n, ng);
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
+  const RefineBufs rb = take_op_refine(ws, m, n, nf);
   EvalArgs a = a0;
   a.geo = geo;
   a.fq = fq;
@@ -859,13 +798,16 @@ static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const St
                                          status, rhs, dxdt, tape, true),
                         "mixed apply")))
       return join_aux(ctx, forked, rc); }
-  // the listed (ill-conditioned) particles again, in FP64: applied in FP32,
-  // their operator would lose kappa eps_32
-  { Prof pf(ctx, "k_apply_rhs<list>");
+  // the listed (ill-conditioned) particles again, by the FP64 refinement on
+  // the data: applied in FP32 their operator would lose kappa eps_32, in
+  // FP64 kappa eps_64
+  if ((rc = refine_fits(ctx, a, fq, stab ? 0 : 1, nf, m.mom, rb)))
+    return join_aux(ctx, forked, rc);
+  { Prof pf(ctx, "k_rows_rhs_finish<list>");
     rc = hip_check(ctx,
-                   launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, gamma, sb, m.gt, status,
-                                    rhs, dxdt, tape, false, m.list, m.count),
-                   "mixed apply (listed)"); }
+                   launch_rows_rhs_finish(ctx->stream, a, stab, rb.cbuf, NBASIS, 1, rb.ldc,
+                                          rb.list, rb.count, status, gamma, sb, rhs, dxdt, tape),
+                   "mixed rhs (listed)"); }
   return join_aux(ctx, forked, rc);
 }
 
@@ -898,28 +840,37 @@ int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, co
       return rc; }
   bool forked = false;
   if ((rc = fork_tape_moments(ctx, a, tape, forked))) return rc;
-  if (stab) {
-    if ((rc = mixed_fit<9>(ctx, a, fq, 0, 8, m, status))) return join_aux(ctx, forked, rc);
-    Prof pf(ctx, "k_mixed_rhs_finish<stab>");
-    hipLaunchKernelGGL(k_mixed_rhs_finish<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
-                       ctx->stream, n, geo, fq, m.rows, status, gamma, sb, rhs, dxdt, tape);
-  } else {
-    // V, B and sigma are entries 1..7 of the packed records
-    if ((rc = mixed_fit<3>(ctx, a, fq, 1, 7, m, status))) return join_aux(ctx, forked, rc);
-    Prof pf(ctx, "k_mixed_rhs_finish");
-    hipLaunchKernelGGL(k_mixed_rhs_finish<false>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
-                       ctx->stream, n, geo, fq, m.rows, status, gamma, sb, rhs, dxdt, tape);
-  }
-  return join_aux(ctx, forked, hip_check(ctx, hipGetLastError(), "mixed rhs"));
+  // V, B and sigma are entries 1..7 of the packed records (all eight with the
+  // stabilisers)
+  rc = stab ? mixed_fit<9>(ctx, a, fq, 0, 8, m, status) : mixed_fit<3>(ctx, a, fq, 1, 7, m, status);
+  if (rc) return join_aux(ctx, forked, rc);
+  const RefineBufs rb = listed_refine(m, n);
+  { Prof pf(ctx, stab ? "k_rows_rhs_finish<stab>" : "k_rows_rhs_finish");
+    if ((rc = hip_check(ctx,
+                        launch_rows_rhs_finish(ctx->stream, a, stab, m.rows, ng, 0, soa_ld(n),
+                                               nullptr, nullptr, status, gamma, sb, rhs, dxdt,
+                                               tape),
+                        "mixed rhs")))
+      return join_aux(ctx, forked, rc); }
+  Prof pf(ctx, "k_rows_rhs_finish<list>");
+  return join_aux(ctx, forked,
+                  hip_check(ctx,
+                            launch_rows_rhs_finish(ctx->stream, a, stab, rb.cbuf, NBASIS, 1,
+                                                   rb.ldc, rb.list, rb.count, status, gamma, sb,
+                                                   rhs, dxdt, tape),
+                            "mixed rhs (listed)"));
 }
 
 size_t mixed_derivs_bytes(int64_t n, bool second) {
   phb_ctx dummy;
-  Workspace ws(&dummy);
-  plan_mixed(ws, n, 8, second ? 9 : 3);
-  ws.plan((size_t)n * sizeof(double4));
-  ws.plan((size_t)8 * n * sizeof(double));
-  return ws.total;
+  const int ng = second ? 9 : 3;
+  Workspace wd(&dummy);
+  plan_mixed(wd, n, 8, ng);
+  wd.plan((size_t)n * sizeof(double4));
+  wd.plan((size_t)8 * n * sizeof(double));
+  Workspace wo(&dummy);
+  plan_op_form(wo, n, ng, 8);
+  return std::max(wd.total, wo.total);
 }
 
 // Operator-level form of mixed_derivs: one refined operator serves every
@@ -929,12 +880,13 @@ static int mixed_derivs_op(phb_ctx* ctx, const EvalArgs& a0, int nf, const doubl
   const int n = a0.n;
   const int ng = d2 ? 9 : 3;
   Workspace ws(ctx);
-  plan_op(ws, n, ng);
-  ws.plan((size_t)n * sizeof(double4));
+  plan_op_form(ws, n, ng, 8);
   int rc;
   if ((rc = ws.commit())) return rc;
   OpBufs m = take_op(ws, n, ng);
   double4* geo = ws.take<double4>(n);
+  double* fa = ws.take<double>((size_t)8 * n);
+  const RefineBufs rb = take_op_refine(ws, m, n, 8);
   EvalArgs a = a0;
   a.geo = geo;
   if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, nullptr, geo, nullptr),
@@ -947,11 +899,19 @@ static int mixed_derivs_op(phb_ctx* ctx, const EvalArgs& a0, int nf, const doubl
                                           fields, d1, d2, true),
                       "mixed derivatives")))
     return rc;
-  // the listed particles again in FP64 (as in mixed_rhs_op)
-  return hip_check(ctx,
-                   launch_apply_derivs(ctx->stream, a, ctx->lanes_apply, m.gt, status, nf, fields,
-                                       d1, d2, false, m.list, m.count),
-                   "mixed derivatives (listed)");
+  // the listed particles again by the FP64 refinement (as in mixed_rhs_op)
+  for (int f0 = 0; f0 < nf; f0 += 8) {
+    const int nfc = nf - f0 < 8 ? nf - f0 : 8;
+    if ((rc = hip_check(ctx, launch_pack_chunk(ctx->stream, n, fields, f0, nfc, fa), "pack")))
+      return rc;
+    if ((rc = refine_fits(ctx, a, fa, 0, nfc, m.mom, rb))) return rc;
+    if ((rc = hip_check(ctx,
+                        launch_rows_derivs_finish(ctx->stream, a, ng, rb.cbuf, NBASIS, 1, rb.ldc,
+                                                  rb.list, rb.count, status, nfc, f0, d1, d2),
+                        "mixed derivatives (listed)")))
+      return rc;
+  }
+  return PHB_OK;
 }
 
 int mixed_derivs(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields, double* d1,
@@ -969,6 +929,7 @@ int mixed_derivs(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields,
   MixedBufs m = take_mixed(ws, n, 8, ng);
   double4* geo = ws.take<double4>(n);
   double* fa = ws.take<double>((size_t)8 * n);
+  const RefineBufs rb = listed_refine(m, n);
   EvalArgs a = a0;
   a.geo = geo;
   if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, nullptr, geo, nullptr),
@@ -976,21 +937,22 @@ int mixed_derivs(phb_ctx* ctx, const EvalArgs& a0, int nf, const double* fields,
     return rc;
   for (int f0 = 0; f0 < nf; f0 += 8) {
     const int nfc = nf - f0 < 8 ? nf - f0 : 8;
-    hipLaunchKernelGGL(k_pack_chunk, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, ctx->stream, n,
-                       fields, f0, nfc, fa);
-    if ((rc = hip_check(ctx, hipGetLastError(), "pack fields"))) return rc;
+    if ((rc = hip_check(ctx, launch_pack_chunk(ctx->stream, n, fields, f0, nfc, fa), "pack")))
+      return rc;
     // the moments are assembled again per chunk: the list form has replaced
     // the flagged particles' moments by FP64 ones
-    if (ng == 9) {
-      if ((rc = mixed_fit<9>(ctx, a, fa, 0, nfc, m, status))) return rc;
-      hipLaunchKernelGGL((k_mixed_derivs_finish<9>), dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
-                         ctx->stream, n, geo, m.rows, status, nfc, f0, d1, d2);
-    } else {
-      if ((rc = mixed_fit<3>(ctx, a, fa, 0, nfc, m, status))) return rc;
-      hipLaunchKernelGGL((k_mixed_derivs_finish<3>), dim3(grid_for(n, THREADS)), dim3(THREADS), 0,
-                         ctx->stream, n, geo, m.rows, status, nfc, f0, d1, d2);
-    }
-    if ((rc = hip_check(ctx, hipGetLastError(), "mixed derivatives"))) return rc;
+    rc = ng == 9 ? mixed_fit<9>(ctx, a, fa, 0, nfc, m, status)
+                 : mixed_fit<3>(ctx, a, fa, 0, nfc, m, status);
+    if (rc) return rc;
+    if ((rc = hip_check(ctx,
+                        launch_rows_derivs_finish(ctx->stream, a, ng, m.rows, ng, 0, soa_ld(n),
+                                                  nullptr, nullptr, status, nfc, f0, d1, d2),
+                        "mixed derivatives")) ||
+        (rc = hip_check(ctx,
+                        launch_rows_derivs_finish(ctx->stream, a, ng, rb.cbuf, NBASIS, 1, rb.ldc,
+                                                  rb.list, rb.count, status, nfc, f0, d1, d2),
+                        "mixed derivatives (listed)")))
+      return rc;
   }
   return PHB_OK;
 }

@@ -107,11 +107,16 @@ __global__ void __launch_bounds__(THREADS)
 __constant__ EntryTab c_tab = make_entry_tab();
 
 // Writes rows 1 .. NT of A^{-1} (the x, y, z monomials first) to
-// gop[t][20][n], and the status.
+// gop[t][20][n], and the status.  Screen (list != null): a particle with
+// status 0 whose equilibrated inverse has a row among the first nscreen
+// operator rows of 2-norm above rcut is appended to list (its operator form
+// would lose more than the fit's own accuracy; the refinement solves it
+// again).
 template <int NT>
 __global__ void __launch_bounds__(THREADS)
     k_factor(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
-             double* __restrict__ gop, int32_t* __restrict__ status, int interp) {
+             double* __restrict__ gop, int32_t* __restrict__ status, int interp, int nscreen,
+             double rcut, int32_t* __restrict__ list, int32_t* __restrict__ count) {
   const int tid = blockIdx.x * THREADS + threadIdx.x;
   const int i = tid >> 2;
   const int l = tid & 3;
@@ -120,6 +125,7 @@ __global__ void __launch_bounds__(THREADS)
   QuadChol c;
   quad_chol_factor(c, c_tab, mom, soa_ld(n), ii, l, interp != 0);
   const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
+  double rmax2 = 0.0;
   // rows in lockstep groups of three
   sfor<0, NT / 3>([&](auto GI) {
     constexpr int t0 = 1 + 3 * GI;
@@ -133,8 +139,12 @@ __global__ void __launch_bounds__(THREADS)
         });
       });
     }
+    if (list && 3 * GI < nscreen) rmax2 = fmax(rmax2, quad_rows_hat_norm2<t0, 3>(c, l, rows));
   });
-  if (valid && l == 0) status[i] = st;
+  if (valid && l == 0) {
+    status[i] = st;
+    if (list && st == 0 && !(rmax2 <= rcut * rcut)) list[atomicAdd(count, 1)] = i;
+  }
 }
 
 // X_r = A^{-1} R_r for NR general right-hand sides R (SoA [NR][20][n]);
@@ -485,15 +495,16 @@ hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
 }
 
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,
-                         double* gop, int32_t* status) {
+                         double* gop, int32_t* status, int nscreen, double rcut, int32_t* list,
+                         int32_t* count) {
   const unsigned grid = grid_for((int64_t)a.n * 4, THREADS);
   const int interp = a.fit == PHB_FIT_INTERP19;
   if (ntargets == 3)
     hipLaunchKernelGGL((k_factor<3>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status,
-                       interp);
+                       interp, nscreen, rcut, list, count);
   else
     hipLaunchKernelGGL((k_factor<9>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, gop, status,
-                       interp);
+                       interp, nscreen, rcut, list, count);
   return hipGetLastError();
 }
 

@@ -50,8 +50,12 @@ hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* la
 // fp32: accumulate in FP32 (the mixed form); the moments are stored in FP64.
 hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom,
                           bool fp32 = false);
+// Screen (list != null): status-0 particles whose equilibrated inverse has one
+// of its first nscreen operator rows of 2-norm above rcut are appended to
+// list[atomicAdd(count)] (count cleared by the caller).
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,
-                         double* gop, int32_t* status);
+                         double* gop, int32_t* status, int nscreen = 0, double rcut = 0.0,
+                         int32_t* list = nullptr, int32_t* count = nullptr);
 // X = A^{-1} R for nr (1..8) right-hand sides given as SoA [nr][20][n].
 hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
                                const double* mom, const double* rhs, double* x, int32_t* status,

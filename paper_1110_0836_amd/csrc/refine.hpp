@@ -1,0 +1,70 @@
+// FP64 refinement of screened (ill-conditioned) fits, and the kernels that
+// turn coefficient rows into derivatives or time derivatives.
+#pragma once
+
+#include "internal.hpp"
+#include "mls.hpp"
+
+namespace phb {
+
+// Most passes of the refinement: the plain solve and up to four corrections
+// (each particle stops once converged; the operator rows of the reverse mode
+// take up to REFINE_PASSES - 1 steps).
+constexpr int REFINE_PASSES = 5;
+
+// Screen cut on the largest 2-norm of a row of the equilibrated inverse
+// among the nrows operator rows a factor kernel computes (the context's
+// fp64_cut_x10, or the default of the shape).
+double fp64_screen_cut(const phb_ctx* ctx, int nrows);
+
+// List of screened particles (device count) and the refinement's buffers, by
+// list position: coefficients cbuf[f][20][ldc], residual sums dbuf[f][20][ldc],
+// the last correction's size prev[f][ldc] (f < 8) and converged flags
+// done[ldc].
+struct RefineBufs {
+  int32_t* list;
+  int32_t* count;
+  double* cbuf;
+  double* dbuf;
+  int64_t ldc;
+  double* prev;
+  int32_t* done;
+};
+void plan_refine(Workspace& ws, int64_t n, int nf);
+RefineBufs take_refine(Workspace& ws, int64_t n, int nf);
+// prev and done alone (for callers that lend their own list and buffers).
+void plan_refine_state(Workspace& ws, int64_t n);
+void take_refine_state(Workspace& ws, int64_t n, RefineBufs& r);
+
+// Refined coefficient vectors (all 20) of nf <= 8 fields of the packed
+// records fa[8 j + fb + f] for the listed particles, into r.cbuf.  mom: FP64
+// moments [84][soa_ld(n)] by row index.
+int refine_fits(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
+                const double* mom, const RefineBufs& r);
+
+// Reverse mode of the listed owners: refined coefficients, K = Ubar C^T and
+// refinement steps on the operator rows G, written into their owner records
+// (G at 0, K at koff, Ubar read at uoff).  a.geo and a.fq must be packed; r
+// must hold max(fields, rows) = 7 (ideal) or 9 (stabilised) fields.
+int refine_adjoint(phb_ctx* ctx, const EvalArgs& a, bool stab, const double* mom,
+                   const RefineBufs& r, double* orec, int orec_len, int koff, int uoff);
+
+// Coefficient (field f, monomial 1 + t) of the particle in column col at
+// coef[(f * fstride + t0 + t) * cld + col].  list == null: every particle, column
+// = particle; else the listed ones, column = list position.
+// Time derivatives (and tape) from the gradient rows of V, B, sigma
+// (coefficient fields 0..6) or, stab, from the nine rows of all eight fields.
+hipError_t launch_rows_rhs_finish(hipStream_t s, const EvalArgs& a, bool stab, const double* coef,
+                                  int fstride, int t0, int64_t cld, const int32_t* list,
+                                  const int32_t* count, const int32_t* status, double gamma,
+                                  const Stab& sb, double* rhs, double* dxdt, double* tape);
+// First (and with ng == 9 second) derivatives of fields f0 .. f0 + nfc - 1.
+hipError_t launch_rows_derivs_finish(hipStream_t s, const EvalArgs& a, int ng, const double* coef,
+                                     int fstride, int t0, int64_t cld, const int32_t* list,
+                                     const int32_t* count, const int32_t* status, int nfc, int f0,
+                                     double* d1, double* d2);
+// fa[8 i + f] = fields[f0 + f][i], f < nfc (zero beyond).
+hipError_t launch_pack_chunk(hipStream_t s, int n, const double* fields, int f0, int nfc,
+                             double* fa);
+
+}  // namespace phb

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_1110_0836_amd import synth
-from _common import dev, setup_of
+from _common import dev, setup_of, fit_kappa, kappa_spread, kappa_tol_adj, particle_err
 
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_1110_0836_amd")
@@ -72,10 +72,15 @@ def test_matches_oracle_ragged_open_box():
     oq, op, ost = oracle.mhd_rhs_adjoint(c["pos"], c["lam"], off, idx, c["q"], gbar, L=c["L"],
                                          periodic=c["periodic"])
     # particles cut by the open faces are ill conditioned (see test_gpu_mls):
-    # the normal equations lose about kappa^2 eps there, and every neighbor of
-    # such a particle inherits part of it through the scatter
-    assert max(grad_err(qb[f], oq[f]) for f in range(8)) < 1e-4
-    assert grad_err(pb, op) < 1e-4
+    # each gradient entry is held to the condition-scaled bound of the worst
+    # fit it receives a contribution from (the reverse mode's products of
+    # inverse rows with monomials cancel to kappa eps in the oracle too)
+    bound = kappa_tol_adj(kappa_spread(fit_kappa(c["pos"], c["lam"], off, idx, L=c["L"],
+                                                 periodic=c["periodic"]), off, idx))
+    wq = max((particle_err(qb[f], oq[f]) / bound).max() for f in range(8))
+    wp = (particle_err(pb, op) / bound).max()
+    print("q_bar, pos_bar: error over the condition-scaled bound, worst particle", wq, wp)
+    assert wq <= 1.0 and wp <= 1.0
 
 
 def loss_bar_oracle(c, w):

@@ -8,7 +8,8 @@ import pytest
 
 import oracle
 from paper_1110_0836_amd import synth
-from _common import dev, setup_of, rel_err, rhs_err, interior
+from _common import (dev, setup_of, rel_err, rhs_err, interior, fit_kappa, kappa_tol,
+                     particle_err)
 from test_gpu_adjoint import random_set, grad_err
 
 pytestmark = pytest.mark.gpu
@@ -40,15 +41,22 @@ def test_derivatives_match_oracle(precision, mixed_refine):
     assert np.array_equal(st, ost)
     ok = st == 0
     g1, g2 = d1.cpu().numpy(), d2.cpu().numpy()
-    # the FP64 form solves the normal equations: the nearly square fits of the
-    # sparsest rows (20-30 entries) lose kappa^2 eps against the oracle's QR
-    full = ok & (np.diff(ooff) >= 30)
-    for sel, tol in (((full, 1e-12), (ok, 1e-9)) if precision == 0 else ((ok, 1e-5),)):
-        e1 = rel_err(g1[:, :, sel], o1[:, :, sel], axis=(1, 2))
-        e2 = rel_err(g2[:, :, sel], o2[:, :, sel], axis=(1, 2))
-        print("interpolating fit:", sel.sum(), "particles, first-order", e1.max(),
+    if precision == 0:
+        # the nearly square fits of the sparsest rows (20-30 entries) are ill
+        # conditioned: every particle within the condition-scaled bound of its
+        # own fit (the 19 non-constant monomials)
+        bound = kappa_tol(fit_kappa(c["pos"], c["lam"], ooff, oidx, fit=1)[ok])
+        w1 = max((particle_err(g1[f], o1[f], ok) / bound).max() for f in range(8))
+        w2 = max((particle_err(g2[f], o2[f], ok) / bound).max() for f in range(8))
+        print("interpolating fit: error over the condition-scaled bound, worst particle",
+              w1, w2)
+        assert w1 <= 1.0 and w2 <= 1.0
+    else:
+        e1 = rel_err(g1[:, :, ok], o1[:, :, ok], axis=(1, 2))
+        e2 = rel_err(g2[:, :, ok], o2[:, :, ok], axis=(1, 2))
+        print("interpolating fit:", ok.sum(), "particles, first-order", e1.max(),
               "second-order", e2.max())
-        assert e1.max() < tol and e2.max() < tol
+        assert e1.max() < 1e-5 and e2.max() < 1e-5
     # and it is not the full fit
     assert rel_err(f1[:, :, ok], o1[:, :, ok], axis=(1, 2)).max() > 1e-3
 

@@ -5,16 +5,20 @@ derivatives) at sizes the oracle finishes quickly, and on sampled particles
 at the benchmark sizes.
 
 Open boxes: particles whose sphere is cut by a face are fitted from a
-lopsided sample; the GPU solves the normal equations (condition number
-squared) while the oracle uses QR, so those particles agree only to about
-kappa^2 * eps.  They are held to a looser bound; every particle with a whole
-sphere (all of them in periodic boxes) is held to 1e-12."""
+lopsided sample, with condition numbers up to ~1e10.  The oracle's QR is
+itself exact only to about kappa(P) eps = sqrt(kappa) eps there, so each
+particle is held to 1e-12 plus 64 sqrt(kappa) eps (kappa of its equilibrated
+moment matrix), and, for the exact cubic fields of the pin variant, the GPU's
+error against the analytic derivatives to within a small factor of the
+oracle's own."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_1110_0836_amd import synth
-from _common import dev, setup_of, rel_err, rhs_err, interior
+from _common import (dev, setup_of, rel_err, rhs_err, interior, fit_kappa, kappa_tol,
+                     particle_err, rhs_particle_err)
+from test_oracle_mls import _analytic
 
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_1110_0836_amd")
@@ -41,12 +45,31 @@ def test_cubic_set_derivatives(pin):
     assert np.array_equal(gs, os_)
     ok = gs == 0
     inner = ok & interior(c["pos"], c["lam"], c["L"], c["periodic"])
-    for sel, tol in ((inner, TOL64), (ok, 1e-5)):
-        e1 = rel_err(g1[:, :, sel], o1[:, :, sel], axis=(1, 2))
-        e2 = rel_err(g2[:, :, sel], o2[:, :, sel], axis=(1, 2))
-        print("first-order max rel err per field", e1)
-        print("second-order max rel err per field", e2)
-        assert e1.max() < tol and e2.max() < tol
+    e1 = rel_err(g1[:, :, inner], o1[:, :, inner], axis=(1, 2))
+    e2 = rel_err(g2[:, :, inner], o2[:, :, inner], axis=(1, 2))
+    print("whole spheres: first-order max rel err per field", e1, "second-order", e2)
+    assert e1.max() < TOL64 and e2.max() < TOL64
+    if pin:
+        # every particle, face particles included, within the condition-scaled
+        # bound of the oracle ...
+        off, idx = oracle.neighbors(c["pos"], c["lam"], L=c["L"], periodic=c["periodic"])
+        tol = kappa_tol(fit_kappa(c["pos"], c["lam"], off, idx, L=c["L"],
+                                  periodic=c["periodic"])[ok])
+        for g, o in ((g1, o1), (g2, o2)):
+            worst = max((particle_err(g[f], o[f], ok) / tol).max() for f in range(8))
+            print("error over the condition-scaled bound, worst particle", worst)
+            assert worst <= 1.0
+        # ... and as close to the exact cubic as the oracle (Sec. 2's third-order
+        # fit reproduces cubics): per field and derivative order, the GPU's
+        # largest error against the analytic derivatives within a small factor
+        # of the oracle's own
+        x1, x2 = _analytic(c["pos"], c["coef"], c["exponents"])
+        for g, o, x in ((g1, o1, x1), (g2, o2, x2)):
+            for f in range(8):
+                eg = particle_err(g[f], x[f], ok).max()
+                eo = particle_err(o[f], x[f], ok).max()
+                print(f"field {f}: exact-cubic error, GPU max {eg:.2e}, oracle max {eo:.2e}")
+                assert eg <= 2.0 * eo + 1e-13
     assert np.all(np.isnan(g1[:, :, ~ok])) and np.all(np.isnan(g2[:, :, ~ok]))
 
 
@@ -102,10 +125,23 @@ def rhs_both(c, rows=None, **kw):
     return g, (orhs, odx, ost, od1), qs
 
 
-def check_rhs(g, o, qs, tol, sel=None, gamma=5.0 / 3.0):
+def check_rhs(g, o, qs, tol, sel=None, gamma=5.0 / 3.0, kappa=None):
+    """tol: the bound of every selected particle; kappa (all particles): each
+    particle's bound is instead kappa_tol(kappa), 1e-12 + 64 sqrt(kappa) eps."""
     (r, x, s, gd), (orr, ox, os_, od1) = g, o
     assert np.array_equal(s, os_)
     ok = s == 0 if sel is None else (s == 0) & sel
+    if kappa is not None:
+        bound = kappa_tol(kappa[ok])
+        # the derivative operator itself, per field (V, B, sigma), and the
+        # time derivatives per quantity, particle by particle
+        wd = max((particle_err(gd[f], od1[1 + f], ok) / bound).max() for f in range(7))
+        wr = (rhs_particle_err(r[:, ok], orr[:, ok], qs[:, ok], od1[:, :, ok], gamma)
+              / bound).max()
+        print("error over the condition-scaled bound, worst particle: gradients", wd, "rhs", wr)
+        assert wd <= 1.0 and wr <= 1.0
+        assert np.array_equal(x, ox)
+        return None
     # the derivative operator itself, per field (V, B, sigma)
     ed = rel_err(gd[:, :, ok], od1[1:, :, ok], axis=(1, 2))
     print("gradient max rel err per field", ed)
@@ -131,7 +167,9 @@ def test_rhs_random_open_box():
     c["q"][0] = 1.0 + 0.1 * np.abs(c["q"][0])
     g, o, qs = rhs_both(c)
     check_rhs(g, o, qs, TOL64, interior(c["pos"], c["lam"], c["L"], c["periodic"]))
-    check_rhs(g, o, qs, 1e-5)
+    off, idx = oracle.neighbors(c["pos"], c["lam"], L=c["L"], periodic=c["periodic"])
+    check_rhs(g, o, qs, None, kappa=fit_kappa(c["pos"], c["lam"], off, idx, L=c["L"],
+                                              periodic=c["periodic"]))
 
 
 def test_rhs_unit_weight():

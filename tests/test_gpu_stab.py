@@ -1,7 +1,8 @@
 """Non-ideal stabilisers (bulk viscosity with a grid-scale and an adaptive
 coefficient, div-B diffusion; Sec. 2 and App. A) on the GPU against the
 oracle: the FP64 form element by element within 1e-12 (per physical
-quantity, relative to the size of the terms it is summed from), the mixed
+quantity, relative to the size of the terms it is summed from; on open-box
+faces within 1e-12 + 64 sqrt(kappa) eps of each fit's condition), the mixed
 form within 1e-5; the reverse mode and torch.autograd through it; the Courant
 step; the App. A damping rate of a sound wave over half a period."""
 import numpy as np
@@ -9,7 +10,7 @@ import pytest
 
 import oracle
 from paper_1110_0836_amd import synth
-from _common import dev, setup_of, interior, GROUPS
+from _common import dev, setup_of, interior, GROUPS, fit_kappa, kappa_tol
 
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_1110_0836_amd")
@@ -40,7 +41,7 @@ def oracle_rhs(c, rows=None, stab=TUPLE):
     return r1, x1, s1, r1 - r0, d1, d2
 
 
-def stab_err(g, o, q, lam, gamma=5.0 / 3.0):
+def stab_err(g, o, q, lam, gamma=5.0 / 3.0, per_particle=False):
     """Max error per physical quantity over the given particles, relative to
     the size of the terms it is summed from: the ideal terms (as in the ideal
     tests) and the stabilising ones, whose grad div X sums second derivatives
@@ -58,22 +59,34 @@ def stab_err(g, o, q, lam, gamma=5.0 / 3.0):
              "V": max(((gamma - 1) * gs + bmax * gb) / rmin, zmax * np.abs(d2[1:4]).max()),
              "B": max(bmax * gv, lcf * STAB["divb_diff"] * np.abs(d2[4:7]).max()),
              "sigma": max(gamma * np.abs(q[7]).max() * gv, np.abs(q[0]).max() * zmax * gv * gv)}
-    return {k: float(np.abs(g[v] - r1[v]).max() /
-                     max(np.abs(r1[v]).max(), floor[k], np.abs(dst[v]).max(), 1e-300))
-            for k, v in GROUPS.items()}
+    den = {k: max(np.abs(r1[v]).max(), floor[k], np.abs(dst[v]).max(), 1e-300)
+           for k, v in GROUPS.items()}
+    if per_particle:
+        return np.max([np.abs(g[v] - r1[v]).max(axis=0) / den[k] for k, v in GROUPS.items()],
+                      axis=0)
+    return {k: float(np.abs(g[v] - r1[v]).max() / den[k]) for k, v in GROUPS.items()}
 
 
-def check(c, tol, sel=None, rows=None, **kw):
+def check(c, tol, sel=None, rows=None, kappa=None, **kw):
+    """tol: bound of every selected particle; kappa (all particles): each
+    particle's bound is kappa_tol(kappa) instead."""
     g = gpu_rhs(c, rows=rows, **STAB, **kw)
     o = oracle_rhs(c, rows=rows)
     assert np.array_equal(g[2], o[2])
     ok = g[2] == 0 if sel is None else (g[2] == 0) & sel
     q = c["q"] if rows is None else c["q"][:, rows]
     lam = c["lam"] if rows is None else c["lam"][rows]
-    e = stab_err(g[0][:, ok], (o[0][:, ok], None, None, o[3][:, ok], o[4][:, :, ok],
-                               o[5][:, :, ok]), q[:, ok], lam[ok])
-    print("stabilised rhs max rel err per quantity", e)
-    assert max(e.values()) < tol
+    args = (g[0][:, ok], (o[0][:, ok], None, None, o[3][:, ok], o[4][:, :, ok], o[5][:, :, ok]),
+            q[:, ok], lam[ok])
+    if kappa is not None:
+        worst = (stab_err(*args, per_particle=True) / kappa_tol(kappa[ok])).max()
+        print("stabilised rhs: error over the condition-scaled bound, worst particle", worst)
+        assert worst <= 1.0
+        e = stab_err(*args)
+    else:
+        e = stab_err(*args)
+        print("stabilised rhs max rel err per quantity", e)
+        assert max(e.values()) < tol
     assert np.array_equal(g[1], o[1])
     # the stabilising terms are a visible part of the answer
     assert np.abs(o[3][1:4, ok]).max() > 1e-3 * np.abs(o[0][1:4, ok]).max()
@@ -105,14 +118,17 @@ def test_adaptive_sensor_covers_both_regimes():
 
 
 def test_fp64_open_box():
-    """Particles whose sphere is cut by a face are fitted from a lopsided sample;
-    the normal equations lose kappa(A) ~ kappa(P)^2 against the oracle's QR, and
-    the second-derivative rows the stabilisers use are the most sensitive:
-    those particles are held to 1e-3, every whole-sphere particle to 1e-12."""
+    """Particles whose sphere is cut by a face are fitted from a lopsided sample
+    (the second-derivative rows the stabilisers use are the most sensitive to
+    it); whole-sphere particles are held to 1e-12, every particle to the
+    condition-scaled bound 1e-12 + 64 sqrt(kappa) eps of its fit, the
+    oracle's own accuracy."""
     c = _steep_cloud(2500, seed=72, periodic=(0, 1, 0))
     inner = interior(c["pos"], c["lam"], c["L"], c["periodic"])
     check(c, 1e-12, sel=inner)
-    check(c, 1e-3)
+    off, idx = oracle.neighbors(c["pos"], c["lam"], L=c["L"], periodic=c["periodic"])
+    check(c, None, kappa=fit_kappa(c["pos"], c["lam"], off, idx, L=c["L"],
+                                   periodic=c["periodic"]))
 
 
 def test_fp64_shear_layer_full_size_sampled():
@@ -129,10 +145,16 @@ def test_mixed_matches_oracle(name, mixed_refine):
 
 
 def test_tiny_coefficients_reproduce_the_ideal_kernel():
-    # the nine-row kernel's gradient part against the three-row kernel
+    # the nine-row kernel's gradient part against the three-row kernel (the
+    # screen of ill-conditioned fits off: the two shapes screen different rows)
     c = synth.cp_alfven(12)
-    g0 = gpu_rhs(c)
-    g1 = gpu_rhs(c, visc_grid=1e-300)
+    old = P.phb_tune_get("fp64_cut_x10")
+    P.phb_tune_set("fp64_cut_x10", 999)
+    try:
+        g0 = gpu_rhs(c)
+        g1 = gpu_rhs(c, visc_grid=1e-300)
+    finally:
+        P.phb_tune_set("fp64_cut_x10", old)
     assert np.array_equal(g0[2], g1[2])
     ok = g0[2] == 0
     d = np.abs(g1[0][:, ok] - g0[0][:, ok]).max(axis=1)
