@@ -195,6 +195,29 @@ int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                 const double* lambda, const int64_t* offsets, const int32_t* idx,
                 const double* q, double* rhs, double* dxdt, int32_t* status, void* tape);
 int64_t phb_tape_bytes(int64_t n);
+
+/* ---- allocation-free variant ----------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments,
+ * results and errors are those of phb_mhd_rhs, computed by the same kernels;
+ * every intermediate buffer lives in a file-scope device array of
+ * PHB_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates nothing (no device memory, no
+ * events, no second stream; with a tape in the mixed form the tape's FP64
+ * moments run in order on the context stream).  PHB_ECAPACITY when the set
+ * needs more scratch than that: about 3.6 KB per particle in the ideal FP64
+ * form (n up to about 18,000), 4.7 KB with the stabilisers; the mixed form
+ * needs more.  Calls that overlap on one GPU share the array and race
+ * (whatever their context or stream): serialize them.  The array keeps the
+ * last call's contents, which no later call reads before writing.  (The HIP
+ * runtime loads the library's device code at the first launch of its kernels
+ * in a process, an allocation of its own: callers that must not allocate at
+ * all make one call first, for instance before a graph capture.)
+ * Asynchronous. */
+#define PHB_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int phb_mhd_rhs_noalloc(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                        const double* lambda, const int64_t* offsets, const int32_t* idx,
+                        const double* q, double* rhs, double* dxdt, int32_t* status, void* tape);
 /* Active-subset evaluation (Sec. 2: each particle has its own time step, so
  * only some particles need new time derivatives at a time): the time
  * derivatives of the m particles rows[0 .. m) (int32, distinct, in [0, n)),

@@ -40,7 +40,7 @@ EXPORTS = [
     "phb_pc_step", "phb_profile", "phb_profile_read", "phb_tune_set", "phb_tune_get",
     "phb_evolve", "phb_courant_dt", "phb_tune", "phb_batch_create", "phb_batch_destroy", "phb_batch_neighbors", "phb_batch_run",
     "phb_batch_capture", "phb_batch_launch", "phb_divb_norm", "phb_bin_mean",
-    "phb_neighbors_build_rows", "phb_mhd_rhs_rows", "phb_evolve_blocks",
+    "phb_neighbors_build_rows", "phb_mhd_rhs_rows", "phb_evolve_blocks", "phb_mhd_rhs_noalloc",
 ]
 
 
@@ -131,6 +131,7 @@ def lib():
             "phb_permute": (I, [P, I64, P, I32, P, P]),
             "phb_mls_derivs": (I, [P, PP, I64, P, P, P, P, I32, P, I32, P, P, P]),
             "phb_mhd_rhs": (I, [P, PP, I64, P, P, P, P, P, P, P, P, P]),
+            "phb_mhd_rhs_noalloc": (I, [P, PP, I64, P, P, P, P, P, P, P, P, P]),
             "phb_tape_bytes": (I64, [I64]),
             "phb_mhd_rhs_adjoint": (I, [P, PP, I64, P, P, P, P, P, P, P, P, P, P, P, P, P]),
             "phb_pc_step": (I, [P, PP, I64, D, P, P, P, P, P, I64, ctypes.POINTER(I64), P]),
@@ -255,6 +256,17 @@ def phb_mhd_rhs(setup, pos, lam, offsets, idx, q, rhs, dxdt, status, tape=None):
     _check(ctx, lib().phb_mhd_rhs(ctx, ctypes.byref(p), lam.shape[0], _f64(pos), _f64(lam),
                                   _ptr(offsets), _ptr(idx), _f64(q), _f64(rhs), _f64(dxdt),
                                   _ptr(status), _ptr(tape)))
+
+
+def phb_mhd_rhs_noalloc(setup, pos, lam, offsets, idx, q, rhs, dxdt, status, tape=None):
+    """phb_mhd_rhs without any allocation: the library's static scratch holds
+    the intermediates (for callers that cannot allocate; size limit in
+    include/phurbas.h)."""
+    ctx = context(pos.device.index)
+    p = setup.params()
+    _check(ctx, lib().phb_mhd_rhs_noalloc(ctx, ctypes.byref(p), lam.shape[0], _f64(pos),
+                                          _f64(lam), _ptr(offsets), _ptr(idx), _f64(q),
+                                          _f64(rhs), _f64(dxdt), _ptr(status), _ptr(tape)))
 
 
 def phb_tape_bytes(n):

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "internal.hpp"
@@ -26,6 +27,10 @@ int hip_check(phb_ctx* ctx, hipError_t e, const char* what) {
 int Workspace::commit() {
   const size_t need = ctx->arena_base + total;
   if (need <= ctx->arena_cap) return PHB_OK;
+  if (ctx->no_alloc)
+    return set_error(ctx, PHB_ECAPACITY, "the static scratch holds " +
+                                             std::to_string(ctx->arena_cap) + " bytes; " +
+                                             std::to_string(need) + " needed");
   if (ctx->arena_base != 0)
     return set_error(ctx, PHB_ESTATE, "nested workspace exceeds the reserved arena");
   if (ctx->capturing)
@@ -339,6 +344,59 @@ int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
 
 using namespace phb;
 
+// ---- allocation-free variant --------------------------------------------------
+// The workspace of phb_mhd_rhs_noalloc: file-scope device memory, one copy on
+// every GPU the library runs on, held until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it stands for no
+// device address): each device's address comes from hipGetSymbolAddress,
+// looked up once with that device current.
+static __device__ __align__(256) char scratch[PHB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of(phb_ctx* ctx, char** out) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return set_error(ctx, PHB_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_check(ctx, e, "scratch address");
+    g_scratch_ptr[ctx->device] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[ctx->device];
+  return PHB_OK;
+}
+
+// For the call's duration the context's workspace is the scratch (it cannot
+// grow: Workspace::commit refuses), per-kernel profiling (which creates
+// events) is off and no second stream is used.
+struct NoAllocScope {
+  phb_ctx* ctx;
+  char* arena;
+  size_t cap, base;
+  bool prof;
+  NoAllocScope(phb_ctx* c, char* sp)
+      : ctx(c), arena(c->arena), cap(c->arena_cap), base(c->arena_base), prof(c->prof_on) {
+    c->arena = sp;
+    c->arena_cap = PHB_NOALLOC_SCRATCH_BYTES;
+    c->arena_base = 0;
+    c->prof_on = false;
+    c->no_alloc = true;
+  }
+  ~NoAllocScope() {
+    ctx->arena = arena;
+    ctx->arena_cap = cap;
+    ctx->arena_base = base;
+    ctx->prof_on = prof;
+    ctx->no_alloc = false;
+  }
+};
+}  // namespace
+
 extern "C" {
 
 const char* phb_strerror(int code) {
@@ -365,6 +423,14 @@ int phb_create(phb_ctx** out, int device, void* hip_stream) {
   phb_ctx* c = new phb_ctx();
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // the device's address of the allocation-free entry point's scratch, looked
+  // up once per device (loading the code object that holds it)
+  char* sp = nullptr;
+  const int rc = scratch_of(c, &sp);
+  if (rc) {
+    delete c;
+    return rc;
+  }
   *out = c;
   return PHB_OK;
 }
@@ -732,6 +798,29 @@ int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* po
   if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
   if (!q || !rhs || !dxdt || !status) return set_error(ctx, PHB_EINVAL, "null pointer");
   hipSetDevice(ctx->device);
+  return eval_rhs(ctx, a, p, q, rhs, dxdt, status, reinterpret_cast<double*>(tape));
+}
+
+int phb_mhd_rhs_noalloc(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                        const double* lambda, const int64_t* offsets, const int32_t* idx,
+                        const double* q, double* rhs, double* dxdt, int32_t* status, void* tape) {
+  if (!ctx) return PHB_EINVAL;
+  EvalArgs a;
+  int rc;
+  if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
+  if (!q || !rhs || !dxdt || !status) return set_error(ctx, PHB_EINVAL, "null pointer");
+  if (ctx->no_alloc || ctx->arena_base != 0)
+    return set_error(ctx, PHB_ESTATE, "allocation-free call inside another library call");
+  const size_t need = ws_bytes_rhs(n64, p);
+  if (need > PHB_NOALLOC_SCRATCH_BYTES)
+    return set_error(ctx, PHB_ECAPACITY,
+                     "n = " + std::to_string(n64) + " needs " + std::to_string(need) +
+                         " bytes of scratch; the allocation-free call holds " +
+                         std::to_string((long long)PHB_NOALLOC_SCRATCH_BYTES));
+  hipSetDevice(ctx->device);
+  char* sp = nullptr;
+  if ((rc = scratch_of(ctx, &sp))) return rc;
+  NoAllocScope scope(ctx, sp);
   return eval_rhs(ctx, a, p, q, rhs, dxdt, status, reinterpret_cast<double*>(tape));
 }
 

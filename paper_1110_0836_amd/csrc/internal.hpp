@@ -41,6 +41,9 @@ struct phb_ctx {
   int record_order = 0;    // pair records at 0: transposed positions, 1: forward slots
   // Per-kernel timing (phb_profile): event pairs awaiting read-out and totals.
   bool capturing = false;  // a graph capture is recording the context stream
+  // An allocation-free call is running: the workspace is the static scratch
+  // and may not grow, and no second stream is used.
+  bool no_alloc = false;
   bool prof_on = false;
   struct ProfRec {
     const char* name;

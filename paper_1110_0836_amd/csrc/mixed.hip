@@ -709,7 +709,7 @@ int fork_tape_moments(phb_ctx* ctx, const EvalArgs& a, double* tape, bool& forke
   forked = false;
   if (!tape) return PHB_OK;
   double* dst = tape + (size_t)TAPE_MOM * soa_ld(a.n);
-  if (ctx->prof_on) {
+  if (ctx->prof_on || ctx->no_alloc) {  // in order (an allocation-free call creates no stream)
     Prof pf(ctx, "k_moments<tape>");
     return hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, dst),
                      "tape moments");
