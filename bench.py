@@ -87,9 +87,11 @@ def time_gpu(fn, reps, torch):
 # the kernels of one forward evaluation, per form (the rest of a step is the
 # reverse mode)
 FORWARD_KERNELS = {
-    "fp64": ("k_pack", "k_moments", "k_factor<3>", "k_apply_rhs"),
+    "fp64": ("k_pack", "k_moments", "k_fit_b<7>", "k_factor_fit<3>", "k_rows_rhs_finish",
+             "k_ref_fit", "k_ref_tape", "k_ref_rows", "k_rows_rhs_finish<list>"),
     "mixed": ("k_pack", "k_moments<fp32>", "k_mixed_screen", "k_mixed_repair", "k_mixed_gta",
-              "k_mixed_refine", "k_apply_rhs<fp32>", "k_apply_rhs<list>", "k_moments<tape>"),
+              "k_mixed_refine", "k_apply_rhs<fp32>", "k_apply_rhs<list>", "k_moments<tape>",
+              "k_ref_fit", "k_rows_rhs_finish<list>"),
 }
 
 

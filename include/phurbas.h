@@ -186,11 +186,18 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* p
  *   drho/dt = -rho div V ; dV/dt = (-(gamma-1) grad sigma + (curl B) x B) / rho ;
  *   dB/dt = (B . grad) V - B div V ; dsigma/dt = -gamma sigma div V ;
  * dxdt[3][n] = V.  status int32[n].  tape: NULL or a device buffer of
- * phb_tape_bytes(n) bytes that keeps what the reverse-mode call reuses:
- * 115 rows of ld = phb_tape_bytes(n) / 920 doubles each (ld >= n, padded so
- * that the row stride is not a power of two), particle i at [row][i]; rows
- * 0..20 the gradients of V, B, sigma (3 each), 21 the status, 31..114 the
- * 84 FP64 moments.  Asynchronous. */
+ * phb_tape_bytes(n) bytes that keeps what the reverse-mode call reuses.
+ * First 115 rows of ld doubles each (ld >= n, padded so that the row stride
+ * is not a power of two), particle i at [row][i]: rows 0..20 the gradients of
+ * V, B, sigma (3 each), 21 the status, 22..30 grad rho, grad div V and
+ * grad div B (stabilisers on), 31..114 the 84 FP64 moments.  Then
+ * PHB_TAPE_AOS doubles per particle (n blocks, particle i at i *
+ * PHB_TAPE_AOS), written in the FP64 form: rows 1..3 of the inverse moment
+ * matrix A^{-1} (1..9 with the stabilisers), then the fit coefficients
+ * C = A^{-1} B of V, B, sigma (of all eight fields with the stabilisers),
+ * 20 each; the block's first 200 (340) doubles are used.  So
+ * phb_tape_bytes(n) = 8 (115 ld + PHB_TAPE_AOS n).  Asynchronous. */
+#define PHB_TAPE_AOS 340
 int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                 const double* lambda, const int64_t* offsets, const int32_t* idx,
                 const double* q, double* rhs, double* dxdt, int32_t* status, void* tape);
@@ -205,8 +212,8 @@ int64_t phb_tape_bytes(int64_t n);
  * until the process ends.  The call allocates nothing (no device memory, no
  * events, no second stream; with a tape in the mixed form the tape's FP64
  * moments run in order on the context stream).  PHB_ECAPACITY when the set
- * needs more scratch than that: about 3.6 KB per particle in the ideal FP64
- * form (n up to about 18,000), 4.7 KB with the stabilisers; the mixed form
+ * needs more scratch than that: about 3.1 KB per particle in the ideal FP64
+ * form (n up to about 21,000), 3.6 KB with the stabilisers; the mixed form
  * needs more.  Calls that overlap on one GPU share the array and race
  * (whatever their context or stream): serialize them.  The array keeps the
  * last call's contents, which no later call reads before writing.  (The HIP
@@ -404,13 +411,19 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * their residuals at the neighbors, all sums in FP32 (corrected seminormal
  * equations); 2, the default: 1 for the three gradient rows (the ideal
  * right-hand side, first derivatives), 0 with nine rows (the stabilisers,
- * second derivatives); the forms agree within the mixed tolerance).  EINVAL
+ * second derivatives); the forms agree within the mixed tolerance),
+ * "fit_fields" (2 or 4: fields per lane in the FP64 form's fit right-hand
+ * sides), "fp64_cut_x10" (-1..999: in the FP64 form a fit whose equilibrated
+ * inverse has an operator row of 2-norm above 10^(value / 10) is refined on
+ * the data; -1, the default, takes 10^2.5 with three rows and 10^1.7 with
+ * nine, 999 refines none; moves results within the FP64 tolerance).  EINVAL
  * for an unknown key or value. */
 int phb_tune_set(phb_ctx* ctx, const char* key, int value);
 int phb_tune_get(phb_ctx* ctx, const char* key, int* value);
 /* Autotuner: times one forward + reverse pass of the given set (or batch
  * concatenation) for each value of each of lanes_moments, lanes_apply,
- * lanes_adj_y, lanes_gather, adj_pairs_mode and record_order in turn
+ * lanes_adj_y, lanes_gather, adj_pairs_mode, record_order and fit_fields in
+ * turn
  * (coordinate descent from the current values; median of reps timed passes
  * after one warm-up; a value must win by 2% to replace the current one) and
  * leaves the winners set on ctx.  nnz (host) = offsets[n].  cache_path: NULL,

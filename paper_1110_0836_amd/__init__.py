@@ -273,14 +273,15 @@ def phb_tape_bytes(n):
     return lib().phb_tape_bytes(n)
 
 
-TAPE_ROWS = 31 + 84  # per-particle quantities a tape holds
+TAPE_ROWS = 31 + 84  # per-particle rows at the start of a tape
+TAPE_AOS = 340  # doubles per particle in the tape's block that follows them
 
 
 def tape_rows(tape, n):
-    """The tape's (TAPE_ROWS, n) rows as a view: the library pads each row to
-    phb_tape_bytes(n) / 8 / TAPE_ROWS entries."""
-    ld = phb_tape_bytes(n) // 8 // TAPE_ROWS
-    return tape.view(TAPE_ROWS, ld)[:, :n]
+    """The tape's (TAPE_ROWS, n) rows as a view: phb_tape_bytes(n) is
+    8 (TAPE_ROWS ld + TAPE_AOS n) for rows padded to ld entries."""
+    ld = (phb_tape_bytes(n) // 8 - TAPE_AOS * n) // TAPE_ROWS
+    return tape[:TAPE_ROWS * ld].view(TAPE_ROWS, ld)[:, :n]
 
 
 def phb_mhd_rhs_adjoint(setup, pos, lam, offsets, idx, t_offsets, t_src, t_pos, q, rhs_bar,
@@ -328,7 +329,8 @@ def phb_courant_dt(setup, q, lam, frozen, cfl):
 
 
 TUNE_KEYS = ("cells_per_rf", "lanes_moments", "lanes_apply", "lanes_adj_y", "lanes_gather",
-             "adj_pairs_mode", "record_order", "mixed_cond_x10", "mixed_refine", "fp64_cut_x10")
+             "adj_pairs_mode", "record_order", "mixed_cond_x10", "mixed_refine", "fp64_cut_x10",
+             "fit_fields")
 
 
 def phb_tune_set(key, value, device=None):

@@ -280,28 +280,68 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
-// The stabilised shape in two steps: k_adj_u (one thread per particle) writes
-// Ubar [8][9] into the owner record and the direct qbar; k_adj_yrows then
+// Ubar [NFA][NR] and the direct qbar, one thread per particle: Ubar into
+// ubuf[i * ustride + uoff ..] (the owner record, or a compact array).  The
+// stabilised shape of the operator form runs it before k_adj_yrows, which
 // accumulates three rows of Y at a time (60 accumulators per lane, as in the
-// ideal kernel), launched for rows 0..2, 3..5 and 6..8.
+// ideal kernel), launched for rows 0..2, 3..5 and 6..8; the data form runs it
+// in both shapes.
 using S9 = Shape<true>;
 
+template <bool STAB>
 __global__ void __launch_bounds__(THREADS)
     k_adj_u(int n, const double4* __restrict__ geo, double gamma, Stab sb,
             const double* __restrict__ q, const double* __restrict__ tape,
             const double* __restrict__ rhs_bar, const double* __restrict__ dxdt_bar,
-            double* __restrict__ orec, double* __restrict__ qb_direct) {
+            double* __restrict__ ubuf, int ustride, int uoff, double* __restrict__ qb_direct) {
   const int i = blockIdx.x * THREADS + threadIdx.x;
   if (i >= n) return;
   const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + i];
-  double qi[8], ub[8][9], qb[8];
-  pointwise_adjoint_stab(n, i, q, tape, rhs_bar, dxdt_bar, gamma, geo[i].w, sb, st, qi, ub, qb);
+  double qi[8], qb[8];
+  double* u = ubuf + (int64_t)i * ustride + uoff;
+  if constexpr (STAB) {
+    double ub[8][9];
+    pointwise_adjoint_stab(n, i, q, tape, rhs_bar, dxdt_bar, gamma, geo[i].w, sb, st, qi, ub, qb);
 #pragma unroll
-  for (int f = 0; f < 8; ++f)
+    for (int f = 0; f < 8; ++f)
 #pragma unroll
-    for (int t = 0; t < 9; ++t) orec[(int64_t)i * S9::OREC + S9::UOFF + f * 9 + t] = ub[f][t];
+      for (int t = 0; t < 9; ++t) u[f * 9 + t] = ub[f][t];
+  } else {
+    double ub[7][3];
+    pointwise_adjoint(n, i, q, tape, rhs_bar, dxdt_bar, gamma, 1.0 / geo[i].w, st, qi, ub, qb);
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+#pragma unroll
+      for (int t = 0; t < 3; ++t) u[f * 3 + t] = ub[f][t];
+  }
 #pragma unroll
   for (int f = 0; f < 8; ++f) qb_direct[(int64_t)f * n + i] = qb[f];
+}
+
+// Data form: the owner record (G, K = Ubar C^T, Ubar) of the lane-per-entry
+// schedule from the tape's G and C and the compact Ubar; one thread per owner
+// and row.
+template <bool STAB>
+__global__ void __launch_bounds__(THREADS)
+    k_adj_orec(int n, const double* __restrict__ aos, const double* __restrict__ ubuf,
+               double* __restrict__ orec) {
+  using SH = Shape<STAB>;
+  constexpr int NR = SH::NR, NFA = SH::NFA, LEN = TAPE_AOS;
+  const int64_t tid = (int64_t)blockIdx.x * THREADS + threadIdx.x;
+  const int i = (int)(tid / NR);
+  const int t = (int)(tid % NR);
+  if (i >= n) return;
+  const double* g = aos + (int64_t)i * LEN;
+  const double* u = ubuf + (int64_t)i * NFA * NR;
+  double* o = orec + (int64_t)i * SH::OREC;
+  for (int b = 0; b < NBASIS; ++b) {
+    double k = 0.0;
+    for (int f = 0; f < NFA; ++f) k = fma(u[f * NR + t], g[NR * NBASIS + f * NBASIS + b], k);
+    o[t * NBASIS + b] = g[t * NBASIS + b];
+    o[SH::KOFF + t * NBASIS + b] = k;
+  }
+  if (t == 0)
+    for (int e = 0; e < NFA * NR; ++e) o[SH::UOFF + e] = u[e];
 }
 
 template <int G>
@@ -720,14 +760,21 @@ __global__ void __launch_bounds__(THREADS)
 // difference b = Ubar df - K p, which is Ubar times the fit's residual, and
 // the cancelling sums of the records over a particle's owners lose up to
 // 1e-3 of the gradient on the 1M shear layer (sharp layers, 4x lambda range).
-template <class RT, class CT = double, bool STAB = false>
+//
+// TAPE (the data form): orec is the tape's AoS block (G, then the fit
+// coefficients C) and ubuf the compact Ubar [n][NFA][NR]; the wavefront
+// stages G and Ubar and forms K = Ubar C^T from the record as it stages it
+// (one entry of K per lane and pass, all in the one staging phase).
+template <class RT, class CT = double, bool STAB = false, bool TAPE = false>
 __global__ void __launch_bounds__(THREADS)
     k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                   const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
                   double rf_ratio, int wkind, const double* __restrict__ fq,
-                  const double* __restrict__ orec, RT* __restrict__ rec,
-                  double* __restrict__ own, int slot_order) {
-  constexpr int OR = Shape<STAB>::OREC, RC = Shape<STAB>::REC;
+                  const double* __restrict__ orec, const double* __restrict__ ubuf,
+                  RT* __restrict__ rec, double* __restrict__ own, int slot_order) {
+  using SH = Shape<STAB>;
+  constexpr int OR = SH::OREC, RC = SH::REC;
+  constexpr int NR = SH::NR, NFA = SH::NFA;
   const int i = __builtin_amdgcn_readfirstlane(xcd_block() * (THREADS / 64) + (threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   // the owner record goes to LDS in one coalesced load per wavefront; the
@@ -750,7 +797,51 @@ __global__ void __launch_bounds__(THREADS)
       gjn = geo[jn];
       if (!slot_order) tpn = t_pos[rs + lane];
     }
-    for (int k = lane; k < OR; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OR + k]);
+    if constexpr (TAPE) {
+      // every load of the staging is issued before the first LDS store, so
+      // the record costs one memory latency
+      const double* g = orec + (int64_t)i * TAPE_AOS;
+      const double* u = ubuf + (int64_t)i * NFA * NR;
+      constexpr int NK = (NR * NBASIS + 63) / 64, NU = (NFA * NR + 63) / 64;
+      double gv[NK], kv[NK], uv[NU];
+#pragma unroll
+      for (int r = 0; r < NK; ++r) {
+        const int e = lane + 64 * r;
+        gv[r] = e < NR * NBASIS ? g[e] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        const int e = lane + 64 * r;
+        uv[r] = e < NFA * NR ? u[e] : 0.0;
+      }
+      // K_t = sum_f Ubar[f][t] C_f
+#pragma unroll
+      for (int r = 0; r < NK; ++r) {
+        const int e = lane + 64 * r;
+        const int t = e / NBASIS, b = e % NBASIS;
+        double k = 0.0;
+        if (e < NR * NBASIS) {
+#pragma unroll
+          for (int f = 0; f < NFA; ++f) k = fma(u[f * NR + t], g[NR * NBASIS + f * NBASIS + b], k);
+        }
+        kv[r] = k;
+      }
+#pragma unroll
+      for (int r = 0; r < NK; ++r) {
+        const int e = lane + 64 * r;
+        if (e < NR * NBASIS) {
+          osh[wv][e] = CT(gv[r]);
+          osh[wv][SH::KOFF + e] = CT(kv[r]);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < NU; ++r) {
+        const int e = lane + 64 * r;
+        if (e < NFA * NR) osh[wv][SH::UOFF + e] = CT(uv[r]);
+      }
+    } else {
+      for (int k = lane; k < OR; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OR + k]);
+    }
   }
   if (i >= n) return;  // whole wavefronts leave together
   // each wavefront reads only its own record: no block barrier
@@ -896,11 +987,17 @@ void launch_gather(hipStream_t s, int gl, int n, const int64_t* t_off, const int
 
 template <bool STAB, class RT>
 void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const double* fq,
-                    const int32_t* t_pos, const double* orec, RT* rec, double* own,
-                    int slot_order) {
-  hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB>), dim3(grid_for((int64_t)a.n * 64, THREADS)),
-                     dim3(THREADS), 0, s, a.n, geo, a.off, a.idx, t_pos, a.box, a.rf_ratio,
-                     a.wkind, fq, orec, rec, own, slot_order);
+                    const int32_t* t_pos, const double* orec, const double* ubuf, RT* rec,
+                    double* own, int slot_order) {
+  const dim3 grid(grid_for((int64_t)a.n * 64, THREADS));
+  if (ubuf)
+    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, true>), grid, dim3(THREADS), 0, s, a.n,
+                       geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec,
+                       own, slot_order);
+  else
+    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, false>), grid, dim3(THREADS), 0, s, a.n,
+                       geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec,
+                       own, slot_order);
 }
 
 template <int G>
@@ -914,6 +1011,13 @@ void launch_yrows(hipStream_t s, const EvalArgs& a, const double* tape, const do
 
 }  // namespace
 
+// Two forms of the owner data.  Data form (the FP64 form, and any call
+// without a tape, whose private forward runs in FP64): the tape holds every
+// owner's G and fit coefficients C, refined for the screened fits, so the
+// reverse pass needs Ubar alone before the pairs (K = Ubar C^T is formed in
+// the pair kernel).  Operator form (the mixed form with the caller's tape,
+// which holds no G or C): Y, a second factorization for G and K = (A^{-1}
+// Y)^T, and the screened owners' refinement.
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
@@ -924,6 +1028,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   const bool stab = sb.on();
   // record shapes of this pass (see Shape)
   const int NRr = stab ? Shape<true>::NR : Shape<false>::NR;
+  const int NFAr = stab ? Shape<true>::NFA : Shape<false>::NFA;
   const int ORr = stab ? Shape<true>::OREC : Shape<false>::OREC;
   const int RCr = stab ? Shape<true>::REC : Shape<false>::REC;
   // nnz sizes the pair records: unless the caller knows it, read offsets[n]
@@ -944,32 +1049,41 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   // transposed positions and pair-record slots are int32
   if (nnz > PHB_NNZ_MAX)
     return set_error(ctx, PHB_EINVAL, "nnz exceeds the int32 positions of the transposed lists");
+  const bool need_tape = tape_in == nullptr;
+  const bool data_form = need_tape || p->precision == PHB_FP64;
+  // the lane-per-entry schedule (ideal shape) reads whole owner records
+  const bool lane_pairs = !stab && ctx->adj_pairs_mode == 0;
+  phb_params p64 = *p;
+  p64.precision = PHB_FP64;
   Workspace ws(ctx);
   const size_t nd = (size_t)n * sizeof(double);
   const size_t ndl = (size_t)soa_ld(n) * sizeof(double);  // the padded stride's rows
   const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
   ws.plan((size_t)n * sizeof(double4));  // packed geometry
   ws.plan(8 * nd);                       // packed fields
-  ws.plan((size_t)NRr * NBASIS * ndl);   // Y
-  ws.plan((size_t)ORr * nd);             // owner records: G, K, Ubar
   ws.plan(8 * nd);                       // direct qbar
   ws.plan((size_t)RCr * nd);             // own sums
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * RCr * sizeof(double));  // pair records
   ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
-  const int NFAr = stab ? Shape<true>::NFA : Shape<false>::NFA;
-  // screened owners (and fits of a private forward); the residual sums also
-  // hold the operator rows' residual products, NRr x 20 of them
-  const int NRFr = std::max(NFAr, NRr);
-  plan_refine(ws, n, NRFr);
-  const bool need_tape = tape_in == nullptr;
-  if (need_tape) {
-    ws.plan((size_t)TAPE_DOUBLES * ndl);  // tape (gradients, status, moments)
-    ws.plan((size_t)NRr * NBASIS * ndl);  // forward operator
-    ws.plan(8 * nd);                     // rhs scratch
-    ws.plan(3 * nd);                     // dxdt scratch
-    ws.plan((size_t)n * sizeof(int32_t));
+  if (data_form) {
+    ws.plan((size_t)NFAr * NRr * nd);               // Ubar
+    if (lane_pairs) ws.plan((size_t)ORr * nd);      // owner records
+  } else {
+    ws.plan((size_t)NRr * NBASIS * ndl);  // Y
+    ws.plan((size_t)ORr * nd);            // owner records: G, K, Ubar
+    // screened owners; the residual sums also hold the operator rows'
+    // residual products, NRr x 20 of them
+    plan_refine(ws, n, std::max(NFAr, NRr));
   }
+  if (need_tape) {
+    ws.plan((size_t)tape_doubles(n) * sizeof(double));  // private tape
+    ws.plan(8 * nd);                                     // rhs scratch
+    ws.plan(3 * nd);                                     // dxdt scratch
+    ws.plan((size_t)n * sizeof(int32_t));                // status scratch
+  }
+  const size_t own_bytes = ws.total;
+  if (need_tape) ws.plan(ws_bytes_rhs(n, &p64));  // the nested forward
   // Every tape holds FP64 moments: the mixed forward assembles them for the
   // tape beside its own FP32 ones, since the reverse mode solves with
   // right-hand sides built from the incoming gradients, which carry no
@@ -977,92 +1091,102 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   if ((rc = ws.commit())) return rc;
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
-  double* ybuf = ws.take<double>((size_t)NRr * NBASIS * soa_ld(n));
-  double* orec = ws.take<double>((size_t)ORr * n);
   double* qbd = ws.take<double>((size_t)8 * n);
   double* own = ws.take<double>((size_t)RCr * n);
   double* rec = ws.take<double>((size_t)std::max<int64_t>(nnz, 1) * RCr);
   double* wpart = ws.take<double>((size_t)nwaves * 2 * REC);
   int32_t* t_slot = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
-  const RefineBufs rb = take_refine(ws, n, NRFr);
-  const double rcut = fp64_screen_cut(ctx, NRr);
+  double *ubuf = nullptr, *ybuf = nullptr, *orec = nullptr;
+  RefineBufs rb{};
+  if (data_form) {
+    ubuf = ws.take<double>((size_t)NFAr * NRr * n);
+    if (lane_pairs) orec = ws.take<double>((size_t)ORr * n);
+  } else {
+    ybuf = ws.take<double>((size_t)NRr * NBASIS * soa_ld(n));
+    orec = ws.take<double>((size_t)ORr * n);
+    rb = take_refine(ws, n, std::max(NFAr, NRr));
+  }
   const int slot_order = ctx->record_order;
   const double* tape = tape_in;
   hipStream_t s = ctx->stream;
+  if (need_tape) {  // the FP64 forward fills a private tape
+    double* tp = ws.take<double>((size_t)tape_doubles(n));
+    double* rs = ws.take<double>((size_t)8 * n);
+    double* dx = ws.take<double>((size_t)3 * n);
+    int32_t* st = ws.take<int32_t>(n);
+    ArenaHold hold(ctx, own_bytes);
+    if ((rc = eval_rhs(ctx, a, &p64, q, rs, dx, st, tp))) return rc;
+    tape = tp;
+  }
   EvalArgs ap = a;
   ap.geo = geo;
   ap.fq = fq;
   { Prof pf(ctx, "k_pack");
   if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
-  if (need_tape) {  // run the forward pass to fill a private tape
-    double* tp = ws.take<double>((size_t)TAPE_DOUBLES * soa_ld(n));
-    double* fg = ws.take<double>((size_t)NRr * NBASIS * soa_ld(n));
-    double* rs = ws.take<double>((size_t)8 * n);
-    double* dx = ws.take<double>((size_t)3 * n);
-    int32_t* st = ws.take<int32_t>(n);
-    double* tmom = tp + (size_t)TAPE_MOM * soa_ld(n);
-    if ((rc = hip_check(ctx, launch_moments(s, ap, ctx->lanes_assemble, tmom), "moments")))
-      return rc;
-    if ((rc = hip_check(ctx, fill_i32(s, rb.count, 0, 1), "clear list")) ||
-        (rc = hip_check(ctx, launch_factor(s, ap, NRr, tmom, fg, st, NRr, rcut, rb.list, rb.count),
-                        "adjoint factor")))
-      return rc;
-    if ((rc = hip_check(ctx,
-                        launch_apply_rhs(s, ap, ctx->lanes_apply, p->gamma, sb, fg, st, rs, dx,
-                                         tp),
-                        "adjoint forward")))
-      return rc;
-    // the screened fits' gradients, refined, into the tape
-    if ((rc = refine_fits(ctx, ap, fq, stab ? 0 : 1, NFAr, tmom, rb))) return rc;
-    if ((rc = hip_check(ctx,
-                        launch_rows_rhs_finish(s, ap, stab, rb.cbuf, NBASIS, 1, rb.ldc, rb.list,
-                                               rb.count, st, p->gamma, sb, rs, dx, tp),
-                        "adjoint forward (refined)")))
-      return rc;
-    tape = tp;
-  }
-  if ((rc = hip_check(ctx, fill_i32(s, rb.count, 0, 1), "clear list"))) return rc;
   const double* mom = tape + (size_t)TAPE_MOM * soa_ld(n);
   const int interp = a.fit == PHB_FIT_INTERP19;
-  if (stab) {
-    { Prof pf(ctx, "k_adj_u");
-    hipLaunchKernelGGL(k_adj_u, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
-                       p->gamma, sb, q, tape, rhs_bar, dxdt_bar, orec, qbd);
+  const double* pair_src = orec;  // what the pair kernel stages per owner
+  if (data_form) {
+    { Prof pf(ctx, stab ? "k_adj_u<stab>" : "k_adj_u");
+    if (stab)
+      hipLaunchKernelGGL(k_adj_u<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
+                         p->gamma, sb, q, tape, rhs_bar, dxdt_bar, ubuf, NFAr * NRr, 0, qbd);
+    else
+      hipLaunchKernelGGL(k_adj_u<false>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
+                         p->gamma, sb, q, tape, rhs_bar, dxdt_bar, ubuf, NFAr * NRr, 0, qbd);
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Ubar"))) return rc; }
-    { Prof pf(ctx, "k_adj_yrows");
-    switch (ctx->lanes_adj_y) {
-      case 1: launch_yrows<1>(s, ap, tape, orec, ybuf); break;
-      case 2: launch_yrows<2>(s, ap, tape, orec, ybuf); break;
-      default: launch_yrows<4>(s, ap, tape, orec, ybuf); break;
+    if (lane_pairs) {
+      Prof pf(ctx, "k_adj_orec");
+      hipLaunchKernelGGL(k_adj_orec<false>, dim3(grid_for((int64_t)n * NRr, THREADS)),
+                         dim3(THREADS), 0, s, n, tape_aos(tape, n), ubuf, orec);
+      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint owner records"))) return rc;
+    } else {
+      pair_src = tape_aos(tape, n);
     }
-    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Y"))) return rc; }
-    { Prof pf(ctx, "k_adj_factor<stab>");
-    hipLaunchKernelGGL(k_adj_factor<true>, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS),
-                       0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list, rb.count);
-    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
   } else {
-    { Prof pf(ctx, "k_adj_y");
-    switch (ctx->lanes_adj_y) {
-      case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
-      case 2: rc = hip_check(ctx, launch_adj_y_g<2>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
-      default: rc = hip_check(ctx, launch_adj_y_g<4>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+    if ((rc = hip_check(ctx, fill_i32(s, rb.count, 0, 1), "clear list"))) return rc;
+    const double rcut = fp64_screen_cut(ctx, NRr);
+    if (stab) {
+      { Prof pf(ctx, "k_adj_u<stab>");
+      hipLaunchKernelGGL(k_adj_u<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
+                         p->gamma, sb, q, tape, rhs_bar, dxdt_bar, orec, S9::OREC, S9::UOFF, qbd);
+      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Ubar"))) return rc; }
+      { Prof pf(ctx, "k_adj_yrows");
+      switch (ctx->lanes_adj_y) {
+        case 1: launch_yrows<1>(s, ap, tape, orec, ybuf); break;
+        case 2: launch_yrows<2>(s, ap, tape, orec, ybuf); break;
+        default: launch_yrows<4>(s, ap, tape, orec, ybuf); break;
+      }
+      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Y"))) return rc; }
+      { Prof pf(ctx, "k_adj_factor<stab>");
+      hipLaunchKernelGGL(k_adj_factor<true>, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS),
+                         0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list, rb.count);
+      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
+    } else {
+      { Prof pf(ctx, "k_adj_y");
+      switch (ctx->lanes_adj_y) {
+        case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+        case 2: rc = hip_check(ctx, launch_adj_y_g<2>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+        default: rc = hip_check(ctx, launch_adj_y_g<4>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
+      }
+      if (rc) return rc; }
+      { Prof pf(ctx, "k_adj_factor");
+      hipLaunchKernelGGL(k_adj_factor<false>, dim3(grid_for((int64_t)n * 4, THREADS)),
+                         dim3(THREADS), 0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list,
+                         rb.count);
+      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
     }
-    if (rc) return rc; }
-    { Prof pf(ctx, "k_adj_factor");
-    hipLaunchKernelGGL(k_adj_factor<false>, dim3(grid_for((int64_t)n * 4, THREADS)),
-                       dim3(THREADS), 0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list,
-                       rb.count);
-    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
-  }
-  // the screened owners' G and K, refined on the data
-  if (stab) {
-    if ((rc = refine_adjoint(ctx, ap, true, mom, rb, orec, Shape<true>::OREC, Shape<true>::KOFF,
-                             Shape<true>::UOFF)))
+    // the screened owners' G and K, refined on the data
+    if (stab) {
+      if ((rc = refine_adjoint(ctx, ap, true, mom, rb, orec, Shape<true>::OREC,
+                               Shape<true>::KOFF, Shape<true>::UOFF)))
+        return rc;
+    } else if ((rc = refine_adjoint(ctx, ap, false, mom, rb, orec, Shape<false>::OREC,
+                                    Shape<false>::KOFF, Shape<false>::UOFF))) {
       return rc;
-  } else if ((rc = refine_adjoint(ctx, ap, false, mom, rb, orec, Shape<false>::OREC,
-                                  Shape<false>::KOFF, Shape<false>::UOFF))) {
-    return rc;
+    }
   }
+  const double* pair_ubuf = (data_form && !lane_pairs) ? ubuf : nullptr;
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;
   float* rec_f = reinterpret_cast<float*>(rec);
@@ -1070,11 +1194,11 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     // the stabilised shape runs the wavefront-per-owner schedule only
     Prof pf(ctx, stab ? "k_adj_pairs_w<stab>" : "k_adj_pairs_w");
     if (stab) {
-      if (rec32) launch_pairs_w<true>(s, a, geo, fq, t_pos, orec, rec_f, own, slot_order);
-      else launch_pairs_w<true>(s, a, geo, fq, t_pos, orec, rec, own, slot_order);
+      if (rec32) launch_pairs_w<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
+      else launch_pairs_w<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
     } else {
-      if (rec32) launch_pairs_w<false>(s, a, geo, fq, t_pos, orec, rec_f, own, slot_order);
-      else launch_pairs_w<false>(s, a, geo, fq, t_pos, orec, rec, own, slot_order);
+      if (rec32) launch_pairs_w<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
+      else launch_pairs_w<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
   } else {

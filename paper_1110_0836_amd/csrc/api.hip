@@ -261,13 +261,19 @@ static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, boo
     return;
   }
   ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
-  ws.plan((size_t)(stab ? 9 : 3) * NBASIS * soa_ld(n) * sizeof(double));
+  ws.plan((size_t)(stab ? 8 : 7) * NBASIS * soa_ld(n) * sizeof(double));  // B, then C
   ws.plan((size_t)n_all * sizeof(double4));
   ws.plan((size_t)n_all * 8 * sizeof(double));
-  plan_refine(ws, n, stab ? 8 : 7);
+  // the screened fits (7 or 8 fields; the residual sums also hold the tape's
+  // 3 or 9 operator rows)
+  plan_refine(ws, n, stab ? 9 : 7);
 }
 
-// The time derivatives in the form p->precision asks for (FP64 here).
+// The time derivatives in the form p->precision asks for.  FP64: the data
+// form of the fit, C_f = A^{-1} B_f with B_f assembled from the data; the
+// screened fits are refined and their outputs replace the plain solve's.
+// With a tape, its AoS block receives G and C (both refined for the screened
+// particles) for the reverse mode.
 int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double* q, double* rhs,
              double* dxdt, int32_t* status, double* tape) {
   const Stab sb = stab_of(p);
@@ -279,18 +285,19 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   const int n = a.n;                        // rows
   const int na = a.rows ? a.n_all : n;      // particles
   const int nrows = sb.on() ? 9 : 3;
+  const int nf = sb.on() ? 8 : 7;  // fields with a gradient (V, B, sigma; rho too when stabilised)
   int rc;
   Workspace ws(ctx);
   plan_rhs(ws, n, na, PHB_FP64, sb.on());
   if ((rc = ws.commit())) return rc;
   double* mom = ws.take<double>((size_t)NMOM * soa_ld(n));
-  double* gop = ws.take<double>((size_t)nrows * NBASIS * soa_ld(n));
+  double* bc = ws.take<double>((size_t)nf * NBASIS * soa_ld(n));
   double4* geo = ws.take<double4>(na);
   double* fq = ws.take<double>((size_t)8 * na);
-  const int nf = sb.on() ? 8 : 7;  // fields with a gradient (V, B, sigma; rho too when stabilised)
-  const RefineBufs rb = take_refine(ws, n, nf);
+  const RefineBufs rb = take_refine(ws, n, sb.on() ? 9 : 7);
   // with a tape, the moments go straight into it for the reverse mode
   if (tape) mom = tape + (size_t)TAPE_MOM * soa_ld(n);
+  double* aos = tape ? tape_aos(tape, n) : nullptr;
   a.geo = geo;
   a.fq = fq;
   { Prof pf(ctx, "k_pack");
@@ -299,22 +306,27 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   { Prof pf(ctx, "k_moments");
   if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
     return rc; }
-  { Prof pf(ctx, nrows == 9 ? "k_factor<9>" : "k_factor<3>");
+  { Prof pf(ctx, nf == 8 ? "k_fit_b<8>" : "k_fit_b<7>");
+  if ((rc = hip_check(ctx, launch_fit_b(ctx->stream, a, nf, ctx->fit_fields, bc), "fit right-hand sides")))
+    return rc; }
+  { Prof pf(ctx, nrows == 9 ? "k_factor_fit<9>" : "k_factor_fit<3>");
   if ((rc = hip_check(ctx, fill_i32(ctx->stream, rb.count, 0, 1), "clear list")) ||
       (rc = hip_check(ctx,
-                      launch_factor(ctx->stream, a, nrows, mom, gop, status, nrows,
-                                    fp64_screen_cut(ctx, nrows), rb.list, rb.count),
-                      "factor")))
+                      launch_factor_fit(ctx->stream, a, nrows, mom, bc, aos, status,
+                                        fp64_screen_cut(ctx, nrows), rb.list, rb.count),
+                      "factor and fit")))
     return rc; }
-  { Prof pf(ctx, nrows == 9 ? "k_apply_rhs<stab>" : "k_apply_rhs");
+  { Prof pf(ctx, sb.on() ? "k_rows_rhs_finish<stab>" : "k_rows_rhs_finish");
   if ((rc = hip_check(ctx,
-                      launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, p->gamma, sb, gop,
-                                       status, rhs, dxdt, tape),
-                      "apply rhs")))
+                      launch_rows_rhs_finish(ctx->stream, a, sb.on(), bc, nrows, 0, soa_ld(n),
+                                             nullptr, nullptr, status, p->gamma, sb, rhs, dxdt,
+                                             tape),
+                      "rhs")))
     return rc; }
-  // the screened fits again, refined on the data; their outputs replace the
-  // operator form's
+  // the screened fits refined on the data; their outputs (and tape records)
+  // replace the plain solve's
   if ((rc = refine_fits(ctx, a, fq, sb.on() ? 0 : 1, nf, mom, rb))) return rc;
+  if (aos && (rc = refine_tape(ctx, a, nrows, mom, rb, aos))) return rc;
   Prof pf(ctx, "k_rows_rhs_finish<list>");
   return hip_check(ctx,
                    launch_rows_rhs_finish(ctx->stream, a, sb.on(), rb.cbuf, NBASIS, 1, rb.ldc,
@@ -518,6 +530,7 @@ static int* tune_slot(phb_ctx* ctx, const char* key) {
   if (!strcmp(key, "adj_pairs_mode")) return &ctx->adj_pairs_mode;
   if (!strcmp(key, "record_order")) return &ctx->record_order;
   if (!strcmp(key, "fp64_cut_x10")) return &ctx->fp64_cut_x10;
+  if (!strcmp(key, "fit_fields")) return &ctx->fit_fields;
   return nullptr;
 }
 
@@ -530,7 +543,9 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
   const bool cut = !strcmp(key, "mixed_cond_x10");
   const bool refine = !strcmp(key, "mixed_refine");
   const bool cut64 = !strcmp(key, "fp64_cut_x10");
-  if (cut64 ? !(value >= -1 && value <= 999)
+  const bool fields = !strcmp(key, "fit_fields");
+  if (fields ? !(value == 2 || value == 4)
+      : cut64 ? !(value >= -1 && value <= 999)
       : cut ? !(value >= -1 && value <= 120)
           : refine ? !(value >= 0 && value <= 2)
           : lanes ? !(value == 1 || value == 2 || value == 4)
@@ -548,8 +563,9 @@ int phb_tune_get(phb_ctx* ctx, const char* key, int* value) {
   return PHB_OK;
 }
 
+static_assert(TAPE_AOS == PHB_TAPE_AOS, "tape block");
 int64_t phb_tape_bytes(int64_t n) {
-  return n <= 0 ? 0 : soa_ld(n) * TAPE_DOUBLES * (int64_t)sizeof(double);
+  return tape_doubles(n) * (int64_t)sizeof(double);
 }
 
 }  // extern "C"

@@ -307,7 +307,8 @@ int phb_tune(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
   };
   const std::vector<Knob> knobs = {
       {"lanes_moments", {1, 2, 4}}, {"lanes_apply", {1, 2, 4}},  {"lanes_adj_y", {1, 2, 4}},
-      {"lanes_gather", {1, 2, 4}},  {"adj_pairs_mode", {0, 1}}, {"record_order", {0, 1}}};
+      {"lanes_gather", {1, 2, 4}},  {"adj_pairs_mode", {0, 1}}, {"record_order", {0, 1}},
+      {"fit_fields", {2, 4}}};
   char sig[160];
   snprintf(sig, sizeof sig, "# phurbas-tune n=%lld nnz=%lld precision=%d weight=%d",
            (long long)n64, (long long)nnz, p->precision, p->weight);
@@ -333,7 +334,7 @@ int phb_tune(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
   int32_t* st = nullptr;
   hipError_t e = hipMalloc((void**)&rhs, (size_t)8 * n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&dxdt, (size_t)3 * n * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc((void**)&tape, (size_t)TAPE_DOUBLES * soa_ld(n) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc((void**)&tape, (size_t)tape_doubles(n) * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&gbar, (size_t)8 * n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&qb, (size_t)8 * n * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&pb, (size_t)3 * n * sizeof(double));

@@ -795,7 +795,7 @@ static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const St
   { Prof pf(ctx, stab ? "k_apply_rhs<fp32, stab>" : "k_apply_rhs<fp32>");
     if ((rc = hip_check(ctx,
                         launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, gamma, sb, m.gt,
-                                         status, rhs, dxdt, tape, true),
+                                         status, rhs, dxdt, tape),
                         "mixed apply")))
       return join_aux(ctx, forked, rc); }
   // the listed (ill-conditioned) particles again, by the FP64 refinement on

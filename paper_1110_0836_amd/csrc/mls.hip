@@ -147,6 +147,169 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
+// ---------------------------------------------------------------------------
+// 2b. data form: right-hand-side moments, the full fit and its tape
+// ---------------------------------------------------------------------------
+// B_f[b] = sum_j w_j p_b(xi_j) (f_j - f_i) for the NF fields of the packed
+// records fq[8 j + 8 - NF + f].  Eight lanes per particle: lane S h + e
+// (S = FPL slots) takes the fields FPL h .. FPL h + FPL - 1 for the entries
+// e, e + S, ...: FPL x 20 accumulators per lane.  FPL = 4 forms each entry's
+// monomials twice per particle, FPL = 2 four times with half the registers.
+// The slots' partial sums retire one value at a time (chained, as in
+// k_moments).  The next entry's record is fetched one iteration ahead, its
+// index two ahead.
+template <int NF, int FPL>
+__global__ void __launch_bounds__(THREADS)
+    k_fit_b(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
+            const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
+            double rf_ratio, int wkind, const int32_t* __restrict__ rows,
+            double* __restrict__ bout) {
+  constexpr int S = FPL, G = 8, F0 = 8 - NF;
+  static_assert(G / S * FPL >= NF, "field groups");
+  const int tid = xcd_block() * THREADS + threadIdx.x;
+  const int i = tid / G;
+  const int l = tid % G;
+  const int h = l / S, e = l % S;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  const int me = rows ? rows[ii] : ii;  // row ii's own particle
+  const double4 gi = geo[me];
+  const double inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
+  const double inv_r2 = 1.0 / (r * r);
+  const int fb = F0 + FPL * h;  // this group's first field record
+  const int nfh = NF - FPL * h < FPL ? NF - FPL * h : FPL;
+  double fi[FPL];
+#pragma unroll
+  for (int c = 0; c < FPL; ++c) fi[c] = c < nfh ? fq[8 * (int64_t)me + fb + c] : 0.0;
+  double acc[FPL][NBASIS];
+#pragma unroll
+  for (int c = 0; c < FPL; ++c)
+#pragma unroll
+    for (int b = 0; b < NBASIS; ++b) acc[c][b] = 0.0;
+  const int64_t s1 = valid ? off[ii + 1] : off[ii];
+  int64_t s = off[ii] + e;
+  double4 gn = gi;
+  double vn[FPL];
+#pragma unroll
+  for (int c = 0; c < FPL; ++c) vn[c] = fi[c];
+  int jn = me;
+  if (s < s1) {
+    const int j = idx[s];
+    gn = geo[j];
+#pragma unroll
+    for (int c = 0; c < FPL; ++c) vn[c] = c < nfh ? fq[8 * (int64_t)j + fb + c] : 0.0;
+  }
+  if (s + S < s1) jn = idx[s + S];
+  for (; s < s1; s += S) {
+    const double4 gj = gn;
+    double vj[FPL];
+#pragma unroll
+    for (int c = 0; c < FPL; ++c) vj[c] = vn[c];
+    if (s + S < s1) {
+      gn = geo[jn];
+#pragma unroll
+      for (int c = 0; c < FPL; ++c) vn[c] = c < nfh ? fq[8 * (int64_t)jn + fb + c] : 0.0;
+      if (s + 2 * S < s1) jn = idx[s + 2 * S];
+    }
+    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+    const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+    double p[NBASIS];
+    basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+#pragma unroll
+    for (int c = 0; c < FPL; ++c) {
+      const double d = w * (vj[c] - fi[c]);
+#pragma unroll
+      for (int b = 0; b < NBASIS; ++b) acc[c][b] = fma(d, p[b], acc[c][b]);
+    }
+  }
+  double* flat = &acc[0][0];
+#pragma unroll
+  for (int k = 0; k < FPL * NBASIS; ++k) {
+    flat[k] = group_sum<S>(flat[k]);
+    if (k + 1 < FPL * NBASIS) asm volatile("" : "+v"(flat[k + 1]) : "v"(flat[k]));
+  }
+  if (valid) {
+#pragma unroll
+    for (int k = 0; k < FPL * NBASIS; ++k)
+      if (k % S == e && k / NBASIS < nfh)
+        bout[((int64_t)(FPL * h + k / NBASIS) * NBASIS + k % NBASIS) * soa_ld(n) + i] = flat[k];
+  }
+}
+
+// The data-form factor: equilibrated Cholesky of the moments, the status,
+// rows 1..NT of A^{-1} (the screen of k_factor; with a tape also its G) and
+// C_f = A^{-1} B_f for the NT == 9 ? 8 : 7 fields in lockstep pairs.  The
+// derivative rows of C (coefficients 1..NT) go in place over B as
+// [NF][NT][ld] (each quad reads a pair's B before it writes that pair's rows,
+// which lie below every later pair's B), all of C to the tape.  Failed fits
+// write zeros.  Interpolating fit: the constant's row and column are the
+// identity's, B's constant entry is dropped and C's stays zero.
+template <int NT>
+__global__ void __launch_bounds__(THREADS)
+    k_factor_fit(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
+                 double* bc, double* __restrict__ aos, int32_t* __restrict__ status, int interp,
+                 double rcut, int32_t* __restrict__ list, int32_t* __restrict__ count) {
+  constexpr int NF = NT == 9 ? 8 : 7;
+  constexpr int LEN = TAPE_AOS, COFF = NT * NBASIS;
+  const int tid = blockIdx.x * THREADS + threadIdx.x;
+  const int i = tid >> 2;
+  const int l = tid & 3;
+  const bool valid = i < n;
+  const int ii = valid ? i : n - 1;
+  QuadChol c;
+  quad_chol_factor(c, c_tab, mom, soa_ld(n), ii, l, interp != 0);
+  const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
+  double* rec = (aos && valid) ? aos + (int64_t)i * LEN : nullptr;
+  double rmax2 = 0.0;
+  sfor<0, NT / 3>([&](auto GI) {
+    constexpr int t0 = 1 + 3 * GI;
+    double rows[3][5];
+    quad_chol_inverse_rows<t0, 3>(c, l, rows);
+    if (rec) {
+      sfor<0, 3>([&](auto RI) {
+        sfor<0, 5>([&](auto R) {
+          constexpr int rho = R;
+          rec[(3 * GI + RI) * NBASIS + 4 * rho + l] = st == 0 ? rows[RI][rho] : 0.0;
+        });
+      });
+    }
+    if (list) rmax2 = fmax(rmax2, quad_rows_hat_norm2<t0, 3>(c, l, rows));
+  });
+  constexpr int LS = 2;  // lockstep solves: two keep the kernel within 256 VGPRs
+  for (int f0 = 0; f0 < NF; f0 += LS) {
+    double y[LS][5], x[LS][5];
+#pragma unroll
+    for (int r = 0; r < LS; ++r)
+#pragma unroll
+      for (int rho = 0; rho < 5; ++rho) {
+        const double b =
+            f0 + r < NF ? bc[((int64_t)(f0 + r) * NBASIS + 4 * rho + l) * soa_ld(n) + ii] : 0.0;
+        y[r][rho] = (interp && rho == 0 && l == 0) ? 0.0 : b * c.s_own[rho];
+      }
+    quad_chol_solve_n<0, LS>(c, l, y, x);
+    if (valid) {
+#pragma unroll
+      for (int r = 0; r < LS; ++r) {
+        if (f0 + r >= NF) break;
+#pragma unroll
+        for (int rho = 0; rho < 5; ++rho) {
+          const double v = st == 0 ? x[r][rho] * c.s_own[rho] : 0.0;
+          const int cf = 4 * rho + l;  // coefficient index
+          if (cf >= 1 && cf <= NT) bc[((int64_t)(f0 + r) * NT + cf - 1) * soa_ld(n) + i] = v;
+          if (rec) rec[COFF + (f0 + r) * NBASIS + cf] = v;
+        }
+      }
+    }
+  }
+  if (valid && l == 0) {
+    status[i] = st;
+    if (list && st == 0 && !(rmax2 <= rcut * rcut)) list[atomicAdd(count, 1)] = i;
+  }
+}
+
 // X_r = A^{-1} R_r for NR general right-hand sides R (SoA [NR][20][n]);
 // status as in k_factor.  NaN-free: a failed factorization writes zeros.
 template <int NR>
@@ -508,6 +671,34 @@ hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const d
   return hipGetLastError();
 }
 
+hipError_t launch_fit_b(hipStream_t s, const EvalArgs& a, int nf, int fpl, double* bout) {
+  const unsigned grid = grid_for((int64_t)a.n * 8, THREADS);
+#define PHB_FIT_B(NF, FPL)                                                                    \
+  hipLaunchKernelGGL((k_fit_b<NF, FPL>), dim3(grid), dim3(THREADS), 0, s, a.n, a.geo, a.fq,   \
+                     a.off, a.idx, a.box, a.rf_ratio, a.wkind, a.rows, bout)
+  if (nf == 8) {
+    if (fpl == 2) PHB_FIT_B(8, 2); else PHB_FIT_B(8, 4);
+  } else {
+    if (fpl == 2) PHB_FIT_B(7, 2); else PHB_FIT_B(7, 4);
+  }
+#undef PHB_FIT_B
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_fit(hipStream_t s, const EvalArgs& a, int nrows, const double* mom,
+                             double* bc, double* aos, int32_t* status, double rcut,
+                             int32_t* list, int32_t* count) {
+  const unsigned grid = grid_for((int64_t)a.n * 4, THREADS);
+  const int interp = a.fit == PHB_FIT_INTERP19;
+  if (nrows == 3)
+    hipLaunchKernelGGL((k_factor_fit<3>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, bc,
+                       aos, status, interp, rcut, list, count);
+  else
+    hipLaunchKernelGGL((k_factor_fit<9>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, bc,
+                       aos, status, interp, rcut, list, count);
+  return hipGetLastError();
+}
+
 template <int G, class CT>
 static hipError_t derivs_g(hipStream_t s, const EvalArgs& a, const double* gop,
                            const int32_t* status, int nf, const double* fields, double* d1,
@@ -566,23 +757,15 @@ hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* la
 
 hipError_t launch_apply_rhs(hipStream_t s, const EvalArgs& a, int lanes, double gamma,
                             const Stab& sb, const double* gop, const int32_t* status, double* rhs,
-                            double* dxdt, double* tape, bool fp32,
-                            const int32_t* list, const int32_t* count) {
+                            double* dxdt, double* tape, const int32_t* list,
+                            const int32_t* count) {
   // nine LDS rows per particle: eight lanes per particle keep a block's rows
-  // at 46 KB (FP64)
-  if (fp32) {
-    if (sb.on()) return rhs_g<8, true, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
-    switch (lanes) {
-      case 1: return rhs_g<1, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
-      case 2: return rhs_g<2, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
-      default: return rhs_g<4, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
-    }
-  }
-  if (sb.on()) return rhs_g<8, true>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+  // small enough for several blocks per CU
+  if (sb.on()) return rhs_g<8, true, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
   switch (lanes) {
-    case 1: return rhs_g<1, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
-    case 2: return rhs_g<2, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
-    default: return rhs_g<4, false>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+    case 1: return rhs_g<1, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+    case 2: return rhs_g<2, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
+    default: return rhs_g<4, false, float>(s, a, gamma, sb, gop, status, rhs, dxdt, tape, list, count);
   }
 }
 

@@ -33,16 +33,32 @@ struct EvalArgs {
   int n_all = 0;
 };
 
-// Tape of the forward evaluation, per particle (SoA, n entries each):
-// 21 gradients (V, B, sigma x 3), the status, grad rho, grad div V and
-// grad div B (written only with the stabilisers on), then the 84 moments,
-// FP64-assembled in both forms.
+// Tape of the forward evaluation.  First TAPE_DOUBLES rows (SoA, leading
+// dimension soa_ld(n)): 21 gradients (V, B, sigma x 3), the status, grad rho,
+// grad div V and grad div B (written only with the stabilisers on), then the
+// 84 moments, FP64-assembled in both forms.  Then, written by the FP64 form,
+// one block of TAPE_AOS doubles per particle (AoS, the reverse mode's
+// per-owner data): the operator rows G (rows 1..nr of A^{-1}, nr = 3, or 9
+// with the stabilisers) at 0 and the fit coefficients C = A^{-1} B of the
+// fields those rows apply to (7 or 8 x 20) at nr x 20.
 constexpr int TAPE_STATUS = 21;
 constexpr int TAPE_GRHO = 22;
 constexpr int TAPE_GDV = 25;
 constexpr int TAPE_GDB = 28;
 constexpr int TAPE_MOM = 31;
 constexpr int TAPE_DOUBLES = TAPE_MOM + NMOM;
+constexpr int TAPE_AOS = (9 + 8) * NBASIS;
+// Doubles of a tape of n particles.
+__host__ __device__ constexpr int64_t tape_doubles(int64_t n) {
+  return n <= 0 ? 0 : (int64_t)TAPE_DOUBLES * soa_ld(n) + (int64_t)TAPE_AOS * n;
+}
+// The AoS block of the tape.
+__host__ __device__ inline double* tape_aos(double* tape, int64_t n) {
+  return tape + (size_t)TAPE_DOUBLES * soa_ld(n);
+}
+__host__ __device__ inline const double* tape_aos(const double* tape, int64_t n) {
+  return tape + (size_t)TAPE_DOUBLES * soa_ld(n);
+}
 
 // geo (and fq when q != null) from the SoA inputs.
 hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* lam,
@@ -56,6 +72,18 @@ hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* m
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,
                          double* gop, int32_t* status, int nscreen = 0, double rcut = 0.0,
                          int32_t* list = nullptr, int32_t* count = nullptr);
+// Data form of the FP64 fit.  B_f = sum_j w_j p_j (f_j - f_i) for the last nf
+// (7 or 8) fields of the packed records, into bout [nf][20][soa_ld(n)]; fpl
+// (2 or 4) fields per lane.
+hipError_t launch_fit_b(hipStream_t s, const EvalArgs& a, int nf, int fpl, double* bout);
+// Equilibrated Cholesky of the moments, status, rows 1..nrows of A^{-1} (3 or
+// 9; nf = 7 or 8 fields to match) and C_f = A^{-1} B_f from B in bc
+// [nf][20][soa_ld(n)]; the derivative rows (coefficients 1..nrows) in place
+// over bc as [nf][nrows][soa_ld(n)].  With aos (the tape's AoS block) G and
+// all of C also go there.  Screen (list != null) as for launch_factor.
+hipError_t launch_factor_fit(hipStream_t s, const EvalArgs& a, int nrows, const double* mom,
+                             double* bc, double* aos, int32_t* status, double rcut,
+                             int32_t* list, int32_t* count);
 // X = A^{-1} R for nr (1..8) right-hand sides given as SoA [nr][20][n].
 hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
                                const double* mom, const double* rhs, double* x, int32_t* status,
@@ -67,11 +95,12 @@ hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, cons
                                double* d2, bool fp32 = false, const int32_t* list = nullptr,
                                const int32_t* count = nullptr);
 // Time derivatives from the operator rows gop: three rows (ideal), nine with
-// the stabilisers on.  fp32: the neighbor loop in FP32 (the mixed form).
-// list, count as for launch_apply_derivs (not with a.rows).
+// the stabilisers on, the neighbor loop in FP32 (the mixed form; the FP64
+// form solves for the fit coefficients instead).  list, count as for
+// launch_apply_derivs (not with a.rows).
 hipError_t launch_apply_rhs(hipStream_t s, const EvalArgs& a, int lanes, double gamma,
                             const Stab& sb, const double* gop, const int32_t* status, double* rhs,
-                            double* dxdt, double* tape, bool fp32 = false,
-                            const int32_t* list = nullptr, const int32_t* count = nullptr);
+                            double* dxdt, double* tape, const int32_t* list = nullptr,
+                            const int32_t* count = nullptr);
 
 }  // namespace phb

@@ -195,6 +195,23 @@ __global__ void __launch_bounds__(THREADS)
   if (l == 0) done[k] = first ? 0 : (conv ? 1 : 0);
 }
 
+// The listed particles' refined coefficients (nf fields, cbuf [nf][20][ldc]
+// by list position) into their tape records at coff (len doubles per
+// particle); grid-stride.
+__global__ void __launch_bounds__(THREADS)
+    k_ref_tape_c(const int32_t* __restrict__ list, const int32_t* __restrict__ count, int nf,
+                 const double* __restrict__ cbuf, int64_t ldc, double* __restrict__ aos, int len,
+                 int coff) {
+  const int64_t tot = (int64_t)*count * nf * NBASIS;
+  for (int64_t t = (int64_t)blockIdx.x * THREADS + threadIdx.x; t < tot;
+       t += (int64_t)gridDim.x * THREADS) {
+    const int k = (int)(t / (nf * NBASIS));
+    const int e = (int)(t % (nf * NBASIS));
+    const int i = list[k];
+    aos[(int64_t)i * len + coff + e] = cbuf[e * ldc + k];
+  }
+}
+
 // ---- reverse mode --------------------------------------------------------
 // K_t = sum_f Ubar[f][t] c_f (coefficient space) of the listed owners, into
 // their owner records (K rows at koff, Ubar [nfa][nr] at uoff); one thread
@@ -536,21 +553,21 @@ void take_refine_state(Workspace& ws, int64_t n, RefineBufs& r) {
   r.done = ws.take<int32_t>(soa_ld(n));
 }
 
-void plan_refine(Workspace& ws, int64_t n, int nf) {
+void plan_refine(Workspace& ws, int64_t n, int nf, bool with_c) {
   const size_t nd = (size_t)soa_ld(n) * sizeof(double);
-  ws.plan((size_t)n * sizeof(int32_t));  // list
-  ws.plan(sizeof(int32_t));              // count
-  ws.plan((size_t)nf * NBASIS * nd);     // coefficients
-  ws.plan((size_t)nf * NBASIS * nd);     // residual sums
+  ws.plan((size_t)n * sizeof(int32_t));               // list
+  ws.plan(sizeof(int32_t));                           // count
+  if (with_c) ws.plan((size_t)nf * NBASIS * nd);      // coefficients
+  ws.plan((size_t)nf * NBASIS * nd);                  // residual sums
   plan_refine_state(ws, n);
 }
 
-RefineBufs take_refine(Workspace& ws, int64_t n, int nf) {
+RefineBufs take_refine(Workspace& ws, int64_t n, int nf, bool with_c) {
   RefineBufs r;
   r.ldc = soa_ld(n);
   r.list = ws.take<int32_t>(n);
   r.count = ws.take<int32_t>(1);
-  r.cbuf = ws.take<double>((size_t)nf * NBASIS * r.ldc);
+  r.cbuf = with_c ? ws.take<double>((size_t)nf * NBASIS * r.ldc) : nullptr;
   r.dbuf = ws.take<double>((size_t)nf * NBASIS * r.ldc);
   take_refine_state(ws, n, r);
   return r;
@@ -574,21 +591,21 @@ int refine_fits(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int n
   return hip_check(ctx, hipGetLastError(), "fit refinement");
 }
 
-int refine_adjoint(phb_ctx* ctx, const EvalArgs& a, bool stab, const double* mom,
-                   const RefineBufs& r, double* orec, int orec_len, int koff, int uoff) {
+int refine_tape(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom, const RefineBufs& r,
+                double* aos) {
+  const int nf = nr == 9 ? 8 : 7;
+  Prof pf(ctx, "k_ref_tape");
+  hipLaunchKernelGGL(k_ref_tape_c, dim3(list_grid((int64_t)a.n * nf * NBASIS)), dim3(THREADS), 0,
+                     ctx->stream, r.list, r.count, nf, r.cbuf, r.ldc, aos, TAPE_AOS, nr * NBASIS);
+  int rc = hip_check(ctx, hipGetLastError(), "tape coefficients");
+  return rc ? rc : refine_oprows(ctx, a, nr, mom, r, aos, TAPE_AOS);
+}
+
+int refine_oprows(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom,
+                  const RefineBufs& r, double* orec, int orec_len) {
   hipStream_t s = ctx->stream;
   const int n = a.n;
-  const int nr = stab ? 9 : 3;
-  const int nfa = stab ? 8 : 7;
-  int rc;
-  // refined coefficients of the fields the owner's rows are applied to
-  if ((rc = refine_fits(ctx, a, a.fq, stab ? 0 : 1, nfa, mom, r))) return rc;
-  Prof pf(ctx, "k_ref_adjoint");
-  hipLaunchKernelGGL(k_ref_adj_k, dim3(grid_for((int64_t)n * nr, THREADS)), dim3(THREADS), 0, s, r.list,
-                     r.count, nr, nfa, orec_len, koff, uoff, r.cbuf, r.ldc, orec);
-  // the residual sums, last corrections and flags are free again:
-  // refinement steps on the operator rows (r.dbuf holds at least nr x 20
-  // rows)
+  Prof pf(ctx, "k_ref_rows");
   for (int step = 0; step < REFINE_PASSES - 1; ++step) {
     const int first = step == 0;
     for (int r0 = 0; r0 < nr; r0 += 3)
@@ -599,7 +616,28 @@ int refine_adjoint(phb_ctx* ctx, const EvalArgs& a, bool stab, const double* mom
                        s, mom, (int64_t)soa_ld(n), r.list, r.count, nr, r.dbuf, r.ldc, orec,
                        orec_len, a.fit == PHB_FIT_INTERP19, first, r.prev, r.done);
   }
-  return hip_check(ctx, hipGetLastError(), "reverse-mode refinement");
+  return hip_check(ctx, hipGetLastError(), "operator-row refinement");
+}
+
+int refine_adjoint(phb_ctx* ctx, const EvalArgs& a, bool stab, const double* mom,
+                   const RefineBufs& r, double* orec, int orec_len, int koff, int uoff) {
+  hipStream_t s = ctx->stream;
+  const int n = a.n;
+  const int nr = stab ? 9 : 3;
+  const int nfa = stab ? 8 : 7;
+  int rc;
+  // refined coefficients of the fields the owner's rows are applied to
+  if ((rc = refine_fits(ctx, a, a.fq, stab ? 0 : 1, nfa, mom, r))) return rc;
+  {
+    Prof pf(ctx, "k_ref_adjoint");
+    hipLaunchKernelGGL(k_ref_adj_k, dim3(grid_for((int64_t)n * nr, THREADS)), dim3(THREADS), 0, s,
+                       r.list, r.count, nr, nfa, orec_len, koff, uoff, r.cbuf, r.ldc, orec);
+    if ((rc = hip_check(ctx, hipGetLastError(), "reverse-mode refinement"))) return rc;
+  }
+  // the residual sums, last corrections and flags are free again:
+  // refinement steps on the operator rows (r.dbuf holds at least nr x 20
+  // rows)
+  return refine_oprows(ctx, a, nr, mom, r, orec, orec_len);
 }
 
 hipError_t launch_rows_rhs_finish(hipStream_t s, const EvalArgs& a, bool stab, const double* coef,

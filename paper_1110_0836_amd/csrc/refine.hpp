@@ -30,8 +30,9 @@ struct RefineBufs {
   double* prev;
   int32_t* done;
 };
-void plan_refine(Workspace& ws, int64_t n, int nf);
-RefineBufs take_refine(Workspace& ws, int64_t n, int nf);
+// nf rows of residual sums per particle; with_c: and of coefficients.
+void plan_refine(Workspace& ws, int64_t n, int nf, bool with_c = true);
+RefineBufs take_refine(Workspace& ws, int64_t n, int nf, bool with_c = true);
 // prev and done alone (for callers that lend their own list and buffers).
 void plan_refine_state(Workspace& ws, int64_t n);
 void take_refine_state(Workspace& ws, int64_t n, RefineBufs& r);
@@ -41,6 +42,16 @@ void take_refine_state(Workspace& ws, int64_t n, RefineBufs& r);
 // moments [84][soa_ld(n)] by row index.
 int refine_fits(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
                 const double* mom, const RefineBufs& r);
+
+// Refinement steps on the operator rows G (nr rows of 20 at the start of each
+// listed owner's record of orec_len doubles); r.dbuf holds nr x 20 rows.
+int refine_oprows(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom,
+                  const RefineBufs& r, double* orec, int orec_len);
+
+// The tape's AoS block for the listed particles: their refined coefficients
+// (r.cbuf, as refine_fits leaves them), then refined operator rows.
+int refine_tape(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom, const RefineBufs& r,
+                double* aos);
 
 // Reverse mode of the listed owners: refined coefficients, K = Ubar C^T and
 // refinement steps on the operator rows G, written into their owner records

@@ -28,6 +28,18 @@ k_adj_pairs      per pair: geometry and dw/dq (18), basis (16),
                  derivatives (30 FMA), dbar (12), sums (10)               = 683
 k_adj_gather     memory bound: 80 B per pair record, 232 B per particle.
 
+FP64 data form (the fit coefficients are solved for, and taped with the
+operator rows for the reverse mode):
+k_fit_b<7>       per pair: geometry and weight (15), basis (16), per field
+                 w df (2) and 20 FMA (40), seven fields                   = 325
+k_factor_fit<3>  per particle: equilibration + Cholesky (3330), three
+                 unit-vector solves (2234), seven general solves (7 x 820),
+                 row norms of the screen (120), output scaling (260)      = 11684
+k_rows_rhs_finish per particle: gradient scaling (21) + right-hand side   = 66
+k_adj_u          per particle: pointwise adjoint                          = 150
+k_adj_pairs_w    as k_adj_pairs; the owner's K = Ubar C^T (840 per
+                 particle) is left out of the count.
+
 Mixed form (FP32 arithmetic after the FP64 displacement, FP64 factor and
 solves; counted the same way, whatever the precision):
 k_moments<fp32>  as k_moments                                            = 187
@@ -62,6 +74,7 @@ PER_PAIR = {
     "k_moments<fp32>": 187,
     "k_moments<tape>": 187,
     "k_mixed_b": 325,
+    "k_fit_b<7>": 325,
     "k_mixed_resid": 612,
     "k_apply_rhs": 203,
     "k_apply_rhs<fp32>": 203,
@@ -72,6 +85,9 @@ PER_PAIR = {
 }
 PER_PARTICLE = {
     "k_factor<3>": 5704,
+    "k_factor_fit<3>": 11684,
+    "k_rows_rhs_finish": 66,
+    "k_adj_u": 150,
     "k_mixed_factor": 13224,
     "k_mixed_resid": 861,
     "k_mixed_rhs_finish": 66,
