@@ -124,7 +124,9 @@ int phb_destroy(phb_ctx* ctx);
 /* Rebind the context to another stream of the same device. */
 int phb_set_stream(phb_ctx* ctx, void* hip_stream);
 /* Grow the workspace for up to n_max particles and nnz_max neighbor entries
- * so that later calls within those sizes allocate nothing. */
+ * so that later calls of the neighbor build (also _async), the transpose,
+ * phb_mls_derivs, phb_mhd_rhs and the reverse mode (also _async) within
+ * those sizes allocate nothing: what a HIP graph capture of them needs. */
 int phb_reserve(phb_ctx* ctx, int64_t n_max, int64_t nnz_max);
 /* Static text for a return code. */
 const char* phb_strerror(int code);
@@ -136,10 +138,26 @@ const char* phb_last_error(phb_ctx* ctx);
  * idx: int32[idx_capacity].  *nnz_out (host) receives the total number of
  * entries.  If it exceeds idx_capacity the call returns PHB_ECAPACITY, fills
  * offsets but leaves idx unspecified; call again with a larger buffer.
- * Synchronizes the context stream (sizes are read back).  n < 2^31. */
+ * Synchronizes the context stream once, at the end (nnz and the status are
+ * read back).  n < 2^31. */
 int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                         const double* lambda, int64_t* offsets, int32_t* idx,
                         int64_t idx_capacity, int64_t* nnz_out);
+/* The same without any host synchronization, for capture in a HIP graph:
+ * nnz_dev (int64, device) receives the total and flag_dev (int32, device)
+ * the status: 0, or a combination of PHB_NB_OVERFLOW (more than
+ * idx_capacity entries: offsets and nnz are written, idx is not),
+ * PHB_NB_INVALID (a position outside [0, L) or not finite, or a lambda that
+ * is not positive) and PHB_NB_RADIUS (r_f >= L/2 on a periodic axis); with
+ * either of the last two, offsets and nnz are zero.  Asynchronous; it
+ * allocates nothing once the workspace covers the set (phb_reserve), so a
+ * capture of it needs the workspace reserved first. */
+#define PHB_NB_OVERFLOW 1
+#define PHB_NB_INVALID 2
+#define PHB_NB_RADIUS 4
+int phb_neighbors_build_async(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                              const double* lambda, int64_t* offsets, int32_t* idx,
+                              int64_t idx_capacity, int64_t* nnz_dev, int32_t* flag_dev);
 /* The lists of the m particles rows[0 .. m) (int32, in [0, n); m may be 0)
  * among all n: offsets int64[m+1], idx as for phb_neighbors_build, rows in
  * the given order, each sorted ascending.  The same errors. */
@@ -151,8 +169,10 @@ int phb_neighbors_build_rows(phb_ctx* ctx, const phb_params* p, int64_t n, const
 /* Transposed lists for the reverse-mode kernels: t_offsets int64[n+1],
  * t_src int32[nnz] (row j lists, ascending, every i whose row holds j),
  * t_pos int32[nnz] (for forward entry s = (i, j): the index into t_src at
- * which i appears in row j).  nnz = offsets[n].  PHB_EINVAL if nnz exceeds
- * PHB_NNZ_MAX (the positions are int32).  Asynchronous. */
+ * which i appears in row j).  nnz = offsets[n], or any bound of it (the
+ * idx capacity of a build whose total stays on the device): it only sizes
+ * the scratch.  PHB_EINVAL if nnz exceeds PHB_NNZ_MAX (the positions are
+ * int32).  Asynchronous. */
 int phb_neighbors_transpose(phb_ctx* ctx, int64_t n, int64_t nnz, const int64_t* offsets,
                             const int32_t* idx, int64_t* t_offsets, int32_t* t_src,
                             int32_t* t_pos);
@@ -251,6 +271,17 @@ int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n, const doub
                         const int64_t* t_offsets, const int32_t* t_src, const int32_t* t_pos,
                         const double* q, const double* rhs_bar, const double* dxdt_bar,
                         double* q_bar, double* pos_bar, const void* tape);
+/* The same without reading offsets[n] back (phb_mhd_rhs_adjoint does, to size
+ * its pair records): nnz_bound >= offsets[n] sizes them instead, so that the
+ * call can be captured in a HIP graph after phb_neighbors_build_async, whose
+ * total stays on the device (its idx capacity is such a bound).  Runs the
+ * one-wavefront-per-owner pair schedule whatever adj_pairs_mode says. */
+int phb_mhd_rhs_adjoint_async(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
+                              const double* lambda, const int64_t* offsets, const int32_t* idx,
+                              const int64_t* t_offsets, const int32_t* t_src,
+                              const int32_t* t_pos, const double* q, const double* rhs_bar,
+                              const double* dxdt_bar, double* q_bar, double* pos_bar,
+                              const void* tape, int64_t nnz_bound);
 
 /* ---- predictor-corrector step (Sec. 2) -----------------------------------
  * Advance (pos, q) in place by dt with Heun's trapezoidal scheme:

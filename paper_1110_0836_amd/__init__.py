@@ -32,6 +32,9 @@ PHB_W_POLY3 = 0
 PHB_W_UNIT = 1
 PHB_FIT_FULL20 = 0
 PHB_FIT_INTERP19 = 1
+PHB_NB_OVERFLOW = 1
+PHB_NB_INVALID = 2
+PHB_NB_RADIUS = 4
 
 EXPORTS = [
     "phb_create", "phb_destroy", "phb_set_stream", "phb_reserve", "phb_strerror",
@@ -41,6 +44,7 @@ EXPORTS = [
     "phb_evolve", "phb_courant_dt", "phb_tune", "phb_batch_create", "phb_batch_destroy", "phb_batch_neighbors", "phb_batch_run",
     "phb_batch_capture", "phb_batch_launch", "phb_divb_norm", "phb_bin_mean",
     "phb_neighbors_build_rows", "phb_mhd_rhs_rows", "phb_evolve_blocks", "phb_mhd_rhs_noalloc",
+    "phb_neighbors_build_async", "phb_mhd_rhs_adjoint_async",
 ]
 
 
@@ -126,6 +130,7 @@ def lib():
             "phb_strerror": (ctypes.c_char_p, [I]),
             "phb_last_error": (ctypes.c_char_p, [P]),
             "phb_neighbors_build": (I, [P, PP, I64, P, P, P, P, I64, ctypes.POINTER(I64)]),
+            "phb_neighbors_build_async": (I, [P, PP, I64, P, P, P, P, I64, P, P]),
             "phb_neighbors_transpose": (I, [P, I64, I64, P, P, P, P, P]),
             "phb_spatial_order": (I, [P, PP, I64, P, P, P]),
             "phb_permute": (I, [P, I64, P, I32, P, P]),
@@ -134,6 +139,8 @@ def lib():
             "phb_mhd_rhs_noalloc": (I, [P, PP, I64, P, P, P, P, P, P, P, P, P]),
             "phb_tape_bytes": (I64, [I64]),
             "phb_mhd_rhs_adjoint": (I, [P, PP, I64, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+            "phb_mhd_rhs_adjoint_async": (I, [P, PP, I64, P, P, P, P, P, P, P, P, P, P, P, P, P,
+                                              I64]),
             "phb_pc_step": (I, [P, PP, I64, D, P, P, P, P, P, I64, ctypes.POINTER(I64), P]),
             "phb_profile": (I, [P, I]),
             "phb_tune_set": (I, [P, ctypes.c_char_p, I]),
@@ -221,6 +228,17 @@ def phb_neighbors_build(setup, pos, lam, offsets, idx, capacity):
     return rc, nnz.value
 
 
+def phb_neighbors_build_async(setup, pos, lam, offsets, idx, capacity, nnz_dev, flag_dev):
+    """The build without host synchronization: nnz_dev (int64[1]) and flag_dev
+    (int32[1]) are device tensors that receive the total and the status bits
+    (PHB_NB_*)."""
+    ctx = context(pos.device.index)
+    p = setup.params()
+    _check(ctx, lib().phb_neighbors_build_async(ctx, ctypes.byref(p), lam.shape[0], _f64(pos),
+                                                _f64(lam), _ptr(offsets), _ptr(idx), capacity,
+                                                _ptr(nnz_dev), _ptr(flag_dev)))
+
+
 def phb_neighbors_transpose(offsets, idx, t_offsets, t_src, t_pos):
     ctx = context(offsets.device.index)
     n = offsets.shape[0] - 1
@@ -293,6 +311,25 @@ def phb_mhd_rhs_adjoint(setup, pos, lam, offsets, idx, t_offsets, t_src, t_pos, 
                                           _ptr(t_src), _ptr(t_pos), _f64(q), _f64(rhs_bar),
                                           _ptr(dxdt_bar), _f64(q_bar), _f64(pos_bar),
                                           _ptr(tape)))
+
+
+def phb_mhd_rhs_adjoint_async(setup, pos, lam, offsets, idx, t_offsets, t_src, t_pos, q,
+                              rhs_bar, dxdt_bar, q_bar, pos_bar, tape, nnz_bound):
+    """phb_mhd_rhs_adjoint without the read-back of offsets[n]: nnz_bound sizes
+    the pair records (capturable in a HIP graph)."""
+    ctx = context(pos.device.index)
+    p = setup.params()
+    _check(ctx, lib().phb_mhd_rhs_adjoint_async(ctx, ctypes.byref(p), lam.shape[0], _f64(pos),
+                                                _f64(lam), _ptr(offsets), _ptr(idx),
+                                                _ptr(t_offsets), _ptr(t_src), _ptr(t_pos),
+                                                _f64(q), _f64(rhs_bar), _ptr(dxdt_bar),
+                                                _f64(q_bar), _f64(pos_bar), _ptr(tape),
+                                                int(nnz_bound)))
+
+
+def phb_reserve(n_max, nnz_max, device=None):
+    ctx = context(device)
+    _check(ctx, lib().phb_reserve(ctx, int(n_max), int(nnz_max)))
 
 
 def phb_pc_step(setup, dt, pos, q, lam, offsets, idx, capacity, status):

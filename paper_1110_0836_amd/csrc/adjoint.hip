@@ -895,10 +895,12 @@ __global__ void __launch_bounds__(THREADS)
 }
 
 // Inverse of t_pos: for transposed entry k, the forward entry it came from.
+// nnz_true: offsets[n] (the launch covers a bound of it).
 __global__ void __launch_bounds__(THREADS)
-    k_invert(int64_t nnz, const int32_t* __restrict__ t_pos, int32_t* __restrict__ t_slot) {
+    k_invert(int64_t nnz, const int64_t* __restrict__ nnz_true, const int32_t* __restrict__ t_pos,
+             int32_t* __restrict__ t_slot) {
   const int64_t s = (int64_t)blockIdx.x * THREADS + threadIdx.x;
-  if (s < nnz) t_slot[t_pos[s]] = (int32_t)s;
+  if (s < nnz && s < *nnz_true) t_slot[t_pos[s]] = (int32_t)s;
 }
 
 // ---- 5. gather over the transposed lists ------------------------------------
@@ -1018,10 +1020,59 @@ void launch_yrows(hipStream_t s, const EvalArgs& a, const double* tape, const do
 // the pair kernel).  Operator form (the mixed form with the caller's tape,
 // which holds no G or C): Y, a second factorization for G and K = (A^{-1}
 // Y)^T, and the screened owners' refinement.
+// Workspace of the reverse pass (see adjoint_rhs for the pieces).
+static void plan_adjoint(Workspace& ws, int64_t n, int64_t nnz, const phb_params* p,
+                         bool need_tape, bool lane_pairs) {
+  const bool stab = stab_of(p).on();
+  const int NRr = stab ? Shape<true>::NR : Shape<false>::NR;
+  const int NFAr = stab ? Shape<true>::NFA : Shape<false>::NFA;
+  const int ORr = stab ? Shape<true>::OREC : Shape<false>::OREC;
+  const int RCr = stab ? Shape<true>::REC : Shape<false>::REC;
+  const bool data_form = need_tape || p->precision == PHB_FP64;
+  const size_t nd = (size_t)n * sizeof(double);
+  const size_t ndl = (size_t)soa_ld(n) * sizeof(double);  // the padded stride's rows
+  const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
+  ws.plan((size_t)n * sizeof(double4));  // packed geometry
+  ws.plan(8 * nd);                       // packed fields
+  ws.plan(8 * nd);                       // direct qbar
+  ws.plan((size_t)RCr * nd);             // own sums
+  ws.plan((size_t)std::max<int64_t>(nnz, 1) * RCr * sizeof(double));  // pair records
+  ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
+  ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
+  if (data_form) {
+    ws.plan((size_t)NFAr * NRr * nd);               // Ubar
+    if (lane_pairs) ws.plan((size_t)ORr * nd);      // owner records
+  } else {
+    ws.plan((size_t)NRr * NBASIS * ndl);  // Y
+    ws.plan((size_t)ORr * nd);            // owner records: G, K, Ubar
+    // screened owners; the residual sums also hold the operator rows'
+    // residual products, NRr x 20 of them
+    plan_refine(ws, n, std::max(NFAr, NRr));
+  }
+  if (need_tape) {
+    ws.plan((size_t)tape_doubles(n) * sizeof(double));  // private tape
+    ws.plan(8 * nd);                                     // rhs scratch
+    ws.plan(3 * nd);                                     // dxdt scratch
+    ws.plan((size_t)n * sizeof(int32_t));                // status scratch
+  }
+}
+
+size_t ws_bytes_adjoint(int64_t n, int64_t nnz, const phb_params* p, bool need_tape) {
+  phb_ctx dummy;
+  Workspace ws(&dummy);
+  plan_adjoint(ws, n, nnz, p, need_tape, !stab_of(p).on());
+  if (need_tape) {
+    phb_params p64 = *p;
+    p64.precision = PHB_FP64;
+    ws.plan(ws_bytes_rhs(n, &p64));
+  }
+  return ws.total;
+}
+
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
-                const double* tape_in, int64_t nnz_known) {
+                const double* tape_in, int64_t nnz_known, bool nnz_exact) {
   (void)t_src;
   const int n = a.n;
   const Stab sb = stab_of(p);
@@ -1051,37 +1102,14 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     return set_error(ctx, PHB_EINVAL, "nnz exceeds the int32 positions of the transposed lists");
   const bool need_tape = tape_in == nullptr;
   const bool data_form = need_tape || p->precision == PHB_FP64;
-  // the lane-per-entry schedule (ideal shape) reads whole owner records
-  const bool lane_pairs = !stab && ctx->adj_pairs_mode == 0;
+  // the lane-per-entry schedule (ideal shape) reads whole owner records and
+  // needs the exact entry count
+  const bool lane_pairs = !stab && ctx->adj_pairs_mode == 0 && nnz_exact;
   phb_params p64 = *p;
   p64.precision = PHB_FP64;
   Workspace ws(ctx);
-  const size_t nd = (size_t)n * sizeof(double);
-  const size_t ndl = (size_t)soa_ld(n) * sizeof(double);  // the padded stride's rows
+  plan_adjoint(ws, n, nnz, p, need_tape, lane_pairs);
   const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
-  ws.plan((size_t)n * sizeof(double4));  // packed geometry
-  ws.plan(8 * nd);                       // packed fields
-  ws.plan(8 * nd);                       // direct qbar
-  ws.plan((size_t)RCr * nd);             // own sums
-  ws.plan((size_t)std::max<int64_t>(nnz, 1) * RCr * sizeof(double));  // pair records
-  ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
-  ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
-  if (data_form) {
-    ws.plan((size_t)NFAr * NRr * nd);               // Ubar
-    if (lane_pairs) ws.plan((size_t)ORr * nd);      // owner records
-  } else {
-    ws.plan((size_t)NRr * NBASIS * ndl);  // Y
-    ws.plan((size_t)ORr * nd);            // owner records: G, K, Ubar
-    // screened owners; the residual sums also hold the operator rows'
-    // residual products, NRr x 20 of them
-    plan_refine(ws, n, std::max(NFAr, NRr));
-  }
-  if (need_tape) {
-    ws.plan((size_t)tape_doubles(n) * sizeof(double));  // private tape
-    ws.plan(8 * nd);                                     // rhs scratch
-    ws.plan(3 * nd);                                     // dxdt scratch
-    ws.plan((size_t)n * sizeof(int32_t));                // status scratch
-  }
   const size_t own_bytes = ws.total;
   if (need_tape) ws.plan(ws_bytes_rhs(n, &p64));  // the nested forward
   // Every tape holds FP64 moments: the mixed forward assembles them for the
@@ -1190,7 +1218,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;
   float* rec_f = reinterpret_cast<float*>(rec);
-  if (stab || ctx->adj_pairs_mode == 1) {
+  if (!lane_pairs) {
     // the stabilised shape runs the wavefront-per-owner schedule only
     Prof pf(ctx, stab ? "k_adj_pairs_w<stab>" : "k_adj_pairs_w");
     if (stab) {
@@ -1221,8 +1249,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   }
   if (slot_order && nnz > 0) {
     Prof pf(ctx, "k_invert");
-    hipLaunchKernelGGL(k_invert, dim3(grid_for(nnz, THREADS)), dim3(THREADS), 0, s, nnz, t_pos,
-                       t_slot);
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(nnz, THREADS)), dim3(THREADS), 0, s, nnz,
+                       a.off + n, t_pos, t_slot);
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint invert"))) return rc;
   }
   const int32_t* tsl = slot_order ? t_slot : nullptr;

@@ -10,7 +10,9 @@ namespace phb {
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
-                const double* tape, int64_t nnz_known);
+                const double* tape, int64_t nnz_known, bool nnz_exact = true);
+// Workspace bytes of adjoint_rhs (the lane-per-entry schedule's included).
+size_t ws_bytes_adjoint(int64_t n, int64_t nnz, const phb_params* p, bool need_tape);
 
 // Time derivatives in the requested precision (FP64 or mixed).
 int eval_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const double* q, double* rhs,

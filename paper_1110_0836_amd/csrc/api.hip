@@ -33,7 +33,9 @@ int Workspace::commit() {
                                              std::to_string(need) + " needed");
   if (ctx->arena_base != 0)
     return set_error(ctx, PHB_ESTATE, "nested workspace exceeds the reserved arena");
-  if (ctx->capturing)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (ctx->capturing ||
+      (hipStreamIsCapturing(ctx->stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone))
     return set_error(ctx, PHB_ESTATE, "a captured call would grow the workspace");
   hipError_t e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_check(ctx, e, "workspace sync");
@@ -149,7 +151,7 @@ int check_n(phb_ctx* ctx, int64_t n) {
 }
 
 // Device-side validation of positions and lambdas; returns min/max lambda.
-static constexpr int VALIDATE_BLOCKS = 512;
+static constexpr int VALIDATE_BLOCKS = NB_VALIDATE_BLOCKS;
 static int validate_inputs(phb_ctx* ctx, const phb_params* p, int n, const double* pos,
                            const double* lam, double* part, double* lmin, double* lmax) {
   const Box box = make_box(p);
@@ -181,45 +183,15 @@ static int validate_inputs(phb_ctx* ctx, const phb_params* p, int n, const doubl
   return PHB_OK;
 }
 
-static Grid make_grid(const phb_params* p, double rmin, int cells_per_rf, int64_t max_cells,
-                      int max_per_axis) {
-  Grid g;
-  double h = rmin / std::max(1, cells_per_rf);
-  for (;;) {
-    int64_t total = 1;
-    for (int a = 0; a < 3; ++a) {
-      double c = floor(p->L[a] / h);
-      if (c < 1) c = 1;
-      if (c > max_per_axis) c = max_per_axis;
-      g.nc[a] = (int)c;
-      total *= g.nc[a];
-    }
-    if (total <= max_cells) break;
-    h *= 1.26;
-  }
-  double hmin = 1e300;
-  for (int a = 0; a < 3; ++a) {
-    g.inv_h[a] = g.nc[a] / p->L[a];
-    hmin = std::min(hmin, p->L[a] / g.nc[a]);
-  }
-  g.margin = 1e-6 * hmin;
-  return g;
-}
+// Device words a synchronous build reads back: nnz, status, lambda range.
+struct NbStat {
+  int64_t nnz;
+  int32_t flag, pad;
+};
 
-// The grid is sized after validation, so its arrays are planned at the
-// largest allowed size.
-static const int64_t kMaxCells = int64_t(1) << 23;
-static void plan_neighbors(Workspace& ws, int64_t n, int64_t idx_capacity) {
-  ws.plan(3 * VALIDATE_BLOCKS * sizeof(double));
-  ws.plan((size_t)n * sizeof(int32_t));                 // key
-  ws.plan((size_t)(kMaxCells + 1) * sizeof(int32_t));   // cell count / cursor
-  ws.plan((size_t)(kMaxCells + 1) * sizeof(int32_t));   // cell start
-  ws.plan((size_t)scan_tmp_elems(kMaxCells) * sizeof(int32_t));
-  ws.plan((size_t)n * sizeof(int32_t));                 // sorted id
-  ws.plan((size_t)n * sizeof(double4));                 // sorted positions
-  ws.plan((size_t)n * sizeof(int32_t));                 // counts
-  ws.plan((size_t)scan_tmp_elems(n) * sizeof(int64_t));
-  ws.plan((size_t)std::max<int64_t>(idx_capacity, 1) * sizeof(int32_t));  // unsorted rows
+static void plan_neighbors(Workspace& ws, int64_t n, int64_t m, int64_t idx_capacity) {
+  ws.plan(nb_work_bytes(n, m, idx_capacity));
+  ws.plan(sizeof(NbStat));
 }
 
 static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, bool stab);
@@ -227,7 +199,7 @@ static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, boo
 size_t ws_bytes_neighbors(int64_t n, int64_t idx_capacity) {
   phb_ctx dummy;
   Workspace ws(&dummy);
-  plan_neighbors(ws, n, idx_capacity);
+  plan_neighbors(ws, n, n, idx_capacity);
   return ws.total;
 }
 
@@ -471,8 +443,25 @@ int phb_set_stream(phb_ctx* ctx, void* hip_stream) {
 
 int phb_reserve(phb_ctx* ctx, int64_t n_max, int64_t nnz_max) {
   if (!ctx || n_max < 0 || nnz_max < 0) return PHB_EINVAL;
+  // the largest workspace of the calls a capture may hold, over both
+  // precisions with the stabilisers on (the larger shapes)
+  phb_params p{};
+  p.gamma = 5.0 / 3.0;
+  p.rf_ratio = 2.3;
+  p.visc_grid = p.visc_adapt = p.divb_diff = 1.0;
+  size_t need = std::max(ws_bytes_neighbors(n_max, nnz_max),
+                         transpose_work_bytes(n_max, nnz_max));
+  for (int prec : {PHB_FP64, PHB_MIXED}) {
+    p.precision = prec;
+    for (int on : {0, 1}) {
+      p.visc_grid = p.visc_adapt = p.divb_diff = on ? 1.0 : 0.0;
+      need = std::max({need, ws_bytes_rhs(n_max, &p), ws_bytes_derivs(n_max, &p, true),
+                       ws_bytes_adjoint(n_max, nnz_max, &p, true),
+                       ws_bytes_adjoint(n_max, nnz_max, &p, false)});
+    }
+  }
   Workspace ws(ctx);
-  ws.plan((size_t)n_max * 1600 + (size_t)nnz_max * 96 + (64 << 20));
+  ws.plan(need);
   return ws.commit();
 }
 
@@ -571,15 +560,20 @@ int64_t phb_tape_bytes(int64_t n) {
 }  // extern "C"
 
 // Neighbor lists of all n particles (rows == nullptr) or of the m particles
-// rows[0 .. m), into offsets[m + 1] and idx.
+// rows[0 .. m), into offsets[m + 1] and idx.  Synchronous (nnz_dev == null:
+// one read-back of nnz and the status at the end, errors returned) or not
+// (the status word and nnz stay on the device).
 static int neighbors_build_impl(phb_ctx* ctx, const phb_params* p, int64_t n64,
                                 const double* pos, const double* lambda, int64_t m64,
                                 const int32_t* rows, int64_t* offsets, int32_t* idx,
-                                int64_t idx_capacity, int64_t* nnz_out, bool check_rows_) {
+                                int64_t idx_capacity, int64_t* nnz_out, bool check_rows_,
+                                int64_t* nnz_dev = nullptr, int32_t* flag_dev = nullptr) {
   if (!ctx) return PHB_EINVAL;
   int rc;
   if ((rc = check_params(ctx, p)) || (rc = check_n(ctx, n64))) return rc;
-  if (!pos || !lambda || !offsets || !nnz_out || idx_capacity < 0 || (idx_capacity > 0 && !idx))
+  const bool sync = nnz_dev == nullptr;
+  if (!pos || !lambda || !offsets || (sync ? !nnz_out : !flag_dev) || idx_capacity < 0 ||
+      (idx_capacity > 0 && !idx))
     return set_error(ctx, PHB_EINVAL, "null pointer or negative capacity");
   if (rows && (m64 < 0 || m64 > n64)) return set_error(ctx, PHB_EINVAL, "bad row count");
   hipSetDevice(ctx->device);
@@ -587,69 +581,39 @@ static int neighbors_build_impl(phb_ctx* ctx, const phb_params* p, int64_t n64,
   const int n = (int)n64;
   const int m = rows ? (int)m64 : n;
   const Box box = make_box(p);
-  const int64_t max_cells = kMaxCells;
   Workspace ws(ctx);
-  plan_neighbors(ws, n, idx_capacity);
+  plan_neighbors(ws, n, m, idx_capacity);
   if ((rc = ws.commit())) return rc;
-  double* part = ws.take<double>(3 * VALIDATE_BLOCKS);
-  int32_t* key = ws.take<int32_t>(n);
-  int32_t* ccount = ws.take<int32_t>(max_cells + 1);
-  int32_t* cstart = ws.take<int32_t>(max_cells + 1);
-  int32_t* cscan = ws.take<int32_t>(scan_tmp_elems(max_cells));
-  int32_t* sid = ws.take<int32_t>(n);
-  double4* spos = ws.take<double4>(n);
-  int32_t* cnt = ws.take<int32_t>(n);
-  int64_t* oscan = ws.take<int64_t>(scan_tmp_elems(n));
-  int32_t* tmp = ws.take<int32_t>(std::max<int64_t>(idx_capacity, 1));
-
-  double lmin, lmax;
-  if ((rc = validate_inputs(ctx, p, n, pos, lambda, part, &lmin, &lmax))) return rc;
-  const Grid g = make_grid(p, p->rf_ratio * lmin, ctx->cells_per_rf, max_cells, 1024);
-  { Prof pf_sort(ctx, "neighbors_cell_sort");
-  if ((rc = hip_check(ctx, launch_cell_sort(ctx->stream, n, pos, lambda, g, key, ccount, cstart,
-                                            cscan, sid, spos),
-                      "cell sort")))
-    return rc; }
-  if (m == 0) {  // no rows: an empty list
-    *nnz_out = 0;
-    // int64 zero is the bit pattern of 0.0
-    return hip_check(ctx, fill_f64(ctx->stream, reinterpret_cast<double*>(offsets), 0.0, 1),
-                     "empty offsets");
-  }
-  { Prof pf(ctx, "k_neighbors<false>");
+  const NbWork w = nb_work_take(ws, n, m, idx_capacity);
+  NbStat* st = ws.take<NbStat>(1);
+  int64_t* nnz_d = sync ? &st->nnz : nnz_dev;
+  int32_t* flag_d = sync ? &st->flag : flag_dev;
+  { Prof pf(ctx, "neighbors_build");
   if ((rc = hip_check(ctx,
-                      rows ? launch_neighbor_count_rows(ctx->stream, m, rows, n, pos, lambda, box,
-                                                        g, p->rf_ratio, cstart, sid, spos, cnt)
-                           : launch_neighbor_count(ctx->stream, n, box, g, p->rf_ratio, cstart,
-                                                   sid, spos, cnt),
-                      "neighbor count")))
+                      launch_neighbor_build(ctx->stream, n, pos, lambda, box, p->rf_ratio,
+                                            ctx->cells_per_rf, m, rows, w, offsets, idx,
+                                            idx_capacity, nnz_d, flag_d),
+                      "neighbor build")))
     return rc; }
-  if ((rc = hip_check(ctx, exclusive_scan_i32_to_i64(ctx->stream, cnt, m, offsets, oscan),
-                      "offset scan")))
-    return rc;
-  if ((rc = ensure_host(ctx, 64))) return rc;
+  if (!sync) return PHB_OK;
+  if ((rc = ensure_host(ctx, sizeof(NbStat)))) return rc;
   if ((rc = hip_check(ctx,
-                      hipMemcpyAsync(ctx->host, offsets + m, sizeof(int64_t),
-                                     hipMemcpyDeviceToHost, ctx->stream),
-                      "nnz read-back")))
+                      hipMemcpyAsync(ctx->host, st, sizeof(NbStat), hipMemcpyDeviceToHost,
+                                     ctx->stream),
+                      "nnz read-back")) ||
+      (rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "nnz sync")))
     return rc;
-  if ((rc = hip_check(ctx, hipStreamSynchronize(ctx->stream), "nnz sync"))) return rc;
-  const int64_t nnz = *reinterpret_cast<int64_t*>(ctx->host);
-  *nnz_out = nnz;
-  if (nnz > idx_capacity)
+  const NbStat h = *reinterpret_cast<const NbStat*>(ctx->host);
+  if (h.flag & PHB_NB_INVALID)
+    return set_error(ctx, PHB_EINVAL,
+                     "a position is outside [0, L) or not finite, or a lambda is not positive");
+  if (h.flag & PHB_NB_RADIUS)
+    return set_error(ctx, PHB_EINVAL, "r_f must stay below L/2 on periodic axes");
+  *nnz_out = h.nnz;
+  if (h.flag & PHB_NB_OVERFLOW)
     return set_error(ctx, PHB_ECAPACITY, "idx capacity " + std::to_string(idx_capacity) +
-                                             " < required " + std::to_string(nnz));
-  { Prof pf(ctx, "k_neighbors<true>");
-  if ((rc = hip_check(ctx,
-                      rows ? launch_neighbor_fill_rows(ctx->stream, m, rows, n, pos, lambda, box,
-                                                       g, p->rf_ratio, cstart, sid, spos, offsets,
-                                                       tmp)
-                           : launch_neighbor_fill(ctx->stream, n, box, g, p->rf_ratio, cstart,
-                                                  sid, spos, offsets, tmp),
-                      "neighbor fill")))
-    return rc; }
-  Prof pf_rs(ctx, "k_row_sort");
-  return hip_check(ctx, launch_row_sort(ctx->stream, m, offsets, tmp, idx), "row sort");
+                                             " < required " + std::to_string(h.nnz));
+  return PHB_OK;
 }
 
 namespace phb {
@@ -669,6 +633,14 @@ int phb_neighbors_build(phb_ctx* ctx, const phb_params* p, int64_t n64, const do
                         int64_t idx_capacity, int64_t* nnz_out) {
   return neighbors_build_impl(ctx, p, n64, pos, lambda, n64, nullptr, offsets, idx, idx_capacity,
                               nnz_out, false);
+}
+
+int phb_neighbors_build_async(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                              const double* lambda, int64_t* offsets, int32_t* idx,
+                              int64_t idx_capacity, int64_t* nnz_dev, int32_t* flag_dev) {
+  if (!nnz_dev) return ctx ? set_error(ctx, PHB_EINVAL, "null nnz") : PHB_EINVAL;
+  return neighbors_build_impl(ctx, p, n64, pos, lambda, n64, nullptr, offsets, idx, idx_capacity,
+                              nullptr, false, nnz_dev, flag_dev);
 }
 
 int phb_neighbors_build_rows(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
@@ -693,16 +665,12 @@ int phb_neighbors_transpose(phb_ctx* ctx, int64_t n64, int64_t nnz, const int64_
   hipSetDevice(ctx->device);
   const int n = (int)n64;
   Workspace ws(ctx);
-  ws.plan((size_t)n * sizeof(int32_t));
-  ws.plan((size_t)scan_tmp_elems(n) * sizeof(int64_t));
-  ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));
+  ws.plan(transpose_work_bytes(n, nnz));
   if ((rc = ws.commit())) return rc;
-  int32_t* cnt = ws.take<int32_t>(n);
-  int64_t* scan = ws.take<int64_t>(scan_tmp_elems(n));
-  int32_t* tmp = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  const TransposeWork w = transpose_work_take(ws, n, nnz);
+  Prof pf(ctx, "neighbors_transpose");
   return hip_check(ctx,
-                   launch_transpose(ctx->stream, n, nnz, offsets, idx, t_offsets, t_src, t_pos,
-                                    cnt, scan, tmp),
+                   launch_transpose(ctx->stream, n, offsets, idx, t_offsets, t_src, t_pos, w),
                    "transpose");
 }
 
@@ -872,6 +840,23 @@ int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n64, const do
   hipSetDevice(ctx->device);
   return adjoint_rhs(ctx, a, p, t_offsets, t_src, t_pos, q, rhs_bar, dxdt_bar, q_bar, pos_bar,
                      reinterpret_cast<const double*>(tape), -1);
+}
+
+int phb_mhd_rhs_adjoint_async(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
+                              const double* lambda, const int64_t* offsets, const int32_t* idx,
+                              const int64_t* t_offsets, const int32_t* t_src,
+                              const int32_t* t_pos, const double* q, const double* rhs_bar,
+                              const double* dxdt_bar, double* q_bar, double* pos_bar,
+                              const void* tape, int64_t nnz_bound) {
+  if (!ctx) return PHB_EINVAL;
+  EvalArgs a;
+  int rc;
+  if ((rc = eval_args(ctx, p, n64, pos, lambda, offsets, idx, &a))) return rc;
+  if (!t_offsets || !t_src || !t_pos || !q || !rhs_bar || !q_bar || !pos_bar || nnz_bound < 0)
+    return set_error(ctx, PHB_EINVAL, "null pointer or negative bound");
+  hipSetDevice(ctx->device);
+  return adjoint_rhs(ctx, a, p, t_offsets, t_src, t_pos, q, rhs_bar, dxdt_bar, q_bar, pos_bar,
+                     reinterpret_cast<const double*>(tape), nnz_bound, false);
 }
 
 int phb_pc_step(phb_ctx* ctx, const phb_params* p, int64_t n64, double dt, double* pos, double* q,

@@ -2,15 +2,20 @@
 // uniform cell grid, its transpose, a Peano-Hilbert particle ordering, and the
 // gather kernel used to apply an ordering.
 //
-// Pipeline of the search:
-//   validate + min/max lambda (read back)  ->  cell keys  ->  counting sort of
-//   particles into cells (positions copied in cell order, 32 B records)  ->
-//   per-particle count over the candidate cells  ->  scan to CSR offsets
-//   (nnz read back)  ->  fill  ->  per-row sort into ascending order.
+// Pipeline of the search, all on the device (no host synchronization):
+//   validate + lambda range  ->  grid sized from the smallest r_f (one
+//   thread)  ->  cell keys  ->  counting sort of particles into cells
+//   (positions copied in cell order, 32 B records)  ->  per-row count over
+//   the candidate cells  ->  scan to CSR offsets  ->  capacity check  ->
+//   fill, each row sorted ascending in registers and written once.
+// A status word carries invalid input and overflow from kernel to kernel;
+// every kernel after the check it concerns leaves at once when it is set.
 // Candidate cells along each axis are those that can hold a point within
 // r_f (plus a margin far above rounding) of the particle; the distance test
 // itself is the exact FP64 expression of the contract, so the lists match a
 // brute-force search bit for bit.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "neighbors.hpp"
 
@@ -62,10 +67,12 @@ __device__ __forceinline__ int cell_of(double x, double inv_h, int nc) {
 }
 
 __global__ void __launch_bounds__(NB_THREADS)
-    k_cell_key(int n, const double* __restrict__ pos, Grid g, int32_t* __restrict__ key,
+    k_cell_key(int n, const double* __restrict__ pos, const Grid* __restrict__ gp,
+               const int32_t* __restrict__ flag, int32_t* __restrict__ key,
                int32_t* __restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || *flag) return;
+  const Grid g = *gp;
   const int cx = cell_of(pos[i], g.inv_h[0], g.nc[0]);
   const int cy = cell_of(pos[(int64_t)n + i], g.inv_h[1], g.nc[1]);
   const int cz = cell_of(pos[2 * (int64_t)n + i], g.inv_h[2], g.nc[2]);
@@ -76,15 +83,68 @@ __global__ void __launch_bounds__(NB_THREADS)
 
 __global__ void __launch_bounds__(NB_THREADS)
     k_cell_scatter(int n, const double* __restrict__ pos, const double* __restrict__ lam,
-                   const int32_t* __restrict__ key, const int32_t* __restrict__ cell_start,
-                   int32_t* __restrict__ cursor, int32_t* __restrict__ sorted_id,
-                   double4* __restrict__ spos) {
+                   const int32_t* __restrict__ flag, const int32_t* __restrict__ key,
+                   const int32_t* __restrict__ cell_start, int32_t* __restrict__ cursor,
+                   int32_t* __restrict__ sorted_id, double4* __restrict__ spos) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || *flag) return;
   const int k = key[i];
   const int slot = cell_start[k] + atomicAdd(&cursor[k], 1);
   sorted_id[slot] = i;
   spos[slot] = make_double4(pos[i], pos[(int64_t)n + i], pos[2 * (int64_t)n + i], lam[i]);
+}
+
+// The lambda range and validity of the inputs (from k_validate's per-block
+// partials), then the cell grid, by one wavefront: cells of side
+// r_f,min / cells_per_rf, coarsened by 1.26 per axis until at most
+// max_cells.  Status: PHB_NB_INVALID for a position outside [0, L) or not
+// finite or a lambda that is not positive, PHB_NB_RADIUS for r_f,max >= L/2
+// on a periodic axis.
+__global__ void __launch_bounds__(64)
+    k_nb_setup(const double* __restrict__ part, int nblocks, Box box, double rf_ratio,
+               int cells_per_rf, int64_t max_cells, int max_per_axis, Grid* __restrict__ gout,
+               int32_t* __restrict__ flag, double* __restrict__ lrange) {
+  const int lane = threadIdx.x;
+  double mn = 1e300, mx = -1e300, bad = 0.0;
+  for (int b = lane; b < nblocks; b += 64) {
+    mn = fmin(mn, part[3 * b]);
+    mx = fmax(mx, part[3 * b + 1]);
+    bad = fmax(bad, part[3 * b + 2]);
+  }
+  for (int d = 32; d > 0; d >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, d, 64));
+    mx = fmax(mx, __shfl_xor(mx, d, 64));
+    bad = fmax(bad, __shfl_xor(bad, d, 64));
+  }
+  if (lane != 0) return;
+  lrange[0] = mn;
+  lrange[1] = mx;
+  int st = bad != 0.0 ? PHB_NB_INVALID : 0;
+  for (int a = 0; a < 3; ++a)
+    if (box.periodic[a] && !(rf_ratio * mx < box.halfL[a])) st |= PHB_NB_RADIUS;
+  *flag = st;
+  if (st) return;
+  Grid g;
+  double h = rf_ratio * mn / (cells_per_rf > 1 ? cells_per_rf : 1);
+  for (;;) {
+    int64_t total = 1;
+    for (int a = 0; a < 3; ++a) {
+      double c = floor(box.L[a] / h);
+      if (c < 1) c = 1;
+      if (c > max_per_axis) c = max_per_axis;
+      g.nc[a] = (int)c;
+      total *= g.nc[a];
+    }
+    if (total <= max_cells) break;
+    h *= 1.26;
+  }
+  double hmin = 1e300;
+  for (int a = 0; a < 3; ++a) {
+    g.inv_h[a] = g.nc[a] / box.L[a];
+    hmin = fmin(hmin, box.L[a] / g.nc[a]);
+  }
+  g.margin = 1e-6 * hmin;
+  *gout = g;
 }
 
 // Candidate cell range on one axis: cells that may hold a point within
@@ -116,138 +176,16 @@ __device__ __forceinline__ int wrap_cell(int c, int nc) {
   return c < 0 ? c + nc : (c >= nc ? c - nc : c);
 }
 
-// Visits every candidate of particle (xi, yi, zi) with squared radius r2 and
-// calls f(slot_index_in_sorted_order, j) for those strictly inside.
-template <class F>
-__device__ __forceinline__ void for_each_neighbor(double xi, double yi, double zi, double r,
-                                                  double r2, const Box& box, const Grid& g,
-                                                  const int32_t* __restrict__ cell_start,
-                                                  const int32_t* __restrict__ sorted_id,
-                                                  const double4* __restrict__ spos, F&& f) {
-  const Range ry = axis_range(yi, r, g.margin, g.inv_h[1], g.nc[1], box.periodic[1]);
-  const Range rz = axis_range(zi, r, g.margin, g.inv_h[2], g.nc[2], box.periodic[2]);
-  // Rows of cells (fixed y and z) are culled to the sphere: a neighbor in a
-  // row is at least the row's distance (dy_min, dz_min) away in y and z, so
-  // |dx|^2 < r^2 - dy_min^2 - dz_min^2.  Rows where that bound is empty are
-  // skipped, the others scan only the cells under the chord.  The bound uses
-  // r + margin, which covers the rounding of the cell binning and of the
-  // distance test; the lists are those of the full box.
-  // A periodic axis whose range was clipped to the whole axis has lost the
-  // image each cell index stood for: it is not culled.
-  const double hy = 1.0 / g.inv_h[1], hz = 1.0 / g.inv_h[2];
-  const bool cull_y = !(box.periodic[1] && ry.lo == 0 && ry.hi == g.nc[1] - 1);
-  const bool cull_z = !(box.periodic[2] && rz.lo == 0 && rz.hi == g.nc[2] - 1);
-  const double rc = r + g.margin;
-  const double rc2 = rc * rc;
-  for (int cz = rz.lo; cz <= rz.hi; ++cz) {
-    const double z0 = cz * hz;
-    const double dzm = cull_z ? fmax(0.0, fmax(z0 - zi, zi - (z0 + hz))) : 0.0;
-    const double remz = rc2 - dzm * dzm;
-    if (!(remz > 0.0)) continue;
-    const int wz = wrap_cell(cz, g.nc[2]);
-    for (int cy = ry.lo; cy <= ry.hi; ++cy) {
-      const double y0 = cy * hy;
-      const double dym = cull_y ? fmax(0.0, fmax(y0 - yi, yi - (y0 + hy))) : 0.0;
-      const double rem = remz - dym * dym;
-      if (!(rem > 0.0)) continue;
-      const Range rx = axis_range(xi, sqrt(rem), g.margin, g.inv_h[0], g.nc[0], box.periodic[0]);
-      // x runs: at most two contiguous pieces after wrapping
-      int xa0, xb0, xa1 = 0, xb1 = -1;
-      if (rx.lo < 0) {
-        xa0 = rx.lo + g.nc[0]; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi;
-      } else if (rx.hi >= g.nc[0]) {
-        xa0 = rx.lo; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi - g.nc[0];
-      } else {
-        xa0 = rx.lo; xb0 = rx.hi;
-      }
-      const int wy = wrap_cell(cy, g.nc[1]);
-      const int row = g.nc[0] * (wy + g.nc[1] * wz);
-      for (int piece = 0; piece < 2; ++piece) {
-        const int a = piece == 0 ? xa0 : xa1;
-        const int b = piece == 0 ? xb0 : xb1;
-        if (b < a) continue;
-        const int s0 = cell_start[row + a];
-        const int s1 = cell_start[row + b + 1];
-        for (int s = s0; s < s1; ++s) {
-          const double4 pj = spos[s];
-          const double dx = min_image(pj.x - xi, box.L[0], box.halfL[0], box.periodic[0]);
-          const double dy = min_image(pj.y - yi, box.L[1], box.halfL[1], box.periodic[1]);
-          const double dz = min_image(pj.z - zi, box.L[2], box.halfL[2], box.periodic[2]);
-          if (dist2_nofma(dx, dy, dz) < r2) f(s, sorted_id[s]);
-        }
-      }
-    }
-  }
-}
-
-// Count (FILL = false) or emit (FILL = true) the neighbors of each particle.
-// Thread t handles the particle in sorted slot t, so a wavefront covers
-// neighboring cells and shares candidates through the caches.
-template <bool FILL>
-__global__ void __launch_bounds__(NB_THREADS)
-    k_neighbors(int n, Box box, Grid g, double rf_ratio, const int32_t* __restrict__ cell_start,
-                const int32_t* __restrict__ sorted_id, const double4* __restrict__ spos,
-                int32_t* __restrict__ count, const int64_t* __restrict__ offsets,
-                int32_t* __restrict__ out) {
-  const int t = xcd_block() * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  const double4 pi = spos[t];
-  const int i = sorted_id[t];
-  const double r2 = radius2_nofma(rf_ratio, pi.w);
-  const double r = rf_ratio * pi.w;
-  if (!FILL) {
-    int c = 0;
-    for_each_neighbor(pi.x, pi.y, pi.z, r, r2, box, g, cell_start, sorted_id, spos,
-                      [&](int, int) { ++c; });
-    count[i] = c;
-  } else {
-    int64_t o = offsets[i];
-    for_each_neighbor(pi.x, pi.y, pi.z, r, r2, box, g, cell_start, sorted_id, spos,
-                      [&](int, int j) { out[o++] = j; });
-  }
-}
-
-// The same for a list of rows: thread r handles particle rows[r] (read from
-// the unsorted SoA positions, which the sorted copy holds bit for bit) and
-// writes its count or its entries at row r.
-template <bool FILL>
-__global__ void __launch_bounds__(NB_THREADS)
-    k_neighbors_rows(int m, const int32_t* __restrict__ rows, int n,
-                     const double* __restrict__ pos, const double* __restrict__ lam, Box box,
-                     Grid g, double rf_ratio, const int32_t* __restrict__ cell_start,
-                     const int32_t* __restrict__ sorted_id, const double4* __restrict__ spos,
-                     int32_t* __restrict__ count, const int64_t* __restrict__ offsets,
-                     int32_t* __restrict__ out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= m) return;
-  const int i = rows[r];
-  const double xi = pos[i], yi = pos[(int64_t)n + i], zi = pos[2 * (int64_t)n + i];
-  const double li = lam[i];
-  const double r2 = radius2_nofma(rf_ratio, li);
-  const double rad = rf_ratio * li;
-  if (!FILL) {
-    int c = 0;
-    for_each_neighbor(xi, yi, zi, rad, r2, box, g, cell_start, sorted_id, spos,
-                      [&](int, int) { ++c; });
-    count[r] = c;
-  } else {
-    int64_t o = offsets[r];
-    for_each_neighbor(xi, yi, zi, rad, r2, box, g, cell_start, sorted_id, spos,
-                      [&](int, int j) { out[o++] = j; });
-  }
-}
-
 // ---- per-row ascending sort ------------------------------------------------
 // One wavefront per row; rows up to ROW_LDS entries are bitonic-sorted in
 // LDS, longer rows by rank counting straight from global memory.
 constexpr int ROW_LDS = 1024;
 
-// Rows of up to SHORT_ROW entries, one wavefront each, sorted in registers:
-// entry k of the row, padded to m = 2^p slots, sits on lane k % 64 in
-// register k / 64, and a bitonic network exchanges partners across lanes
-// with shuffles and across registers within a lane (distances 64 and 128).
-// Entries are distinct, so the sort is a permutation.
-constexpr int SHORT_ROW = 256;
+// In-register sort of a row of up to 256 entries, one wavefront: entry k of
+// the row, padded to m = 2^p slots, sits on lane k % 64 in register k / 64,
+// and a bitonic network exchanges partners across lanes with shuffles and
+// across registers within a lane (distances 64 and 128).  Entries are
+// distinct, so the sort is a permutation.
 
 __device__ __forceinline__ int32_t bitonic_keep(int32_t v, int32_t w, int i, int j, int k) {
   const bool lower = (i & j) == 0, up = (i & k) == 0;
@@ -291,45 +229,20 @@ __device__ __forceinline__ void wave_bitonic(int32_t (&v)[R], int m, int lane) {
   }
 }
 
-template <int R>
-__device__ __forceinline__ void sort_row_in_registers(const int32_t* __restrict__ in,
-                                                      int32_t* __restrict__ out, int64_t b,
-                                                      int len, int lane) {
-  int m = 1;
-  while (m < len) m <<= 1;
-  int32_t v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = lane + 64 * r < len ? in[b + 64 * r + lane] : 0x7fffffff;
-  wave_bitonic<R>(v, m, lane);
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (lane + 64 * r < len) out[b + 64 * r + lane] = v[r];
-}
-
-__global__ void __launch_bounds__(256)
-    k_row_sort_short(int64_t nrows, const int64_t* __restrict__ off,
-                     const int32_t* __restrict__ in, int32_t* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < nrows;
-       r += waves) {
-    const int64_t b = off[r];
-    const int len = (int)(off[r + 1] - b);  // wavefront-uniform
-    if (len <= 64) sort_row_in_registers<1>(in, out, b, len, lane);
-    else if (len <= 128) sort_row_in_registers<2>(in, out, b, len, lane);
-    else if (len <= SHORT_ROW) sort_row_in_registers<4>(in, out, b, len, lane);
-  }
-}
-
+// The rows list[0 .. *count) (one block of one wavefront per row, the grid
+// striding over the list).
 __global__ void __launch_bounds__(64)
-    k_row_sort(int64_t nrows, const int64_t* __restrict__ off, const int32_t* __restrict__ in,
-               int32_t* __restrict__ out, int min_len) {
+    k_row_sort(const int32_t* __restrict__ list, const int32_t* __restrict__ count,
+               const int64_t* __restrict__ off, const int32_t* __restrict__ in,
+               int32_t* __restrict__ out, const int32_t* __restrict__ flag) {
   __shared__ int32_t buf[ROW_LDS];
   const int lane = threadIdx.x;
-  for (int64_t r = blockIdx.x; r < nrows; r += gridDim.x) {
+  if (*flag) return;
+  const int nl = *count;
+  for (int q = blockIdx.x; q < nl; q += gridDim.x) {
+    const int r = list[q];
     const int64_t b = off[r];
     const int len = (int)(off[r + 1] - b);
-    if (len < min_len) continue;  // sorted by k_row_sort_short
     if (len <= ROW_LDS) {
       int m = 1;
       while (m < len) m <<= 1;
@@ -364,49 +277,489 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-// ---- transpose -------------------------------------------------------------
-__global__ void __launch_bounds__(NB_THREADS)
-    k_t_count(int64_t nnz, const int32_t* __restrict__ idx, int32_t* __restrict__ tcount) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < nnz) atomicAdd(&tcount[idx[s]], 1);
+// ---- the search: one wavefront per row ----------------------------------
+// Row k of cells (fixed y and z) in the candidate block of a particle, as at
+// most two contiguous runs of cell-sorted slots [s0a, s0a + lena),
+// [s0b, s0b + lenb) (an x range that wraps is two pieces).  Rows of cells
+// are culled to the sphere: a neighbor in a row is at least the row's
+// distance (dy_min, dz_min) away in y and z, so |dx|^2 < r^2 - dy_min^2 -
+// dz_min^2; rows where that bound is empty hold no candidates, the others
+// only the cells under the chord.  The bound uses r + margin, which covers
+// the rounding of the cell binning and of the distance test: the lists are
+// those of the full box.  A periodic axis whose range was clipped to the
+// whole axis has lost the image each cell index stood for: it is not culled.
+struct CellRows {
+  Range ry, rz;
+  int ny, nrows;
+  bool cull_y, cull_z;
+};
+
+__device__ __forceinline__ CellRows cell_rows(double yi, double zi, double r, const Box& box,
+                                              const Grid& g) {
+  CellRows c;
+  c.ry = axis_range(yi, r, g.margin, g.inv_h[1], g.nc[1], box.periodic[1]);
+  c.rz = axis_range(zi, r, g.margin, g.inv_h[2], g.nc[2], box.periodic[2]);
+  c.ny = c.ry.hi - c.ry.lo + 1;
+  c.nrows = c.ny * (c.rz.hi - c.rz.lo + 1);
+  c.cull_y = !(box.periodic[1] && c.ry.lo == 0 && c.ry.hi == g.nc[1] - 1);
+  c.cull_z = !(box.periodic[2] && c.rz.lo == 0 && c.rz.hi == g.nc[2] - 1);
+  return c;
 }
 
-// k_t_fill and k_t_pos: TL lanes share a row, so that its entries are read
-// coalesced and the rows' lengths even out over the lanes.
-constexpr int TL = 16;
-
-__global__ void __launch_bounds__(NB_THREADS)
-    k_t_fill(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
-             const int64_t* __restrict__ toff, int32_t* __restrict__ cursor,
-             int32_t* __restrict__ tmp) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(t / TL);
-  if (i >= n) return;
-  for (int64_t s = off[i] + t % TL; s < off[i + 1]; s += TL) {
-    const int j = idx[s];
-    const int p = atomicAdd(&cursor[j], 1);
-    tmp[toff[j] + p] = i;
+__device__ __forceinline__ void cell_row_runs(int k, const CellRows& c, double xi, double yi,
+                                              double zi, double r, const Box& box,
+                                              const Grid& g,
+                                              const int32_t* __restrict__ cell_start, int& s0a,
+                                              int& lena, int& s0b, int& lenb) {
+  s0a = lena = s0b = lenb = 0;
+  const int cz = c.rz.lo + k / c.ny, cy = c.ry.lo + k % c.ny;
+  const double hy = 1.0 / g.inv_h[1], hz = 1.0 / g.inv_h[2];
+  const double rc = r + g.margin;
+  const double z0 = cz * hz, y0 = cy * hy;
+  const double dzm = c.cull_z ? fmax(0.0, fmax(z0 - zi, zi - (z0 + hz))) : 0.0;
+  const double dym = c.cull_y ? fmax(0.0, fmax(y0 - yi, yi - (y0 + hy))) : 0.0;
+  const double rem = (rc * rc - dzm * dzm) - dym * dym;
+  if (!(rc * rc - dzm * dzm > 0.0) || !(rem > 0.0)) return;
+  const Range rx = axis_range(xi, sqrt(rem), g.margin, g.inv_h[0], g.nc[0], box.periodic[0]);
+  int xa0, xb0, xa1 = 0, xb1 = -1;
+  if (rx.lo < 0) {
+    xa0 = rx.lo + g.nc[0]; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi;
+  } else if (rx.hi >= g.nc[0]) {
+    xa0 = rx.lo; xb0 = g.nc[0] - 1; xa1 = 0; xb1 = rx.hi - g.nc[0];
+  } else {
+    xa0 = rx.lo; xb0 = rx.hi;
+  }
+  const int row = g.nc[0] * (wrap_cell(cy, g.nc[1]) + g.nc[1] * wrap_cell(cz, g.nc[2]));
+  s0a = cell_start[row + xa0];
+  lena = cell_start[row + xb0 + 1] - s0a;
+  if (xb1 >= xa1) {
+    s0b = cell_start[row + xa1];
+    lenb = cell_start[row + xb1 + 1] - s0b;
   }
 }
 
+__device__ __forceinline__ int wave_inclusive_scan(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// Rows of up to NB_ROW entries are collected in LDS and sorted in registers.
+constexpr int NB_WAVES = NB_THREADS / 64;
+constexpr int NB_ROW = 256;
+constexpr int NB_LONG_BLOCKS = 64;  // grid of the passes over the long rows
+
+template <int R>
+__device__ __forceinline__ void sort_lds_row(const int32_t* buf, int32_t* __restrict__ out,
+                                             int64_t o, int len, int lane) {
+  int mm = 1;
+  while (mm < len) mm <<= 1;
+  int32_t v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = lane + 64 * r < len ? buf[lane + 64 * r] : 0x7fffffff;
+  wave_bitonic<R>(v, mm, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (lane + 64 * r < len) out[o + 64 * r + lane] = v[r];
+}
+
+// Row r's neighbors: the particle in cell-sorted slot r (rows == null; the
+// row is its particle index) or particle rows[r] (read from the SoA inputs,
+// which the sorted copy holds bit for bit).  The lanes take the candidate
+// block's rows of cells 64 at a time; their runs, prefix-summed over the
+// wavefront, flatten the candidates into one index range that the lanes
+// then test, U candidates per lane at a time (their loads in flight
+// together), a ballot compacting the hits.  Consecutive rows are spatial
+// neighbors (cell order): the XCD-aware block order keeps them in one L2.
+//   LONG = false: count the row; a row of up to NB_ROW entries is collected
+//   in LDS, sorted in registers and written once, coalesced, to its slot of
+//   the padded scratch (NB_ROW entries per row), to be copied to its CSR
+//   place after the scan.
+//   LONG = true: the rows longer than NB_ROW, listed by the first pass
+//   (long_slot: their r, long_row: their output row), again, written unsorted
+//   at their CSR place in long_tmp (for k_row_sort); the wavefronts stride
+//   over the list.
+constexpr int NB_U = 2;
+
+template <bool LONG>
 __global__ void __launch_bounds__(NB_THREADS)
-    k_t_pos(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
-            const int64_t* __restrict__ toff, const int32_t* __restrict__ tsrc,
-            int32_t* __restrict__ tpos) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = (int)(t / TL);
-  if (i >= n) return;
-  for (int64_t s = off[i] + t % TL; s < off[i + 1]; s += TL) {
-    const int j = idx[s];
-    int64_t lo = toff[j], hi = toff[j + 1] - 1;
-    while (lo < hi) {  // first position with tsrc >= i (i is present)
-      const int64_t mid = (lo + hi) >> 1;
-      if (tsrc[mid] < i)
-        lo = mid + 1;
-      else
-        hi = mid;
+    k_nb_wave(int m, const int32_t* __restrict__ rows, int n, const double* __restrict__ pos,
+              const double* __restrict__ lam, Box box, const Grid* __restrict__ gp,
+              double rf_ratio, const int32_t* __restrict__ cell_start,
+              const int32_t* __restrict__ sorted_id, const double4* __restrict__ spos,
+              const int32_t* __restrict__ flag, int32_t* __restrict__ count,
+              int32_t* __restrict__ scratch, const int64_t* __restrict__ offsets,
+              int32_t* __restrict__ long_tmp, int32_t* __restrict__ long_slot,
+              int32_t* __restrict__ long_row, int32_t* __restrict__ long_count) {
+  __shared__ int sh_start[NB_WAVES][64], sh_s0a[NB_WAVES][64], sh_lena[NB_WAVES][64],
+      sh_s0b[NB_WAVES][64];
+  __shared__ int32_t sh_row[LONG ? 1 : NB_WAVES][LONG ? 1 : NB_ROW];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w0 = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + wv);
+  const int fl = *flag;
+  const int nrows_here = LONG ? (fl ? 0 : *long_count) : m;
+  for (int w = w0; w < nrows_here; w += LONG ? (int)gridDim.x * NB_WAVES : nrows_here) {
+  const int r = LONG ? long_slot[w] : w;
+  if (!LONG && fl) {
+    if (lane == 0) count[r] = 0;
+    return;
+  }
+  int i;
+  if (rows) i = rows[r];
+  else i = sorted_id[r];
+  const int orow = rows ? r : i;
+  int64_t o = 0;
+  int len = 0;
+  if constexpr (LONG) {
+    o = offsets[orow];
+    len = (int)(offsets[orow + 1] - o);
+  }
+  const Grid g = *gp;
+  double xi, yi, zi, li;
+  if (rows) {
+    xi = pos[i];
+    yi = pos[(int64_t)n + i];
+    zi = pos[2 * (int64_t)n + i];
+    li = lam[i];
+  } else {
+    const double4 pi = spos[r];
+    xi = pi.x;
+    yi = pi.y;
+    zi = pi.z;
+    li = pi.w;
+  }
+  const double r2 = radius2_nofma(rf_ratio, li);
+  const double rad = rf_ratio * li;
+  const CellRows cr = cell_rows(yi, zi, rad, box, g);
+  int c = 0;  // hits so far (wavefront-uniform)
+  for (int base = 0; base < cr.nrows; base += 64) {
+    int s0a = 0, lena = 0, s0b = 0, lenb = 0;
+    if (base + lane < cr.nrows)
+      cell_row_runs(base + lane, cr, xi, yi, zi, rad, box, g, cell_start, s0a, lena, s0b, lenb);
+    const int tot = lena + lenb;
+    const int incl = wave_inclusive_scan(tot, lane);
+    const int ncand = __shfl(incl, 63, 64);
+    sh_start[wv][lane] = incl - tot;
+    sh_s0a[wv][lane] = s0a;
+    sh_lena[wv][lane] = lena;
+    sh_s0b[wv][lane] = s0b;
+    wave_lds_sync();
+    for (int q0 = 0; q0 < ncand; q0 += 64 * NB_U) {
+      int sl[NB_U];
+      bool hit[NB_U];
+#pragma unroll
+      for (int u = 0; u < NB_U; ++u) {
+        const int q = q0 + 64 * u + lane;
+        sl[u] = -1;
+        if (q < ncand) {
+          // the last row of cells whose run starts at or before q (rows
+          // without candidates share the next row's start and are passed)
+          int lo = 0, hi = 63;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sh_start[wv][mid] <= q) lo = mid; else hi = mid - 1;
+          }
+          const int d = q - sh_start[wv][lo];
+          const int la = sh_lena[wv][lo];
+          sl[u] = d < la ? sh_s0a[wv][lo] + d : sh_s0b[wv][lo] + (d - la);
+        }
+      }
+      double4 pj[NB_U];
+#pragma unroll
+      for (int u = 0; u < NB_U; ++u)
+        pj[u] = sl[u] >= 0 ? spos[sl[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < NB_U; ++u) {
+        const double dx = min_image(pj[u].x - xi, box.L[0], box.halfL[0], box.periodic[0]);
+        const double dy = min_image(pj[u].y - yi, box.L[1], box.halfL[1], box.periodic[1]);
+        const double dz = min_image(pj[u].z - zi, box.L[2], box.halfL[2], box.periodic[2]);
+        hit[u] = sl[u] >= 0 && dist2_nofma(dx, dy, dz) < r2;
+      }
+#pragma unroll
+      for (int u = 0; u < NB_U; ++u) {
+        const int j = hit[u] ? sorted_id[sl[u]] : 0;
+        const uint64_t mask = __ballot(hit[u]);
+        const int at = c + __popcll(mask & ((1ull << lane) - 1ull));
+        if (hit[u]) {
+          if constexpr (LONG) {
+            if (at < len) long_tmp[o + at] = j;  // the count saw the same hits
+          } else if (at < NB_ROW) {
+            sh_row[wv][at] = j;
+          }
+        }
+        c += __popcll(mask);
+      }
     }
-    tpos[s] = (int32_t)lo;
+    wave_lds_sync();  // the run table is rewritten for the next rows of cells
+  }
+  if constexpr (!LONG) {
+    if (lane == 0) {
+      count[orow] = c;
+      if (c > NB_ROW) {
+        const int q = atomicAdd(long_count, 1);
+        long_slot[q] = r;
+        long_row[q] = orow;
+      }
+    }
+    if (c <= NB_ROW) {
+      int32_t* dst = scratch + (int64_t)orow * NB_ROW;
+      if (c <= 64) sort_lds_row<1>(sh_row[wv], dst, 0, c, lane);
+      else if (c <= 128) sort_lds_row<2>(sh_row[wv], dst, 0, c, lane);
+      else sort_lds_row<4>(sh_row[wv], dst, 0, c, lane);
+    }
+  }
+  }
+}
+
+// The sorted rows of up to NB_ROW entries from the padded scratch to their
+// CSR places; 16 lanes per row.
+__global__ void __launch_bounds__(NB_THREADS)
+    k_nb_copy(int m, const int64_t* __restrict__ offsets, const int32_t* __restrict__ scratch,
+              const int32_t* __restrict__ flag, int32_t* __restrict__ idx) {
+  const int64_t t = (int64_t)blockIdx.x * NB_THREADS + threadIdx.x;
+  const int r = (int)(t / 16);
+  if (r >= m || *flag) return;
+  const int64_t o = offsets[r];
+  const int len = (int)(offsets[r + 1] - o);
+  if (len > NB_ROW) return;
+  const int32_t* src = scratch + (int64_t)r * NB_ROW;
+  for (int k = (int)(t % 16); k < len; k += 16) idx[o + k] = src[k];
+}
+
+// nnz = offsets[m] to the caller's word and the capacity check.
+__global__ void k_nb_total(const int64_t* __restrict__ offsets, int m, int64_t capacity,
+                           int64_t* __restrict__ nnz, int32_t* __restrict__ flag) {
+  const int64_t t = offsets[m];
+  *nnz = t;
+  if (t > capacity) *flag |= PHB_NB_OVERFLOW;
+}
+
+// ---- transpose -------------------------------------------------------------
+// The transposed row of x is T(x) = {i : x in N(i)} = A(x) + B(x):
+//   A(x) = {y in N(x) : x in N(y)}, the mutual entries of row x, a sorted
+//          subsequence of it;
+//   B(x) = {i not in N(x) : x in N(i)}, from the one-way entries (i, x).
+// With equal radii every entry is mutual; with graded lambdas the one-way
+// entries are a thin shell near each sphere's edge.  Pass 1 finds, for each
+// entry s = (x, y), x's place in row y (rows are sorted: a binary search):
+// rev[s] = the mirrored entry (y, x), or -1 (one-way: x joins B(y)).  Pass 2
+// puts the one-way entries into B's part of their transposed rows (after
+// A's), unsorted.  Pass 3 sorts each transposed row with the forward entry
+// each element stands for, in registers, and writes t_src and t_pos.  Only
+// the one-way entries use atomics (their order is undone by the sort).
+
+
+// Pass 1, one wavefront per row x, a lane per entry.
+__global__ void __launch_bounds__(NB_THREADS)
+    k_tr_mutual(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
+                int32_t* __restrict__ rev, int32_t* __restrict__ acnt,
+                int32_t* __restrict__ bcnt) {
+  const int lane = threadIdx.x & 63;
+  const int x = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + (threadIdx.x >> 6));
+  if (x >= n) return;
+  const int64_t s0 = off[x];
+  const int len = (int)(off[x + 1] - s0);
+  int a = 0;
+  for (int base = 0; base < len; base += 64) {
+    const int k = base + lane;
+    bool mutual = false;
+    if (k < len) {
+      const int y = idx[s0 + k];
+      int64_t lo = off[y], hi = off[y + 1];  // first entry >= x in [lo, hi)
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (idx[mid] < x) lo = mid + 1; else hi = mid;
+      }
+      mutual = lo < off[y + 1] && idx[lo] == x;
+      rev[s0 + k] = mutual ? (int32_t)lo : -1;
+      if (!mutual) atomicAdd(&bcnt[y], 1);
+    }
+    a += __popcll(__ballot(mutual));
+  }
+  if (lane == 0) acnt[x] = a;
+}
+
+// Row lengths |A| + |B| for the scan; the B counts become the B cursors.
+__global__ void __launch_bounds__(NB_THREADS)
+    k_tr_total(int n, const int32_t* __restrict__ acnt, int32_t* __restrict__ bcnt,
+               int32_t* __restrict__ tcount) {
+  const int x = blockIdx.x * NB_THREADS + threadIdx.x;
+  if (x >= n) return;
+  tcount[x] = acnt[x] + bcnt[x];
+  bcnt[x] = 0;
+}
+
+// Pass 2: one-way entry s = (i, x) into B(x): key i, payload s.  One
+// wavefront per forward row i, a lane per entry.
+__global__ void __launch_bounds__(NB_THREADS)
+    k_tr_oneway(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
+                const int32_t* __restrict__ rev, const int64_t* __restrict__ toff,
+                const int32_t* __restrict__ acnt, int32_t* __restrict__ bcur,
+                int32_t* __restrict__ tkey, int32_t* __restrict__ tpay) {
+  const int lane = threadIdx.x & 63;
+  const int i = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + (threadIdx.x >> 6));
+  if (i >= n) return;
+  const int64_t s1 = off[i + 1];
+  for (int64_t s = off[i] + lane; s < s1; s += 64) {
+    if (rev[s] >= 0) continue;
+    const int x = idx[s];
+    const int64_t q = toff[x] + acnt[x] + atomicAdd(&bcur[x], 1);
+    tkey[q] = i;
+    tpay[q] = (int32_t)s;
+  }
+}
+
+// compare-exchange of keys (and their payloads) held in registers a
+// (lower index i) and b
+__device__ __forceinline__ void bitonic_regs_kv(int32_t& ka, int32_t& va, int32_t& kb,
+                                                int32_t& vb, int i, int k) {
+  const bool up = (i & k) == 0;
+  if ((ka > kb) == up) {
+    const int32_t tk = ka, tv = va;
+    ka = kb; va = vb;
+    kb = tk; vb = tv;
+  }
+}
+
+// wave_bitonic carrying a payload per key.
+template <int R>
+__device__ __forceinline__ void wave_bitonic_kv(int32_t (&key)[R], int32_t (&val)[R], int m,
+                                                int lane) {
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        if constexpr (R == 2) {
+          bitonic_regs_kv(key[0], val[0], key[1], val[1], lane, k);
+        } else if constexpr (R == 4) {
+          if (j == 64) {
+            bitonic_regs_kv(key[0], val[0], key[1], val[1], lane, k);
+            bitonic_regs_kv(key[2], val[2], key[3], val[3], lane + 128, k);
+          } else {
+            bitonic_regs_kv(key[0], val[0], key[2], val[2], lane, k);
+            bitonic_regs_kv(key[1], val[1], key[3], val[3], lane + 64, k);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (64 * r < m) {
+            const int32_t wk = __shfl_xor(key[r], j, 64);
+            const int32_t wv = __shfl_xor(val[r], j, 64);
+            const int i = lane + 64 * r;
+            const bool lower = (i & j) == 0, up = (i & k) == 0;
+            // keep the smaller key where the pair runs up and this is its
+            // lower end (or down and upper end), else the larger
+            const bool take = (lower == up) ? (wk < key[r]) : (wk > key[r]);
+            if (take) {
+              key[r] = wk;
+              val[r] = wv;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void sort_write_trow(const int32_t* sk, const int32_t* sp, int len,
+                                                int64_t t0, int lane, int32_t* __restrict__ tsrc,
+                                                int32_t* __restrict__ tpos) {
+  int mm = 1;
+  while (mm < len) mm <<= 1;
+  int32_t k[R], v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = lane + 64 * r;
+    k[r] = e < len ? sk[e] : 0x7fffffff;
+    v[r] = e < len ? sp[e] : -1;
+  }
+  wave_bitonic_kv<R>(k, v, mm, lane);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = lane + 64 * r;
+    if (e < len) {
+      tsrc[t0 + e] = k[r];
+      tpos[v[r]] = (int32_t)(t0 + e);
+    }
+  }
+}
+
+// Pass 3, one wavefront per transposed row x.  Rows longer than NB_ROW are
+// left in the scratch (A's part written there too) and listed for k_tr_long.
+__global__ void __launch_bounds__(NB_THREADS)
+    k_tr_rows(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
+              const int32_t* __restrict__ rev, const int64_t* __restrict__ toff,
+              int32_t* __restrict__ tkey, int32_t* __restrict__ tpay,
+              int32_t* __restrict__ tsrc, int32_t* __restrict__ tpos,
+              int32_t* __restrict__ long_list, int32_t* __restrict__ long_count) {
+  __shared__ int32_t sk[NB_WAVES][NB_ROW], sp[NB_WAVES][NB_ROW];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int x = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + wv);
+  if (x >= n) return;
+  const int64_t t0 = toff[x];
+  const int tl = (int)(toff[x + 1] - t0);
+  const bool in_lds = tl <= NB_ROW;
+  const int64_t s0 = off[x];
+  const int len = (int)(off[x + 1] - s0);
+  int c = 0;  // A's elements so far, in row order
+  for (int base = 0; base < len; base += 64) {
+    const int k = base + lane;
+    int32_t rv = -1, y = 0;
+    if (k < len) {
+      rv = rev[s0 + k];
+      y = idx[s0 + k];
+    }
+    const bool mutual = rv >= 0;
+    const uint64_t mask = __ballot(mutual);
+    const int at = c + __popcll(mask & ((1ull << lane) - 1ull));
+    if (mutual && at < tl) {
+      if (in_lds) {
+        sk[wv][at] = y;
+        sp[wv][at] = rv;
+      } else {
+        tkey[t0 + at] = y;
+        tpay[t0 + at] = rv;
+      }
+    }
+    c += __popcll(mask);
+  }
+  if (!in_lds) {
+    if (lane == 0) long_list[atomicAdd(long_count, 1)] = x;
+    return;
+  }
+  for (int k = c + lane; k < tl; k += 64) {
+    sk[wv][k] = tkey[t0 + k];
+    sp[wv][k] = tpay[t0 + k];
+  }
+  wave_lds_sync();
+  if (tl <= 64) sort_write_trow<1>(sk[wv], sp[wv], tl, t0, lane, tsrc, tpos);
+  else if (tl <= 128) sort_write_trow<2>(sk[wv], sp[wv], tl, t0, lane, tsrc, tpos);
+  else sort_write_trow<4>(sk[wv], sp[wv], tl, t0, lane, tsrc, tpos);
+}
+
+// The listed transposed rows longer than NB_ROW (rare): each element's rank
+// among its row's keys (distinct) is its place.
+__global__ void __launch_bounds__(64)
+    k_tr_long(const int32_t* __restrict__ long_list, const int32_t* __restrict__ long_count,
+              const int64_t* __restrict__ toff, const int32_t* __restrict__ tkey,
+              const int32_t* __restrict__ tpay, int32_t* __restrict__ tsrc,
+              int32_t* __restrict__ tpos) {
+  const int nl = *long_count;
+  for (int q = blockIdx.x; q < nl; q += gridDim.x) {
+    const int x = long_list[q];
+    const int64_t t0 = toff[x];
+    const int tl = (int)(toff[x + 1] - t0);
+    for (int k = threadIdx.x; k < tl; k += 64) {
+      const int32_t key = tkey[t0 + k];
+      int rank = 0;
+      for (int u = 0; u < tl; ++u) rank += tkey[t0 + u] < key ? 1 : 0;
+      tsrc[t0 + rank] = key;
+      tpos[tpay[t0 + k]] = (int32_t)(t0 + rank);
+    }
   }
 }
 
@@ -522,94 +875,128 @@ hipError_t launch_validate(hipStream_t s, int n, const double* pos, const double
   return hipGetLastError();
 }
 
-hipError_t launch_cell_sort(hipStream_t s, int n, const double* pos, const double* lam,
-                            const Grid& g, int32_t* key, int32_t* cell_count,
-                            int32_t* cell_start, int32_t* scan_tmp, int32_t* sorted_id,
-                            double4* spos) {
-  const int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
-  hipError_t e = fill_i32(s, cell_count, 0, ncell);
+int64_t nb_max_cells(int64_t n) {
+  return std::min<int64_t>(NB_MAX_CELLS, std::max<int64_t>(4096, 8 * n));
+}
+
+size_t nb_work_bytes(int64_t n, int64_t m, int64_t capacity) {
+  const int64_t mc = nb_max_cells(n);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(3 * NB_VALIDATE_BLOCKS * sizeof(double)) + al(sizeof(Grid)) + al(2 * sizeof(double)) +
+         al((size_t)n * sizeof(int32_t)) + 2 * al((size_t)(mc + 1) * sizeof(int32_t)) +
+         al((size_t)scan_tmp_elems(mc + 1) * sizeof(int32_t)) + al((size_t)n * sizeof(int32_t)) +
+         al((size_t)n * sizeof(double4)) + al((size_t)std::max<int64_t>(m, 1) * sizeof(int32_t)) +
+         al((size_t)scan_tmp_elems(std::max<int64_t>(m, 1)) * sizeof(int64_t)) +
+         al((size_t)std::max<int64_t>(capacity, 1) * sizeof(int32_t)) +
+         al((size_t)std::max<int64_t>(m, 1) * NB_ROW * sizeof(int32_t)) +
+         2 * al((size_t)std::max<int64_t>(m, 1) * sizeof(int32_t)) + al(sizeof(int32_t));
+}
+
+NbWork nb_work_take(Workspace& ws, int64_t n, int64_t m, int64_t capacity) {
+  const int64_t mc = nb_max_cells(n);
+  NbWork w;
+  w.part = ws.take<double>(3 * NB_VALIDATE_BLOCKS);
+  w.grid = ws.take<Grid>(1);
+  w.lrange = ws.take<double>(2);
+  w.key = ws.take<int32_t>(n);
+  w.ccount = ws.take<int32_t>(mc + 1);
+  w.cstart = ws.take<int32_t>(mc + 1);
+  w.cscan = ws.take<int32_t>(scan_tmp_elems(mc + 1));
+  w.sid = ws.take<int32_t>(n);
+  w.spos = ws.take<double4>(n);
+  w.cnt = ws.take<int32_t>(std::max<int64_t>(m, 1));
+  w.oscan = ws.take<int64_t>(scan_tmp_elems(std::max<int64_t>(m, 1)));
+  w.tmp = ws.take<int32_t>(std::max<int64_t>(capacity, 1));
+  w.rowbuf = ws.take<int32_t>((size_t)std::max<int64_t>(m, 1) * NB_ROW);
+  w.long_slot = ws.take<int32_t>(std::max<int64_t>(m, 1));
+  w.long_row = ws.take<int32_t>(std::max<int64_t>(m, 1));
+  w.long_count = ws.take<int32_t>(1);
+  return w;
+}
+
+__global__ void k_nb_empty(int64_t* __restrict__ offsets, int64_t* __restrict__ nnz) {
+  offsets[0] = 0;
+  *nnz = 0;
+}
+
+hipError_t launch_neighbor_build(hipStream_t s, int n, const double* pos, const double* lam,
+                                 const Box& box, double rf_ratio, int cells_per_rf, int m,
+                                 const int32_t* rows, const NbWork& w, int64_t* offsets,
+                                 int32_t* idx, int64_t capacity, int64_t* nnz, int32_t* flag) {
+  const int64_t mc = nb_max_cells(n);
+  hipLaunchKernelGGL(k_validate, dim3(NB_VALIDATE_BLOCKS), dim3(NB_THREADS), 0, s, n, pos, lam,
+                     box, w.part);
+  hipLaunchKernelGGL(k_nb_setup, dim3(1), dim3(64), 0, s, w.part, NB_VALIDATE_BLOCKS, box,
+                     rf_ratio, cells_per_rf, mc, 1024, w.grid, flag, w.lrange);
+  hipError_t e = fill_i32(s, w.ccount, 0, mc + 1);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cell_key, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, pos, g,
-                     key, cell_count);
-  e = exclusive_scan_i32_to_i32(s, cell_count, ncell, cell_start, scan_tmp);
-  if (e != hipSuccess) return e;
-  e = fill_i32(s, cell_count, 0, ncell);  // reused as the scatter cursor
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n,
-                     pos, lam, key, cell_start, cell_count, sorted_id, spos);
+  hipLaunchKernelGGL(k_cell_key, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, pos,
+                     w.grid, flag, w.key, w.ccount);
+  if ((e = exclusive_scan_i32_to_i32(s, w.ccount, mc, w.cstart, w.cscan)) != hipSuccess) return e;
+  if ((e = fill_i32(s, w.ccount, 0, mc)) != hipSuccess) return e;  // the scatter's cursors
+  hipLaunchKernelGGL(k_cell_scatter, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n, pos,
+                     lam, flag, w.key, w.cstart, w.ccount, w.sid, w.spos);
+  if (m == 0) {
+    hipLaunchKernelGGL(k_nb_empty, dim3(1), dim3(1), 0, s, offsets, nnz);
+    return hipGetLastError();
+  }
+  const dim3 gw(grid_for(m, NB_WAVES));
+  if ((e = fill_i32(s, w.long_count, 0, 1)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_nb_wave<false>), gw, dim3(NB_THREADS), 0, s, m, rows, n, pos, lam, box,
+                     w.grid, rf_ratio, w.cstart, w.sid, w.spos, flag, w.cnt, w.rowbuf, nullptr,
+                     nullptr, w.long_slot, w.long_row, w.long_count);
+  if ((e = exclusive_scan_i32_to_i64(s, w.cnt, m, offsets, w.oscan)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_nb_total, dim3(1), dim3(1), 0, s, offsets, m, capacity, nnz, flag);
+  hipLaunchKernelGGL(k_nb_copy, dim3(grid_for((int64_t)m * 16, NB_THREADS)), dim3(NB_THREADS), 0,
+                     s, m, offsets, w.rowbuf, flag, idx);
+  // rows longer than NB_ROW are rare: small grids stride over their list
+  hipLaunchKernelGGL((k_nb_wave<true>), dim3(NB_LONG_BLOCKS), dim3(NB_THREADS), 0, s, m, rows, n,
+                     pos, lam, box, w.grid, rf_ratio, w.cstart, w.sid, w.spos, flag, nullptr,
+                     nullptr, offsets, w.tmp, w.long_slot, w.long_row, w.long_count);
+  hipLaunchKernelGGL(k_row_sort, dim3(NB_LONG_BLOCKS * NB_WAVES), dim3(64), 0, s, w.long_row,
+                     w.long_count, offsets, w.tmp, idx, flag);
   return hipGetLastError();
 }
 
-hipError_t launch_neighbor_count(hipStream_t s, int n, const Box& box, const Grid& g,
-                                 double rf_ratio, const int32_t* cell_start,
-                                 const int32_t* sorted_id, const double4* spos, int32_t* count) {
-  hipLaunchKernelGGL((k_neighbors<false>), dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s,
-                     n, box, g, rf_ratio, cell_start, sorted_id, spos, count, nullptr, nullptr);
-  return hipGetLastError();
+TransposeWork transpose_work_take(Workspace& ws, int64_t n, int64_t nnz) {
+  TransposeWork w;
+  w.acnt = ws.take<int32_t>(n);
+  w.bcnt = ws.take<int32_t>(n);
+  w.tcount = ws.take<int32_t>(n);
+  w.scan = ws.take<int64_t>(scan_tmp_elems(n));
+  w.rev = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  w.tkey = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  w.tpay = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  w.long_list = ws.take<int32_t>(std::max<int64_t>(n, 1));
+  w.counts = ws.take<int32_t>(2);
+  return w;
 }
 
-hipError_t launch_neighbor_fill(hipStream_t s, int n, const Box& box, const Grid& g,
-                                double rf_ratio, const int32_t* cell_start,
-                                const int32_t* sorted_id, const double4* spos,
-                                const int64_t* offsets, int32_t* tmp) {
-  hipLaunchKernelGGL((k_neighbors<true>), dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s,
-                     n, box, g, rf_ratio, cell_start, sorted_id, spos, nullptr, offsets, tmp);
-  return hipGetLastError();
+size_t transpose_work_bytes(int64_t n, int64_t nnz) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return 3 * al((size_t)n * sizeof(int32_t)) + al((size_t)scan_tmp_elems(n) * sizeof(int64_t)) +
+         3 * al((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t)) +
+         al((size_t)std::max<int64_t>(n, 1) * sizeof(int32_t)) + al(2 * sizeof(int32_t));
 }
 
-hipError_t launch_neighbor_count_rows(hipStream_t s, int m, const int32_t* rows, int n,
-                                      const double* pos, const double* lam, const Box& box,
-                                      const Grid& g, double rf_ratio, const int32_t* cell_start,
-                                      const int32_t* sorted_id, const double4* spos,
-                                      int32_t* count) {
-  hipLaunchKernelGGL((k_neighbors_rows<false>), dim3(grid_for(m, NB_THREADS)), dim3(NB_THREADS),
-                     0, s, m, rows, n, pos, lam, box, g, rf_ratio, cell_start, sorted_id, spos,
-                     count, nullptr, nullptr);
-  return hipGetLastError();
-}
-
-hipError_t launch_neighbor_fill_rows(hipStream_t s, int m, const int32_t* rows, int n,
-                                     const double* pos, const double* lam, const Box& box,
-                                     const Grid& g, double rf_ratio, const int32_t* cell_start,
-                                     const int32_t* sorted_id, const double4* spos,
-                                     const int64_t* offsets, int32_t* tmp) {
-  hipLaunchKernelGGL((k_neighbors_rows<true>), dim3(grid_for(m, NB_THREADS)), dim3(NB_THREADS),
-                     0, s, m, rows, n, pos, lam, box, g, rf_ratio, cell_start, sorted_id, spos,
-                     nullptr, offsets, tmp);
-  return hipGetLastError();
-}
-
-hipError_t launch_row_sort(hipStream_t s, int64_t nrows, const int64_t* off, const int32_t* in,
-                           int32_t* out) {
-  const int64_t sblocks = std::min<int64_t>(std::max<int64_t>((nrows + 3) / 4, 1), 65536);
-  hipLaunchKernelGGL(k_row_sort_short, dim3((unsigned)sblocks), dim3(256), 0, s, nrows, off, in,
-                     out);
-  // rows longer than SHORT_ROW are rare: a small grid strides over all rows
-  // and sorts only those
-  const int64_t blocks = std::min<int64_t>(std::max<int64_t>(nrows, 1), 2048);
-  hipLaunchKernelGGL(k_row_sort, dim3((unsigned)blocks), dim3(64), 0, s, nrows, off, in, out,
-                     SHORT_ROW + 1);
-  return hipGetLastError();
-}
-
-hipError_t launch_transpose(hipStream_t s, int n, int64_t nnz, const int64_t* off,
-                            const int32_t* idx, int64_t* toff, int32_t* tsrc, int32_t* tpos,
-                            int32_t* count, int64_t* scan_tmp, int32_t* tmp) {
-  hipError_t e = fill_i32(s, count, 0, n);
+hipError_t launch_transpose(hipStream_t s, int n, const int64_t* off, const int32_t* idx,
+                            int64_t* toff, int32_t* tsrc, int32_t* tpos,
+                            const TransposeWork& w) {
+  hipError_t e = fill_i32(s, w.bcnt, 0, n);
   if (e != hipSuccess) return e;
-  if (nnz > 0)
-    hipLaunchKernelGGL(k_t_count, dim3(grid_for(nnz, NB_THREADS)), dim3(NB_THREADS), 0, s, nnz,
-                       idx, count);
-  e = exclusive_scan_i32_to_i64(s, count, n, toff, scan_tmp);
-  if (e != hipSuccess) return e;
-  e = fill_i32(s, count, 0, n);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_t_fill, dim3(grid_for((int64_t)n * TL, NB_THREADS)), dim3(NB_THREADS), 0, s,
-                     n, off, idx, toff, count, tmp);
-  e = launch_row_sort(s, n, toff, tmp, tsrc);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_t_pos, dim3(grid_for((int64_t)n * TL, NB_THREADS)), dim3(NB_THREADS), 0, s,
-                     n, off, idx, toff, tsrc, tpos);
+  if ((e = fill_i32(s, w.counts, 0, 2)) != hipSuccess) return e;
+  const dim3 gw(grid_for(n, NB_WAVES));
+  hipLaunchKernelGGL(k_tr_mutual, gw, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, w.acnt,
+                     w.bcnt);
+  hipLaunchKernelGGL(k_tr_total, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n,
+                     w.acnt, w.bcnt, w.tcount);
+  if ((e = exclusive_scan_i32_to_i64(s, w.tcount, n, toff, w.scan)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_tr_oneway, gw, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, toff, w.acnt,
+                     w.bcnt, w.tkey, w.tpay);
+  hipLaunchKernelGGL(k_tr_rows, gw, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, toff, w.tkey,
+                     w.tpay, tsrc, tpos, w.long_list, w.counts + 1);
+  hipLaunchKernelGGL(k_tr_long, dim3(NB_LONG_BLOCKS * NB_WAVES), dim3(64), 0, s, w.long_list,
+                     w.counts + 1, toff, w.tkey, w.tpay, tsrc, tpos);
   return hipGetLastError();
 }
 
