@@ -444,7 +444,9 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * right-hand side, first derivatives), 0 with nine rows (the stabilisers,
  * second derivatives); the forms agree within the mixed tolerance),
  * "fit_fields" (2 or 4: fields per lane in the FP64 form's fit right-hand
- * sides), "fp64_cut_x10" (-1..999: in the FP64 form a fit whose equilibrated
+ * sides), "moments_mfma" (0 or 1: the mixed form's FP32 moments on the
+ * matrix cores, 16 x 16 x 4 FP32 products of the weighted monomials),
+ * "fp64_cut_x10" (-1..999: in the FP64 form a fit whose equilibrated
  * inverse has an operator row of 2-norm above 10^(value / 10) is refined on
  * the data; -1, the default, takes 10^2.5 with three rows and 10^1.7 with
  * nine, 999 refines none; moves results within the FP64 tolerance).  EINVAL
@@ -453,8 +455,8 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value);
 int phb_tune_get(phb_ctx* ctx, const char* key, int* value);
 /* Autotuner: times one forward + reverse pass of the given set (or batch
  * concatenation) for each value of each of lanes_moments, lanes_apply,
- * lanes_adj_y, lanes_gather, adj_pairs_mode, record_order and fit_fields in
- * turn
+ * lanes_adj_y, lanes_gather, adj_pairs_mode, record_order, fit_fields and
+ * moments_mfma in turn
  * (coordinate descent from the current values; median of reps timed passes
  * after one warm-up; a value must win by 2% to replace the current one) and
  * leaves the winners set on ctx.  nnz (host) = offsets[n].  cache_path: NULL,

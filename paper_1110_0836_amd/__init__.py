@@ -367,7 +367,7 @@ def phb_courant_dt(setup, q, lam, frozen, cfl):
 
 TUNE_KEYS = ("cells_per_rf", "lanes_moments", "lanes_apply", "lanes_adj_y", "lanes_gather",
              "adj_pairs_mode", "record_order", "mixed_cond_x10", "mixed_refine", "fp64_cut_x10",
-             "fit_fields")
+             "fit_fields", "moments_mfma")
 
 
 def phb_tune_set(key, value, device=None):

@@ -520,6 +520,7 @@ static int* tune_slot(phb_ctx* ctx, const char* key) {
   if (!strcmp(key, "record_order")) return &ctx->record_order;
   if (!strcmp(key, "fp64_cut_x10")) return &ctx->fp64_cut_x10;
   if (!strcmp(key, "fit_fields")) return &ctx->fit_fields;
+  if (!strcmp(key, "moments_mfma")) return &ctx->moments_mfma;
   return nullptr;
 }
 
@@ -528,7 +529,8 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
   int* slot = tune_slot(ctx, key);
   if (!slot) return set_error(ctx, PHB_EINVAL, std::string("unknown tuning key ") + key);
   const bool lanes = strncmp(key, "lanes_", 6) == 0;
-  const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order");
+  const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order") ||
+                    !strcmp(key, "moments_mfma");
   const bool cut = !strcmp(key, "mixed_cond_x10");
   const bool refine = !strcmp(key, "mixed_refine");
   const bool cut64 = !strcmp(key, "fp64_cut_x10");

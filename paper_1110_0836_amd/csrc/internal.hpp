@@ -34,6 +34,7 @@ struct phb_ctx {
   int lanes_adj_y = 2;
   int lanes_gather = 4;
   int fit_fields = 4;        // FP64 fit right-hand sides: fields per lane (2, 4)
+  int moments_mfma = 0;      // mixed form: FP32 moments on the matrix cores (1)
   int mixed_cond_x10 = -1;  // mixed form: FP64 path above ||A_hat^-1|| ~ 10^(x10 / 10)
   int mixed_refine = 2;     // mixed form: 1 operator-level, 0 data-level, 2 by shape
   int fp64_cut_x10 = -1;    // refinement of fits whose inverse has a row norm above

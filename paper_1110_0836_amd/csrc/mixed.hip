@@ -589,7 +589,7 @@ int mixed_fit(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int nf,
   const unsigned gq = grid_for((int64_t)n * 4, THREADS);
   int rc;
   { Prof pf(ctx, "k_moments<fp32>");
-    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, m.mom, true), "moments")))
+    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->moments_mfma ? 0 : ctx->lanes_assemble, m.mom, true), "moments")))
       return rc; }
   { Prof pf(ctx, "k_mixed_b");
     hipLaunchKernelGGL(k_mixed_b, dim3(gq), dim3(THREADS), 0, s, n, a.geo, a.off, a.idx, a.box,
@@ -669,7 +669,7 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
   const unsigned gq = grid_for((int64_t)n * 4, THREADS);
   int rc;
   { Prof pf(ctx, "k_moments<fp32>");
-    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, m.mom, true), "moments")))
+    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->moments_mfma ? 0 : ctx->lanes_assemble, m.mom, true), "moments")))
       return rc; }
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
   { Prof pf(ctx, "k_mixed_screen");

@@ -101,6 +101,109 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
+// The FP32 moments on the matrix cores: A = P^T W P (P: the entries' 20
+// monomials) as 16 x 16 x 4 FP32 MFMA products over groups of four entries,
+// one wavefront per particle.  Lane l feeds monomial l % 16 (and 16 + l % 16,
+// the four cubic monomials past the first tile) of entry l / 16 of the group:
+// the A operand is p_c(xi), the B operand w p_c(xi), and the 32 x 32 padded
+// product needs three tiles by symmetry (rows/columns 0-15 x 0-15, 0-15 x
+// 16-31, 16-31 x 16-31), whose valid entries hold every one of the 84
+// moments; a table names the lane and register that writes each.  The
+// displacement and weight are formed in FP64 and rounded to FP32, as in the
+// VALU kernel; the monomials are x^a y^b z^c from per-lane exponents.
+struct MfmaMomTab {
+  int8_t id[3][4][64];  // moment written by (tile, register, lane), or -1
+  int8_t ex[16][3], ex_hi[16][3];  // exponents of monomials c and 16 + c
+};
+
+constexpr MfmaMomTab make_mfma_mom_tab() {
+  MfmaMomTab t{};
+  bool done[NMOM] = {};
+  for (int tile = 0; tile < 3; ++tile)
+    for (int reg = 0; reg < 4; ++reg)
+      for (int lane = 0; lane < 64; ++lane) t.id[tile][reg][lane] = -1;
+  const int r0[3] = {0, 0, 16}, c0[3] = {0, 16, 16};
+  for (int tile = 0; tile < 3; ++tile)
+    for (int lane = 0; lane < 64; ++lane)
+      for (int reg = 0; reg < 4; ++reg) {
+        const int r = r0[tile] + 4 * (lane / 16) + reg, c = c0[tile] + lane % 16;
+        if (r >= NBASIS || c >= NBASIS) continue;
+        const int k = entry_moment(r, c);
+        if (!done[k]) {
+          done[k] = true;
+          t.id[tile][reg][lane] = (int8_t)k;
+        }
+      }
+  for (int c = 0; c < 16; ++c) {
+    t.ex[c][0] = (int8_t)basis_expo(c).a;
+    t.ex[c][1] = (int8_t)basis_expo(c).b;
+    t.ex[c][2] = (int8_t)basis_expo(c).c;
+    const int h = 16 + c < NBASIS ? 16 + c : 0;
+    t.ex_hi[c][0] = (int8_t)(16 + c < NBASIS ? basis_expo(h).a : -1);
+    t.ex_hi[c][1] = (int8_t)basis_expo(h).b;
+    t.ex_hi[c][2] = (int8_t)basis_expo(h).c;
+  }
+  return t;
+}
+
+__constant__ MfmaMomTab c_mfma_tab = make_mfma_mom_tab();
+
+// x^e for e in 0..3 from precomputed powers
+__device__ __forceinline__ float pow3_sel(int e, float x, float x2, float x3) {
+  return e == 0 ? 1.0f : (e == 1 ? x : (e == 2 ? x2 : x3));
+}
+
+__global__ void __launch_bounds__(THREADS)
+    k_moments_mfma(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                   const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
+                   double* __restrict__ mom, const int32_t* __restrict__ rows) {
+  typedef float float4_t __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  const int i = __builtin_amdgcn_readfirstlane(xcd_block() * (THREADS / 64) + (threadIdx.x >> 6));
+  if (i >= n) return;  // whole wavefronts
+  const int c = lane & 15, k = lane >> 4;
+  const int ea = c_mfma_tab.ex[c][0], eb = c_mfma_tab.ex[c][1], ec = c_mfma_tab.ex[c][2];
+  const int ha = c_mfma_tab.ex_hi[c][0], hb = c_mfma_tab.ex_hi[c][1],
+            hc = c_mfma_tab.ex_hi[c][2];
+  const double4 gi = geo[rows ? rows[i] : i];
+  const double inv_lam = 1.0 / gi.w;
+  const double r = rf_ratio * gi.w;
+  const double inv_r2 = 1.0 / (r * r);
+  const int64_t s0 = off[i], s1 = off[i + 1];
+  float4_t t00 = {0.f, 0.f, 0.f, 0.f}, t01 = t00, t11 = t00;
+  for (int64_t g = s0; g < s1; g += 4) {
+    const int64_t s = g + k;
+    float w = 0.f, x = 0.f, y = 0.f, z = 0.f;
+    if (s < s1) {
+      const double4 gj = geo[idx[s]];
+      const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+      const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+      const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+      w = (float)weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
+      x = (float)(dx * inv_lam);
+      y = (float)(dy * inv_lam);
+      z = (float)(dz * inv_lam);
+    }
+    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    const float plo = pow3_sel(ea, x, x2, x2 * x) * pow3_sel(eb, y, y2, y2 * y) *
+                      pow3_sel(ec, z, z2, z2 * z);
+    const float phi = ha < 0 ? 0.0f
+                             : pow3_sel(ha, x, x2, x2 * x) * pow3_sel(hb, y, y2, y2 * y) *
+                                   pow3_sel(hc, z, z2, z2 * z);
+    t00 = __builtin_amdgcn_mfma_f32_16x16x4f32(plo, w * plo, t00, 0, 0, 0);
+    t01 = __builtin_amdgcn_mfma_f32_16x16x4f32(plo, w * phi, t01, 0, 0, 0);
+    t11 = __builtin_amdgcn_mfma_f32_16x16x4f32(phi, w * phi, t11, 0, 0, 0);
+  }
+  const float4_t tl[3] = {t00, t01, t11};
+#pragma unroll
+  for (int tile = 0; tile < 3; ++tile)
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) {
+      const int m = c_mfma_tab.id[tile][reg][lane];
+      if (m >= 0) mom[(int64_t)m * soa_ld(n) + i] = (double)tl[tile][reg];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 2. factor: equilibrated FP64 Cholesky, four lanes per particle
 // ---------------------------------------------------------------------------
@@ -626,6 +729,12 @@ hipError_t launch_moments_g(hipStream_t s, const EvalArgs& a, double* mom) {
 
 hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom, bool fp32) {
   if (fp32) {
+    if (lanes == 0) {
+      hipLaunchKernelGGL(k_moments_mfma, dim3(grid_for((int64_t)a.n * 64, THREADS)),
+                         dim3(THREADS), 0, s, a.n, a.geo, a.off, a.idx, a.box, a.rf_ratio, a.wkind,
+                         mom, a.rows);
+      return hipGetLastError();
+    }
     switch (lanes) {
       case 1: return launch_moments_g<1, float>(s, a, mom);
       case 2: return launch_moments_g<2, float>(s, a, mom);

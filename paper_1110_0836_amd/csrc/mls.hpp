@@ -64,6 +64,7 @@ __host__ __device__ inline const double* tape_aos(const double* tape, int64_t n)
 hipError_t launch_pack(hipStream_t s, int n, const double* pos, const double* lam,
                        const double* q, double4* geo, double* fq);
 // fp32: accumulate in FP32 (the mixed form); the moments are stored in FP64.
+// lanes: 1, 2 or 4 per particle; with fp32, 0 runs the matrix-core kernel.
 hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* mom,
                           bool fp32 = false);
 // Screen (list != null): status-0 particles whose equilibrated inverse has one
