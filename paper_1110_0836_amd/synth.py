@@ -39,6 +39,25 @@ def jittered_lattice(side: int, jitter: float = 0.3, rng=None, box: float = 1.0)
     return pos
 
 
+def tiled_lattice(base: int, tiles: int, jitter: float = 0.3, seed: int = 11,
+                  box: float = 1.0):
+    """A jittered base^3 lattice of the unit cube, scaled by 1/tiles and tiled
+    tiles^3 times to fill the box: (base tiles)^3 points whose neighborhoods
+    repeat the base set's at every resolution (Sec. 3.1 refines its relaxed
+    set this way, so that convergence studies see the same local particle
+    arrangements).  Index order: tiles in x fastest, then y, then z."""
+    rng = np.random.default_rng(seed)
+    b = jittered_lattice(base, jitter, rng)
+    parts = []
+    for tz in range(tiles):
+        for ty in range(tiles):
+            for tx in range(tiles):
+                parts.append((b + np.array([[tx], [ty], [tz]], dtype=np.float64)) / tiles)
+    pos = np.concatenate(parts, axis=1) * box
+    pos[pos >= box] -= box
+    return pos
+
+
 # Exponent table of the cubic polynomial fields (all |alpha| <= 3), used only
 # to draw test inputs with a known polynomial form.
 CUBIC_EXPONENTS = [(a, b, c) for a in range(4) for b in range(4) for c in range(4)
@@ -194,7 +213,8 @@ def shear_layer(seed: int = 3, n: int = 1 << 20):
                 name=f"shear_layer_adaptive_{n}")
 
 
-def linear_wave(kind: str, side: int, eps: float = 1e-6, seed: int = 6, jitter: float = 0.3):
+def linear_wave(kind: str, side: int, eps: float = 1e-6, seed: int = 6, jitter: float = 0.3,
+                base: int = 0):
     """Linear-wave set of Sec. 3.1: a jittered side^3 lattice in the periodic unit
     cube, rho = 1, P = 1/gamma (sound speed 1), gamma = 5/3, carrying
     eps R cos(2 pi x - omega t) at t = 0 with R of unit 2-norm:
@@ -205,9 +225,11 @@ def linear_wave(kind: str, side: int, eps: float = 1e-6, seed: int = 6, jitter: 
     The other components follow from the linearized equations (App. A with no
     viscosity): rho = rho0 k.V/omega, P = gamma P0 k.V/omega,
     B = (B0 k.V - (k.B0) V)/omega, sigma = P/(gamma - 1).  Returns the set with
-    omega, R, eps and the background q0."""
+    omega, R, eps and the background q0.  base > 0: the particles are a jittered
+    base^3 cube tiled side / base times per axis (tiled_lattice)."""
     rng = np.random.default_rng(seed)
-    pos = jittered_lattice(side, jitter, rng)
+    pos = (tiled_lattice(base, side // base, jitter, seed) if base else
+           jittered_lattice(side, jitter, rng))
     n = pos.shape[1]
     lam = np.full(n, 1.0 / side)
     rho0, P0 = 1.0, 1.0 / GAMMA
@@ -259,11 +281,14 @@ def batched_cubes(seed: int = 5, n_sets: int = 32, smin: int = 16, smax: int = 6
     return dict(sets=sets, sides=sides, name=f"batched_{n_sets}_sets")
 
 
-def cp_alfven(side: int = 16, seed: int = 7, jitter: float = 0.3, gamma: float = GAMMA):
+def cp_alfven(side: int = 16, seed: int = 7, jitter: float = 0.3, gamma: float = GAMMA,
+              base: int = 0):
     """Circularly polarized Alfven wave initial state (Sec. 3.2): rho = 1, Vx = 0,
-    Bx = 1, Vy = By = 0.1 sin 2 pi x, Vz = Bz = 0.1 cos 2 pi x, P = 0.1."""
+    Bx = 1, Vy = By = 0.1 sin 2 pi x, Vz = Bz = 0.1 cos 2 pi x, P = 0.1.  base > 0:
+    particles tiled from a base^3 cube (tiled_lattice)."""
     rng = np.random.default_rng(seed)
-    pos = jittered_lattice(side, jitter, rng)
+    pos = (tiled_lattice(base, side // base, jitter, seed) if base else
+           jittered_lattice(side, jitter, rng))
     n = pos.shape[1]
     lam = np.full(n, 1.0 / side)
     x = pos[0]

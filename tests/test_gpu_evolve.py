@@ -9,6 +9,7 @@ diffusion on, the remainder converges and the magnetoacoustic mode decays at
 App. A's rate."""
 import numpy as np
 import pytest
+from scipy.linalg import expm
 
 import oracle
 from paper_1110_0836_amd import synth
@@ -181,6 +182,91 @@ def test_stabilised_magnetized_waves_converge(kind):
         assert abs(a / want - 1) < (0.03 if side == 16 else 0.005) and abs(ph) < 0.05
     order = np.log2(out[16][0] / out[32][0])
     assert order > 1.3, order
+
+
+def viscous_linear_solution(c, T, zeta):
+    """Exact solution at time T of App. A's linearized equations with bulk
+    viscosity zeta (k = 2 pi along x) for the set's initial data
+    q0 + eps R cos(k x): the complex amplitudes u = (rho, V, B, P) obey
+    du/dt = M u with
+      rho' = -i k rho0 Vx,
+      rho0 V' = -i k (P + B0 . B) x + i k B0x B - zeta rho0 k^2 Vx x,
+      B' = i k B0x V - i k Vx B0,      P' = -i k gamma P0 Vx,
+    and q(x, T) = q0 + eps Re(exp(M T) R exp(i k x)) (sigma = P / (gamma - 1)).
+    The compressive modes decay at zeta k^2 / 2 and carry an O(k zeta / c)
+    phase between V and (rho, B, P); the shear Alfven mode is unchanged."""
+    k = 2 * np.pi
+    g = c["gamma"]
+    q0 = c["q0"]
+    rho0, B0, P0 = q0[0], q0[4:7], q0[7] * (g - 1.0)
+    M = np.zeros((8, 8), dtype=complex)  # (rho, Vx, Vy, Vz, Bx, By, Bz, P)
+    M[0, 1] = -1j * k * rho0
+    M[1, 7] = -1j * k / rho0
+    for a in range(3):
+        M[1, 4 + a] += -1j * k * B0[a] / rho0
+        M[1 + a, 4 + a] += 1j * k * B0[0] / rho0
+        M[4 + a, 1 + a] += 1j * k * B0[0]
+        M[4 + a, 1] += -1j * k * B0[a]
+    M[1, 1] = -zeta * k * k
+    M[7, 1] = -1j * k * g * P0
+    R = c["R"].astype(complex)
+    R[7] *= g - 1.0
+    u = expm(M * T) @ R
+    u[7] /= g - 1.0
+    return u
+
+
+@pytest.mark.parametrize("kind", ["sound", "alfven", "fast"])
+def test_linear_waves_converge_at_second_order(kind):
+    """Sec. 3.1 as the paper measures it: each wave propagated one period with
+    the stabilisers on, the L1 error summed over all fields against the exact
+    solution of the viscous linear equations for the same initial data (App.
+    A; for the compressive waves it depends on the resolution through
+    zeta = c_g lambda c_f), divided by that solution's perturbation; particle
+    sets refined by tiling one 8^3 cube, as the paper tiles its relaxed set.
+    At least second order between every pair of the resolutions 16, 24, 32."""
+    errs = {}
+    for side in (16, 24, 32):
+        c = synth.linear_wave(kind, side, base=8)
+        T = 2 * np.pi / c["omega"]
+        pos, q, st, nsteps = run(c, T, setup=setup_of(c, **STAB))
+        assert np.all(st == 0)
+        c_f = np.sqrt((c["gamma"] * c["q0"][7] * (c["gamma"] - 1.0) + (c["q0"][4:7] ** 2).sum())
+                      / c["q0"][0])
+        u = viscous_linear_solution(c, T, STAB["visc_grid"] / side * c_f)
+        pert = c["eps"] * np.real(u[:, None] * np.exp(2j * np.pi * pos[0])[None, :])
+        errs[side] = np.abs(q - c["q0"][:, None] - pert).sum() / np.abs(pert).sum()
+        print(f"stabilised {kind} wave {side}^3, one period ({nsteps} steps): relative L1 error "
+              f"{errs[side]:.3e}")
+    o1 = np.log(errs[16] / errs[24]) / np.log(1.5)
+    o2 = np.log(errs[24] / errs[32]) / np.log(4 / 3)
+    o = np.log2(errs[16] / errs[32])
+    print(f"{kind}: orders 16-24 {o1:.2f}, 24-32 {o2:.2f}, 16-32 {o:.2f}")
+    assert o >= 2.0 and o1 >= 1.8 and o2 >= 1.8
+
+
+def test_cp_alfven_one_crossing_converges_at_second_order():
+    """Sec. 3.2's wave after one crossing (stabilisers on, tiled sets 16, 24,
+    32): the L1 error over all fields against the exact travelling wave, over
+    the wave's own size, falls at least at second order."""
+    errs = {}
+    for side in (16, 24, 32):
+        c = synth.cp_alfven(side, base=8)
+        pos, q, st, nsteps = run(c, 1.0, setup=setup_of(c, **STAB))
+        assert np.all(st == 0)
+        x = pos[0] + 1.0
+        ex = np.zeros_like(q)
+        ex[0], ex[4], ex[7] = 1.0, 1.0, 0.1 / (c["gamma"] - 1.0)
+        bg = ex.copy()
+        ex[2] = ex[5] = 0.1 * np.sin(2 * np.pi * x)
+        ex[3] = ex[6] = 0.1 * np.cos(2 * np.pi * x)
+        errs[side] = np.abs(q - ex).sum() / np.abs(ex - bg).sum()
+        print(f"stabilised CP Alfven {side}^3, one crossing ({nsteps} steps): relative L1 error "
+              f"{errs[side]:.3e}")
+    o = np.log2(errs[16] / errs[32])
+    o2 = np.log(errs[24] / errs[32]) / np.log(4 / 3)
+    print(f"CP Alfven, one crossing: orders 16-32 {o:.2f}, 24-32 {o2:.2f}")
+    assert o >= 2.0 and o2 >= 1.8
 
 
 def test_stabilised_cp_alfven_converges():
