@@ -145,9 +145,13 @@ def test_autograd_full_size_vs_oracle_samples_and_fd():
     gbar = np.zeros((8, n))
     gbar[1:4, rows] = 2 * w[None, rows] * orhs[1:4]
     oq, op = oracle.adjoint_sampled(c["pos"], c["lam"], c["q"], gbar, samples)
+    eq = max(grad_err(qg[f, samples], oq[f]) for f in range(8))
+    ep = grad_err(pg[:, samples], op)
+    print(f"config-4 set, 24 sampled columns: q_bar {eq:.2e}, pos_bar {ep:.2e}")
+    # every fit of this lattice is well conditioned: the FP64 contract's 1e-12
     for f in range(8):
-        assert grad_err(qg[f, samples], oq[f]) < 1e-11, f
-    assert grad_err(pg[:, samples], op) < 1e-11
+        assert grad_err(qg[f, samples], oq[f]) < 1e-12, f
+    assert grad_err(pg[:, samples], op) < 1e-12
     # (b) central finite differences with h = 1e-6 on 64 random coordinates of the
     # 11 n inputs.  The wave amplitude (1e-6) is no larger than h, so the cubic
     # term of the loss leaves the plain difference ~1e-5 off; the comparison
@@ -190,11 +194,16 @@ def test_shear_layer_full_size_samples():
     c = synth.shear_layer()
     n = c["lam"].shape[0]
     rng = np.random.default_rng(5)
-    gbar = np.zeros((8, n))
-    gbar[1:4] = rng.uniform(0, 1, n)[None] * rng.normal(size=(3, n))
+    # incoming gradients on all eight time derivatives: dV/dt alone vanishes
+    # on this set (uniform pressure and field) and would leave pos_bar zero
+    gbar = rng.uniform(0, 1, n)[None] * rng.normal(size=(8, n))
     qb, pb = gpu_adjoint(c, gbar)
     samples = rng.choice(n, 12, replace=False)
     oq, op = oracle.adjoint_sampled(c["pos"], c["lam"], c["q"], gbar, samples)
+    eq = max(grad_err(qb[f, samples], oq[f]) for f in range(8))
+    ep = grad_err(pb[:, samples], op)
+    print(f"shear layer, 12 sampled columns: q_bar {eq:.2e}, pos_bar {ep:.2e}")
+    assert np.abs(op).max() > 0
     for f in range(8):
-        assert grad_err(qb[f, samples], oq[f]) < 1e-11, f
-    assert grad_err(pb[:, samples], op) < 1e-11
+        assert grad_err(qb[f, samples], oq[f]) < 1e-12, f
+    assert grad_err(pb[:, samples], op) < 1e-12

@@ -114,6 +114,15 @@ def test_rhs_cp_alfven():
     check_rhs(*rhs_both(synth.cp_alfven(16), precision=P.PHB_MIXED), TOLMIX)
 
 
+def test_rhs_fast_wave_full_size_sampled():
+    """The 262,144-particle fast-magnetosonic wave set (64^3 jittered lattice) in
+    the mixed form: 2000 sampled rows against the oracle's rows."""
+    c = synth.fast_wave_set()
+    assert c["lam"].shape[0] == 262144
+    rows = np.random.default_rng(3).choice(c["lam"].shape[0], 2000, replace=False)
+    check_rhs(*rhs_both(c, rows=rows, precision=P.PHB_MIXED), TOLMIX)
+
+
 def test_rhs_shear_layer_full_size_sampled():
     c = synth.shear_layer()
     rows = np.random.default_rng(4).choice(c["lam"].shape[0], 300, replace=False)
