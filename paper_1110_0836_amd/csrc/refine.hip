@@ -197,18 +197,29 @@ __global__ void __launch_bounds__(THREADS)
 
 // The listed particles' refined coefficients (nf fields, cbuf [nf][20][ldc]
 // by list position) into their tape records at coff (len doubles per
-// particle); grid-stride.
+// particle).  A block takes 32 list positions at a time through LDS: it reads
+// each coefficient row for the 32 positions (contiguous) and writes each
+// particle's nf x 20 coefficients (contiguous); the grid strides over the
+// list.
+constexpr int TAPE_TILE = 32;
+
 __global__ void __launch_bounds__(THREADS)
     k_ref_tape_c(const int32_t* __restrict__ list, const int32_t* __restrict__ count, int nf,
                  const double* __restrict__ cbuf, int64_t ldc, double* __restrict__ aos, int len,
                  int coff) {
-  const int64_t tot = (int64_t)*count * nf * NBASIS;
-  for (int64_t t = (int64_t)blockIdx.x * THREADS + threadIdx.x; t < tot;
-       t += (int64_t)gridDim.x * THREADS) {
-    const int k = (int)(t / (nf * NBASIS));
-    const int e = (int)(t % (nf * NBASIS));
-    const int i = list[k];
-    aos[(int64_t)i * len + coff + e] = cbuf[e * ldc + k];
+  __shared__ double tile[TAPE_TILE][8 * NBASIS + 1];
+  const int m = *count;
+  const int ne = nf * NBASIS;
+  for (int k0 = blockIdx.x * TAPE_TILE; k0 < m; k0 += gridDim.x * TAPE_TILE) {
+    const int kk = threadIdx.x % TAPE_TILE;
+    for (int e = threadIdx.x / TAPE_TILE; e < ne; e += THREADS / TAPE_TILE)
+      if (k0 + kk < m) tile[kk][e] = cbuf[e * ldc + k0 + kk];
+    __syncthreads();
+    for (int t = threadIdx.x; t < TAPE_TILE * ne; t += THREADS) {
+      const int q = t / ne, e = t % ne;
+      if (k0 + q < m) aos[(int64_t)list[k0 + q] * len + coff + e] = tile[q][e];
+    }
+    __syncthreads();
   }
 }
 
@@ -534,12 +545,14 @@ static unsigned list_grid(int64_t threads) {
   return (unsigned)std::max<int64_t>(1, std::min(g, REF_MAX_BLOCKS));
 }
 
-double fp64_screen_cut(const phb_ctx* ctx, int nrows) {
+double fp64_screen_cut(const phb_ctx* ctx, int nrows, bool data_form) {
   // defaults measured on open-box cubic fields, graded lambdas and the shear
   // layer: below them the operator form stays within about 1e-13 of the
   // exact fit for the first derivatives (rows 1..3, cut 10^2.5) and within
-  // 2e-13 for the second (rows 1..9, cut 10^1.7)
-  const int x10 = ctx->fp64_cut_x10 >= 0 ? ctx->fp64_cut_x10 : (nrows > 3 ? 17 : 25);
+  // 2e-13 for the second (rows 1..9, cut 10^1.7); the data form's solve has
+  // no cancellation of G . p_j and takes 10^2.5 for both
+  const int x10 = ctx->fp64_cut_x10 >= 0 ? ctx->fp64_cut_x10
+                                          : ((nrows > 3 && !data_form) ? 17 : 25);
   return x10 >= 999 ? 1e300 : pow(10.0, 0.1 * x10);
 }
 
@@ -595,8 +608,11 @@ int refine_tape(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom, cons
                 double* aos) {
   const int nf = nr == 9 ? 8 : 7;
   Prof pf(ctx, "k_ref_tape");
-  hipLaunchKernelGGL(k_ref_tape_c, dim3(list_grid((int64_t)a.n * nf * NBASIS)), dim3(THREADS), 0,
-                     ctx->stream, r.list, r.count, nf, r.cbuf, r.ldc, aos, TAPE_AOS, nr * NBASIS);
+  // each block holds a 41 KB tile: two per CU stride over the list (empty
+  // blocks of a larger grid cost more than the loop)
+  const unsigned grid = std::min<unsigned>(list_grid((int64_t)a.n * THREADS / TAPE_TILE), 512);
+  hipLaunchKernelGGL(k_ref_tape_c, dim3(grid), dim3(THREADS), 0, ctx->stream, r.list, r.count, nf,
+                     r.cbuf, r.ldc, aos, TAPE_AOS, nr * NBASIS);
   int rc = hip_check(ctx, hipGetLastError(), "tape coefficients");
   return rc ? rc : refine_oprows(ctx, a, nr, mom, r, aos, TAPE_AOS);
 }
