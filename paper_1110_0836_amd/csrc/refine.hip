@@ -607,12 +607,14 @@ int refine_fits(phb_ctx* ctx, const EvalArgs& a, const double* fa, int fb, int n
 int refine_tape(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom, const RefineBufs& r,
                 double* aos) {
   const int nf = nr == 9 ? 8 : 7;
+  {
   Prof pf(ctx, "k_ref_tape");
   // each block holds a 41 KB tile: two per CU stride over the list (empty
   // blocks of a larger grid cost more than the loop)
   const unsigned grid = std::min<unsigned>(list_grid((int64_t)a.n * THREADS / TAPE_TILE), 512);
   hipLaunchKernelGGL(k_ref_tape_c, dim3(grid), dim3(THREADS), 0, ctx->stream, r.list, r.count, nf,
                      r.cbuf, r.ldc, aos, TAPE_AOS, nr * NBASIS);
+  }
   int rc = hip_check(ctx, hipGetLastError(), "tape coefficients");
   return rc ? rc : refine_oprows(ctx, a, nr, mom, r, aos, TAPE_AOS);
 }
