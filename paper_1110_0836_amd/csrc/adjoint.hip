@@ -1173,7 +1173,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     }
   } else {
     if ((rc = hip_check(ctx, fill_i32(s, rb.count, 0, 1), "clear list"))) return rc;
-    const double rcut = fp64_screen_cut(ctx, NRr);
+    // the operator form runs for the mixed form's tapes only
+    const double rcut = fp64_screen_cut(ctx, NRr, p->precision != PHB_MIXED);
     if (stab) {
       { Prof pf(ctx, "k_adj_u<stab>");
       hipLaunchKernelGGL(k_adj_u<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,

@@ -285,7 +285,7 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   if ((rc = hip_check(ctx, fill_i32(ctx->stream, rb.count, 0, 1), "clear list")) ||
       (rc = hip_check(ctx,
                       launch_factor_fit(ctx->stream, a, nrows, mom, bc, aos, status,
-                                        fp64_screen_cut(ctx, nrows, true), rb.list, rb.count),
+                                        fp64_screen_cut(ctx, nrows, false), rb.list, rb.count),
                       "factor and fit")))
     return rc; }
   { Prof pf(ctx, sb.on() ? "k_rows_rhs_finish<stab>" : "k_rows_rhs_finish");

@@ -545,14 +545,15 @@ static unsigned list_grid(int64_t threads) {
   return (unsigned)std::max<int64_t>(1, std::min(g, REF_MAX_BLOCKS));
 }
 
-double fp64_screen_cut(const phb_ctx* ctx, int nrows, bool data_form) {
+double fp64_screen_cut(const phb_ctx* ctx, int nrows, bool tight_rows) {
   // defaults measured on open-box cubic fields, graded lambdas and the shear
   // layer: below them the operator form stays within about 1e-13 of the
   // exact fit for the first derivatives (rows 1..3, cut 10^2.5) and within
   // 2e-13 for the second (rows 1..9, cut 10^1.7); the data form's solve has
-  // no cancellation of G . p_j and takes 10^2.5 for both
+  // no cancellation of G . p_j, and the mixed form's reverse mode is held to
+  // its own tolerance: both take 10^2.5 for nine rows too
   const int x10 = ctx->fp64_cut_x10 >= 0 ? ctx->fp64_cut_x10
-                                          : ((nrows > 3 && !data_form) ? 17 : 25);
+                                          : ((nrows > 3 && tight_rows) ? 17 : 25);
   return x10 >= 999 ? 1e300 : pow(10.0, 0.1 * x10);
 }
 

@@ -14,9 +14,9 @@ constexpr int REFINE_PASSES = 5;
 
 // Screen cut on the largest 2-norm of a row of the equilibrated inverse
 // among the nrows operator rows a factor kernel computes (the context's
-// fp64_cut_x10, or the default of the shape and form: data_form for fits
-// solved for their coefficients, else the operator form).
-double fp64_screen_cut(const phb_ctx* ctx, int nrows, bool data_form = false);
+// fp64_cut_x10, or the default of the shape: tight_rows for the FP64
+// operator form, whose second-derivative rows are held to FP64 accuracy).
+double fp64_screen_cut(const phb_ctx* ctx, int nrows, bool tight_rows = true);
 
 // List of screened particles (device count) and the refinement's buffers, by
 // list position: coefficients cbuf[f][20][ldc], residual sums dbuf[f][20][ldc],
