@@ -267,17 +267,7 @@ __global__ void __launch_bounds__(THREADS)
       for (int b = 0; b < NBASIS; ++b) y[t][b] = fma(wh, p[b], y[t][b]);
     }
   }
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) y[t][b] = group_sum<G>(y[t][b]);
-  if (valid) {
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-      for (int b = 0; b < NBASIS; ++b)
-        if ((t * NBASIS + b) % G == l) ybuf[((int64_t)t * NBASIS + b) * soa_ld(n) + i] = y[t][b];
-  }
+  store_rows3<G>(&y[0][0], l, valid, ybuf, 0, soa_ld(n), i);
 }
 
 // Ubar [NFA][NR] and the direct qbar, one thread per particle: Ubar into
@@ -419,17 +409,7 @@ __global__ void __launch_bounds__(THREADS)
       for (int b = 0; b < NBASIS; ++b) y[t][b] = fma(wh, p[b], y[t][b]);
     }
   }
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) y[t][b] = group_sum<G>(y[t][b]);
-  if (valid) {
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-      for (int b = 0; b < NBASIS; ++b)
-        if ((t * NBASIS + b) % G == l) ybuf[((int64_t)(r0 + t) * NBASIS + b) * soa_ld(n) + i] = y[t][b];
-  }
+  store_rows3<G>(&y[0][0], l, valid, ybuf, r0, soa_ld(n), i);
 }
 
 // ---- 3. factor again: G = rows 1..3 of A^{-1}, K_t = A^{-1} Y_t ------------
@@ -523,6 +503,50 @@ __device__ __forceinline__ void row_value_grad(const CT* __restrict__ c, const C
          two * p[6] * c[15] + p[7] * c[17] + two * p[8] * c[18] + three * p[9] * c[19];
 }
 
+// Value and gradient of one row's cubic c . p(xi) at xi = (x, y, z), nested
+// over the quadratic monomials so that the 20 monomials are never held:
+// value c0 + c1 x + c2 y + c3 z + xx (c4 + c10 x + c11 y + c12 z)
+//       + xy (c5 + c13 y + c14 z) + xz (c6 + c15 z) + yy (c7 + c16 y + c17 z)
+//       + yz (c8 + c18 z) + zz (c9 + c19 z),
+// and each gradient component likewise.
+template <class CT>
+struct CubicAt {
+  CT x, y, z, xx, xy, xz, yy, yz, zz, x2, y2, z2, x3, y3, z3;
+};
+template <class CT>
+__device__ __forceinline__ CubicAt<CT> cubic_at(CT x, CT y, CT z) {
+  CubicAt<CT> q;
+  q.x = x; q.y = y; q.z = z;
+  q.xx = x * x; q.xy = x * y; q.xz = x * z; q.yy = y * y; q.yz = y * z; q.zz = z * z;
+  q.x2 = x + x; q.y2 = y + y; q.z2 = z + z;
+  q.x3 = CT(3) * x; q.y3 = CT(3) * y; q.z3 = CT(3) * z;
+  return q;
+}
+template <class CT>
+__device__ __forceinline__ void row_value_grad_q(const CT* __restrict__ c, const CubicAt<CT>& q,
+                                                 CT& v, CT (&g)[3]) {
+  const CT c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5], c6 = c[6];
+  const CT c7 = c[7], c8 = c[8], c9 = c[9], c10 = c[10], c11 = c[11], c12 = c[12];
+  const CT c13 = c[13], c14 = c[14], c15 = c[15], c16 = c[16], c17 = c[17], c18 = c[18];
+  const CT c19 = c[19];
+  CT t = fma(c10, q.x, fma(c11, q.y, fma(c12, q.z, c4)));
+  v = fma(q.xx, t, fma(c1, q.x, fma(c2, q.y, fma(c3, q.z, c0))));
+  v = fma(q.xy, fma(c13, q.y, fma(c14, q.z, c5)), v);
+  v = fma(q.xz, fma(c15, q.z, c6), v);
+  v = fma(q.yy, fma(c16, q.y, fma(c17, q.z, c7)), v);
+  v = fma(q.yz, fma(c18, q.z, c8), v);
+  v = fma(q.zz, fma(c19, q.z, c9), v);
+  // gx = c1 + x (2 c4 + 3x c10 + 2y c11 + 2z c12) + y (c5 + y c13 + z c14) + z (c6 + z c15)
+  t = fma(q.x3, c10, fma(q.y2, c11, fma(q.z2, c12, c4 + c4)));
+  g[0] = fma(q.x, t, fma(q.y, fma(q.y, c13, fma(q.z, c14, c5)), fma(q.z, fma(q.z, c15, c6), c1)));
+  // gy = c2 + x (c5 + x c11 + 2y c13 + z c14) + y (2 c7 + 3y c16 + 2z c17) + z (c8 + z c18)
+  t = fma(q.x, c11, fma(q.y2, c13, fma(q.z, c14, c5)));
+  g[1] = fma(q.x, t, fma(q.y, fma(q.y3, c16, fma(q.z2, c17, c7 + c7)), fma(q.z, fma(q.z, c18, c8), c2)));
+  // gz = c3 + x (c6 + x c12 + y c14 + 2z c15) + y (c8 + y c17 + 2z c18) + z (2 c9 + 3z c19)
+  t = fma(q.x, c12, fma(q.y, c14, fma(q.z2, c15, c6)));
+  g[2] = fma(q.x, t, fma(q.y, fma(q.y, c17, fma(q.z2, c18, c8)), fma(q.z, fma(q.z3, c19, c9 + c9), c3)));
+}
+
 // CT: the arithmetic type of the pair terms.  The displacement, the weight and
 // the field differences are formed in FP64 and rounded once.  STAB: the
 // stabilised shape (nine rows, eight fields).
@@ -533,27 +557,25 @@ __device__ __forceinline__ void pair_terms(const CT* __restrict__ o, double w, d
                                            const double* __restrict__ fj,
                                            CT (&v)[Shape<STAB>::REC]) {
   using SH = Shape<STAB>;
-  CT p[NBASIS];
-  basis(p, CT(dx * inv_lam), CT(dy * inv_lam), CT(dz * inv_lam));
-  CT df[SH::NFA];
-#pragma unroll
-  for (int f = 0; f < SH::NFA; ++f) df[f] = CT(fj[SH::F0 + f] - fi[SH::F0 + f]);
   CT h[SH::NR];
 #pragma unroll
   for (int t = 0; t < SH::NR; ++t) h[t] = CT(0);
 #pragma unroll
-  for (int f = 0; f < SH::NFA; ++f)
+  for (int f = 0; f < SH::NFA; ++f) {
+    const CT df = CT(fj[SH::F0 + f] - fi[SH::F0 + f]);
 #pragma unroll
-    for (int t = 0; t < SH::NR; ++t) h[t] = fma(o[SH::UOFF + SH::NR * f + t], df[f], h[t]);
+    for (int t = 0; t < SH::NR; ++t) h[t] = fma(o[SH::UOFF + SH::NR * f + t], df, h[t]);
+  }
+  const CubicAt<CT> q = cubic_at(CT(dx * inv_lam), CT(dy * inv_lam), CT(dz * inv_lam));
   CT av[SH::NR], bv[SH::NR], xg[3] = {CT(0), CT(0), CT(0)};
 #pragma unroll
   for (int t = 0; t < SH::NR; ++t) {
     compiler_fence();
     CT a, ga[3];
-    row_value_grad(o + t * NBASIS, p, a, ga);
+    row_value_grad_q(o + t * NBASIS, q, a, ga);
     compiler_fence();
     CT k, gk[3];
-    row_value_grad(o + SH::KOFF + t * NBASIS, p, k, gk);
+    row_value_grad_q(o + SH::KOFF + t * NBASIS, q, k, gk);
     const CT b = h[t] - k;
 #pragma unroll
     for (int c = 0; c < 3; ++c) xg[c] = fma(b, ga[c], fma(-a, gk[c], xg[c]));
@@ -752,7 +774,9 @@ __global__ void __launch_bounds__(THREADS)
 // The owner's G, K and Ubar are wavefront-uniform and staged in LDS; lanes
 // take the owner's neighbor entries 64 at a time (rows longer than 64
 // entries loop); the owner's own share is one transposed wavefront sum of the
-// record's components at the end.
+// record's components at the end.  Each block is one wavefront: the waves
+// live for different times (row lengths vary 10x), and a block of several
+// holds its slots until the longest of them ends.
 
 // RT: type of the pair records (double; float in the mixed form, where the
 // records are an application-level quantity and halve the record traffic).
@@ -766,7 +790,7 @@ __global__ void __launch_bounds__(THREADS)
 // stages G and Ubar and forms K = Ubar C^T from the record as it stages it
 // (one entry of K per lane and pass, all in the one staging phase).
 template <class RT, class CT = double, bool STAB = false, bool TAPE = false>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(64)
     k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                   const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
                   double rf_ratio, int wkind, const double* __restrict__ fq,
@@ -775,12 +799,12 @@ __global__ void __launch_bounds__(THREADS)
   using SH = Shape<STAB>;
   constexpr int OR = SH::OREC, RC = SH::REC;
   constexpr int NR = SH::NR, NFA = SH::NFA;
-  const int i = __builtin_amdgcn_readfirstlane(xcd_block() * (THREADS / 64) + (threadIdx.x >> 6));
+  const int i = __builtin_amdgcn_readfirstlane(xcd_block());
   const int lane = threadIdx.x & 63;
   // the owner record goes to LDS in one coalesced load per wavefront; the
   // pair terms then read it row by row at LDS latency
-  __shared__ CT osh[THREADS / 64][OR];
-  const int wv = threadIdx.x >> 6;
+  __shared__ CT osh[1][OR];
+  const int wv = 0;
   // Each lane's first entry (index, neighbor geometry, transposed position)
   // is fetched before the record is staged, so that this dependent chain of
   // loads overlaps the staging; later entries are fetched one iteration
@@ -991,13 +1015,13 @@ template <bool STAB, class RT>
 void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const double* fq,
                     const int32_t* t_pos, const double* orec, const double* ubuf, RT* rec,
                     double* own, int slot_order) {
-  const dim3 grid(grid_for((int64_t)a.n * 64, THREADS));
+  const dim3 grid(grid_for(a.n, 1));  // one wavefront per owner, one per block
   if (ubuf)
-    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, true>), grid, dim3(THREADS), 0, s, a.n,
+    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, true>), grid, dim3(64), 0, s, a.n,
                        geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec,
                        own, slot_order);
   else
-    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, false>), grid, dim3(THREADS), 0, s, a.n,
+    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, false>), grid, dim3(64), 0, s, a.n,
                        geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec,
                        own, slot_order);
 }

@@ -290,6 +290,67 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Reduce-scatter over the G = 1, 2 or 4 lanes of an aligned group: every lane
+// holds N partial values a[0 .. N), and lane e of the group receives
+// r[m] = the group's sum of a[G m + e], m < N / G.  Each step pairs two of a
+// lane's values, keeps the one its half of the group owns and sends the
+// other, so a lane sends half of what it holds per step (group_sum sends all
+// of it) and ends with only the sums it stores.  Every sum is formed as
+// group_sum<G> forms it (the pair's sum, then the sum of the two pair sums;
+// the additions commute), so the values are bit-identical to it.
+// The pairs retire one at a time: each next pair is tied to the previous
+// sum, so the selected and exchanged copies of all values are never live
+// together (hoisted, they double the register footprint).
+template <int G, int N, class T>
+__device__ __forceinline__ void group_reduce_scatter(T* a, T* r, int e) {
+  static_assert(G == 1 || G == 2 || G == 4, "group of 1, 2 or 4 lanes");
+  static_assert(N % G == 0, "the values split evenly over the group");
+  if constexpr (G == 1) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) r[k] = a[k];
+  } else {
+    const bool odd = (e & 1) != 0;
+    T h[N / 2];
+#pragma unroll
+    for (int m = 0; m < N / 2; ++m) {
+      const T keep = odd ? a[2 * m + 1] : a[2 * m];
+      const T send = odd ? a[2 * m] : a[2 * m + 1];
+      h[m] = keep + quad_xor1(send);  // the pair's sum of a[2 m + (e & 1)]
+      if (m + 1 < N / 2) asm volatile("" : "+v"(a[2 * m + 2]), "+v"(a[2 * m + 3]) : "v"(h[m]));
+    }
+    if constexpr (G == 2) {
+#pragma unroll
+      for (int m = 0; m < N / 2; ++m) r[m] = h[m];
+    } else {
+      const bool up = (e & 2) != 0;
+#pragma unroll
+      for (int m = 0; m < N / 4; ++m) {
+        const T keep = up ? h[2 * m + 1] : h[2 * m];
+        const T send = up ? h[2 * m] : h[2 * m + 1];
+        r[m] = keep + quad_xor2(send);  // the quad's sum of a[4 m + e]
+        if (m + 1 < N / 4) asm volatile("" : "+v"(h[2 * m + 2]), "+v"(h[2 * m + 3]) : "v"(r[m]));
+      }
+    }
+  }
+}
+
+// Group sums of three 20-coefficient rows a[t][b] (flat, t-major), stored to
+// rows r0 + t of an SoA array buf[row][20][ld], column i.  Lane e of the
+// group stores the coefficients b = e, e + G, ... of each row.
+template <int G>
+__device__ __forceinline__ void store_rows3(double* a, int e, bool valid, double* buf,
+                                            int r0, int64_t ld, int i) {
+  constexpr int PER = NBASIS / G;
+  static_assert(NBASIS % G == 0, "coefficients split evenly over the group");
+  double r[3 * PER];
+  group_reduce_scatter<G, 3 * NBASIS>(a, r, e);
+  if (valid) {
+    double* dst = buf + ((int64_t)r0 * NBASIS + e) * ld + i;
+#pragma unroll
+    for (int m = 0; m < 3 * PER; ++m) dst[(int64_t)((m / PER) * NBASIS + G * (m % PER)) * ld] = r[m];
+  }
+}
+
 // Makes a wavefront's LDS writes visible to its own later LDS reads from any
 // of its lanes (the lanes run in lockstep: the writes only have to complete
 // and stay ordered before the reads).  Wavefronts of the same block are not

@@ -457,17 +457,7 @@ __global__ void __launch_bounds__(THREADS)
       for (int b = 0; b < NBASIS; ++b) m[t][b] = fma(a, p[b], m[t][b]);
     }
   }
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) m[t][b] = group_sum<G>(m[t][b]);
-  if (valid) {
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-      for (int b = 0; b < NBASIS; ++b)
-        if ((t * NBASIS + b) % G == l) mbuf[((int64_t)(r0 + t) * NBASIS + b) * soa_ld(n) + i] = m[t][b];
-  }
+  store_rows3<G>(&m[0][0], l, valid, mbuf, r0, soa_ld(n), i);
 }
 
 // The Newton step G^_t = 2 G~_t - A~^{-1} M_t for rows 1..NG (quad per

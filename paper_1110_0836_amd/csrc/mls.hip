@@ -85,19 +85,13 @@ __global__ void __launch_bounds__(THREADS)
     const double w = weight_of(qd, wkind);
     accumulate_moments(m, T(w), T(dx * inv_lam), T(dy * inv_lam), T(dz * inv_lam));
   }
-  // The lane sums retire one moment at a time: each next moment is tied to
-  // the previous sum, so the exchanged copies of all 84 moments are never
-  // live together (hoisted, they double the register footprint).
-#pragma unroll
-  for (int k = 0; k < NMOM; ++k) {
-    m[k] = group_sum<G>(m[k]);
-    if constexpr (G > 1)
-      if (k + 1 < NMOM) asm volatile("" : "+v"(m[k + 1]) : "v"(m[k]));
-  }
+  // lane l of the group ends with the moments l, l + G, ... and stores them
+  T mine[NMOM / G];
+  group_reduce_scatter<G, NMOM>(m, mine, l);
   if (valid) {
+    double* dst = mom + (int64_t)l * soa_ld(n) + i;
 #pragma unroll
-    for (int k = 0; k < NMOM; ++k)
-      if (k % G == l) mom[(int64_t)k * soa_ld(n) + i] = widen(m[k]);
+    for (int k = 0; k < NMOM / G; ++k) dst[(int64_t)(G * k) * soa_ld(n)] = widen(mine[k]);
   }
 }
 
@@ -258,11 +252,15 @@ __global__ void __launch_bounds__(THREADS)
 // (S = FPL slots) takes the fields FPL h .. FPL h + FPL - 1 for the entries
 // e, e + S, ...: FPL x 20 accumulators per lane.  FPL = 4 forms each entry's
 // monomials twice per particle, FPL = 2 four times with half the registers.
-// The slots' partial sums retire one value at a time (chained, as in
-// k_moments).  The next entry's record is fetched one iteration ahead, its
-// index two ahead.
+// The slots' partial sums meet in a reduce-scatter (each slot ends with the
+// coefficients it stores).  The next entry's record is fetched one iteration
+// ahead, its index two ahead.
+// At least two wavefronts per SIMD: unconstrained, the allocator parks one
+// value live across the loop in an accumulation register, and the 257
+// registers halve the occupancy; held to 256 it keeps that value in 8 bytes
+// of scratch, written once before the loop and read once after it.
 template <int NF, int FPL>
-__global__ void __launch_bounds__(THREADS)
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2)))
     k_fit_b(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
             const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
             double rf_ratio, int wkind, const int32_t* __restrict__ rows,
@@ -328,17 +326,18 @@ __global__ void __launch_bounds__(THREADS)
       for (int b = 0; b < NBASIS; ++b) acc[c][b] = fma(d, p[b], acc[c][b]);
     }
   }
-  double* flat = &acc[0][0];
-#pragma unroll
-  for (int k = 0; k < FPL * NBASIS; ++k) {
-    flat[k] = group_sum<S>(flat[k]);
-    if (k + 1 < FPL * NBASIS) asm volatile("" : "+v"(flat[k + 1]) : "v"(flat[k]));
-  }
+  // slot e ends with the sums of flat index S m + e: field m / (20 / S),
+  // coefficient S (m % (20 / S)) + e
+  constexpr int PER = NBASIS / S;
+  static_assert(NBASIS % S == 0, "coefficients split evenly over the slots");
+  double mine[FPL * PER];
+  group_reduce_scatter<S, FPL * NBASIS>(&acc[0][0], mine, e);
   if (valid) {
+    const int64_t ld = soa_ld(n);
+    double* dst = bout + ((int64_t)FPL * h * NBASIS + e) * ld + i;
 #pragma unroll
-    for (int k = 0; k < FPL * NBASIS; ++k)
-      if (k % S == e && k / NBASIS < nfh)
-        bout[((int64_t)(FPL * h + k / NBASIS) * NBASIS + k % NBASIS) * soa_ld(n) + i] = flat[k];
+    for (int m = 0; m < FPL * PER; ++m)
+      if (m / PER < nfh) dst[(int64_t)((m / PER) * NBASIS + S * (m % PER)) * ld] = mine[m];
   }
 }
 
