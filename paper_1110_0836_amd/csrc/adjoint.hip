@@ -918,6 +918,226 @@ __global__ void __launch_bounds__(64)
   if (comp >= 0) own[(int64_t)comp * n + i] = -tot;
 }
 
+// ---- 4c. pair contributions, pipelined over owners --------------------------
+// A persistent wavefront takes a contiguous range of owners and runs the
+// wavefront-per-owner pair terms over it as a two-stage pipeline.  While
+// owner k is computed from LDS, gfx950's direct-to-LDS loads bring owner
+// k + 1 into the other half of a double buffer (each lane's neighbor
+// position and fields, 16 bytes per lane and instruction, and the owner's
+// record), and the neighbor indices of owner k + 2 load into registers.  The
+// two dependent memory latencies of an owner (its indices, then its
+// neighbors) overlap the previous owner's arithmetic; the one-shot schedule
+// waits them out with three wavefronts per SIMD to cover them.  Entries past
+// a row's 64th are fetched directly (rows that long are rare).
+//
+// The compiler does not track the direct-to-LDS loads: the wavefront drains
+// its vector-memory counter before it reads a stage.
+constexpr int PIPE_SLABS = 6;  // 16-byte pieces per entry: x y, z lambda, fields 0-1 .. 6-7
+
+template <bool STAB, bool TAPE>
+struct PipeShape {
+  using SH = Shape<STAB>;
+  static constexpr int GC = (SH::NR + SH::NFA) * NBASIS;  // the tape's G and C rows
+  static constexpr int UW = SH::NFA * SH::NR;            // compact Ubar
+  static constexpr int RAW = TAPE ? GC + UW : SH::OREC;   // doubles staged per owner
+  static constexpr int RAW_PAD = (RAW + 1) & ~1;
+  static constexpr int OSH = TAPE ? SH::OREC : 1;         // G | K | Ubar, formed from the stage
+};
+
+__device__ __forceinline__ void vmem_drain() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt left alone
+  asm volatile("" ::: "memory");       // no memory access moves above the wait
+}
+
+// The direct-to-LDS loads of one owner into one stage.  len: the row's
+// entries in the stage (at most 64); j: this lane's neighbor.
+template <bool STAB, bool TAPE>
+__device__ __forceinline__ void pipe_issue(int i, int len, int j, int lane,
+                                           const double4* __restrict__ geo,
+                                           const double* __restrict__ fq,
+                                           const double* __restrict__ orec,
+                                           const double* __restrict__ ubuf,
+                                           double (*ent)[64][2], double* raw, double* self) {
+  using PS = PipeShape<STAB, TAPE>;
+  // the owner's own position and fields: lanes 0-1 and 2-5
+  if (lane < 6) {
+    const double* g = lane < 2 ? reinterpret_cast<const double*>(geo + i) + 2 * lane
+                               : fq + 8 * (int64_t)i + 2 * (lane - 2);
+    __builtin_amdgcn_global_load_lds(g, self, 16, 0, 0);
+  }
+  if (lane < len) {
+    const double* g = reinterpret_cast<const double*>(geo + j);
+    const double* f = fq + 8 * (int64_t)j;
+    __builtin_amdgcn_global_load_lds(g, &ent[0][0][0], 16, 0, 0);
+    __builtin_amdgcn_global_load_lds(g + 2, &ent[1][0][0], 16, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) __builtin_amdgcn_global_load_lds(f + 2 * k, &ent[2 + k][0][0], 16, 0, 0);
+  }
+  constexpr int NW = TAPE ? PS::GC : Shape<STAB>::OREC;  // even
+  const double* src = orec + (int64_t)i * (TAPE ? TAPE_AOS : Shape<STAB>::OREC);
+#pragma unroll
+  for (int c = 0; c < (NW + 127) / 128; ++c) {
+    const int e = 128 * c + 2 * lane;
+    if (e < NW) __builtin_amdgcn_global_load_lds(src + e, raw + 128 * c, 16, 0, 0);
+  }
+  if constexpr (TAPE) {  // Ubar [NFA][NR], four bytes per lane (8-byte aligned rows)
+    const uint32_t* u = reinterpret_cast<const uint32_t*>(ubuf + (int64_t)i * PS::UW);
+    uint32_t* ru = reinterpret_cast<uint32_t*>(raw + PS::GC);
+#pragma unroll
+    for (int c = 0; c < (2 * PS::UW + 63) / 64; ++c) {
+      const int e = 64 * c + lane;
+      if (e < 2 * PS::UW) __builtin_amdgcn_global_load_lds(u + e, ru + 64 * c, 4, 0, 0);
+    }
+  }
+}
+
+template <class RT, bool STAB, bool TAPE>
+__global__ void __launch_bounds__(64)
+    k_adj_pairs_p(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                  const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
+                  double rf_ratio, int wkind, const double* __restrict__ fq,
+                  const double* __restrict__ orec, const double* __restrict__ ubuf,
+                  RT* __restrict__ rec, double* __restrict__ own, int slot_order) {
+  using SH = Shape<STAB>;
+  using PS = PipeShape<STAB, TAPE>;
+  constexpr int RC = SH::REC, NR = SH::NR, NFA = SH::NFA;
+  __shared__ __align__(16) double s_ent[2][PIPE_SLABS][64][2];
+  __shared__ __align__(16) double s_raw[2][PS::RAW_PAD];
+  __shared__ double osh[PS::OSH];
+  __shared__ __align__(16) double s_self[2][12];  // the owner's x y z lambda and eight fields
+  const int lane = threadIdx.x;
+  const int w = xcd_block(), nw = (int)gridDim.x;
+  const int i0 = (int)((int64_t)n * w / nw), i1 = (int)((int64_t)n * (w + 1) / nw);
+  if (i0 >= i1) return;
+  // owner i0 into stage 0; the indices of owner i0 + 1
+  int64_t rs = off[i0], re = off[i0 + 1];
+  int jc = i0, tpc = 0;
+  if (rs + lane < re) {
+    jc = idx[rs + lane];
+    if (!slot_order) tpc = t_pos[rs + lane];
+  }
+  pipe_issue<STAB, TAPE>(i0, (int)min<int64_t>(re - rs, 64), jc, lane, geo, fq, orec, ubuf,
+                         s_ent[0], s_raw[0], s_self[0]);
+  int64_t rsn = re, ren = re;
+  int jn = 0, tpn = 0;
+  if (i0 + 1 < i1) {
+    ren = off[i0 + 2];
+    if (rsn + lane < ren) {
+      jn = idx[rsn + lane];
+      if (!slot_order) tpn = t_pos[rsn + lane];
+    }
+  }
+  for (int i = i0; i < i1; ++i) {
+    const int c = (i - i0) & 1;
+    vmem_drain();  // stage c has landed, the indices of owner i + 1 are in
+    if (i + 1 < i1)
+      pipe_issue<STAB, TAPE>(i + 1, (int)min<int64_t>(ren - rsn, 64), jn, lane, geo, fq, orec,
+                             ubuf, s_ent[c ^ 1], s_raw[c ^ 1], s_self[c ^ 1]);
+    int64_t rsnn = ren, rENN = ren;
+    int jnn = 0, tpnn = 0;
+    if (i + 2 < i1) {
+      rENN = off[i + 3];
+      if (rsnn + lane < rENN) {
+        jnn = idx[rsnn + lane];
+        if (!slot_order) tpnn = t_pos[rsnn + lane];
+      }
+    }
+    // ---- owner i from stage c
+    const double* o;
+    if constexpr (TAPE) {  // G | K | Ubar, K_t = sum_f Ubar[f][t] C_f
+      const double* raw = s_raw[c];
+#pragma unroll
+      for (int r = 0; r < (NR * NBASIS + 63) / 64; ++r) {
+        const int e = lane + 64 * r;
+        if (e < NR * NBASIS) {
+          const int t = e / NBASIS, b = e % NBASIS;
+          double k = 0.0;
+#pragma unroll
+          for (int f = 0; f < NFA; ++f)
+            k = fma(raw[PS::GC + f * NR + t], raw[NR * NBASIS + f * NBASIS + b], k);
+          osh[e] = raw[e];
+          osh[SH::KOFF + e] = k;
+        }
+      }
+      for (int e = lane; e < PS::UW; e += 64) osh[SH::UOFF + e] = raw[PS::GC + e];
+      wave_lds_sync();
+      o = osh;
+    } else {
+      o = s_raw[c];
+    }
+    // the owner's own data from the stage too: a global load here would
+    // wait for the next owner's loads as well (the counter drains in order)
+    const double4 gi = make_double4(s_self[c][0], s_self[c][1], s_self[c][2], s_self[c][3]);
+    const double inv_lam = 1.0 / gi.w;
+    const double r = rf_ratio * gi.w;
+    const double inv_r2 = 1.0 / (r * r);
+    const double* fi = &s_self[c][4];
+    double acc[RC];
+#pragma unroll
+    for (int k = 0; k < RC; ++k) acc[k] = 0.0;
+    for (int64_t s = rs + lane; s < re; s += 64) {
+      int j, tp;
+      double4 gj;
+      double fj[8];
+      if (s - lane == rs) {  // the staged first 64 entries
+        j = jc;
+        tp = tpc;
+        const double2 a = *reinterpret_cast<const double2*>(&s_ent[c][0][lane][0]);
+        const double2 b = *reinterpret_cast<const double2*>(&s_ent[c][1][lane][0]);
+        gj = make_double4(a.x, a.y, b.x, b.y);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const double2 t = *reinterpret_cast<const double2*>(&s_ent[c][2 + k][lane][0]);
+          fj[2 * k] = t.x;
+          fj[2 * k + 1] = t.y;
+        }
+      } else {
+        j = idx[s];
+        tp = slot_order ? 0 : t_pos[s];
+        gj = geo[j];
+        load_fields(fq, j, fj);
+      }
+      double v[RC];
+#pragma unroll
+      for (int k = 0; k < RC; ++k) v[k] = 0.0;
+      if (j != i) {
+        const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+        const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+        const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+        const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
+        const double wt = weight_of(qd, wkind);
+        const double dw = weight_dq(qd, wkind);
+        pair_terms<double, STAB>(o, wt, dw, inv_lam, inv_r2, dx, dy, dz, fi, fj, v);
+      }
+      RT* out = rec + (slot_order ? s : (int64_t)tp) * RC;
+      if constexpr (sizeof(RT) == 8) {
+        double2* o2 = reinterpret_cast<double2*>(out);
+#pragma unroll
+        for (int k = 0; k < RC; k += 2) o2[k / 2] = make_double2(v[k], v[k + 1]);
+      } else {
+        float2* o2 = reinterpret_cast<float2*>(out);
+#pragma unroll
+        for (int k = 0; k < RC; k += 2) o2[k / 2] = make_float2((float)v[k], (float)v[k + 1]);
+      }
+#pragma unroll
+      for (int k = 0; k < RC; ++k) acc[k] += v[k];
+    }
+    double tot;
+    int comp;
+    wave_sum_transposed<RC>(acc, tot, comp);
+    if (comp >= 0) own[(int64_t)comp * n + i] = -tot;
+    // rotate the pipeline
+    rs = rsn;
+    re = ren;
+    jc = jn;
+    tpc = tpn;
+    rsn = rsnn;
+    ren = rENN;
+    jn = jnn;
+    tpn = tpnn;
+  }
+}
+
 // Inverse of t_pos: for transposed entry k, the forward entry it came from.
 // nnz_true: offsets[n] (the launch covers a bound of it).
 __global__ void __launch_bounds__(THREADS)
@@ -1024,6 +1244,24 @@ void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const 
     hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, false>), grid, dim3(64), 0, s, a.n,
                        geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec,
                        own, slot_order);
+}
+
+// Persistent pipelined schedule: about 64 owners per wavefront, at most 8192
+// wavefronts (several per slot, so that ranges that finish early are
+// replaced).
+template <bool STAB, class RT>
+void launch_pairs_p(hipStream_t s, const EvalArgs& a, const double4* geo, const double* fq,
+                    const int32_t* t_pos, const double* orec, const double* ubuf, RT* rec,
+                    double* own, int slot_order) {
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(a.n / 64, 8192)));
+  if (ubuf)
+    hipLaunchKernelGGL((k_adj_pairs_p<RT, STAB, true>), grid, dim3(64), 0, s, a.n, geo, a.off,
+                       a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
+                       slot_order);
+  else
+    hipLaunchKernelGGL((k_adj_pairs_p<RT, STAB, false>), grid, dim3(64), 0, s, a.n, geo, a.off,
+                       a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
+                       slot_order);
 }
 
 template <int G>
@@ -1243,8 +1481,22 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;
   float* rec_f = reinterpret_cast<float*>(rec);
-  if (!lane_pairs) {
-    // the stabilised shape runs the wavefront-per-owner schedule only
+  // the pipelined schedule stages 16-byte pieces: the owner records (a
+  // caller's tape) must be 16-byte aligned, else the one-shot schedule runs
+  const bool piped = !lane_pairs && ctx->adj_pairs_mode == 2 &&
+                     (reinterpret_cast<uintptr_t>(pair_src) & 15) == 0;
+  if (piped) {
+    Prof pf(ctx, stab ? "k_adj_pairs_p<stab>" : "k_adj_pairs_p");
+    if (stab) {
+      if (rec32) launch_pairs_p<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
+      else launch_pairs_p<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
+    } else {
+      if (rec32) launch_pairs_p<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
+      else launch_pairs_p<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
+  } else if (!lane_pairs) {
+    // the stabilised shape runs a wavefront-per-owner schedule only
     Prof pf(ctx, stab ? "k_adj_pairs_w<stab>" : "k_adj_pairs_w");
     if (stab) {
       if (rec32) launch_pairs_w<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);

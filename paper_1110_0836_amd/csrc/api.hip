@@ -529,8 +529,8 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
   int* slot = tune_slot(ctx, key);
   if (!slot) return set_error(ctx, PHB_EINVAL, std::string("unknown tuning key ") + key);
   const bool lanes = strncmp(key, "lanes_", 6) == 0;
-  const bool mode = !strcmp(key, "adj_pairs_mode") || !strcmp(key, "record_order") ||
-                    !strcmp(key, "moments_mfma");
+  const bool pairs = !strcmp(key, "adj_pairs_mode");
+  const bool mode = !strcmp(key, "record_order") || !strcmp(key, "moments_mfma");
   const bool cut = !strcmp(key, "mixed_cond_x10");
   const bool refine = !strcmp(key, "mixed_refine");
   const bool cut64 = !strcmp(key, "fp64_cut_x10");
@@ -540,6 +540,7 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
       : cut ? !(value >= -1 && value <= 120)
           : refine ? !(value >= 0 && value <= 2)
           : lanes ? !(value == 1 || value == 2 || value == 4)
+          : pairs ? !(value >= 0 && value <= 2)
                   : (mode ? !(value == 0 || value == 1) : !(value >= 1 && value <= 4)))
     return set_error(ctx, PHB_EINVAL, std::string("bad value for ") + key);
   *slot = value;

@@ -307,7 +307,7 @@ int phb_tune(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
   };
   const std::vector<Knob> knobs = {
       {"lanes_moments", {1, 2, 4}}, {"lanes_apply", {1, 2, 4}},  {"lanes_adj_y", {1, 2, 4}},
-      {"lanes_gather", {1, 2, 4}},  {"adj_pairs_mode", {0, 1}}, {"record_order", {0, 1}},
+      {"lanes_gather", {1, 2, 4}},  {"adj_pairs_mode", {0, 1, 2}}, {"record_order", {0, 1}},
       {"fit_fields", {2, 4}}, {"moments_mfma", {0, 1}}};
   char sig[160];
   snprintf(sig, sizeof sig, "# phurbas-tune n=%lld nnz=%lld precision=%d weight=%d",
