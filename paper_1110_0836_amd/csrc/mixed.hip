@@ -801,8 +801,60 @@ static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const St
   return join_aux(ctx, forked, rc);
 }
 
+// With a tape the reverse mode needs the FP64 moments (see fork_tape_moments),
+// so the forward assembles only those: an FP32 copy, its screen and its
+// refinement would repeat the assembly to reach what the FP64 Cholesky of the
+// tape's moments gives at once.  The operator rows are applied in FP32 as in
+// the untaped form; fits whose equilibrated operator rows exceed the operator
+// screen's bound (10^2.5) are solved again by the FP64 refinement on the data.
+static int mixed_rhs_taped(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb,
+                           const double* q, double* rhs, double* dxdt, int32_t* status,
+                           double* tape) {
+  const int n = a0.n;
+  const bool stab = sb.on();
+  const int ng = stab ? 9 : 3, nf = stab ? 8 : 7;
+  Workspace ws(ctx);
+  plan_op_form(ws, n, ng, nf);
+  int rc;
+  if ((rc = ws.commit())) return rc;
+  OpBufs m = take_op(ws, n, ng);
+  double4* geo = ws.take<double4>(n);
+  double* fq = ws.take<double>((size_t)8 * n);
+  const RefineBufs rb = take_op_refine(ws, m, n, nf);
+  EvalArgs a = a0;
+  a.geo = geo;
+  a.fq = fq;
+  hipStream_t s = ctx->stream;
+  { Prof pf(ctx, "k_pack");
+    if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
+  double* mom = tape + (size_t)TAPE_MOM * soa_ld(n);
+  { Prof pf(ctx, "k_moments<tape>");
+    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, mom), "tape moments")))
+      return rc; }
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
+  { Prof pf(ctx, stab ? "k_factor<9>" : "k_factor<3>");
+    if ((rc = hip_check(ctx,
+                        launch_factor(s, a, ng, mom, m.gt, status, ng, screen_cut(ctx, 25),
+                                      m.list, m.count),
+                        "mixed factor")))
+      return rc; }
+  { Prof pf(ctx, stab ? "k_apply_rhs<fp32, stab>" : "k_apply_rhs<fp32>");
+    if ((rc = hip_check(ctx,
+                        launch_apply_rhs(s, a, ctx->lanes_apply, gamma, sb, m.gt, status, rhs,
+                                         dxdt, tape),
+                        "mixed apply")))
+      return rc; }
+  if ((rc = refine_fits(ctx, a, fq, stab ? 0 : 1, nf, mom, rb))) return rc;
+  Prof pf(ctx, "k_rows_rhs_finish<list>");
+  return hip_check(ctx,
+                   launch_rows_rhs_finish(s, a, stab, rb.cbuf, NBASIS, 1, rb.ldc, rb.list,
+                                          rb.count, status, gamma, sb, rhs, dxdt, tape),
+                   "mixed rhs (listed)");
+}
+
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, const double* q,
               double* rhs, double* dxdt, int32_t* status, double* tape) {
+  if (tape) return mixed_rhs_taped(ctx, a0, gamma, sb, q, rhs, dxdt, status, tape);
   // by shape (2): the operator-level step for the three gradient rows; with
   // the stabilisers' nine rows it needs three residual-product passes, and
   // the data-level step's two passes over the eight fields cost less
