@@ -89,10 +89,9 @@ def time_gpu(fn, reps, torch):
 FORWARD_KERNELS = {
     "fp64": ("k_pack", "k_moments", "k_fit_b<7>", "k_factor_fit<3>", "k_rows_rhs_finish",
              "k_ref_fit", "k_ref_tape", "k_ref_rows", "k_rows_rhs_finish<list>"),
-    "mixed": ("k_pack", "k_moments<fp32>", "k_mixed_screen", "k_mixed_repair", "k_mixed_gta",
-              "k_mixed_refine", "k_apply_rhs<fp32>", "k_apply_rhs<list>", "k_moments<tape>",
-              "k_ref_fit", "k_rows_rhs_finish<list>"),
 }
+# a mixed call with a tape (the benchmark's) runs the FP64 data form forward
+FORWARD_KERNELS["mixed"] = FORWARD_KERNELS["fp64"]
 
 
 def source_digest():

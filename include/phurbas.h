@@ -63,15 +63,18 @@ extern "C" {
 #define PHB_ENOTIMPL (-6)  /* option not built */
 
 #define PHB_FP64 0        /* all arithmetic in FP64 */
-#define PHB_MIXED 1       /* FP32 assembly and application, FP64 factor and solve,
-                             one refinement step (see mixed_refine: by default
-                             one Newton step on the operator rows with an FP64
-                             residual product); particles whose FP32 moment
-                             matrix is too ill-conditioned for one step are
-                             evaluated in FP64 (see mixed_cond_x10); with a
-                             tape the forward call also assembles the FP64
-                             moments the reverse mode solves with (on a
-                             second stream, joined before it returns) */
+#define PHB_MIXED 1       /* without a tape: FP32 assembly and application,
+                             FP64 factor and solve, one refinement step (see
+                             mixed_refine: by default one Newton step on the
+                             operator rows with an FP64 residual product);
+                             particles whose FP32 moment matrix is too
+                             ill-conditioned for one step are evaluated in
+                             FP64 (see mixed_cond_x10).  With a tape (a call
+                             the reverse mode follows) the forward is the
+                             FP64 form's data form, since the reverse mode
+                             needs the FP64 moments and FP32 arithmetic runs
+                             no faster than FP64 here, and the reverse mode
+                             stores its pair records in FP32 */
 #define PHB_W_POLY3 0     /* w = (1 - d^2/r_f^2)^3 */
 #define PHB_W_UNIT 1      /* w = 1 */
 #define PHB_FIT_FULL20 0  /* all 20 monomials, constant included */
@@ -230,8 +233,7 @@ int64_t phb_tape_bytes(int64_t n);
  * every intermediate buffer lives in a file-scope device array of
  * PHB_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
  * until the process ends.  The call allocates nothing (no device memory, no
- * events, no second stream; with a tape in the mixed form the tape's FP64
- * moments run in order on the context stream).  PHB_ECAPACITY when the set
+ * events, no second stream).  PHB_ECAPACITY when the set
  * needs more scratch than that: about 3.1 KB per particle in the ideal FP64
  * form (n up to about 21,000), 3.6 KB with the stabilisers; the mixed form
  * needs more.  Calls that overlap on one GPU share the array and race
@@ -422,22 +424,21 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * results to rounding) ------------------------------------------------------
  * Keys: "cells_per_rf" (1..4: neighbor-grid cells per minimum r_f),
  * "lanes_moments", "lanes_apply", "lanes_adj_y" (1, 2 or 4 lanes sharing one
- * particle's neighbor loop in the moment, application and reverse-mode
- * assembly kernels; lanes_adj_y also sets the mixed form's residual-product
- * kernel, of the same shape), "lanes_gather" (1, 2 or 4 lanes summing one particle's
+ * particle's neighbor loop in the moment and application kernels and in the
+ * untaped mixed form's residual-product kernel), "lanes_gather" (1, 2 or 4 lanes summing one particle's
  * transposed row in the reverse mode), "adj_pairs_mode" (0: one lane per
  * neighbor entry, 1: one wavefront per owner particle, 2: persistent
  * wavefronts that stage the next owner through direct-to-LDS loads while
  * computing the current one), "record_order" (0:
  * pair records written at their transposed position, 1: written in forward
  * order and gathered through the inverse map), "mixed_cond_x10" (-1..120:
- * in the mixed form a particle whose FP32-assembled moment matrix, scaled to
+ * in the untaped mixed form a particle whose FP32-assembled moment matrix, scaled to
  * unit diagonal, has an estimated ||A^{-1}||_2 above 10^(value / 10) is
  * evaluated in FP64 instead; -1, the default, takes the refinement form's own
  * threshold, 10^2.5 for the operator-level step and 10^2 for the data-level
  * step; this knob moves results within the mixed tolerance, the others only
  * by rounding), "mixed_refine"
- * (mixed form's refinement step; 1: the rows G~ = E A~^{-1} of the inverse of
+ * (the untaped mixed form's refinement step; 1: the rows G~ = E A~^{-1} of the inverse of
  * the FP32-assembled matrix are refined once, G^ = 2 G~ - (G~ A) A~^{-1},
  * with the product G~ A formed in FP64 over the neighbors, and G^ is applied
  * to the fields in FP32 (each operator weight formed in FP64, the sums in
@@ -446,8 +447,8 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * equations); 2, the default: 1 for the three gradient rows (the ideal
  * right-hand side, first derivatives), 0 with nine rows (the stabilisers,
  * second derivatives); the forms agree within the mixed tolerance),
- * "fit_fields" (2 or 4: fields per lane in the FP64 form's fit right-hand
- * sides), "moments_mfma" (0 or 1: the mixed form's FP32 moments on the
+ * "fit_fields" (2 or 4: fields per lane in the data form's fit right-hand
+ * sides), "moments_mfma" (0 or 1: the untaped mixed form's FP32 moments on the
  * matrix cores, 16 x 16 x 4 FP32 products of the weighted monomials),
  * "fp64_cut_x10" (-1..999: in the FP64 form a fit whose equilibrated
  * inverse has an operator row of 2-norm above 10^(value / 10) is refined on

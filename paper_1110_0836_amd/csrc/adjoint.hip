@@ -1,24 +1,25 @@
 // Reverse mode of the MLS / ideal-MHD time derivatives with the neighbor
 // lists held fixed.
 //
-// Forward, per particle i (operator form): A = sum_j w_j p_j p_j^T,
-// G = E A^{-1} (E picks the x, y, z monomials), grad f = (1/lambda) sum_j
-// w_j (G p_j) (f_j - f_i), then the pointwise right-hand side.
+// Forward, per particle i (data form): A = sum_j w_j p_j p_j^T, B_f = sum_j
+// w_j p_j (f_j - f_i), C_f = A^{-1} B_f, the derivatives from C's rows 1..NR,
+// then the pointwise right-hand side.  The tape keeps G (rows 1..NR of
+// A^{-1}) and C per particle.
 //
 // Reverse, per particle i:
 //   1. pointwise adjoint of the right-hand side: qbar_i (direct part) and
-//      Ubar = grad_bar / lambda  (3 x 7, coefficient space);
-//   2. Y = sum_j w_j p_j (Ubar df_j)^T  (20 x 3);
-//   3. factor A again, G as in the forward and K = (A^{-1} Y)^T  (3 x 20);
-//      with C = A^{-1} B the fit coefficients, K = Ubar C^T, so the adjoint
-//      of A is  Abar = -G^T K  and of B is  Bbar = G^T Ubar;
-//   4. for each neighbor: a = G p, h = Ubar df, b = h - K p,
+//      Ubar = grad_bar / lambda  (NR x NFA, coefficient space);
+//   2. K = Ubar C^T  (NR x 20; with C = A^{-1} B this is (A^{-1} Y)^T for
+//      Y = sum_j w_j p_j (Ubar df_j)^T, without forming Y or factoring A
+//      again), so the adjoint of A is  Abar = -G^T K  and of B is
+//      Bbar = G^T Ubar;
+//   3. for each neighbor: a = G p, h = Ubar df, b = h - K p,
 //        wbar  = a . b,
 //        pbar  = w (G^T b - K^T a),  xibar = (dp/dxi)^T pbar,
 //        dfbar = w Ubar^T a,
 //        dbar  = xibar / lambda + wbar (dw/dq) 2 d / r_f^2,
 //      and the pair contributes +dfbar, +dbar to j and -dfbar, -dbar to i;
-//   5. every particle sums the pair records addressed to it (the transposed
+//   4. every particle sums the pair records addressed to it (the transposed
 //      lists), in a fixed order, plus its own terms.  No atomics.
 #include <type_traits>
 
@@ -169,114 +170,8 @@ __device__ __forceinline__ void pointwise_adjoint_stab(int n, int i, const doubl
   }
 }
 
-// ---- 2. Y = sum_j w_j p_j (Ubar df_j)^T, plus Ubar and the direct qbar ------
-template <int G>
-__global__ void __launch_bounds__(THREADS)
-    k_adj_y(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
-            const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
-            double rf_ratio, int wkind, double gamma, const double* __restrict__ q,
-            const double* __restrict__ tape, const double* __restrict__ rhs_bar,
-            const double* __restrict__ dxdt_bar, double* __restrict__ ybuf,
-            double* __restrict__ ubuf, double* __restrict__ qb_direct) {
-  const int tid = xcd_block() * THREADS + threadIdx.x;
-  const int i = tid / G;
-  const int l = tid % G;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
-  const double4 gi = geo[ii];
-  const double inv_lam = 1.0 / gi.w;
-  const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii];
-  // Ubar (21 doubles) waits in LDS during the neighbor loop instead of in
-  // every lane's registers; ush[k][pl] holds entries 2k, 2k+1.
-  constexpr int PPB = THREADS / G;
-  __shared__ double2 ush[11][PPB];
-  const int pl = threadIdx.x / G;
-  // the first neighbor entry is fetched before the pointwise part and the
-  // barrier, whose work then covers its latency
-  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
-  int64_t s = s0 + l;
-  int jc = ii, jn = ii;
-  double4 gn = gi;
-  if (s < s1) {
-    jc = idx[s];
-    gn = geo[jc];
-  }
-  if (s + G < s1) jn = idx[s + G];
-  double qi[8];
-  {
-    double ub[7][3], qb[8];
-    pointwise_adjoint(n, ii, q, tape, rhs_bar, dxdt_bar, gamma, inv_lam, st, qi, ub, qb);
-    // the owner's Ubar and direct qbar go out now
-    if (valid && l == 0) {
-#pragma unroll
-      for (int f = 0; f < 7; ++f)
-#pragma unroll
-        for (int t = 0; t < 3; ++t) ubuf[(int64_t)i * OREC + UOFF + f * 3 + t] = ub[f][t];
-#pragma unroll
-      for (int f = 0; f < 8; ++f) qb_direct[(int64_t)f * n + i] = qb[f];
-    }
-    if (l == 0) {
-#pragma unroll
-      for (int k = 0; k < 11; ++k) {
-        const int e0 = 2 * k, e1 = 2 * k + 1;
-        ush[k][pl] = make_double2(ub[e0 / 3][e0 % 3], e1 < 21 ? ub[e1 / 3][e1 % 3] : 0.0);
-      }
-    }
-  }
-  __syncthreads();
-  const double r = rf_ratio * gi.w;
-  const double inv_r2 = 1.0 / (r * r);
-  double y[3][NBASIS];
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) y[t][b] = 0.0;
-  for (; s < s1; s += G) {
-    const double4 gj = gn;
-    const int j = jc;
-    if (s + G < s1) {
-      gn = geo[jn];
-      jc = jn;
-      if (s + 2 * G < s1) jn = idx[s + 2 * G];
-    }
-    const double2* fj = reinterpret_cast<const double2*>(fq + 8 * (int64_t)j);
-    const double2 f01 = fj[0], f23 = fj[1], f45 = fj[2], f67 = fj[3];
-    const double qj[8] = {f01.x, f01.y, f23.x, f23.y, f45.x, f45.y, f67.x, f67.y};
-    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
-    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
-    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
-    const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
-    double p[NBASIS];
-    basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-    double df[7];
-#pragma unroll
-    for (int f = 0; f < 7; ++f) df[f] = qj[f + 1] - qi[f + 1];
-    double h[3] = {0.0, 0.0, 0.0};
-    asm volatile("" ::: "memory");  // re-read Ubar from LDS (see above)
-#pragma unroll
-    for (int k = 0; k < 11; ++k) {
-      const double2 u = ush[k][pl];
-      const int e0 = 2 * k, e1 = 2 * k + 1;
-      h[e0 % 3] = fma(u.x, df[e0 / 3], h[e0 % 3]);
-      if (e1 < 21) h[e1 % 3] = fma(u.y, df[e1 / 3], h[e1 % 3]);
-    }
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const double wh = w * h[t];
-#pragma unroll
-      for (int b = 0; b < NBASIS; ++b) y[t][b] = fma(wh, p[b], y[t][b]);
-    }
-  }
-  store_rows3<G>(&y[0][0], l, valid, ybuf, 0, soa_ld(n), i);
-}
-
-// Ubar [NFA][NR] and the direct qbar, one thread per particle: Ubar into
-// ubuf[i * ustride + uoff ..] (the owner record, or a compact array).  The
-// stabilised shape of the operator form runs it before k_adj_yrows, which
-// accumulates three rows of Y at a time (60 accumulators per lane, as in the
-// ideal kernel), launched for rows 0..2, 3..5 and 6..8; the data form runs it
-// in both shapes.
-using S9 = Shape<true>;
+// ---- 1. Ubar [NFA][NR] and the direct qbar, one thread per particle ---------
+// Ubar into ubuf[i * ustride + uoff ..] (a compact array).
 
 template <bool STAB>
 __global__ void __launch_bounds__(THREADS)
@@ -334,147 +229,7 @@ __global__ void __launch_bounds__(THREADS)
     for (int e = 0; e < NFA * NR; ++e) o[SH::UOFF + e] = u[e];
 }
 
-template <int G>
-__global__ void __launch_bounds__(THREADS)
-    k_adj_yrows(int n, const double4* __restrict__ geo, const double* __restrict__ fq,
-                const int64_t* __restrict__ off, const int32_t* __restrict__ idx, Box box,
-                double rf_ratio, int wkind, const double* __restrict__ tape,
-                const double* __restrict__ orec, int r0, double* __restrict__ ybuf) {
-  const int tid = xcd_block() * THREADS + threadIdx.x;
-  const int i = tid / G;
-  const int l = tid % G;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
-  const double4 gi = geo[ii];
-  const double inv_lam = 1.0 / gi.w;
-  const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii];
-  // Ubar rows r0..r0+2 of the eight fields (24 values) in LDS
-  constexpr int PPB = THREADS / G;
-  __shared__ double2 ush[12][PPB];
-  const int pl = threadIdx.x / G;
-  // first neighbor entry ahead of the staging and the barrier
-  const int64_t s0 = off[ii], s1 = (valid && st == 0) ? off[ii + 1] : s0;
-  int64_t s = s0 + l;
-  int jc = ii, jn = ii;
-  double4 gn = gi;
-  if (s < s1) {
-    jc = idx[s];
-    gn = geo[jc];
-  }
-  if (s + G < s1) jn = idx[s + G];
-  for (int k = l; k < 12; k += G) {
-    const int e0 = 2 * k, e1 = 2 * k + 1;
-    const double* u = orec + (int64_t)ii * S9::OREC + S9::UOFF;
-    ush[k][pl] = make_double2(u[(e0 / 3) * 9 + r0 + e0 % 3], u[(e1 / 3) * 9 + r0 + e1 % 3]);
-  }
-  __syncthreads();
-  double qi[8];
-  load_fields(fq, ii, qi);
-  const double r = rf_ratio * gi.w;
-  const double inv_r2 = 1.0 / (r * r);
-  double y[3][NBASIS];
-#pragma unroll
-  for (int t = 0; t < 3; ++t)
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) y[t][b] = 0.0;
-  for (; s < s1; s += G) {
-    const double4 gj = gn;
-    const int j = jc;
-    if (s + G < s1) {
-      gn = geo[jn];
-      jc = jn;
-      if (s + 2 * G < s1) jn = idx[s + 2 * G];
-    }
-    double qj[8];
-    load_fields(fq, j, qj);
-    const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
-    const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
-    const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
-    const double w = weight_of((dx * dx + dy * dy + dz * dz) * inv_r2, wkind);
-    double p[NBASIS];
-    basis(p, dx * inv_lam, dy * inv_lam, dz * inv_lam);
-    double h[3] = {0.0, 0.0, 0.0};
-    asm volatile("" ::: "memory");  // re-read Ubar from LDS every iteration
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const double2 u = ush[k][pl];
-      const int e0 = 2 * k, e1 = 2 * k + 1;
-      h[e0 % 3] = fma(u.x, qj[e0 / 3] - qi[e0 / 3], h[e0 % 3]);
-      h[e1 % 3] = fma(u.y, qj[e1 / 3] - qi[e1 / 3], h[e1 % 3]);
-    }
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const double wh = w * h[t];
-#pragma unroll
-      for (int b = 0; b < NBASIS; ++b) y[t][b] = fma(wh, p[b], y[t][b]);
-    }
-  }
-  store_rows3<G>(&y[0][0], l, valid, ybuf, r0, soa_ld(n), i);
-}
-
-// ---- 3. factor again: G = rows 1..3 of A^{-1}, K_t = A^{-1} Y_t ------------
-__constant__ EntryTab c_tab_a = make_entry_tab();
-
-// Screen (list != null): owners with status 0 whose equilibrated inverse has
-// an operator row of 2-norm above rcut are appended to list (count cleared
-// by the caller); their G and K are refined afterwards.
-template <bool STAB>
-__global__ void __launch_bounds__(THREADS)
-    k_adj_factor(int n, const double* __restrict__ mom, const double* __restrict__ ybuf,
-                 const double* __restrict__ tape, double* __restrict__ gop, int interp,
-                 double rcut, int32_t* __restrict__ list, int32_t* __restrict__ count) {
-  using SH = Shape<STAB>;
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
-  const int i = tid >> 2;
-  const int l = tid & 3;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
-  QuadChol c;
-  quad_chol_factor(c, c_tab_a, mom, soa_ld(n), ii, l, interp != 0);
-  const int st = (int)tape[(int64_t)TAPE_STATUS * soa_ld(n) + ii];
-  double rmax2 = 0.0;
-  // G rows at 0 and K rows at KOFF of the owner record, in lockstep groups of
-  // three solves
-  sfor<0, SH::NR / 3>([&](auto GI) {
-    constexpr int g0 = 3 * GI;
-    double out[3][5];
-    quad_chol_inverse_rows<1 + g0, 3>(c, l, out);
-    if (list) rmax2 = fmax(rmax2, quad_rows_hat_norm2<1 + g0, 3>(c, l, out));
-    if (valid) {
-#pragma unroll
-      for (int rh = 0; rh < 3; ++rh)
-#pragma unroll
-        for (int rho = 0; rho < 5; ++rho)
-          gop[(int64_t)i * SH::OREC + (g0 + rh) * NBASIS + 4 * rho + l] =
-              st == 0 ? out[rh][rho] : 0.0;
-    }
-  });
-  sfor<0, SH::NR / 3>([&](auto GI) {
-    constexpr int g0 = 3 * GI;
-    double y[3][5], out[3][5];
-#pragma unroll
-    for (int rh = 0; rh < 3; ++rh)
-#pragma unroll
-      for (int rho = 0; rho < 5; ++rho)
-        y[rh][rho] = ybuf[((int64_t)(g0 + rh) * NBASIS + 4 * rho + l) * soa_ld(n) + ii] * c.s_own[rho];
-    // interpolating fit: Y's constant entry belongs to no basis function
-    if (interp && l == 0)
-#pragma unroll
-      for (int rh = 0; rh < 3; ++rh) y[rh][0] = 0.0;
-    quad_chol_solve_n<0, 3>(c, l, y, out);
-    if (valid) {
-#pragma unroll
-      for (int rh = 0; rh < 3; ++rh)
-#pragma unroll
-        for (int rho = 0; rho < 5; ++rho)
-          gop[(int64_t)i * SH::OREC + SH::KOFF + (g0 + rh) * NBASIS + 4 * rho + l] =
-              st == 0 ? out[rh][rho] * c.s_own[rho] : 0.0;
-    }
-  });
-  if (list && valid && l == 0 && st == 0 && !(rmax2 <= rcut * rcut)) list[atomicAdd(count, 1)] = i;
-}
-
-// ---- 4. pair contributions ---------------------------------------------------
+// ---- 3. pair contributions ---------------------------------------------------
 // Reverse-mode contributions of one neighbor entry (i, j), j != i, given the
 // owner record o (G rows 0..59, K rows 60..119, Ubar at UOFF):
 //   a = G p, b = Ubar df - K p, dfbar_f = w Ubar_f . a, wbar = a . b,
@@ -770,7 +525,7 @@ __global__ void __launch_bounds__(THREADS)
   for (int c = 0; c < REC; ++c) own[(int64_t)c * n + i] = -acc[c];
 }
 
-// ---- 4b. pair contributions, one wavefront per owner ------------------------
+// ---- 3b. pair contributions, one wavefront per owner ------------------------
 // The owner's G, K and Ubar are wavefront-uniform and staged in LDS; lanes
 // take the owner's neighbor entries 64 at a time (rows longer than 64
 // entries loop); the owner's own share is one transposed wavefront sum of the
@@ -918,7 +673,7 @@ __global__ void __launch_bounds__(64)
   if (comp >= 0) own[(int64_t)comp * n + i] = -tot;
 }
 
-// ---- 4c. pair contributions, pipelined over owners --------------------------
+// ---- 3c. pair contributions, pipelined over owners --------------------------
 // A persistent wavefront takes a contiguous range of owners and runs the
 // wavefront-per-owner pair terms over it as a two-stage pipeline.  While
 // owner k is computed from LDS, gfx950's direct-to-LDS loads bring owner
@@ -1147,7 +902,7 @@ __global__ void __launch_bounds__(THREADS)
   if (s < nnz && s < *nnz_true) t_slot[t_pos[s]] = (int32_t)s;
 }
 
-// ---- 5. gather over the transposed lists ------------------------------------
+// ---- 4. gather over the transposed lists ------------------------------------
 // G lanes share one particle's transposed row; their partial sums meet in a
 // quad reduction.  The summation order is fixed for a given G.
 template <int G, class RT, bool STAB = false>
@@ -1200,16 +955,6 @@ __global__ void __launch_bounds__(THREADS)
   for (int a = 0; a < 3; ++a) pos_bar[(int64_t)a * n + j] = acc[SH::NFA + a];
 }
 
-template <int G>
-hipError_t launch_adj_y_g(hipStream_t s, const EvalArgs& a, double gamma, const double* q,
-                          const double* tape, const double* rhs_bar, const double* dxdt_bar,
-                          double* ybuf, double* ubuf, double* qbd) {
-  hipLaunchKernelGGL((k_adj_y<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS), 0, s,
-                     a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio, a.wkind, gamma, q, tape,
-                     rhs_bar, dxdt_bar, ybuf, ubuf, qbd);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 namespace {
@@ -1236,14 +981,9 @@ void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const 
                     const int32_t* t_pos, const double* orec, const double* ubuf, RT* rec,
                     double* own, int slot_order) {
   const dim3 grid(grid_for(a.n, 1));  // one wavefront per owner, one per block
-  if (ubuf)
-    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, true>), grid, dim3(64), 0, s, a.n,
-                       geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec,
-                       own, slot_order);
-  else
-    hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, false>), grid, dim3(64), 0, s, a.n,
-                       geo, a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec,
-                       own, slot_order);
+  hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, true>), grid, dim3(64), 0, s, a.n, geo,
+                     a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
+                     slot_order);
 }
 
 // Persistent pipelined schedule: about 64 owners per wavefront, at most 8192
@@ -1254,34 +994,17 @@ void launch_pairs_p(hipStream_t s, const EvalArgs& a, const double4* geo, const 
                     const int32_t* t_pos, const double* orec, const double* ubuf, RT* rec,
                     double* own, int slot_order) {
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(a.n / 64, 8192)));
-  if (ubuf)
-    hipLaunchKernelGGL((k_adj_pairs_p<RT, STAB, true>), grid, dim3(64), 0, s, a.n, geo, a.off,
-                       a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
-                       slot_order);
-  else
-    hipLaunchKernelGGL((k_adj_pairs_p<RT, STAB, false>), grid, dim3(64), 0, s, a.n, geo, a.off,
-                       a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
-                       slot_order);
-}
-
-template <int G>
-void launch_yrows(hipStream_t s, const EvalArgs& a, const double* tape, const double* orec,
-                  double* ybuf) {
-  for (int r0 = 0; r0 < 9; r0 += 3)
-    hipLaunchKernelGGL((k_adj_yrows<G>), dim3(grid_for((int64_t)a.n * G, THREADS)), dim3(THREADS),
-                       0, s, a.n, a.geo, a.fq, a.off, a.idx, a.box, a.rf_ratio, a.wkind, tape,
-                       orec, r0, ybuf);
+  hipLaunchKernelGGL((k_adj_pairs_p<RT, STAB, true>), grid, dim3(64), 0, s, a.n, geo, a.off,
+                     a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
+                     slot_order);
 }
 
 }  // namespace
 
-// Two forms of the owner data.  Data form (the FP64 form, and any call
-// without a tape, whose private forward runs in FP64): the tape holds every
-// owner's G and fit coefficients C, refined for the screened fits, so the
-// reverse pass needs Ubar alone before the pairs (K = Ubar C^T is formed in
-// the pair kernel).  Operator form (the mixed form with the caller's tape,
-// which holds no G or C): Y, a second factorization for G and K = (A^{-1}
-// Y)^T, and the screened owners' refinement.
+// The owner data: every tape holds each owner's G and fit coefficients C,
+// refined for the screened fits (the FP64 form's, and the mixed form's, whose
+// taped forward is the FP64 data form), so the reverse pass needs Ubar alone
+// before the pairs (K = Ubar C^T is formed in the pair kernel).
 // Workspace of the reverse pass (see adjoint_rhs for the pieces).
 static void plan_adjoint(Workspace& ws, int64_t n, int64_t nnz, const phb_params* p,
                          bool need_tape, bool lane_pairs) {
@@ -1290,9 +1013,7 @@ static void plan_adjoint(Workspace& ws, int64_t n, int64_t nnz, const phb_params
   const int NFAr = stab ? Shape<true>::NFA : Shape<false>::NFA;
   const int ORr = stab ? Shape<true>::OREC : Shape<false>::OREC;
   const int RCr = stab ? Shape<true>::REC : Shape<false>::REC;
-  const bool data_form = need_tape || p->precision == PHB_FP64;
   const size_t nd = (size_t)n * sizeof(double);
-  const size_t ndl = (size_t)soa_ld(n) * sizeof(double);  // the padded stride's rows
   const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
   ws.plan((size_t)n * sizeof(double4));  // packed geometry
   ws.plan(8 * nd);                       // packed fields
@@ -1301,16 +1022,8 @@ static void plan_adjoint(Workspace& ws, int64_t n, int64_t nnz, const phb_params
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * RCr * sizeof(double));  // pair records
   ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
-  if (data_form) {
-    ws.plan((size_t)NFAr * NRr * nd);               // Ubar
-    if (lane_pairs) ws.plan((size_t)ORr * nd);      // owner records
-  } else {
-    ws.plan((size_t)NRr * NBASIS * ndl);  // Y
-    ws.plan((size_t)ORr * nd);            // owner records: G, K, Ubar
-    // screened owners; the residual sums also hold the operator rows'
-    // residual products, NRr x 20 of them
-    plan_refine(ws, n, std::max(NFAr, NRr));
-  }
+  ws.plan((size_t)NFAr * NRr * nd);               // Ubar
+  if (lane_pairs) ws.plan((size_t)ORr * nd);      // owner records
   if (need_tape) {
     ws.plan((size_t)tape_doubles(n) * sizeof(double));  // private tape
     ws.plan(8 * nd);                                     // rhs scratch
@@ -1363,7 +1076,6 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   if (nnz > PHB_NNZ_MAX)
     return set_error(ctx, PHB_EINVAL, "nnz exceeds the int32 positions of the transposed lists");
   const bool need_tape = tape_in == nullptr;
-  const bool data_form = need_tape || p->precision == PHB_FP64;
   // the lane-per-entry schedule (ideal shape) reads whole owner records and
   // needs the exact entry count
   const bool lane_pairs = !stab && ctx->adj_pairs_mode == 0 && nnz_exact;
@@ -1374,10 +1086,6 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   const int64_t nwaves = (std::max<int64_t>(nnz, 1) + 63) / 64;
   const size_t own_bytes = ws.total;
   if (need_tape) ws.plan(ws_bytes_rhs(n, &p64));  // the nested forward
-  // Every tape holds FP64 moments: the mixed forward assembles them for the
-  // tape beside its own FP32 ones, since the reverse mode solves with
-  // right-hand sides built from the incoming gradients, which carry no
-  // smooth-data structure to refine FP32 assembly error away.
   if ((rc = ws.commit())) return rc;
   double4* geo = ws.take<double4>(n);
   double* fq = ws.take<double>((size_t)8 * n);
@@ -1386,16 +1094,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   double* rec = ws.take<double>((size_t)std::max<int64_t>(nnz, 1) * RCr);
   double* wpart = ws.take<double>((size_t)nwaves * 2 * REC);
   int32_t* t_slot = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
-  double *ubuf = nullptr, *ybuf = nullptr, *orec = nullptr;
-  RefineBufs rb{};
-  if (data_form) {
-    ubuf = ws.take<double>((size_t)NFAr * NRr * n);
-    if (lane_pairs) orec = ws.take<double>((size_t)ORr * n);
-  } else {
-    ybuf = ws.take<double>((size_t)NRr * NBASIS * soa_ld(n));
-    orec = ws.take<double>((size_t)ORr * n);
-    rb = take_refine(ws, n, std::max(NFAr, NRr));
-  }
+  double* ubuf = ws.take<double>((size_t)NFAr * NRr * n);
+  double* orec = lane_pairs ? ws.take<double>((size_t)ORr * n) : nullptr;
   const int slot_order = ctx->record_order;
   const double* tape = tape_in;
   hipStream_t s = ctx->stream;
@@ -1413,71 +1113,24 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   ap.fq = fq;
   { Prof pf(ctx, "k_pack");
   if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
-  const double* mom = tape + (size_t)TAPE_MOM * soa_ld(n);
-  const int interp = a.fit == PHB_FIT_INTERP19;
   const double* pair_src = orec;  // what the pair kernel stages per owner
-  if (data_form) {
-    { Prof pf(ctx, stab ? "k_adj_u<stab>" : "k_adj_u");
-    if (stab)
-      hipLaunchKernelGGL(k_adj_u<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
-                         p->gamma, sb, q, tape, rhs_bar, dxdt_bar, ubuf, NFAr * NRr, 0, qbd);
-    else
-      hipLaunchKernelGGL(k_adj_u<false>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
-                         p->gamma, sb, q, tape, rhs_bar, dxdt_bar, ubuf, NFAr * NRr, 0, qbd);
-    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Ubar"))) return rc; }
-    if (lane_pairs) {
-      Prof pf(ctx, "k_adj_orec");
-      hipLaunchKernelGGL(k_adj_orec<false>, dim3(grid_for((int64_t)n * NRr, THREADS)),
-                         dim3(THREADS), 0, s, n, tape_aos(tape, n), ubuf, orec);
-      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint owner records"))) return rc;
-    } else {
-      pair_src = tape_aos(tape, n);
-    }
+  { Prof pf(ctx, stab ? "k_adj_u<stab>" : "k_adj_u");
+  if (stab)
+    hipLaunchKernelGGL(k_adj_u<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
+                       p->gamma, sb, q, tape, rhs_bar, dxdt_bar, ubuf, NFAr * NRr, 0, qbd);
+  else
+    hipLaunchKernelGGL(k_adj_u<false>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
+                       p->gamma, sb, q, tape, rhs_bar, dxdt_bar, ubuf, NFAr * NRr, 0, qbd);
+  if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Ubar"))) return rc; }
+  if (lane_pairs) {
+    Prof pf(ctx, "k_adj_orec");
+    hipLaunchKernelGGL(k_adj_orec<false>, dim3(grid_for((int64_t)n * NRr, THREADS)),
+                       dim3(THREADS), 0, s, n, tape_aos(tape, n), ubuf, orec);
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint owner records"))) return rc;
   } else {
-    if ((rc = hip_check(ctx, fill_i32(s, rb.count, 0, 1), "clear list"))) return rc;
-    // the operator form runs for the mixed form's tapes only
-    const double rcut = fp64_screen_cut(ctx, NRr, p->precision != PHB_MIXED);
-    if (stab) {
-      { Prof pf(ctx, "k_adj_u<stab>");
-      hipLaunchKernelGGL(k_adj_u<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
-                         p->gamma, sb, q, tape, rhs_bar, dxdt_bar, orec, S9::OREC, S9::UOFF, qbd);
-      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Ubar"))) return rc; }
-      { Prof pf(ctx, "k_adj_yrows");
-      switch (ctx->lanes_adj_y) {
-        case 1: launch_yrows<1>(s, ap, tape, orec, ybuf); break;
-        case 2: launch_yrows<2>(s, ap, tape, orec, ybuf); break;
-        default: launch_yrows<4>(s, ap, tape, orec, ybuf); break;
-      }
-      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint Y"))) return rc; }
-      { Prof pf(ctx, "k_adj_factor<stab>");
-      hipLaunchKernelGGL(k_adj_factor<true>, dim3(grid_for((int64_t)n * 4, THREADS)), dim3(THREADS),
-                         0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list, rb.count);
-      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
-    } else {
-      { Prof pf(ctx, "k_adj_y");
-      switch (ctx->lanes_adj_y) {
-        case 1: rc = hip_check(ctx, launch_adj_y_g<1>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
-        case 2: rc = hip_check(ctx, launch_adj_y_g<2>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
-        default: rc = hip_check(ctx, launch_adj_y_g<4>(s, ap, p->gamma, q, tape, rhs_bar, dxdt_bar, ybuf, orec, qbd), "adjoint Y"); break;
-      }
-      if (rc) return rc; }
-      { Prof pf(ctx, "k_adj_factor");
-      hipLaunchKernelGGL(k_adj_factor<false>, dim3(grid_for((int64_t)n * 4, THREADS)),
-                         dim3(THREADS), 0, s, n, mom, ybuf, tape, orec, interp, rcut, rb.list,
-                         rb.count);
-      if ((rc = hip_check(ctx, hipGetLastError(), "adjoint factor"))) return rc; }
-    }
-    // the screened owners' G and K, refined on the data
-    if (stab) {
-      if ((rc = refine_adjoint(ctx, ap, true, mom, rb, orec, Shape<true>::OREC,
-                               Shape<true>::KOFF, Shape<true>::UOFF)))
-        return rc;
-    } else if ((rc = refine_adjoint(ctx, ap, false, mom, rb, orec, Shape<false>::OREC,
-                                    Shape<false>::KOFF, Shape<false>::UOFF))) {
-      return rc;
-    }
+    pair_src = tape_aos(tape, n);
   }
-  const double* pair_ubuf = (data_form && !lane_pairs) ? ubuf : nullptr;
+  const double* pair_ubuf = lane_pairs ? nullptr : ubuf;
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;
   float* rec_f = reinterpret_cast<float*>(rec);

@@ -21,8 +21,9 @@ int eval_args(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
               const double* lambda, const int64_t* offsets, const int32_t* idx, EvalArgs* a);
 
 size_t mixed_rhs_bytes(int64_t n, bool stab);
+// The mixed form without a tape (a taped mixed call runs the FP64 data form).
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a, double gamma, const Stab& sb, const double* q,
-              double* rhs, double* dxdt, int32_t* status, double* tape);
+              double* rhs, double* dxdt, int32_t* status);
 
 int mixed_derivs(phb_ctx* ctx, const EvalArgs& a, int nf, const double* fields, double* d1,
                  double* d2, int32_t* status);

@@ -63,14 +63,6 @@ Box make_box(const phb_params* p) {
   return b;
 }
 
-int ensure_aux(phb_ctx* ctx) {
-  if (ctx->aux) return PHB_OK;
-  hipError_t e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming);
-  return hip_check(ctx, e, "second stream");
-}
-
 int ensure_host(phb_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->host_cap) return PHB_OK;
   if (ctx->host) hipHostFree(ctx->host);
@@ -228,8 +220,11 @@ size_t ws_bytes_rhs(int64_t n, const phb_params* p) {
 
 // n rows of n_all particles
 static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, bool stab) {
-  if (precision == PHB_MIXED) {
-    ws.plan(mixed_rhs_bytes(n, stab));
+  if (precision == PHB_MIXED) {  // untaped: the mixed module; taped: the data form
+    phb_ctx dummy;
+    Workspace wd(&dummy);
+    plan_rhs(wd, n, n_all, PHB_FP64, stab);
+    ws.plan(std::max(mixed_rhs_bytes(n, stab), wd.total));
     return;
   }
   ws.plan((size_t)NMOM * soa_ld(n) * sizeof(double));
@@ -249,9 +244,14 @@ static void plan_rhs(Workspace& ws, int64_t n, int64_t n_all, int precision, boo
 int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double* q, double* rhs,
              double* dxdt, int32_t* status, double* tape) {
   const Stab sb = stab_of(p);
+  // The mixed form: without a tape, FP32 assembly and its refinement (mixed
+  // module).  With one, the reverse mode needs FP64 moments anyway and FP32
+  // arithmetic runs no faster than FP64 here (no packed FP32), so the forward
+  // is this FP64 data form; the mixed form's FP32 is then in the reverse
+  // mode's pair records, half the bytes of its dominant traffic.
   if (p->precision == PHB_MIXED) {
     if (a0.rows) return set_error(ctx, PHB_ENOTIMPL, "row subsets in the mixed form");
-    return mixed_rhs(ctx, a0, p->gamma, sb, q, rhs, dxdt, status, tape);
+    if (!tape) return mixed_rhs(ctx, a0, p->gamma, sb, q, rhs, dxdt, status);
   }
   EvalArgs a = a0;
   const int n = a.n;                        // rows
@@ -423,12 +423,6 @@ int phb_destroy(phb_ctx* ctx) {
   if (!ctx) return PHB_EINVAL;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
-  if (ctx->aux) {
-    hipStreamSynchronize(ctx->aux);
-    hipStreamDestroy(ctx->aux);
-  }
-  if (ctx->ev_fork) hipEventDestroy(ctx->ev_fork);
-  if (ctx->ev_join) hipEventDestroy(ctx->ev_join);
   if (ctx->arena) hipFree(ctx->arena);
   if (ctx->host) hipHostFree(ctx->host);
   delete ctx;

@@ -15,10 +15,6 @@
 struct phb_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  // Second stream for independent passes (default priority), created on
-  // first use, and the events that fork work to it and join it back.
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // Workspace arena (device memory owned by the library).
   char* arena = nullptr;
   size_t arena_cap = 0;
@@ -61,8 +57,6 @@ int set_error(phb_ctx* ctx, int code, const std::string& msg);
 int check_params(phb_ctx* ctx, const phb_params* p);
 // Grows the context's pinned host staging buffer (ctx->host) to bytes.
 int ensure_host(phb_ctx* ctx, size_t bytes);
-// Creates ctx->aux and its fork/join events if needed.
-int ensure_aux(phb_ctx* ctx);
 int check_n(phb_ctx* ctx, int64_t n);
 // The stabiliser coefficients of p (all zero: ideal MHD).
 Stab stab_of(const phb_params* p);

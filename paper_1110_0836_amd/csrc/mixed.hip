@@ -690,37 +690,6 @@ int mixed_operator(phb_ctx* ctx, const EvalArgs& a, const OpBufs& m, int32_t* st
   return hip_check(ctx, hipGetLastError(), "mixed refinement");
 }
 
-// With a tape, the reverse mode needs FP64 moments (its right-hand sides,
-// built from incoming gradients, would see the FP32 assembly error
-// unrefined).  They depend on the packed geometry only: the pass runs on the
-// second stream beside the forward's own chain and is joined before the
-// forward returns (in order while per-kernel profiling is on).
-int fork_tape_moments(phb_ctx* ctx, const EvalArgs& a, double* tape, bool& forked) {
-  forked = false;
-  if (!tape) return PHB_OK;
-  double* dst = tape + (size_t)TAPE_MOM * soa_ld(a.n);
-  if (ctx->prof_on || ctx->no_alloc) {  // in order (an allocation-free call creates no stream)
-    Prof pf(ctx, "k_moments<tape>");
-    return hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, dst),
-                     "tape moments");
-  }
-  int rc;
-  if ((rc = ensure_aux(ctx))) return rc;
-  hipError_t e = hipEventRecord(ctx->ev_fork, ctx->stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
-  if (e == hipSuccess) e = launch_moments(ctx->aux, a, ctx->lanes_assemble, dst);
-  if (e == hipSuccess) e = hipEventRecord(ctx->ev_join, ctx->aux);
-  if ((rc = hip_check(ctx, e, "tape moments"))) return rc;
-  forked = true;
-  return PHB_OK;
-}
-
-int join_aux(phb_ctx* ctx, bool forked, int rc) {
-  if (!forked) return rc;
-  const int rj = hip_check(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_join, 0), "join");
-  return rc ? rc : rj;
-}
-
 }  // namespace
 
 // Workspace of the operator-level form: its buffers, the packed records and
@@ -759,8 +728,7 @@ size_t mixed_rhs_bytes(int64_t n, bool stab) {
 
 // Operator-level form of mixed_rhs: the refined rows applied in FP32.
 static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb,
-                        const double* q, double* rhs, double* dxdt, int32_t* status,
-                        double* tape) {
+                        const double* q, double* rhs, double* dxdt, int32_t* status) {
   const int n = a0.n;
   const bool stab = sb.on();
   const int ng = stab ? 9 : 3, nf = stab ? 8 : 7;
@@ -778,88 +746,33 @@ static int mixed_rhs_op(phb_ctx* ctx, const EvalArgs& a0, double gamma, const St
   { Prof pf(ctx, "k_pack");
     if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
       return rc; }
-  bool forked = false;
-  if ((rc = fork_tape_moments(ctx, a, tape, forked))) return rc;
   rc = stab ? mixed_operator<9>(ctx, a, m, status) : mixed_operator<3>(ctx, a, m, status);
-  if (rc) return join_aux(ctx, forked, rc);
+  if (rc) return rc;
   { Prof pf(ctx, stab ? "k_apply_rhs<fp32, stab>" : "k_apply_rhs<fp32>");
     if ((rc = hip_check(ctx,
                         launch_apply_rhs(ctx->stream, a, ctx->lanes_apply, gamma, sb, m.gt,
-                                         status, rhs, dxdt, tape),
+                                         status, rhs, dxdt, nullptr),
                         "mixed apply")))
-      return join_aux(ctx, forked, rc); }
+      return rc; }
   // the listed (ill-conditioned) particles again, by the FP64 refinement on
   // the data: applied in FP32 their operator would lose kappa eps_32, in
   // FP64 kappa eps_64
-  if ((rc = refine_fits(ctx, a, fq, stab ? 0 : 1, nf, m.mom, rb)))
-    return join_aux(ctx, forked, rc);
-  { Prof pf(ctx, "k_rows_rhs_finish<list>");
-    rc = hip_check(ctx,
-                   launch_rows_rhs_finish(ctx->stream, a, stab, rb.cbuf, NBASIS, 1, rb.ldc,
-                                          rb.list, rb.count, status, gamma, sb, rhs, dxdt, tape),
-                   "mixed rhs (listed)"); }
-  return join_aux(ctx, forked, rc);
-}
-
-// With a tape the reverse mode needs the FP64 moments (see fork_tape_moments),
-// so the forward assembles only those: an FP32 copy, its screen and its
-// refinement would repeat the assembly to reach what the FP64 Cholesky of the
-// tape's moments gives at once.  The operator rows are applied in FP32 as in
-// the untaped form; fits whose equilibrated operator rows exceed the operator
-// screen's bound (10^2.5) are solved again by the FP64 refinement on the data.
-static int mixed_rhs_taped(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb,
-                           const double* q, double* rhs, double* dxdt, int32_t* status,
-                           double* tape) {
-  const int n = a0.n;
-  const bool stab = sb.on();
-  const int ng = stab ? 9 : 3, nf = stab ? 8 : 7;
-  Workspace ws(ctx);
-  plan_op_form(ws, n, ng, nf);
-  int rc;
-  if ((rc = ws.commit())) return rc;
-  OpBufs m = take_op(ws, n, ng);
-  double4* geo = ws.take<double4>(n);
-  double* fq = ws.take<double>((size_t)8 * n);
-  const RefineBufs rb = take_op_refine(ws, m, n, nf);
-  EvalArgs a = a0;
-  a.geo = geo;
-  a.fq = fq;
-  hipStream_t s = ctx->stream;
-  { Prof pf(ctx, "k_pack");
-    if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
-  double* mom = tape + (size_t)TAPE_MOM * soa_ld(n);
-  { Prof pf(ctx, "k_moments<tape>");
-    if ((rc = hip_check(ctx, launch_moments(s, a, ctx->lanes_assemble, mom), "tape moments")))
-      return rc; }
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, m.count, 1);
-  { Prof pf(ctx, stab ? "k_factor<9>" : "k_factor<3>");
-    if ((rc = hip_check(ctx,
-                        launch_factor(s, a, ng, mom, m.gt, status, ng, screen_cut(ctx, 25),
-                                      m.list, m.count),
-                        "mixed factor")))
-      return rc; }
-  { Prof pf(ctx, stab ? "k_apply_rhs<fp32, stab>" : "k_apply_rhs<fp32>");
-    if ((rc = hip_check(ctx,
-                        launch_apply_rhs(s, a, ctx->lanes_apply, gamma, sb, m.gt, status, rhs,
-                                         dxdt, tape),
-                        "mixed apply")))
-      return rc; }
-  if ((rc = refine_fits(ctx, a, fq, stab ? 0 : 1, nf, mom, rb))) return rc;
+  if ((rc = refine_fits(ctx, a, fq, stab ? 0 : 1, nf, m.mom, rb))) return rc;
   Prof pf(ctx, "k_rows_rhs_finish<list>");
   return hip_check(ctx,
-                   launch_rows_rhs_finish(s, a, stab, rb.cbuf, NBASIS, 1, rb.ldc, rb.list,
-                                          rb.count, status, gamma, sb, rhs, dxdt, tape),
+                   launch_rows_rhs_finish(ctx->stream, a, stab, rb.cbuf, NBASIS, 1, rb.ldc,
+                                          rb.list, rb.count, status, gamma, sb, rhs, dxdt,
+                                          nullptr),
                    "mixed rhs (listed)");
 }
 
 int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, const double* q,
-              double* rhs, double* dxdt, int32_t* status, double* tape) {
-  if (tape) return mixed_rhs_taped(ctx, a0, gamma, sb, q, rhs, dxdt, status, tape);
+              double* rhs, double* dxdt, int32_t* status) {
   // by shape (2): the operator-level step for the three gradient rows; with
   // the stabilisers' nine rows it needs three residual-product passes, and
   // the data-level step's two passes over the eight fields cost less
   const int form = ctx->mixed_refine == 2 ? (sb.on() ? 0 : 1) : ctx->mixed_refine;
-  if (form == 1) return mixed_rhs_op(ctx, a0, gamma, sb, q, rhs, dxdt, status, tape);
+  if (form == 1) return mixed_rhs_op(ctx, a0, gamma, sb, q, rhs, dxdt, status);
   const int n = a0.n;
   const bool stab = sb.on();
   // ideal: V, B, sigma (records 1..7), three rows; stabilised: all eight
@@ -880,27 +793,24 @@ int mixed_rhs(phb_ctx* ctx, const EvalArgs& a0, double gamma, const Stab& sb, co
   { Prof pf(ctx, "k_pack");
     if ((rc = hip_check(ctx, launch_pack(ctx->stream, n, a.pos, a.lam, q, geo, fq), "pack")))
       return rc; }
-  bool forked = false;
-  if ((rc = fork_tape_moments(ctx, a, tape, forked))) return rc;
   // V, B and sigma are entries 1..7 of the packed records (all eight with the
   // stabilisers)
   rc = stab ? mixed_fit<9>(ctx, a, fq, 0, 8, m, status) : mixed_fit<3>(ctx, a, fq, 1, 7, m, status);
-  if (rc) return join_aux(ctx, forked, rc);
+  if (rc) return rc;
   const RefineBufs rb = listed_refine(m, n);
   { Prof pf(ctx, stab ? "k_rows_rhs_finish<stab>" : "k_rows_rhs_finish");
     if ((rc = hip_check(ctx,
                         launch_rows_rhs_finish(ctx->stream, a, stab, m.rows, ng, 0, soa_ld(n),
                                                nullptr, nullptr, status, gamma, sb, rhs, dxdt,
-                                               tape),
+                                               nullptr),
                         "mixed rhs")))
-      return join_aux(ctx, forked, rc); }
+      return rc; }
   Prof pf(ctx, "k_rows_rhs_finish<list>");
-  return join_aux(ctx, forked,
-                  hip_check(ctx,
-                            launch_rows_rhs_finish(ctx->stream, a, stab, rb.cbuf, NBASIS, 1,
-                                                   rb.ldc, rb.list, rb.count, status, gamma, sb,
-                                                   rhs, dxdt, tape),
-                            "mixed rhs (listed)"));
+  return hip_check(ctx,
+                   launch_rows_rhs_finish(ctx->stream, a, stab, rb.cbuf, NBASIS, 1, rb.ldc,
+                                          rb.list, rb.count, status, gamma, sb, rhs, dxdt,
+                                          nullptr),
+                   "mixed rhs (listed)");
 }
 
 size_t mixed_derivs_bytes(int64_t n, bool second) {

@@ -223,34 +223,6 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
-// ---- reverse mode --------------------------------------------------------
-// K_t = sum_f Ubar[f][t] c_f (coefficient space) of the listed owners, into
-// their owner records (K rows at koff, Ubar [nfa][nr] at uoff); one thread
-// per owner and row.
-__global__ void __launch_bounds__(THREADS)
-    k_ref_adj_k(const int32_t* __restrict__ list, const int32_t* __restrict__ count, int nr,
-                int nfa, int orec_len, int koff, int uoff, const double* __restrict__ cbuf,
-                int64_t ldc, double* __restrict__ orec) {
-  const int64_t tid = (int64_t)blockIdx.x * THREADS + threadIdx.x;
-  const int k = (int)(tid / nr);
-  const int t = (int)(tid % nr);
-  if (k >= *count) return;
-  const int i = list[k];
-  double* o = orec + (int64_t)i * orec_len;
-  {
-    double kt[NBASIS];
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) kt[b] = 0.0;
-    for (int f = 0; f < nfa; ++f) {
-      const double u = o[uoff + f * nr + t];
-#pragma unroll
-      for (int b = 0; b < NBASIS; ++b) kt[b] = fma(u, cbuf[((int64_t)f * NBASIS + b) * ldc + k], kt[b]);
-    }
-#pragma unroll
-    for (int b = 0; b < NBASIS; ++b) o[koff + t * NBASIS + b] = kt[b];
-  }
-}
-
 // The residual product of the operator rows, M_t = sum_j w_j (G_t . p_j) p_j^T,
 // formed from the data in FP64 for three rows r0 .. r0 + 2 of the listed
 // owners (G read from the owner records at offset 0).  Eight lanes per owner
@@ -636,27 +608,6 @@ int refine_oprows(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom,
                        orec_len, a.fit == PHB_FIT_INTERP19, first, r.prev, r.done);
   }
   return hip_check(ctx, hipGetLastError(), "operator-row refinement");
-}
-
-int refine_adjoint(phb_ctx* ctx, const EvalArgs& a, bool stab, const double* mom,
-                   const RefineBufs& r, double* orec, int orec_len, int koff, int uoff) {
-  hipStream_t s = ctx->stream;
-  const int n = a.n;
-  const int nr = stab ? 9 : 3;
-  const int nfa = stab ? 8 : 7;
-  int rc;
-  // refined coefficients of the fields the owner's rows are applied to
-  if ((rc = refine_fits(ctx, a, a.fq, stab ? 0 : 1, nfa, mom, r))) return rc;
-  {
-    Prof pf(ctx, "k_ref_adjoint");
-    hipLaunchKernelGGL(k_ref_adj_k, dim3(grid_for((int64_t)n * nr, THREADS)), dim3(THREADS), 0, s,
-                       r.list, r.count, nr, nfa, orec_len, koff, uoff, r.cbuf, r.ldc, orec);
-    if ((rc = hip_check(ctx, hipGetLastError(), "reverse-mode refinement"))) return rc;
-  }
-  // the residual sums, last corrections and flags are free again:
-  // refinement steps on the operator rows (r.dbuf holds at least nr x 20
-  // rows)
-  return refine_oprows(ctx, a, nr, mom, r, orec, orec_len);
 }
 
 hipError_t launch_rows_rhs_finish(hipStream_t s, const EvalArgs& a, bool stab, const double* coef,

@@ -54,13 +54,6 @@ int refine_oprows(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom,
 int refine_tape(phb_ctx* ctx, const EvalArgs& a, int nr, const double* mom, const RefineBufs& r,
                 double* aos);
 
-// Reverse mode of the listed owners: refined coefficients, K = Ubar C^T and
-// refinement steps on the operator rows G, written into their owner records
-// (G at 0, K at koff, Ubar read at uoff).  a.geo and a.fq must be packed; r
-// must hold max(fields, rows) = 7 (ideal) or 9 (stabilised) fields.
-int refine_adjoint(phb_ctx* ctx, const EvalArgs& a, bool stab, const double* mom,
-                   const RefineBufs& r, double* orec, int orec_len, int koff, int uoff);
-
 // Coefficient (field f, monomial 1 + t) of the particle in column col at
 // coef[(f * fstride + t0 + t) * cld + col].  list == null: every particle, column
 // = particle; else the listed ones, column = list position.

@@ -15,12 +15,6 @@ k_apply_rhs      per pair: geometry and weight (15), basis (16), three
                  operator rows G p (60 FMA), w (3), field differences (7),
                  gradient accumulation (21 FMA)                          = 203
                  per particle: gradient scaling (21) + right-hand side (45) = 66
-k_adj_y          per pair: geometry (15), basis (16), h = Ubar df (7 sub,
-                 21 FMA), w h (3), Y update (60 FMA)                      = 203
-                 per particle: pointwise adjoint                          = 150
-k_adj_factor     per particle: equilibration + Cholesky (3330), three
-                 unit-vector and three general solves (2234 + 2460),
-                 scaling (240)                                            = 8264
 k_adj_pairs      per pair: geometry and dw/dq (18), basis (16),
                  G p and K p (120 FMA), h (7 sub, 21 FMA), dfbar (42),
                  wbar (5), pbar = w (G^T b - K^T a) (120 FMA, 20 mul),
@@ -38,13 +32,12 @@ k_factor_fit<3>  per particle: equilibration + Cholesky (3330), three
 k_rows_rhs_finish per particle: gradient scaling (21) + right-hand side   = 66
 k_adj_u          per particle: pointwise adjoint                          = 150
 k_adj_pairs_w    as k_adj_pairs; the owner's K = Ubar C^T (840 per
-                 particle) is left out of the count.
+k_adj_pairs_p    particle) is left out of the count.
 
-Mixed form (FP32 arithmetic after the FP64 displacement, FP64 factor and
-solves; counted the same way, whatever the precision):
+Mixed form without a tape (FP32 arithmetic after the FP64 displacement,
+FP64 factor and solves; counted the same way, whatever the precision; a
+mixed call with a tape runs the FP64 data form above):
 k_moments<fp32>  as k_moments                                            = 187
-k_moments<tape>  the FP64 moments a forward call with a tape assembles for the
-                 reverse mode, as k_moments                               = 187
 k_mixed_b        per pair: geometry and weight (15), basis (16), per field
                  w df (2) and 20 FMA (40), seven fields                   = 325
 k_mixed_factor   per particle: equilibration + Cholesky (3330), seven
@@ -72,16 +65,15 @@ k_apply_rhs<fp32> as k_apply_rhs (FP64 operator weights, FP32 sums)       = 203
 PER_PAIR = {
     "k_moments": 187,
     "k_moments<fp32>": 187,
-    "k_moments<tape>": 187,
     "k_mixed_b": 325,
     "k_fit_b<7>": 325,
     "k_mixed_resid": 612,
     "k_apply_rhs": 203,
     "k_apply_rhs<fp32>": 203,
     "k_mixed_gta": 274,
-    "k_adj_y": 203,
     "k_adj_pairs": 683,
     "k_adj_pairs_w": 683,
+    "k_adj_pairs_p": 683,
 }
 PER_PARTICLE = {
     "k_factor<3>": 5704,
@@ -95,8 +87,6 @@ PER_PARTICLE = {
     "k_apply_rhs<fp32>": 66,
     "k_mixed_screen": 7404,
     "k_mixed_refine": 6030,
-    "k_adj_y": 150,
-    "k_adj_factor": 8264,
 }
 BYTES_PER_PAIR = {"k_adj_gather": 80}
 BYTES_PER_PARTICLE = {"k_adj_gather": 232}

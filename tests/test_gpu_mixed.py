@@ -225,18 +225,31 @@ def test_refinement_knobs():
 
 
 @pytest.mark.parametrize("stab", [{}, dict(visc_grid=0.3, visc_adapt=0.3, divb_diff=0.3)])
-def test_tape_holds_fp64_moments(stab):
-    """A mixed forward call with a tape assembles the reverse mode's FP64
-    moments into it (on the second stream): the same moments, bit for bit, as
-    the FP64 form's tape; the tape's other entries are the mixed form's."""
+def test_taped_mixed_forward_is_the_fp64_data_form(stab):
+    """With a tape the reverse mode needs FP64 moments anyway, and the mixed
+    form's forward is the FP64 data form: its outputs and its whole tape equal
+    the FP64 form's bit for bit.  Without a tape it keeps its FP32 assembly
+    (within the mixed tolerance of the FP64 form, and not equal to it)."""
     c = synth.cp_alfven(12)
     pos, lam, q = dev(c["pos"]), dev(c["lam"]), dev(c["q"])
     s64 = setup_of(c, **stab)
     smx = setup_of(c, precision=P.PHB_MIXED, **stab)
     off, idx = P.neighbors(pos, lam, s64)
     n = c["lam"].shape[0]
-    t64 = P.tape_rows(P.mhd_rhs(pos, lam, off, idx, q, s64, tape=True)[3], n).cpu().numpy()
-    tmx = P.tape_rows(P.mhd_rhs(pos, lam, off, idx, q, smx, tape=True)[3], n).cpu().numpy()
-    assert np.array_equal(tmx[-84:], t64[-84:])
-    assert np.array_equal(tmx[21], t64[21])  # status
-    assert 0 < np.abs(tmx[:21] - t64[:21]).max() < 1e-5 * np.abs(t64[:21]).max()
+    o64 = P.mhd_rhs(pos, lam, off, idx, q, s64, tape=True)
+    omx = P.mhd_rhs(pos, lam, off, idx, q, smx, tape=True)
+    r64 = [t.cpu().numpy() for t in o64[:3]]
+    for a, b in zip([t.cpu().numpy() for t in omx[:3]], r64):
+        assert np.array_equal(a, b, equal_nan=True)
+    # the tape's derivative rows and status, its moments, and the used part
+    # of each particle's (G, C) block
+    t64, tmx = P.tape_rows(o64[3], n).cpu().numpy(), P.tape_rows(omx[3], n).cpu().numpy()
+    assert np.array_equal(tmx[:22], t64[:22]) and np.array_equal(tmx[-84:], t64[-84:])
+    used = 340 if stab else 200
+    a64 = o64[3][-340 * n:].view(n, 340)[:, :used].cpu().numpy()
+    amx = omx[3][-340 * n:].view(n, 340)[:, :used].cpu().numpy()
+    assert np.array_equal(amx, a64)
+    untaped = P.mhd_rhs(pos, lam, off, idx, q, smx)[0].cpu().numpy()
+    ok = r64[2] == 0
+    d = np.abs(untaped[:, ok] - r64[0][:, ok]).max()
+    assert 0 < d < 1e-5 * np.abs(r64[0][:, ok]).max()
