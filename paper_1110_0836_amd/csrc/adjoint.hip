@@ -242,22 +242,6 @@ __global__ void __launch_bounds__(THREADS)
 // 141 doubles do not fit the scalar registers).
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-template <class CT>
-__device__ __forceinline__ void row_value_grad(const CT* __restrict__ c, const CT (&p)[NBASIS],
-                                               CT& v, CT (&g)[3]) {
-  v = CT(0);
-#pragma unroll
-  for (int b = 0; b < NBASIS; ++b) v = fma(c[b], p[b], v);
-  const CT two = CT(2), three = CT(3);
-  g[0] = c[1] + two * p[1] * c[4] + p[2] * c[5] + p[3] * c[6] + three * p[4] * c[10] +
-         two * p[5] * c[11] + two * p[6] * c[12] + p[7] * c[13] + p[8] * c[14] + p[9] * c[15];
-  g[1] = c[2] + p[1] * c[5] + two * p[2] * c[7] + p[3] * c[8] + p[4] * c[11] +
-         two * p[5] * c[13] + p[6] * c[14] + three * p[7] * c[16] + two * p[8] * c[17] +
-         p[9] * c[18];
-  g[2] = c[3] + p[1] * c[6] + p[2] * c[8] + two * p[3] * c[9] + p[4] * c[12] + p[5] * c[14] +
-         two * p[6] * c[15] + p[7] * c[17] + two * p[8] * c[18] + three * p[9] * c[19];
-}
-
 // Value and gradient of one row's cubic c . p(xi) at xi = (x, y, z), nested
 // over the quadratic monomials so that the 20 monomials are never held:
 // value c0 + c1 x + c2 y + c3 z + xx (c4 + c10 x + c11 y + c12 z)
@@ -540,26 +524,25 @@ __global__ void __launch_bounds__(THREADS)
 // the cancelling sums of the records over a particle's owners lose up to
 // 1e-3 of the gradient on the 1M shear layer (sharp layers, 4x lambda range).
 //
-// TAPE (the data form): orec is the tape's AoS block (G, then the fit
-// coefficients C) and ubuf the compact Ubar [n][NFA][NR]; the wavefront
-// stages G and Ubar and forms K = Ubar C^T from the record as it stages it
-// (one entry of K per lane and pass, all in the one staging phase).
-template <class RT, class CT = double, bool STAB = false, bool TAPE = false>
+// aos is the tape's AoS block (G, then the fit coefficients C) and ubuf the
+// compact Ubar [n][NFA][NR]; the wavefront stages G and Ubar and forms
+// K = Ubar C^T as it stages them (one entry of K per lane and pass, all in
+// the one staging phase).
+template <class RT, class CT = double, bool STAB = false>
 __global__ void __launch_bounds__(64)
     k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                   const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
                   double rf_ratio, int wkind, const double* __restrict__ fq,
-                  const double* __restrict__ orec, const double* __restrict__ ubuf,
+                  const double* __restrict__ aos, const double* __restrict__ ubuf,
                   RT* __restrict__ rec, double* __restrict__ own, int slot_order) {
   using SH = Shape<STAB>;
   constexpr int OR = SH::OREC, RC = SH::REC;
   constexpr int NR = SH::NR, NFA = SH::NFA;
   const int i = __builtin_amdgcn_readfirstlane(xcd_block());
   const int lane = threadIdx.x & 63;
-  // the owner record goes to LDS in one coalesced load per wavefront; the
-  // pair terms then read it row by row at LDS latency
-  __shared__ CT osh[1][OR];
-  const int wv = 0;
+  // the owner record (G | K | Ubar) goes to LDS once per wavefront; the pair
+  // terms then read it row by row at LDS latency
+  __shared__ CT osh[OR];
   // Each lane's first entry (index, neighbor geometry, transposed position)
   // is fetched before the record is staged, so that this dependent chain of
   // loads overlaps the staging; later entries are fetched one iteration
@@ -576,10 +559,10 @@ __global__ void __launch_bounds__(64)
       gjn = geo[jn];
       if (!slot_order) tpn = t_pos[rs + lane];
     }
-    if constexpr (TAPE) {
+    {
       // every load of the staging is issued before the first LDS store, so
       // the record costs one memory latency
-      const double* g = orec + (int64_t)i * TAPE_AOS;
+      const double* g = aos + (int64_t)i * TAPE_AOS;
       const double* u = ubuf + (int64_t)i * NFA * NR;
       constexpr int NK = (NR * NBASIS + 63) / 64, NU = (NFA * NR + 63) / 64;
       double gv[NK], kv[NK], uv[NU];
@@ -609,17 +592,15 @@ __global__ void __launch_bounds__(64)
       for (int r = 0; r < NK; ++r) {
         const int e = lane + 64 * r;
         if (e < NR * NBASIS) {
-          osh[wv][e] = CT(gv[r]);
-          osh[wv][SH::KOFF + e] = CT(kv[r]);
+          osh[e] = CT(gv[r]);
+          osh[SH::KOFF + e] = CT(kv[r]);
         }
       }
 #pragma unroll
       for (int r = 0; r < NU; ++r) {
         const int e = lane + 64 * r;
-        if (e < NFA * NR) osh[wv][SH::UOFF + e] = CT(uv[r]);
+        if (e < NFA * NR) osh[SH::UOFF + e] = CT(uv[r]);
       }
-    } else {
-      for (int k = lane; k < OR; k += 64) osh[wv][k] = CT(orec[(int64_t)i * OR + k]);
     }
   }
   if (i >= n) return;  // whole wavefronts leave together
@@ -628,7 +609,7 @@ __global__ void __launch_bounds__(64)
   const double inv_lam = 1.0 / gi.w;
   const double r = rf_ratio * gi.w;
   const double inv_r2 = 1.0 / (r * r);
-  const CT* o = osh[wv];
+  const CT* o = osh;
   const double* fi = fq + 8 * (int64_t)i;
   double acc[RC];
 #pragma unroll
@@ -689,14 +670,13 @@ __global__ void __launch_bounds__(64)
 // its vector-memory counter before it reads a stage.
 constexpr int PIPE_SLABS = 6;  // 16-byte pieces per entry: x y, z lambda, fields 0-1 .. 6-7
 
-template <bool STAB, bool TAPE>
+template <bool STAB>
 struct PipeShape {
   using SH = Shape<STAB>;
   static constexpr int GC = (SH::NR + SH::NFA) * NBASIS;  // the tape's G and C rows
   static constexpr int UW = SH::NFA * SH::NR;            // compact Ubar
-  static constexpr int RAW = TAPE ? GC + UW : SH::OREC;   // doubles staged per owner
+  static constexpr int RAW = GC + UW;                     // doubles staged per owner
   static constexpr int RAW_PAD = (RAW + 1) & ~1;
-  static constexpr int OSH = TAPE ? SH::OREC : 1;         // G | K | Ubar, formed from the stage
 };
 
 __device__ __forceinline__ void vmem_drain() {
@@ -706,14 +686,14 @@ __device__ __forceinline__ void vmem_drain() {
 
 // The direct-to-LDS loads of one owner into one stage.  len: the row's
 // entries in the stage (at most 64); j: this lane's neighbor.
-template <bool STAB, bool TAPE>
+template <bool STAB>
 __device__ __forceinline__ void pipe_issue(int i, int len, int j, int lane,
                                            const double4* __restrict__ geo,
                                            const double* __restrict__ fq,
-                                           const double* __restrict__ orec,
+                                           const double* __restrict__ aos,
                                            const double* __restrict__ ubuf,
                                            double (*ent)[64][2], double* raw, double* self) {
-  using PS = PipeShape<STAB, TAPE>;
+  using PS = PipeShape<STAB>;
   // the owner's own position and fields: lanes 0-1 and 2-5
   if (lane < 6) {
     const double* g = lane < 2 ? reinterpret_cast<const double*>(geo + i) + 2 * lane
@@ -728,37 +708,36 @@ __device__ __forceinline__ void pipe_issue(int i, int len, int j, int lane,
 #pragma unroll
     for (int k = 0; k < 4; ++k) __builtin_amdgcn_global_load_lds(f + 2 * k, &ent[2 + k][0][0], 16, 0, 0);
   }
-  constexpr int NW = TAPE ? PS::GC : Shape<STAB>::OREC;  // even
-  const double* src = orec + (int64_t)i * (TAPE ? TAPE_AOS : Shape<STAB>::OREC);
+  constexpr int NW = PS::GC;  // even
+  const double* src = aos + (int64_t)i * TAPE_AOS;
 #pragma unroll
   for (int c = 0; c < (NW + 127) / 128; ++c) {
     const int e = 128 * c + 2 * lane;
     if (e < NW) __builtin_amdgcn_global_load_lds(src + e, raw + 128 * c, 16, 0, 0);
   }
-  if constexpr (TAPE) {  // Ubar [NFA][NR], four bytes per lane (8-byte aligned rows)
-    const uint32_t* u = reinterpret_cast<const uint32_t*>(ubuf + (int64_t)i * PS::UW);
-    uint32_t* ru = reinterpret_cast<uint32_t*>(raw + PS::GC);
+  // Ubar [NFA][NR], four bytes per lane (its rows are 8-byte aligned)
+  const uint32_t* u = reinterpret_cast<const uint32_t*>(ubuf + (int64_t)i * PS::UW);
+  uint32_t* ru = reinterpret_cast<uint32_t*>(raw + PS::GC);
 #pragma unroll
-    for (int c = 0; c < (2 * PS::UW + 63) / 64; ++c) {
-      const int e = 64 * c + lane;
-      if (e < 2 * PS::UW) __builtin_amdgcn_global_load_lds(u + e, ru + 64 * c, 4, 0, 0);
-    }
+  for (int c = 0; c < (2 * PS::UW + 63) / 64; ++c) {
+    const int e = 64 * c + lane;
+    if (e < 2 * PS::UW) __builtin_amdgcn_global_load_lds(u + e, ru + 64 * c, 4, 0, 0);
   }
 }
 
-template <class RT, bool STAB, bool TAPE>
+template <class RT, bool STAB>
 __global__ void __launch_bounds__(64)
     k_adj_pairs_p(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
                   const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
                   double rf_ratio, int wkind, const double* __restrict__ fq,
-                  const double* __restrict__ orec, const double* __restrict__ ubuf,
+                  const double* __restrict__ aos, const double* __restrict__ ubuf,
                   RT* __restrict__ rec, double* __restrict__ own, int slot_order) {
   using SH = Shape<STAB>;
-  using PS = PipeShape<STAB, TAPE>;
+  using PS = PipeShape<STAB>;
   constexpr int RC = SH::REC, NR = SH::NR, NFA = SH::NFA;
   __shared__ __align__(16) double s_ent[2][PIPE_SLABS][64][2];
   __shared__ __align__(16) double s_raw[2][PS::RAW_PAD];
-  __shared__ double osh[PS::OSH];
+  __shared__ double osh[SH::OREC];  // G | K | Ubar, formed from the stage
   __shared__ __align__(16) double s_self[2][12];  // the owner's x y z lambda and eight fields
   const int lane = threadIdx.x;
   const int w = xcd_block(), nw = (int)gridDim.x;
@@ -771,8 +750,8 @@ __global__ void __launch_bounds__(64)
     jc = idx[rs + lane];
     if (!slot_order) tpc = t_pos[rs + lane];
   }
-  pipe_issue<STAB, TAPE>(i0, (int)min<int64_t>(re - rs, 64), jc, lane, geo, fq, orec, ubuf,
-                         s_ent[0], s_raw[0], s_self[0]);
+  pipe_issue<STAB>(i0, (int)min<int64_t>(re - rs, 64), jc, lane, geo, fq, aos, ubuf, s_ent[0],
+                   s_raw[0], s_self[0]);
   int64_t rsn = re, ren = re;
   int jn = 0, tpn = 0;
   if (i0 + 1 < i1) {
@@ -786,8 +765,8 @@ __global__ void __launch_bounds__(64)
     const int c = (i - i0) & 1;
     vmem_drain();  // stage c has landed, the indices of owner i + 1 are in
     if (i + 1 < i1)
-      pipe_issue<STAB, TAPE>(i + 1, (int)min<int64_t>(ren - rsn, 64), jn, lane, geo, fq, orec,
-                             ubuf, s_ent[c ^ 1], s_raw[c ^ 1], s_self[c ^ 1]);
+      pipe_issue<STAB>(i + 1, (int)min<int64_t>(ren - rsn, 64), jn, lane, geo, fq, aos, ubuf,
+                       s_ent[c ^ 1], s_raw[c ^ 1], s_self[c ^ 1]);
     int64_t rsnn = ren, rENN = ren;
     int jnn = 0, tpnn = 0;
     if (i + 2 < i1) {
@@ -797,9 +776,8 @@ __global__ void __launch_bounds__(64)
         if (!slot_order) tpnn = t_pos[rsnn + lane];
       }
     }
-    // ---- owner i from stage c
-    const double* o;
-    if constexpr (TAPE) {  // G | K | Ubar, K_t = sum_f Ubar[f][t] C_f
+    // ---- owner i from stage c: G | K | Ubar, K_t = sum_f Ubar[f][t] C_f
+    {
       const double* raw = s_raw[c];
 #pragma unroll
       for (int r = 0; r < (NR * NBASIS + 63) / 64; ++r) {
@@ -816,10 +794,8 @@ __global__ void __launch_bounds__(64)
       }
       for (int e = lane; e < PS::UW; e += 64) osh[SH::UOFF + e] = raw[PS::GC + e];
       wave_lds_sync();
-      o = osh;
-    } else {
-      o = s_raw[c];
     }
+    const double* o = osh;
     // the owner's own data from the stage too: a global load here would
     // wait for the next owner's loads as well (the counter drains in order)
     const double4 gi = make_double4(s_self[c][0], s_self[c][1], s_self[c][2], s_self[c][3]);
@@ -978,11 +954,11 @@ void launch_gather(hipStream_t s, int gl, int n, const int64_t* t_off, const int
 
 template <bool STAB, class RT>
 void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const double* fq,
-                    const int32_t* t_pos, const double* orec, const double* ubuf, RT* rec,
+                    const int32_t* t_pos, const double* aos, const double* ubuf, RT* rec,
                     double* own, int slot_order) {
   const dim3 grid(grid_for(a.n, 1));  // one wavefront per owner, one per block
-  hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB, true>), grid, dim3(64), 0, s, a.n, geo,
-                     a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
+  hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB>), grid, dim3(64), 0, s, a.n, geo, a.off,
+                     a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, aos, ubuf, rec, own,
                      slot_order);
 }
 
@@ -991,12 +967,11 @@ void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const 
 // replaced).
 template <bool STAB, class RT>
 void launch_pairs_p(hipStream_t s, const EvalArgs& a, const double4* geo, const double* fq,
-                    const int32_t* t_pos, const double* orec, const double* ubuf, RT* rec,
+                    const int32_t* t_pos, const double* aos, const double* ubuf, RT* rec,
                     double* own, int slot_order) {
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(a.n / 64, 8192)));
-  hipLaunchKernelGGL((k_adj_pairs_p<RT, STAB, true>), grid, dim3(64), 0, s, a.n, geo, a.off,
-                     a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, orec, ubuf, rec, own,
-                     slot_order);
+  hipLaunchKernelGGL((k_adj_pairs_p<RT, STAB>), grid, dim3(64), 0, s, a.n, geo, a.off, a.idx,
+                     t_pos, a.box, a.rf_ratio, a.wkind, fq, aos, ubuf, rec, own, slot_order);
 }
 
 }  // namespace
@@ -1113,7 +1088,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   ap.fq = fq;
   { Prof pf(ctx, "k_pack");
   if ((rc = hip_check(ctx, launch_pack(s, n, a.pos, a.lam, q, geo, fq), "pack"))) return rc; }
-  const double* pair_src = orec;  // what the pair kernel stages per owner
+  const double* aos = tape_aos(tape, n);  // each owner's G and C
   { Prof pf(ctx, stab ? "k_adj_u<stab>" : "k_adj_u");
   if (stab)
     hipLaunchKernelGGL(k_adj_u<true>, dim3(grid_for(n, THREADS)), dim3(THREADS), 0, s, n, geo,
@@ -1125,38 +1100,35 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   if (lane_pairs) {
     Prof pf(ctx, "k_adj_orec");
     hipLaunchKernelGGL(k_adj_orec<false>, dim3(grid_for((int64_t)n * NRr, THREADS)),
-                       dim3(THREADS), 0, s, n, tape_aos(tape, n), ubuf, orec);
+                       dim3(THREADS), 0, s, n, aos, ubuf, orec);
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint owner records"))) return rc;
-  } else {
-    pair_src = tape_aos(tape, n);
   }
-  const double* pair_ubuf = lane_pairs ? nullptr : ubuf;
   // FP32 pair records in the mixed form
   const bool rec32 = p->precision == PHB_MIXED;
   float* rec_f = reinterpret_cast<float*>(rec);
-  // the pipelined schedule stages 16-byte pieces: the owner records (a
+  // the pipelined schedule stages 16-byte pieces: the tape's blocks (a
   // caller's tape) must be 16-byte aligned, else the one-shot schedule runs
   const bool piped = !lane_pairs && ctx->adj_pairs_mode == 2 &&
-                     (reinterpret_cast<uintptr_t>(pair_src) & 15) == 0;
+                     (reinterpret_cast<uintptr_t>(aos) & 15) == 0;
   if (piped) {
     Prof pf(ctx, stab ? "k_adj_pairs_p<stab>" : "k_adj_pairs_p");
     if (stab) {
-      if (rec32) launch_pairs_p<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
-      else launch_pairs_p<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
+      if (rec32) launch_pairs_p<true>(s, a, geo, fq, t_pos, aos, ubuf, rec_f, own, slot_order);
+      else launch_pairs_p<true>(s, a, geo, fq, t_pos, aos, ubuf, rec, own, slot_order);
     } else {
-      if (rec32) launch_pairs_p<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
-      else launch_pairs_p<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
+      if (rec32) launch_pairs_p<false>(s, a, geo, fq, t_pos, aos, ubuf, rec_f, own, slot_order);
+      else launch_pairs_p<false>(s, a, geo, fq, t_pos, aos, ubuf, rec, own, slot_order);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
   } else if (!lane_pairs) {
     // the stabilised shape runs a wavefront-per-owner schedule only
     Prof pf(ctx, stab ? "k_adj_pairs_w<stab>" : "k_adj_pairs_w");
     if (stab) {
-      if (rec32) launch_pairs_w<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
-      else launch_pairs_w<true>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
+      if (rec32) launch_pairs_w<true>(s, a, geo, fq, t_pos, aos, ubuf, rec_f, own, slot_order);
+      else launch_pairs_w<true>(s, a, geo, fq, t_pos, aos, ubuf, rec, own, slot_order);
     } else {
-      if (rec32) launch_pairs_w<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec_f, own, slot_order);
-      else launch_pairs_w<false>(s, a, geo, fq, t_pos, pair_src, pair_ubuf, rec, own, slot_order);
+      if (rec32) launch_pairs_w<false>(s, a, geo, fq, t_pos, aos, ubuf, rec_f, own, slot_order);
+      else launch_pairs_w<false>(s, a, geo, fq, t_pos, aos, ubuf, rec, own, slot_order);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
   } else {

@@ -117,43 +117,6 @@ __device__ __forceinline__ void basis(T (&p)[NBASIS], T x, T y, T z) {
   p[19] = zz * z;
 }
 
-// d p_k / d xi_axis for all k, at (x, y, z).
-template <class T>
-__device__ __forceinline__ void basis_grad(T (&gx)[NBASIS], T (&gy)[NBASIS], T (&gz)[NBASIS],
-                                           T x, T y, T z) {
-  const T xx = x * x, yy = y * y, zz = z * z;
-  const T xy = x * y, xz = x * z, yz = y * z;
-  // d/dx
-  gx[0] = 0; gx[1] = 1; gx[2] = 0; gx[3] = 0;
-  gx[4] = 2 * x; gx[5] = y; gx[6] = z; gx[7] = 0; gx[8] = 0; gx[9] = 0;
-  gx[10] = 3 * xx; gx[11] = 2 * xy; gx[12] = 2 * xz; gx[13] = yy; gx[14] = yz;
-  gx[15] = zz; gx[16] = 0; gx[17] = 0; gx[18] = 0; gx[19] = 0;
-  // d/dy
-  gy[0] = 0; gy[1] = 0; gy[2] = 1; gy[3] = 0;
-  gy[4] = 0; gy[5] = x; gy[6] = 0; gy[7] = 2 * y; gy[8] = z; gy[9] = 0;
-  gy[10] = 0; gy[11] = xx; gy[12] = 0; gy[13] = 2 * xy; gy[14] = xz;
-  gy[15] = 0; gy[16] = 3 * yy; gy[17] = 2 * yz; gy[18] = zz; gy[19] = 0;
-  // d/dz
-  gz[0] = 0; gz[1] = 0; gz[2] = 0; gz[3] = 1;
-  gz[4] = 0; gz[5] = 0; gz[6] = x; gz[7] = 0; gz[8] = y; gz[9] = 2 * z;
-  gz[10] = 0; gz[11] = 0; gz[12] = xx; gz[13] = 0; gz[14] = xy;
-  gz[15] = 2 * xz; gz[16] = 0; gz[17] = yy; gz[18] = 2 * yz; gz[19] = 3 * zz;
-}
-
-// g_axis = sum_k c_k d p_k / d xi_axis, from the basis values p (their
-// degree-1 and degree-2 entries are the derivatives' monomials).
-template <class T>
-__device__ __forceinline__ void basis_grad_dot(const T (&p)[NBASIS], const T (&c)[NBASIS],
-                                               T (&g)[3]) {
-  g[0] = c[1] + T(2) * p[1] * c[4] + p[2] * c[5] + p[3] * c[6] + T(3) * p[4] * c[10] +
-         T(2) * p[5] * c[11] + T(2) * p[6] * c[12] + p[7] * c[13] + p[8] * c[14] + p[9] * c[15];
-  g[1] = c[2] + p[1] * c[5] + T(2) * p[2] * c[7] + p[3] * c[8] + p[4] * c[11] +
-         T(2) * p[5] * c[13] + p[6] * c[14] + T(3) * p[7] * c[16] + T(2) * p[8] * c[17] +
-         p[9] * c[18];
-  g[2] = c[3] + p[1] * c[6] + p[2] * c[8] + T(2) * p[3] * c[9] + p[4] * c[12] + p[5] * c[14] +
-         T(2) * p[6] * c[15] + p[7] * c[17] + T(2) * p[8] * c[18] + T(3) * p[9] * c[19];
-}
-
 // ---------------------------------------------------------------------------
 // Geometry
 // ---------------------------------------------------------------------------

@@ -412,39 +412,6 @@ __global__ void __launch_bounds__(THREADS)
   }
 }
 
-// X_r = A^{-1} R_r for NR general right-hand sides R (SoA [NR][20][n]);
-// status as in k_factor.  NaN-free: a failed factorization writes zeros.
-template <int NR>
-__global__ void __launch_bounds__(THREADS)
-    k_factor_solve(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
-                   const double* __restrict__ rhs, double* __restrict__ x,
-                   int32_t* __restrict__ status, int interp) {
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
-  const int i = tid >> 2;
-  const int l = tid & 3;
-  const bool valid = i < n;
-  const int ii = valid ? i : n - 1;
-  QuadChol c;
-  quad_chol_factor(c, c_tab, mom, soa_ld(n), ii, l, interp != 0);
-  const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
-  sfor<0, NR>([&](auto RI) {
-    constexpr int r = RI;
-    double b[5], out[5];
-    sfor<0, 5>([&](auto R) {
-      constexpr int rho = R;
-      b[rho] = rhs[((int64_t)r * NBASIS + 4 * rho + l) * soa_ld(n) + ii];
-    });
-    quad_chol_apply_inverse(c, l, b, out);
-    if (valid) {
-      sfor<0, 5>([&](auto R) {
-        constexpr int rho = R;
-        x[((int64_t)r * NBASIS + 4 * rho + l) * soa_ld(n) + i] = st == 0 ? out[rho] : 0.0;
-      });
-    }
-  });
-  if (status && valid && l == 0) status[i] = st;
-}
-
 // ---------------------------------------------------------------------------
 // 3a. derivatives of up to 8 fields for three operator rows
 // ---------------------------------------------------------------------------
@@ -745,24 +712,6 @@ hipError_t launch_moments(hipStream_t s, const EvalArgs& a, int lanes, double* m
     case 2: return launch_moments_g<2, double>(s, a, mom);
     default: return launch_moments_g<4, double>(s, a, mom);
   }
-}
-
-hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
-                               const double* mom, const double* rhs, double* x, int32_t* status,
-                               int fit) {
-  const unsigned grid = grid_for((int64_t)n * 4, THREADS);
-  const int interp = fit == PHB_FIT_INTERP19;
-  switch (nr) {
-    case 1: hipLaunchKernelGGL((k_factor_solve<1>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-    case 2: hipLaunchKernelGGL((k_factor_solve<2>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-    case 3: hipLaunchKernelGGL((k_factor_solve<3>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-    case 4: hipLaunchKernelGGL((k_factor_solve<4>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-    case 5: hipLaunchKernelGGL((k_factor_solve<5>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-    case 6: hipLaunchKernelGGL((k_factor_solve<6>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-    case 7: hipLaunchKernelGGL((k_factor_solve<7>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-    default: hipLaunchKernelGGL((k_factor_solve<8>), dim3(grid), dim3(THREADS), 0, s, n, mom, off, rhs, x, status, interp); break;
-  }
-  return hipGetLastError();
 }
 
 hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const double* mom,

@@ -85,10 +85,6 @@ hipError_t launch_fit_b(hipStream_t s, const EvalArgs& a, int nf, int fpl, doubl
 hipError_t launch_factor_fit(hipStream_t s, const EvalArgs& a, int nrows, const double* mom,
                              double* bc, double* aos, int32_t* status, double rcut,
                              int32_t* list, int32_t* count);
-// X = A^{-1} R for nr (1..8) right-hand sides given as SoA [nr][20][n].
-hipError_t launch_factor_solve(hipStream_t s, int n, const int64_t* off, int nr,
-                               const double* mom, const double* rhs, double* x, int32_t* status,
-                               int fit);
 // fp32: the neighbor loop in FP32 (the mixed form).  list, count (device):
 // only the particles list[0 .. *count), outputs at their own indices.
 hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,
