@@ -552,34 +552,84 @@ __global__ void k_nb_total(const int64_t* __restrict__ offsets, int m, int64_t c
 // the one-way entries use atomics (their order is undone by the sort).
 
 
-// Pass 1, one wavefront per row x, a lane per entry.
+// Pass 1, RW consecutive rows x per wavefront, a lane per entry of each: the
+// rows' loads are issued together, so each lane keeps RW searches in flight
+// (the passes are bound by the latency of dependent loads, not by bytes).
+// The search for x in row y is a lower bound; the step that sets the upper
+// end to the answer reads that entry, so a match is seen when it is read,
+// and ends the search there.
+constexpr int TR_RW = 4;
+
 __global__ void __launch_bounds__(NB_THREADS)
     k_tr_mutual(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
                 int32_t* __restrict__ rev, int32_t* __restrict__ acnt,
                 int32_t* __restrict__ bcnt) {
   const int lane = threadIdx.x & 63;
-  const int x = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + (threadIdx.x >> 6));
-  if (x >= n) return;
-  const int64_t s0 = off[x];
-  const int len = (int)(off[x + 1] - s0);
-  int a = 0;
-  for (int base = 0; base < len; base += 64) {
-    const int k = base + lane;
-    bool mutual = false;
-    if (k < len) {
-      const int y = idx[s0 + k];
-      int64_t lo = off[y], hi = off[y + 1];  // first entry >= x in [lo, hi)
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (idx[mid] < x) lo = mid + 1; else hi = mid;
-      }
-      mutual = lo < off[y + 1] && idx[lo] == x;
-      rev[s0 + k] = mutual ? (int32_t)lo : -1;
-      if (!mutual) atomicAdd(&bcnt[y], 1);
-    }
-    a += __popcll(__ballot(mutual));
+  const int x0 =
+      __builtin_amdgcn_readfirstlane((xcd_block() * NB_WAVES + (threadIdx.x >> 6)) * TR_RW);
+  if (x0 >= n) return;
+  int64_t s0[TR_RW];
+  int len[TR_RW], a[TR_RW];
+  int maxlen = 0;
+#pragma unroll
+  for (int r = 0; r < TR_RW; ++r) {
+    const int x = x0 + r;
+    s0[r] = x < n ? off[x] : 0;
+    len[r] = x < n ? (int)(off[x + 1] - s0[r]) : 0;
+    maxlen = max(maxlen, len[r]);
+    a[r] = 0;
   }
-  if (lane == 0) acnt[x] = a;
+  for (int base = 0; base < maxlen; base += 64) {
+    const int k = base + lane;
+    int y[TR_RW], lo[TR_RW], hi[TR_RW], found[TR_RW];
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r) y[r] = k < len[r] ? idx[s0[r] + k] : -1;
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r) {
+      lo[r] = y[r] >= 0 ? (int)off[y[r]] : 0;  // nnz < 2^31: offsets fit
+      hi[r] = y[r] >= 0 ? (int)off[y[r] + 1] : 0;
+      found[r] = -1;
+    }
+    for (;;) {
+      bool pend = false;
+#pragma unroll
+      for (int r = 0; r < TR_RW; ++r) pend |= lo[r] < hi[r];
+      if (!pend) break;
+      // a lane with a search still open has a non-empty row, so idx[0]
+      // exists for its finished searches to read
+      int mid[TR_RW], v[TR_RW];
+#pragma unroll
+      for (int r = 0; r < TR_RW; ++r) {
+        mid[r] = lo[r] + ((hi[r] - lo[r]) >> 1);
+        v[r] = idx[lo[r] < hi[r] ? mid[r] : 0];
+      }
+#pragma unroll
+      for (int r = 0; r < TR_RW; ++r) {
+        if (lo[r] < hi[r]) {
+          if (v[r] < x0 + r) {
+            lo[r] = mid[r] + 1;
+          } else if (v[r] == x0 + r) {  // keys are distinct: the answer
+            found[r] = lo[r] = hi[r] = mid[r];
+          } else {
+            hi[r] = mid[r];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r) {
+      if (y[r] >= 0) {
+        rev[s0[r] + k] = found[r];
+        if (found[r] < 0) atomicAdd(&bcnt[y[r]], 1);
+      }
+      a[r] += __popcll(__ballot(found[r] >= 0));
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r)
+      if (x0 + r < n) acnt[x0 + r] = a[r];
+  }
 }
 
 // Row lengths |A| + |B| for the scan; the B counts become the B cursors.
@@ -592,23 +642,54 @@ __global__ void __launch_bounds__(NB_THREADS)
   bcnt[x] = 0;
 }
 
-// Pass 2: one-way entry s = (i, x) into B(x): key i, payload s.  One
-// wavefront per forward row i, a lane per entry.
+// Pass 2: one-way entry s = (i, x) into B(x): key i, payload s.  TR_RW
+// forward rows i per wavefront, a lane per entry of each; the cursors' and
+// offsets' reads of all the rows are in flight before the first store.
 __global__ void __launch_bounds__(NB_THREADS)
     k_tr_oneway(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
                 const int32_t* __restrict__ rev, const int64_t* __restrict__ toff,
                 const int32_t* __restrict__ acnt, int32_t* __restrict__ bcur,
                 int32_t* __restrict__ tkey, int32_t* __restrict__ tpay) {
   const int lane = threadIdx.x & 63;
-  const int i = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + (threadIdx.x >> 6));
-  if (i >= n) return;
-  const int64_t s1 = off[i + 1];
-  for (int64_t s = off[i] + lane; s < s1; s += 64) {
-    if (rev[s] >= 0) continue;
-    const int x = idx[s];
-    const int64_t q = toff[x] + acnt[x] + atomicAdd(&bcur[x], 1);
-    tkey[q] = i;
-    tpay[q] = (int32_t)s;
+  const int i0 =
+      __builtin_amdgcn_readfirstlane((xcd_block() * NB_WAVES + (threadIdx.x >> 6)) * TR_RW);
+  if (i0 >= n) return;
+  int64_t s0[TR_RW];
+  int len[TR_RW];
+  int maxlen = 0;
+#pragma unroll
+  for (int r = 0; r < TR_RW; ++r) {
+    const int i = i0 + r;
+    s0[r] = i < n ? off[i] : 0;
+    len[r] = i < n ? (int)(off[i + 1] - s0[r]) : 0;
+    maxlen = max(maxlen, len[r]);
+  }
+  for (int base = 0; base < maxlen; base += 64) {
+    const int k = base + lane;
+    int x[TR_RW];
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r) {
+      const bool in = k < len[r];
+      const int32_t rv = in ? rev[s0[r] + k] : 0;
+      const int32_t xr = in ? idx[s0[r] + k] : -1;
+      x[r] = rv < 0 ? xr : -1;
+    }
+    int64_t t[TR_RW];
+    int cur[TR_RW];
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r) {
+      const int xs = x[r] >= 0 ? x[r] : 0;
+      t[r] = toff[xs] + acnt[xs];
+      cur[r] = 0;
+      if (x[r] >= 0) cur[r] = atomicAdd(&bcur[x[r]], 1);
+    }
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r) {
+      if (x[r] >= 0) {
+        tkey[t[r] + cur[r]] = i0 + r;
+        tpay[t[r] + cur[r]] = (int32_t)(s0[r] + k);
+      }
+    }
   }
 }
 
@@ -688,57 +769,118 @@ __device__ __forceinline__ void sort_write_trow(const int32_t* sk, const int32_t
   }
 }
 
-// Pass 3, one wavefront per transposed row x.  Rows longer than NB_ROW are
-// left in the scratch (A's part written there too) and listed for k_tr_long.
+// Pass 3, TR_RR transposed rows x per wavefront.  A row's mutual count
+// (acnt) places its one-way part, so the first 64 entries of both parts of
+// every row are read together before any is used.  A row without one-way
+// entries is A itself, already in order: written as it is compacted.  With
+// up to 64 one-way entries, each element's place is counted (an element of
+// A: its index plus the B keys below it; of B: A's keys below it, by binary
+// search, plus B's); with more, the row is sorted in registers.  Keys are
+// distinct, so the places are a permutation.  Rows longer than NB_ROW with
+// one-way entries are left in the scratch (A's part written there too) and
+// listed for k_tr_long.
+constexpr int TR_RR = 2;
+
 __global__ void __launch_bounds__(NB_THREADS)
     k_tr_rows(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
               const int32_t* __restrict__ rev, const int64_t* __restrict__ toff,
-              int32_t* __restrict__ tkey, int32_t* __restrict__ tpay,
-              int32_t* __restrict__ tsrc, int32_t* __restrict__ tpos,
-              int32_t* __restrict__ long_list, int32_t* __restrict__ long_count) {
-  __shared__ int32_t sk[NB_WAVES][NB_ROW], sp[NB_WAVES][NB_ROW];
+              const int32_t* __restrict__ acnt, int32_t* __restrict__ tkey,
+              int32_t* __restrict__ tpay, int32_t* __restrict__ tsrc,
+              int32_t* __restrict__ tpos, int32_t* __restrict__ long_list,
+              int32_t* __restrict__ long_count) {
+  __shared__ int32_t sk[NB_WAVES][TR_RR][NB_ROW], sp[NB_WAVES][TR_RR][NB_ROW];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int x = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + wv);
-  if (x >= n) return;
-  const int64_t t0 = toff[x];
-  const int tl = (int)(toff[x + 1] - t0);
-  const bool in_lds = tl <= NB_ROW;
-  const int64_t s0 = off[x];
-  const int len = (int)(off[x + 1] - s0);
-  int c = 0;  // A's elements so far, in row order
-  for (int base = 0; base < len; base += 64) {
-    const int k = base + lane;
-    int32_t rv = -1, y = 0;
-    if (k < len) {
-      rv = rev[s0 + k];
-      y = idx[s0 + k];
-    }
-    const bool mutual = rv >= 0;
-    const uint64_t mask = __ballot(mutual);
-    const int at = c + __popcll(mask & ((1ull << lane) - 1ull));
-    if (mutual && at < tl) {
-      if (in_lds) {
-        sk[wv][at] = y;
-        sp[wv][at] = rv;
-      } else {
-        tkey[t0 + at] = y;
-        tpay[t0 + at] = rv;
+  const int x0 = __builtin_amdgcn_readfirstlane((xcd_block() * NB_WAVES + wv) * TR_RR);
+  if (x0 >= n) return;
+  int64_t t0[TR_RR], s0[TR_RR];
+  int tl[TR_RR], len[TR_RR], c[TR_RR];
+#pragma unroll
+  for (int r = 0; r < TR_RR; ++r) {
+    const int x = x0 + r;
+    const bool ok = x < n;
+    t0[r] = ok ? toff[x] : 0;
+    tl[r] = ok ? (int)(toff[x + 1] - t0[r]) : 0;
+    s0[r] = ok ? off[x] : 0;
+    len[r] = ok ? (int)(off[x + 1] - s0[r]) : 0;
+    c[r] = ok ? acnt[x] : 0;
+  }
+  int32_t rv[TR_RR], y[TR_RR], bk[TR_RR], bp[TR_RR];
+#pragma unroll
+  for (int r = 0; r < TR_RR; ++r) {
+    const bool in = lane < len[r];
+    rv[r] = in ? rev[s0[r] + lane] : -1;
+    y[r] = in ? idx[s0[r] + lane] : 0;
+    const bool inb = tl[r] <= NB_ROW && c[r] + lane < tl[r];
+    bk[r] = inb ? tkey[t0[r] + c[r] + lane] : 0;
+    bp[r] = inb ? tpay[t0[r] + c[r] + lane] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < TR_RR; ++r) {
+    if (x0 + r >= n) break;
+    const bool direct = c[r] == tl[r];  // no one-way entries
+    const bool in_lds = tl[r] <= NB_ROW;
+    int32_t* K = sk[wv][r];
+    int32_t* P = sp[wv][r];
+    int cc = 0;  // A's elements so far, in row order
+    for (int base = 0; base < len[r]; base += 64) {
+      int32_t v = rv[r], yy = y[r];
+      if (base > 0) {
+        const int k = base + lane;
+        v = k < len[r] ? rev[s0[r] + k] : -1;
+        yy = k < len[r] ? idx[s0[r] + k] : 0;
       }
+      const bool mutual = v >= 0;
+      const uint64_t mask = __ballot(mutual);
+      const int at = cc + __popcll(mask & ((1ull << lane) - 1ull));
+      if (mutual && at < tl[r]) {
+        if (direct) {
+          tsrc[t0[r] + at] = yy;
+          tpos[v] = (int32_t)(t0[r] + at);
+        } else if (in_lds) {
+          K[at] = yy;
+          P[at] = v;
+        } else {
+          tkey[t0[r] + at] = yy;
+          tpay[t0[r] + at] = v;
+        }
+      }
+      cc += __popcll(mask);
     }
-    c += __popcll(mask);
+    if (direct) continue;
+    if (!in_lds) {
+      if (lane == 0) long_list[atomicAdd(long_count, 1)] = x0 + r;
+      continue;
+    }
+    for (int k = c[r] + lane; k < tl[r]; k += 64) {
+      const bool first = k < c[r] + 64;
+      K[k] = first ? bk[r] : tkey[t0[r] + k];
+      P[k] = first ? bp[r] : tpay[t0[r] + k];
+    }
+    wave_lds_sync();
+    if (tl[r] - c[r] <= 64) {
+      for (int k = lane; k < tl[r]; k += 64) {
+        const int32_t key = K[k];
+        int rank = k;
+        if (k >= c[r]) {  // first element of A not below the key
+          int lo = 0, hi = c[r];
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (K[mid] < key) lo = mid + 1; else hi = mid;
+          }
+          rank = lo;
+        }
+        for (int j = c[r]; j < tl[r]; ++j) rank += K[j] < key ? 1 : 0;
+        tsrc[t0[r] + rank] = key;
+        tpos[P[k]] = (int32_t)(t0[r] + rank);
+      }
+    } else if (tl[r] <= 64) {
+      sort_write_trow<1>(K, P, tl[r], t0[r], lane, tsrc, tpos);
+    } else if (tl[r] <= 128) {
+      sort_write_trow<2>(K, P, tl[r], t0[r], lane, tsrc, tpos);
+    } else {
+      sort_write_trow<4>(K, P, tl[r], t0[r], lane, tsrc, tpos);
+    }
   }
-  if (!in_lds) {
-    if (lane == 0) long_list[atomicAdd(long_count, 1)] = x;
-    return;
-  }
-  for (int k = c + lane; k < tl; k += 64) {
-    sk[wv][k] = tkey[t0 + k];
-    sp[wv][k] = tpay[t0 + k];
-  }
-  wave_lds_sync();
-  if (tl <= 64) sort_write_trow<1>(sk[wv], sp[wv], tl, t0, lane, tsrc, tpos);
-  else if (tl <= 128) sort_write_trow<2>(sk[wv], sp[wv], tl, t0, lane, tsrc, tpos);
-  else sort_write_trow<4>(sk[wv], sp[wv], tl, t0, lane, tsrc, tpos);
 }
 
 // The listed transposed rows longer than NB_ROW (rare): each element's rank
@@ -985,7 +1127,7 @@ hipError_t launch_transpose(hipStream_t s, int n, const int64_t* off, const int3
   hipError_t e = fill_i32(s, w.bcnt, 0, n);
   if (e != hipSuccess) return e;
   if ((e = fill_i32(s, w.counts, 0, 2)) != hipSuccess) return e;
-  const dim3 gw(grid_for(n, NB_WAVES));
+  const dim3 gw(grid_for(n, NB_WAVES * TR_RW)), gr(grid_for(n, NB_WAVES * TR_RR));
   hipLaunchKernelGGL(k_tr_mutual, gw, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, w.acnt,
                      w.bcnt);
   hipLaunchKernelGGL(k_tr_total, dim3(grid_for(n, NB_THREADS)), dim3(NB_THREADS), 0, s, n,
@@ -993,8 +1135,8 @@ hipError_t launch_transpose(hipStream_t s, int n, const int64_t* off, const int3
   if ((e = exclusive_scan_i32_to_i64(s, w.tcount, n, toff, w.scan)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tr_oneway, gw, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, toff, w.acnt,
                      w.bcnt, w.tkey, w.tpay);
-  hipLaunchKernelGGL(k_tr_rows, gw, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, toff, w.tkey,
-                     w.tpay, tsrc, tpos, w.long_list, w.counts + 1);
+  hipLaunchKernelGGL(k_tr_rows, gr, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, toff, w.acnt,
+                     w.tkey, w.tpay, tsrc, tpos, w.long_list, w.counts + 1);
   hipLaunchKernelGGL(k_tr_long, dim3(NB_LONG_BLOCKS * NB_WAVES), dim3(64), 0, s, w.long_list,
                      w.counts + 1, toff, w.tkey, w.tpay, tsrc, tpos);
   return hipGetLastError();
