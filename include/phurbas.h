@@ -276,9 +276,9 @@ int phb_mhd_rhs_adjoint(phb_ctx* ctx, const phb_params* p, int64_t n, const doub
 /* The same without reading offsets[n] back (phb_mhd_rhs_adjoint does, to size
  * its pair records): nnz_bound >= offsets[n] sizes them instead, so that the
  * call can be captured in a HIP graph after phb_neighbors_build_async, whose
- * total stays on the device (its idx capacity is such a bound).  Runs a
- * wavefront-per-owner pair schedule: adj_pairs_mode 0 (one lane per entry,
- * sized by the exact count) runs as 1. */
+ * total stays on the device (its idx capacity is such a bound).
+ * adj_pairs_mode 0 (one lane per entry, sized by the exact count) runs as 1
+ * here. */
 int phb_mhd_rhs_adjoint_async(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                               const double* lambda, const int64_t* offsets, const int32_t* idx,
                               const int64_t* t_offsets, const int32_t* t_src,
@@ -429,7 +429,11 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * transposed row in the reverse mode), "adj_pairs_mode" (0: one lane per
  * neighbor entry, 1: one wavefront per owner particle, 2: persistent
  * wavefronts that stage the next owner through direct-to-LDS loads while
- * computing the current one), "record_order" (0:
+ * computing the current one, 3, the default: one block per tile of 128
+ * consecutive owners (a batch's sets tiled from their first particles), its
+ * four wavefronts taking the owners in ascending order, summing the pair
+ * terms whose target lies in the tile in LDS instead of writing them as
+ * records), "record_order" (0:
  * pair records written at their transposed position, 1: written in forward
  * order and gathered through the inverse map), "mixed_cond_x10" (-1..120:
  * in the untaped mixed form a particle whose FP32-assembled moment matrix, scaled to

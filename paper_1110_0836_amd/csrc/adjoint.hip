@@ -528,82 +528,83 @@ __global__ void __launch_bounds__(THREADS)
 // compact Ubar [n][NFA][NR]; the wavefront stages G and Ubar and forms
 // K = Ubar C^T as it stages them (one entry of K per lane and pass, all in
 // the one staging phase).
-template <class RT, class CT = double, bool STAB = false>
-__global__ void __launch_bounds__(64)
-    k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
-                  const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
-                  double rf_ratio, int wkind, const double* __restrict__ fq,
-                  const double* __restrict__ aos, const double* __restrict__ ubuf,
-                  RT* __restrict__ rec, double* __restrict__ own, int slot_order) {
+// PAIR_TILE: owners per tile of the tile schedule (its LDS sums).  The
+// tiles of a set are fixed by its size alone: a batch tiles each of its
+// sets as a call on that set would.
+constexpr int PAIR_TILE = 128;
+
+// One owner's pair terms.  TILE = false: every record to its slot and the
+// owner's share to own.  TILE = true (the tile schedule): the terms for
+// targets j in the wavefront's tile [T0, T1) and the owner's share are
+// added to the tile's LDS sums tacc[component][j - T0] instead; a row's
+// targets are distinct, so its lanes never add to one sum together, and a
+// wavefront's LDS accesses complete in program order.
+template <class RT, class CT, bool STAB, bool TILE>
+__device__ __forceinline__ void owner_pairs(
+    int i, int lane, int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+    const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, const Box& box,
+    double rf_ratio, int wkind, const double* __restrict__ fq, const double* __restrict__ aos,
+    const double* __restrict__ ubuf, RT* __restrict__ rec, double* __restrict__ own,
+    int slot_order, CT* osh, double* tacc, int T0, int T1) {
   using SH = Shape<STAB>;
-  constexpr int OR = SH::OREC, RC = SH::REC;
+  constexpr int RC = SH::REC;
   constexpr int NR = SH::NR, NFA = SH::NFA;
-  const int i = __builtin_amdgcn_readfirstlane(xcd_block());
-  const int lane = threadIdx.x & 63;
-  // the owner record (G | K | Ubar) goes to LDS once per wavefront; the pair
-  // terms then read it row by row at LDS latency
-  __shared__ CT osh[OR];
   // Each lane's first entry (index, neighbor geometry, transposed position)
   // is fetched before the record is staged, so that this dependent chain of
   // loads overlaps the staging; later entries are fetched one iteration
   // ahead.
-  int64_t rs = 0, re = 0;
-  double4 gi = make_double4(0.0, 0.0, 0.0, 1.0), gjn = gi;
+  const int64_t rs = off[i], re = off[i + 1];
+  const double4 gi = geo[i];
+  double4 gjn = make_double4(0.0, 0.0, 0.0, 1.0);
   int jn = 0, tpn = 0;
-  if (i < n) {
-    rs = off[i];
-    re = off[i + 1];
-    gi = geo[i];
-    if (rs + lane < re) {
-      jn = idx[rs + lane];
-      gjn = geo[jn];
-      if (!slot_order) tpn = t_pos[rs + lane];
+  if (rs + lane < re) {
+    jn = idx[rs + lane];
+    gjn = geo[jn];
+    if (!slot_order) tpn = t_pos[rs + lane];
+  }
+  {
+    // every load of the staging is issued before the first LDS store, so
+    // the record costs one memory latency
+    const double* g = aos + (int64_t)i * TAPE_AOS;
+    const double* u = ubuf + (int64_t)i * NFA * NR;
+    constexpr int NK = (NR * NBASIS + 63) / 64, NU = (NFA * NR + 63) / 64;
+    double gv[NK], kv[NK], uv[NU];
+#pragma unroll
+    for (int r = 0; r < NK; ++r) {
+      const int e = lane + 64 * r;
+      gv[r] = e < NR * NBASIS ? g[e] : 0.0;
     }
-    {
-      // every load of the staging is issued before the first LDS store, so
-      // the record costs one memory latency
-      const double* g = aos + (int64_t)i * TAPE_AOS;
-      const double* u = ubuf + (int64_t)i * NFA * NR;
-      constexpr int NK = (NR * NBASIS + 63) / 64, NU = (NFA * NR + 63) / 64;
-      double gv[NK], kv[NK], uv[NU];
 #pragma unroll
-      for (int r = 0; r < NK; ++r) {
-        const int e = lane + 64 * r;
-        gv[r] = e < NR * NBASIS ? g[e] : 0.0;
+    for (int r = 0; r < NU; ++r) {
+      const int e = lane + 64 * r;
+      uv[r] = e < NFA * NR ? u[e] : 0.0;
+    }
+    // K_t = sum_f Ubar[f][t] C_f
+#pragma unroll
+    for (int r = 0; r < NK; ++r) {
+      const int e = lane + 64 * r;
+      const int t = e / NBASIS, b = e % NBASIS;
+      double k = 0.0;
+      if (e < NR * NBASIS) {
+#pragma unroll
+        for (int f = 0; f < NFA; ++f) k = fma(u[f * NR + t], g[NR * NBASIS + f * NBASIS + b], k);
       }
+      kv[r] = k;
+    }
 #pragma unroll
-      for (int r = 0; r < NU; ++r) {
-        const int e = lane + 64 * r;
-        uv[r] = e < NFA * NR ? u[e] : 0.0;
+    for (int r = 0; r < NK; ++r) {
+      const int e = lane + 64 * r;
+      if (e < NR * NBASIS) {
+        osh[e] = CT(gv[r]);
+        osh[SH::KOFF + e] = CT(kv[r]);
       }
-      // K_t = sum_f Ubar[f][t] C_f
+    }
 #pragma unroll
-      for (int r = 0; r < NK; ++r) {
-        const int e = lane + 64 * r;
-        const int t = e / NBASIS, b = e % NBASIS;
-        double k = 0.0;
-        if (e < NR * NBASIS) {
-#pragma unroll
-          for (int f = 0; f < NFA; ++f) k = fma(u[f * NR + t], g[NR * NBASIS + f * NBASIS + b], k);
-        }
-        kv[r] = k;
-      }
-#pragma unroll
-      for (int r = 0; r < NK; ++r) {
-        const int e = lane + 64 * r;
-        if (e < NR * NBASIS) {
-          osh[e] = CT(gv[r]);
-          osh[SH::KOFF + e] = CT(kv[r]);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < NU; ++r) {
-        const int e = lane + 64 * r;
-        if (e < NFA * NR) osh[SH::UOFF + e] = CT(uv[r]);
-      }
+    for (int r = 0; r < NU; ++r) {
+      const int e = lane + 64 * r;
+      if (e < NFA * NR) osh[SH::UOFF + e] = CT(uv[r]);
     }
   }
-  if (i >= n) return;  // whole wavefronts leave together
   // each wavefront reads only its own record: no block barrier
   wave_lds_sync();
   const double inv_lam = 1.0 / gi.w;
@@ -635,15 +636,20 @@ __global__ void __launch_bounds__(64)
       const double dw = weight_dq(qd, wkind);
       pair_terms<CT, STAB>(o, w, dw, inv_lam, inv_r2, dx, dy, dz, fi, fq + 8 * (int64_t)j, v);
     }
-    RT* out = rec + (slot_order ? s : (int64_t)tp) * RC;
-    if constexpr (sizeof(RT) == 8) {
-      double2* o2 = reinterpret_cast<double2*>(out);
+    if (TILE && j >= T0 && j < T1) {
 #pragma unroll
-      for (int c = 0; c < RC; c += 2) o2[c / 2] = make_double2(v[c], v[c + 1]);
+      for (int c = 0; c < RC; ++c) tacc[c * PAIR_TILE + (j - T0)] += double(v[c]);
     } else {
-      float2* o2 = reinterpret_cast<float2*>(out);
+      RT* out = rec + (slot_order ? s : (int64_t)tp) * RC;
+      if constexpr (sizeof(RT) == 8) {
+        double2* o2 = reinterpret_cast<double2*>(out);
 #pragma unroll
-      for (int c = 0; c < RC; c += 2) o2[c / 2] = make_float2((float)v[c], (float)v[c + 1]);
+        for (int c = 0; c < RC; c += 2) o2[c / 2] = make_double2(v[c], v[c + 1]);
+      } else {
+        float2* o2 = reinterpret_cast<float2*>(out);
+#pragma unroll
+        for (int c = 0; c < RC; c += 2) o2[c / 2] = make_float2((float)v[c], (float)v[c + 1]);
+      }
     }
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] += v[c];
@@ -651,7 +657,86 @@ __global__ void __launch_bounds__(64)
   double tot;
   int comp;
   wave_sum_transposed<RC>(acc, tot, comp);
-  if (comp >= 0) own[(int64_t)comp * n + i] = -tot;
+  if (comp >= 0) {
+    if constexpr (TILE) tacc[comp * PAIR_TILE + (i - T0)] -= tot;
+    else own[(int64_t)comp * n + i] = -tot;
+  }
+}
+
+template <class RT, class CT = double, bool STAB = false>
+__global__ void __launch_bounds__(64)
+    k_adj_pairs_w(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                  const int32_t* __restrict__ idx, const int32_t* __restrict__ t_pos, Box box,
+                  double rf_ratio, int wkind, const double* __restrict__ fq,
+                  const double* __restrict__ aos, const double* __restrict__ ubuf,
+                  RT* __restrict__ rec, double* __restrict__ own, int slot_order) {
+  const int i = __builtin_amdgcn_readfirstlane(xcd_block());
+  if (i >= n) return;  // one wavefront per block
+  // the owner record (G | K | Ubar) goes to LDS once per wavefront; the pair
+  // terms then read it row by row at LDS latency
+  __shared__ CT osh[Shape<STAB>::OREC];
+  owner_pairs<RT, CT, STAB, false>(i, threadIdx.x & 63, n, geo, off, idx, t_pos, box, rf_ratio,
+                                   wkind, fq, aos, ubuf, rec, own, slot_order, osh, nullptr, 0,
+                                   0);
+}
+
+// ---- 3b'. pair contributions, one block per tile of owners ------------------
+// A block of TILE_WAVES wavefronts takes the owners of one tile of
+// ts <= PAIR_TILE consecutive particles (consecutive along the Hilbert
+// curve: a compact region); wavefront w takes owners w, w + TILE_WAVES, ...
+// in ascending order.  Pair terms whose target lies in the tile are summed
+// in LDS, in FP64, each wavefront in its own copy of the tile's sums, and
+// the copies are added in a fixed order and written once per particle with
+// the owner's share (into own, which the gather adds); only the other
+// records go to memory, and the gather skips a particle's in-tile owners (a
+// contiguous run of its sorted transposed row; tbound gives each particle
+// its tile).  The order of every sum is fixed by the tiles: uniform tiles of
+// ts owners, or the tile starts tstart[0 .. ntiles] (a batch tiles each set
+// from its first particle, as a call on that set alone does, so that its
+// results are the same to the last bit).  Several wavefronts per tile keep
+// the tiles short, so that
+// the tiles in flight on an XCD span a region whose neighbor data stays in
+// its L2.
+constexpr int TILE_WAVES = 4;
+
+// Three wavefronts per SIMD, as the wavefront-per-owner kernel gets by
+// itself (its 64-thread blocks): a 256-thread block lets the compiler take
+// more registers and leaves two.
+template <class RT, class CT = double, bool STAB = false>
+__global__ void __launch_bounds__(64 * TILE_WAVES) __attribute__((amdgpu_waves_per_eu(3)))
+    k_adj_pairs_t(int n, int ts, const int32_t* __restrict__ tstart, int2* __restrict__ tbound,
+                  const double4* __restrict__ geo,
+                  const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
+                  const int32_t* __restrict__ t_pos, Box box, double rf_ratio, int wkind,
+                  const double* __restrict__ fq, const double* __restrict__ aos,
+                  const double* __restrict__ ubuf, RT* __restrict__ rec,
+                  double* __restrict__ own, int slot_order) {
+  using SH = Shape<STAB>;
+  constexpr int RC = SH::REC;
+  const int t = xcd_block();
+  const int T0 = tstart ? tstart[t] : t * ts;
+  if (T0 >= n) return;  // whole blocks leave together
+  const int T1 = tstart ? tstart[t + 1] : min(T0 + ts, n);
+  // the wavefront's index made uniform, so that the owner index and all it
+  // addresses stay in scalar registers
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  __shared__ CT osh[TILE_WAVES][SH::OREC];
+  __shared__ double tacc[TILE_WAVES][RC * PAIR_TILE];
+  for (int e = lane; e < RC * PAIR_TILE; e += 64) tacc[wv][e] = 0.0;
+  for (int i = T0 + wv; i < T1; i += TILE_WAVES)
+    owner_pairs<RT, CT, STAB, true>(i, lane, n, geo, off, idx, t_pos, box, rf_ratio, wkind, fq,
+                                    aos, ubuf, rec, own, slot_order, osh[wv], tacc[wv], T0, T1);
+  __syncthreads();
+  for (int e = threadIdx.x; e < T1 - T0; e += 64 * TILE_WAVES) {
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+      double sum = tacc[0][c * PAIR_TILE + e];
+#pragma unroll
+      for (int w = 1; w < TILE_WAVES; ++w) sum += tacc[w][c * PAIR_TILE + e];
+      own[(int64_t)c * n + T0 + e] = sum;
+    }
+    tbound[T0 + e] = make_int2(T0, T1);
+  }
 }
 
 // ---- 3c. pair contributions, pipelined over owners --------------------------
@@ -880,10 +965,14 @@ __global__ void __launch_bounds__(THREADS)
 
 // ---- 4. gather over the transposed lists ------------------------------------
 // G lanes share one particle's transposed row; their partial sums meet in a
-// quad reduction.  The summation order is fixed for a given G.
-template <int G, class RT, bool STAB = false>
+// quad reduction.  The summation order is fixed for a given G.  TILE: the
+// pair records of owners in the particle's own tile (tbound) were summed
+// into own by the tile schedule and are skipped here (t_src names each
+// entry's owner).
+template <int G, class RT, bool STAB = false, bool TILE = false>
 __global__ void __launch_bounds__(THREADS)
-    k_adj_gather(int n, const int64_t* __restrict__ t_off, const int32_t* __restrict__ t_slot,
+    k_adj_gather(int n, const int2* __restrict__ tbound, const int64_t* __restrict__ t_off,
+                 const int32_t* __restrict__ t_slot, const int32_t* __restrict__ t_src,
                  const RT* __restrict__ rec, const double* __restrict__ own,
                  const double* __restrict__ qb_direct, double* __restrict__ q_bar,
                  double* __restrict__ pos_bar) {
@@ -894,11 +983,17 @@ __global__ void __launch_bounds__(THREADS)
   const int l = tid % G;
   const bool valid = j < n;
   const int jj = valid ? j : n - 1;
+  const int2 tb = TILE ? tbound[jj] : make_int2(0, 0);
+  const int tlo = tb.x, thi = tb.y;
   double acc[REC];
 #pragma unroll
   for (int c = 0; c < REC; ++c) acc[c] = 0.0;
   const int64_t k1 = valid ? t_off[jj + 1] : 0;
   for (int64_t k = t_off[jj] + l; k < k1; k += G) {
+    if constexpr (TILE) {
+      const int src = t_src[k];
+      if (src >= tlo && src < thi) continue;
+    }
     const RT* r = rec + (t_slot ? (int64_t)t_slot[k] : k) * REC;
     if constexpr (sizeof(RT) == 8) {
       const double2* r2 = reinterpret_cast<const double2*>(r);
@@ -936,20 +1031,32 @@ __global__ void __launch_bounds__(THREADS)
 namespace {
 
 // Launch helpers that pick the template instance from run-time choices.
-template <bool STAB, class RT>
-void launch_gather(hipStream_t s, int gl, int n, const int64_t* t_off, const int32_t* tsl,
-                   const RT* rec, const double* own, const double* qbd, double* q_bar,
-                   double* pos_bar) {
+template <bool STAB, bool TILE, class RT>
+void launch_gather_t(hipStream_t s, int gl, int n, const int2* tb, const int64_t* t_off,
+                     const int32_t* tsl, const int32_t* t_src, const RT* rec, const double* own,
+                     const double* qbd, double* q_bar, double* pos_bar) {
   const unsigned gg = grid_for((int64_t)n * gl, THREADS);
   if (gl == 1)
-    hipLaunchKernelGGL((k_adj_gather<1, RT, STAB>), dim3(gg), dim3(THREADS), 0, s, n, t_off, tsl,
-                       rec, own, qbd, q_bar, pos_bar);
+    hipLaunchKernelGGL((k_adj_gather<1, RT, STAB, TILE>), dim3(gg), dim3(THREADS), 0, s, n, tb,
+                       t_off, tsl, t_src, rec, own, qbd, q_bar, pos_bar);
   else if (gl == 2)
-    hipLaunchKernelGGL((k_adj_gather<2, RT, STAB>), dim3(gg), dim3(THREADS), 0, s, n, t_off, tsl,
-                       rec, own, qbd, q_bar, pos_bar);
+    hipLaunchKernelGGL((k_adj_gather<2, RT, STAB, TILE>), dim3(gg), dim3(THREADS), 0, s, n, tb,
+                       t_off, tsl, t_src, rec, own, qbd, q_bar, pos_bar);
   else
-    hipLaunchKernelGGL((k_adj_gather<4, RT, STAB>), dim3(gg), dim3(THREADS), 0, s, n, t_off, tsl,
-                       rec, own, qbd, q_bar, pos_bar);
+    hipLaunchKernelGGL((k_adj_gather<4, RT, STAB, TILE>), dim3(gg), dim3(THREADS), 0, s, n, tb,
+                       t_off, tsl, t_src, rec, own, qbd, q_bar, pos_bar);
+}
+
+// tb: each particle's tile under the tile schedule (its in-tile records are
+// skipped), or null.
+template <bool STAB, class RT>
+void launch_gather(hipStream_t s, int gl, const int2* tb, int n, const int64_t* t_off,
+                   const int32_t* tsl, const int32_t* t_src, const RT* rec, const double* own,
+                   const double* qbd, double* q_bar, double* pos_bar) {
+  if (tb)
+    launch_gather_t<STAB, true>(s, gl, n, tb, t_off, tsl, t_src, rec, own, qbd, q_bar, pos_bar);
+  else
+    launch_gather_t<STAB, false>(s, gl, n, tb, t_off, tsl, t_src, rec, own, qbd, q_bar, pos_bar);
 }
 
 template <bool STAB, class RT>
@@ -959,6 +1066,18 @@ void launch_pairs_w(hipStream_t s, const EvalArgs& a, const double4* geo, const 
   const dim3 grid(grid_for(a.n, 1));  // one wavefront per owner, one per block
   hipLaunchKernelGGL((k_adj_pairs_w<RT, double, STAB>), grid, dim3(64), 0, s, a.n, geo, a.off,
                      a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, aos, ubuf, rec, own,
+                     slot_order);
+}
+
+template <bool STAB, class RT>
+void launch_pairs_t(hipStream_t s, const EvalArgs& a, int ts, const int32_t* tstart,
+                    int64_t ntiles, int2* tb, const double4* geo, const double* fq,
+                    const int32_t* t_pos, const double* aos, const double* ubuf, RT* rec,
+                    double* own, int slot_order) {
+  const dim3 grid(tstart ? (unsigned)ntiles : grid_for(a.n, ts));  // one block per tile
+  hipLaunchKernelGGL((k_adj_pairs_t<RT, double, STAB>), grid, dim3(64 * TILE_WAVES), 0, s, a.n,
+                     ts, tstart, tb, geo,
+                     a.off, a.idx, t_pos, a.box, a.rf_ratio, a.wkind, fq, aos, ubuf, rec, own,
                      slot_order);
 }
 
@@ -997,6 +1116,7 @@ static void plan_adjoint(Workspace& ws, int64_t n, int64_t nnz, const phb_params
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * RCr * sizeof(double));  // pair records
   ws.plan((size_t)nwaves * 2 * REC * sizeof(double));                 // wavefront partials
   ws.plan((size_t)std::max<int64_t>(nnz, 1) * sizeof(int32_t));       // inverse of t_pos
+  ws.plan((size_t)n * sizeof(int2));                                  // tile of each particle
   ws.plan((size_t)NFAr * NRr * nd);               // Ubar
   if (lane_pairs) ws.plan((size_t)ORr * nd);      // owner records
   if (need_tape) {
@@ -1006,6 +1126,8 @@ static void plan_adjoint(Workspace& ws, int64_t n, int64_t nnz, const phb_params
     ws.plan((size_t)n * sizeof(int32_t));                // status scratch
   }
 }
+
+int adjoint_pair_tile() { return PAIR_TILE; }
 
 size_t ws_bytes_adjoint(int64_t n, int64_t nnz, const phb_params* p, bool need_tape) {
   phb_ctx dummy;
@@ -1022,8 +1144,8 @@ size_t ws_bytes_adjoint(int64_t n, int64_t nnz, const phb_params* p, bool need_t
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
-                const double* tape_in, int64_t nnz_known, bool nnz_exact) {
-  (void)t_src;
+                const double* tape_in, int64_t nnz_known, bool nnz_exact,
+                const int32_t* tstart, int64_t ntiles) {
   const int n = a.n;
   const Stab sb = stab_of(p);
   const bool stab = sb.on();
@@ -1069,6 +1191,7 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   double* rec = ws.take<double>((size_t)std::max<int64_t>(nnz, 1) * RCr);
   double* wpart = ws.take<double>((size_t)nwaves * 2 * REC);
   int32_t* t_slot = ws.take<int32_t>(std::max<int64_t>(nnz, 1));
+  int2* tbound = ws.take<int2>(n);
   double* ubuf = ws.take<double>((size_t)NFAr * NRr * n);
   double* orec = lane_pairs ? ws.take<double>((size_t)ORr * n) : nullptr;
   const int slot_order = ctx->record_order;
@@ -1110,6 +1233,8 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   // caller's tape) must be 16-byte aligned, else the one-shot schedule runs
   const bool piped = !lane_pairs && ctx->adj_pairs_mode == 2 &&
                      (reinterpret_cast<uintptr_t>(aos) & 15) == 0;
+  const bool tiled = !lane_pairs && ctx->adj_pairs_mode == 3;
+  const int ts = PAIR_TILE;
   if (piped) {
     Prof pf(ctx, stab ? "k_adj_pairs_p<stab>" : "k_adj_pairs_p");
     if (stab) {
@@ -1118,6 +1243,16 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
     } else {
       if (rec32) launch_pairs_p<false>(s, a, geo, fq, t_pos, aos, ubuf, rec_f, own, slot_order);
       else launch_pairs_p<false>(s, a, geo, fq, t_pos, aos, ubuf, rec, own, slot_order);
+    }
+    if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
+  } else if (tiled) {
+    Prof pf(ctx, stab ? "k_adj_pairs_t<stab>" : "k_adj_pairs_t");
+    if (stab) {
+      if (rec32) launch_pairs_t<true>(s, a, ts, tstart, ntiles, tbound, geo, fq, t_pos, aos, ubuf, rec_f, own, slot_order);
+      else launch_pairs_t<true>(s, a, ts, tstart, ntiles, tbound, geo, fq, t_pos, aos, ubuf, rec, own, slot_order);
+    } else {
+      if (rec32) launch_pairs_t<false>(s, a, ts, tstart, ntiles, tbound, geo, fq, t_pos, aos, ubuf, rec_f, own, slot_order);
+      else launch_pairs_t<false>(s, a, ts, tstart, ntiles, tbound, geo, fq, t_pos, aos, ubuf, rec, own, slot_order);
     }
     if ((rc = hip_check(ctx, hipGetLastError(), "adjoint pairs"))) return rc;
   } else if (!lane_pairs) {
@@ -1159,11 +1294,11 @@ int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int6
   Prof pf(ctx, "k_adj_gather");
   const int gl = ctx->lanes_gather;
   if (stab) {
-    if (rec32) launch_gather<true>(s, gl, n, t_offsets, tsl, (const float*)rec_f, own, qbd, q_bar, pos_bar);
-    else launch_gather<true>(s, gl, n, t_offsets, tsl, (const double*)rec, own, qbd, q_bar, pos_bar);
+    if (rec32) launch_gather<true>(s, gl, tiled ? tbound : nullptr, n, t_offsets, tsl, t_src, (const float*)rec_f, own, qbd, q_bar, pos_bar);
+    else launch_gather<true>(s, gl, tiled ? tbound : nullptr, n, t_offsets, tsl, t_src, (const double*)rec, own, qbd, q_bar, pos_bar);
   } else {
-    if (rec32) launch_gather<false>(s, gl, n, t_offsets, tsl, (const float*)rec_f, own, qbd, q_bar, pos_bar);
-    else launch_gather<false>(s, gl, n, t_offsets, tsl, (const double*)rec, own, qbd, q_bar, pos_bar);
+    if (rec32) launch_gather<false>(s, gl, tiled ? tbound : nullptr, n, t_offsets, tsl, t_src, (const float*)rec_f, own, qbd, q_bar, pos_bar);
+    else launch_gather<false>(s, gl, tiled ? tbound : nullptr, n, t_offsets, tsl, t_src, (const double*)rec, own, qbd, q_bar, pos_bar);
   }
   return hip_check(ctx, hipGetLastError(), "adjoint gather");
 }

@@ -10,7 +10,12 @@ namespace phb {
 int adjoint_rhs(phb_ctx* ctx, const EvalArgs& a, const phb_params* p, const int64_t* t_offsets,
                 const int32_t* t_src, const int32_t* t_pos, const double* q,
                 const double* rhs_bar, const double* dxdt_bar, double* q_bar, double* pos_bar,
-                const double* tape, int64_t nnz_known, bool nnz_exact = true);
+                const double* tape, int64_t nnz_known, bool nnz_exact = true,
+                const int32_t* tile_start = nullptr, int64_t ntiles = 0);
+// Owners per tile of the reverse mode's tile schedule (tile_start above:
+// device int32[ntiles + 1], the tiles' first particles and then n; null:
+// uniform tiles of this size from particle 0).
+int adjoint_pair_tile();
 // Workspace bytes of adjoint_rhs (the lane-per-entry schedule's included).
 size_t ws_bytes_adjoint(int64_t n, int64_t nnz, const phb_params* p, bool need_tape);
 

@@ -534,7 +534,7 @@ int phb_tune_set(phb_ctx* ctx, const char* key, int value) {
       : cut ? !(value >= -1 && value <= 120)
           : refine ? !(value >= 0 && value <= 2)
           : lanes ? !(value == 1 || value == 2 || value == 4)
-          : pairs ? !(value >= 0 && value <= 2)
+          : pairs ? !(value >= 0 && value <= 3)
                   : (mode ? !(value == 0 || value == 1) : !(value >= 1 && value <= 4)))
     return set_error(ctx, PHB_EINVAL, std::string("bad value for ") + key);
   *slot = value;

@@ -43,6 +43,10 @@ struct phb_batch {
   // calls may regrow the context's arena without touching it.
   char* arena = nullptr;
   size_t arena_cap = 0;
+  // The reverse mode's tile schedule tiles each set from its first particle,
+  // as a call on that set alone does (tile starts, device, ntiles + 1).
+  int32_t* tiles = nullptr;
+  int64_t ntiles = 0;
 };
 
 namespace phb {
@@ -95,7 +99,8 @@ int batch_pass(phb_ctx* ctx, phb_batch* b, const phb_batch_io* io) {
   if (!io->q_bar) return PHB_OK;
   return adjoint_rhs(ctx, a, &b->p, io->t_offsets, io->t_src, io->t_pos, io->q, io->rhs_bar,
                      io->dxdt_bar, io->q_bar, io->pos_bar,
-                     reinterpret_cast<const double*>(io->tape), b->nnz);
+                     reinterpret_cast<const double*>(io->tape), b->nnz, true, b->tiles,
+                     b->ntiles);
 }
 
 int check_io(phb_ctx* ctx, const phb_batch* b, const phb_batch_io* io) {
@@ -145,6 +150,19 @@ int phb_batch_create(phb_ctx* ctx, const phb_params* p, int32_t n_sets,
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) {
+    std::vector<int32_t> t;
+    for (int s = 0; s < n_sets; ++s) {
+      const int64_t ns = set_offsets[s + 1] - set_offsets[s];
+      const int64_t ts = adjoint_pair_tile();
+      for (int64_t k = 0; k < ns; k += ts) t.push_back((int32_t)(set_offsets[s] + k));
+    }
+    t.push_back((int32_t)b->n_total);
+    b->ntiles = (int64_t)t.size() - 1;
+    e = hipMalloc((void**)&b->tiles, t.size() * sizeof(int32_t));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->tiles, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     phb_batch_destroy(b);
     return hip_check(ctx, e, "batch create");
@@ -163,6 +181,7 @@ int phb_batch_destroy(phb_batch* b) {
   if (b->stream) hipStreamDestroy(b->stream);
   if (b->tmp_pos) hipFree(b->tmp_pos);
   if (b->tmp_off) hipFree(b->tmp_off);
+  if (b->tiles) hipFree(b->tiles);
   delete b;
   return PHB_OK;
 }
@@ -307,7 +326,7 @@ int phb_tune(phb_ctx* ctx, const phb_params* p, int64_t n64, const double* pos,
   };
   const std::vector<Knob> knobs = {
       {"lanes_moments", {1, 2, 4}}, {"lanes_apply", {1, 2, 4}},  {"lanes_adj_y", {1, 2, 4}},
-      {"lanes_gather", {1, 2, 4}},  {"adj_pairs_mode", {0, 1, 2}}, {"record_order", {0, 1}},
+      {"lanes_gather", {1, 2, 4}},  {"adj_pairs_mode", {0, 1, 2, 3}}, {"record_order", {0, 1}},
       {"fit_fields", {2, 4}}, {"moments_mfma", {0, 1}}};
   char sig[160];
   snprintf(sig, sizeof sig, "# phurbas-tune n=%lld nnz=%lld precision=%d weight=%d",

@@ -35,7 +35,8 @@ struct phb_ctx {
   int mixed_refine = 2;     // mixed form: 1 operator-level, 0 data-level, 2 by shape
   int fp64_cut_x10 = -1;    // refinement of fits whose inverse has a row norm above
                             // 10^(x10 / 10); -1: the shape's default, 999: never
-  int adj_pairs_mode = 1;  // 0: one lane per entry, 1: one wavefront per owner
+  int adj_pairs_mode = 3;  // 0: one lane per entry, 1: one wavefront per owner, 2: pipelined,
+                           // 3: one block per tile of owners
   int record_order = 0;    // pair records at 0: transposed positions, 1: forward slots
   // Per-kernel timing (phb_profile): event pairs awaiting read-out and totals.
   bool capturing = false;  // a graph capture is recording the context stream

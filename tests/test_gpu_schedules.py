@@ -20,7 +20,7 @@ P = pytest.importorskip("paper_1110_0836_amd")
 
 VARIANTS = [("lanes_moments", 1), ("lanes_moments", 2), ("lanes_apply", 1), ("lanes_apply", 2),
             ("lanes_adj_y", 1), ("lanes_adj_y", 4), ("lanes_gather", 1), ("lanes_gather", 2),
-            ("adj_pairs_mode", 0), ("adj_pairs_mode", 2), ("record_order", 1), ("cells_per_rf", 1),
+            ("adj_pairs_mode", 0), ("adj_pairs_mode", 1), ("adj_pairs_mode", 2), ("record_order", 1), ("cells_per_rf", 1),
             ("cells_per_rf", 3), ("fit_fields", 2), ("moments_mfma", 1)]
 
 

@@ -232,6 +232,31 @@ def test_reverse_mode_mixed():
     assert eq < 1e-5 and ep < 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("mode,order", [(1, 1), (2, 0), (3, 0), (3, 1)])
+def test_reverse_mode_pair_schedules(mode, order, precision):
+    # 729 particles: five tiles of the tile schedule, the last one ragged
+    from test_gpu_adjoint import random_set
+    c, gbar, xbar = random_set(side=9, seed=79)
+    keys = {"adj_pairs_mode": mode, "record_order": order}
+    old = {k: P.phb_tune_get(k) for k in keys}
+    kw = {"precision": P.PHB_MIXED} if precision == "mixed" else {}
+    try:
+        for k, v in keys.items():
+            P.phb_tune_set(k, v)
+        (qb, pb), (oq, op, ost), _ = _adjoint_both(c, gbar, xbar, **kw)
+    finally:
+        for k, v in old.items():
+            P.phb_tune_set(k, v)
+    assert np.all(ost == 0)
+    eq = max(_gerr(qb[f], oq[f]) for f in range(8))
+    ep = _gerr(pb, op)
+    print(f"stabilised reverse mode, pairs {mode}, order {order}, {precision}: q_bar {eq:.2e}, "
+          f"pos_bar {ep:.2e}")
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert eq < tol and ep < tol
+
+
 def test_autograd_with_stabilisers():
     """torch.autograd through MHDRHS with the stabilisers on equals the
     oracle's gradient of the same loss."""
