@@ -32,7 +32,9 @@ k_factor_fit<3>  per particle: equilibration + Cholesky (3330), three
 k_rows_rhs_finish per particle: gradient scaling (21) + right-hand side   = 66
 k_adj_u          per particle: pointwise adjoint                          = 150
 k_adj_pairs_w    as k_adj_pairs; the owner's K = Ubar C^T (840 per
-k_adj_pairs_p    particle) is left out of the count.
+k_adj_pairs_p    particle) and the tile schedule's LDS sums (adds that
+k_adj_pairs_t    replace a record's write and the gather's adds) are left
+                 out of the count.
 
 Mixed form without a tape (FP32 arithmetic after the FP64 displacement,
 FP64 factor and solves; counted the same way, whatever the precision; a
@@ -74,6 +76,7 @@ PER_PAIR = {
     "k_adj_pairs": 683,
     "k_adj_pairs_w": 683,
     "k_adj_pairs_p": 683,
+    "k_adj_pairs_t": 683,
 }
 PER_PARTICLE = {
     "k_factor<3>": 5704,
