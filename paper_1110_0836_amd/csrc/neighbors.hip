@@ -545,11 +545,13 @@ __global__ void k_nb_total(const int64_t* __restrict__ offsets, int m, int64_t c
 // With equal radii every entry is mutual; with graded lambdas the one-way
 // entries are a thin shell near each sphere's edge.  Pass 1 finds, for each
 // entry s = (x, y), x's place in row y (rows are sorted: a binary search):
-// rev[s] = the mirrored entry (y, x), or -1 (one-way: x joins B(y)).  Pass 2
-// puts the one-way entries into B's part of their transposed rows (after
-// A's), unsorted.  Pass 3 sorts each transposed row with the forward entry
-// each element stands for, in registers, and writes t_src and t_pos.  Only
-// the one-way entries use atomics (their order is undone by the sort).
+// rev[s] = the mirrored entry (y, x), or, for a one-way entry (x joins
+// B(y)), -(k + 1) with k its slot in B(y), taken from an atomic count on y.
+// Pass 2 puts the one-way entries at their slots in B's part of their
+// transposed rows (after A's).  Pass 3 places each transposed row's
+// elements in order with the forward entry each stands for and writes t_src
+// and t_pos.  Only the one-way entries use atomics, once each (the order of
+// the slots they hand out is undone in pass 3).
 
 
 // Pass 1, RW consecutive rows x per wavefront, a lane per entry of each: the
@@ -616,12 +618,17 @@ __global__ void __launch_bounds__(NB_THREADS)
         }
       }
     }
+    // a one-way entry's count on y is also its slot in B(y): rev holds
+    // -(slot + 1)
+    int slot[TR_RW];
 #pragma unroll
     for (int r = 0; r < TR_RW; ++r) {
-      if (y[r] >= 0) {
-        rev[s0[r] + k] = found[r];
-        if (found[r] < 0) atomicAdd(&bcnt[y[r]], 1);
-      }
+      slot[r] = 0;
+      if (y[r] >= 0 && found[r] < 0) slot[r] = atomicAdd(&bcnt[y[r]], 1);
+    }
+#pragma unroll
+    for (int r = 0; r < TR_RW; ++r) {
+      if (y[r] >= 0) rev[s0[r] + k] = found[r] >= 0 ? found[r] : -(slot[r] + 1);
       a[r] += __popcll(__ballot(found[r] >= 0));
     }
   }
@@ -632,24 +639,24 @@ __global__ void __launch_bounds__(NB_THREADS)
   }
 }
 
-// Row lengths |A| + |B| for the scan; the B counts become the B cursors.
+// Row lengths |A| + |B| for the scan.
 __global__ void __launch_bounds__(NB_THREADS)
-    k_tr_total(int n, const int32_t* __restrict__ acnt, int32_t* __restrict__ bcnt,
+    k_tr_total(int n, const int32_t* __restrict__ acnt, const int32_t* __restrict__ bcnt,
                int32_t* __restrict__ tcount) {
   const int x = blockIdx.x * NB_THREADS + threadIdx.x;
   if (x >= n) return;
   tcount[x] = acnt[x] + bcnt[x];
-  bcnt[x] = 0;
 }
 
-// Pass 2: one-way entry s = (i, x) into B(x): key i, payload s.  TR_RW
-// forward rows i per wavefront, a lane per entry of each; the cursors' and
-// offsets' reads of all the rows are in flight before the first store.
+// Pass 2: one-way entry s = (i, x) into B(x) at the slot pass 1 gave it:
+// key i, payload s.  TR_RW forward rows i per wavefront, a lane per entry of
+// each; the offsets' reads of all the rows are in flight before the first
+// store.
 __global__ void __launch_bounds__(NB_THREADS)
     k_tr_oneway(int n, const int64_t* __restrict__ off, const int32_t* __restrict__ idx,
                 const int32_t* __restrict__ rev, const int64_t* __restrict__ toff,
-                const int32_t* __restrict__ acnt, int32_t* __restrict__ bcur,
-                int32_t* __restrict__ tkey, int32_t* __restrict__ tpay) {
+                const int32_t* __restrict__ acnt, int32_t* __restrict__ tkey,
+                int32_t* __restrict__ tpay) {
   const int lane = threadIdx.x & 63;
   const int i0 =
       __builtin_amdgcn_readfirstlane((xcd_block() * NB_WAVES + (threadIdx.x >> 6)) * TR_RW);
@@ -666,22 +673,20 @@ __global__ void __launch_bounds__(NB_THREADS)
   }
   for (int base = 0; base < maxlen; base += 64) {
     const int k = base + lane;
-    int x[TR_RW];
+    int x[TR_RW], cur[TR_RW];
 #pragma unroll
     for (int r = 0; r < TR_RW; ++r) {
       const bool in = k < len[r];
       const int32_t rv = in ? rev[s0[r] + k] : 0;
       const int32_t xr = in ? idx[s0[r] + k] : -1;
       x[r] = rv < 0 ? xr : -1;
+      cur[r] = -rv - 1;  // the slot in B(x) (one-way entries)
     }
     int64_t t[TR_RW];
-    int cur[TR_RW];
 #pragma unroll
     for (int r = 0; r < TR_RW; ++r) {
       const int xs = x[r] >= 0 ? x[r] : 0;
       t[r] = toff[xs] + acnt[xs];
-      cur[r] = 0;
-      if (x[r] >= 0) cur[r] = atomicAdd(&bcur[x[r]], 1);
     }
 #pragma unroll
     for (int r = 0; r < TR_RW; ++r) {
@@ -1134,7 +1139,7 @@ hipError_t launch_transpose(hipStream_t s, int n, const int64_t* off, const int3
                      w.acnt, w.bcnt, w.tcount);
   if ((e = exclusive_scan_i32_to_i64(s, w.tcount, n, toff, w.scan)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_tr_oneway, gw, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, toff, w.acnt,
-                     w.bcnt, w.tkey, w.tpay);
+                     w.tkey, w.tpay);
   hipLaunchKernelGGL(k_tr_rows, gr, dim3(NB_THREADS), 0, s, n, off, idx, w.rev, toff, w.acnt,
                      w.tkey, w.tpay, tsrc, tpos, w.long_list, w.counts + 1);
   hipLaunchKernelGGL(k_tr_long, dim3(NB_LONG_BLOCKS * NB_WAVES), dim3(64), 0, s, w.long_list,
