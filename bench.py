@@ -87,7 +87,7 @@ def time_gpu(fn, reps, torch):
 # the kernels of one forward evaluation, per form (the rest of a step is the
 # reverse mode)
 FORWARD_KERNELS = {
-    "fp64": ("k_pack", "k_moments", "k_fit_b<7>", "k_factor_fit<3>", "k_rows_rhs_finish",
+    "fp64": ("k_pack", "k_fit_b<7>", "k_moments_factor_fit<3>", "k_rows_rhs_finish",
              "k_ref_fit", "k_ref_tape", "k_ref_rows", "k_rows_rhs_finish<list>"),
 }
 # a mixed call with a tape (the benchmark's) runs the FP64 data form forward

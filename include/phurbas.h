@@ -210,16 +210,16 @@ int phb_mls_derivs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* p
  *   dB/dt = (B . grad) V - B div V ; dsigma/dt = -gamma sigma div V ;
  * dxdt[3][n] = V.  status int32[n].  tape: NULL or a device buffer of
  * phb_tape_bytes(n) bytes that keeps what the reverse-mode call reuses.
- * First 115 rows of ld doubles each (ld >= n, padded so that the row stride
+ * First 31 rows of ld doubles each (ld >= n, padded so that the row stride
  * is not a power of two), particle i at [row][i]: rows 0..20 the gradients of
  * V, B, sigma (3 each), 21 the status, 22..30 grad rho, grad div V and
- * grad div B (stabilisers on), 31..114 the 84 FP64 moments.  Then
+ * grad div B (stabilisers on).  Then
  * PHB_TAPE_AOS doubles per particle (n blocks, particle i at i *
  * PHB_TAPE_AOS), written in the FP64 form: rows 1..3 of the inverse moment
  * matrix A^{-1} (1..9 with the stabilisers), then the fit coefficients
  * C = A^{-1} B of V, B, sigma (of all eight fields with the stabilisers),
  * 20 each; the block's first 200 (340) doubles are used.  So
- * phb_tape_bytes(n) = 8 (115 ld + PHB_TAPE_AOS n).  Asynchronous. */
+ * phb_tape_bytes(n) = 8 (31 ld + PHB_TAPE_AOS n).  Asynchronous. */
 #define PHB_TAPE_AOS 340
 int phb_mhd_rhs(phb_ctx* ctx, const phb_params* p, int64_t n, const double* pos,
                 const double* lambda, const int64_t* offsets, const int32_t* idx,

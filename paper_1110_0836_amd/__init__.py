@@ -291,7 +291,7 @@ def phb_tape_bytes(n):
     return lib().phb_tape_bytes(n)
 
 
-TAPE_ROWS = 31 + 84  # per-particle rows at the start of a tape
+TAPE_ROWS = 31  # per-particle rows at the start of a tape
 TAPE_AOS = 340  # doubles per particle in the tape's block that follows them
 
 

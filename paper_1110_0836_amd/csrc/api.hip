@@ -267,26 +267,24 @@ int eval_rhs(phb_ctx* ctx, const EvalArgs& a0, const phb_params* p, const double
   double4* geo = ws.take<double4>(na);
   double* fq = ws.take<double>((size_t)8 * na);
   const RefineBufs rb = take_refine(ws, n, sb.on() ? 9 : 7);
-  // with a tape, the moments go straight into it for the reverse mode
-  if (tape) mom = tape + (size_t)TAPE_MOM * soa_ld(n);
   double* aos = tape ? tape_aos(tape, n) : nullptr;
   a.geo = geo;
   a.fq = fq;
   { Prof pf(ctx, "k_pack");
   if ((rc = hip_check(ctx, launch_pack(ctx->stream, na, a.pos, a.lam, q, geo, fq), "pack")))
     return rc; }
-  { Prof pf(ctx, "k_moments");
-  if ((rc = hip_check(ctx, launch_moments(ctx->stream, a, ctx->lanes_assemble, mom), "moments")))
-    return rc; }
   { Prof pf(ctx, nf == 8 ? "k_fit_b<8>" : "k_fit_b<7>");
   if ((rc = hip_check(ctx, launch_fit_b(ctx->stream, a, nf, ctx->fit_fields, bc), "fit right-hand sides")))
     return rc; }
-  { Prof pf(ctx, nrows == 9 ? "k_factor_fit<9>" : "k_factor_fit<3>");
+  // the moments stay on chip for the factor; only the listed fits' moments
+  // reach mom, for their refinement
+  { Prof pf(ctx, nrows == 9 ? "k_moments_factor_fit<9>" : "k_moments_factor_fit<3>");
   if ((rc = hip_check(ctx, fill_i32(ctx->stream, rb.count, 0, 1), "clear list")) ||
       (rc = hip_check(ctx,
-                      launch_factor_fit(ctx->stream, a, nrows, mom, bc, aos, status,
-                                        fp64_screen_cut(ctx, nrows, false), rb.list, rb.count),
-                      "factor and fit")))
+                      launch_moments_factor_fit(ctx->stream, a, nrows, mom, bc, aos, status,
+                                                fp64_screen_cut(ctx, nrows, false), rb.list,
+                                                rb.count),
+                      "moments, factor and fit")))
     return rc; }
   { Prof pf(ctx, sb.on() ? "k_rows_rhs_finish<stab>" : "k_rows_rhs_finish");
   if ((rc = hip_check(ctx,

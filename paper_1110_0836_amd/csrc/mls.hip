@@ -341,44 +341,87 @@ __global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(2)
   }
 }
 
-// The data-form factor: equilibrated Cholesky of the moments, the status,
-// rows 1..NT of A^{-1} (the screen of k_factor; with a tape also its G) and
-// C_f = A^{-1} B_f for the NT == 9 ? 8 : 7 fields in lockstep pairs.  The
-// derivative rows of C (coefficients 1..NT) go in place over B as
-// [NF][NT][ld] (each quad reads a pair's B before it writes that pair's rows,
-// which lie below every later pair's B), all of C to the tape.  Failed fits
-// write zeros.  Interpolating fit: the constant's row and column are the
-// identity's, B's constant entry is dropped and C's stays zero.
+// The FP64 moments and the data-form factor in one kernel.  Four lanes per
+// particle sum the 84 moments as k_moments<4, double> does (the same sums,
+// bit for bit) and leave them in LDS; the quad then factors A from there:
+// equilibrated Cholesky, the status, rows 1..NT of A^{-1} (the screen of
+// k_factor; with a tape also its G) and C_f = A^{-1} B_f for the
+// NT == 9 ? 8 : 7 fields in lockstep pairs.  The derivative rows of C
+// (coefficients 1..NT) go in place over B as [NF][NT][ld] (each quad reads a
+// pair's B before it writes that pair's rows, which lie below every later
+// pair's B), all of C to the tape.  Failed fits write zeros.  Interpolating
+// fit: the constant's row and column are the identity's, B's constant entry
+// is dropped and C's stays zero.  Only the particles listed for refinement
+// write their moments to mom (the refinement reads them), so the moments
+// make no round trip through HBM.
 template <int NT>
 __global__ void __launch_bounds__(THREADS)
-    k_factor_fit(int n, const double* __restrict__ mom, const int64_t* __restrict__ off,
-                 double* bc, double* __restrict__ aos, int32_t* __restrict__ status, int interp,
-                 double rcut, int32_t* __restrict__ list, int32_t* __restrict__ count) {
+    k_moments_factor_fit(int n, const double4* __restrict__ geo, const int64_t* __restrict__ off,
+                         const int32_t* __restrict__ idx, Box box, double rf_ratio, int wkind,
+                         const int32_t* __restrict__ rows, double* __restrict__ mom, double* bc,
+                         double* __restrict__ aos, int32_t* __restrict__ status, int interp,
+                         double rcut, int32_t* __restrict__ list, int32_t* __restrict__ count) {
   constexpr int NF = NT == 9 ? 8 : 7;
-  constexpr int LEN = TAPE_AOS, COFF = NT * NBASIS;
-  const int tid = blockIdx.x * THREADS + threadIdx.x;
-  const int i = tid >> 2;
-  const int l = tid & 3;
+  constexpr int LEN = TAPE_AOS, COFF = NT * NBASIS, G = 4, PW = 64 / G;
+  __shared__ double smom[THREADS / 64][NMOM][PW];
+  const int tid = xcd_block() * THREADS + threadIdx.x;
+  const int i = tid / G;
+  const int l = tid % G;
+  const int wv = threadIdx.x >> 6, p = (threadIdx.x & 63) / G;  // particle within the wavefront
   const bool valid = i < n;
   const int ii = valid ? i : n - 1;
+  {
+    double m[NMOM];
+#pragma unroll
+    for (int k = 0; k < NMOM; ++k) m[k] = 0.0;
+    const double4 gi = geo[rows ? rows[ii] : ii];  // row ii's own particle
+    const double inv_lam = 1.0 / gi.w;
+    const double r = rf_ratio * gi.w;
+    const double inv_r2 = 1.0 / (r * r);
+    const int64_t s0 = off[ii], s1 = valid ? off[ii + 1] : s0;
+    int64_t s = s0 + l;
+    double4 gn = gi;
+    int jn = 0;
+    if (s < s1) gn = geo[idx[s]];
+    if (s + G < s1) jn = idx[s + G];
+    for (; s < s1; s += G) {
+      const double4 gj = gn;
+      if (s + G < s1) {
+        gn = geo[jn];
+        if (s + 2 * G < s1) jn = idx[s + 2 * G];
+      }
+      const double dx = min_image(gj.x - gi.x, box.L[0], box.halfL[0], box.periodic[0]);
+      const double dy = min_image(gj.y - gi.y, box.L[1], box.halfL[1], box.periodic[1]);
+      const double dz = min_image(gj.z - gi.z, box.L[2], box.halfL[2], box.periodic[2]);
+      const double qd = (dx * dx + dy * dy + dz * dz) * inv_r2;
+      const double w = weight_of(qd, wkind);
+      accumulate_moments(m, w, dx * inv_lam, dy * inv_lam, dz * inv_lam);
+    }
+    double mine[NMOM / G];
+    group_reduce_scatter<G, NMOM>(m, mine, l);
+#pragma unroll
+    for (int k = 0; k < NMOM / G; ++k) smom[wv][l + G * k][p] = mine[k];
+  }
+  // each wavefront reads only its own particles' moments
+  wave_lds_sync();
   QuadChol c;
-  quad_chol_factor(c, c_tab, mom, soa_ld(n), ii, l, interp != 0);
+  quad_chol_factor(c, c_tab, &smom[wv][0][0], PW, p, l, interp != 0);
   const int st = quad_chol_status(c, (int)(off[ii + 1] - off[ii]));
   double* rec = (aos && valid) ? aos + (int64_t)i * LEN : nullptr;
   double rmax2 = 0.0;
   sfor<0, NT / 3>([&](auto GI) {
     constexpr int t0 = 1 + 3 * GI;
-    double rows[3][5];
-    quad_chol_inverse_rows<t0, 3>(c, l, rows);
+    double rws[3][5];
+    quad_chol_inverse_rows<t0, 3>(c, l, rws);
     if (rec) {
       sfor<0, 3>([&](auto RI) {
         sfor<0, 5>([&](auto R) {
           constexpr int rho = R;
-          rec[(3 * GI + RI) * NBASIS + 4 * rho + l] = st == 0 ? rows[RI][rho] : 0.0;
+          rec[(3 * GI + RI) * NBASIS + 4 * rho + l] = st == 0 ? rws[RI][rho] : 0.0;
         });
       });
     }
-    if (list) rmax2 = fmax(rmax2, quad_rows_hat_norm2<t0, 3>(c, l, rows));
+    if (list) rmax2 = fmax(rmax2, quad_rows_hat_norm2<t0, 3>(c, l, rws));
   });
   constexpr int LS = 2;  // lockstep solves: two keep the kernel within 256 VGPRs
   for (int f0 = 0; f0 < NF; f0 += LS) {
@@ -406,9 +449,16 @@ __global__ void __launch_bounds__(THREADS)
       }
     }
   }
+  // the quad agrees on the status and on the screen (rmax2 is a quad sum)
+  const bool listed = valid && list && st == 0 && !(rmax2 <= rcut * rcut);
+  if (listed) {
+#pragma unroll
+    for (int k = 0; k < NMOM / G; ++k)
+      mom[(int64_t)(l + G * k) * soa_ld(n) + i] = smom[wv][l + G * k][p];
+  }
   if (valid && l == 0) {
     status[i] = st;
-    if (list && st == 0 && !(rmax2 <= rcut * rcut)) list[atomicAdd(count, 1)] = i;
+    if (listed) list[atomicAdd(count, 1)] = i;
   }
 }
 
@@ -742,17 +792,19 @@ hipError_t launch_fit_b(hipStream_t s, const EvalArgs& a, int nf, int fpl, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_factor_fit(hipStream_t s, const EvalArgs& a, int nrows, const double* mom,
-                             double* bc, double* aos, int32_t* status, double rcut,
-                             int32_t* list, int32_t* count) {
+hipError_t launch_moments_factor_fit(hipStream_t s, const EvalArgs& a, int nrows, double* mom,
+                                     double* bc, double* aos, int32_t* status, double rcut,
+                                     int32_t* list, int32_t* count) {
   const unsigned grid = grid_for((int64_t)a.n * 4, THREADS);
   const int interp = a.fit == PHB_FIT_INTERP19;
   if (nrows == 3)
-    hipLaunchKernelGGL((k_factor_fit<3>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, bc,
-                       aos, status, interp, rcut, list, count);
+    hipLaunchKernelGGL((k_moments_factor_fit<3>), dim3(grid), dim3(THREADS), 0, s, a.n, a.geo,
+                       a.off, a.idx, a.box, a.rf_ratio, a.wkind, a.rows, mom, bc, aos, status,
+                       interp, rcut, list, count);
   else
-    hipLaunchKernelGGL((k_factor_fit<9>), dim3(grid), dim3(THREADS), 0, s, a.n, mom, a.off, bc,
-                       aos, status, interp, rcut, list, count);
+    hipLaunchKernelGGL((k_moments_factor_fit<9>), dim3(grid), dim3(THREADS), 0, s, a.n, a.geo,
+                       a.off, a.idx, a.box, a.rf_ratio, a.wkind, a.rows, mom, bc, aos, status,
+                       interp, rcut, list, count);
   return hipGetLastError();
 }
 

@@ -35,8 +35,8 @@ struct EvalArgs {
 
 // Tape of the forward evaluation.  First TAPE_DOUBLES rows (SoA, leading
 // dimension soa_ld(n)): 21 gradients (V, B, sigma x 3), the status, grad rho,
-// grad div V and grad div B (written only with the stabilisers on), then the
-// 84 moments, FP64-assembled in both forms.  Then, written by the FP64 form,
+// grad div V and grad div B (written only with the stabilisers on).  Then,
+// written by the FP64 form,
 // one block of TAPE_AOS doubles per particle (AoS, the reverse mode's
 // per-owner data): the operator rows G (rows 1..nr of A^{-1}, nr = 3, or 9
 // with the stabilisers) at 0 and the fit coefficients C = A^{-1} B of the
@@ -45,8 +45,7 @@ constexpr int TAPE_STATUS = 21;
 constexpr int TAPE_GRHO = 22;
 constexpr int TAPE_GDV = 25;
 constexpr int TAPE_GDB = 28;
-constexpr int TAPE_MOM = 31;
-constexpr int TAPE_DOUBLES = TAPE_MOM + NMOM;
+constexpr int TAPE_DOUBLES = 31;
 constexpr int TAPE_AOS = (9 + 8) * NBASIS;
 // Doubles of a tape of n particles.
 __host__ __device__ constexpr int64_t tape_doubles(int64_t n) {
@@ -77,14 +76,16 @@ hipError_t launch_factor(hipStream_t s, const EvalArgs& a, int ntargets, const d
 // (7 or 8) fields of the packed records, into bout [nf][20][soa_ld(n)]; fpl
 // (2 or 4) fields per lane.
 hipError_t launch_fit_b(hipStream_t s, const EvalArgs& a, int nf, int fpl, double* bout);
-// Equilibrated Cholesky of the moments, status, rows 1..nrows of A^{-1} (3 or
-// 9; nf = 7 or 8 fields to match) and C_f = A^{-1} B_f from B in bc
-// [nf][20][soa_ld(n)]; the derivative rows (coefficients 1..nrows) in place
-// over bc as [nf][nrows][soa_ld(n)].  With aos (the tape's AoS block) G and
-// all of C also go there.  Screen (list != null) as for launch_factor.
-hipError_t launch_factor_fit(hipStream_t s, const EvalArgs& a, int nrows, const double* mom,
-                             double* bc, double* aos, int32_t* status, double rcut,
-                             int32_t* list, int32_t* count);
+// The FP64 moments (kept in LDS) and their equilibrated Cholesky in one
+// pass: status, rows 1..nrows of A^{-1} (3 or 9; nf = 7 or 8 fields to
+// match) and C_f = A^{-1} B_f from B in bc [nf][20][soa_ld(n)]; the
+// derivative rows (coefficients 1..nrows) in place over bc as
+// [nf][nrows][soa_ld(n)].  With aos (the tape's AoS block) G and all of C
+// also go there.  Screen (list != null) as for launch_factor; mom
+// [84][soa_ld(n)] receives the moments of the listed particles only.
+hipError_t launch_moments_factor_fit(hipStream_t s, const EvalArgs& a, int nrows, double* mom,
+                                     double* bc, double* aos, int32_t* status, double rcut,
+                                     int32_t* list, int32_t* count);
 // fp32: the neighbor loop in FP32 (the mixed form).  list, count (device):
 // only the particles list[0 .. *count), outputs at their own indices.
 hipError_t launch_apply_derivs(hipStream_t s, const EvalArgs& a, int lanes, const double* gop,

@@ -26,7 +26,8 @@ FP64 data form (the fit coefficients are solved for, and taped with the
 operator rows for the reverse mode):
 k_fit_b<7>       per pair: geometry and weight (15), basis (16), per field
                  w df (2) and 20 FMA (40), seven fields                   = 325
-k_factor_fit<3>  per particle: equilibration + Cholesky (3330), three
+k_moments_factor_fit<3>  per pair: the moments as k_moments            = 187
+                 per particle: equilibration + Cholesky (3330), three
                  unit-vector solves (2234), seven general solves (7 x 820),
                  row norms of the screen (120), output scaling (260)      = 11684
 k_rows_rhs_finish per particle: gradient scaling (21) + right-hand side   = 66
@@ -77,10 +78,11 @@ PER_PAIR = {
     "k_adj_pairs_w": 683,
     "k_adj_pairs_p": 683,
     "k_adj_pairs_t": 683,
+    "k_moments_factor_fit<3>": 187,
 }
 PER_PARTICLE = {
     "k_factor<3>": 5704,
-    "k_factor_fit<3>": 11684,
+    "k_moments_factor_fit<3>": 11684,
     "k_rows_rhs_finish": 66,
     "k_adj_u": 150,
     "k_mixed_factor": 13224,
