@@ -425,7 +425,9 @@ int phb_batch_launch(phb_ctx* ctx, phb_batch* b);
  * Keys: "cells_per_rf" (1..4: neighbor-grid cells per minimum r_f),
  * "lanes_moments", "lanes_apply", "lanes_adj_y" (1, 2 or 4 lanes sharing one
  * particle's neighbor loop in the moment and application kernels and in the
- * untaped mixed form's residual-product kernel), "lanes_gather" (1, 2 or 4 lanes summing one particle's
+ * untaped mixed form's residual-product kernel; the FP64 data form sums its
+ * moments with four lanes in the factor's kernel whatever lanes_moments
+ * says), "lanes_gather" (1, 2 or 4 lanes summing one particle's
  * transposed row in the reverse mode), "adj_pairs_mode" (0: one lane per
  * neighbor entry, 1: one wavefront per owner particle, 2: persistent
  * wavefronts that stage the next owner through direct-to-LDS loads while
