@@ -20,7 +20,10 @@
 //        dbar  = xibar / lambda + wbar (dw/dq) 2 d / r_f^2,
 //      and the pair contributes +dfbar, +dbar to j and -dfbar, -dbar to i;
 //   4. every particle sums the pair records addressed to it (the transposed
-//      lists), in a fixed order, plus its own terms.  No atomics.
+//      lists), in a fixed order, plus its own terms.  No atomics.  Under the
+//      tile schedule (the default) the pairs whose target lies in the
+//      owner's tile of consecutive particles are summed on chip instead and
+//      arrive with the particle's own terms.
 #include <type_traits>
 
 #include "adjoint.hpp"
