@@ -338,6 +338,16 @@ __device__ __forceinline__ void cell_row_runs(int k, const CellRows& c, double x
   }
 }
 
+// Inclusive maximum over lanes 0..lane.
+__device__ __forceinline__ int wave_inclusive_max(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(v, d, 64);
+    if (lane >= d) v = max(v, t);
+  }
+  return v;
+}
+
 __device__ __forceinline__ int wave_inclusive_scan(int v, int lane) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -395,7 +405,7 @@ __global__ void __launch_bounds__(NB_THREADS)
               int32_t* __restrict__ long_tmp, int32_t* __restrict__ long_slot,
               int32_t* __restrict__ long_row, int32_t* __restrict__ long_count) {
   __shared__ int sh_start[NB_WAVES][64], sh_s0a[NB_WAVES][64], sh_lena[NB_WAVES][64],
-      sh_s0b[NB_WAVES][64];
+      sh_s0b[NB_WAVES][64], sh_mark[NB_WAVES][NB_U][64];
   __shared__ int32_t sh_row[LONG ? 1 : NB_WAVES][LONG ? 1 : NB_ROW];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int w0 = __builtin_amdgcn_readfirstlane(xcd_block() * NB_WAVES + wv);
@@ -447,24 +457,41 @@ __global__ void __launch_bounds__(NB_THREADS)
     sh_lena[wv][lane] = lena;
     sh_s0b[wv][lane] = s0b;
     wave_lds_sync();
+    const int my_start = incl - tot;  // this lane's run of cells
     for (int q0 = 0; q0 < ncand; q0 += 64 * NB_U) {
       int sl[NB_U];
       bool hit[NB_U];
+      // The run of candidate q is the last non-empty run starting at or
+      // before q.  For the 64 candidates Q .. Q + 63 of a window: each
+      // non-empty run starting inside it marks its start with its index, a
+      // maximum scan carries the marks forward, and the runs starting before
+      // Q give the window's first run (non-empty runs start apart).
+      int run[NB_U];
+#pragma unroll
+      for (int u = 0; u < NB_U; ++u) sh_mark[wv][u][lane] = -1;
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < NB_U; ++u) {
+        const int Q = q0 + 64 * u;
+        if (tot > 0 && my_start >= Q && my_start < Q + 64) sh_mark[wv][u][my_start - Q] = lane;
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int u = 0; u < NB_U; ++u) {
+        const int Q = q0 + 64 * u;
+        const uint64_t before = __ballot(tot > 0 && my_start < Q);
+        const int carry = before ? 63 - (int)__clzll(before) : -1;
+        run[u] = max(carry, wave_inclusive_max(sh_mark[wv][u][lane], lane));
+      }
 #pragma unroll
       for (int u = 0; u < NB_U; ++u) {
         const int q = q0 + 64 * u + lane;
         sl[u] = -1;
         if (q < ncand) {
-          // the last row of cells whose run starts at or before q (rows
-          // without candidates share the next row's start and are passed)
-          int lo = 0, hi = 63;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sh_start[wv][mid] <= q) lo = mid; else hi = mid - 1;
-          }
-          const int d = q - sh_start[wv][lo];
-          const int la = sh_lena[wv][lo];
-          sl[u] = d < la ? sh_s0a[wv][lo] + d : sh_s0b[wv][lo] + (d - la);
+          const int k = run[u];
+          const int d = q - sh_start[wv][k];
+          const int la = sh_lena[wv][k];
+          sl[u] = d < la ? sh_s0a[wv][k] + d : sh_s0b[wv][k] + (d - la);
         }
       }
       double4 pj[NB_U];
