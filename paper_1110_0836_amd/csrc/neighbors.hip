@@ -381,8 +381,9 @@ __device__ __forceinline__ void sort_lds_row(const int32_t* buf, int32_t* __rest
 // which the sorted copy holds bit for bit).  The lanes take the candidate
 // block's rows of cells 64 at a time; their runs, prefix-summed over the
 // wavefront, flatten the candidates into one index range that the lanes
-// then test, U candidates per lane at a time (their loads in flight
-// together), a ballot compacting the hits.  Consecutive rows are spatial
+// then test, NB_U candidates per lane at a time (one: with more, rows of
+// fewer candidates leave more of each pass's lanes idle), a ballot
+// compacting the hits.  Consecutive rows are spatial
 // neighbors (cell order): the XCD-aware block order keeps them in one L2.
 //   LONG = false: count the row; a row of up to NB_ROW entries is collected
 //   in LDS, sorted in registers and written once, coalesced, to its slot of
@@ -392,7 +393,7 @@ __device__ __forceinline__ void sort_lds_row(const int32_t* buf, int32_t* __rest
 //   (long_slot: their r, long_row: their output row), again, written unsorted
 //   at their CSR place in long_tmp (for k_row_sort); the wavefronts stride
 //   over the list.
-constexpr int NB_U = 2;
+constexpr int NB_U = 1;
 
 template <bool LONG>
 __global__ void __launch_bounds__(NB_THREADS)
